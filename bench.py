@@ -1,0 +1,182 @@
+"""Benchmark: NEP-ZBL molecular dynamics of 8,192,000-atom bcc tungsten on one MI355X.
+
+Workload (synthetic): 160x160x160 conventional bcc W cells (a = 3.165 A),
+Maxwell-Boltzmann velocities at 300 K and one 1 keV primary knock-on atom
+near the box centre moving along a seeded random direction; velocity-Verlet
+with the adaptive step of the paper (fastest atom moves at most 0.015 A per
+step, at most 1 fs); neighbour lists with a 1 A skin rebuilt on the device
+when an atom moved more than 0.5 A.  A "step" is one full MD step: half
+kick, drift, conditional rebuild, energy + forces + virial, half kick, step
+length update.  Random NEP weights (the trained model is not available).
+
+Prints one JSON line:  python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (256 CUs x 2.4 GHz x 256 flop/clk)
+PEAK_HBM_GBS = 8000.0
+
+
+def flops_per_atom(n_rad: float, n_ang: float):
+    """Algorithmic flops per atom of the two evaluation kernels, minimal
+    formulation of this model (9 radial + 5x4 angular descriptors, Chebyshev
+    k = 0..8, 30 tanh neurons); FMA = 2, other arithmetic and each sqrt /
+    reciprocal / cos / sin / tanh = 1.  n_rad, n_ang: neighbours inside the
+    radial (6 A) and angular (4 A) cutoffs."""
+    # descriptor + network kernel
+    pair_geom = 9            # FP64 difference (3), r^2 (5), sqrt (1)
+    rad_fwd = pair_geom + 3 + 3 + 3 + 14 + 18                   # t, fc, x, T_2..T_8, accumulate fc T_k
+    ang_fwd = 23 + 100 + 4 + 60 + 240                           # basis, g_n, r^-1 u, Y_lm, s += g Y
+    per_atom_fwd = 180 + 240 + 1900 + 1830 + 162 + 240          # q, q_nl, network fwd, network bwd, adjoints
+    desc = rad_fwd * n_rad + ang_fwd * n_ang + per_atom_fwd
+    # force + virial kernel (both ends of every pair folded into one gradient)
+    rad_bwd = pair_geom + 1 + 3 + 6 + 3 + 14 + 28 + 2 + 9 + 36 + 9 + 6 + 3 + 18 + 3
+    ang_bwd = 56 + 210 + 60 + 120 + 480 + 48 + 150 + 20
+    force = rad_bwd * n_rad + ang_bwd * n_ang + 20
+    return desc, force
+
+
+def _kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("nep_kernels.hip", "nep_device.h"):
+        with open(os.path.join(ROOT, "paper_2305_08140_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel: str, n_launch_atoms: int):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration);
+    None when the summary is missing or was taken on another kernel source."""
+    p = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    k = d.get("kernels", {}).get(kernel)
+    if not k or d.get("source_hash") != _kernel_source_hash() or d.get("n_atoms") != n_launch_atoms:
+        return None
+    return float(k["bytes_per_launch"])
+
+
+def cpu_baseline(model, s, seconds_target=15.0):
+    """FP64 oracle (untuned, all host threads) on a bounded sample of the same
+    workload: energies and forces of a contiguous block of atoms."""
+    import oracle
+    n_thr = oracle.num_threads()
+    # probe with a small sample, then size the sample for ~seconds_target
+    sample = 2000
+    t0 = time.time()
+    oracle.efv_cell(model, s.pos, s.h[0], targets=np.arange(sample), virial=False)
+    t_probe = time.time() - t0
+    per_atom = t_probe / sample
+    sample = int(min(s.n_atoms, max(2000, seconds_target / max(per_atom, 1e-9))))
+    sample = min(sample, 400000)
+    t0 = time.time()
+    oracle.efv_cell(model, s.pos, s.h[0], targets=np.arange(sample), virial=False)
+    dt = time.time() - t0
+    return {"value": sample / dt, "unit": "atom-steps/s", "cores": n_thr, "kind": "oracle",
+            "sample": f"FP64 energies+forces of {sample} atoms of the 8,192,000-atom configuration "
+                      f"(one evaluation, neighbours found afresh; the integrator update is negligible), "
+                      f"{dt:.1f} s on {n_thr} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cells", type=int, default=160, help="conventional cells per edge")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--timing-reps", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU (the NEP-ZBL evaluation is not sharded "
+              "across GPUs here); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import nep_synth
+    import paper_2305_08140_amd as nep
+
+    model = nep_synth.random_model()
+    s = nep_synth.large(n_cells=args.cells)
+    N = s.n_atoms
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(model, N, 1, max_neigh_ang=48, max_neigh_rad=96, skin=1.0, check=True)
+    out = nep.EFV(N, 1)
+    md = dict(dt_max=1.0, max_disp=0.015, dt_min=1e-6)
+
+    # warm-up (includes the first neighbour build and force evaluation)
+    ctx.nep_step_verlet(sysd, args.warmup, out, forces_valid=False, **md)
+    torch.cuda.synchronize()
+
+    # timed region: K full MD steps in one chunk
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = ctx.nep_step_verlet(sysd, args.steps, out, forces_valid=True, **md)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    value = N * args.steps / wall
+
+    # per-kernel durations (HIP events on the library's stream) at the final state
+    ctx.nep_compute_efv(sysd, out)
+    ktimes = ctx.nep_time_efv(sysd, out, reps=args.timing_reps)
+    n_rad, n_ang = ctx.nep_mean_neighbors()
+    f_desc, f_force = flops_per_atom(n_rad, n_ang)
+    t_force = ktimes["force"] * 1e-3
+    achieved = f_force * N / t_force / 1e12
+    traffic = _traffic("k_force", N)
+
+    # force error against FP64 on a sample of atoms of the final configuration
+    import oracle
+    pos_now = sysd.positions().cpu().numpy()
+    F_gpu = out.forces().cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(N, size=256, replace=False))
+    pka = s.meta["pka"]
+    idx = np.unique(np.concatenate([idx, [pka]]))
+    ref = oracle.efv_cell(model, pos_now, s.h[0], targets=idx, virial=False)
+    ferr = float(np.linalg.norm(F_gpu[idx] - ref["forces"]) / np.linalg.norm(ref["forces"]))
+    eerr = float(np.max(np.abs(out.energy_atom.cpu().numpy()[idx].astype(np.float64) - ref["energy_atom"])))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(model, s)
+
+    line = {
+        "metric": "atom-steps/s NEP-ZBL E+F+virial (plain vs batched/differentiable), force err vs FP64",
+        "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"plain MD, {N} atom bcc W ({args.cells}^3 cells), 300 K + 1 keV PKA, "
+                               "adaptive dt (0.015 A/step, <= 1 fs), 1 A skin",
+                   "n_atoms": N, "model": "NEP-ZBL r_c 6/4 A, 9+20 descriptors, 30 tanh, random weights"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic, "kernel": "k_force"},
+        "cpu_baseline": cpu,
+        "kernels_ms": ktimes,
+        "flops_per_atom": {"descriptor": f_desc, "force": f_force, "mean_neighbors_rad": n_rad,
+                           "mean_neighbors_ang": n_ang},
+        "descriptor_kernel_tflops": f_desc * N / (ktimes["descriptor"] * 1e-3) / 1e12,
+        "md": {"n_rebuilds": stats["n_rebuilds"], "dt_last_fs": stats["dt_last"], "time_fs": stats["time"]},
+        "force_rel_err_vs_fp64": ferr, "site_energy_max_abs_err_eV": eerr,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

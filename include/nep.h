@@ -1,0 +1,191 @@
+/*
+ * nep.h - C ABI of the MI355X (gfx950) NEP-ZBL energy / force / virial library.
+ *
+ * The potential (arXiv 2305.08140, Sec. II.A):
+ *   U_i = U_i^NEP({q_nu^i}) + 1/2 sum_{j != i} U_ZBL(r_ij)                 (Eq. 1)
+ *   U_ZBL(r) = e^2/(4 pi eps0) Z^2/r phi(r/a) f_c(r)                        (Eq. 2)
+ *   phi(x) = 0.32825 e^{-2.54931x} + 0.09219 e^{-0.29182x} + 0.58110 e^{-0.59231x}   (Eq. 3)
+ *   a = 0.46848 / (Z_i^0.23 + Z_j^0.23)                                     (Eq. 4)
+ *   f_c: Tersoff switch between 1.0 A and 2.0 A (Sec. II.A)
+ * U^NEP is a one-hidden-layer tanh network of a descriptor made of Chebyshev
+ * radial components (cutoff 6 A) and Legendre angular components l <= 4
+ * (cutoff 4 A), as in the NEP framework the paper builds on (Sec. II.A,
+ * hyperparameter names in Sec. III.A).  Forces are F = -grad E and the
+ * virial is W_ab = -sum_i sum_j (dU_i/dr_ij)_a (r_ij)_b, r_ij = x_j - x_i.
+ * Molecular dynamics uses velocity Verlet with the time step chosen so that
+ * the fastest atom moves at most a given distance per step (Sec. II.B).
+ *
+ * Conventions
+ *   Units: eV, A, fs, u.  Positions and velocities are FP64, forces FP32,
+ *   energy and virial FP64.  All arrays are structure-of-arrays.
+ *   Device pointers are HIP device memory owned by the caller; the library
+ *   never frees caller memory.  `stream` is a hipStream_t (NULL = default).
+ *   Calls are stream-ordered and asynchronous.  Argument errors are returned
+ *   immediately.  Errors found on the device (neighbour overflow, overlapping
+ *   atoms, non-finite positions, time-step underflow) are latched in the
+ *   context; they are returned by nep_status() and by nep_step_verlet(), which
+ *   synchronises at the end of its chunk.  Once an error is latched, the
+ *   kernels of later calls return without work until nep_status() clears it.
+ *   A context may be used from one host thread at a time; calls that overlap
+ *   on different streams with the same context race.
+ */
+#ifndef NEP_H
+#define NEP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define NEP_OK                 0
+#define NEP_E_ARG             -1  /* bad argument (NULL pointer, size out of range, ...) */
+#define NEP_E_HIP             -2  /* a HIP runtime call failed */
+#define NEP_E_NEIGH_OVERFLOW  -3  /* a neighbour list exceeded its capacity, see nep_required_neighbors */
+#define NEP_E_OVERLAP         -4  /* two atoms closer than 1e-3 A */
+#define NEP_E_NONFINITE       -5  /* a position or velocity is NaN or infinite */
+#define NEP_E_DT_UNDERFLOW    -6  /* adaptive time step fell below nep_md.dt_min */
+#define NEP_E_STATE           -7  /* call order: nep_compute_efv before nep_build_neighbors on this system */
+#define NEP_E_UNSUPPORTED     -8  /* hyperparameters for which no kernel is compiled */
+
+typedef struct nep_ctx nep_ctx;
+
+/* Model hyperparameters (names as in Sec. III.A).  Compiled kernels exist for
+ * n_rad = 9 (n_max^R = 8), n_ang = 5 (n_max^A = 4), k_rad = k_ang = 9
+ * (Chebyshev k = 0..8), l_max = 4, n_hidden <= 32; other values give
+ * NEP_E_UNSUPPORTED. */
+typedef struct {
+    int32_t n_rad;      /* radial descriptor components */
+    int32_t n_ang;      /* radial functions of the angular components */
+    int32_t k_rad;      /* Chebyshev basis size, radial */
+    int32_t k_ang;      /* Chebyshev basis size, angular */
+    int32_t l_max;      /* Legendre orders 1..l_max */
+    int32_t n_hidden;   /* tanh neurons */
+    int32_t Z;          /* nuclear charge of the (single) species */
+    int32_t pad_;
+    double rc_rad;      /* radial cutoff, A (6) */
+    double rc_ang;      /* angular cutoff, A (4) */
+    double zbl_r1;      /* ZBL Tersoff switch inner cutoff, A (1) */
+    double zbl_r2;      /* ZBL Tersoff switch outer cutoff, A (2) */
+} nep_hparams;
+
+/* Model parameters, FP32, row-major.  D = n_rad + n_ang * l_max.
+ * Descriptor order: nu = n for radial; nu = n_rad + n_ang*(l-1) + n for angular.
+ * U^NEP = sum_mu w1[mu] tanh(sum_nu w0[mu][nu] q_scale[nu] q_nu - b0[mu]) - b1. */
+typedef struct {
+    const float *c_rad;    /* [n_rad][k_rad] radial expansion coefficients */
+    const float *c_ang;    /* [n_ang][k_ang] angular radial-function coefficients */
+    const float *q_scale;  /* [D] descriptor scale */
+    const float *w0;       /* [n_hidden][D] */
+    const float *b0;       /* [n_hidden] */
+    const float *w1;       /* [n_hidden] */
+    float b1;
+    int32_t pad_;
+} nep_weights;
+
+/* Capacities, fixed at creation. */
+typedef struct {
+    int64_t max_atoms;      /* total atoms over all cells; at most 2^26 */
+    int32_t max_cells;      /* cells per batch */
+    int32_t max_neigh_ang;  /* per-atom capacity of the list r < rc_ang + skin (<= 255) */
+    int32_t max_neigh_rad;  /* per-atom capacity of the list rc_ang + skin <= r < rc_rad + skin (<= 255) */
+    int32_t pad_;
+    double skin;            /* neighbour-list skin, A; lists are rebuilt when an atom moved > skin/2 */
+} nep_config;
+
+/* A batch of independent cells (one cell for a bulk MD system). */
+typedef struct {
+    int64_t n_atoms;
+    int32_t n_cells;
+    int32_t pbc[3];              /* periodic along lattice vector a (1) or open (0) */
+    const int64_t *cell_start;   /* HOST [n_cells + 1]; NULL means one cell of n_atoms */
+    const double *h;             /* HOST [n_cells][9]; rows are lattice vectors, x = s h */
+    double *x, *y, *z;           /* DEVICE [n_atoms] positions, A */
+    double *vx, *vy, *vz;        /* DEVICE [n_atoms] velocities, A/fs (nep_step_verlet only) */
+    double mass;                 /* atomic mass, u */
+} nep_system;
+
+/* Outputs (DEVICE, caller-owned, written by nep_compute_efv / nep_step_verlet). */
+typedef struct {
+    double *energy;       /* [n_cells] total energy per cell, eV */
+    float *fx, *fy, *fz;  /* [n_atoms] forces, eV/A, in the caller's atom order */
+    double *virial;       /* [n_cells][9] W_ab row-major, eV; may be NULL */
+    float *energy_atom;   /* [n_atoms] site energies U_i, eV; may be NULL */
+} nep_efv;
+
+/* Molecular-dynamics controls. */
+typedef struct {
+    double dt_max;        /* fs, upper limit of the step (Sec. II.B: 1 fs) */
+    double max_disp;      /* A, the fastest atom moves at most this far per step; 0 = fixed dt_max */
+    double dt_min;        /* fs, a step below this latches NEP_E_DT_UNDERFLOW */
+    int32_t forces_valid; /* nonzero: out->f* already hold the forces of the current positions */
+    int32_t pad_;
+} nep_md;
+
+typedef struct {
+    int64_t n_rebuilds;   /* neighbour rebuilds during the chunk */
+    double dt_last;       /* fs, the last step length */
+    double time;          /* fs, simulated time of the chunk */
+} nep_md_stats;
+
+/* Create a context for the given hyperparameters and capacities; weights are
+ * set with nep_set_weights.  Allocates device memory on the current device.
+ * Returns NEP_OK, NEP_E_ARG, NEP_E_UNSUPPORTED or NEP_E_HIP; *out is NULL on error. */
+int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out);
+
+/* Free the context and its device memory (synchronises the device). NULL is allowed. */
+void nep_destroy(nep_ctx *ctx);
+
+/* Copy the model parameters into the context.  weights_on_device = 0: the
+ * pointers are host memory (copied synchronously); 1: device memory (copied
+ * asynchronously on `stream`).  Returns NEP_OK, NEP_E_ARG or NEP_E_HIP. */
+int nep_set_weights(nep_ctx *ctx, const nep_weights *w, int32_t weights_on_device, void *stream);
+
+/* Build the cell list and the neighbour lists (radius rc + skin) of `sys`.
+ * Positions may lie anywhere; they are wrapped into the cell internally.
+ * Overflow of a list capacity latches NEP_E_NEIGH_OVERFLOW.
+ * Returns NEP_OK, NEP_E_ARG or NEP_E_HIP. */
+int nep_build_neighbors(nep_ctx *ctx, const nep_system *sys, void *stream);
+
+/* Energy, forces and virial of `sys` at its current positions, using the
+ * neighbour lists of the last nep_build_neighbors on the same system (atoms
+ * may have moved by less than skin/2 since).  Returns NEP_OK, NEP_E_ARG,
+ * NEP_E_STATE or NEP_E_HIP. */
+int nep_compute_efv(nep_ctx *ctx, const nep_system *sys, nep_efv *out, void *stream);
+
+/* Advance `sys` by n_steps velocity-Verlet steps (x, v updated in place), with
+ * the adaptive step of `md`, rebuilding the neighbour lists on the device when
+ * an atom has moved more than skin/2 since the last build.  On return `out`
+ * holds energy, forces and virial of the final positions.  Synchronises
+ * `stream` at the end; returns NEP_OK or the first latched device error, or
+ * NEP_E_ARG / NEP_E_HIP.  `stats` may be NULL. */
+int nep_step_verlet(nep_ctx *ctx, nep_system *sys, const nep_md *md, int32_t n_steps,
+                    nep_efv *out, nep_md_stats *stats, void *stream);
+
+/* Synchronise `stream`, return the latched device error (NEP_OK if none) and clear it. */
+int nep_status(nep_ctx *ctx, void *stream);
+
+/* After NEP_E_NEIGH_OVERFLOW: the per-atom list lengths the last build needed. */
+int nep_required_neighbors(nep_ctx *ctx, int32_t *ang, int32_t *rad);
+
+/* Mean neighbour counts inside the cutoffs at the last nep_compute_efv
+ * (synchronises `stream`); used for algorithmic-flop accounting. */
+int nep_mean_neighbors(nep_ctx *ctx, void *stream, double *mean_rad, double *mean_ang);
+
+/* Measurement support: run the evaluation path of nep_compute_efv `reps`
+ * times, each kernel bracketed by HIP events recorded on `stream`, and return
+ * the mean duration per launch in milliseconds:
+ *   ms[0] position refresh, ms[1] descriptor + network kernel,
+ *   ms[2] force + virial kernel, ms[3] energy / virial reductions.
+ * Synchronises `stream`.  Same preconditions as nep_compute_efv. */
+int nep_time_efv(nep_ctx *ctx, const nep_system *sys, nep_efv *out, int32_t reps, double *ms, void *stream);
+
+/* Static description of an error code. */
+const char *nep_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEP_H */

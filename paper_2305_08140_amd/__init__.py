@@ -1,0 +1,297 @@
+"""MI355X NEP-ZBL energy / force / virial library (HIP, gfx950).
+
+A thin ctypes binding over ``libnep_hip.so``: it marshals arguments into the
+C ABI declared in ``include/nep.h`` and nothing else.  Every step of the
+computation runs in the library's HIP kernels; PyTorch only provides device
+memory and the current stream.  If the library has not been built the
+import of the context raises: there is no CPU fallback.
+
+Build:  python -m paper_2305_08140_amd.build
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnep_hip.so")
+
+NEP_OK = 0
+NEP_E_ARG = -1
+NEP_E_HIP = -2
+NEP_E_NEIGH_OVERFLOW = -3
+NEP_E_OVERLAP = -4
+NEP_E_NONFINITE = -5
+NEP_E_DT_UNDERFLOW = -6
+NEP_E_STATE = -7
+NEP_E_UNSUPPORTED = -8
+
+EXPORTED = ("nep_create", "nep_destroy", "nep_set_weights", "nep_build_neighbors", "nep_compute_efv",
+            "nep_step_verlet", "nep_status", "nep_required_neighbors", "nep_mean_neighbors",
+            "nep_time_efv", "nep_strerror")
+
+
+class NepError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+class Hparams(C.Structure):
+    _fields_ = [("n_rad", C.c_int32), ("n_ang", C.c_int32), ("k_rad", C.c_int32), ("k_ang", C.c_int32),
+                ("l_max", C.c_int32), ("n_hidden", C.c_int32), ("Z", C.c_int32), ("pad_", C.c_int32),
+                ("rc_rad", C.c_double), ("rc_ang", C.c_double), ("zbl_r1", C.c_double),
+                ("zbl_r2", C.c_double)]
+
+
+class Weights(C.Structure):
+    _fields_ = [("c_rad", C.c_void_p), ("c_ang", C.c_void_p), ("q_scale", C.c_void_p), ("w0", C.c_void_p),
+                ("b0", C.c_void_p), ("w1", C.c_void_p), ("b1", C.c_float), ("pad_", C.c_int32)]
+
+
+class Config(C.Structure):
+    _fields_ = [("max_atoms", C.c_int64), ("max_cells", C.c_int32), ("max_neigh_ang", C.c_int32),
+                ("max_neigh_rad", C.c_int32), ("pad_", C.c_int32), ("skin", C.c_double)]
+
+
+class System(C.Structure):
+    _fields_ = [("n_atoms", C.c_int64), ("n_cells", C.c_int32), ("pbc", C.c_int32 * 3),
+                ("cell_start", C.c_void_p), ("h", C.c_void_p),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("vx", C.c_void_p), ("vy", C.c_void_p), ("vz", C.c_void_p), ("mass", C.c_double)]
+
+
+class Efv(C.Structure):
+    _fields_ = [("energy", C.c_void_p), ("fx", C.c_void_p), ("fy", C.c_void_p), ("fz", C.c_void_p),
+                ("virial", C.c_void_p), ("energy_atom", C.c_void_p)]
+
+
+class Md(C.Structure):
+    _fields_ = [("dt_max", C.c_double), ("max_disp", C.c_double), ("dt_min", C.c_double),
+                ("forces_valid", C.c_int32), ("pad_", C.c_int32)]
+
+
+class MdStats(C.Structure):
+    _fields_ = [("n_rebuilds", C.c_int64), ("dt_last", C.c_double), ("time", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libnep_hip.so; raises if it is missing (build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_2305_08140_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.nep_create.argtypes = [C.POINTER(Hparams), C.POINTER(Config), C.POINTER(P)]
+        L.nep_destroy.argtypes = [P]
+        L.nep_destroy.restype = None
+        L.nep_set_weights.argtypes = [P, C.POINTER(Weights), C.c_int32, P]
+        L.nep_build_neighbors.argtypes = [P, C.POINTER(System), P]
+        L.nep_compute_efv.argtypes = [P, C.POINTER(System), C.POINTER(Efv), P]
+        L.nep_step_verlet.argtypes = [P, C.POINTER(System), C.POINTER(Md), C.c_int32, C.POINTER(Efv),
+                                      C.POINTER(MdStats), P]
+        L.nep_status.argtypes = [P, P]
+        L.nep_required_neighbors.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.nep_mean_neighbors.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.nep_time_efv.argtypes = [P, C.POINTER(System), C.POINTER(Efv), C.c_int32, C.POINTER(C.c_double), P]
+        L.nep_strerror.argtypes = [C.c_int]
+        L.nep_strerror.restype = C.c_char_p
+        for name in EXPORTED:
+            if name not in ("nep_destroy", "nep_strerror"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().nep_strerror(int(code)).decode()
+    except ImportError:
+        return "error %d" % code
+
+
+def _check(code: int, where: str):
+    if code != NEP_OK:
+        raise NepError(code, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class DeviceSystem:
+    """Positions / velocities in device memory plus the host-side cell description."""
+
+    def __init__(self, pos, h, cell_start=None, vel=None, pbc=(1, 1, 1), mass=183.84, device="cuda"):
+        torch = _torch()
+        pos = np.asarray(pos, dtype=np.float64)
+        n = pos.shape[0]
+        self.h = np.ascontiguousarray(np.asarray(h, dtype=np.float64).reshape(-1, 9))
+        self.n_cells = self.h.shape[0]
+        if cell_start is None:
+            cell_start = np.array([0, n], dtype=np.int64)
+        self.cell_start = np.ascontiguousarray(cell_start, dtype=np.int64)
+        self.pbc = tuple(int(p) for p in pbc)
+        self.mass = float(mass)
+        p = torch.from_numpy(np.ascontiguousarray(pos.T)).to(device)
+        self.x, self.y, self.z = p[0].contiguous(), p[1].contiguous(), p[2].contiguous()
+        if vel is None:
+            vel = np.zeros_like(pos)
+        v = torch.from_numpy(np.ascontiguousarray(np.asarray(vel, dtype=np.float64).T)).to(device)
+        self.vx, self.vy, self.vz = v[0].contiguous(), v[1].contiguous(), v[2].contiguous()
+        self.n_atoms = n
+
+    @classmethod
+    def from_synth(cls, s, device="cuda"):
+        return cls(s.pos, s.h, s.cell_start, s.vel, s.pbc, s.mass, device)
+
+    def positions(self):
+        torch = _torch()
+        return torch.stack([self.x, self.y, self.z], dim=1)
+
+    def velocities(self):
+        torch = _torch()
+        return torch.stack([self.vx, self.vy, self.vz], dim=1)
+
+    def c_struct(self) -> System:
+        s = System()
+        s.n_atoms = self.n_atoms
+        s.n_cells = self.n_cells
+        for a in range(3):
+            s.pbc[a] = self.pbc[a]
+        s.cell_start = self.cell_start.ctypes.data
+        s.h = self.h.ctypes.data
+        s.x, s.y, s.z = self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr()
+        s.vx, s.vy, s.vz = self.vx.data_ptr(), self.vy.data_ptr(), self.vz.data_ptr()
+        s.mass = self.mass
+        return s
+
+
+class EFV:
+    """Output buffers: energy [C] f64, fx/fy/fz [N] f32, virial [C,9] f64, energy_atom [N] f32."""
+
+    def __init__(self, n_atoms, n_cells, device="cuda", energy_atom=True):
+        torch = _torch()
+        self.energy = torch.zeros(n_cells, dtype=torch.float64, device=device)
+        self.fx = torch.zeros(n_atoms, dtype=torch.float32, device=device)
+        self.fy = torch.zeros(n_atoms, dtype=torch.float32, device=device)
+        self.fz = torch.zeros(n_atoms, dtype=torch.float32, device=device)
+        self.virial = torch.zeros(n_cells, 9, dtype=torch.float64, device=device)
+        self.energy_atom = torch.zeros(n_atoms, dtype=torch.float32, device=device) if energy_atom else None
+
+    def forces(self):
+        torch = _torch()
+        return torch.stack([self.fx, self.fy, self.fz], dim=1)
+
+    def c_struct(self) -> Efv:
+        e = Efv()
+        e.energy = self.energy.data_ptr()
+        e.fx, e.fy, e.fz = self.fx.data_ptr(), self.fy.data_ptr(), self.fz.data_ptr()
+        e.virial = self.virial.data_ptr()
+        e.energy_atom = self.energy_atom.data_ptr() if self.energy_atom is not None else None
+        return e
+
+
+def hparams_from(m) -> Hparams:
+    return Hparams(m.n_rad, m.n_ang, m.k_rad, m.k_ang, m.l_max, m.n_hidden, int(m.Z), 0,
+                   m.rc_rad, m.rc_ang, m.zbl_r1, m.zbl_r2)
+
+
+class Context:
+    """One nep_ctx: model, capacities and the neighbour-list state."""
+
+    def __init__(self, model, max_atoms, max_cells=1, max_neigh_ang=48, max_neigh_rad=96, skin=1.0,
+                 check=True):
+        self._ptr = None
+        self.check = check
+        L = lib()
+        hp = hparams_from(model)
+        cfg = Config(int(max_atoms), int(max_cells), int(max_neigh_ang), int(max_neigh_rad), 0, float(skin))
+        ptr = C.c_void_p()
+        _check(L.nep_create(C.byref(hp), C.byref(cfg), C.byref(ptr)), "nep_create")
+        self._ptr = ptr
+        self.nep_set_weights(model)
+
+    def __del__(self):
+        if getattr(self, "_ptr", None) is not None and _lib is not None:
+            _lib.nep_destroy(self._ptr)
+            self._ptr = None
+
+    def close(self):
+        self.__del__()
+
+    def nep_set_weights(self, model):
+        arrs = [np.ascontiguousarray(getattr(model, k), dtype=np.float32)
+                for k in ("c_rad", "c_ang", "q_scale", "w0", "b0", "w1")]
+        w = Weights(*[a.ctypes.data for a in arrs], float(model.b1), 0)
+        _check(lib().nep_set_weights(self._ptr, C.byref(w), 0, None), "nep_set_weights")
+
+    def nep_build_neighbors(self, system: DeviceSystem, stream=None):
+        s = system.c_struct()
+        _check(lib().nep_build_neighbors(self._ptr, C.byref(s), _stream_ptr(stream)), "nep_build_neighbors")
+        if self.check:
+            self.nep_status(stream)
+
+    def nep_compute_efv(self, system: DeviceSystem, out: EFV, stream=None):
+        s = system.c_struct()
+        o = out.c_struct()
+        _check(lib().nep_compute_efv(self._ptr, C.byref(s), C.byref(o), _stream_ptr(stream)), "nep_compute_efv")
+        if self.check:
+            self.nep_status(stream)
+        return out
+
+    def nep_step_verlet(self, system: DeviceSystem, n_steps, out: EFV, dt_max=1.0, max_disp=0.0, dt_min=1e-6,
+                        forces_valid=False, stream=None):
+        s = system.c_struct()
+        o = out.c_struct()
+        md = Md(float(dt_max), float(max_disp), float(dt_min), int(bool(forces_valid)), 0)
+        st = MdStats()
+        _check(lib().nep_step_verlet(self._ptr, C.byref(s), C.byref(md), int(n_steps), C.byref(o), C.byref(st),
+                                     _stream_ptr(stream)), "nep_step_verlet")
+        return {"n_rebuilds": int(st.n_rebuilds), "dt_last": float(st.dt_last), "time": float(st.time)}
+
+    def nep_status(self, stream=None):
+        _check(lib().nep_status(self._ptr, _stream_ptr(stream)), "device status")
+
+    def nep_required_neighbors(self):
+        a, r = C.c_int32(), C.c_int32()
+        _check(lib().nep_required_neighbors(self._ptr, C.byref(a), C.byref(r)), "nep_required_neighbors")
+        return int(a.value), int(r.value)
+
+    def nep_time_efv(self, system: DeviceSystem, out: EFV, reps=5, stream=None):
+        """Mean per-launch milliseconds of (position refresh, descriptor, force, reductions)."""
+        s = system.c_struct()
+        o = out.c_struct()
+        ms = (C.c_double * 4)()
+        _check(lib().nep_time_efv(self._ptr, C.byref(s), C.byref(o), int(reps), ms, _stream_ptr(stream)),
+               "nep_time_efv")
+        return {"sort": ms[0], "descriptor": ms[1], "force": ms[2], "reduce": ms[3]}
+
+    def nep_mean_neighbors(self, stream=None):
+        r, a = C.c_double(), C.c_double()
+        _check(lib().nep_mean_neighbors(self._ptr, _stream_ptr(stream), C.byref(r), C.byref(a)),
+               "nep_mean_neighbors")
+        return float(r.value), float(a.value)
+
+
+def efv(model, system: DeviceSystem, ctx: Context | None = None, max_neigh_ang=48, max_neigh_rad=96, skin=1.0):
+    """Convenience: build lists and evaluate once; returns (EFV, Context)."""
+    if ctx is None:
+        ctx = Context(model, system.n_atoms, system.n_cells, max_neigh_ang, max_neigh_rad, skin)
+    out = EFV(system.n_atoms, system.n_cells)
+    ctx.nep_build_neighbors(system)
+    ctx.nep_compute_efv(system, out)
+    return out, ctx

@@ -1,0 +1,631 @@
+// Host side of the C ABI declared in include/nep.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "nep.h"
+#include "nep_device.h"
+
+namespace nep {
+// kernels (nep_kernels.hip)
+__global__ void k_descriptor(PairConsts, const double *, const double *, const double *, const int32_t *,
+                             const CellGeom *, const int32_t *, const int32_t *, const uint32_t *,
+                             const float *, float *, float *, double *, int32_t *, int);
+__global__ void k_force(PairConsts, const double *, const double *, const double *, const int32_t *,
+                        const CellGeom *, const int32_t *, const int32_t *, const uint32_t *, const float *,
+                        const float *, const float *, const int32_t *, float *, float *, float *, float *,
+                        const int32_t *, int);
+__global__ void k_reduce_chunks(const int32_t *, const int32_t *, const double *, const float *, double *,
+                                const int32_t *);
+__global__ void k_reduce_cells(int, const int32_t *, const double *, double *, double *, const int32_t *);
+__global__ void k_energy_atom_out(int, const int32_t *, const double *, float *);
+__global__ void k_count_inside(PairConsts, const double *, const double *, const double *, const int32_t *,
+                               const CellGeom *, const int32_t *, const int32_t *, const uint32_t *,
+                               unsigned long long *);
+// kernels (nep_build.hip)
+__global__ void k_fill_i32(int, int32_t *, int32_t, const int32_t *);
+__global__ void k_bin_assign(int, const double *, const double *, const double *, const int32_t *,
+                             const CellGeom *, int32_t *, int32_t *, int32_t *, double *, int32_t *,
+                             const int32_t *);
+__global__ void k_scan_blocks(int, const int32_t *, int32_t *, int32_t *, const int32_t *);
+__global__ void k_scan_sums(int, int32_t *, const int32_t *);
+__global__ void k_scan_add(int, int32_t *, const int32_t *, const int32_t *);
+__global__ void k_bin_scatter(int, const int32_t *, const int32_t *, int32_t *, int32_t *, const int32_t *);
+__global__ void k_bin_rank(int, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
+                           const CellGeom *, int32_t *, int32_t *, const int32_t *);
+__global__ void k_sort_positions(int, const int32_t *, const double *, const double *, const double *,
+                                 const int32_t *, const int32_t *, const CellGeom *, double *, double *,
+                                 double *, int32_t *);
+__global__ void k_build_lists(PairConsts, double, double, double, double, const double *, const double *,
+                              const double *, const int32_t *, const CellGeom *, const int32_t *,
+                              const int32_t *, int32_t *, int32_t *, uint32_t *, int32_t *, const int32_t *);
+__global__ void k_kick_drift(int, double *, double *, double *, double *, double *, double *, const float *,
+                             const float *, const float *, double, const double *, double *, int32_t *);
+__global__ void k_kick(int, double *, double *, double *, const float *, const float *, const float *, double,
+                       double *, const int32_t *);
+__global__ void k_vmax(int, const double *, const double *, const double *, double *);
+__global__ void k_dt_update(double, double, double, double *, int32_t *, int);
+__global__ void k_rebuild_flag(double, double *, int32_t *);
+__global__ void k_disp(int, const double *, const double *, const double *, const double *, double *);
+__global__ void k_set_flag(int32_t *, int32_t);
+__global__ void k_cell_of(int, int, const int64_t *, int32_t *);
+}  // namespace nep
+
+using namespace nep;
+
+// (eV / u) -> (A / fs)^2, i.e. an acceleration F/m in eV/(u A) to A/fs^2
+// (e = 1.602176634e-19 C, u = 1.66053906660e-27 kg).
+static const double ACC_EV_U_A = 9.6485332156653280e-3;
+
+#define HIP_TRY(x)                                   \
+    do {                                             \
+        if ((x) != hipSuccess) return NEP_E_HIP;     \
+    } while (0)
+
+struct nep_ctx {
+    nep_hparams hp;
+    nep_config cfg;
+    int device = 0;
+    float *params = nullptr;
+    // per-atom storage (capacity cfg.max_atoms)
+    double *xs = nullptr;        // [3][N] sorted wrapped positions
+    double *xref = nullptr;      // [3][N] caller-order positions at the last build
+    int32_t *perm = nullptr, *bin_of = nullptr, *wrap = nullptr, *cell_of = nullptr, *tmp = nullptr,
+            *bin_sorted = nullptr;
+    uint32_t *ncnt = nullptr;
+    int32_t *nl_ang = nullptr, *nl_rad = nullptr;
+    float *adj_r = nullptr, *adj_a = nullptr, *w_atom = nullptr;
+    double *e_atom = nullptr;
+    // per-cell storage
+    CellGeom *cells = nullptr;
+    int64_t *cell_start_d = nullptr;
+    int32_t *chunk_begin = nullptr, *chunk_end = nullptr, *cell_chunk = nullptr;
+    double *part = nullptr;
+    int n_chunks = 0, chunk_cap = 0;
+    // bins
+    int32_t *bin_count = nullptr, *bin_start = nullptr, *bin_fill = nullptr, *scan_sums = nullptr;
+    int64_t bin_cap = 0;
+    int n_bins = 0;
+    // status and md state
+    int32_t *status = nullptr;       // [8]
+    int32_t *flag = nullptr;         // rebuild flag
+    double *md = nullptr;            // [8]
+    unsigned long long *counts = nullptr;
+    int32_t *h_status = nullptr;     // pinned
+    double *h_md = nullptr;          // pinned
+    unsigned long long *h_counts = nullptr;
+    // state of the last build
+    bool built = false;
+    int64_t built_n = -1;
+    int built_cells = -1;
+    std::vector<double> built_h;
+    std::vector<int64_t> built_start;
+    int pbc[3] = {1, 1, 1};
+    PairConsts pc;
+    std::vector<CellGeom> geom;
+};
+
+static int grid_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+static int xcd_grid(int tiles) { return 8 * ((tiles + 7) / 8); }
+
+static void inv3(const double *h, double *hi)
+{
+    const double a = h[0], b = h[1], c = h[2], d = h[3], e = h[4], f = h[5], g = h[6], k = h[7], l = h[8];
+    const double det = a * (e * l - f * k) - b * (d * l - f * g) + c * (d * k - e * g);
+    hi[0] = (e * l - f * k) / det; hi[1] = (c * k - b * l) / det; hi[2] = (b * f - c * e) / det;
+    hi[3] = (f * g - d * l) / det; hi[4] = (a * l - c * g) / det; hi[5] = (c * d - a * f) / det;
+    hi[6] = (d * k - e * g) / det; hi[7] = (b * g - a * k) / det; hi[8] = (a * e - b * d) / det;
+}
+
+extern "C" {
+
+const char *nep_strerror(int code)
+{
+    switch (code) {
+    case NEP_OK: return "ok";
+    case NEP_E_ARG: return "invalid argument";
+    case NEP_E_HIP: return "HIP runtime error";
+    case NEP_E_NEIGH_OVERFLOW: return "neighbour list capacity exceeded";
+    case NEP_E_OVERLAP: return "overlapping atoms (distance below 1e-3 A)";
+    case NEP_E_NONFINITE: return "non-finite position or velocity";
+    case NEP_E_DT_UNDERFLOW: return "adaptive time step below dt_min";
+    case NEP_E_STATE: return "neighbour lists not built for this system";
+    case NEP_E_UNSUPPORTED: return "hyperparameters not supported by the compiled kernels";
+    default: return "unknown error";
+    }
+}
+
+void nep_destroy(nep_ctx *c)
+{
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    void *bufs[] = {c->params, c->xs, c->xref, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
+                    c->bin_sorted, c->ncnt, c->nl_ang, c->nl_rad, c->adj_r, c->adj_a, c->w_atom,
+                    c->e_atom, c->cells, c->cell_start_d, c->chunk_begin, c->chunk_end, c->cell_chunk,
+                    c->part, c->bin_count, c->bin_start, c->bin_fill, c->scan_sums, c->status, c->flag,
+                    c->md, c->counts};
+    for (void *p : bufs)
+        if (p) hipFree(p);
+    if (c->h_status) hipHostFree(c->h_status);
+    if (c->h_md) hipHostFree(c->h_md);
+    if (c->h_counts) hipHostFree(c->h_counts);
+    delete c;
+}
+
+int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
+{
+    if (!out) return NEP_E_ARG;
+    *out = nullptr;
+    if (!hp || !cfg) return NEP_E_ARG;
+    if (hp->n_rad != NR || hp->n_ang != NA || hp->k_rad != KB || hp->k_ang != KB || hp->l_max != LMAX ||
+        hp->n_hidden != NH)
+        return NEP_E_UNSUPPORTED;
+    if (!(hp->rc_rad > 0 && hp->rc_ang > 0 && hp->rc_ang <= hp->rc_rad && hp->zbl_r1 >= 0 &&
+          hp->zbl_r2 > hp->zbl_r1 && hp->zbl_r2 <= hp->rc_ang && hp->Z > 0))
+        return NEP_E_ARG;
+    if (cfg->max_atoms <= 0 || cfg->max_atoms > (1LL << 26) || cfg->max_cells <= 0 ||
+        cfg->max_neigh_ang <= 0 || cfg->max_neigh_ang > 255 || cfg->max_neigh_rad <= 0 ||
+        cfg->max_neigh_rad > 255 || !(cfg->skin >= 0.0))
+        return NEP_E_ARG;
+    nep_ctx *c = new nep_ctx();
+    c->hp = *hp;
+    c->cfg = *cfg;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return NEP_E_HIP; }
+    const size_t N = (size_t)cfg->max_atoms;
+    bool ok = true;
+    auto A = [&](void **p, size_t bytes) {
+        if (ok && hipMalloc(p, bytes > 0 ? bytes : 16) != hipSuccess) ok = false;
+    };
+    A((void **)&c->params, P_SIZE * sizeof(float));
+    A((void **)&c->xs, 3 * N * sizeof(double));
+    A((void **)&c->xref, 3 * N * sizeof(double));
+    A((void **)&c->perm, N * 4);
+    A((void **)&c->bin_of, N * 4);
+    A((void **)&c->wrap, N * 4);
+    A((void **)&c->cell_of, N * 4);
+    A((void **)&c->tmp, N * 4);
+    A((void **)&c->bin_sorted, N * 4);
+    A((void **)&c->ncnt, N * 4);
+    A((void **)&c->nl_ang, N * cfg->max_neigh_ang * 4);
+    A((void **)&c->nl_rad, N * cfg->max_neigh_rad * 4);
+    A((void **)&c->adj_r, N * ADJ_R * 4);
+    A((void **)&c->adj_a, N * ADJ_A * 4);
+    A((void **)&c->w_atom, N * 9 * 4);
+    A((void **)&c->e_atom, N * 8);
+    A((void **)&c->cells, (size_t)cfg->max_cells * sizeof(CellGeom));
+    A((void **)&c->cell_start_d, ((size_t)cfg->max_cells + 1) * 8);
+    A((void **)&c->status, 8 * 4);
+    A((void **)&c->flag, 4);
+    A((void **)&c->md, 8 * 8);
+    A((void **)&c->counts, 2 * 8);
+    if (ok && hipHostMalloc((void **)&c->h_status, 8 * 4, hipHostMallocDefault) != hipSuccess) ok = false;
+    if (ok && hipHostMalloc((void **)&c->h_md, 8 * 8, hipHostMallocDefault) != hipSuccess) ok = false;
+    if (ok && hipHostMalloc((void **)&c->h_counts, 2 * 8, hipHostMallocDefault) != hipSuccess) ok = false;
+    if (ok && hipMemset(c->status, 0, 8 * 4) != hipSuccess) ok = false;
+    if (ok && hipMemset(c->md, 0, 8 * 8) != hipSuccess) ok = false;
+    if (ok && hipMemset(c->params, 0, P_SIZE * sizeof(float)) != hipSuccess) ok = false;
+    if (ok && hipDeviceSynchronize() != hipSuccess) ok = false;
+    if (!ok) { nep_destroy(c); return NEP_E_HIP; }
+    *out = c;
+    return NEP_OK;
+}
+
+int nep_set_weights(nep_ctx *c, const nep_weights *w, int32_t on_device, void *stream)
+{
+    if (!c || !w || !w->c_rad || !w->c_ang || !w->q_scale || !w->w0 || !w->b0 || !w->w1) return NEP_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    struct { const float *src; int off, n; } parts[] = {
+        {w->c_rad, P_CR, NR * KB}, {w->c_ang, P_CA, NA * KB}, {w->q_scale, P_QS, DIM},
+        {w->w0, P_W0, NH * DIM},   {w->b0, P_B0, NH},         {w->w1, P_W1, NH}};
+    for (auto &p : parts) {
+        if (on_device) HIP_TRY(hipMemcpyAsync(c->params + p.off, p.src, p.n * 4, kind, s));
+        else HIP_TRY(hipMemcpy(c->params + p.off, p.src, p.n * 4, kind));
+    }
+    if (on_device) {
+        // b1 is a host scalar even when the arrays live on the device
+        HIP_TRY(hipMemcpyAsync(c->params + P_B1, &w->b1, 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    } else {
+        HIP_TRY(hipMemcpy(c->params + P_B1, &w->b1, 4, hipMemcpyHostToDevice));
+    }
+    return NEP_OK;
+}
+
+static int check_system(const nep_ctx *c, const nep_system *s, bool need_vel)
+{
+    if (!s || !s->x || !s->y || !s->z || !s->h) return NEP_E_ARG;
+    if (s->n_atoms <= 0 || s->n_atoms > c->cfg.max_atoms) return NEP_E_ARG;
+    const int nc = s->cell_start ? s->n_cells : 1;
+    if (nc <= 0 || nc > c->cfg.max_cells) return NEP_E_ARG;
+    if (s->cell_start) {
+        if (s->cell_start[0] != 0 || s->cell_start[nc] != s->n_atoms) return NEP_E_ARG;
+        for (int k = 0; k < nc; ++k)
+            if (s->cell_start[k + 1] <= s->cell_start[k]) return NEP_E_ARG;
+    }
+    if (need_vel && (!s->vx || !s->vy || !s->vz || !(s->mass > 0))) return NEP_E_ARG;
+    return NEP_OK;
+}
+
+static bool same_system(const nep_ctx *c, const nep_system *s)
+{
+    const int nc = s->cell_start ? s->n_cells : 1;
+    if (!c->built || c->built_n != s->n_atoms || c->built_cells != nc) return false;
+    for (int a = 0; a < 3; ++a)
+        if (c->pbc[a] != (s->pbc[a] ? 1 : 0)) return false;
+    if (memcmp(c->built_h.data(), s->h, (size_t)nc * 9 * sizeof(double)) != 0) return false;
+    if (s->cell_start && memcmp(c->built_start.data(), s->cell_start, (size_t)(nc + 1) * 8) != 0) return false;
+    return true;
+}
+
+// Geometry, bins and reduction chunks of a new system (host decisions).
+static int setup_system(nep_ctx *c, const nep_system *s, hipStream_t st)
+{
+    const int nc = s->cell_start ? s->n_cells : 1;
+    const int64_t n = s->n_atoms;
+    std::vector<int64_t> start(nc + 1);
+    if (s->cell_start) for (int k = 0; k <= nc; ++k) start[k] = s->cell_start[k];
+    else { start[0] = 0; start[1] = n; }
+    const double lcut = c->hp.rc_rad + c->cfg.skin;
+    c->geom.assign(nc, CellGeom());
+    int64_t nbins = 0;
+    bool small_images = false;
+    int64_t max_cell_atoms = 0;
+    for (int k = 0; k < nc; ++k) {
+        CellGeom &g = c->geom[k];
+        memset(&g, 0, sizeof g);
+        memcpy(g.h, s->h + 9 * k, 9 * sizeof(double));
+        inv3(g.h, g.hinv);
+        if (!std::isfinite(g.hinv[0]) || !std::isfinite(g.hinv[4]) || !std::isfinite(g.hinv[8])) return NEP_E_ARG;
+        for (int a = 0; a < 3; ++a) {
+            const double q = g.hinv[0 * 3 + a] * g.hinv[0 * 3 + a] + g.hinv[1 * 3 + a] * g.hinv[1 * 3 + a] +
+                             g.hinv[2 * 3 + a] * g.hinv[2 * 3 + a];
+            const double width = 1.0 / std::sqrt(q);
+            g.periodic[a] = s->pbc[a] ? 1 : 0;
+            int nb = (int)std::floor(width / lcut);
+            if (g.periodic[a]) {
+                if (nb >= 3) { g.nb[a] = nb; g.R[a] = 0; }
+                else {
+                    g.nb[a] = 1;
+                    g.R[a] = (int)std::ceil(lcut / width);
+                    if (g.R[a] > 1) small_images = true;
+                    if (g.R[a] > 7) return NEP_E_ARG;   // cell thinner than (rc + skin) / 7
+                }
+            } else {
+                g.nb[a] = nb < 1 ? 1 : (nb > 4096 ? 4096 : nb);
+                g.R[a] = 0;
+            }
+        }
+        const int64_t cb = (int64_t)g.nb[0] * g.nb[1] * g.nb[2];
+        if (cb > (1 << 28)) return NEP_E_ARG;
+        g.bin_offset = (int)nbins;
+        nbins += cb;
+        g.atom_start = (int)start[k];
+        g.n_atoms = (int)(start[k + 1] - start[k]);
+        max_cell_atoms = std::max<int64_t>(max_cell_atoms, g.n_atoms);
+    }
+    if (nbins > (1LL << 30)) return NEP_E_ARG;
+    PairConsts &pc = c->pc;
+    pc.rc_rad = (float)c->hp.rc_rad;
+    pc.rc_ang = (float)c->hp.rc_ang;
+    pc.rc_rad2 = pc.rc_rad * pc.rc_rad;
+    pc.rc_ang2 = pc.rc_ang * pc.rc_ang;
+    pc.inv_rc_rad = (float)(1.0 / c->hp.rc_rad);
+    pc.inv_rc_ang = (float)(1.0 / c->hp.rc_ang);
+    pc.inv_rc_rad_lo = (float)(1.0 / c->hp.rc_rad - (double)pc.inv_rc_rad);
+    pc.inv_rc_ang_lo = (float)(1.0 / c->hp.rc_ang - (double)pc.inv_rc_ang);
+    pc.zbl_r1 = (float)c->hp.zbl_r1;
+    pc.zbl_r2 = (float)c->hp.zbl_r2;
+    pc.zbl_r2sq = pc.zbl_r2 * pc.zbl_r2;
+    pc.zbl_z = (float)c->hp.Z;
+    pc.capA = c->cfg.max_neigh_ang;
+    pc.capR = c->cfg.max_neigh_rad;
+    if (small_images) { pc.ibits = 4; pc.ioff = 8; pc.jbits = 20; }
+    else { pc.ibits = 2; pc.ioff = 1; pc.jbits = 26; }
+    if (max_cell_atoms > (1LL << pc.jbits)) return NEP_E_ARG;
+    pc.n = (int)n;
+
+    // bins
+    if (nbins + 1 > c->bin_cap) {
+        if (c->bin_count) { hipFree(c->bin_count); hipFree(c->bin_start); hipFree(c->bin_fill); hipFree(c->scan_sums); }
+        c->bin_count = c->bin_start = c->bin_fill = c->scan_sums = nullptr;
+        c->bin_cap = 0;
+        const int64_t cap = nbins + 1;
+        HIP_TRY(hipMalloc(&c->bin_count, cap * 4));
+        HIP_TRY(hipMalloc(&c->bin_start, cap * 4));
+        HIP_TRY(hipMalloc(&c->bin_fill, cap * 4));
+        HIP_TRY(hipMalloc(&c->scan_sums, ((cap + 2047) / 2048 + 1) * 4));
+        c->bin_cap = cap;
+    }
+    c->n_bins = (int)nbins;
+
+    // reduction chunks: contiguous sorted-atom ranges that never span two cells
+    const int CH = 4096;
+    std::vector<int32_t> cb, ce, cc(nc + 1);
+    for (int k = 0; k < nc; ++k) {
+        cc[k] = (int32_t)cb.size();
+        for (int64_t a = start[k]; a < start[k + 1]; a += CH) {
+            cb.push_back((int32_t)a);
+            ce.push_back((int32_t)std::min<int64_t>(a + CH, start[k + 1]));
+        }
+    }
+    cc[nc] = (int32_t)cb.size();
+    const int nch = (int)cb.size();
+    if (nch > c->chunk_cap) {
+        if (c->chunk_begin) { hipFree(c->chunk_begin); hipFree(c->chunk_end); hipFree(c->part); }
+        c->chunk_begin = c->chunk_end = nullptr;
+        c->part = nullptr;
+        HIP_TRY(hipMalloc(&c->chunk_begin, nch * 4));
+        HIP_TRY(hipMalloc(&c->chunk_end, nch * 4));
+        HIP_TRY(hipMalloc(&c->part, (size_t)nch * 10 * 8));
+        c->chunk_cap = nch;
+    }
+    if (!c->cell_chunk) HIP_TRY(hipMalloc(&c->cell_chunk, ((size_t)c->cfg.max_cells + 1) * 4));
+    c->n_chunks = nch;
+    HIP_TRY(hipMemcpyAsync(c->chunk_begin, cb.data(), nch * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->chunk_end, ce.data(), nch * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->cell_chunk, cc.data(), (nc + 1) * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->cells, c->geom.data(), nc * sizeof(CellGeom), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->cell_start_d, start.data(), (nc + 1) * 8, hipMemcpyHostToDevice, st));
+    // cell index of every atom
+    k_cell_of<<<grid_for(n, 256), 256, 0, st>>>((int)n, nc, c->cell_start_d, c->cell_of);
+    HIP_TRY(hipGetLastError());
+    // the host vectors above are released on return: wait for the copies
+    HIP_TRY(hipStreamSynchronize(st));
+
+    c->built_n = n;
+    c->built_cells = nc;
+    c->built_h.assign(s->h, s->h + 9 * nc);
+    c->built_start = start;
+    for (int a = 0; a < 3; ++a) c->pbc[a] = s->pbc[a] ? 1 : 0;
+    return NEP_OK;
+}
+
+// Launch the list build on `st`; with `flag` non-NULL every kernel returns
+// at once unless *flag is set on the device.
+static int launch_build(nep_ctx *c, const nep_system *s, hipStream_t st, const int32_t *flag)
+{
+    const int n = (int)s->n_atoms;
+    const int nb1 = c->n_bins + 1;
+    k_fill_i32<<<grid_for(nb1, 256), 256, 0, st>>>(nb1, c->bin_count, 0, flag);
+    k_fill_i32<<<grid_for(nb1, 256), 256, 0, st>>>(nb1, c->bin_fill, 0, flag);
+    k_bin_assign<<<grid_for(n, 256), 256, 0, st>>>(n, s->x, s->y, s->z, c->cell_of, c->cells, c->bin_of,
+                                                   c->wrap, c->bin_count, c->xref, c->status, flag);
+    const int nblk = grid_for(nb1, 2048);
+    k_scan_blocks<<<nblk, 256, 0, st>>>(nb1, c->bin_count, c->bin_start, c->scan_sums, flag);
+    k_scan_sums<<<1, 256, 0, st>>>(nblk, c->scan_sums, flag);
+    k_scan_add<<<grid_for(nb1, 256), 256, 0, st>>>(nb1, c->bin_start, c->scan_sums, flag);
+    k_bin_scatter<<<grid_for(n, 256), 256, 0, st>>>(n, c->bin_of, c->bin_start, c->bin_fill, c->tmp, flag);
+    k_bin_rank<<<grid_for(n, 256), 256, 0, st>>>(n, c->bin_of, c->bin_start, c->tmp, c->cell_of, c->cells,
+                                                 c->perm, c->bin_sorted, flag);
+    // sorted positions are needed by the list build; unconditional is fine
+    // (every evaluation refreshes them anyway)
+    k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
+                                                       c->cells, c->xs, c->xs + c->cfg.max_atoms,
+                                                       c->xs + 2 * c->cfg.max_atoms, c->status);
+    const double lA = c->hp.rc_ang + c->cfg.skin, lR = c->hp.rc_rad + c->cfg.skin;
+    k_build_lists<<<grid_for(n, 256), 256, 0, st>>>(
+        c->pc, lA * lA, lR * lR, c->hp.rc_ang * c->hp.rc_ang, c->hp.rc_rad * c->hp.rc_rad, c->xs,
+        c->xs + c->cfg.max_atoms, c->xs + 2 * c->cfg.max_atoms, c->cell_of, c->cells, c->bin_sorted,
+        c->bin_start, c->nl_ang, c->nl_rad, c->ncnt, c->status, flag);
+    HIP_TRY(hipGetLastError());
+    return NEP_OK;
+}
+
+int nep_build_neighbors(nep_ctx *c, const nep_system *s, void *stream)
+{
+    if (!c) return NEP_E_ARG;
+    int rc = check_system(c, s, false);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (!same_system(c, s)) {
+        c->built = false;
+        rc = setup_system(c, s, st);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipMemsetAsync(c->status + ST_NEED_A, 0, 2 * 4, st));
+    rc = launch_build(c, s, st, nullptr);
+    if (rc) return rc;
+    c->built = true;
+    return NEP_OK;
+}
+
+// One evaluation: sorted positions, descriptor + network, forces, reductions.
+static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t st, bool refresh_positions)
+{
+    const int n = (int)s->n_atoms;
+    double *xs = c->xs, *ys = c->xs + c->cfg.max_atoms, *zs = c->xs + 2 * c->cfg.max_atoms;
+    if (refresh_positions)
+        k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
+                                                           c->cells, xs, ys, zs, c->status);
+    const int tiles = grid_for(n, 256);
+    k_descriptor<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xs, ys, zs, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
+                                                  c->ncnt, c->params, c->adj_r, c->adj_a, c->e_atom, c->status,
+                                                  tiles);
+    k_force<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xs, ys, zs, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
+                                             c->ncnt, c->params, c->adj_r, c->adj_a, c->perm, o->fx, o->fy, o->fz,
+                                             c->w_atom, c->status, tiles);
+    k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom, c->part,
+                                                 c->status);
+    k_reduce_cells<<<grid_for(c->built_cells, 64), 64, 0, st>>>(c->built_cells, c->cell_chunk, c->part,
+                                                                o->energy, o->virial, c->status);
+    if (o->energy_atom)
+        k_energy_atom_out<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, c->e_atom, o->energy_atom);
+    HIP_TRY(hipGetLastError());
+    return NEP_OK;
+}
+
+static int check_out(const nep_efv *o)
+{
+    if (!o || !o->energy || !o->fx || !o->fy || !o->fz) return NEP_E_ARG;
+    return NEP_OK;
+}
+
+int nep_compute_efv(nep_ctx *c, const nep_system *s, nep_efv *o, void *stream)
+{
+    if (!c) return NEP_E_ARG;
+    int rc = check_system(c, s, false);
+    if (rc) return rc;
+    if ((rc = check_out(o))) return rc;
+    if (!same_system(c, s)) return NEP_E_STATE;
+    return launch_efv(c, s, o, (hipStream_t)stream, true);
+}
+
+int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, double *ms, void *stream)
+{
+    if (!c || !ms || reps <= 0) return NEP_E_ARG;
+    int rc = check_system(c, s, false);
+    if (rc) return rc;
+    if ((rc = check_out(o))) return rc;
+    if (!same_system(c, s)) return NEP_E_STATE;
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)s->n_atoms;
+    double *xs = c->xs, *ys = c->xs + c->cfg.max_atoms, *zs = c->xs + 2 * c->cfg.max_atoms;
+    const int tiles = grid_for(n, 256);
+    hipEvent_t ev[5];
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    double acc[4] = {0, 0, 0, 0};
+    for (int r = 0; r < reps; ++r) {
+        HIP_TRY(hipEventRecord(ev[0], st));
+        k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
+                                                           c->cells, xs, ys, zs, c->status);
+        HIP_TRY(hipEventRecord(ev[1], st));
+        k_descriptor<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xs, ys, zs, c->cell_of, c->cells, c->nl_ang,
+                                                      c->nl_rad, c->ncnt, c->params, c->adj_r, c->adj_a,
+                                                      c->e_atom, c->status, tiles);
+        HIP_TRY(hipEventRecord(ev[2], st));
+        k_force<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xs, ys, zs, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
+                                                 c->ncnt, c->params, c->adj_r, c->adj_a, c->perm, o->fx, o->fy,
+                                                 o->fz, c->w_atom, c->status, tiles);
+        HIP_TRY(hipEventRecord(ev[3], st));
+        k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom,
+                                                     c->part, c->status);
+        k_reduce_cells<<<grid_for(c->built_cells, 64), 64, 0, st>>>(c->built_cells, c->cell_chunk, c->part,
+                                                                    o->energy, o->virial, c->status);
+        HIP_TRY(hipEventRecord(ev[4], st));
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventSynchronize(ev[4]));
+        for (int k = 0; k < 4; ++k) {
+            float t = 0.f;
+            HIP_TRY(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+            acc[k] += t;
+        }
+    }
+    for (auto &e : ev) HIP_TRY(hipEventDestroy(e));
+    for (int k = 0; k < 4; ++k) ms[k] = acc[k] / reps;
+    return NEP_OK;
+}
+
+int nep_status(nep_ctx *c, void *stream)
+{
+    if (!c) return NEP_E_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(c->h_status, c->status, 8 * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int code = c->h_status[ST_ERR];
+    if (code != 0) {
+        const int32_t zero = 0;
+        HIP_TRY(hipMemcpy(c->status + ST_ERR, &zero, 4, hipMemcpyHostToDevice));
+    }
+    return code;
+}
+
+int nep_required_neighbors(nep_ctx *c, int32_t *ang, int32_t *rad)
+{
+    if (!c || !ang || !rad) return NEP_E_ARG;
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(c->h_status, c->status, 8 * 4, hipMemcpyDeviceToHost));
+    *ang = c->h_status[ST_NEED_A];
+    *rad = c->h_status[ST_NEED_R];
+    return NEP_OK;
+}
+
+int nep_mean_neighbors(nep_ctx *c, void *stream, double *mean_rad, double *mean_ang)
+{
+    if (!c || !mean_rad || !mean_ang || !c->built) return NEP_E_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemsetAsync(c->counts, 0, 16, st));
+    const int n = c->pc.n;
+    k_count_inside<<<grid_for(n, 256), 256, 0, st>>>(c->pc, c->xs, c->xs + c->cfg.max_atoms,
+                                                     c->xs + 2 * c->cfg.max_atoms, c->cell_of, c->cells,
+                                                     c->nl_ang, c->nl_rad, c->ncnt, c->counts);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(c->h_counts, c->counts, 16, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *mean_rad = (double)c->h_counts[0] / n;
+    *mean_ang = (double)c->h_counts[1] / n;
+    return NEP_OK;
+}
+
+int nep_step_verlet(nep_ctx *c, nep_system *s, const nep_md *md, int32_t n_steps, nep_efv *o,
+                    nep_md_stats *stats, void *stream)
+{
+    if (!c || !md || n_steps < 0) return NEP_E_ARG;
+    int rc = check_system(c, s, true);
+    if (rc) return rc;
+    if ((rc = check_out(o))) return rc;
+    if (!(md->dt_max > 0) || !(md->max_disp >= 0) || !(md->dt_min >= 0)) return NEP_E_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)s->n_atoms;
+    const double acc = ACC_EV_U_A / s->mass;
+    const double half_skin2 = 0.25 * c->cfg.skin * c->cfg.skin;
+
+    // reset the step state (the pinned staging buffer is idle: the previous
+    // chunk synchronised before reading it)
+    for (int k = 0; k < 8; ++k) c->h_md[k] = 0.0;
+    HIP_TRY(hipMemcpyAsync(c->md, c->h_md, 8 * 8, hipMemcpyHostToDevice, st));
+    // lists valid for the current positions?
+    bool fresh = false;
+    if (!same_system(c, s)) {
+        c->built = false;
+        if ((rc = setup_system(c, s, st))) return rc;
+        if ((rc = launch_build(c, s, st, nullptr))) return rc;
+        c->built = true;
+        fresh = true;
+    } else {
+        k_disp<<<grid_for(n, 256), 256, 0, st>>>(n, s->x, s->y, s->z, c->xref, c->md);
+        k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag);
+        if ((rc = launch_build(c, s, st, c->flag))) return rc;
+    }
+    if (!md->forces_valid || fresh) {
+        if ((rc = launch_efv(c, s, o, st, true))) return rc;
+    }
+    (void)fresh;
+    // first step length from the initial velocities
+    k_vmax<<<grid_for(n, 256), 256, 0, st>>>(n, s->vx, s->vy, s->vz, c->md);
+    k_dt_update<<<1, 64, 0, st>>>(md->dt_max, md->max_disp, md->dt_min, c->md, c->status, 0);
+    // the rebuild counter counts rebuilds inside the chunk only
+    HIP_TRY(hipMemsetAsync(c->md + MD_NREB, 0, 8, st));
+    for (int k = 0; k < n_steps; ++k) {
+        k_kick_drift<<<grid_for(n, 256), 256, 0, st>>>(n, s->x, s->y, s->z, s->vx, s->vy, s->vz, o->fx, o->fy,
+                                                       o->fz, acc, c->xref, c->md, c->status);
+        k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag);
+        if ((rc = launch_build(c, s, st, c->flag))) return rc;
+        if ((rc = launch_efv(c, s, o, st, true))) return rc;
+        k_kick<<<grid_for(n, 256), 256, 0, st>>>(n, s->vx, s->vy, s->vz, o->fx, o->fy, o->fz, acc, c->md,
+                                                 c->status);
+        k_dt_update<<<1, 64, 0, st>>>(md->dt_max, md->max_disp, md->dt_min, c->md, c->status, 1);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(c->h_md, c->md, 8 * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(c->h_status, c->status, 8 * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (stats) {
+        stats->n_rebuilds = (int64_t)c->h_md[MD_NREB];
+        stats->dt_last = c->h_md[MD_DT];
+        stats->time = c->h_md[MD_TIME];
+    }
+    const int code = c->h_status[ST_ERR];
+    if (code != 0) {
+        const int32_t zero = 0;
+        HIP_TRY(hipMemcpy(c->status + ST_ERR, &zero, 4, hipMemcpyHostToDevice));
+    }
+    return code;
+}
+
+}  // extern "C"

@@ -1,0 +1,426 @@
+// Cell list, neighbour lists and velocity-Verlet kernels (gfx950).
+//
+// Cell list: every cell of the batch gets its own bin grid.  Along an axis
+// whose perpendicular width is at least 3 (rc + skin) the cell is cut into
+// nb >= 3 bins of width >= rc + skin and the search visits the bins b-1..b+1
+// (with periodic wrap); a narrower periodic axis gets one bin and the search
+// loops over the explicit images -R..R, R = ceil((rc + skin) / width), which
+// covers every image within reach (small cells see several images of the same
+// atom and their own images).  Atoms are counting-sorted by bin (stable in the
+// caller's index), and their wrapped FP64 positions are stored in that order.
+//
+// Neighbour lists: per atom two fixed-capacity columns (stored transposed,
+// [slot][atom], so that a wavefront reads them coalesced):
+//   angular list   r < rc_ang + skin:  r < rc_ang filled from the front,
+//                                      the skin shell from the back
+//   radial list    rc_ang + skin <= r < rc_rad + skin: r < rc_rad from the
+//                                      front, the skin shell from the back
+// so that the pair loops meet the inside-cutoff entries first and in the
+// same order on all lanes (little divergence).  An entry packs the neighbour's
+// index within its cell (jbits bits) with the image n in 3 fields of ibits.
+#include "nep_device.h"
+
+namespace nep {
+
+// ------------------------------------------------------------------ binning
+
+__device__ inline int pack_wrap(int w0, int w1, int w2)
+{
+    return ((w0 + 512) & 1023) | (((w1 + 512) & 1023) << 10) | (((w2 + 512) & 1023) << 20);
+}
+
+__device__ inline void unpack_wrap(int p, int &w0, int &w1, int &w2)
+{
+    w0 = (p & 1023) - 512;
+    w1 = ((p >> 10) & 1023) - 512;
+    w2 = ((p >> 20) & 1023) - 512;
+}
+
+__global__ void k_fill_i32(int n, int32_t *__restrict__ a, int32_t v, const int32_t *__restrict__ flag)
+{
+    if (flag && *flag == 0) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) a[t] = v;
+}
+
+// Per atom (caller order): bin, wrap count, bin histogram, reference position.
+__global__ void k_bin_assign(int n, const double *__restrict__ x, const double *__restrict__ y,
+                             const double *__restrict__ z, const int32_t *__restrict__ cell_of,
+                             const CellGeom *__restrict__ cells, int32_t *__restrict__ bin_of,
+                             int32_t *__restrict__ wrap, int32_t *__restrict__ bin_count,
+                             double *__restrict__ xref, int32_t *__restrict__ status,
+                             const int32_t *__restrict__ flag)
+{
+    if (flag && *flag == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const CellGeom &cg = cells[cell_of[i]];
+    const double p[3] = {x[i], y[i], z[i]};
+    if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) {
+        latch_error(status, -5);
+        bin_of[i] = cg.bin_offset;
+        wrap[i] = pack_wrap(0, 0, 0);
+        atomicAdd(bin_count + cg.bin_offset, 1);
+        return;
+    }
+    int w[3], b[3];
+    for (int a = 0; a < 3; ++a) {
+        double s = p[0] * cg.hinv[a] + p[1] * cg.hinv[3 + a] + p[2] * cg.hinv[6 + a];
+        w[a] = 0;
+        if (cg.periodic[a]) {
+            const double fl = floor(s);
+            w[a] = (int)fl;
+            s -= fl;
+        }
+        int bb = (int)floor(s * cg.nb[a]);
+        bb = bb < 0 ? 0 : (bb >= cg.nb[a] ? cg.nb[a] - 1 : bb);
+        b[a] = bb;
+        if (w[a] < -511 || w[a] > 511) latch_error(status, -1);
+    }
+    const int gb = cg.bin_offset + (b[2] * cg.nb[1] + b[1]) * cg.nb[0] + b[0];
+    bin_of[i] = gb;
+    wrap[i] = pack_wrap(w[0], w[1], w[2]);
+    atomicAdd(bin_count + gb, 1);
+    xref[i] = p[0];
+    xref[(size_t)n + i] = p[1];
+    xref[2 * (size_t)n + i] = p[2];
+}
+
+// Exclusive scan, three phases: 2048-element block scans, a serial scan of
+// the block sums (one block, in chunks), and the block offsets added back.
+__global__ __launch_bounds__(256) void k_scan_blocks(int n, const int32_t *__restrict__ in,
+                                                     int32_t *__restrict__ out,
+                                                     int32_t *__restrict__ sums,
+                                                     const int32_t *__restrict__ flag)
+{
+    if (flag && *flag == 0) return;
+    __shared__ int32_t sh[256];
+    const int base = blockIdx.x * 2048 + threadIdx.x * 8;
+    int32_t v[8], s = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int32_t add = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int32_t run = sh[threadIdx.x] - s;   // exclusive prefix of this thread
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 255) sums[blockIdx.x] = sh[255];
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(int nb, int32_t *__restrict__ sums,
+                                                   const int32_t *__restrict__ flag)
+{
+    if (flag && *flag == 0) return;
+    __shared__ int32_t sh[256];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < nb; c0 += 256) {
+        const int k = c0 + threadIdx.x;
+        const int32_t v = k < nb ? sums[k] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const int32_t add = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (k < nb) sums[k] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 255) carry += sh[255];
+        __syncthreads();
+    }
+}
+
+__global__ void k_scan_add(int n, int32_t *__restrict__ out, const int32_t *__restrict__ sums,
+                           const int32_t *__restrict__ flag)
+{
+    if (flag && *flag == 0) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] += sums[t / 2048];
+}
+
+// Scatter atoms into their bins (arbitrary order within a bin).
+__global__ void k_bin_scatter(int n, const int32_t *__restrict__ bin_of,
+                              const int32_t *__restrict__ bin_start, int32_t *__restrict__ fill,
+                              int32_t *__restrict__ tmp, const int32_t *__restrict__ flag)
+{
+    if (flag && *flag == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int b = bin_of[i];
+    const int slot = atomicAdd(fill + b, 1);
+    tmp[bin_start[b] + slot] = i;
+}
+
+// Stable order within each bin: an atom's rank is the number of atoms of its
+// bin with a smaller caller index.  Also records the sorted atom's local bin.
+__global__ void k_bin_rank(int n, const int32_t *__restrict__ bin_of,
+                           const int32_t *__restrict__ bin_start, const int32_t *__restrict__ tmp,
+                           const int32_t *__restrict__ cell_of, const CellGeom *__restrict__ cells,
+                           int32_t *__restrict__ perm, int32_t *__restrict__ bin_sorted,
+                           const int32_t *__restrict__ flag)
+{
+    if (flag && *flag == 0) return;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int i = tmp[p];
+    const int b = bin_of[i];
+    const int b0 = bin_start[b], b1 = bin_start[b + 1];
+    int rank = 0;
+    for (int q = b0; q < b1; ++q) rank += tmp[q] < i;
+    perm[b0 + rank] = i;
+    bin_sorted[b0 + rank] = b - cells[cell_of[i]].bin_offset;
+}
+
+// Wrapped positions in sorted order: xs[t] = x[perm[t]] - w . h.  Runs at
+// every evaluation; non-finite positions latch NEP_E_NONFINITE.
+__global__ void k_sort_positions(int n, const int32_t *__restrict__ perm,
+                                 const double *__restrict__ x, const double *__restrict__ y,
+                                 const double *__restrict__ z, const int32_t *__restrict__ wrap,
+                                 const int32_t *__restrict__ cell_of,
+                                 const CellGeom *__restrict__ cells, double *__restrict__ xs,
+                                 double *__restrict__ ys, double *__restrict__ zs,
+                                 int32_t *__restrict__ status)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int i = perm[t];
+    int w0, w1, w2;
+    unpack_wrap(wrap[i], w0, w1, w2);
+    const double *h = cells[cell_of[t]].h;
+    const double px = x[i], py = y[i], pz = z[i];
+    if (!isfinite(px) || !isfinite(py) || !isfinite(pz)) latch_error(status, -5);
+    xs[t] = px - (w0 * h[0] + w1 * h[3] + w2 * h[6]);
+    ys[t] = py - (w0 * h[1] + w1 * h[4] + w2 * h[7]);
+    zs[t] = pz - (w0 * h[2] + w1 * h[5] + w2 * h[8]);
+}
+
+// Neighbour lists of every sorted atom (see the file comment for the layout).
+__global__ __launch_bounds__(256) void k_build_lists(
+    PairConsts pc, double lA2, double lR2, double cA2, double cR2, const double *__restrict__ xs,
+    const double *__restrict__ ys, const double *__restrict__ zs,
+    const int32_t *__restrict__ cell_of, const CellGeom *__restrict__ cells,
+    const int32_t *__restrict__ bin_sorted, const int32_t *__restrict__ bin_start,
+    int32_t *__restrict__ nl_ang, int32_t *__restrict__ nl_rad, uint32_t *__restrict__ ncnt,
+    int32_t *__restrict__ status, const int32_t *__restrict__ flag)
+{
+    if (flag && *flag == 0) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= pc.n) return;
+    const CellGeom &cg = cells[cell_of[t]];
+    const double xi = xs[t], yi = ys[t], zi = zs[t];
+    const int lb = bin_sorted[t];
+    const int bc[3] = {lb % cg.nb[0], (lb / cg.nb[0]) % cg.nb[1], lb / (cg.nb[0] * cg.nb[1])};
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        if (cg.R[a] > 0) { lo[a] = -cg.R[a]; hi[a] = cg.R[a]; }
+        else { lo[a] = -1; hi[a] = 1; }
+    }
+    int naf = 0, nab = 0, nrf = 0, nrb = 0;
+    const int capA = pc.capA, capR = pc.capR;
+    const uint32_t jmask_limit = 1u << pc.jbits;
+    for (int o2 = lo[2]; o2 <= hi[2]; ++o2)
+        for (int o1 = lo[1]; o1 <= hi[1]; ++o1)
+            for (int o0 = lo[0]; o0 <= hi[0]; ++o0) {
+                const int o[3] = {o0, o1, o2};
+                int bb[3], m[3];
+                bool skip = false;
+                for (int a = 0; a < 3; ++a) {
+                    if (cg.R[a] > 0) { bb[a] = 0; m[a] = o[a]; }
+                    else {
+                        int b = bc[a] + o[a];
+                        m[a] = 0;
+                        if (cg.periodic[a]) {
+                            if (b < 0) { b += cg.nb[a]; m[a] = -1; }
+                            else if (b >= cg.nb[a]) { b -= cg.nb[a]; m[a] = 1; }
+                        } else if (b < 0 || b >= cg.nb[a]) skip = true;
+                        bb[a] = b;
+                    }
+                }
+                if (skip) continue;
+                const double sx = m[0] * cg.h[0] + m[1] * cg.h[3] + m[2] * cg.h[6];
+                const double sy = m[0] * cg.h[1] + m[1] * cg.h[4] + m[2] * cg.h[7];
+                const double sz = m[0] * cg.h[2] + m[1] * cg.h[5] + m[2] * cg.h[8];
+                const bool self_image = (m[0] | m[1] | m[2]) == 0;
+                const uint32_t code = (uint32_t)(m[0] + pc.ioff) | ((uint32_t)(m[1] + pc.ioff) << pc.ibits)
+                                      | ((uint32_t)(m[2] + pc.ioff) << (2 * pc.ibits));
+                const int gb = cg.bin_offset + (bb[2] * cg.nb[1] + bb[1]) * cg.nb[0] + bb[0];
+                for (int u = bin_start[gb]; u < bin_start[gb + 1]; ++u) {
+                    if (u == t && self_image) continue;
+                    const double dx = xs[u] + sx - xi, dy = ys[u] + sy - yi, dz = zs[u] + sz - zi;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 >= lR2) continue;
+                    const uint32_t jl = (uint32_t)(u - cg.atom_start);
+                    const int32_t e = (int32_t)(jl | (code << pc.jbits));
+                    if (jl >= jmask_limit) latch_error(status, -1);
+                    if (r2 < lA2) {
+                        if (r2 < cA2) {
+                            if (naf + nab < capA) nl_ang[(size_t)naf * pc.n + t] = e;
+                            ++naf;
+                        } else {
+                            if (naf + nab < capA) nl_ang[(size_t)(capA - 1 - nab) * pc.n + t] = e;
+                            ++nab;
+                        }
+                    } else {
+                        if (r2 < cR2) {
+                            if (nrf + nrb < capR) nl_rad[(size_t)nrf * pc.n + t] = e;
+                            ++nrf;
+                        } else {
+                            if (nrf + nrb < capR) nl_rad[(size_t)(capR - 1 - nrb) * pc.n + t] = e;
+                            ++nrb;
+                        }
+                    }
+                }
+            }
+    const int nA = naf + nab, nR = nrf + nrb;
+    if (nA > capA || nR > capR) {
+        latch_error(status, -3);
+        atomicMax(status + ST_NEED_A, nA);
+        atomicMax(status + ST_NEED_R, nR);
+        // keep the stored counts consistent with what was written
+        if (nA > capA) { naf = naf < capA ? naf : capA; nab = capA - naf; }
+        if (nR > capR) { nrf = nrf < capR ? nrf : capR; nrb = capR - nrf; }
+    } else {
+        atomicMax(status + ST_NEED_A, nA);
+        atomicMax(status + ST_NEED_R, nR);
+    }
+    ncnt[t] = (uint32_t)naf | ((uint32_t)nab << 8) | ((uint32_t)nrf << 16) | ((uint32_t)nrb << 24);
+}
+
+// ------------------------------------------------------------------ velocity Verlet
+
+__device__ inline void wave_max_atomic(double v, double *dst)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0)
+        atomicMax(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)__double_as_longlong(v));
+}
+
+// v += dt/2 F/m ; x += dt v ; track the largest displacement since the last build.
+__global__ void k_kick_drift(int n, double *__restrict__ x, double *__restrict__ y,
+                             double *__restrict__ z, double *__restrict__ vx,
+                             double *__restrict__ vy, double *__restrict__ vz,
+                             const float *__restrict__ fx, const float *__restrict__ fy,
+                             const float *__restrict__ fz, double acc_per_mass,
+                             const double *__restrict__ xref, double *__restrict__ md,
+                             int32_t *__restrict__ status)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double d2 = 0.0;
+    if (i < n && status[ST_ERR] == 0) {
+        const double dt = md[MD_DT];
+        const double c = 0.5 * dt * acc_per_mass;
+        double v0 = vx[i] + c * fx[i], v1 = vy[i] + c * fy[i], v2 = vz[i] + c * fz[i];
+        vx[i] = v0; vy[i] = v1; vz[i] = v2;
+        const double p0 = x[i] + dt * v0, p1 = y[i] + dt * v1, p2 = z[i] + dt * v2;
+        x[i] = p0; y[i] = p1; z[i] = p2;
+        const double e0 = p0 - xref[i], e1 = p1 - xref[(size_t)n + i], e2 = p2 - xref[2 * (size_t)n + i];
+        d2 = e0 * e0 + e1 * e1 + e2 * e2;
+        if (!isfinite(d2)) { latch_error(status, -5); d2 = 0.0; }
+    }
+    wave_max_atomic(d2, md + MD_DISP2);
+}
+
+// v += dt/2 F/m ; track max |v|^2 for the next step length.
+__global__ void k_kick(int n, double *__restrict__ vx, double *__restrict__ vy,
+                       double *__restrict__ vz, const float *__restrict__ fx,
+                       const float *__restrict__ fy, const float *__restrict__ fz,
+                       double acc_per_mass, double *__restrict__ md,
+                       const int32_t *__restrict__ status)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v2 = 0.0;
+    if (i < n && status[ST_ERR] == 0) {
+        const double c = 0.5 * md[MD_DT] * acc_per_mass;
+        const double v0 = vx[i] + c * fx[i], v1 = vy[i] + c * fy[i], v2_ = vz[i] + c * fz[i];
+        vx[i] = v0; vy[i] = v1; vz[i] = v2_;
+        v2 = v0 * v0 + v1 * v1 + v2_ * v2_;
+    }
+    wave_max_atomic(v2, md + MD_VMAX2);
+}
+
+// max |v|^2 of the current velocities.
+__global__ void k_vmax(int n, const double *__restrict__ vx, const double *__restrict__ vy,
+                       const double *__restrict__ vz, double *__restrict__ md)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v2 = 0.0;
+    if (i < n) v2 = vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
+    wave_max_atomic(v2, md + MD_VMAX2);
+}
+
+// Step length for the next step: dt = min(dt_max, max_disp / max|v|) (Sec. II.B).
+__global__ void k_dt_update(double dt_max, double max_disp, double dt_min, double *__restrict__ md,
+                            int32_t *__restrict__ status, int advance_time)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (advance_time) md[MD_TIME] += md[MD_DT];
+    const double vmax = sqrt(md[MD_VMAX2]);
+    double dt = dt_max;
+    if (max_disp > 0.0 && vmax > 0.0) dt = fmin(dt_max, max_disp / vmax);
+    if (!(dt >= dt_min)) latch_error(status, -6);
+    md[MD_DT] = dt;
+    md[MD_VMAX2] = 0.0;
+}
+
+// Rebuild decision: an atom moved more than skin/2 since the last build.
+__global__ void k_rebuild_flag(double half_skin2, double *__restrict__ md, int32_t *__restrict__ flag)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int r = md[MD_DISP2] > half_skin2;
+    *flag = r;
+    if (r) md[MD_NREB] += 1.0;
+    md[MD_DISP2] = 0.0;
+}
+
+// Largest displacement since the last build (for the rebuild decision at a
+// chunk start, when positions may have been changed by the caller).
+__global__ void k_disp(int n, const double *__restrict__ x, const double *__restrict__ y,
+                       const double *__restrict__ z, const double *__restrict__ xref,
+                       double *__restrict__ md)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double d2 = 0.0;
+    if (i < n) {
+        const double e0 = x[i] - xref[i], e1 = y[i] - xref[(size_t)n + i], e2 = z[i] - xref[2 * (size_t)n + i];
+        d2 = e0 * e0 + e1 * e1 + e2 * e2;
+        if (!isfinite(d2)) d2 = 1e300;
+    }
+    wave_max_atomic(d2, md + MD_DISP2);
+}
+
+__global__ void k_set_flag(int32_t *__restrict__ flag, int32_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *flag = v;
+}
+
+// Cell index of every atom from the cell offsets (binary search).
+__global__ void k_cell_of(int n, int n_cells, const int64_t *__restrict__ cell_start,
+                          int32_t *__restrict__ cell_of)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int lo = 0, hi = n_cells;   // cell_start[lo] <= i < cell_start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cell_start[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    cell_of[i] = lo;
+}
+
+}  // namespace nep

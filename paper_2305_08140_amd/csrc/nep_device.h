@@ -1,0 +1,292 @@
+// Device-side building blocks of the NEP-ZBL kernels (gfx950).
+//
+// Everything here is single precision except the ZBL pair term, which is
+// rare (pairs closer than 2 A) and evaluated in double precision.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nep {
+
+// ---------------------------------------------------------------- model sizes
+// Compiled model: n_max^R = 8 (9 radial components), n_max^A = 4 (5 angular
+// radial functions), Chebyshev k = 0..8, l = 1..4, 30 hidden neurons.
+constexpr int NR = 9;        // radial descriptor components
+constexpr int NA = 5;        // angular radial functions
+constexpr int KB = 9;        // Chebyshev basis size (radial and angular)
+constexpr int LMAX = 4;
+constexpr int NLM = 24;      // (l, m) pairs for l = 1..4
+constexpr int DIM = NR + NA * LMAX;   // 29
+constexpr int NH = 30;       // hidden neurons
+
+// Packed FP32 parameter block (offsets in floats).
+constexpr int P_CR = 0;                  // [NR][KB]
+constexpr int P_CA = P_CR + NR * KB;     // [NA][KB]
+constexpr int P_QS = P_CA + NA * KB;     // [DIM]
+constexpr int P_W0 = P_QS + DIM;         // [NH][DIM]
+constexpr int P_B0 = P_W0 + NH * DIM;    // [NH]
+constexpr int P_W1 = P_B0 + NH;          // [NH]
+constexpr int P_B1 = P_W1 + NH;          // [1]
+constexpr int P_SIZE = P_B1 + 1;
+
+// Per-atom adjoint records written by the descriptor kernel and gathered by
+// the force kernel.
+constexpr int ADJ_R = 12;    // floats per atom: dU/dF_k, k = 0..8 (padded to 12)
+constexpr int ADJ_A = NA * NLM;   // 120 floats per atom: dU/ds_{n,lm}
+
+// Runtime constants shared by the pair kernels.
+struct PairConsts {
+    float rc_rad, rc_ang;             // cutoffs
+    float rc_rad2, rc_ang2;           // squared
+    float inv_rc_rad, inv_rc_ang;     // 1/rc rounded to FP32 ...
+    float inv_rc_rad_lo, inv_rc_ang_lo;   // ... and the rounding remainder 1/rc - inv_rc
+    float zbl_r1, zbl_r2, zbl_r2sq;
+    float zbl_z;                      // nuclear charge
+    int capA, capR;                   // list capacities
+    int jbits, ibits, ioff;           // neighbour entry encoding
+    int n;                            // atoms (list stride)
+};
+
+struct CellGeom {
+    double h[9];       // rows: lattice vectors
+    double hinv[9];    // x = s h  =>  s = x hinv
+    int nb[3];         // bins per axis (1 for image-loop axes)
+    int R[3];          // image range for image-loop axes, 0 for binned axes
+    int periodic[3];
+    int bin_offset;    // first global bin of this cell
+    int atom_start;    // first atom (caller and sorted order coincide per cell)
+    int n_atoms;
+    int pad_;
+};
+
+// ---------------------------------------------------------------- status word
+// status[0]: latched error code (0 = none); status[1], status[2]: required
+// angular / radial list lengths seen by the last build.
+constexpr int ST_ERR = 0;
+constexpr int ST_NEED_A = 1;
+constexpr int ST_NEED_R = 2;
+
+// velocity-Verlet state (doubles): step length (fs), max |v|^2, max
+// displacement^2 since the last build (both as ordered bit patterns of
+// non-negative doubles), simulated time, rebuild count.
+constexpr int MD_DT = 0, MD_VMAX2 = 1, MD_DISP2 = 2, MD_TIME = 3, MD_NREB = 4;
+
+__device__ inline void latch_error(int *status, int code)
+{
+    atomicCAS(status + ST_ERR, 0, code);
+}
+
+// ---------------------------------------------------------------- fast math
+__device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// sin(y) and cos(y) for |y| <= pi/2 from their Taylor series (truncation
+// error below 1e-9 there), evaluated in Horner form.
+__host__ __device__ inline void sincos_halfpi(float y, float &s, float &c)
+{
+    const float y2 = y * y;
+    float ps = 1.0f / 6227020800.0f;               // 1/13!
+    ps = fmaf(ps, y2, -1.0f / 39916800.0f);        // -1/11!
+    ps = fmaf(ps, y2, 1.0f / 362880.0f);           // 1/9!
+    ps = fmaf(ps, y2, -1.0f / 5040.0f);            // -1/7!
+    ps = fmaf(ps, y2, 1.0f / 120.0f);
+    ps = fmaf(ps, y2, -1.0f / 6.0f);
+    ps = fmaf(ps, y2, 1.0f);
+    s = ps * y;
+    float pc = 1.0f / 479001600.0f;                // 1/12!
+    pc = fmaf(pc, y2, -1.0f / 3628800.0f);         // -1/10!
+    pc = fmaf(pc, y2, 1.0f / 40320.0f);            // 1/8!
+    pc = fmaf(pc, y2, -1.0f / 720.0f);             // -1/6!
+    pc = fmaf(pc, y2, 1.0f / 24.0f);
+    pc = fmaf(pc, y2, -0.5f);
+    c = fmaf(pc, y2, 1.0f);
+}
+
+// tt = r/rc - 1 without the systematic bias that the FP32 rounding of 1/rc
+// would add (the Chebyshev argument x = 2 tt^2 - 1 amplifies any bias of x by
+// up to k^2 in T_k): 1/rc is carried as inv + inv_lo.
+__host__ __device__ inline float scaled_minus_one(float r, float inv, float inv_lo)
+{
+    return fmaf(r, inv, -1.0f) + r * inv_lo;
+}
+
+// Smooth cutoff fc(r) = (1 + cos(pi r/rc))/2 and its derivative, for r < rc,
+// from tt = r/rc - 1.  With y = pi (tt + 1/2): cos(pi r/rc) = -sin(y),
+// sin(pi r/rc) = cos(y); pi is carried as two floats for the same reason.
+__host__ __device__ inline void cutoff(float tt, float inv_rc, float &fc, float &dfc)
+{
+    const float PI_HI = 3.14159274101257324f, PI_LO = -8.74227765734758577e-8f;
+    const float u = tt + 0.5f;
+    const float y = fmaf(PI_HI, u, PI_LO * u);
+    float s, c;
+    sincos_halfpi(y, s, c);
+    fc = 0.5f - 0.5f * s;
+    dfc = -0.5f * PI_HI * inv_rc * c;
+}
+
+__host__ __device__ inline void cutoff_value(float tt, float &fc)
+{
+    float d;
+    cutoff(tt, 1.0f, fc, d);
+}
+
+// Chebyshev polynomials T_0..T_8 at x (three-term recurrence).
+__host__ __device__ inline void cheb(float x, float T[KB])
+{
+    T[0] = 1.0f;
+    T[1] = x;
+    const float x2 = 2.0f * x;
+#pragma unroll
+    for (int k = 2; k < KB; ++k) T[k] = fmaf(x2, T[k - 1], -T[k - 2]);
+}
+
+// T_k and dT_k/dx (dT_{k} = 2 T_{k-1} + 2x dT_{k-1} - dT_{k-2}).
+__host__ __device__ inline void cheb_d(float x, float T[KB], float dT[KB])
+{
+    T[0] = 1.0f;
+    T[1] = x;
+    dT[0] = 0.0f;
+    dT[1] = 1.0f;
+    const float x2 = 2.0f * x;
+#pragma unroll
+    for (int k = 2; k < KB; ++k) {
+        T[k] = fmaf(x2, T[k - 1], -T[k - 2]);
+        dT[k] = fmaf(x2, dT[k - 1], fmaf(2.0f, T[k - 1], -dT[k - 2]));
+    }
+}
+
+// ---------------------------------------------------------------- harmonics
+// Real spherical harmonics scaled by sqrt(4 pi / (2l+1)), so that
+// sum_m Y_lm(u) Y_lm(v) = P_l(u.v) (addition theorem).  Index lm = l^2 - 1 + (m + l).
+// Written as polynomials valid on the unit sphere.
+#define NEP_S3 1.7320508075688772f
+#define NEP_S5 2.2360679774997896f
+#define NEP_S6 2.4494897427831781f
+#define NEP_S10 3.1622776601683795f
+#define NEP_S15 3.8729833462074170f
+#define NEP_S35 5.9160797830996160f
+#define NEP_S70 8.3666002653407555f
+
+__host__ __device__ inline void sph(float x, float y, float z, float Y[NLM])
+{
+    const float x2 = x * x, y2 = y * y, z2 = z * z;
+    Y[0] = y; Y[1] = z; Y[2] = x;
+    Y[3] = NEP_S3 * x * y;
+    Y[4] = NEP_S3 * y * z;
+    Y[5] = 0.5f * (3.0f * z2 - 1.0f);
+    Y[6] = NEP_S3 * x * z;
+    Y[7] = 0.5f * NEP_S3 * (x2 - y2);
+    Y[8] = 0.25f * NEP_S10 * y * (3.0f * x2 - y2);
+    Y[9] = NEP_S15 * x * y * z;
+    Y[10] = 0.25f * NEP_S6 * y * (5.0f * z2 - 1.0f);
+    Y[11] = 0.5f * z * (5.0f * z2 - 3.0f);
+    Y[12] = 0.25f * NEP_S6 * x * (5.0f * z2 - 1.0f);
+    Y[13] = 0.5f * NEP_S15 * z * (x2 - y2);
+    Y[14] = 0.25f * NEP_S10 * x * (x2 - 3.0f * y2);
+    Y[15] = 0.5f * NEP_S35 * x * y * (x2 - y2);
+    Y[16] = 0.25f * NEP_S70 * y * z * (3.0f * x2 - y2);
+    Y[17] = 0.5f * NEP_S5 * x * y * (7.0f * z2 - 1.0f);
+    Y[18] = 0.25f * NEP_S10 * y * z * (7.0f * z2 - 3.0f);
+    Y[19] = 0.125f * (35.0f * z2 * z2 - 30.0f * z2 + 3.0f);
+    Y[20] = 0.25f * NEP_S10 * x * z * (7.0f * z2 - 3.0f);
+    Y[21] = 0.25f * NEP_S5 * (x2 - y2) * (7.0f * z2 - 1.0f);
+    Y[22] = 0.25f * NEP_S70 * x * z * (x2 - 3.0f * y2);
+    Y[23] = 0.125f * NEP_S35 * (x2 * x2 - 6.0f * x2 * y2 + y2 * y2);
+}
+
+// v = sum_lm Dc[lm] * grad_u p_lm(u), the gradient of the polynomials above
+// taken with x, y, z independent (the caller projects out the radial part).
+__host__ __device__ inline void sph_grad_contract(float x, float y, float z, const float Dc[NLM],
+                                         float &vx, float &vy, float &vz)
+{
+    const float x2 = x * x, y2 = y * y, z2 = z * z;
+    float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+    // l = 1
+    gy += Dc[0]; gz += Dc[1]; gx += Dc[2];
+    // l = 2
+    gx += NEP_S3 * (Dc[3] * y + Dc[6] * z + Dc[7] * x);
+    gy += NEP_S3 * (Dc[3] * x + Dc[4] * z - Dc[7] * y);
+    gz += NEP_S3 * (Dc[4] * y + Dc[6] * x) + 3.0f * Dc[5] * z;
+    // l = 3
+    {
+        const float a = 0.25f * NEP_S10, b = NEP_S15, c = 0.25f * NEP_S6, e = 0.5f * NEP_S15;
+        const float t5 = 5.0f * z2 - 1.0f;
+        gx += a * Dc[8] * 6.0f * x * y + b * Dc[9] * y * z + c * Dc[12] * t5
+              + e * Dc[13] * 2.0f * x * z + a * Dc[14] * 3.0f * (x2 - y2);
+        gy += a * Dc[8] * 3.0f * (x2 - y2) + b * Dc[9] * x * z + c * Dc[10] * t5
+              - e * Dc[13] * 2.0f * y * z - a * Dc[14] * 6.0f * x * y;
+        gz += b * Dc[9] * x * y + c * Dc[10] * 10.0f * y * z + Dc[11] * (7.5f * z2 - 1.5f)
+              + c * Dc[12] * 10.0f * x * z + e * Dc[13] * (x2 - y2);
+    }
+    // l = 4
+    {
+        const float a = 0.5f * NEP_S35, b = 0.25f * NEP_S70, c = 0.5f * NEP_S5, d = 0.25f * NEP_S10;
+        const float e = 0.25f * NEP_S5, f = 0.125f * NEP_S35;
+        const float t7 = 7.0f * z2 - 1.0f, t73 = 7.0f * z2 - 3.0f;
+        gx += a * Dc[15] * (3.0f * x2 * y - y2 * y) + b * Dc[16] * 6.0f * x * y * z
+              + c * Dc[17] * y * t7 + d * Dc[20] * z * t73 + e * Dc[21] * 2.0f * x * t7
+              + b * Dc[22] * 3.0f * z * (x2 - y2) + f * Dc[23] * (4.0f * x2 * x - 12.0f * x * y2);
+        gy += a * Dc[15] * (x2 * x - 3.0f * x * y2) + b * Dc[16] * 3.0f * z * (x2 - y2)
+              + c * Dc[17] * x * t7 + d * Dc[18] * z * t73 - e * Dc[21] * 2.0f * y * t7
+              - b * Dc[22] * 6.0f * x * y * z + f * Dc[23] * (4.0f * y2 * y - 12.0f * x2 * y);
+        gz += b * Dc[16] * y * (3.0f * x2 - y2) + c * Dc[17] * 14.0f * x * y * z
+              + d * Dc[18] * y * (21.0f * z2 - 3.0f) + Dc[19] * (17.5f * z2 * z - 7.5f * z)
+              + d * Dc[20] * x * (21.0f * z2 - 3.0f) + e * Dc[21] * 14.0f * z * (x2 - y2)
+              + b * Dc[22] * x * (x2 - 3.0f * y2);
+    }
+    vx = gx; vy = gy; vz = gz;
+}
+
+// ---------------------------------------------------------------- ZBL
+// Eqs. 2-4 of the paper with the Tersoff switch between r1 and r2, double
+// precision.  Returns U and dU/dr for r < r2.
+__host__ __device__ inline void zbl_pair(double r, double Z, double r1, double r2, double &U, double &dU)
+{
+    const double KE = 14.399645478425668;          // e^2 / (4 pi eps0), eV A
+    const double a = 0.46848 / (2.0 * pow(Z, 0.23));
+    const double inva = 1.0 / a;
+    const double c0 = 0.32825, c1 = 0.09219, c2 = 0.58110;
+    const double e0 = 2.54931, e1 = 0.29182, e2 = 0.59231;
+    const double t0 = c0 * exp(-e0 * r * inva);
+    const double t1 = c1 * exp(-e1 * r * inva);
+    const double t2 = c2 * exp(-e2 * r * inva);
+    const double phi = t0 + t1 + t2;
+    const double dphi = -(e0 * t0 + e1 * t1 + e2 * t2) * inva;
+    double ft = 1.0, dft = 0.0;
+    if (r >= r1) {
+        const double w = 3.14159265358979323846 / (r2 - r1);
+        ft = 0.5 * (1.0 + cos(w * (r - r1)));
+        dft = -0.5 * w * sin(w * (r - r1));
+    }
+    const double k = KE * Z * Z;
+    const double rinv = 1.0 / r;
+    U = k * rinv * phi * ft;
+    dU = k * rinv * (dphi * ft + phi * dft - phi * ft * rinv);
+}
+
+// ---------------------------------------------------------------- neighbours
+__host__ __device__ inline void decode_entry(int32_t e, int jbits, int ibits, int ioff, int &j, int &n0,
+                                    int &n1, int &n2)
+{
+    const uint32_t u = (uint32_t)e;
+    j = (int)(u & ((1u << jbits) - 1u));
+    const uint32_t code = u >> jbits;
+    const uint32_t m = (1u << ibits) - 1u;
+    n0 = (int)(code & m) - ioff;
+    n1 = (int)((code >> ibits) & m) - ioff;
+    n2 = (int)(code >> (2 * ibits)) - ioff;
+}
+
+// XCD-aware block order: the hardware dispatches workgroups round-robin over
+// the 8 XCDs, so launched block b runs on XCD b % 8.  Mapping it to logical
+// tile (b % 8) * per + b / 8 gives every XCD one contiguous run of tiles, so
+// spatially adjacent atom tiles share one L2.  The grid must be launched with
+// 8 * per blocks (per = ceil(tiles / 8)); logical tiles >= tiles do nothing.
+__device__ inline int xcd_block(int ntiles)
+{
+    const int b = blockIdx.x;
+    const int per = (ntiles + 7) / 8;
+    return (b % 8) * per + b / 8;
+}
+
+}  // namespace nep

@@ -1,0 +1,35 @@
+// Host-compiled copies of the kernels' scalar building blocks, exported for
+// the CPU unit tests (the same source as the device code, compiled for x86).
+// Not part of the library ABI; built into libnep_hostmath.so.
+#include "nep_device.h"
+
+using namespace nep;
+
+extern "C" {
+
+void nep_test_sincos(float y, float *s, float *c) { sincos_halfpi(y, *s, *c); }
+
+void nep_test_cutoff(float r, float rc, float *fc, float *dfc)
+{
+    const float inv = (float)(1.0 / rc);
+    const float lo = (float)(1.0 / rc - (double)inv);
+    cutoff(scaled_minus_one(r, inv, lo), inv, *fc, *dfc);
+}
+
+void nep_test_cheb(float x, float *T, float *dT) { cheb_d(x, T, dT); }
+
+void nep_test_sph(float x, float y, float z, float *Y) { sph(x, y, z, Y); }
+
+void nep_test_sph_grad(float x, float y, float z, const float *Dc, float *v)
+{
+    sph_grad_contract(x, y, z, Dc, v[0], v[1], v[2]);
+}
+
+void nep_test_zbl(double r, double Z, double r1, double r2, double *U, double *dU) { zbl_pair(r, Z, r1, r2, *U, *dU); }
+
+void nep_test_decode(int32_t e, int jbits, int ibits, int ioff, int *out)
+{
+    decode_entry(e, jbits, ibits, ioff, out[0], out[1], out[2], out[3]);
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+"""The C ABI library loads and exports every symbol that include/nep.h declares
+(no compute call: this runs without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nep.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(nep_[a-z_]+)\s*\(", txt)))
+
+
+def _lib():
+    import paper_2305_08140_amd as nep
+    if not os.path.exists(nep.LIB_PATH):
+        pytest.skip("libnep_hip.so not built")
+    return nep, nep.lib()
+
+
+def test_header_declares_the_entry_points():
+    d = _declared()
+    for name in ("nep_create", "nep_destroy", "nep_build_neighbors", "nep_compute_efv", "nep_step_verlet",
+                 "nep_status", "nep_strerror"):
+        assert name in d
+
+
+def test_library_exports_every_declared_symbol():
+    nep, L = _lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert set(_declared()) == set(nep.EXPORTED)
+
+
+def test_argument_errors_without_device():
+    nep, L = _lib()
+    import nep_synth
+    m = nep_synth.random_model()
+    ptr = C.c_void_p()
+    hp = nep.hparams_from(m)
+    cfg = nep.Config(1000, 1, 48, 96, 0, 1.0)
+    assert L.nep_create(None, C.byref(cfg), C.byref(ptr)) == nep.NEP_E_ARG
+    assert L.nep_create(C.byref(hp), C.byref(cfg), None) == nep.NEP_E_ARG
+    bad = nep.hparams_from(m)
+    bad.n_hidden = 100
+    assert L.nep_create(C.byref(bad), C.byref(cfg), C.byref(ptr)) == nep.NEP_E_UNSUPPORTED
+    cfg2 = nep.Config(1000, 1, 300, 96, 0, 1.0)   # list capacity above 255
+    assert L.nep_create(C.byref(hp), C.byref(cfg2), C.byref(ptr)) == nep.NEP_E_ARG
+    assert not ptr.value
+    assert L.nep_compute_efv(None, None, None, None) == nep.NEP_E_ARG
+    assert L.nep_step_verlet(None, None, None, 1, None, None, None) == nep.NEP_E_ARG
+    L.nep_destroy(None)
+
+
+def test_strerror_covers_codes():
+    nep, L = _lib()
+    for code in range(0, -9, -1):
+        s = nep.strerror(code)
+        assert s and s != "unknown error"
+    assert nep.strerror(-99) == "unknown error"

@@ -1,0 +1,121 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import nep_synth
+import oracle
+from gpu_common import (E_ATOM_TOL, F_REL_TOL, W_ATOM_TOL, W_REL_TOL, force_errors, gpu_available,
+                        model, run_gpu, zbl_atoms)
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _compare(s, m, ref, res, zbl=None, label=""):
+    N = s.n_atoms
+    print(f"[{label}] N={N} cells={s.n_cells}", flush=True)
+    for c in range(s.n_cells):
+        n_c = int(s.cell_start[c + 1] - s.cell_start[c])
+        de = abs(res["energy"][c] - ref["energy"][c]) / n_c
+        assert de <= E_ATOM_TOL, (label, c, res["energy"][c], ref["energy"][c])
+        dW = np.linalg.norm(res["virial"][c] - ref["virial"][c])
+        assert dW <= W_REL_TOL * np.linalg.norm(ref["virial"][c]) + W_ATOM_TOL * n_c, (label, c, dW)
+    e_all, e_rest = force_errors(res["forces"], ref["forces"], zbl)
+    print(f"[{label}] force rel err all={e_all:.3e} non-ZBL={e_rest:.3e}", flush=True)
+    assert e_all <= F_REL_TOL and e_rest <= F_REL_TOL
+    assert np.abs(res["energy_atom"] - ref["energy_atom"]).max() <= 1e-4 * max(1.0, np.abs(ref["energy_atom"]).max())
+
+
+def test_tiny_matches_oracle():
+    m = model()
+    s = nep_synth.tiny()
+    ref = oracle.efv_system(m, s)
+    res, *_ = run_gpu(m, s)
+    _compare(s, m, ref, res, zbl_atoms(s.pos, s.h[0]), "tiny")
+
+
+def test_perfect_lattice_zero_force():
+    m = model()
+    pos, h = nep_synth.bcc_lattice(8, 8, 8)
+    s = nep_synth._single(pos, h)
+    res, *_ = run_gpu(m, s)
+    ref = oracle.efv_system(m, s)
+    assert np.abs(res["forces"]).max() < 1e-4
+    assert abs(res["energy"][0] - ref["energy"][0]) / s.n_atoms <= E_ATOM_TOL
+
+
+def test_small_strained_cells_with_images():
+    # cells of 8-60 atoms: several periodic images of the same neighbour, own images
+    m = model()
+    full = nep_synth.batch()
+    sizes = np.diff(full.cell_start)
+    pick = [int(c) for c in np.argsort(sizes)[:24]]
+    pos = np.concatenate([full.cell(c)[0] for c in pick])
+    starts = np.concatenate([[0], np.cumsum([sizes[c] for c in pick])]).astype(np.int64)
+    s = nep_synth.System(pos=pos, vel=np.zeros_like(pos), cell_start=starts, h=full.h[pick].copy())
+    ref = oracle.efv_system(m, s)
+    res, *_ = run_gpu(m, s)
+    _compare(s, m, ref, res, None, "small cells")
+
+
+def test_diffbatch_cells():
+    m = model()
+    full = nep_synth.diffbatch()
+    pick = list(range(0, 512, 16))
+    pos = np.concatenate([full.cell(c)[0] for c in pick])
+    sizes = np.diff(full.cell_start)
+    starts = np.concatenate([[0], np.cumsum([sizes[c] for c in pick])]).astype(np.int64)
+    s = nep_synth.System(pos=pos, vel=np.zeros_like(pos), cell_start=starts, h=full.h[pick].copy())
+    ref = oracle.efv_system(m, s)
+    res, *_ = run_gpu(m, s)
+    _compare(s, m, ref, res, None, "diffbatch")
+
+
+def test_rebuild_not_needed_within_half_skin():
+    # move atoms by < skin/2 after the build: the lists still cover every pair
+    m = model()
+    s = nep_synth.tiny()
+    import torch
+    import paper_2305_08140_amd as nep
+    res, ctx, sysd, out = run_gpu(m, s)
+    rng = np.random.default_rng(11)
+    d = rng.uniform(-0.28, 0.28, size=s.pos.shape)   # |d| < 0.49 A
+    s2 = nep_synth._single(s.pos + d, s.h[0])
+    sysd.x.copy_(torch.from_numpy(s2.pos[:, 0].copy()))
+    sysd.y.copy_(torch.from_numpy(s2.pos[:, 1].copy()))
+    sysd.z.copy_(torch.from_numpy(s2.pos[:, 2].copy()))
+    ctx.nep_compute_efv(sysd, out)
+    torch.cuda.synchronize()
+    F = out.forces().cpu().numpy().astype(np.float64)
+    ref = oracle.efv_system(m, s2)
+    e_all, _ = force_errors(F, ref["forces"])
+    assert e_all <= F_REL_TOL
+    assert abs(out.energy.cpu().numpy()[0] - ref["energy"][0]) / s.n_atoms <= E_ATOM_TOL
+
+
+def test_verlet_ten_steps_tiny():
+    # one E+F+virial evaluation plus 10 velocity-Verlet steps at dt = 1 fs
+    import torch
+    import paper_2305_08140_amd as nep
+    m = model()
+    s = nep_synth.tiny()
+    rng = np.random.default_rng(2)
+    s.vel = nep_synth.maxwell_boltzmann(rng, s.n_atoms, 300.0)
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(m, s.n_atoms, 1)
+    out = nep.EFV(s.n_atoms, 1)
+    st = ctx.nep_step_verlet(sysd, 10, out, dt_max=1.0, max_disp=0.0)
+    torch.cuda.synchronize()
+    pos_ref, vel_ref, F_ref, _ = oracle.velocity_verlet(m, s.pos, s.vel, s.h[0], s.mass, 10, dt_max=1.0)
+    pos = sysd.positions().cpu().numpy()
+    vel = sysd.velocities().cpu().numpy()
+    assert abs(st["time"] - 10.0) < 1e-12
+    # FP32 forces (relative error <= 1e-5) give an acceleration error
+    # da <= 1e-5 |F|max / m; after T = 10 fs the drift is ~ da T^2 / 2 and
+    # ~ da T in velocity.  Bounds: 10x that.
+    acc = oracle.EV_PER_U_TO_A2_PER_FS2 / s.mass
+    F0 = oracle.efv_cell(m, s.pos, s.h[0], virial=False)["forces"]
+    da = 1e-5 * max(np.abs(F0).max(), np.abs(F_ref).max()) * acc
+    assert np.abs(pos - pos_ref).max() < 10 * 0.5 * da * 100.0
+    assert np.abs(vel - vel_ref).max() < 10 * da * 10.0
+    e_all, _ = force_errors(out.forces().cpu().numpy().astype(np.float64), F_ref)
+    assert e_all <= 1e-4
