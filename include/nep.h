@@ -48,12 +48,13 @@ extern "C" {
 #define NEP_E_DT_UNDERFLOW    -6  /* adaptive time step fell below nep_md.dt_min */
 #define NEP_E_STATE           -7  /* call order: nep_compute_efv before nep_build_neighbors on this system */
 #define NEP_E_UNSUPPORTED     -8  /* hyperparameters for which no kernel is compiled */
+#define NEP_E_INTERNAL        -9  /* internal consistency check failed (neighbour lists not symmetric) */
 
 typedef struct nep_ctx nep_ctx;
 
 /* Model hyperparameters (names as in Sec. III.A).  Compiled kernels exist for
  * n_rad = 9 (n_max^R = 8), n_ang = 5 (n_max^A = 4), k_rad = k_ang = 9
- * (Chebyshev k = 0..8), l_max = 4, n_hidden <= 32; other values give
+ * (Chebyshev k = 0..8), l_max = 4, n_hidden = 30; other values give
  * NEP_E_UNSUPPORTED. */
 typedef struct {
     int32_t n_rad;      /* radial descriptor components */

@@ -27,6 +27,7 @@ NEP_E_NONFINITE = -5
 NEP_E_DT_UNDERFLOW = -6
 NEP_E_STATE = -7
 NEP_E_UNSUPPORTED = -8
+NEP_E_INTERNAL = -9
 
 EXPORTED = ("nep_create", "nep_destroy", "nep_set_weights", "nep_build_neighbors", "nep_compute_efv",
             "nep_step_verlet", "nep_status", "nep_required_neighbors", "nep_mean_neighbors",

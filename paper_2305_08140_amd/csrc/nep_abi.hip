@@ -14,11 +14,11 @@ namespace nep {
 // kernels (nep_kernels.hip)
 __global__ void k_descriptor(PairConsts, const double *, const double *, const double *, const int32_t *,
                              const CellGeom *, const int32_t *, const int32_t *, const uint32_t *,
-                             const float *, float *, float *, double *, int32_t *, int);
+                             const float *, float *, float4 *, float4 *, float *, double *, int32_t *, int);
 __global__ void k_force(PairConsts, const double *, const double *, const double *, const int32_t *,
-                        const CellGeom *, const int32_t *, const int32_t *, const uint32_t *, const float *,
-                        const float *, const float *, const int32_t *, float *, float *, float *, float *,
-                        const int32_t *, int);
+                        const CellGeom *, const int32_t *, const int32_t *, const uint32_t *, const uint8_t *,
+                        const float *, const float4 *, const float4 *, const int32_t *, float *, float *,
+                        float *, float *, int32_t *, int);
 __global__ void k_reduce_chunks(const int32_t *, const int32_t *, const double *, const float *, double *,
                                 const int32_t *);
 __global__ void k_reduce_cells(int, const int32_t *, const double *, double *, double *, const int32_t *);
@@ -43,6 +43,8 @@ __global__ void k_sort_positions(int, const int32_t *, const double *, const dou
 __global__ void k_build_lists(PairConsts, double, double, double, double, const double *, const double *,
                               const double *, const int32_t *, const CellGeom *, const int32_t *,
                               const int32_t *, int32_t *, int32_t *, uint32_t *, int32_t *, const int32_t *);
+__global__ void k_build_reverse(PairConsts, const int32_t *, const CellGeom *, const int32_t *,
+                                const uint32_t *, uint8_t *, int32_t *, const int32_t *);
 __global__ void k_kick_drift(int, double *, double *, double *, double *, double *, double *, const float *,
                              const float *, const float *, double, const double *, double *, int32_t *);
 __global__ void k_kick(int, double *, double *, double *, const float *, const float *, const float *, double,
@@ -78,7 +80,10 @@ struct nep_ctx {
             *bin_sorted = nullptr;
     uint32_t *ncnt = nullptr;
     int32_t *nl_ang = nullptr, *nl_rad = nullptr;
-    float *adj_r = nullptr, *adj_a = nullptr, *w_atom = nullptr;
+    float *adj_r = nullptr, *w_atom = nullptr;
+    float4 *pair_grad = nullptr;  // [capA][N] dU_i/dr_ij of every angular list slot
+    float4 *f_own = nullptr;      // [N] sum_j dU_i/dr_ij (angular)
+    uint8_t *rev = nullptr;       // [capA][N] reverse slot index
     double *e_atom = nullptr;
     // per-cell storage
     CellGeom *cells = nullptr;
@@ -135,6 +140,7 @@ const char *nep_strerror(int code)
     case NEP_E_DT_UNDERFLOW: return "adaptive time step below dt_min";
     case NEP_E_STATE: return "neighbour lists not built for this system";
     case NEP_E_UNSUPPORTED: return "hyperparameters not supported by the compiled kernels";
+    case NEP_E_INTERNAL: return "internal consistency check failed (asymmetric neighbour lists)";
     default: return "unknown error";
     }
 }
@@ -145,7 +151,8 @@ void nep_destroy(nep_ctx *c)
     hipSetDevice(c->device);
     hipDeviceSynchronize();
     void *bufs[] = {c->params, c->xs, c->xref, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
-                    c->bin_sorted, c->ncnt, c->nl_ang, c->nl_rad, c->adj_r, c->adj_a, c->w_atom,
+                    c->bin_sorted, c->ncnt, c->nl_ang, c->nl_rad, c->adj_r, c->pair_grad, c->f_own, c->rev,
+                    c->w_atom,
                     c->e_atom, c->cells, c->cell_start_d, c->chunk_begin, c->chunk_end, c->cell_chunk,
                     c->part, c->bin_count, c->bin_start, c->bin_fill, c->scan_sums, c->status, c->flag,
                     c->md, c->counts};
@@ -194,7 +201,9 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     A((void **)&c->nl_ang, N * cfg->max_neigh_ang * 4);
     A((void **)&c->nl_rad, N * cfg->max_neigh_rad * 4);
     A((void **)&c->adj_r, N * ADJ_R * 4);
-    A((void **)&c->adj_a, N * ADJ_A * 4);
+    A((void **)&c->pair_grad, N * cfg->max_neigh_ang * sizeof(float4));
+    A((void **)&c->f_own, N * sizeof(float4));
+    A((void **)&c->rev, N * cfg->max_neigh_ang);
     A((void **)&c->w_atom, N * 9 * 4);
     A((void **)&c->e_atom, N * 8);
     A((void **)&c->cells, (size_t)cfg->max_cells * sizeof(CellGeom));
@@ -209,6 +218,10 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     if (ok && hipMemset(c->status, 0, 8 * 4) != hipSuccess) ok = false;
     if (ok && hipMemset(c->md, 0, 8 * 8) != hipSuccess) ok = false;
     if (ok && hipMemset(c->params, 0, P_SIZE * sizeof(float)) != hipSuccess) ok = false;
+    // index arrays start in range, so that no kernel can ever see garbage indices
+    if (ok && hipMemset(c->perm, 0, N * 4) != hipSuccess) ok = false;
+    if (ok && hipMemset(c->ncnt, 0, N * 4) != hipSuccess) ok = false;
+    if (ok && hipMemset(c->cell_of, 0, N * 4) != hipSuccess) ok = false;
     if (ok && hipDeviceSynchronize() != hipSuccess) ok = false;
     if (!ok) { nep_destroy(c); return NEP_E_HIP; }
     *out = c;
@@ -413,6 +426,8 @@ static int launch_build(nep_ctx *c, const nep_system *s, hipStream_t st, const i
         c->pc, lA * lA, lR * lR, c->hp.rc_ang * c->hp.rc_ang, c->hp.rc_rad * c->hp.rc_rad, c->xs,
         c->xs + c->cfg.max_atoms, c->xs + 2 * c->cfg.max_atoms, c->cell_of, c->cells, c->bin_sorted,
         c->bin_start, c->nl_ang, c->nl_rad, c->ncnt, c->status, flag);
+    k_build_reverse<<<grid_for(n, 256), 256, 0, st>>>(c->pc, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->rev,
+                                                      c->status, flag);
     HIP_TRY(hipGetLastError());
     return NEP_OK;
 }
@@ -445,11 +460,11 @@ static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t s
                                                            c->cells, xs, ys, zs, c->status);
     const int tiles = grid_for(n, 256);
     k_descriptor<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xs, ys, zs, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
-                                                  c->ncnt, c->params, c->adj_r, c->adj_a, c->e_atom, c->status,
-                                                  tiles);
+                                                  c->ncnt, c->params, c->adj_r, c->pair_grad, c->f_own, c->w_atom,
+                                                  c->e_atom, c->status, tiles);
     k_force<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xs, ys, zs, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
-                                             c->ncnt, c->params, c->adj_r, c->adj_a, c->perm, o->fx, o->fy, o->fz,
-                                             c->w_atom, c->status, tiles);
+                                             c->ncnt, c->rev, c->adj_r, c->pair_grad, c->f_own, c->perm, o->fx, o->fy,
+                                             o->fz, c->w_atom, c->status, tiles);
     k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom, c->part,
                                                  c->status);
     k_reduce_cells<<<grid_for(c->built_cells, 64), 64, 0, st>>>(c->built_cells, c->cell_chunk, c->part,
@@ -496,12 +511,12 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
                                                            c->cells, xs, ys, zs, c->status);
         HIP_TRY(hipEventRecord(ev[1], st));
         k_descriptor<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xs, ys, zs, c->cell_of, c->cells, c->nl_ang,
-                                                      c->nl_rad, c->ncnt, c->params, c->adj_r, c->adj_a,
-                                                      c->e_atom, c->status, tiles);
+                                                      c->nl_rad, c->ncnt, c->params, c->adj_r, c->pair_grad,
+                                                      c->f_own, c->w_atom, c->e_atom, c->status, tiles);
         HIP_TRY(hipEventRecord(ev[2], st));
         k_force<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xs, ys, zs, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
-                                                 c->ncnt, c->params, c->adj_r, c->adj_a, c->perm, o->fx, o->fy,
-                                                 o->fz, c->w_atom, c->status, tiles);
+                                                 c->ncnt, c->rev, c->adj_r, c->pair_grad, c->f_own, c->perm, o->fx,
+                                                 o->fy, o->fz, c->w_atom, c->status, tiles);
         HIP_TRY(hipEventRecord(ev[3], st));
         k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom,
                                                      c->part, c->status);

@@ -261,7 +261,8 @@ __global__ __launch_bounds__(256) void k_build_lists(
                 const int gb = cg.bin_offset + (bb[2] * cg.nb[1] + bb[1]) * cg.nb[0] + bb[0];
                 for (int u = bin_start[gb]; u < bin_start[gb + 1]; ++u) {
                     if (u == t && self_image) continue;
-                    const double dx = xs[u] + sx - xi, dy = ys[u] + sy - yi, dz = zs[u] + sz - zi;
+                    // (x_u - x_i) + shift: exactly the negative of the vector seen from u
+                    const double dx = (xs[u] - xi) + sx, dy = (ys[u] - yi) + sy, dz = (zs[u] - zi) + sz;
                     const double r2 = dx * dx + dy * dy + dz * dz;
                     if (r2 >= lR2) continue;
                     const uint32_t jl = (uint32_t)(u - cg.atom_start);
@@ -299,6 +300,45 @@ __global__ __launch_bounds__(256) void k_build_lists(
         atomicMax(status + ST_NEED_R, nR);
     }
     ncnt[t] = (uint32_t)naf | ((uint32_t)nab << 8) | ((uint32_t)nrf << 16) | ((uint32_t)nrb << 24);
+}
+
+// Reverse index of the angular lists: for entry (t, slot) naming atom j with
+// image n, the slot of j's list that names t with image -n (255 if absent,
+// which symmetric lists never produce).
+__global__ __launch_bounds__(256) void k_build_reverse(PairConsts pc, const int32_t *__restrict__ cell_of,
+                                                       const CellGeom *__restrict__ cells,
+                                                       const int32_t *__restrict__ nl_ang,
+                                                       const uint32_t *__restrict__ ncnt,
+                                                       uint8_t *__restrict__ rev, int32_t *__restrict__ status,
+                                                       const int32_t *__restrict__ flag)
+{
+    if (flag && *flag == 0) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= pc.n) return;
+    if (status[ST_ERR] != 0) return;
+    const int base = cells[cell_of[t]].atom_start;
+    const uint32_t cnt = ncnt[t];
+    const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff;
+    const uint32_t jmask = (1u << pc.jbits) - 1u, imask = (1u << pc.ibits) - 1u;
+    const uint32_t tl = (uint32_t)(t - base);
+    for (int s = 0; s < naf + nab; ++s) {
+        const int slot = s < naf ? s : s + (pc.capA - naf - nab);
+        const uint32_t e = (uint32_t)nl_ang[(size_t)slot * pc.n + t];
+        const int j = (int)(e & jmask) + base;
+        const uint32_t code = e >> pc.jbits;
+        const int n0 = (int)(code & imask) - pc.ioff, n1 = (int)((code >> pc.ibits) & imask) - pc.ioff,
+                  n2 = (int)(code >> (2 * pc.ibits)) - pc.ioff;
+        const uint32_t want = tl | (((uint32_t)(-n0 + pc.ioff) | ((uint32_t)(-n1 + pc.ioff) << pc.ibits) |
+                                     ((uint32_t)(-n2 + pc.ioff) << (2 * pc.ibits))) << pc.jbits);
+        const uint32_t cj = ncnt[j];
+        const int jf = cj & 0xff, jb = (cj >> 8) & 0xff;
+        int found = 255;
+        for (int q = 0; q < jf + jb; ++q) {
+            const int sq = q < jf ? q : q + (pc.capA - jf - jb);
+            if ((uint32_t)nl_ang[(size_t)sq * pc.n + j] == want) { found = sq; break; }
+        }
+        rev[(size_t)slot * pc.n + t] = (uint8_t)found;
+    }
 }
 
 // ------------------------------------------------------------------ velocity Verlet

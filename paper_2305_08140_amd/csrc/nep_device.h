@@ -110,6 +110,37 @@ __host__ __device__ inline float scaled_minus_one(float r, float inv, float inv_
     return fmaf(r, inv, -1.0f) + r * inv_lo;
 }
 
+// Double-precision pieces of the descriptor's pair geometry.
+// sin(y) for |y| <= pi/2, Taylor series to y^17 (truncation error < 5e-14).
+__host__ __device__ inline double sin_halfpi_d(double y)
+{
+    const double y2 = y * y;
+    double p = 1.0 / 355687428096000.0;            // 1/17!
+    p = fma(p, y2, -1.0 / 1307674368000.0);        // -1/15!
+    p = fma(p, y2, 1.0 / 6227020800.0);            // 1/13!
+    p = fma(p, y2, -1.0 / 39916800.0);             // -1/11!
+    p = fma(p, y2, 1.0 / 362880.0);                // 1/9!
+    p = fma(p, y2, -1.0 / 5040.0);                 // -1/7!
+    p = fma(p, y2, 1.0 / 120.0);
+    p = fma(p, y2, -1.0 / 6.0);
+    p = fma(p, y2, 1.0);
+    return p * y;
+}
+
+// fc(r) and T_0..T_8(x), x = 2 (r/rc - 1)^2 - 1, in double precision.
+__host__ __device__ inline void basis_d(double r, double inv_rc, double &fc, double T[KB])
+{
+    const double PI = 3.14159265358979323846;
+    const double tt = r * inv_rc - 1.0;
+    fc = 0.5 - 0.5 * sin_halfpi_d(PI * (tt + 0.5));
+    const double x = 2.0 * tt * tt - 1.0;
+    T[0] = 1.0;
+    T[1] = x;
+    const double x2 = 2.0 * x;
+#pragma unroll
+    for (int k = 2; k < KB; ++k) T[k] = fma(x2, T[k - 1], -T[k - 2]);
+}
+
 // Smooth cutoff fc(r) = (1 + cos(pi r/rc))/2 and its derivative, for r < rc,
 // from tt = r/rc - 1.  With y = pi (tt + 1/2): cos(pi r/rc) = -sin(y),
 // sin(pi r/rc) = cos(y); pi is carried as two floats for the same reason.

@@ -18,6 +18,8 @@ void nep_test_cutoff(float r, float rc, float *fc, float *dfc)
 
 void nep_test_cheb(float x, float *T, float *dT) { cheb_d(x, T, dT); }
 
+void nep_test_basis_d(double r, double rc, double *fc, double *T) { basis_d(r, 1.0 / rc, *fc, T); }
+
 void nep_test_sph(float x, float y, float z, float *Y) { sph(x, y, z, Y); }
 
 void nep_test_sph_grad(float x, float y, float z, const float *Dc, float *v)

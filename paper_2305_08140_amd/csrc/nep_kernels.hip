@@ -3,9 +3,13 @@
 // Atom data live in a cell-list ("sorted") order: within every cell, atoms
 // are grouped by bin, so that a 64-wide wavefront works on spatially close
 // atoms and its neighbour gathers hit the same cache lines.  Positions are
-// FP64 structure-of-arrays; every pair vector is formed in FP64 and rounded
-// to FP32 before any further arithmetic, so that absolute coordinates of a
-// 500 A box never lose precision in the pair geometry.
+// FP64 structure-of-arrays; every pair vector is formed in FP64, so absolute
+// coordinates of a 500 A box never lose precision in the pair geometry.  The
+// descriptor's pair geometry and Chebyshev basis stay in FP64 (on CDNA an
+// FP64 FMA issues at the rate of an unpacked FP32 FMA): the odd-l angular
+// descriptors of a near-perfect lattice are small sums of large cancelling
+// terms, and FP32 rounding there would dominate the force error.  Harmonics,
+// sums, network and the force-side arithmetic are FP32.
 //
 // Energy (Eq. 1): the descriptor kernel computes, per atom i,
 //   radial   A_k = sum_j fc(r_ij) T_k(x_ij)  ->  F_k = (A_k + A_0)/2 = sum_j f_k(r_ij)
@@ -17,40 +21,24 @@
 // and stores the adjoints dU_i/dF_k (9 floats) and B_{n,lm} = dU_i/ds_{n,lm}
 // (120 floats).
 //
-// Forces: F_i = sum_j [dU_i/dr_ij - dU_j/dr_ji].  Because Y_lm(-u) = (-1)^l Y_lm(u)
-// and the radial basis depends on |r| only, both terms are the gradient at r_ij
-// of ONE function:  G(r) = sum_k (a^i_k + a^j_k) f_k(|r|)
-//                        + sum_{n,lm} (B^i_{n,lm} + (-1)^l B^j_{n,lm}) g_n(|r|) Y_lm(r/|r|)
-// plus the ZBL term, so the force kernel evaluates one pair gradient per
-// neighbour (no second evaluation for the j side) and needs no atomics: every
-// atom gathers its own force, deterministically.
-// Virial: W = -1/2 sum_i sum_j f_ij (x) r_ij with f_ij the pair's contribution to F_i.
+// Forces: F_i = sum_j [dU_i/dr_ij - dU_j/dr_ji].
+//   radial part: both terms depend on |r_ij| only, so together they are
+//     (a^i + a^j) . f'(r_ij) u_ij, one evaluation per pair with the neighbour's
+//     9 adjoint floats gathered;
+//   angular part: the descriptor kernel, which holds B^i in registers, stores
+//     dU_i/dr_ij for every angular pair (16 bytes per pair) and the force
+//     kernel subtracts the stored dU_j/dr_ji found through a reverse index
+//     built with the lists.
+// No atomics: every atom gathers its own force, deterministically.  The pair
+// vector seen from j is the exact negative of the one seen from i, so both
+// ends agree bit for bit on which pairs are inside a cutoff.
+// Virial: W = -sum_i sum_j dU_i/dr_ij (x) r_ij (angular, per owner) plus
+// -1/2 sum_i sum_j f_ij (x) r_ij for the radial and ZBL pair forces f_ij.
 #include "nep_device.h"
 
 namespace nep {
 
 // ------------------------------------------------------------------ helpers
-
-__device__ inline void pair_vector(int32_t e, const PairConsts &pc, int base, double xi, double yi,
-                                   double zi, const double *__restrict__ xs,
-                                   const double *__restrict__ ys, const double *__restrict__ zs,
-                                   const CellGeom *__restrict__ cg, int &j, float &dx, float &dy,
-                                   float &dz)
-{
-    int n0, n1, n2;
-    decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
-    j += base;
-    double ddx = xs[j] - xi, ddy = ys[j] - yi, ddz = zs[j] - zi;
-    if (n0 | n1 | n2) {
-        const double *h = cg->h;
-        ddx += n0 * h[0] + n1 * h[3] + n2 * h[6];
-        ddy += n0 * h[1] + n1 * h[4] + n2 * h[7];
-        ddz += n0 * h[2] + n1 * h[5] + n2 * h[8];
-    }
-    dx = (float)ddx;
-    dy = (float)ddy;
-    dz = (float)ddz;
-}
 
 // slot of the s-th entry of a list stored front-to-back (nf entries) and
 // back-to-front (nb entries) in a column of capacity cap
@@ -68,13 +56,53 @@ __device__ inline float ftanh(float z)
 
 // ------------------------------------------------------------------ descriptor + network
 
+// Pair vector in double precision, computed so that the vector seen from the
+// other end of the pair is its exact negative: (x_j - x_i) first, then the
+// image shift n.h (which is exactly negated for -n).
+__device__ inline void pair_vector_d(int32_t e, const PairConsts &pc, int base, double xi, double yi,
+                                     double zi, const double *__restrict__ xs,
+                                     const double *__restrict__ ys, const double *__restrict__ zs,
+                                     const CellGeom *__restrict__ cg, int &j, double &dx, double &dy,
+                                     double &dz)
+{
+    int n0, n1, n2;
+    decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
+    j += base;
+    dx = xs[j] - xi;
+    dy = ys[j] - yi;
+    dz = zs[j] - zi;
+    if (n0 | n1 | n2) {
+        const double *h = cg->h;
+        dx += n0 * h[0] + n1 * h[3] + n2 * h[6];
+        dy += n0 * h[1] + n1 * h[4] + n2 * h[7];
+        dz += n0 * h[2] + n1 * h[5] + n2 * h[8];
+    }
+}
+
+// |r| in double precision from r^2: FP32 square root refined by one
+// Newton step (relative error ~1e-15).
+__device__ inline double dist_d(double r2)
+{
+    const float rf = fsqrt((float)r2);
+    const double rd = (double)rf;
+    return rd + fma(-rd, rd, r2) * (double)(0.5f * frcp(rf));
+}
+
+// Descriptor (FP64 pair geometry and basis, FP32 harmonics and sums), site
+// energy, network forward and backward, the radial adjoint dU_i/dF_k (stored),
+// and then, with B_{n,lm} = dU_i/ds_{n,lm} kept in registers, the gradient of
+// U_i with respect to every angular pair vector, dU_i/dr_ij.  Those pair
+// gradients are stored per list slot (the force kernel subtracts them at the
+// other end of the pair), their sum is this atom's own angular force term,
+// and -sum_j dU_i/dr_ij (x) r_ij is its angular virial.
 __global__ __launch_bounds__(256) void k_descriptor(
     PairConsts pc, const double *__restrict__ xs, const double *__restrict__ ys,
     const double *__restrict__ zs, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
-    const float *__restrict__ P, float *__restrict__ adj_r, float *__restrict__ adj_a,
-    double *__restrict__ e_atom, int32_t *__restrict__ status, int ntiles)
+    const float *__restrict__ P, float *__restrict__ adj_r, float4 *__restrict__ pair_grad,
+    float4 *__restrict__ f_own, float *__restrict__ w_atom, double *__restrict__ e_atom,
+    int32_t *__restrict__ status, int ntiles)
 {
     const int tile = xcd_block(ntiles);
     if (tile >= ntiles) return;
@@ -87,6 +115,8 @@ __global__ __launch_bounds__(256) void k_descriptor(
     const int base = cg->atom_start;
     const uint32_t cnt = ncnt[t];
     const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
+    const double inv_rR = 1.0 / (double)pc.rc_rad, inv_rA = 1.0 / (double)pc.rc_ang;
+    const double rcR2 = (double)pc.rc_rad * pc.rc_rad, rcA2 = (double)pc.rc_ang * pc.rc_ang;
 
     float csA[NA];
 #pragma unroll
@@ -97,9 +127,9 @@ __global__ __launch_bounds__(256) void k_descriptor(
         csA[n] = s;
     }
 
-    float AR[KB];
+    double AR[KB];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) AR[k] = 0.0f;
+    for (int k = 0; k < KB; ++k) AR[k] = 0.0;
     float S[NA][NLM];
 #pragma unroll
     for (int n = 0; n < NA; ++n)
@@ -108,71 +138,59 @@ __global__ __launch_bounds__(256) void k_descriptor(
     double ezbl = 0.0;
     bool overlap = false;
 
-    // angular list: every entry may be inside both cutoffs
     const int nA = naf + nab;
     for (int s = 0; s < nA; ++s) {
         const int32_t e = nl_ang[(size_t)list_slot(s, naf, nab, pc.capA) * pc.n + t];
         int j;
-        float dx, dy, dz;
-        pair_vector(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 >= pc.rc_rad2) continue;
-        const float r = fsqrt(r2);
-        overlap |= (r < 1e-3f);
-        {   // radial basis
-            const float tt = scaled_minus_one(r, pc.inv_rc_rad, pc.inv_rc_rad_lo);
-            float fc;
-            cutoff_value(tt, fc);
-            float T[KB];
-            cheb(fmaf(2.0f * tt, tt, -1.0f), T);
+        double dx, dy, dz;
+        pair_vector_d(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= rcR2) continue;
+        const double r = dist_d(r2);
+        overlap |= (r < 1e-3);
+        {
+            double fc, T[KB];
+            basis_d(r, inv_rR, fc, T);
 #pragma unroll
-            for (int k = 0; k < KB; ++k) AR[k] = fmaf(fc, T[k], AR[k]);
+            for (int k = 0; k < KB; ++k) AR[k] = fma(fc, T[k], AR[k]);
         }
-        if (r2 < pc.rc_ang2) {
-            const float tt = scaled_minus_one(r, pc.inv_rc_ang, pc.inv_rc_ang_lo);
-            float fc;
-            cutoff_value(tt, fc);
-            float T[KB];
-            cheb(fmaf(2.0f * tt, tt, -1.0f), T);
+        if (r2 < rcA2) {
+            double fc, T[KB];
+            basis_d(r, inv_rA, fc, T);
             float g[NA];
 #pragma unroll
             for (int n = 0; n < NA; ++n) {
-                float s2 = csA[n];
+                double s2 = (double)csA[n];
 #pragma unroll
-                for (int k = 0; k < KB; ++k) s2 = fmaf(P[P_CA + n * KB + k], T[k], s2);
-                g[n] = 0.5f * fc * s2;
+                for (int k = 0; k < KB; ++k) s2 = fma((double)P[P_CA + n * KB + k], T[k], s2);
+                g[n] = (float)(0.5 * fc * s2);
             }
-            const float rinv = frcp(r);
+            const float rinv = frcp((float)r);
             float Y[NLM];
-            sph(dx * rinv, dy * rinv, dz * rinv, Y);
+            sph((float)dx * rinv, (float)dy * rinv, (float)dz * rinv, Y);
 #pragma unroll
             for (int n = 0; n < NA; ++n)
 #pragma unroll
                 for (int lm = 0; lm < NLM; ++lm) S[n][lm] = fmaf(g[n], Y[lm], S[n][lm]);
         }
-        if (r2 < pc.zbl_r2sq) {
+        if (r < (double)pc.zbl_r2) {
             double U, dU;
-            zbl_pair((double)r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
+            zbl_pair(r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
             ezbl += 0.5 * U;
         }
     }
-    // radial-only list
     const int nRl = nrf + nrb;
     for (int s = 0; s < nRl; ++s) {
         const int32_t e = nl_rad[(size_t)list_slot(s, nrf, nrb, pc.capR) * pc.n + t];
         int j;
-        float dx, dy, dz;
-        pair_vector(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 >= pc.rc_rad2) continue;
-        const float r = fsqrt(r2);
-        const float tt = scaled_minus_one(r, pc.inv_rc_rad, pc.inv_rc_rad_lo);
-        float fc;
-        cutoff_value(tt, fc);
-        float T[KB];
-        cheb(fmaf(2.0f * tt, tt, -1.0f), T);
+        double dx, dy, dz;
+        pair_vector_d(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= rcR2) continue;
+        double fc, T[KB];
+        basis_d(dist_d(r2), inv_rR, fc, T);
 #pragma unroll
-        for (int k = 0; k < KB; ++k) AR[k] = fmaf(fc, T[k], AR[k]);
+        for (int k = 0; k < KB; ++k) AR[k] = fma(fc, T[k], AR[k]);
     }
     if (overlap) latch_error(status, -4);
 
@@ -181,7 +199,7 @@ __global__ __launch_bounds__(256) void k_descriptor(
     {
         float F[KB];
 #pragma unroll
-        for (int k = 0; k < KB; ++k) F[k] = 0.5f * (AR[k] + AR[0]);
+        for (int k = 0; k < KB; ++k) F[k] = (float)(0.5 * (AR[k] + AR[0]));
 #pragma unroll
         for (int n = 0; n < NR; ++n) {
             float s = 0.0f;
@@ -199,65 +217,139 @@ __global__ __launch_bounds__(256) void k_descriptor(
                 q[NR + NA * (l - 1) + n] = s;
             }
     }
-    // network: forward and backward
+    // network, forward and backward in one pass over the hidden neurons: row
+    // mu of w0 gives z_mu, and dU/dz_mu times the same row accumulates dU/dq
+    float qt[DIM];
+#pragma unroll
+    for (int nu = 0; nu < DIM; ++nu) qt[nu] = P[P_QS + nu] * q[nu];
     float U = -P[P_B1];
-    float dzv[NH];
-#pragma unroll
-    for (int mu = 0; mu < NH; ++mu) {
-        float z = -P[P_B0 + mu];
-#pragma unroll
-        for (int nu = 0; nu < DIM; ++nu) z = fmaf(P[P_W0 + mu * DIM + nu], P[P_QS + nu] * q[nu], z);
-        const float th = ftanh(z);
-        U = fmaf(P[P_W1 + mu], th, U);
-        dzv[mu] = P[P_W1 + mu] * fmaf(-th, th, 1.0f);
-    }
     float Fp[DIM];
 #pragma unroll
-    for (int nu = 0; nu < DIM; ++nu) {
-        float s = 0.0f;
+    for (int nu = 0; nu < DIM; ++nu) Fp[nu] = 0.0f;
+#pragma unroll 1
+    for (int mu = 0; mu < NH; ++mu) {
+        const float *w = P + P_W0 + mu * DIM;
+        float z = -P[P_B0 + mu];
 #pragma unroll
-        for (int mu = 0; mu < NH; ++mu) s = fmaf(dzv[mu], P[P_W0 + mu * DIM + nu], s);
-        Fp[nu] = s * P[P_QS + nu];
+        for (int nu = 0; nu < DIM; ++nu) z = fmaf(w[nu], qt[nu], z);
+        const float th = ftanh(z);
+        const float w1 = P[P_W1 + mu];
+        U = fmaf(w1, th, U);
+        const float dz = w1 * fmaf(-th, th, 1.0f);
+#pragma unroll
+        for (int nu = 0; nu < DIM; ++nu) Fp[nu] = fmaf(dz, w[nu], Fp[nu]);
     }
-    // adjoints
-    float *ar = adj_r + (size_t)t * ADJ_R;
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-        float s = 0.0f;
+    for (int nu = 0; nu < DIM; ++nu) Fp[nu] *= P[P_QS + nu];
+    e_atom[t] = (double)U + ezbl;
+    // radial adjoint a_k = dU_i / dF_k
+    {
+        float a[ADJ_R];
 #pragma unroll
-        for (int n = 0; n < NR; ++n) s = fmaf(Fp[n], P[P_CR + n * KB + k], s);
-        ar[k] = s;
+        for (int k = 0; k < KB; ++k) {
+            float s = 0.0f;
+#pragma unroll
+            for (int n = 0; n < NR; ++n) s = fmaf(Fp[n], P[P_CR + n * KB + k], s);
+            a[k] = s;
+        }
+#pragma unroll
+        for (int k = KB; k < ADJ_R; ++k) a[k] = 0.0f;
+        float4 *ar = reinterpret_cast<float4 *>(adj_r + (size_t)t * ADJ_R);
+        ar[0] = make_float4(a[0], a[1], a[2], a[3]);
+        ar[1] = make_float4(a[4], a[5], a[6], a[7]);
+        ar[2] = make_float4(a[8], 0.0f, 0.0f, 0.0f);
     }
-#pragma unroll
-    for (int k = KB; k < ADJ_R; ++k) ar[k] = 0.0f;
-    float4 *aa = reinterpret_cast<float4 *>(adj_a + (size_t)t * ADJ_A);
+    // angular adjoint B_{n,lm} = 2 (dU/dq_nl) s_{n,lm}, in place of S
 #pragma unroll
     for (int n = 0; n < NA; ++n)
 #pragma unroll
-        for (int v = 0; v < NLM / 4; ++v) {
-            float o[4];
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const int lm = 4 * v + w;
-                const int l = lm < 3 ? 1 : (lm < 8 ? 2 : (lm < 15 ? 3 : 4));
-                o[w] = 2.0f * Fp[NR + NA * (l - 1) + n] * S[n][lm];
-            }
-            aa[n * (NLM / 4) + v] = make_float4(o[0], o[1], o[2], o[3]);
+        for (int lm = 0; lm < NLM; ++lm) {
+            const int l = lm < 3 ? 1 : (lm < 8 ? 2 : (lm < 15 ? 3 : 4));
+            S[n][lm] *= 2.0f * Fp[NR + NA * (l - 1) + n];
         }
-    e_atom[t] = (double)U + ezbl;
+
+    // angular pair gradients dU_i/dr_ij = grad_r [sum_{n,lm} B_{n,lm} g_n(|r|) Y_lm(r/|r|)]
+    float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
+    float W[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) W[k] = 0.0f;
+    for (int s = 0; s < nA; ++s) {
+        const int slot = list_slot(s, naf, nab, pc.capA);
+        const int32_t e = nl_ang[(size_t)slot * pc.n + t];
+        int j;
+        double ddx, ddy, ddz;
+        pair_vector_d(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, ddx, ddy, ddz);
+        const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= pc.rc_ang2) continue;
+        const float r = fsqrt(r2);
+        const float rinv = frcp(r);
+        const float tt = scaled_minus_one(r, pc.inv_rc_ang, pc.inv_rc_ang_lo);
+        float fc, dfc;
+        cutoff(tt, pc.inv_rc_ang, fc, dfc);
+        const float dxdr = 4.0f * tt * pc.inv_rc_ang;
+        float T[KB], dT[KB];
+        cheb_d(fmaf(2.0f * tt, tt, -1.0f), T, dT);
+        float g[NA], gp[NA];
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
+            float sn = csA[n], sp = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                sn = fmaf(P[P_CA + n * KB + k], T[k], sn);
+                sp = fmaf(P[P_CA + n * KB + k], dT[k], sp);
+            }
+            g[n] = 0.5f * fc * sn;
+            gp[n] = 0.5f * fmaf(dxdr * fc, sp, dfc * sn);
+        }
+        const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+        float Y[NLM];
+        sph(ux, uy, uz, Y);
+        float Dc[NLM];
+        float s1 = 0.0f;
+#pragma unroll
+        for (int lm = 0; lm < NLM; ++lm) {
+            float D = 0.0f, Dp = 0.0f;
+#pragma unroll
+            for (int n = 0; n < NA; ++n) {
+                D = fmaf(S[n][lm], g[n], D);
+                Dp = fmaf(S[n][lm], gp[n], Dp);
+            }
+            Dc[lm] = D;
+            s1 = fmaf(Dp, Y[lm], s1);
+        }
+        float vx, vy, vz;
+        sph_grad_contract(ux, uy, uz, Dc, vx, vy, vz);
+        const float uv = ux * vx + uy * vy + uz * vz;
+        const float gx = fmaf(s1, ux, (vx - uv * ux) * rinv);
+        const float gy = fmaf(s1, uy, (vy - uv * uy) * rinv);
+        const float gz = fmaf(s1, uz, (vz - uv * uz) * rinv);
+        pair_grad[(size_t)slot * pc.n + t] = make_float4(gx, gy, gz, 0.0f);
+        Fx += gx; Fy += gy; Fz += gz;
+        W[0] = fmaf(gx, dx, W[0]); W[1] = fmaf(gx, dy, W[1]); W[2] = fmaf(gx, dz, W[2]);
+        W[3] = fmaf(gy, dx, W[3]); W[4] = fmaf(gy, dy, W[4]); W[5] = fmaf(gy, dz, W[5]);
+        W[6] = fmaf(gz, dx, W[6]); W[7] = fmaf(gz, dy, W[7]); W[8] = fmaf(gz, dz, W[8]);
+    }
+    f_own[t] = make_float4(Fx, Fy, Fz, 0.0f);
+    float *w = w_atom + (size_t)t * 9;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k] = -W[k];
 }
 
 // ------------------------------------------------------------------ forces + virial
 
+// F_i = sum_j (a^i + a^j) . f'(r_ij) u_ij + U'_ZBL(r_ij) u_ij        (radial + ZBL)
+//     + sum_j [dU_i/dr_ij - dU_j/dr_ji]_angular                       (stored pair gradients)
+// and the radial + ZBL virial -1/2 sum_j f_ij (x) r_ij added to the angular one.
 __global__ __launch_bounds__(256) void k_force(
     PairConsts pc, const double *__restrict__ xs, const double *__restrict__ ys,
     const double *__restrict__ zs, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
-    const float *__restrict__ P, const float *__restrict__ adj_r, const float *__restrict__ adj_a,
+    const uint8_t *__restrict__ rev, const float *__restrict__ adj_r,
+    const float4 *__restrict__ pair_grad, const float4 *__restrict__ f_own,
     const int32_t *__restrict__ perm, float *__restrict__ fx, float *__restrict__ fy,
-    float *__restrict__ fz, float *__restrict__ w_atom, const int32_t *__restrict__ status,
-    int ntiles)
+    float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status, int ntiles)
 {
     const int tile = xcd_block(ntiles);
     if (tile >= ntiles) return;
@@ -272,43 +364,29 @@ __global__ __launch_bounds__(256) void k_force(
     const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
 
     float ai[KB];
-#pragma unroll
-    for (int k = 0; k < KB; ++k) ai[k] = adj_r[(size_t)t * ADJ_R + k];
-    float Bi[NA * NLM];
     {
-        const float4 *src = reinterpret_cast<const float4 *>(adj_a + (size_t)t * ADJ_A);
-#pragma unroll
-        for (int v = 0; v < ADJ_A / 4; ++v) {
-            const float4 b = src[v];
-            Bi[4 * v] = b.x; Bi[4 * v + 1] = b.y; Bi[4 * v + 2] = b.z; Bi[4 * v + 3] = b.w;
-        }
+        const float4 *a4 = reinterpret_cast<const float4 *>(adj_r + (size_t)t * ADJ_R);
+        const float4 a0 = a4[0], a1 = a4[1], a2 = a4[2];
+        ai[0] = a0.x; ai[1] = a0.y; ai[2] = a0.z; ai[3] = a0.w;
+        ai[4] = a1.x; ai[5] = a1.y; ai[6] = a1.z; ai[7] = a1.w; ai[8] = a2.x;
     }
-    float csA[NA];
-#pragma unroll
-    for (int n = 0; n < NA; ++n) {
-        float s = 0.0f;
-#pragma unroll
-        for (int k = 0; k < KB; ++k) s += P[P_CA + n * KB + k];
-        csA[n] = s;
-    }
-
-    float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
+    const float4 fo = f_own[t];
+    float Fx = fo.x, Fy = fo.y, Fz = fo.z;
     float W[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) W[k] = 0.0f;
 
-    // radial part of the pair gradient, plus ZBL; returns dG/dr
-    auto radial_dr = [&](int j, float r) -> float {
+    // dG/dr of the radial part of the pair (both ends) plus ZBL, divided by r
+    auto radial_over_r = [&](int j, float r, float rinv) -> float {
         const float tt = scaled_minus_one(r, pc.inv_rc_rad, pc.inv_rc_rad_lo);
         float fc, dfc;
         cutoff(tt, pc.inv_rc_rad, fc, dfc);
         const float dxdr = 4.0f * tt * pc.inv_rc_rad;
         float T[KB], dT[KB];
         cheb_d(fmaf(2.0f * tt, tt, -1.0f), T, dT);
-        const float *aj = adj_r + (size_t)j * ADJ_R;
-        const float4 a0 = reinterpret_cast<const float4 *>(aj)[0];
-        const float4 a1 = reinterpret_cast<const float4 *>(aj)[1];
-        const float a8 = aj[8];
+        const float4 *a4 = reinterpret_cast<const float4 *>(adj_r + (size_t)j * ADJ_R);
+        const float4 a0 = a4[0], a1 = a4[1];
+        const float a8 = adj_r[(size_t)j * ADJ_R + 8];
         const float ah[KB] = {ai[0] + a0.x, ai[1] + a0.y, ai[2] + a0.z, ai[3] + a0.w, ai[4] + a1.x,
                               ai[5] + a1.y, ai[6] + a1.z, ai[7] + a1.w, ai[8] + a8};
         float s0 = 0.0f, s1 = 0.0f, sa = 0.0f;
@@ -318,109 +396,65 @@ __global__ __launch_bounds__(256) void k_force(
             s1 = fmaf(ah[k], dT[k], s1);
             sa += ah[k];
         }
-        return 0.5f * (dxdr * fc * s1 + dfc * (s0 + sa));
-    };
-
-    const int nA = naf + nab;
-    for (int s = 0; s < nA; ++s) {
-        const int32_t e = nl_ang[(size_t)list_slot(s, naf, nab, pc.capA) * pc.n + t];
-        int j;
-        float dx, dy, dz;
-        pair_vector(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 >= pc.rc_rad2) continue;
-        const float r = fsqrt(r2);
-        const float rinv = frcp(r);
-        float dGdr = radial_dr(j, r);
-        if (r2 < pc.zbl_r2sq) {
+        float dGdr = 0.5f * (dxdr * fc * s1 + dfc * (s0 + sa));
+        if (r < pc.zbl_r2) {
             double U, dU;
             zbl_pair((double)r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
             dGdr += (float)dU;
         }
-        const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
-        float fxp = dGdr * ux, fyp = dGdr * uy, fzp = dGdr * uz;
+        return dGdr * rinv;
+    };
+
+    const int nA = naf + nab;
+    bool bad = false;
+    for (int s = 0; s < nA; ++s) {
+        const int slot = list_slot(s, naf, nab, pc.capA);
+        const int32_t e = nl_ang[(size_t)slot * pc.n + t];
+        int j;
+        double ddx, ddy, ddz;
+        pair_vector_d(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, ddx, ddy, ddz);
+        const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= pc.rc_rad2) continue;
+        const float r = fsqrt(r2);
+        const float c = radial_over_r(j, r, frcp(r));
+        const float px = c * dx, py = c * dy, pz = c * dz;
+        Fx += px; Fy += py; Fz += pz;
+        W[0] = fmaf(px, dx, W[0]); W[1] = fmaf(px, dy, W[1]); W[2] = fmaf(px, dz, W[2]);
+        W[3] = fmaf(py, dx, W[3]); W[4] = fmaf(py, dy, W[4]); W[5] = fmaf(py, dz, W[5]);
+        W[6] = fmaf(pz, dx, W[6]); W[7] = fmaf(pz, dy, W[7]); W[8] = fmaf(pz, dz, W[8]);
         if (r2 < pc.rc_ang2) {
-            const float tt = scaled_minus_one(r, pc.inv_rc_ang, pc.inv_rc_ang_lo);
-            float fc, dfc;
-            cutoff(tt, pc.inv_rc_ang, fc, dfc);
-            const float dxdr = 4.0f * tt * pc.inv_rc_ang;
-            float T[KB], dT[KB];
-            cheb_d(fmaf(2.0f * tt, tt, -1.0f), T, dT);
-            float g[NA], gp[NA];
-#pragma unroll
-            for (int n = 0; n < NA; ++n) {
-                float sn = csA[n], sp = 0.0f;
-#pragma unroll
-                for (int k = 0; k < KB; ++k) {
-                    sn = fmaf(P[P_CA + n * KB + k], T[k], sn);
-                    sp = fmaf(P[P_CA + n * KB + k], dT[k], sp);
-                }
-                g[n] = 0.5f * fc * sn;
-                gp[n] = 0.5f * fmaf(dxdr * fc, sp, dfc * sn);
-            }
-            float Y[NLM];
-            sph(ux, uy, uz, Y);
-            const float4 *bj4 = reinterpret_cast<const float4 *>(adj_a + (size_t)j * ADJ_A);
-            float Dc[NLM];
-            float s1 = 0.0f;
-#pragma unroll
-            for (int lm = 0; lm < NLM; ++lm) Dc[lm] = 0.0f;
-            float Dp[NLM];
-#pragma unroll
-            for (int lm = 0; lm < NLM; ++lm) Dp[lm] = 0.0f;
-#pragma unroll
-            for (int n = 0; n < NA; ++n) {
-#pragma unroll
-                for (int v = 0; v < NLM / 4; ++v) {
-                    const float4 b = bj4[n * (NLM / 4) + v];
-                    const float bj[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        const int lm = 4 * v + w;
-                        const bool odd = (lm < 3) || (lm >= 8 && lm < 15);
-                        const float bh = odd ? Bi[n * NLM + lm] - bj[w] : Bi[n * NLM + lm] + bj[w];
-                        Dc[lm] = fmaf(bh, g[n], Dc[lm]);
-                        Dp[lm] = fmaf(bh, gp[n], Dp[lm]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int lm = 0; lm < NLM; ++lm) s1 = fmaf(Dp[lm], Y[lm], s1);
-            float vx, vy, vz;
-            sph_grad_contract(ux, uy, uz, Dc, vx, vy, vz);
-            const float uv = ux * vx + uy * vy + uz * vz;
-            fxp += s1 * ux + (vx - uv * ux) * rinv;
-            fyp += s1 * uy + (vy - uv * uy) * rinv;
-            fzp += s1 * uz + (vz - uv * uz) * rinv;
+            const int sj = rev[(size_t)slot * pc.n + t];
+            if (sj == 255) { bad = true; continue; }
+            const float4 gj = pair_grad[(size_t)sj * pc.n + j];
+            Fx -= gj.x; Fy -= gj.y; Fz -= gj.z;
         }
-        Fx += fxp; Fy += fyp; Fz += fzp;
-        W[0] = fmaf(fxp, dx, W[0]); W[1] = fmaf(fxp, dy, W[1]); W[2] = fmaf(fxp, dz, W[2]);
-        W[3] = fmaf(fyp, dx, W[3]); W[4] = fmaf(fyp, dy, W[4]); W[5] = fmaf(fyp, dz, W[5]);
-        W[6] = fmaf(fzp, dx, W[6]); W[7] = fmaf(fzp, dy, W[7]); W[8] = fmaf(fzp, dz, W[8]);
     }
     const int nRl = nrf + nrb;
     for (int s = 0; s < nRl; ++s) {
         const int32_t e = nl_rad[(size_t)list_slot(s, nrf, nrb, pc.capR) * pc.n + t];
         int j;
-        float dx, dy, dz;
-        pair_vector(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
+        double ddx, ddy, ddz;
+        pair_vector_d(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, ddx, ddy, ddz);
+        const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
         const float r2 = dx * dx + dy * dy + dz * dz;
         if (r2 >= pc.rc_rad2) continue;
         const float r = fsqrt(r2);
-        const float c = radial_dr(j, r) * frcp(r);
-        const float fxp = c * dx, fyp = c * dy, fzp = c * dz;
-        Fx += fxp; Fy += fyp; Fz += fzp;
-        W[0] = fmaf(fxp, dx, W[0]); W[1] = fmaf(fxp, dy, W[1]); W[2] = fmaf(fxp, dz, W[2]);
-        W[3] = fmaf(fyp, dx, W[3]); W[4] = fmaf(fyp, dy, W[4]); W[5] = fmaf(fyp, dz, W[5]);
-        W[6] = fmaf(fzp, dx, W[6]); W[7] = fmaf(fzp, dy, W[7]); W[8] = fmaf(fzp, dz, W[8]);
+        const float c = radial_over_r(j, r, frcp(r));
+        const float px = c * dx, py = c * dy, pz = c * dz;
+        Fx += px; Fy += py; Fz += pz;
+        W[0] = fmaf(px, dx, W[0]); W[1] = fmaf(px, dy, W[1]); W[2] = fmaf(px, dz, W[2]);
+        W[3] = fmaf(py, dx, W[3]); W[4] = fmaf(py, dy, W[4]); W[5] = fmaf(py, dz, W[5]);
+        W[6] = fmaf(pz, dx, W[6]); W[7] = fmaf(pz, dy, W[7]); W[8] = fmaf(pz, dz, W[8]);
     }
+    if (bad) latch_error(status, -9);
     const int i = perm[t];
     fx[i] = Fx;
     fy[i] = Fy;
     fz[i] = Fz;
     float *w = w_atom + (size_t)t * 9;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) w[k] = -0.5f * W[k];
+    for (int k = 0; k < 9; ++k) w[k] = fmaf(-0.5f, W[k], w[k]);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -501,21 +535,22 @@ __global__ __launch_bounds__(256) void k_count_inside(
         const CellGeom *cg = cells + cell_of[t];
         const uint32_t cnt = ncnt[t];
         const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
+        const double rcR2 = (double)pc.rc_rad * pc.rc_rad, rcA2 = (double)pc.rc_ang * pc.rc_ang;
         for (int s = 0; s < naf + nab; ++s) {
             int j;
-            float dx, dy, dz;
-            pair_vector(nl_ang[(size_t)list_slot(s, naf, nab, pc.capA) * pc.n + t], pc, cg->atom_start,
-                        xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            nr += r2 < pc.rc_rad2;
-            na += r2 < pc.rc_ang2;
+            double dx, dy, dz;
+            pair_vector_d(nl_ang[(size_t)list_slot(s, naf, nab, pc.capA) * pc.n + t], pc, cg->atom_start,
+                          xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            nr += r2 < rcR2;
+            na += r2 < rcA2;
         }
         for (int s = 0; s < nrf + nrb; ++s) {
             int j;
-            float dx, dy, dz;
-            pair_vector(nl_rad[(size_t)list_slot(s, nrf, nrb, pc.capR) * pc.n + t], pc, cg->atom_start,
-                        xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
-            nr += (dx * dx + dy * dy + dz * dz) < pc.rc_rad2;
+            double dx, dy, dz;
+            pair_vector_d(nl_rad[(size_t)list_slot(s, nrf, nrb, pc.capR) * pc.n + t], pc, cg->atom_start,
+                          xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
+            nr += (dx * dx + dy * dy + dz * dz) < rcR2;
         }
     }
     // wave-level sum, one atomic per wave

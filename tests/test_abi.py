@@ -59,7 +59,7 @@ def test_argument_errors_without_device():
 
 def test_strerror_covers_codes():
     nep, L = _lib()
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         s = nep.strerror(code)
         assert s and s != "unknown error"
     assert nep.strerror(-99) == "unknown error"

@@ -24,6 +24,7 @@ def L():
     lib.nep_test_sincos.argtypes = [F, FP, FP]
     lib.nep_test_cutoff.argtypes = [F, F, FP, FP]
     lib.nep_test_cheb.argtypes = [F, FP, FP]
+    lib.nep_test_basis_d.argtypes = [C.c_double, C.c_double, DP, DP]
     lib.nep_test_sph.argtypes = [F, F, F, FP]
     lib.nep_test_sph_grad.argtypes = [F, F, F, FP, FP]
     lib.nep_test_zbl.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, DP, DP]
@@ -56,6 +57,17 @@ def test_cutoff_and_derivative(L):
             assert abs(dfc.value + 0.5 * math.pi / rc * math.sin(math.pi * r / rc)) < 3e-7
         L.nep_test_cutoff(rc * (1 - 1e-6), rc, C.byref(fc), C.byref(dfc))
         assert abs(fc.value) < 1e-7
+
+
+def test_double_precision_basis(L):
+    fc = C.c_double()
+    T = np.zeros(9)
+    for rc in (4.0, 6.0):
+        for r in np.linspace(0.05, rc - 1e-9, 300):
+            L.nep_test_basis_d(r, rc, C.byref(fc), T.ctypes.data_as(DP))
+            assert abs(fc.value - 0.5 * (1 + math.cos(math.pi * r / rc))) < 1e-13
+            x = 2 * (r / rc - 1) ** 2 - 1
+            assert np.allclose(T, np.cos(np.arange(9) * math.acos(max(-1.0, min(1.0, x)))), atol=1e-12)
 
 
 def test_chebyshev_values_and_derivatives(L):

@@ -119,3 +119,78 @@ def test_verlet_ten_steps_tiny():
     assert np.abs(vel - vel_ref).max() < 10 * da * 10.0
     e_all, _ = force_errors(out.forces().cpu().numpy().astype(np.float64), F_ref)
     assert e_all <= 1e-4
+
+
+def _sampled(m, s, sysd, out, n_sample=256, extra=()):
+    import torch
+    torch.cuda.synchronize()
+    pos = sysd.positions().cpu().numpy()
+    F = out.forces().cpu().numpy().astype(np.float64)
+    U = out.energy_atom.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([rng.choice(s.n_atoms, size=n_sample, replace=False),
+                                   np.asarray(extra, dtype=np.int64)]))
+    ref = oracle.efv_cell(m, pos, s.h[0], targets=idx, virial=False)
+    ferr = np.linalg.norm(F[idx] - ref["forces"]) / np.linalg.norm(ref["forces"])
+    uerr = np.abs(U[idx] - ref["energy_atom"]).max()
+    return ferr, uerr, ref
+
+
+def test_mid_sampled_after_md():
+    # 128,000-atom bcc W, 300 K, 50 steps at 1 fs, then sampled atoms vs FP64
+    import torch
+    import paper_2305_08140_amd as nep
+    m = model()
+    s = nep_synth.mid()
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(m, s.n_atoms, 1)
+    out = nep.EFV(s.n_atoms, 1)
+    st = ctx.nep_step_verlet(sysd, 50, out, dt_max=1.0)
+    ferr, uerr, _ = _sampled(m, s, sysd, out)
+    print(f"[mid] sampled force rel err {ferr:.3e}, site energy max err {uerr:.2e}, rebuilds {st['n_rebuilds']}",
+          flush=True)
+    assert ferr <= F_REL_TOL
+    assert uerr <= 1e-5
+
+
+def test_large_sampled_after_md():
+    # the 8,192,000-atom cascade start in the benchmark's launch configuration
+    import torch
+    import paper_2305_08140_amd as nep
+    m = model()
+    s = nep_synth.large()
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(m, s.n_atoms, 1, max_neigh_ang=48, max_neigh_rad=96, skin=1.0)
+    out = nep.EFV(s.n_atoms, 1)
+    st = ctx.nep_step_verlet(sysd, 200, out, dt_max=1.0, max_disp=0.015)
+    pka = s.meta["pka"]
+    ferr, uerr, ref = _sampled(m, s, sysd, out, extra=[pka])
+    print(f"[large] sampled force rel err {ferr:.3e}, site energy max err {uerr:.2e}, "
+          f"time {st['time']:.3f} fs, rebuilds {st['n_rebuilds']}", flush=True)
+    assert ferr <= F_REL_TOL
+    assert uerr <= 1e-5
+    # properties that hold at any size: net force ~ 0, virial symmetric
+    F = out.forces().double()
+    assert float(F.sum(0).abs().max()) <= 1e-6 * float(F.abs().sum())
+    W = out.virial.cpu().numpy().reshape(3, 3)
+    assert np.abs(W - W.T).max() <= 1e-5 * np.abs(W).max()
+
+
+def test_verlet_trajectory_thermal():
+    # 16,000-atom bcc W at 300 K: 10 steps against the oracle's trajectory
+    import torch
+    import paper_2305_08140_amd as nep
+    m = model()
+    s = nep_synth.mid(n_cells=20)
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(m, s.n_atoms, 1)
+    out = nep.EFV(s.n_atoms, 1)
+    ctx.nep_step_verlet(sysd, 10, out, dt_max=1.0)
+    torch.cuda.synchronize()
+    pos_ref, vel_ref, F_ref, log = oracle.velocity_verlet(m, s.pos, s.vel, s.h[0], s.mass, 10, dt_max=1.0,
+                                                          record=True)
+    assert np.abs(sysd.positions().cpu().numpy() - pos_ref).max() < 1e-7
+    assert np.abs(sysd.velocities().cpu().numpy() - vel_ref).max() < 1e-8
+    e_all, _ = force_errors(out.forces().cpu().numpy().astype(np.float64), F_ref)
+    assert e_all <= F_REL_TOL
+    assert abs(out.energy.item() - log[-1]["epot"]) / s.n_atoms <= E_ATOM_TOL
