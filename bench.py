@@ -96,6 +96,68 @@ def cpu_baseline(model, s, seconds_target=15.0):
                       f"{dt:.1f} s on {n_thr} threads"}
 
 
+def summarize_rocprof(kt_dir, fetch_dir, write_dir, n_atoms, command, out_dir):
+    """Write profiles/ summaries from rocprofv3 output: kernel-trace statistics
+    and the HBM bytes per launch from FETCH_SIZE / WRITE_SIZE, scaled by what
+    the counters read for the plain 1 GiB device copy (__amd_rocclr_copyBuffer)."""
+    import csv
+    import glob
+
+    def one(d, pat):
+        f = glob.glob(os.path.join(d, "**", pat), recursive=True)
+        if not f:
+            raise FileNotFoundError(os.path.join(d, pat))
+        return f[0]
+
+    rows = list(csv.DictReader(open(one(kt_dir, "*kernel_stats.csv"))))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# Kernel time, NEP-ZBL MD of %d-atom bcc W" % n_atoms, "", "Command:", "",
+             "    " + command["kt"], "", "| kernel | calls | avg ms | total % |", "|---|---|---|---|"]
+    for r in rows[:16]:
+        name = r["Name"].split("(")[0]
+        lines.append("| %s | %s | %.3f | %.1f |" % (name, r["Calls"], float(r["AverageNs"]) / 1e6,
+                                                    float(r["Percentage"])))
+    with open(os.path.join(out_dir, "nep_md_%d_kernel_stats.md" % n_atoms), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    def counters(d, cname):
+        acc = {}
+        for r in csv.DictReader(open(one(d, "*counter_collection.csv"))):
+            if r["Counter_Name"] != cname:
+                continue
+            acc.setdefault(r["Kernel_Name"].split("(")[0], []).append(float(r["Counter_Value"]))
+        return acc
+    fe = counters(fetch_dir, "FETCH_SIZE")
+    wr = counters(write_dir, "WRITE_SIZE")
+    gib_kib = 1 << 20
+    f_fac = gib_kib / max(fe["__amd_rocclr_copyBuffer"])       # 1 GiB read by the calibration copy
+    w_fac = gib_kib / max(wr["__amd_rocclr_copyBuffer"])       # 1 GiB written
+    out = {"source_hash": _kernel_source_hash(), "n_atoms": n_atoms, "fetch_factor": f_fac,
+           "write_factor": w_fac, "kernels": {}, "commands": command}
+    lines = ["# HBM traffic per launch, NEP-ZBL MD of %d-atom bcc W" % n_atoms, "",
+             "Commands (FETCH_SIZE and WRITE_SIZE in separate runs):", "",
+             "    " + command["fetch"], "    " + command["write"], "",
+             "Calibration: a plain 1 GiB device copy reads FETCH_SIZE x %.3f and WRITE_SIZE x %.3f of "
+             "its true bytes; all values below are scaled by those factors." % (1 / f_fac, 1 / w_fac), "",
+             "| kernel | launches | GB read | GB written | bytes/atom |", "|---|---|---|---|---|"]
+    for k in ("nep::k_descriptor", "nep::k_force", "nep::k_sort_positions", "nep::k_kick_drift",
+              "nep::k_kick", "nep::k_reduce_chunks", "nep::k_build_lists", "nep::k_build_reverse"):
+        if k not in fe or k not in wr:
+            continue
+        rd = float(np.median(fe[k])) * 1024 * f_fac
+        wb = float(np.median(wr[k])) * 1024 * w_fac
+        if k in ("nep::k_build_lists", "nep::k_build_reverse"):
+            rd = max(fe[k]) * 1024 * f_fac
+            wb = max(wr[k]) * 1024 * w_fac
+        out["kernels"][k.split("::")[1]] = {"read_bytes": rd, "write_bytes": wb, "bytes_per_launch": rd + wb}
+        lines.append("| %s | %d | %.2f | %.2f | %.0f |" % (k.split("::")[1], len(fe[k]), rd / 1e9, wb / 1e9,
+                                                           (rd + wb) / n_atoms))
+    with open(os.path.join(out_dir, "nep_md_%d_hbm_counters.md" % n_atoms), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(os.path.join(out_dir, "hbm_traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,7 +166,23 @@ def main():
     ap.add_argument("--cells", type=int, default=160, help="conventional cells per edge")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-reps", type=int, default=5)
+    ap.add_argument("--summarize-rocprof", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/ summaries from rocprofv3 output directories and exit")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.summarize_rocprof:
+        n = 2 * args.cells ** 3
+        cmd = {"kt": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_kt -o kt --output-format csv -- "
+                     "python3 bench.py --steps 20 --warmup 3 --no-cpu-baseline",
+               "fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o f --output-format csv -- "
+                        "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-calibration-mib 1024 "
+                        "--timing-reps 1",
+               "write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o w --output-format csv -- "
+                        "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-calibration-mib 1024 "
+                        "--timing-reps 1"}
+        summarize_rocprof(*args.summarize_rocprof, n, cmd, os.path.join(ROOT, "profiles"))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU (the NEP-ZBL evaluation is not sharded "
               "across GPUs here); run with --gpus 1", file=sys.stderr)
@@ -113,6 +191,15 @@ def main():
     import torch
     import nep_synth
     import paper_2305_08140_amd as nep
+
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     model = nep_synth.random_model()
     s = nep_synth.large(n_cells=args.cells)
