@@ -12,10 +12,10 @@
 
 namespace nep {
 // kernels (nep_kernels.hip)
-__global__ void k_descriptor(PairConsts, const double *, const double *, const double *, const int32_t *,
+__global__ void k_descriptor(PairConsts, const double4 *, const int32_t *,
                              const CellGeom *, const int32_t *, const int32_t *, const uint32_t *,
                              const float *, float *, float4 *, float4 *, float *, double *, int32_t *, int);
-__global__ void k_force(PairConsts, const double *, const double *, const double *, const int32_t *,
+__global__ void k_force(PairConsts, const double4 *, const int32_t *,
                         const CellGeom *, const int32_t *, const int32_t *, const uint32_t *, const uint8_t *,
                         const float *, const float4 *, const float4 *, const int32_t *, float *, float *,
                         float *, float *, int32_t *, int);
@@ -23,26 +23,25 @@ __global__ void k_reduce_chunks(const int32_t *, const int32_t *, const double *
                                 const int32_t *);
 __global__ void k_reduce_cells(int, const int32_t *, const double *, double *, double *, const int32_t *);
 __global__ void k_energy_atom_out(int, const int32_t *, const double *, float *);
-__global__ void k_count_inside(PairConsts, const double *, const double *, const double *, const int32_t *,
+__global__ void k_count_inside(PairConsts, const double4 *, const int32_t *,
                                const CellGeom *, const int32_t *, const int32_t *, const uint32_t *,
                                unsigned long long *);
 // kernels (nep_build.hip)
 __global__ void k_fill_i32(int, int32_t *, int32_t, const int32_t *);
 __global__ void k_bin_assign(int, const double *, const double *, const double *, const int32_t *,
-                             const CellGeom *, int32_t *, int32_t *, int32_t *, double *, int32_t *,
-                             const int32_t *);
+                             const CellGeom *, int32_t *, int32_t *, int32_t *, double *, const int32_t *,
+                             int32_t *, const int32_t *);
 __global__ void k_scan_blocks(int, const int32_t *, int32_t *, int32_t *, const int32_t *);
 __global__ void k_scan_sums(int, int32_t *, const int32_t *);
 __global__ void k_scan_add(int, int32_t *, const int32_t *, const int32_t *);
 __global__ void k_bin_scatter(int, const int32_t *, const int32_t *, int32_t *, int32_t *, const int32_t *);
 __global__ void k_bin_rank(int, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
-                           const CellGeom *, int32_t *, int32_t *, const int32_t *);
+                           const CellGeom *, int32_t *, int32_t *, const int32_t *, const int32_t *);
 __global__ void k_sort_positions(int, const int32_t *, const double *, const double *, const double *,
-                                 const int32_t *, const int32_t *, const CellGeom *, double *, double *,
-                                 double *, int32_t *);
-__global__ void k_build_lists(PairConsts, double, double, double, double, const double *, const double *,
-                              const double *, const int32_t *, const CellGeom *, const int32_t *,
-                              const int32_t *, int32_t *, int32_t *, uint32_t *, int32_t *, const int32_t *);
+                                 const int32_t *, const int32_t *, const CellGeom *, double4 *, int32_t *);
+__global__ void k_build_lists(PairConsts, double, double, double, double, const double4 *, const int32_t *,
+                              const CellGeom *, const int32_t *, const int32_t *, const int32_t *, int32_t *,
+                              int32_t *, uint32_t *, int32_t *, const int32_t *);
 __global__ void k_build_reverse(PairConsts, const int32_t *, const CellGeom *, const int32_t *,
                                 const uint32_t *, uint8_t *, int32_t *, const int32_t *);
 __global__ void k_kick_drift(int, double *, double *, double *, double *, double *, double *, const float *,
@@ -74,7 +73,7 @@ struct nep_ctx {
     int device = 0;
     float *params = nullptr;
     // per-atom storage (capacity cfg.max_atoms)
-    double *xs = nullptr;        // [3][N] sorted wrapped positions
+    double4 *xp = nullptr;       // [N] sorted wrapped positions (x, y, z, 0)
     double *xref = nullptr;      // [3][N] caller-order positions at the last build
     int32_t *perm = nullptr, *bin_of = nullptr, *wrap = nullptr, *cell_of = nullptr, *tmp = nullptr,
             *bin_sorted = nullptr;
@@ -93,6 +92,7 @@ struct nep_ctx {
     int n_chunks = 0, chunk_cap = 0;
     // bins
     int32_t *bin_count = nullptr, *bin_start = nullptr, *bin_fill = nullptr, *scan_sums = nullptr;
+    int32_t *bin_rank = nullptr, *bin_lin = nullptr;   // Morton order of the bins of every cell
     int64_t bin_cap = 0;
     int n_bins = 0;
     // status and md state
@@ -116,6 +116,8 @@ struct nep_ctx {
 
 static int grid_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 static int xcd_grid(int tiles) { return 8 * ((tiles + 7) / 8); }
+// grid of the streaming (grid-stride) kernels: enough blocks to fill the chip
+static int stream_grid(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 2048); }
 
 static void inv3(const double *h, double *hi)
 {
@@ -150,7 +152,7 @@ void nep_destroy(nep_ctx *c)
     if (!c) return;
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    void *bufs[] = {c->params, c->xs, c->xref, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
+    void *bufs[] = {c->params, c->xp, c->xref, c->bin_rank, c->bin_lin, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
                     c->bin_sorted, c->ncnt, c->nl_ang, c->nl_rad, c->adj_r, c->pair_grad, c->f_own, c->rev,
                     c->w_atom,
                     c->e_atom, c->cells, c->cell_start_d, c->chunk_begin, c->chunk_end, c->cell_chunk,
@@ -189,7 +191,7 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
         if (ok && hipMalloc(p, bytes > 0 ? bytes : 16) != hipSuccess) ok = false;
     };
     A((void **)&c->params, P_SIZE * sizeof(float));
-    A((void **)&c->xs, 3 * N * sizeof(double));
+    A((void **)&c->xp, N * sizeof(double4));
     A((void **)&c->xref, 3 * N * sizeof(double));
     A((void **)&c->perm, N * 4);
     A((void **)&c->bin_of, N * 4);
@@ -345,17 +347,51 @@ static int setup_system(nep_ctx *c, const nep_system *s, hipStream_t st)
 
     // bins
     if (nbins + 1 > c->bin_cap) {
-        if (c->bin_count) { hipFree(c->bin_count); hipFree(c->bin_start); hipFree(c->bin_fill); hipFree(c->scan_sums); }
-        c->bin_count = c->bin_start = c->bin_fill = c->scan_sums = nullptr;
+        int32_t *old_bufs[] = {c->bin_count, c->bin_start, c->bin_fill, c->scan_sums, c->bin_rank, c->bin_lin};
+        for (int32_t *p : old_bufs)
+            if (p) (void)hipFree(p);
+        c->bin_count = c->bin_start = c->bin_fill = c->scan_sums = c->bin_rank = c->bin_lin = nullptr;
         c->bin_cap = 0;
         const int64_t cap = nbins + 1;
         HIP_TRY(hipMalloc(&c->bin_count, cap * 4));
         HIP_TRY(hipMalloc(&c->bin_start, cap * 4));
         HIP_TRY(hipMalloc(&c->bin_fill, cap * 4));
         HIP_TRY(hipMalloc(&c->scan_sums, ((cap + 2047) / 2048 + 1) * 4));
+        HIP_TRY(hipMalloc(&c->bin_rank, cap * 4));
+        HIP_TRY(hipMalloc(&c->bin_lin, cap * 4));
         c->bin_cap = cap;
     }
     c->n_bins = (int)nbins;
+    // Morton order of every cell's bins: rank[lin] and its inverse lin[rank]
+    std::vector<int32_t> rank(nbins), lin_of(nbins);
+    {
+        auto spread = [](uint64_t v) {   // interleave the low 21 bits with two zero bits
+            v &= 0x1fffff;
+            v = (v | v << 32) & 0x1f00000000ffffULL;
+            v = (v | v << 16) & 0x1f0000ff0000ffULL;
+            v = (v | v << 8) & 0x100f00f00f00f00fULL;
+            v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+            v = (v | v << 2) & 0x1249249249249249ULL;
+            return v;
+        };
+        std::vector<std::pair<uint64_t, int32_t>> key;
+        for (int k = 0; k < nc; ++k) {
+            const CellGeom &g = c->geom[k];
+            const int cb = g.nb[0] * g.nb[1] * g.nb[2];
+            key.resize(cb);
+            for (int l = 0; l < cb; ++l) {
+                const int b0 = l % g.nb[0], b1 = (l / g.nb[0]) % g.nb[1], b2 = l / (g.nb[0] * g.nb[1]);
+                key[l] = {spread(b0) | spread(b1) << 1 | spread(b2) << 2, l};
+            }
+            std::sort(key.begin(), key.end());
+            for (int r = 0; r < cb; ++r) {
+                rank[g.bin_offset + key[r].second] = r;
+                lin_of[g.bin_offset + r] = key[r].second;
+            }
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(c->bin_rank, rank.data(), nbins * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c->bin_lin, lin_of.data(), nbins * 4, hipMemcpyHostToDevice, st));
 
     // reduction chunks: contiguous sorted-atom ranges that never span two cells
     const int CH = 4096;
@@ -408,24 +444,22 @@ static int launch_build(nep_ctx *c, const nep_system *s, hipStream_t st, const i
     k_fill_i32<<<grid_for(nb1, 256), 256, 0, st>>>(nb1, c->bin_count, 0, flag);
     k_fill_i32<<<grid_for(nb1, 256), 256, 0, st>>>(nb1, c->bin_fill, 0, flag);
     k_bin_assign<<<grid_for(n, 256), 256, 0, st>>>(n, s->x, s->y, s->z, c->cell_of, c->cells, c->bin_of,
-                                                   c->wrap, c->bin_count, c->xref, c->status, flag);
+                                                   c->wrap, c->bin_count, c->xref, c->bin_rank, c->status, flag);
     const int nblk = grid_for(nb1, 2048);
     k_scan_blocks<<<nblk, 256, 0, st>>>(nb1, c->bin_count, c->bin_start, c->scan_sums, flag);
     k_scan_sums<<<1, 256, 0, st>>>(nblk, c->scan_sums, flag);
     k_scan_add<<<grid_for(nb1, 256), 256, 0, st>>>(nb1, c->bin_start, c->scan_sums, flag);
     k_bin_scatter<<<grid_for(n, 256), 256, 0, st>>>(n, c->bin_of, c->bin_start, c->bin_fill, c->tmp, flag);
     k_bin_rank<<<grid_for(n, 256), 256, 0, st>>>(n, c->bin_of, c->bin_start, c->tmp, c->cell_of, c->cells,
-                                                 c->perm, c->bin_sorted, flag);
+                                                 c->perm, c->bin_sorted, c->bin_lin, flag);
     // sorted positions are needed by the list build; unconditional is fine
     // (every evaluation refreshes them anyway)
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                       c->cells, c->xs, c->xs + c->cfg.max_atoms,
-                                                       c->xs + 2 * c->cfg.max_atoms, c->status);
+                                                       c->cells, c->xp, c->status);
     const double lA = c->hp.rc_ang + c->cfg.skin, lR = c->hp.rc_rad + c->cfg.skin;
     k_build_lists<<<grid_for(n, 256), 256, 0, st>>>(
-        c->pc, lA * lA, lR * lR, c->hp.rc_ang * c->hp.rc_ang, c->hp.rc_rad * c->hp.rc_rad, c->xs,
-        c->xs + c->cfg.max_atoms, c->xs + 2 * c->cfg.max_atoms, c->cell_of, c->cells, c->bin_sorted,
-        c->bin_start, c->nl_ang, c->nl_rad, c->ncnt, c->status, flag);
+        c->pc, lA * lA, lR * lR, c->hp.rc_ang * c->hp.rc_ang, c->hp.rc_rad * c->hp.rc_rad, c->xp, c->cell_of,
+        c->cells, c->bin_sorted, c->bin_start, c->bin_rank, c->nl_ang, c->nl_rad, c->ncnt, c->status, flag);
     k_build_reverse<<<grid_for(n, 256), 256, 0, st>>>(c->pc, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->rev,
                                                       c->status, flag);
     HIP_TRY(hipGetLastError());
@@ -454,20 +488,20 @@ int nep_build_neighbors(nep_ctx *c, const nep_system *s, void *stream)
 static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t st, bool refresh_positions)
 {
     const int n = (int)s->n_atoms;
-    double *xs = c->xs, *ys = c->xs + c->cfg.max_atoms, *zs = c->xs + 2 * c->cfg.max_atoms;
+    double4 *xp = c->xp;
     if (refresh_positions)
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                           c->cells, xs, ys, zs, c->status);
+                                                           c->cells, xp, c->status);
     const int tiles = grid_for(n, 256);
-    k_descriptor<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xs, ys, zs, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
+    k_descriptor<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
                                                   c->ncnt, c->params, c->adj_r, c->pair_grad, c->f_own, c->w_atom,
                                                   c->e_atom, c->status, tiles);
-    k_force<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xs, ys, zs, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
+    k_force<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
                                              c->ncnt, c->rev, c->adj_r, c->pair_grad, c->f_own, c->perm, o->fx, o->fy,
                                              o->fz, c->w_atom, c->status, tiles);
     k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom, c->part,
                                                  c->status);
-    k_reduce_cells<<<grid_for(c->built_cells, 64), 64, 0, st>>>(c->built_cells, c->cell_chunk, c->part,
+    k_reduce_cells<<<c->built_cells, 256, 0, st>>>(c->built_cells, c->cell_chunk, c->part,
                                                                 o->energy, o->virial, c->status);
     if (o->energy_atom)
         k_energy_atom_out<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, c->e_atom, o->energy_atom);
@@ -500,7 +534,7 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
     if (!same_system(c, s)) return NEP_E_STATE;
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)s->n_atoms;
-    double *xs = c->xs, *ys = c->xs + c->cfg.max_atoms, *zs = c->xs + 2 * c->cfg.max_atoms;
+    double4 *xp = c->xp;
     const int tiles = grid_for(n, 256);
     hipEvent_t ev[5];
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
@@ -508,19 +542,19 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
     for (int r = 0; r < reps; ++r) {
         HIP_TRY(hipEventRecord(ev[0], st));
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                           c->cells, xs, ys, zs, c->status);
+                                                           c->cells, xp, c->status);
         HIP_TRY(hipEventRecord(ev[1], st));
-        k_descriptor<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xs, ys, zs, c->cell_of, c->cells, c->nl_ang,
+        k_descriptor<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xp, c->cell_of, c->cells, c->nl_ang,
                                                       c->nl_rad, c->ncnt, c->params, c->adj_r, c->pair_grad,
                                                       c->f_own, c->w_atom, c->e_atom, c->status, tiles);
         HIP_TRY(hipEventRecord(ev[2], st));
-        k_force<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xs, ys, zs, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
+        k_force<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
                                                  c->ncnt, c->rev, c->adj_r, c->pair_grad, c->f_own, c->perm, o->fx,
                                                  o->fy, o->fz, c->w_atom, c->status, tiles);
         HIP_TRY(hipEventRecord(ev[3], st));
         k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom,
                                                      c->part, c->status);
-        k_reduce_cells<<<grid_for(c->built_cells, 64), 64, 0, st>>>(c->built_cells, c->cell_chunk, c->part,
+        k_reduce_cells<<<c->built_cells, 256, 0, st>>>(c->built_cells, c->cell_chunk, c->part,
                                                                     o->energy, o->virial, c->status);
         HIP_TRY(hipEventRecord(ev[4], st));
         HIP_TRY(hipGetLastError());
@@ -566,8 +600,7 @@ int nep_mean_neighbors(nep_ctx *c, void *stream, double *mean_rad, double *mean_
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(hipMemsetAsync(c->counts, 0, 16, st));
     const int n = c->pc.n;
-    k_count_inside<<<grid_for(n, 256), 256, 0, st>>>(c->pc, c->xs, c->xs + c->cfg.max_atoms,
-                                                     c->xs + 2 * c->cfg.max_atoms, c->cell_of, c->cells,
+    k_count_inside<<<grid_for(n, 256), 256, 0, st>>>(c->pc, c->xp, c->cell_of, c->cells,
                                                      c->nl_ang, c->nl_rad, c->ncnt, c->counts);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(c->h_counts, c->counts, 16, hipMemcpyDeviceToHost, st));
@@ -603,7 +636,7 @@ int nep_step_verlet(nep_ctx *c, nep_system *s, const nep_md *md, int32_t n_steps
         c->built = true;
         fresh = true;
     } else {
-        k_disp<<<grid_for(n, 256), 256, 0, st>>>(n, s->x, s->y, s->z, c->xref, c->md);
+        k_disp<<<stream_grid(n), 256, 0, st>>>(n, s->x, s->y, s->z, c->xref, c->md);
         k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag);
         if ((rc = launch_build(c, s, st, c->flag))) return rc;
     }
@@ -612,17 +645,17 @@ int nep_step_verlet(nep_ctx *c, nep_system *s, const nep_md *md, int32_t n_steps
     }
     (void)fresh;
     // first step length from the initial velocities
-    k_vmax<<<grid_for(n, 256), 256, 0, st>>>(n, s->vx, s->vy, s->vz, c->md);
+    k_vmax<<<stream_grid(n), 256, 0, st>>>(n, s->vx, s->vy, s->vz, c->md);
     k_dt_update<<<1, 64, 0, st>>>(md->dt_max, md->max_disp, md->dt_min, c->md, c->status, 0);
     // the rebuild counter counts rebuilds inside the chunk only
     HIP_TRY(hipMemsetAsync(c->md + MD_NREB, 0, 8, st));
     for (int k = 0; k < n_steps; ++k) {
-        k_kick_drift<<<grid_for(n, 256), 256, 0, st>>>(n, s->x, s->y, s->z, s->vx, s->vy, s->vz, o->fx, o->fy,
+        k_kick_drift<<<stream_grid(n), 256, 0, st>>>(n, s->x, s->y, s->z, s->vx, s->vy, s->vz, o->fx, o->fy,
                                                        o->fz, acc, c->xref, c->md, c->status);
         k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag);
         if ((rc = launch_build(c, s, st, c->flag))) return rc;
         if ((rc = launch_efv(c, s, o, st, true))) return rc;
-        k_kick<<<grid_for(n, 256), 256, 0, st>>>(n, s->vx, s->vy, s->vz, o->fx, o->fy, o->fz, acc, c->md,
+        k_kick<<<stream_grid(n), 256, 0, st>>>(n, s->vx, s->vy, s->vz, o->fx, o->fy, o->fz, acc, c->md,
                                                  c->status);
         k_dt_update<<<1, 64, 0, st>>>(md->dt_max, md->max_disp, md->dt_min, c->md, c->status, 1);
     }

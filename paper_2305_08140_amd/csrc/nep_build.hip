@@ -44,12 +44,15 @@ __global__ void k_fill_i32(int n, int32_t *__restrict__ a, int32_t v, const int3
 }
 
 // Per atom (caller order): bin, wrap count, bin histogram, reference position.
+// Bins are numbered along a Morton curve within each cell (bin_rank maps the
+// x-fastest linear bin index to that order), so that a run of consecutive
+// sorted atoms occupies a compact 3D region and its neighbour halo fits L2.
 __global__ void k_bin_assign(int n, const double *__restrict__ x, const double *__restrict__ y,
                              const double *__restrict__ z, const int32_t *__restrict__ cell_of,
                              const CellGeom *__restrict__ cells, int32_t *__restrict__ bin_of,
                              int32_t *__restrict__ wrap, int32_t *__restrict__ bin_count,
-                             double *__restrict__ xref, int32_t *__restrict__ status,
-                             const int32_t *__restrict__ flag)
+                             double *__restrict__ xref, const int32_t *__restrict__ bin_rank,
+                             int32_t *__restrict__ status, const int32_t *__restrict__ flag)
 {
     if (flag && *flag == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -77,7 +80,8 @@ __global__ void k_bin_assign(int n, const double *__restrict__ x, const double *
         b[a] = bb;
         if (w[a] < -511 || w[a] > 511) latch_error(status, -1);
     }
-    const int gb = cg.bin_offset + (b[2] * cg.nb[1] + b[1]) * cg.nb[0] + b[0];
+    const int lin = (b[2] * cg.nb[1] + b[1]) * cg.nb[0] + b[0];
+    const int gb = cg.bin_offset + bin_rank[cg.bin_offset + lin];
     bin_of[i] = gb;
     wrap[i] = pack_wrap(w[0], w[1], w[2]);
     atomicAdd(bin_count + gb, 1);
@@ -172,7 +176,7 @@ __global__ void k_bin_rank(int n, const int32_t *__restrict__ bin_of,
                            const int32_t *__restrict__ bin_start, const int32_t *__restrict__ tmp,
                            const int32_t *__restrict__ cell_of, const CellGeom *__restrict__ cells,
                            int32_t *__restrict__ perm, int32_t *__restrict__ bin_sorted,
-                           const int32_t *__restrict__ flag)
+                           const int32_t *__restrict__ bin_lin, const int32_t *__restrict__ flag)
 {
     if (flag && *flag == 0) return;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -183,7 +187,7 @@ __global__ void k_bin_rank(int n, const int32_t *__restrict__ bin_of,
     int rank = 0;
     for (int q = b0; q < b1; ++q) rank += tmp[q] < i;
     perm[b0 + rank] = i;
-    bin_sorted[b0 + rank] = b - cells[cell_of[i]].bin_offset;
+    bin_sorted[b0 + rank] = bin_lin[b];   // x-fastest linear index of the bin within its cell
 }
 
 // Wrapped positions in sorted order: xs[t] = x[perm[t]] - w . h.  Runs at
@@ -192,8 +196,7 @@ __global__ void k_sort_positions(int n, const int32_t *__restrict__ perm,
                                  const double *__restrict__ x, const double *__restrict__ y,
                                  const double *__restrict__ z, const int32_t *__restrict__ wrap,
                                  const int32_t *__restrict__ cell_of,
-                                 const CellGeom *__restrict__ cells, double *__restrict__ xs,
-                                 double *__restrict__ ys, double *__restrict__ zs,
+                                 const CellGeom *__restrict__ cells, double4 *__restrict__ xp,
                                  int32_t *__restrict__ status)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -204,17 +207,16 @@ __global__ void k_sort_positions(int n, const int32_t *__restrict__ perm,
     const double *h = cells[cell_of[t]].h;
     const double px = x[i], py = y[i], pz = z[i];
     if (!isfinite(px) || !isfinite(py) || !isfinite(pz)) latch_error(status, -5);
-    xs[t] = px - (w0 * h[0] + w1 * h[3] + w2 * h[6]);
-    ys[t] = py - (w0 * h[1] + w1 * h[4] + w2 * h[7]);
-    zs[t] = pz - (w0 * h[2] + w1 * h[5] + w2 * h[8]);
+    xp[t] = make_double4(px - (w0 * h[0] + w1 * h[3] + w2 * h[6]), py - (w0 * h[1] + w1 * h[4] + w2 * h[7]),
+                         pz - (w0 * h[2] + w1 * h[5] + w2 * h[8]), 0.0);
 }
 
 // Neighbour lists of every sorted atom (see the file comment for the layout).
 __global__ __launch_bounds__(256) void k_build_lists(
-    PairConsts pc, double lA2, double lR2, double cA2, double cR2, const double *__restrict__ xs,
-    const double *__restrict__ ys, const double *__restrict__ zs,
+    PairConsts pc, double lA2, double lR2, double cA2, double cR2, const double4 *__restrict__ xp,
     const int32_t *__restrict__ cell_of, const CellGeom *__restrict__ cells,
     const int32_t *__restrict__ bin_sorted, const int32_t *__restrict__ bin_start,
+    const int32_t *__restrict__ bin_rank,
     int32_t *__restrict__ nl_ang, int32_t *__restrict__ nl_rad, uint32_t *__restrict__ ncnt,
     int32_t *__restrict__ status, const int32_t *__restrict__ flag)
 {
@@ -222,7 +224,8 @@ __global__ __launch_bounds__(256) void k_build_lists(
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= pc.n) return;
     const CellGeom &cg = cells[cell_of[t]];
-    const double xi = xs[t], yi = ys[t], zi = zs[t];
+    const double4 pi = xp[t];
+    const double xi = pi.x, yi = pi.y, zi = pi.z;
     const int lb = bin_sorted[t];
     const int bc[3] = {lb % cg.nb[0], (lb / cg.nb[0]) % cg.nb[1], lb / (cg.nb[0] * cg.nb[1])};
     int lo[3], hi[3];
@@ -258,11 +261,13 @@ __global__ __launch_bounds__(256) void k_build_lists(
                 const bool self_image = (m[0] | m[1] | m[2]) == 0;
                 const uint32_t code = (uint32_t)(m[0] + pc.ioff) | ((uint32_t)(m[1] + pc.ioff) << pc.ibits)
                                       | ((uint32_t)(m[2] + pc.ioff) << (2 * pc.ibits));
-                const int gb = cg.bin_offset + (bb[2] * cg.nb[1] + bb[1]) * cg.nb[0] + bb[0];
+                const int gb = cg.bin_offset +
+                               bin_rank[cg.bin_offset + (bb[2] * cg.nb[1] + bb[1]) * cg.nb[0] + bb[0]];
                 for (int u = bin_start[gb]; u < bin_start[gb + 1]; ++u) {
                     if (u == t && self_image) continue;
                     // (x_u - x_i) + shift: exactly the negative of the vector seen from u
-                    const double dx = (xs[u] - xi) + sx, dy = (ys[u] - yi) + sy, dz = (zs[u] - zi) + sz;
+                    const double4 pu = xp[u];
+                    const double dx = (pu.x - xi) + sx, dy = (pu.y - yi) + sy, dz = (pu.z - zi) + sz;
                     const double r2 = dx * dx + dy * dy + dz * dz;
                     if (r2 >= lR2) continue;
                     const uint32_t jl = (uint32_t)(u - cg.atom_start);
@@ -343,64 +348,76 @@ __global__ __launch_bounds__(256) void k_build_reverse(PairConsts pc, const int3
 
 // ------------------------------------------------------------------ velocity Verlet
 
-__device__ inline void wave_max_atomic(double v, double *dst)
+// Block maximum of a non-negative double, one atomicMax per block on its
+// bit pattern (non-negative doubles order like their unsigned bit patterns).
+__device__ inline void block_max_atomic(double v, double *dst)
 {
+    __shared__ double sh[4];
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-    if ((threadIdx.x & 63) == 0)
-        atomicMax(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)__double_as_longlong(v));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = sh[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, sh[w]);
+        atomicMax(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)__double_as_longlong(m));
+    }
 }
 
-// v += dt/2 F/m ; x += dt v ; track the largest displacement since the last build.
-__global__ void k_kick_drift(int n, double *__restrict__ x, double *__restrict__ y,
-                             double *__restrict__ z, double *__restrict__ vx,
-                             double *__restrict__ vy, double *__restrict__ vz,
-                             const float *__restrict__ fx, const float *__restrict__ fy,
-                             const float *__restrict__ fz, double acc_per_mass,
-                             const double *__restrict__ xref, double *__restrict__ md,
-                             int32_t *__restrict__ status)
+// v += dt/2 F/m ; x += dt v ; track the largest displacement since the last
+// build.  Grid-stride loop over atoms (blocks of 256 threads).
+__global__ __launch_bounds__(256) void k_kick_drift(int n, double *__restrict__ x, double *__restrict__ y,
+                                                    double *__restrict__ z, double *__restrict__ vx,
+                                                    double *__restrict__ vy, double *__restrict__ vz,
+                                                    const float *__restrict__ fx, const float *__restrict__ fy,
+                                                    const float *__restrict__ fz, double acc_per_mass,
+                                                    const double *__restrict__ xref, double *__restrict__ md,
+                                                    int32_t *__restrict__ status)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double d2 = 0.0;
-    if (i < n && status[ST_ERR] == 0) {
+    double dmax = 0.0;
+    if (status[ST_ERR] == 0) {
         const double dt = md[MD_DT];
         const double c = 0.5 * dt * acc_per_mass;
-        double v0 = vx[i] + c * fx[i], v1 = vy[i] + c * fy[i], v2 = vz[i] + c * fz[i];
-        vx[i] = v0; vy[i] = v1; vz[i] = v2;
-        const double p0 = x[i] + dt * v0, p1 = y[i] + dt * v1, p2 = z[i] + dt * v2;
-        x[i] = p0; y[i] = p1; z[i] = p2;
-        const double e0 = p0 - xref[i], e1 = p1 - xref[(size_t)n + i], e2 = p2 - xref[2 * (size_t)n + i];
-        d2 = e0 * e0 + e1 * e1 + e2 * e2;
-        if (!isfinite(d2)) { latch_error(status, -5); d2 = 0.0; }
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            const double v0 = vx[i] + c * fx[i], v1 = vy[i] + c * fy[i], v2 = vz[i] + c * fz[i];
+            vx[i] = v0; vy[i] = v1; vz[i] = v2;
+            const double p0 = x[i] + dt * v0, p1 = y[i] + dt * v1, p2 = z[i] + dt * v2;
+            x[i] = p0; y[i] = p1; z[i] = p2;
+            const double e0 = p0 - xref[i], e1 = p1 - xref[(size_t)n + i], e2 = p2 - xref[2 * (size_t)n + i];
+            double d2 = e0 * e0 + e1 * e1 + e2 * e2;
+            if (!isfinite(d2)) { latch_error(status, -5); d2 = 0.0; }
+            dmax = fmax(dmax, d2);
+        }
     }
-    wave_max_atomic(d2, md + MD_DISP2);
+    block_max_atomic(dmax, md + MD_DISP2);
 }
 
 // v += dt/2 F/m ; track max |v|^2 for the next step length.
-__global__ void k_kick(int n, double *__restrict__ vx, double *__restrict__ vy,
-                       double *__restrict__ vz, const float *__restrict__ fx,
-                       const float *__restrict__ fy, const float *__restrict__ fz,
-                       double acc_per_mass, double *__restrict__ md,
-                       const int32_t *__restrict__ status)
+__global__ __launch_bounds__(256) void k_kick(int n, double *__restrict__ vx, double *__restrict__ vy,
+                                              double *__restrict__ vz, const float *__restrict__ fx,
+                                              const float *__restrict__ fy, const float *__restrict__ fz,
+                                              double acc_per_mass, double *__restrict__ md,
+                                              const int32_t *__restrict__ status)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double v2 = 0.0;
-    if (i < n && status[ST_ERR] == 0) {
+    double vmax = 0.0;
+    if (status[ST_ERR] == 0) {
         const double c = 0.5 * md[MD_DT] * acc_per_mass;
-        const double v0 = vx[i] + c * fx[i], v1 = vy[i] + c * fy[i], v2_ = vz[i] + c * fz[i];
-        vx[i] = v0; vy[i] = v1; vz[i] = v2_;
-        v2 = v0 * v0 + v1 * v1 + v2_ * v2_;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            const double v0 = vx[i] + c * fx[i], v1 = vy[i] + c * fy[i], v2 = vz[i] + c * fz[i];
+            vx[i] = v0; vy[i] = v1; vz[i] = v2;
+            vmax = fmax(vmax, v0 * v0 + v1 * v1 + v2 * v2);
+        }
     }
-    wave_max_atomic(v2, md + MD_VMAX2);
+    block_max_atomic(vmax, md + MD_VMAX2);
 }
 
 // max |v|^2 of the current velocities.
-__global__ void k_vmax(int n, const double *__restrict__ vx, const double *__restrict__ vy,
-                       const double *__restrict__ vz, double *__restrict__ md)
+__global__ __launch_bounds__(256) void k_vmax(int n, const double *__restrict__ vx, const double *__restrict__ vy,
+                                              const double *__restrict__ vz, double *__restrict__ md)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double v2 = 0.0;
-    if (i < n) v2 = vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
-    wave_max_atomic(v2, md + MD_VMAX2);
+    double vmax = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        vmax = fmax(vmax, vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
+    block_max_atomic(vmax, md + MD_VMAX2);
 }
 
 // Step length for the next step: dt = min(dt_max, max_disp / max|v|) (Sec. II.B).
@@ -429,18 +446,18 @@ __global__ void k_rebuild_flag(double half_skin2, double *__restrict__ md, int32
 
 // Largest displacement since the last build (for the rebuild decision at a
 // chunk start, when positions may have been changed by the caller).
-__global__ void k_disp(int n, const double *__restrict__ x, const double *__restrict__ y,
-                       const double *__restrict__ z, const double *__restrict__ xref,
-                       double *__restrict__ md)
+__global__ __launch_bounds__(256) void k_disp(int n, const double *__restrict__ x, const double *__restrict__ y,
+                                              const double *__restrict__ z, const double *__restrict__ xref,
+                                              double *__restrict__ md)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double d2 = 0.0;
-    if (i < n) {
+    double dmax = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const double e0 = x[i] - xref[i], e1 = y[i] - xref[(size_t)n + i], e2 = z[i] - xref[2 * (size_t)n + i];
-        d2 = e0 * e0 + e1 * e1 + e2 * e2;
+        double d2 = e0 * e0 + e1 * e1 + e2 * e2;
         if (!isfinite(d2)) d2 = 1e300;
+        dmax = fmax(dmax, d2);
     }
-    wave_max_atomic(d2, md + MD_DISP2);
+    block_max_atomic(dmax, md + MD_DISP2);
 }
 
 __global__ void k_set_flag(int32_t *__restrict__ flag, int32_t v)

@@ -31,7 +31,7 @@ constexpr int P_SIZE = P_B1 + 1;
 
 // Per-atom adjoint records written by the descriptor kernel and gathered by
 // the force kernel.
-constexpr int ADJ_R = 12;    // floats per atom: dU/dF_k, k = 0..8 (padded to 12)
+constexpr int ADJ_R = 16;    // floats per atom: dU/dF_k, k = 0..8 (64-byte records)
 constexpr int ADJ_A = NA * NLM;   // 120 floats per atom: dU/ds_{n,lm}
 
 // Runtime constants shared by the pair kernels.

@@ -60,17 +60,17 @@ __device__ inline float ftanh(float z)
 // other end of the pair is its exact negative: (x_j - x_i) first, then the
 // image shift n.h (which is exactly negated for -n).
 __device__ inline void pair_vector_d(int32_t e, const PairConsts &pc, int base, double xi, double yi,
-                                     double zi, const double *__restrict__ xs,
-                                     const double *__restrict__ ys, const double *__restrict__ zs,
+                                     double zi, const double4 *__restrict__ xp,
                                      const CellGeom *__restrict__ cg, int &j, double &dx, double &dy,
                                      double &dz)
 {
     int n0, n1, n2;
     decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
     j += base;
-    dx = xs[j] - xi;
-    dy = ys[j] - yi;
-    dz = zs[j] - zi;
+    const double4 pj = xp[j];
+    dx = pj.x - xi;
+    dy = pj.y - yi;
+    dz = pj.z - zi;
     if (n0 | n1 | n2) {
         const double *h = cg->h;
         dx += n0 * h[0] + n1 * h[3] + n2 * h[6];
@@ -96,8 +96,7 @@ __device__ inline double dist_d(double r2)
 // other end of the pair), their sum is this atom's own angular force term,
 // and -sum_j dU_i/dr_ij (x) r_ij is its angular virial.
 __global__ __launch_bounds__(256) void k_descriptor(
-    PairConsts pc, const double *__restrict__ xs, const double *__restrict__ ys,
-    const double *__restrict__ zs, const int32_t *__restrict__ cell_of,
+    PairConsts pc, const double4 *__restrict__ xp, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     const float *__restrict__ P, float *__restrict__ adj_r, float4 *__restrict__ pair_grad,
@@ -110,7 +109,8 @@ __global__ __launch_bounds__(256) void k_descriptor(
     if (t >= pc.n) return;
     if (status[ST_ERR] != 0) return;
 
-    const double xi = xs[t], yi = ys[t], zi = zs[t];
+    const double4 pi = xp[t];
+    const double xi = pi.x, yi = pi.y, zi = pi.z;
     const CellGeom *cg = cells + cell_of[t];
     const int base = cg->atom_start;
     const uint32_t cnt = ncnt[t];
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_descriptor(
         const int32_t e = nl_ang[(size_t)list_slot(s, naf, nab, pc.capA) * pc.n + t];
         int j;
         double dx, dy, dz;
-        pair_vector_d(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
+        pair_vector_d(e, pc, base, xi, yi, zi, xp, cg, j, dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 >= rcR2) continue;
         const double r = dist_d(r2);
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void k_descriptor(
         const int32_t e = nl_rad[(size_t)list_slot(s, nrf, nrb, pc.capR) * pc.n + t];
         int j;
         double dx, dy, dz;
-        pair_vector_d(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
+        pair_vector_d(e, pc, base, xi, yi, zi, xp, cg, j, dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 >= rcR2) continue;
         double fc, T[KB];
@@ -258,6 +258,7 @@ __global__ __launch_bounds__(256) void k_descriptor(
         ar[0] = make_float4(a[0], a[1], a[2], a[3]);
         ar[1] = make_float4(a[4], a[5], a[6], a[7]);
         ar[2] = make_float4(a[8], 0.0f, 0.0f, 0.0f);
+        ar[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     // angular adjoint B_{n,lm} = 2 (dU/dq_nl) s_{n,lm}, in place of S
 #pragma unroll
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(256) void k_descriptor(
         const int32_t e = nl_ang[(size_t)slot * pc.n + t];
         int j;
         double ddx, ddy, ddz;
-        pair_vector_d(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, ddx, ddy, ddz);
+        pair_vector_d(e, pc, base, xi, yi, zi, xp, cg, j, ddx, ddy, ddz);
         const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
         const float r2 = dx * dx + dy * dy + dz * dz;
         if (r2 >= pc.rc_ang2) continue;
@@ -338,12 +339,18 @@ __global__ __launch_bounds__(256) void k_descriptor(
 
 // ------------------------------------------------------------------ forces + virial
 
+#ifndef NEP_FORCE_BATCH
+#define NEP_FORCE_BATCH 2
+#endif
+
 // F_i = sum_j (a^i + a^j) . f'(r_ij) u_ij + U'_ZBL(r_ij) u_ij        (radial + ZBL)
 //     + sum_j [dU_i/dr_ij - dU_j/dr_ji]_angular                       (stored pair gradients)
 // and the radial + ZBL virial -1/2 sum_j f_ij (x) r_ij added to the angular one.
+// The neighbour loop runs in batches: the loads of a whole batch (list entry,
+// neighbour position, neighbour adjoint) are issued before any of its pairs
+// is evaluated, so that several gathers per lane are in flight.
 __global__ __launch_bounds__(256) void k_force(
-    PairConsts pc, const double *__restrict__ xs, const double *__restrict__ ys,
-    const double *__restrict__ zs, const int32_t *__restrict__ cell_of,
+    PairConsts pc, const double4 *__restrict__ xp, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     const uint8_t *__restrict__ rev, const float *__restrict__ adj_r,
@@ -351,13 +358,14 @@ __global__ __launch_bounds__(256) void k_force(
     const int32_t *__restrict__ perm, float *__restrict__ fx, float *__restrict__ fy,
     float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status, int ntiles)
 {
+    constexpr int BATCH = NEP_FORCE_BATCH;
     const int tile = xcd_block(ntiles);
     if (tile >= ntiles) return;
     const int t = tile * 256 + threadIdx.x;
     if (t >= pc.n) return;
     if (status[ST_ERR] != 0) return;
 
-    const double xi = xs[t], yi = ys[t], zi = zs[t];
+    const double4 pi = xp[t];
     const CellGeom *cg = cells + cell_of[t];
     const int base = cg->atom_start;
     const uint32_t cnt = ncnt[t];
@@ -375,18 +383,22 @@ __global__ __launch_bounds__(256) void k_force(
     float W[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) W[k] = 0.0f;
+    bool bad = false;
 
-    // dG/dr of the radial part of the pair (both ends) plus ZBL, divided by r
-    auto radial_over_r = [&](int j, float r, float rinv) -> float {
+    // one pair: radial + ZBL force of both ends, and the angular assembly
+    auto pair = [&](int slot, bool angular, int j, double ddx, double ddy, double ddz, float4 a0, float4 a1,
+                    float a8) {
+        const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= pc.rc_rad2) return;
+        const float r = fsqrt(r2);
+        const float rinv = frcp(r);
         const float tt = scaled_minus_one(r, pc.inv_rc_rad, pc.inv_rc_rad_lo);
         float fc, dfc;
         cutoff(tt, pc.inv_rc_rad, fc, dfc);
         const float dxdr = 4.0f * tt * pc.inv_rc_rad;
         float T[KB], dT[KB];
         cheb_d(fmaf(2.0f * tt, tt, -1.0f), T, dT);
-        const float4 *a4 = reinterpret_cast<const float4 *>(adj_r + (size_t)j * ADJ_R);
-        const float4 a0 = a4[0], a1 = a4[1];
-        const float a8 = adj_r[(size_t)j * ADJ_R + 8];
         const float ah[KB] = {ai[0] + a0.x, ai[1] + a0.y, ai[2] + a0.z, ai[3] + a0.w, ai[4] + a1.x,
                               ai[5] + a1.y, ai[6] + a1.z, ai[7] + a1.w, ai[8] + a8};
         float s0 = 0.0f, s1 = 0.0f, sa = 0.0f;
@@ -402,51 +414,47 @@ __global__ __launch_bounds__(256) void k_force(
             zbl_pair((double)r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
             dGdr += (float)dU;
         }
-        return dGdr * rinv;
-    };
-
-    const int nA = naf + nab;
-    bool bad = false;
-    for (int s = 0; s < nA; ++s) {
-        const int slot = list_slot(s, naf, nab, pc.capA);
-        const int32_t e = nl_ang[(size_t)slot * pc.n + t];
-        int j;
-        double ddx, ddy, ddz;
-        pair_vector_d(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, ddx, ddy, ddz);
-        const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 >= pc.rc_rad2) continue;
-        const float r = fsqrt(r2);
-        const float c = radial_over_r(j, r, frcp(r));
+        const float c = dGdr * rinv;
         const float px = c * dx, py = c * dy, pz = c * dz;
         Fx += px; Fy += py; Fz += pz;
         W[0] = fmaf(px, dx, W[0]); W[1] = fmaf(px, dy, W[1]); W[2] = fmaf(px, dz, W[2]);
         W[3] = fmaf(py, dx, W[3]); W[4] = fmaf(py, dy, W[4]); W[5] = fmaf(py, dz, W[5]);
         W[6] = fmaf(pz, dx, W[6]); W[7] = fmaf(pz, dy, W[7]); W[8] = fmaf(pz, dz, W[8]);
-        if (r2 < pc.rc_ang2) {
+        if (angular && r2 < pc.rc_ang2) {
             const int sj = rev[(size_t)slot * pc.n + t];
-            if (sj == 255) { bad = true; continue; }
+            if (sj == 255) { bad = true; return; }
             const float4 gj = pair_grad[(size_t)sj * pc.n + j];
             Fx -= gj.x; Fy -= gj.y; Fz -= gj.z;
         }
-    }
-    const int nRl = nrf + nrb;
-    for (int s = 0; s < nRl; ++s) {
-        const int32_t e = nl_rad[(size_t)list_slot(s, nrf, nrb, pc.capR) * pc.n + t];
-        int j;
-        double ddx, ddy, ddz;
-        pair_vector_d(e, pc, base, xi, yi, zi, xs, ys, zs, cg, j, ddx, ddy, ddz);
-        const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 >= pc.rc_rad2) continue;
-        const float r = fsqrt(r2);
-        const float c = radial_over_r(j, r, frcp(r));
-        const float px = c * dx, py = c * dy, pz = c * dz;
-        Fx += px; Fy += py; Fz += pz;
-        W[0] = fmaf(px, dx, W[0]); W[1] = fmaf(px, dy, W[1]); W[2] = fmaf(px, dz, W[2]);
-        W[3] = fmaf(py, dx, W[3]); W[4] = fmaf(py, dy, W[4]); W[5] = fmaf(py, dz, W[5]);
-        W[6] = fmaf(pz, dx, W[6]); W[7] = fmaf(pz, dy, W[7]); W[8] = fmaf(pz, dz, W[8]);
-    }
+    };
+
+    // batched sweep over one list (front nf entries, back nb entries)
+    auto sweep = [&](const int32_t *__restrict__ nl, int nf, int nb, int cap, bool angular) {
+        const int total = nf + nb;
+        for (int s0 = 0; s0 < total; s0 += BATCH) {
+            int slot[BATCH], jj[BATCH];
+            double dx[BATCH], dy[BATCH], dz[BATCH];
+            float4 a0[BATCH], a1[BATCH];
+            float a8[BATCH];
+#pragma unroll
+            for (int b = 0; b < BATCH; ++b) {
+                const int sb = s0 + b < total ? s0 + b : total - 1;   // tail repeats the last entry
+                slot[b] = list_slot(sb, nf, nb, cap);
+                const int32_t e = nl[(size_t)slot[b] * pc.n + t];
+                pair_vector_d(e, pc, base, pi.x, pi.y, pi.z, xp, cg, jj[b], dx[b], dy[b], dz[b]);
+                const float4 *a4 = reinterpret_cast<const float4 *>(adj_r + (size_t)jj[b] * ADJ_R);
+                a0[b] = a4[0];
+                a1[b] = a4[1];
+                a8[b] = adj_r[(size_t)jj[b] * ADJ_R + 8];
+            }
+#pragma unroll
+            for (int b = 0; b < BATCH; ++b)
+                if (s0 + b < total) pair(slot[b], angular, jj[b], dx[b], dy[b], dz[b], a0[b], a1[b], a8[b]);
+        }
+    };
+    sweep(nl_ang, naf, nab, pc.capA, true);
+    sweep(nl_rad, nrf, nrb, pc.capR, false);
+
     if (bad) latch_error(status, -9);
     const int i = perm[t];
     fx[i] = Fx;
@@ -492,24 +500,34 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(const int32_t *__restrict
     if (threadIdx.x < 10) part[(size_t)k * 10 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// One thread per cell: ordered sum of its chunk partials.
-__global__ void k_reduce_cells(int n_cells, const int32_t *__restrict__ cell_chunk,
-                               const double *__restrict__ part, double *__restrict__ energy,
-                               double *__restrict__ virial, const int32_t *__restrict__ status)
+// One block per cell: sum of its chunk partials (fixed order: strided
+// partial sums per thread, then a fixed tree), deterministic.
+__global__ __launch_bounds__(256) void k_reduce_cells(int n_cells, const int32_t *__restrict__ cell_chunk,
+                                                      const double *__restrict__ part, double *__restrict__ energy,
+                                                      double *__restrict__ virial,
+                                                      const int32_t *__restrict__ status)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double sh[10][256];
+    const int c = blockIdx.x;
     if (c >= n_cells) return;
     if (status[ST_ERR] != 0) return;
     double acc[10];
 #pragma unroll
     for (int q = 0; q < 10; ++q) acc[q] = 0.0;
-    for (int k = cell_chunk[c]; k < cell_chunk[c + 1]; ++k)
+    for (int k = cell_chunk[c] + threadIdx.x; k < cell_chunk[c + 1]; k += 256)
 #pragma unroll
         for (int q = 0; q < 10; ++q) acc[q] += part[(size_t)k * 10 + q];
-    energy[c] = acc[0];
-    if (virial)
 #pragma unroll
-        for (int q = 0; q < 9; ++q) virial[(size_t)c * 9 + q] = acc[1 + q];
+    for (int q = 0; q < 10; ++q) sh[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int q = 0; q < 10; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) energy[c] = sh[0][0];
+    if (virial && threadIdx.x < 9) virial[(size_t)c * 9 + threadIdx.x] = sh[1 + threadIdx.x][0];
 }
 
 // Site energies to the caller's order (FP32 output).
@@ -522,8 +540,7 @@ __global__ void k_energy_atom_out(int n, const int32_t *__restrict__ perm,
 
 // Neighbour counts inside the cutoffs (diagnostics for flop accounting).
 __global__ __launch_bounds__(256) void k_count_inside(
-    PairConsts pc, const double *__restrict__ xs, const double *__restrict__ ys,
-    const double *__restrict__ zs, const int32_t *__restrict__ cell_of,
+    PairConsts pc, const double4 *__restrict__ xp, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     unsigned long long *__restrict__ counts)
@@ -531,7 +548,8 @@ __global__ __launch_bounds__(256) void k_count_inside(
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long nr = 0, na = 0;
     if (t < pc.n) {
-        const double xi = xs[t], yi = ys[t], zi = zs[t];
+        const double4 pi = xp[t];
+    const double xi = pi.x, yi = pi.y, zi = pi.z;
         const CellGeom *cg = cells + cell_of[t];
         const uint32_t cnt = ncnt[t];
         const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
@@ -540,7 +558,7 @@ __global__ __launch_bounds__(256) void k_count_inside(
             int j;
             double dx, dy, dz;
             pair_vector_d(nl_ang[(size_t)list_slot(s, naf, nab, pc.capA) * pc.n + t], pc, cg->atom_start,
-                          xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
+                          xi, yi, zi, xp, cg, j, dx, dy, dz);
             const double r2 = dx * dx + dy * dy + dz * dz;
             nr += r2 < rcR2;
             na += r2 < rcA2;
@@ -549,7 +567,7 @@ __global__ __launch_bounds__(256) void k_count_inside(
             int j;
             double dx, dy, dz;
             pair_vector_d(nl_rad[(size_t)list_slot(s, nrf, nrb, pc.capR) * pc.n + t], pc, cg->atom_start,
-                          xi, yi, zi, xs, ys, zs, cg, j, dx, dy, dz);
+                          xi, yi, zi, xp, cg, j, dx, dy, dz);
             nr += (dx * dx + dy * dy + dz * dz) < rcR2;
         }
     }
