@@ -66,6 +66,10 @@ def lib():
         L.orc_tersoff_fc.argtypes = [C.c_double, C.c_double, C.c_double, dp, dp]
         L.orc_zbl.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_num_params.restype = C.c_int
+        L.orc_num_params.argtypes = [C.POINTER(_Model)]
+        L.orc_param_grad.restype = C.c_int
+        L.orc_param_grad.argtypes = [C.POINTER(_Model), C.c_int64, dp, dp, i32p, C.c_int, dp]
         L.orc_coulomb.restype = C.c_double
         _lib = L
     return _lib
@@ -146,6 +150,22 @@ def efv_system(model, system, virial=True):
         if virial:
             W[c] = r["virial"]
     return {"energy": E, "forces": F, "virial": W, "energy_atom": U}
+
+
+def param_grad_cell(model, pos, h, pbc=(1, 1, 1), method=-1):
+    """dE/dtheta of one cell, theta = (c_rad, c_ang, w0, b0, w1, b1) flattened (see Model.param_vector)."""
+    L = lib()
+    mr = _ModelRef(model)
+    pos = _c64(pos)
+    h = _c64(np.asarray(h).reshape(9))
+    pbc_a = np.ascontiguousarray(pbc, dtype=np.int32)
+    P = L.orc_num_params(C.byref(mr.s))
+    g = np.zeros(P)
+    rc = L.orc_param_grad(C.byref(mr.s), pos.shape[0], _dp(pos), _dp(h), pbc_a.ctypes.data_as(C.POINTER(C.c_int32)),
+                          method, _dp(g))
+    if rc != 0:
+        raise ValueError("orc_param_grad rejected its arguments")
+    return g
 
 
 def pairs(pos, h, pbc, rc, method=0):

@@ -590,6 +590,114 @@ int orc_efv(const orc_model *m, int64_t N, const double *x, const double *h, con
     return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* public: gradient of the energy with respect to the model parameters */
+/* ------------------------------------------------------------------ */
+
+/* Number of trainable parameters: c_rad, c_ang, w0, b0, w1, b1. */
+int orc_num_params(const orc_model *m)
+{
+    return m->n_rad * m->k_rad + m->n_ang * m->k_ang + m->n_hidden * orc_dim(m) + 2 * m->n_hidden + 1;
+}
+
+/* dE/dtheta of one cell, theta = (c_rad, c_ang, w0, b0, w1, b1) flattened in
+ * that order (row-major), by the chain rule through the definitions:
+ *   dU/dw1_mu = tanh z_mu,  dU/db1 = -1,
+ *   dU/dw0_mu,nu = w1_mu (1 - tanh^2 z_mu) s_nu q_nu,  dU/db0_mu = -w1_mu (1 - tanh^2 z_mu),
+ *   dU/dc^R_nk = (dU/dq_n) sum_j f_k(r_ij),
+ *   dU/dc^A_nk = sum_l (dU/dq_nl) 2 sum_j sum_k' f_k(r_ij) g_n(r_ik') P_l(cos theta_ijk').
+ * The ZBL term has no parameters.  grad must hold orc_num_params doubles. */
+int orc_param_grad(const orc_model *m, int64_t N, const double *x, const double *h, const int32_t *pbc,
+                   int method, double *grad)
+{
+    if (!m || N <= 0 || !x || !h || !pbc || !grad) return -1;
+    const int D = orc_dim(m), nR = m->n_rad, nA = m->n_ang, H = m->n_hidden, LM = m->l_max;
+    const int KR = m->k_rad, KA = m->k_ang;
+    const int P = orc_num_params(m);
+    const int o_cA = nR * KR, o_w0 = o_cA + nA * KA, o_b0 = o_w0 + H * D, o_w1 = o_b0 + H, o_b1 = o_w1 + H;
+    double hi[9], wid[3];
+    orc_inv3(h, hi);
+    orc_widths(h, wid);
+    const double rc = m->rc_rad;
+    if (method < 0) {
+        method = 1;
+        for (int a = 0; a < 3; ++a) if (!pbc[a] || wid[a] < 3.0 * rc) method = 0;
+    }
+    orc_bins B;
+    memset(&B, 0, sizeof B);
+    if (method == 1) {
+        for (int a = 0; a < 3; ++a) if (!pbc[a] || wid[a] < 3.0 * rc) return -1;
+        orc_bins_build(N, x, h, hi, wid, rc, &B);
+    }
+    for (int p = 0; p < P; ++p) grad[p] = 0.0;
+#pragma omp parallel
+    {
+        double *g = (double *)calloc((size_t)P, sizeof(double));
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t i = 0; i < N; ++i) {
+            orc_plist L = {0, 0, NULL};
+            if (method == 1) orc_pairs_binned(&B, h, i, rc, &L);
+            else orc_pairs_brute(N, x, h, hi, wid, pbc, i, rc, &L);
+            double q[256], dUdq[256], U;
+            double *Dij = (double *)malloc((size_t)(3 * L.count + 1) * sizeof(double));
+            orc_site(m, &L, q, &U, dUdq, Dij);
+            free(Dij);
+            /* network parameters */
+            for (int mu = 0; mu < H; ++mu) {
+                double z = -m->b0[mu];
+                for (int nu = 0; nu < D; ++nu) z += m->w0[mu * D + nu] * m->q_scale[nu] * q[nu];
+                const double t = tanh(z), dz = m->w1[mu] * (1.0 - t * t);
+                g[o_w1 + mu] += t;
+                g[o_b0 + mu] -= dz;
+                for (int nu = 0; nu < D; ++nu) g[o_w0 + mu * D + nu] += dz * m->q_scale[nu] * q[nu];
+            }
+            g[o_b1] -= 1.0;
+            /* radial coefficients */
+            double f[64], df[64];
+            for (int64_t p = 0; p < L.count; ++p) {
+                orc_basis(KR, L.p[p].r, m->rc_rad, f, df);
+                for (int n = 0; n < nR; ++n)
+                    for (int k = 0; k < KR; ++k) g[n * KR + k] += dUdq[n] * f[k];
+            }
+            /* angular coefficients: 2 sum_l dU/dq_nl sum_j sum_k' f_k(r_j) g_n(r_k') P_l */
+            int64_t MA = 0;
+            for (int64_t p = 0; p < L.count; ++p) MA += L.p[p].r < m->rc_ang;
+            double *fa = (double *)malloc((size_t)(MA * KA + 1) * sizeof(double));
+            double *ga = (double *)malloc((size_t)(MA * nA + 1) * sizeof(double));
+            double *dga = (double *)malloc((size_t)(MA * nA + 1) * sizeof(double));
+            const orc_pair **pa = (const orc_pair **)malloc((size_t)(MA + 1) * sizeof(orc_pair *));
+            int64_t a = 0;
+            for (int64_t p = 0; p < L.count; ++p) {
+                if (L.p[p].r >= m->rc_ang) continue;
+                orc_basis(KA, L.p[p].r, m->rc_ang, fa + a * KA, df);
+                orc_radial_fns(nA, KA, m->c_ang, L.p[p].r, m->rc_ang, ga + a * nA, dga + a * nA);
+                pa[a++] = &L.p[p];
+            }
+            for (int64_t j = 0; j < MA; ++j)
+                for (int64_t k = 0; k < MA; ++k) {
+                    double c = (pa[j]->d[0] * pa[k]->d[0] + pa[j]->d[1] * pa[k]->d[1] + pa[j]->d[2] * pa[k]->d[2]) /
+                               (pa[j]->r * pa[k]->r);
+                    if (j == k) c = 1.0;
+                    double Pl[5], dPl[5];
+                    orc_legendre(c, Pl, dPl);
+                    for (int n = 0; n < nA; ++n) {
+                        double w = 0.0;
+                        for (int l = 1; l <= LM; ++l) w += dUdq[nR + nA * (l - 1) + n] * Pl[l];
+                        w *= 2.0 * ga[k * nA + n];
+                        for (int kk = 0; kk < KA; ++kk) g[o_cA + n * KA + kk] += w * fa[j * KA + kk];
+                    }
+                }
+            free(fa); free(ga); free(dga); free(pa);
+            free(L.p);
+        }
+#pragma omp critical
+        for (int p = 0; p < P; ++p) grad[p] += g[p];
+        free(g);
+    }
+    if (method == 1) orc_bins_free(&B);
+    return 0;
+}
+
 /* Number of OpenMP threads the oracle will use. */
 int orc_num_threads(void)
 {

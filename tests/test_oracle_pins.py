@@ -416,3 +416,41 @@ def test_adaptive_time_step_caps_displacement():
     for x in log:
         assert x["dt"] <= 1.0
     assert abs(log[0]["dt"] - 0.015 / nep_synth.speed_for_energy(1000.0)) < 1e-12
+
+
+# ------------------------------------------------------------------ parameter gradients
+
+
+def test_parameter_gradient_matches_finite_differences():
+    # dE/dtheta (analytic, FP64) against central differences of the energy,
+    # on every parameter group; h scaled to each parameter's size
+    m = nep_synth.random_model()
+    s = nep_synth.diffbatch()
+    pos, hc = s.cell(11)
+    g = oracle.param_grad_cell(m, pos, hc)
+    theta = m.param_vector()
+    assert g.shape == theta.shape == (81 + 45 + 870 + 30 + 30 + 1,)
+    rng = np.random.default_rng(4)
+    groups = {"c_rad": (0, 81), "c_ang": (81, 126), "w0": (126, 996), "b0": (996, 1026),
+              "w1": (1026, 1056), "b1": (1056, 1057)}
+    for name, (a, b) in groups.items():
+        for p in rng.choice(np.arange(a, b), size=min(6, b - a), replace=False):
+            h = 1e-5 * max(1.0, abs(theta[p]))
+            tp, tm = theta.copy(), theta.copy()
+            tp[p] += h
+            tm[p] -= h
+            ep = oracle.efv_cell(m.with_param_vector(tp), pos, hc, virial=False)["energy"]
+            em = oracle.efv_cell(m.with_param_vector(tm), pos, hc, virial=False)["energy"]
+            fd = (ep - em) / (2 * h)
+            assert abs(g[p] - fd) <= 1e-6 * max(1.0, abs(fd)), (name, p, g[p], fd)
+    assert g[1056] == -pos.shape[0]      # dE/db1 = -N
+
+
+def test_parameter_gradient_linear_in_output_weights():
+    # E is linear in w1 and b1: E(theta) = w1 . dE/dw1 + b1 dE/db1 + (ZBL part)
+    m = nep_synth.random_model()
+    pos, h = nep_synth.bcc_lattice(3, 3, 3)
+    pos = pos + np.random.default_rng(1).normal(0, 0.05, pos.shape)
+    g = oracle.param_grad_cell(m, pos, h)
+    E = oracle.efv_cell(m, pos, h)["energy"]
+    assert abs(E - (m.w1 @ g[1026:1056] + m.b1 * g[1056])) < 1e-9 * max(1.0, abs(E))
