@@ -174,6 +174,27 @@ int nep_required_neighbors(nep_ctx *ctx, int32_t *ang, int32_t *rad);
  * (synchronises `stream`); used for algorithmic-flop accounting. */
 int nep_mean_neighbors(nep_ctx *ctx, void *stream, double *mean_rad, double *mean_ang);
 
+/* Number of trainable model parameters, theta = (c_rad, c_ang, w0, b0, w1, b1)
+ * flattened row-major in that order (1057 for the compiled model). */
+int nep_num_params(const nep_ctx *ctx);
+
+/* Backward pass of L = sum_c gE[c] E_c at the positions of the last
+ * nep_compute_efv on `sys`, whose outputs `out` must still hold that call's
+ * forces and virial (same stream).  All pointers are DEVICE FP64 arrays:
+ *   gE          [n_cells]        upstream gradient (input)
+ *   grad_params [nep_num_params] dL/dtheta, by the chain rule through the
+ *               network and the descriptor coefficients
+ *   grad_x/y/z  [n_atoms]        dL/dx_i = -gE[c(i)] F_i (caller order); may be NULL
+ *   grad_h      [n_cells][9]     dL/dh at fixed Cartesian positions,
+ *               gE[c] h^-T (sum_i x_i (x) F_i - W^T); may be NULL
+ * The forces and virial follow from Eq. 1; the parameter gradient is what a
+ * gradient-based fit of the model would use (the paper trains by a
+ * gradient-free evolution strategy, Sec. III.A).  Returns NEP_OK, NEP_E_ARG,
+ * NEP_E_STATE or NEP_E_HIP; device errors are latched as for nep_compute_efv. */
+int nep_backward(nep_ctx *ctx, const nep_system *sys, const nep_efv *out, const double *gE,
+                 double *grad_params, double *grad_x, double *grad_y, double *grad_z, double *grad_h,
+                 void *stream);
+
 /* Measurement support: run the evaluation path of nep_compute_efv `reps`
  * times, each kernel bracketed by HIP events recorded on `stream`, and return
  * the mean duration per launch in milliseconds:

@@ -31,7 +31,7 @@ NEP_E_INTERNAL = -9
 
 EXPORTED = ("nep_create", "nep_destroy", "nep_set_weights", "nep_build_neighbors", "nep_compute_efv",
             "nep_step_verlet", "nep_status", "nep_required_neighbors", "nep_mean_neighbors",
-            "nep_time_efv", "nep_strerror")
+            "nep_time_efv", "nep_num_params", "nep_backward", "nep_strerror")
 
 
 class NepError(RuntimeError):
@@ -101,6 +101,8 @@ def lib():
         L.nep_required_neighbors.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.nep_mean_neighbors.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.nep_time_efv.argtypes = [P, C.POINTER(System), C.POINTER(Efv), C.c_int32, C.POINTER(C.c_double), P]
+        L.nep_num_params.argtypes = [P]
+        L.nep_backward.argtypes = [P, C.POINTER(System), C.POINTER(Efv), P, P, P, P, P, P, P]
         L.nep_strerror.argtypes = [C.c_int]
         L.nep_strerror.restype = C.c_char_p
         for name in EXPORTED:
@@ -280,6 +282,30 @@ class Context:
         _check(lib().nep_time_efv(self._ptr, C.byref(s), C.byref(o), int(reps), ms, _stream_ptr(stream)),
                "nep_time_efv")
         return {"sort": ms[0], "descriptor": ms[1], "force": ms[2], "reduce": ms[3]}
+
+    def nep_num_params(self):
+        return int(lib().nep_num_params(self._ptr))
+
+    def nep_backward(self, system: DeviceSystem, out: EFV, gE, grad_pos=True, grad_cell=True, stream=None):
+        """dL/dtheta [P], dL/dx [N,3] and dL/dh [C,3,3] for L = sum_c gE[c] E_c (device FP64 tensors)."""
+        torch = _torch()
+        dev = out.fx.device
+        gE = gE.to(device=dev, dtype=torch.float64).contiguous()
+        gp = torch.empty(self.nep_num_params(), dtype=torch.float64, device=dev)
+        gx = gy = gz = gh = None
+        if grad_pos:
+            gx, gy, gz = (torch.empty(system.n_atoms, dtype=torch.float64, device=dev) for _ in range(3))
+        if grad_cell:
+            gh = torch.empty(system.n_cells, 9, dtype=torch.float64, device=dev)
+        s = system.c_struct()
+        o = out.c_struct()
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+        _check(lib().nep_backward(self._ptr, C.byref(s), C.byref(o), ptr(gE), ptr(gp), ptr(gx), ptr(gy), ptr(gz),
+                                  ptr(gh), _stream_ptr(stream)), "nep_backward")
+        if self.check:
+            self.nep_status(stream)
+        gpos = torch.stack([gx, gy, gz], dim=1) if grad_pos else None
+        return gp, gpos, (gh.view(-1, 3, 3) if grad_cell else None)
 
     def nep_mean_neighbors(self, stream=None):
         r, a = C.c_double(), C.c_double()

@@ -12,18 +12,25 @@
 
 namespace nep {
 // kernels (nep_kernels.hip)
-__global__ void k_descriptor(PairConsts, const double4 *, const int32_t *,
-                             const CellGeom *, const int32_t *, const int32_t *, const uint32_t *,
-                             const float *, float *, float4 *, float4 *, float *, double *, int32_t *, int);
-__global__ void k_force(PairConsts, const double4 *, const int32_t *,
-                        const CellGeom *, const int32_t *, const int32_t *, const uint32_t *, const uint8_t *,
-                        const float *, const float4 *, const float4 *, const int32_t *, float *, float *,
-                        float *, float *, int32_t *, int);
+__global__ void k_descriptor(PairConsts, AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
+                             const int32_t *, const uint32_t *, const float *, float4 *, float4 *, float *,
+                             double *, int32_t *, int);
+__global__ void k_force(PairConsts, const AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
+                        const int32_t *, const uint32_t *, const uint8_t *, const float4 *, const float4 *,
+                        const int32_t *, float *, float *, float *, float *, int32_t *, int);
 __global__ void k_reduce_chunks(const int32_t *, const int32_t *, const double *, const float *, double *,
                                 const int32_t *);
 __global__ void k_reduce_cells(int, const int32_t *, const double *, double *, double *, const int32_t *);
 __global__ void k_energy_atom_out(int, const int32_t *, const double *, float *);
-__global__ void k_count_inside(PairConsts, const double4 *, const int32_t *,
+__global__ void k_param_grad(PairConsts, const AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
+                             const int32_t *, const uint32_t *, const float *, const double *, double *,
+                             const int32_t *, int);
+__global__ void k_param_reduce(int, const double *, double *);
+__global__ void k_grad_pos(int, const int32_t *, const double *, const float *, const float *, const float *,
+                           double *, double *, double *);
+__global__ void k_grad_cell(const CellGeom *, const double *, const double *, const double *, const float *,
+                            const float *, const float *, const double *, const double *, double *);
+__global__ void k_count_inside(PairConsts, const AtomRec *, const int32_t *,
                                const CellGeom *, const int32_t *, const int32_t *, const uint32_t *,
                                unsigned long long *);
 // kernels (nep_build.hip)
@@ -38,8 +45,8 @@ __global__ void k_bin_scatter(int, const int32_t *, const int32_t *, int32_t *, 
 __global__ void k_bin_rank(int, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
                            const CellGeom *, int32_t *, int32_t *, const int32_t *, const int32_t *);
 __global__ void k_sort_positions(int, const int32_t *, const double *, const double *, const double *,
-                                 const int32_t *, const int32_t *, const CellGeom *, double4 *, int32_t *);
-__global__ void k_build_lists(PairConsts, double, double, double, double, const double4 *, const int32_t *,
+                                 const int32_t *, const int32_t *, const CellGeom *, AtomRec *, int32_t *);
+__global__ void k_build_lists(PairConsts, double, double, double, double, const AtomRec *, const int32_t *,
                               const CellGeom *, const int32_t *, const int32_t *, const int32_t *, int32_t *,
                               int32_t *, uint32_t *, int32_t *, const int32_t *);
 __global__ void k_build_reverse(PairConsts, const int32_t *, const CellGeom *, const int32_t *,
@@ -73,13 +80,13 @@ struct nep_ctx {
     int device = 0;
     float *params = nullptr;
     // per-atom storage (capacity cfg.max_atoms)
-    double4 *xp = nullptr;       // [N] sorted wrapped positions (x, y, z, 0)
+    AtomRec *xp = nullptr;       // [N] sorted wrapped positions and radial adjoints
     double *xref = nullptr;      // [3][N] caller-order positions at the last build
     int32_t *perm = nullptr, *bin_of = nullptr, *wrap = nullptr, *cell_of = nullptr, *tmp = nullptr,
             *bin_sorted = nullptr;
     uint32_t *ncnt = nullptr;
     int32_t *nl_ang = nullptr, *nl_rad = nullptr;
-    float *adj_r = nullptr, *w_atom = nullptr;
+    float *w_atom = nullptr;
     float4 *pair_grad = nullptr;  // [capA][N] dU_i/dr_ij of every angular list slot
     float4 *f_own = nullptr;      // [N] sum_j dU_i/dr_ij (angular)
     uint8_t *rev = nullptr;       // [capA][N] reverse slot index
@@ -100,6 +107,8 @@ struct nep_ctx {
     int32_t *flag = nullptr;         // rebuild flag
     double *md = nullptr;            // [8]
     unsigned long long *counts = nullptr;
+    double *pg_part = nullptr;       // parameter-gradient block partials
+    int pg_blocks = 0;
     int32_t *h_status = nullptr;     // pinned
     double *h_md = nullptr;          // pinned
     unsigned long long *h_counts = nullptr;
@@ -153,11 +162,11 @@ void nep_destroy(nep_ctx *c)
     hipSetDevice(c->device);
     hipDeviceSynchronize();
     void *bufs[] = {c->params, c->xp, c->xref, c->bin_rank, c->bin_lin, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
-                    c->bin_sorted, c->ncnt, c->nl_ang, c->nl_rad, c->adj_r, c->pair_grad, c->f_own, c->rev,
+                    c->bin_sorted, c->ncnt, c->nl_ang, c->nl_rad, c->pair_grad, c->f_own, c->rev,
                     c->w_atom,
                     c->e_atom, c->cells, c->cell_start_d, c->chunk_begin, c->chunk_end, c->cell_chunk,
                     c->part, c->bin_count, c->bin_start, c->bin_fill, c->scan_sums, c->status, c->flag,
-                    c->md, c->counts};
+                    c->md, c->counts, c->pg_part};
     for (void *p : bufs)
         if (p) hipFree(p);
     if (c->h_status) hipHostFree(c->h_status);
@@ -191,7 +200,7 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
         if (ok && hipMalloc(p, bytes > 0 ? bytes : 16) != hipSuccess) ok = false;
     };
     A((void **)&c->params, P_SIZE * sizeof(float));
-    A((void **)&c->xp, N * sizeof(double4));
+    A((void **)&c->xp, N * sizeof(AtomRec));
     A((void **)&c->xref, 3 * N * sizeof(double));
     A((void **)&c->perm, N * 4);
     A((void **)&c->bin_of, N * 4);
@@ -202,7 +211,6 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     A((void **)&c->ncnt, N * 4);
     A((void **)&c->nl_ang, N * cfg->max_neigh_ang * 4);
     A((void **)&c->nl_rad, N * cfg->max_neigh_rad * 4);
-    A((void **)&c->adj_r, N * ADJ_R * 4);
     A((void **)&c->pair_grad, N * cfg->max_neigh_ang * sizeof(float4));
     A((void **)&c->f_own, N * sizeof(float4));
     A((void **)&c->rev, N * cfg->max_neigh_ang);
@@ -488,16 +496,16 @@ int nep_build_neighbors(nep_ctx *c, const nep_system *s, void *stream)
 static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t st, bool refresh_positions)
 {
     const int n = (int)s->n_atoms;
-    double4 *xp = c->xp;
+    AtomRec *xp = c->xp;
     if (refresh_positions)
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
                                                            c->cells, xp, c->status);
     const int tiles = grid_for(n, 256);
     k_descriptor<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
-                                                  c->ncnt, c->params, c->adj_r, c->pair_grad, c->f_own, c->w_atom,
+                                                  c->ncnt, c->params, c->pair_grad, c->f_own, c->w_atom,
                                                   c->e_atom, c->status, tiles);
     k_force<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
-                                             c->ncnt, c->rev, c->adj_r, c->pair_grad, c->f_own, c->perm, o->fx, o->fy,
+                                             c->ncnt, c->rev, c->pair_grad, c->f_own, c->perm, o->fx, o->fy,
                                              o->fz, c->w_atom, c->status, tiles);
     k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom, c->part,
                                                  c->status);
@@ -534,7 +542,7 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
     if (!same_system(c, s)) return NEP_E_STATE;
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)s->n_atoms;
-    double4 *xp = c->xp;
+    AtomRec *xp = c->xp;
     const int tiles = grid_for(n, 256);
     hipEvent_t ev[5];
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
@@ -545,11 +553,11 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
                                                            c->cells, xp, c->status);
         HIP_TRY(hipEventRecord(ev[1], st));
         k_descriptor<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xp, c->cell_of, c->cells, c->nl_ang,
-                                                      c->nl_rad, c->ncnt, c->params, c->adj_r, c->pair_grad,
+                                                      c->nl_rad, c->ncnt, c->params, c->pair_grad,
                                                       c->f_own, c->w_atom, c->e_atom, c->status, tiles);
         HIP_TRY(hipEventRecord(ev[2], st));
         k_force<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
-                                                 c->ncnt, c->rev, c->adj_r, c->pair_grad, c->f_own, c->perm, o->fx,
+                                                 c->ncnt, c->rev, c->pair_grad, c->f_own, c->perm, o->fx,
                                                  o->fy, o->fz, c->w_atom, c->status, tiles);
         HIP_TRY(hipEventRecord(ev[3], st));
         k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom,
@@ -567,6 +575,47 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
     }
     for (auto &e : ev) HIP_TRY(hipEventDestroy(e));
     for (int k = 0; k < 4; ++k) ms[k] = acc[k] / reps;
+    return NEP_OK;
+}
+
+static constexpr int N_PARAMS = NR * KB + NA * KB + NH * DIM + NH + NH + 1;
+
+int nep_num_params(const nep_ctx *c)
+{
+    if (!c) return NEP_E_ARG;
+    return N_PARAMS;
+}
+
+int nep_backward(nep_ctx *c, const nep_system *s, const nep_efv *o, const double *gE, double *grad_params,
+                 double *gx, double *gy, double *gz, double *gh, void *stream)
+{
+    if (!c || !gE || !grad_params) return NEP_E_ARG;
+    int rc = check_system(c, s, false);
+    if (rc) return rc;
+    if ((rc = check_out(o))) return rc;
+    if ((gx || gy || gz) && !(gx && gy && gz)) return NEP_E_ARG;
+    if (gh && !o->virial) return NEP_E_ARG;
+    if (!same_system(c, s)) return NEP_E_STATE;
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)s->n_atoms;
+    const int tiles = (n + 63) / 64;
+    const int blocks = std::min(tiles, 1024);
+    if (blocks > c->pg_blocks) {
+        if (c->pg_part) (void)hipFree(c->pg_part);
+        c->pg_part = nullptr;
+        HIP_TRY(hipMalloc(&c->pg_part, (size_t)blocks * N_PARAMS * sizeof(double)));
+        c->pg_blocks = blocks;
+    }
+    k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
+                                                       c->cells, c->xp, c->status);
+    k_param_grad<<<blocks, 64, 0, st>>>(c->pc, c->xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
+                                        c->params, gE, c->pg_part, c->status, tiles);
+    k_param_reduce<<<grid_for(N_PARAMS, 256), 256, 0, st>>>(blocks, c->pg_part, grad_params);
+    if (gx) k_grad_pos<<<grid_for(n, 256), 256, 0, st>>>(n, c->cell_of, gE, o->fx, o->fy, o->fz, gx, gy, gz);
+    if (gh)
+        k_grad_cell<<<c->built_cells, 256, 0, st>>>(c->cells, s->x, s->y, s->z, o->fx, o->fy, o->fz, o->virial,
+                                                    gE, gh);
+    HIP_TRY(hipGetLastError());
     return NEP_OK;
 }
 

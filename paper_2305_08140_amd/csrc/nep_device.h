@@ -29,10 +29,16 @@ constexpr int P_W1 = P_B0 + NH;          // [NH]
 constexpr int P_B1 = P_W1 + NH;          // [1]
 constexpr int P_SIZE = P_B1 + 1;
 
-// Per-atom adjoint records written by the descriptor kernel and gathered by
-// the force kernel.
-constexpr int ADJ_R = 16;    // floats per atom: dU/dF_k, k = 0..8 (64-byte records)
-constexpr int ADJ_A = NA * NLM;   // 120 floats per atom: dU/ds_{n,lm}
+// Per-atom record in sorted order, one 64-byte half cache line: the wrapped
+// FP64 position (written by the position refresh) and the radial adjoint
+// a_k = dU_i/dF_k (written by the descriptor kernel).  A neighbour gather in
+// the force kernel touches exactly one record.
+struct __attribute__((aligned(64))) AtomRec {
+    double x, y, z;
+    float a[KB];
+    float pad;
+};
+static_assert(sizeof(AtomRec) == 64, "AtomRec must be 64 bytes");
 
 // Runtime constants shared by the pair kernels.
 struct PairConsts {

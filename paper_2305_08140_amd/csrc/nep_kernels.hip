@@ -60,17 +60,16 @@ __device__ inline float ftanh(float z)
 // other end of the pair is its exact negative: (x_j - x_i) first, then the
 // image shift n.h (which is exactly negated for -n).
 __device__ inline void pair_vector_d(int32_t e, const PairConsts &pc, int base, double xi, double yi,
-                                     double zi, const double4 *__restrict__ xp,
+                                     double zi, const AtomRec *__restrict__ xp,
                                      const CellGeom *__restrict__ cg, int &j, double &dx, double &dy,
                                      double &dz)
 {
     int n0, n1, n2;
     decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
     j += base;
-    const double4 pj = xp[j];
-    dx = pj.x - xi;
-    dy = pj.y - yi;
-    dz = pj.z - zi;
+    dx = xp[j].x - xi;
+    dy = xp[j].y - yi;
+    dz = xp[j].z - zi;
     if (n0 | n1 | n2) {
         const double *h = cg->h;
         dx += n0 * h[0] + n1 * h[3] + n2 * h[6];
@@ -88,55 +87,27 @@ __device__ inline double dist_d(double r2)
     return rd + fma(-rd, rd, r2) * (double)(0.5f * frcp(rf));
 }
 
-// Descriptor (FP64 pair geometry and basis, FP32 harmonics and sums), site
-// energy, network forward and backward, the radial adjoint dU_i/dF_k (stored),
-// and then, with B_{n,lm} = dU_i/ds_{n,lm} kept in registers, the gradient of
-// U_i with respect to every angular pair vector, dU_i/dr_ij.  Those pair
-// gradients are stored per list slot (the force kernel subtracts them at the
-// other end of the pair), their sum is this atom's own angular force term,
-// and -sum_j dU_i/dr_ij (x) r_ij is its angular virial.
-__global__ __launch_bounds__(256) void k_descriptor(
-    PairConsts pc, const double4 *__restrict__ xp, const int32_t *__restrict__ cell_of,
-    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
-    const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
-    const float *__restrict__ P, float *__restrict__ adj_r, float4 *__restrict__ pair_grad,
-    float4 *__restrict__ f_own, float *__restrict__ w_atom, double *__restrict__ e_atom,
-    int32_t *__restrict__ status, int ntiles)
+// Descriptor of one atom: FP64 pair geometry and Chebyshev basis, FP32
+// harmonics and sums.  Returns the radial sums F_k = sum_j f_k(r_ij), the
+// angular sums S[n][lm] = sum_j g_n(r_ij) Y_lm(u_ij), and the ZBL half-energy.
+__device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const AtomRec *__restrict__ xp, int t,
+                                                double xi, double yi, double zi, const CellGeom *cg, int base,
+                                                const int32_t *__restrict__ nl_ang,
+                                                const int32_t *__restrict__ nl_rad, int naf, int nab, int nrf,
+                                                int nrb, const float *__restrict__ P, const float csA[NA],
+                                                float F[KB], float S[NA][NLM], double &ezbl, bool &overlap)
 {
-    const int tile = xcd_block(ntiles);
-    if (tile >= ntiles) return;
-    const int t = tile * 256 + threadIdx.x;
-    if (t >= pc.n) return;
-    if (status[ST_ERR] != 0) return;
-
-    const double4 pi = xp[t];
-    const double xi = pi.x, yi = pi.y, zi = pi.z;
-    const CellGeom *cg = cells + cell_of[t];
-    const int base = cg->atom_start;
-    const uint32_t cnt = ncnt[t];
-    const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
     const double inv_rR = 1.0 / (double)pc.rc_rad, inv_rA = 1.0 / (double)pc.rc_ang;
     const double rcR2 = (double)pc.rc_rad * pc.rc_rad, rcA2 = (double)pc.rc_ang * pc.rc_ang;
-
-    float csA[NA];
-#pragma unroll
-    for (int n = 0; n < NA; ++n) {
-        float s = 0.0f;
-#pragma unroll
-        for (int k = 0; k < KB; ++k) s += P[P_CA + n * KB + k];
-        csA[n] = s;
-    }
-
     double AR[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) AR[k] = 0.0;
-    float S[NA][NLM];
 #pragma unroll
     for (int n = 0; n < NA; ++n)
 #pragma unroll
         for (int lm = 0; lm < NLM; ++lm) S[n][lm] = 0.0f;
-    double ezbl = 0.0;
-    bool overlap = false;
+    ezbl = 0.0;
+    overlap = false;
 
     const int nA = naf + nab;
     for (int s = 0; s < nA; ++s) {
@@ -192,38 +163,41 @@ __global__ __launch_bounds__(256) void k_descriptor(
 #pragma unroll
         for (int k = 0; k < KB; ++k) AR[k] = fma(fc, T[k], AR[k]);
     }
-    if (overlap) latch_error(status, -4);
+#pragma unroll
+    for (int k = 0; k < KB; ++k) F[k] = (float)(0.5 * (AR[k] + AR[0]));
+}
 
-    // descriptor
-    float q[DIM];
-    {
-        float F[KB];
+// Descriptor vector q from the sums (radial q_n = sum_k c_nk F_k, angular q_nl = sum_m S^2).
+__device__ __forceinline__ void descriptor_vector(const float *__restrict__ P, const float F[KB],
+                                                  const float S[NA][NLM], float q[DIM])
+{
 #pragma unroll
-        for (int k = 0; k < KB; ++k) F[k] = (float)(0.5 * (AR[k] + AR[0]));
+    for (int n = 0; n < NR; ++n) {
+        float s = 0.0f;
 #pragma unroll
-        for (int n = 0; n < NR; ++n) {
+        for (int k = 0; k < KB; ++k) s = fmaf(P[P_CR + n * KB + k], F[k], s);
+        q[n] = s;
+    }
+#pragma unroll
+    for (int l = 1; l <= LMAX; ++l)
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
             float s = 0.0f;
 #pragma unroll
-            for (int k = 0; k < KB; ++k) s = fmaf(P[P_CR + n * KB + k], F[k], s);
-            q[n] = s;
+            for (int lm = l * l - 1; lm < (l + 1) * (l + 1) - 1; ++lm) s = fmaf(S[n][lm], S[n][lm], s);
+            q[NR + NA * (l - 1) + n] = s;
         }
-#pragma unroll
-        for (int l = 1; l <= LMAX; ++l)
-#pragma unroll
-            for (int n = 0; n < NA; ++n) {
-                float s = 0.0f;
-#pragma unroll
-                for (int lm = l * l - 1; lm < (l + 1) * (l + 1) - 1; ++lm) s = fmaf(S[n][lm], S[n][lm], s);
-                q[NR + NA * (l - 1) + n] = s;
-            }
-    }
-    // network, forward and backward in one pass over the hidden neurons: row
-    // mu of w0 gives z_mu, and dU/dz_mu times the same row accumulates dU/dq
+}
+
+// Network forward and backward in one pass over the hidden neurons: row mu of
+// w0 gives z_mu, and dU/dz_mu times the same row accumulates dU/dq.  Returns
+// U (without ZBL) and Fp = dU/dq (q unscaled).
+__device__ __forceinline__ float network(const float *__restrict__ P, const float q[DIM], float Fp[DIM])
+{
     float qt[DIM];
 #pragma unroll
     for (int nu = 0; nu < DIM; ++nu) qt[nu] = P[P_QS + nu] * q[nu];
     float U = -P[P_B1];
-    float Fp[DIM];
 #pragma unroll
     for (int nu = 0; nu < DIM; ++nu) Fp[nu] = 0.0f;
 #pragma unroll 1
@@ -241,24 +215,69 @@ __global__ __launch_bounds__(256) void k_descriptor(
     }
 #pragma unroll
     for (int nu = 0; nu < DIM; ++nu) Fp[nu] *= P[P_QS + nu];
+    return U;
+}
+
+__device__ __forceinline__ void angular_coef_sums(const float *__restrict__ P, float csA[NA])
+{
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < KB; ++k) s += P[P_CA + n * KB + k];
+        csA[n] = s;
+    }
+}
+
+// Descriptor, site energy, network forward and backward, the radial adjoint
+// dU_i/dF_k (stored in the atom's record), and then, with
+// B_{n,lm} = dU_i/ds_{n,lm} kept in registers, the gradient of U_i with
+// respect to every angular pair vector, dU_i/dr_ij.  Those pair gradients are
+// stored per list slot (the force kernel subtracts them at the other end of
+// the pair), their sum is this atom's own angular force term, and
+// -sum_j dU_i/dr_ij (x) r_ij is its angular virial.
+__global__ __launch_bounds__(256) void k_descriptor(
+    PairConsts pc, AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
+    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
+    const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
+    const float *__restrict__ P, float4 *__restrict__ pair_grad,
+    float4 *__restrict__ f_own, float *__restrict__ w_atom, double *__restrict__ e_atom,
+    int32_t *__restrict__ status, int ntiles)
+{
+    const int tile = xcd_block(ntiles);
+    if (tile >= ntiles) return;
+    const int t = tile * 256 + threadIdx.x;
+    if (t >= pc.n) return;
+    if (status[ST_ERR] != 0) return;
+
+    const double xi = xp[t].x, yi = xp[t].y, zi = xp[t].z;
+    const CellGeom *cg = cells + cell_of[t];
+    const int base = cg->atom_start;
+    const uint32_t cnt = ncnt[t];
+    const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
+    const int nA = naf + nab;
+
+    float csA[NA];
+    angular_coef_sums(P, csA);
+    float F[KB];
+    float S[NA][NLM];
+    double ezbl;
+    bool overlap;
+    descriptor_sums(pc, xp, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, P, csA, F, S, ezbl,
+                    overlap);
+    if (overlap) latch_error(status, -4);
+    float q[DIM];
+    descriptor_vector(P, F, S, q);
+    float Fp[DIM];
+    const float U = network(P, q, Fp);
     e_atom[t] = (double)U + ezbl;
-    // radial adjoint a_k = dU_i / dF_k
-    {
-        float a[ADJ_R];
+    // radial adjoint a_k = dU_i / dF_k, into this atom's record
 #pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            float s = 0.0f;
+    for (int k = 0; k < KB; ++k) {
+        float s = 0.0f;
 #pragma unroll
-            for (int n = 0; n < NR; ++n) s = fmaf(Fp[n], P[P_CR + n * KB + k], s);
-            a[k] = s;
-        }
-#pragma unroll
-        for (int k = KB; k < ADJ_R; ++k) a[k] = 0.0f;
-        float4 *ar = reinterpret_cast<float4 *>(adj_r + (size_t)t * ADJ_R);
-        ar[0] = make_float4(a[0], a[1], a[2], a[3]);
-        ar[1] = make_float4(a[4], a[5], a[6], a[7]);
-        ar[2] = make_float4(a[8], 0.0f, 0.0f, 0.0f);
-        ar[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int n = 0; n < NR; ++n) s = fmaf(Fp[n], P[P_CR + n * KB + k], s);
+        xp[t].a[k] = s;
     }
     // angular adjoint B_{n,lm} = 2 (dU/dq_nl) s_{n,lm}, in place of S
 #pragma unroll
@@ -282,7 +301,11 @@ __global__ __launch_bounds__(256) void k_descriptor(
         pair_vector_d(e, pc, base, xi, yi, zi, xp, cg, j, ddx, ddy, ddz);
         const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
         const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 >= pc.rc_ang2) continue;
+        if (r2 >= pc.rc_ang2) {
+            // outside the angular cutoff now: the other end subtracts a zero
+            pair_grad[(size_t)slot * pc.n + t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            continue;
+        }
         const float r = fsqrt(r2);
         const float rinv = frcp(r);
         const float tt = scaled_minus_one(r, pc.inv_rc_ang, pc.inv_rc_ang_lo);
@@ -339,45 +362,34 @@ __global__ __launch_bounds__(256) void k_descriptor(
 
 // ------------------------------------------------------------------ forces + virial
 
-#ifndef NEP_FORCE_BATCH
-#define NEP_FORCE_BATCH 2
-#endif
-
 // F_i = sum_j (a^i + a^j) . f'(r_ij) u_ij + U'_ZBL(r_ij) u_ij        (radial + ZBL)
 //     + sum_j [dU_i/dr_ij - dU_j/dr_ji]_angular                       (stored pair gradients)
 // and the radial + ZBL virial -1/2 sum_j f_ij (x) r_ij added to the angular one.
-// The neighbour loop runs in batches: the loads of a whole batch (list entry,
-// neighbour position, neighbour adjoint) are issued before any of its pairs
-// is evaluated, so that several gathers per lane are in flight.
+// Each neighbour costs one 64-byte record gather (position and adjoint) and,
+// for angular entries, one 16-byte pair-gradient gather.
 __global__ __launch_bounds__(256) void k_force(
-    PairConsts pc, const double4 *__restrict__ xp, const int32_t *__restrict__ cell_of,
+    PairConsts pc, const AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
-    const uint8_t *__restrict__ rev, const float *__restrict__ adj_r,
-    const float4 *__restrict__ pair_grad, const float4 *__restrict__ f_own,
+    const uint8_t *__restrict__ rev, const float4 *__restrict__ pair_grad, const float4 *__restrict__ f_own,
     const int32_t *__restrict__ perm, float *__restrict__ fx, float *__restrict__ fy,
     float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status, int ntiles)
 {
-    constexpr int BATCH = NEP_FORCE_BATCH;
     const int tile = xcd_block(ntiles);
     if (tile >= ntiles) return;
     const int t = tile * 256 + threadIdx.x;
     if (t >= pc.n) return;
     if (status[ST_ERR] != 0) return;
 
-    const double4 pi = xp[t];
+    const double xi = xp[t].x, yi = xp[t].y, zi = xp[t].z;
     const CellGeom *cg = cells + cell_of[t];
     const int base = cg->atom_start;
     const uint32_t cnt = ncnt[t];
     const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
 
     float ai[KB];
-    {
-        const float4 *a4 = reinterpret_cast<const float4 *>(adj_r + (size_t)t * ADJ_R);
-        const float4 a0 = a4[0], a1 = a4[1], a2 = a4[2];
-        ai[0] = a0.x; ai[1] = a0.y; ai[2] = a0.z; ai[3] = a0.w;
-        ai[4] = a1.x; ai[5] = a1.y; ai[6] = a1.z; ai[7] = a1.w; ai[8] = a2.x;
-    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) ai[k] = xp[t].a[k];
     const float4 fo = f_own[t];
     float Fx = fo.x, Fy = fo.y, Fz = fo.z;
     float W[9];
@@ -385,28 +397,36 @@ __global__ __launch_bounds__(256) void k_force(
     for (int k = 0; k < 9; ++k) W[k] = 0.0f;
     bool bad = false;
 
-    // one pair: radial + ZBL force of both ends, and the angular assembly
-    auto pair = [&](int slot, bool angular, int j, double ddx, double ddy, double ddz, float4 a0, float4 a1,
-                    float a8) {
+    // radial + ZBL force of one pair (both ends); returns false outside rc_rad
+    auto radial = [&](int32_t e) -> bool {
+        int n0, n1, n2, j;
+        decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
+        j += base;
+        const AtomRec rj = xp[j];
+        double ddx = rj.x - xi, ddy = rj.y - yi, ddz = rj.z - zi;
+        if (n0 | n1 | n2) {
+            const double *h = cg->h;
+            ddx += n0 * h[0] + n1 * h[3] + n2 * h[6];
+            ddy += n0 * h[1] + n1 * h[4] + n2 * h[7];
+            ddz += n0 * h[2] + n1 * h[5] + n2 * h[8];
+        }
         const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
         const float r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 >= pc.rc_rad2) return;
+        if (r2 >= pc.rc_rad2) return false;
         const float r = fsqrt(r2);
-        const float rinv = frcp(r);
         const float tt = scaled_minus_one(r, pc.inv_rc_rad, pc.inv_rc_rad_lo);
         float fc, dfc;
         cutoff(tt, pc.inv_rc_rad, fc, dfc);
         const float dxdr = 4.0f * tt * pc.inv_rc_rad;
         float T[KB], dT[KB];
         cheb_d(fmaf(2.0f * tt, tt, -1.0f), T, dT);
-        const float ah[KB] = {ai[0] + a0.x, ai[1] + a0.y, ai[2] + a0.z, ai[3] + a0.w, ai[4] + a1.x,
-                              ai[5] + a1.y, ai[6] + a1.z, ai[7] + a1.w, ai[8] + a8};
         float s0 = 0.0f, s1 = 0.0f, sa = 0.0f;
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
-            s0 = fmaf(ah[k], T[k], s0);
-            s1 = fmaf(ah[k], dT[k], s1);
-            sa += ah[k];
+            const float ah = ai[k] + rj.a[k];
+            s0 = fmaf(ah, T[k], s0);
+            s1 = fmaf(ah, dT[k], s1);
+            sa += ah;
         }
         float dGdr = 0.5f * (dxdr * fc * s1 + dfc * (s0 + sa));
         if (r < pc.zbl_r2) {
@@ -414,46 +434,29 @@ __global__ __launch_bounds__(256) void k_force(
             zbl_pair((double)r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
             dGdr += (float)dU;
         }
-        const float c = dGdr * rinv;
+        const float c = dGdr * frcp(r);
         const float px = c * dx, py = c * dy, pz = c * dz;
         Fx += px; Fy += py; Fz += pz;
         W[0] = fmaf(px, dx, W[0]); W[1] = fmaf(px, dy, W[1]); W[2] = fmaf(px, dz, W[2]);
         W[3] = fmaf(py, dx, W[3]); W[4] = fmaf(py, dy, W[4]); W[5] = fmaf(py, dz, W[5]);
         W[6] = fmaf(pz, dx, W[6]); W[7] = fmaf(pz, dy, W[7]); W[8] = fmaf(pz, dz, W[8]);
-        if (angular && r2 < pc.rc_ang2) {
-            const int sj = rev[(size_t)slot * pc.n + t];
-            if (sj == 255) { bad = true; return; }
-            const float4 gj = pair_grad[(size_t)sj * pc.n + j];
-            Fx -= gj.x; Fy -= gj.y; Fz -= gj.z;
-        }
+        return true;
     };
 
-    // batched sweep over one list (front nf entries, back nb entries)
-    auto sweep = [&](const int32_t *__restrict__ nl, int nf, int nb, int cap, bool angular) {
-        const int total = nf + nb;
-        for (int s0 = 0; s0 < total; s0 += BATCH) {
-            int slot[BATCH], jj[BATCH];
-            double dx[BATCH], dy[BATCH], dz[BATCH];
-            float4 a0[BATCH], a1[BATCH];
-            float a8[BATCH];
-#pragma unroll
-            for (int b = 0; b < BATCH; ++b) {
-                const int sb = s0 + b < total ? s0 + b : total - 1;   // tail repeats the last entry
-                slot[b] = list_slot(sb, nf, nb, cap);
-                const int32_t e = nl[(size_t)slot[b] * pc.n + t];
-                pair_vector_d(e, pc, base, pi.x, pi.y, pi.z, xp, cg, jj[b], dx[b], dy[b], dz[b]);
-                const float4 *a4 = reinterpret_cast<const float4 *>(adj_r + (size_t)jj[b] * ADJ_R);
-                a0[b] = a4[0];
-                a1[b] = a4[1];
-                a8[b] = adj_r[(size_t)jj[b] * ADJ_R + 8];
-            }
-#pragma unroll
-            for (int b = 0; b < BATCH; ++b)
-                if (s0 + b < total) pair(slot[b], angular, jj[b], dx[b], dy[b], dz[b], a0[b], a1[b], a8[b]);
-        }
-    };
-    sweep(nl_ang, naf, nab, pc.capA, true);
-    sweep(nl_rad, nrf, nrb, pc.capR, false);
+    const int nA = naf + nab;
+    for (int s = 0; s < nA; ++s) {
+        const int slot = list_slot(s, naf, nab, pc.capA);
+        const int32_t e = nl_ang[(size_t)slot * pc.n + t];
+        if (!radial(e)) continue;
+        // angular: subtract the other end's stored dU_j/dr_ji (zero outside rc_ang)
+        const int sj = rev[(size_t)slot * pc.n + t];
+        if (sj == 255) { bad = true; continue; }
+        const int j = (int)((uint32_t)e & ((1u << pc.jbits) - 1u)) + base;
+        const float4 gj = pair_grad[(size_t)sj * pc.n + j];
+        Fx -= gj.x; Fy -= gj.y; Fz -= gj.z;
+    }
+    const int nRl = nrf + nrb;
+    for (int s = 0; s < nRl; ++s) radial(nl_rad[(size_t)list_slot(s, nrf, nrb, pc.capR) * pc.n + t]);
 
     if (bad) latch_error(status, -9);
     const int i = perm[t];
@@ -463,6 +466,235 @@ __global__ __launch_bounds__(256) void k_force(
     float *w = w_atom + (size_t)t * 9;
 #pragma unroll
     for (int k = 0; k < 9; ++k) w[k] = fmaf(-0.5f, W[k], w[k]);
+}
+
+// ------------------------------------------------------------------ parameter gradients
+
+// theta = (c_rad [NR][KB], c_ang [NA][KB], w0 [NH][DIM], b0 [NH], w1 [NH], b1)
+constexpr int NPARAM = NR * KB + NA * KB + NH * DIM + NH + NH + 1;
+constexpr int PG_TILE = 64;
+// per-atom factors kept in LDS: g dz_mu, g tanh z_mu, s q (unweighted),
+// g dU/dq_n (radial), F_k (unweighted), g G_nk, g
+constexpr int PG_DZ = 0, PG_TH = PG_DZ + NH, PG_QT = PG_TH + NH, PG_FPR = PG_QT + DIM, PG_F = PG_FPR + NR,
+              PG_G = PG_F + KB, PG_W = PG_G + NA * KB, PG_REC = PG_W + 1;
+
+// Gradient of sum_i gE[cell(i)] U_i with respect to theta.  Per atom:
+//   dU/dw1_mu = tanh z_mu, dU/db0_mu = -dz_mu, dU/dw0_mu,nu = dz_mu s_nu q_nu,
+//   dU/db1 = -1, dU/dc^R_nk = (dU/dq_n) F_k,
+//   dU/dc^A_nk = sum_{lm} B_{n,lm} sum_j f_k(r_ij) Y_lm(u_ij)   (B = dU/ds_{n,lm}),
+// with dz_mu = w1_mu (1 - tanh^2 z_mu).  64-atom tiles: the factors go to
+// LDS, then every thread sums its own outputs (o = lane + 64 k) over the
+// tile; one FP64 partial per block and output, reduced afterwards in order.
+__global__ __launch_bounds__(64) void k_param_grad(
+    PairConsts pc, const AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
+    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
+    const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt, const float *__restrict__ P,
+    const double *__restrict__ gE, double *__restrict__ part, const int32_t *__restrict__ status, int ntiles)
+{
+    __shared__ float rec[PG_TILE][PG_REC + 1];
+    constexpr int NOWN = (NPARAM + PG_TILE - 1) / PG_TILE;
+    const int lane = threadIdx.x;
+    double acc[NOWN];
+#pragma unroll
+    for (int k = 0; k < NOWN; ++k) acc[k] = 0.0;
+    const bool ok = status[ST_ERR] == 0;
+    float csA[NA];
+    angular_coef_sums(P, csA);
+
+    for (int tile = blockIdx.x; tile < ntiles && ok; tile += gridDim.x) {
+        const int t = tile * PG_TILE + lane;
+        float *r = rec[lane];
+        if (t < pc.n) {
+            const double xi = xp[t].x, yi = xp[t].y, zi = xp[t].z;
+            const CellGeom *cg = cells + cell_of[t];
+            const int base = cg->atom_start;
+            const uint32_t cnt = ncnt[t];
+            const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
+            const float g = (float)gE[cell_of[t]];
+            float F[KB];
+            float S[NA][NLM];
+            double ezbl;
+            bool overlap;
+            descriptor_sums(pc, xp, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, P, csA, F, S,
+                            ezbl, overlap);
+            float q[DIM];
+            descriptor_vector(P, F, S, q);
+            // network with the per-neuron factors written to LDS
+            float Fp[DIM];
+#pragma unroll
+            for (int nu = 0; nu < DIM; ++nu) {
+                Fp[nu] = 0.0f;
+                r[PG_QT + nu] = P[P_QS + nu] * q[nu];
+            }
+#pragma unroll 1
+            for (int mu = 0; mu < NH; ++mu) {
+                const float *w = P + P_W0 + mu * DIM;
+                float z = -P[P_B0 + mu];
+#pragma unroll
+                for (int nu = 0; nu < DIM; ++nu) z = fmaf(w[nu], P[P_QS + nu] * q[nu], z);
+                const float th = ftanh(z);
+                const float dz = P[P_W1 + mu] * fmaf(-th, th, 1.0f);
+                r[PG_TH + mu] = g * th;
+                r[PG_DZ + mu] = g * dz;
+#pragma unroll
+                for (int nu = 0; nu < DIM; ++nu) Fp[nu] = fmaf(dz, w[nu], Fp[nu]);
+            }
+#pragma unroll
+            for (int nu = 0; nu < DIM; ++nu) Fp[nu] *= P[P_QS + nu];
+#pragma unroll
+            for (int n = 0; n < NR; ++n) r[PG_FPR + n] = g * Fp[n];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) r[PG_F + k] = F[k];
+            // B = 2 (dU/dq_nl) s_{n,lm} in place of S
+#pragma unroll
+            for (int n = 0; n < NA; ++n)
+#pragma unroll
+                for (int lm = 0; lm < NLM; ++lm) {
+                    const int l = lm < 3 ? 1 : (lm < 8 ? 2 : (lm < 15 ? 3 : 4));
+                    S[n][lm] *= 2.0f * Fp[NR + NA * (l - 1) + n];
+                }
+            // G_nk = sum_j f_k(r_ij) sum_lm B_{n,lm} Y_lm(u_ij)
+            float G[NA][KB];
+#pragma unroll
+            for (int n = 0; n < NA; ++n)
+#pragma unroll
+                for (int k = 0; k < KB; ++k) G[n][k] = 0.0f;
+            for (int s = 0; s < naf + nab; ++s) {
+                const int32_t e = nl_ang[(size_t)list_slot(s, naf, nab, pc.capA) * pc.n + t];
+                int j;
+                double ddx, ddy, ddz;
+                pair_vector_d(e, pc, base, xi, yi, zi, xp, cg, j, ddx, ddy, ddz);
+                const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 >= pc.rc_ang2) continue;
+                const float rr = fsqrt(r2);
+                const float rinv = frcp(rr);
+                const float tt = scaled_minus_one(rr, pc.inv_rc_ang, pc.inv_rc_ang_lo);
+                float fc;
+                cutoff_value(tt, fc);
+                float T[KB];
+                cheb(fmaf(2.0f * tt, tt, -1.0f), T);
+                float Y[NLM];
+                sph(dx * rinv, dy * rinv, dz * rinv, Y);
+#pragma unroll
+                for (int n = 0; n < NA; ++n) {
+                    float D = 0.0f;
+#pragma unroll
+                    for (int lm = 0; lm < NLM; ++lm) D = fmaf(S[n][lm], Y[lm], D);
+                    const float hD = 0.5f * fc * D;      // f_k = (T_k + 1) fc / 2
+#pragma unroll
+                    for (int k = 0; k < KB; ++k) G[n][k] = fmaf(hD, T[k] + 1.0f, G[n][k]);
+                }
+            }
+#pragma unroll
+            for (int n = 0; n < NA; ++n)
+#pragma unroll
+                for (int k = 0; k < KB; ++k) r[PG_G + n * KB + k] = g * G[n][k];
+            r[PG_W] = g;
+        } else {
+            for (int k = 0; k < PG_REC; ++k) r[k] = 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NOWN; ++k) {
+            const int o = lane + PG_TILE * k;
+            if (o >= NPARAM) break;
+            int i1, i2 = -1;
+            float sign = 1.0f;
+            if (o < NR * KB) { i1 = PG_FPR + o / KB; i2 = PG_F + o % KB; }
+            else if (o < NR * KB + NA * KB) { i1 = PG_G + (o - NR * KB); }
+            else if (o < NR * KB + NA * KB + NH * DIM) {
+                const int p = o - NR * KB - NA * KB;
+                i1 = PG_DZ + p / DIM; i2 = PG_QT + p % DIM;
+            } else if (o < NR * KB + NA * KB + NH * DIM + NH) { i1 = PG_DZ + (o - (NPARAM - 1 - 2 * NH)); sign = -1.0f; }
+            else if (o < NPARAM - 1) { i1 = PG_TH + (o - (NPARAM - 1 - NH)); }
+            else { i1 = PG_W; sign = -1.0f; }
+            float sum = 0.0f;
+            if (i2 >= 0)
+                for (int a = 0; a < PG_TILE; ++a) sum = fmaf(rec[a][i1], rec[a][i2], sum);
+            else
+                for (int a = 0; a < PG_TILE; ++a) sum += rec[a][i1];
+            acc[k] += (double)(sign * sum);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < NOWN; ++k) {
+        const int o = lane + PG_TILE * k;
+        if (o < NPARAM) part[(size_t)blockIdx.x * NPARAM + o] = acc[k];
+    }
+}
+
+// grad[o] = sum over blocks of part[b][o], in block order.
+__global__ void k_param_reduce(int nblocks, const double *__restrict__ part, double *__restrict__ grad)
+{
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= NPARAM) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * NPARAM + o];
+    grad[o] = s;
+}
+
+// dL/dx_i = -gE[cell(i)] F_i (caller order, FP64).
+__global__ void k_grad_pos(int n, const int32_t *__restrict__ cell_of, const double *__restrict__ gE,
+                           const float *__restrict__ fx, const float *__restrict__ fy,
+                           const float *__restrict__ fz, double *__restrict__ gx, double *__restrict__ gy,
+                           double *__restrict__ gz)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double g = gE[cell_of[i]];
+    gx[i] = -g * fx[i];
+    gy[i] = -g * fy[i];
+    gz[i] = -g * fz[i];
+}
+
+// dL/dh of every cell at fixed Cartesian positions:
+//   dE/dh = h^-T (sum_i x_i (x) F_i - W^T),  times gE[c].
+// One block per cell (caller order; a cell's atoms are contiguous).
+__global__ __launch_bounds__(256) void k_grad_cell(const CellGeom *__restrict__ cells,
+                                                   const double *__restrict__ x, const double *__restrict__ y,
+                                                   const double *__restrict__ z, const float *__restrict__ fx,
+                                                   const float *__restrict__ fy, const float *__restrict__ fz,
+                                                   const double *__restrict__ virial,
+                                                   const double *__restrict__ gE, double *__restrict__ gh)
+{
+    __shared__ double sh[9][256];
+    const CellGeom &cg = cells[blockIdx.x];
+    double m[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) m[q] = 0.0;
+    for (int i = cg.atom_start + threadIdx.x; i < cg.atom_start + cg.n_atoms; i += 256) {
+        const double p[3] = {x[i], y[i], z[i]};
+        const double f[3] = {fx[i], fy[i], fz[i]};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) m[3 * a + b] += p[a] * f[b];
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sh[q][threadIdx.x] = m[q];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int q = 0; q < 9; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double *W = virial + (size_t)blockIdx.x * 9;
+        double A[9];   // M - W^T
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) A[3 * a + b] = sh[3 * a + b][0] - W[3 * b + a];
+        const double g = gE[blockIdx.x];
+        // (h^-T A)_ab = sum_c hinv[c][a] A[c][b]
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double v = 0.0;
+                for (int c = 0; c < 3; ++c) v += cg.hinv[3 * c + a] * A[3 * c + b];
+                gh[(size_t)blockIdx.x * 9 + 3 * a + b] = g * v;
+            }
+    }
 }
 
 // ------------------------------------------------------------------ reductions
@@ -540,7 +772,7 @@ __global__ void k_energy_atom_out(int n, const int32_t *__restrict__ perm,
 
 // Neighbour counts inside the cutoffs (diagnostics for flop accounting).
 __global__ __launch_bounds__(256) void k_count_inside(
-    PairConsts pc, const double4 *__restrict__ xp, const int32_t *__restrict__ cell_of,
+    PairConsts pc, const AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     unsigned long long *__restrict__ counts)
@@ -548,8 +780,7 @@ __global__ __launch_bounds__(256) void k_count_inside(
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long nr = 0, na = 0;
     if (t < pc.n) {
-        const double4 pi = xp[t];
-    const double xi = pi.x, yi = pi.y, zi = pi.z;
+        const double xi = xp[t].x, yi = xp[t].y, zi = xp[t].z;
         const CellGeom *cg = cells + cell_of[t];
         const uint32_t cnt = ncnt[t];
         const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;

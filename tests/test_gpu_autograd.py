@@ -1,0 +1,92 @@
+"""Differentiable energy: the library's backward against the FP64 oracle's
+analytic gradients (parameters, forces) and finite differences (cell)."""
+import numpy as np
+import pytest
+
+import nep_synth
+import oracle
+from gpu_common import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+# Parameter gradients are sums over atoms of FP32 products (relative rounding
+# ~1e-7 per term, FP64 sums across blocks); the network-weight components of
+# a small batch reach ~1e-6 relative, so the bar is 1e-5 per parameter group.
+P_REL_TOL = 1e-5
+
+
+def _subset(full, picks):
+    sizes = np.diff(full.cell_start)
+    pos = np.concatenate([full.cell(c)[0] for c in picks])
+    starts = np.concatenate([[0], np.cumsum([sizes[c] for c in picks])]).astype(np.int64)
+    return nep_synth.System(pos=pos, vel=np.zeros_like(pos), cell_start=starts, h=full.h[list(picks)].copy())
+
+
+def _energy_fn(m, s):
+    import torch
+    import paper_2305_08140_amd as nep
+    from paper_2305_08140_amd.autograd import nep_energy
+    ctx = nep.Context(m, s.n_atoms, s.n_cells)
+    pos = torch.tensor(s.pos, device="cuda", requires_grad=True)
+    cell = torch.tensor(s.h, device="cuda", requires_grad=True)
+    theta = torch.tensor(m.param_vector(), device="cuda", dtype=torch.float32, requires_grad=True)
+    q_scale = torch.tensor(m.q_scale, device="cuda", dtype=torch.float32)
+    E = nep_energy(ctx, pos, cell, theta, q_scale, cell_start=s.cell_start)
+    return E, pos, cell, theta, ctx
+
+
+def test_backward_matches_oracle_gradients():
+    import torch
+    m = nep_synth.random_model()
+    full = nep_synth.diffbatch()
+    s = _subset(full, range(0, 512, 32))
+    E, pos, cell, theta, _ = _energy_fn(m, s)
+    rng = np.random.default_rng(3)
+    gE = torch.tensor(rng.normal(size=s.n_cells), device="cuda")
+    (E * gE).sum().backward()
+    g_np = gE.cpu().numpy()
+    ref_E = np.zeros(s.n_cells)
+    ref_gp = np.zeros(theta.numel())
+    ref_gx = np.zeros((s.n_atoms, 3))
+    for c in range(s.n_cells):
+        a, b = int(s.cell_start[c]), int(s.cell_start[c + 1])
+        r = oracle.efv_cell(m, s.pos[a:b], s.h[c])
+        ref_E[c] = r["energy"]
+        ref_gx[a:b] = -g_np[c] * r["forces"]
+        ref_gp += g_np[c] * oracle.param_grad_cell(m, s.pos[a:b], s.h[c])
+    counts = np.diff(s.cell_start)
+    assert np.all(np.abs(E.detach().cpu().numpy() - ref_E) / counts <= 1e-6)
+    gx = pos.grad.cpu().numpy()
+    assert np.linalg.norm(gx - ref_gx) / np.linalg.norm(ref_gx) <= 1e-5
+    gp = theta.grad.double().cpu().numpy()
+    groups = {"c_rad": (0, 81), "c_ang": (81, 126), "w0": (126, 996), "b0": (996, 1026), "w1": (1026, 1056),
+              "b1": (1056, 1057)}
+    for name, (a, b) in groups.items():
+        err = np.linalg.norm(gp[a:b] - ref_gp[a:b]) / np.linalg.norm(ref_gp[a:b])
+        print(f"[param grad] {name}: rel err {err:.2e}", flush=True)
+        assert err <= P_REL_TOL, name
+
+
+def test_cell_gradient_matches_finite_differences():
+    import torch
+    m = nep_synth.random_model()
+    full = nep_synth.diffbatch()
+    s = _subset(full, [5, 40])
+    E, pos, cell, theta, _ = _energy_fn(m, s)
+    E.sum().backward()
+    gh = cell.grad.cpu().numpy()
+    for c in range(s.n_cells):
+        a, b = int(s.cell_start[c]), int(s.cell_start[c + 1])
+        p = s.pos[a:b]
+        fd = np.zeros((3, 3))
+        h = 1e-5
+        for i in range(3):
+            for j in range(3):
+                hp, hm = s.h[c].copy(), s.h[c].copy()
+                hp[i, j] += h
+                hm[i, j] -= h
+                fd[i, j] = (oracle.efv_cell(m, p, hp, virial=False)["energy"] -
+                            oracle.efv_cell(m, p, hm, virial=False)["energy"]) / (2 * h)
+        err = np.linalg.norm(gh[c] - fd) / np.linalg.norm(fd)
+        print(f"[cell grad] cell {c}: rel err {err:.2e}", flush=True)
+        assert err <= 1e-4
