@@ -158,6 +158,101 @@ def summarize_rocprof(kt_dir, fetch_dir, write_dir, n_atoms, command, out_dir):
         json.dump(out, f, indent=1)
 
 
+def _subset_system(full, picks):
+    import nep_synth
+    sizes = np.diff(full.cell_start)
+    pos = np.concatenate([full.cell(c)[0] for c in picks])
+    starts = np.concatenate([[0], np.cumsum([sizes[c] for c in picks])]).astype(np.int64)
+    return nep_synth.System(pos=pos, vel=np.zeros_like(pos), cell_start=starts, h=full.h[list(picks)].copy())
+
+
+def _timed(fn, reps, torch, stream=None):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def bench_batches(model, reps=20, n_percell=128):
+    """Batched evaluation of many small cells against per-cell launches.
+
+    batch:     4,096 cells of 8-512 atoms (log-uniform), vacancies, half strained
+               -> energy + forces + virial of all cells per evaluation
+    diffbatch: 512 cells of 16-256 atoms, +-3 % strain
+               -> energy, forces, virial and dE/dtheta (backward) per evaluation
+    The per-cell path evaluates a sample of n_percell cells one by one (each
+    with its own context, lists prebuilt, launches back to back, one sync)."""
+    import torch
+    import nep_synth
+    import oracle
+    import paper_2305_08140_amd as nep
+    out = {}
+    rng = np.random.default_rng(0)
+    for name in ("batch", "diffbatch"):
+        s = nep_synth.WORKLOADS[name]()
+        C_ = s.n_cells
+        sysd = nep.DeviceSystem.from_synth(s)
+        ctx = nep.Context(model, s.n_atoms, C_, check=False)
+        o = nep.EFV(s.n_atoms, C_)
+        ctx.nep_build_neighbors(sysd)
+        ctx.nep_compute_efv(sysd, o)
+        ctx.nep_status()
+        shapes = ctx.nep_autotune(sysd, o, reps=3)
+        gE = torch.ones(C_, dtype=torch.float64, device="cuda")
+        diff = name == "diffbatch"
+
+        def batched():
+            ctx.nep_compute_efv(sysd, o)
+            if diff:
+                ctx.nep_backward(sysd, o, gE, grad_pos=False, grad_cell=False)
+        t_b = _timed(batched, reps, torch)
+        res = {"n_cells": C_, "n_atoms": s.n_atoms, "launch_shapes": shapes,
+               "batched_cells_per_s": C_ / t_b, "batched_ms": t_b * 1e3}
+        if not diff:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                t_g = _timed(lambda: ctx.nep_compute_efv_graph(sysd, o, stream=st), reps, torch)
+            res["graph_cells_per_s"] = C_ / t_g
+            res["graph_ms"] = t_g * 1e3
+        ctx.nep_status()
+        # force error of sampled cells against FP64
+        F = o.forces().cpu().numpy().astype(np.float64)
+        num = den = 0.0
+        for c in rng.choice(C_, size=16, replace=False):
+            a, b = int(s.cell_start[c]), int(s.cell_start[c + 1])
+            r = oracle.efv_cell(model, s.pos[a:b], s.h[c], virial=False)
+            num += float(np.sum((F[a:b] - r["forces"]) ** 2))
+            den += float(np.sum(r["forces"] ** 2))
+        res["force_rel_err_vs_fp64"] = (num / den) ** 0.5
+        # per-cell path on a sample of cells
+        picks = rng.choice(C_, size=min(n_percell, C_), replace=False)
+        per = []
+        for c in picks:
+            sc = _subset_system(s, [int(c)])
+            d = nep.DeviceSystem.from_synth(sc)
+            cx = nep.Context(model, sc.n_atoms, 1, check=False)
+            oc = nep.EFV(sc.n_atoms, 1)
+            cx.nep_build_neighbors(d)
+            per.append((cx, d, oc))
+        g1 = torch.ones(1, dtype=torch.float64, device="cuda")
+
+        def percell():
+            for cx, d, oc in per:
+                cx.nep_compute_efv(d, oc)
+                if diff:
+                    cx.nep_backward(d, oc, g1, grad_pos=False, grad_cell=False)
+        t_p = _timed(percell, max(2, reps // 4), torch)
+        res["per_cell_cells_per_s"] = len(per) / t_p
+        res["speedup_vs_per_cell"] = res["batched_cells_per_s"] / res["per_cell_cells_per_s"]
+        out[name] = res
+        del per, ctx, sysd, o
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +260,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cells", type=int, default=160, help="conventional cells per edge")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batches", action="store_true", help="skip the batched small-cell workloads")
     ap.add_argument("--timing-reps", type=int, default=5)
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ summaries from rocprofv3 output directories and exit")
@@ -245,6 +341,12 @@ def main():
     ferr = float(np.linalg.norm(F_gpu[idx] - ref["forces"]) / np.linalg.norm(ref["forces"]))
     eerr = float(np.max(np.abs(out.energy_atom.cpu().numpy()[idx].astype(np.float64) - ref["energy_atom"])))
 
+    batches = None
+    if not args.no_batches:
+        del ctx, sysd, out
+        torch.cuda.empty_cache()
+        batches = bench_batches(model)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(model, s)
@@ -267,6 +369,7 @@ def main():
                           "force": f_force * N / (ktimes["force"] * 1e-3) / 1e12},
         "md": {"n_rebuilds": stats["n_rebuilds"], "dt_last_fs": stats["dt_last"], "time_fs": stats["time"]},
         "force_rel_err_vs_fp64": ferr, "site_energy_max_abs_err_eV": eerr,
+        "batches": batches,
     }
     print(json.dumps(line), flush=True)
 

@@ -174,6 +174,33 @@ int nep_required_neighbors(nep_ctx *ctx, int32_t *ang, int32_t *rad);
  * (synchronises `stream`); used for algorithmic-flop accounting. */
 int nep_mean_neighbors(nep_ctx *ctx, void *stream, double *mean_rad, double *mean_ang);
 
+/* Same evaluation as nep_compute_efv, replayed from a HIP graph: the first
+ * call (and any call whose system size, position or output pointers differ
+ * from the captured ones) captures the launch sequence on `stream` into a
+ * graph; later calls launch the graph.  `stream` must not be the NULL stream
+ * (capture is not allowed there).  Positions may change between calls by less
+ * than skin/2 as for nep_compute_efv.  Returns NEP_OK, NEP_E_ARG,
+ * NEP_E_STATE or NEP_E_HIP. */
+int nep_compute_efv_graph(nep_ctx *ctx, const nep_system *sys, nep_efv *out, void *stream);
+
+/* Autotune the launch shapes (threads per block 64/128/256, one block per
+ * atom tile or a persistent grid striding over tiles) of the descriptor and
+ * force kernels for `sys`: each candidate is timed `reps` times with HIP
+ * events on `stream`; the fastest pair is kept for this system size bucket
+ * (floor(log2 n_atoms)) and used by later evaluations in that bucket.
+ * shape_out (host int32[2], may be NULL) receives the chosen shape indices
+ * (0..2: 64/128/256 threads, one block per tile; 3..5: the same, persistent).
+ * Synchronises `stream`.  Same preconditions as nep_compute_efv. */
+int nep_autotune(nep_ctx *ctx, const nep_system *sys, nep_efv *out, int32_t reps, int32_t *shape_out,
+                 void *stream);
+
+/* Precision of the network's hidden layer in later evaluations:
+ *   0 (default) FP32 on the vector ALUs;
+ *   1 BF16 inputs on the matrix cores (v_mfma_f32_32x32x16_bf16) with FP32
+ *     accumulation, for the forward z = w0 s q and the backward dU/dq.
+ * Descriptors, forces and reductions are unaffected.  Returns NEP_OK or NEP_E_ARG. */
+int nep_set_precision(nep_ctx *ctx, int32_t mode);
+
 /* Number of trainable model parameters, theta = (c_rad, c_ang, w0, b0, w1, b1)
  * flattened row-major in that order (1057 for the compiled model). */
 int nep_num_params(const nep_ctx *ctx);

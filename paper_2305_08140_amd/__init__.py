@@ -31,7 +31,8 @@ NEP_E_INTERNAL = -9
 
 EXPORTED = ("nep_create", "nep_destroy", "nep_set_weights", "nep_build_neighbors", "nep_compute_efv",
             "nep_step_verlet", "nep_status", "nep_required_neighbors", "nep_mean_neighbors",
-            "nep_time_efv", "nep_num_params", "nep_backward", "nep_strerror")
+            "nep_time_efv", "nep_num_params", "nep_backward", "nep_compute_efv_graph", "nep_autotune",
+            "nep_set_precision", "nep_strerror")
 
 
 class NepError(RuntimeError):
@@ -102,6 +103,9 @@ def lib():
         L.nep_mean_neighbors.argtypes = [P, P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.nep_time_efv.argtypes = [P, C.POINTER(System), C.POINTER(Efv), C.c_int32, C.POINTER(C.c_double), P]
         L.nep_num_params.argtypes = [P]
+        L.nep_set_precision.argtypes = [P, C.c_int32]
+        L.nep_compute_efv_graph.argtypes = [P, C.POINTER(System), C.POINTER(Efv), P]
+        L.nep_autotune.argtypes = [P, C.POINTER(System), C.POINTER(Efv), C.c_int32, C.POINTER(C.c_int32), P]
         L.nep_backward.argtypes = [P, C.POINTER(System), C.POINTER(Efv), P, P, P, P, P, P, P]
         L.nep_strerror.argtypes = [C.c_int]
         L.nep_strerror.restype = C.c_char_p
@@ -282,6 +286,31 @@ class Context:
         _check(lib().nep_time_efv(self._ptr, C.byref(s), C.byref(o), int(reps), ms, _stream_ptr(stream)),
                "nep_time_efv")
         return {"sort": ms[0], "descriptor": ms[1], "force": ms[2], "reduce": ms[3]}
+
+    def nep_compute_efv_graph(self, system: DeviceSystem, out: EFV, stream=None):
+        """Graph-replayed evaluation; needs a non-default stream (e.g. torch.cuda.Stream())."""
+        s = system.c_struct()
+        o = out.c_struct()
+        _check(lib().nep_compute_efv_graph(self._ptr, C.byref(s), C.byref(o), _stream_ptr(stream)),
+               "nep_compute_efv_graph")
+        if self.check:
+            self.nep_status(stream)
+        return out
+
+    SHAPE_NAMES = ("64/tile", "128/tile", "256/tile", "64/persistent", "128/persistent", "256/persistent")
+
+    def nep_autotune(self, system: DeviceSystem, out: EFV, reps=3, stream=None):
+        """Pick the fastest launch shapes for this size; returns (descriptor, force) shape names."""
+        s = system.c_struct()
+        o = out.c_struct()
+        sh = (C.c_int32 * 2)()
+        _check(lib().nep_autotune(self._ptr, C.byref(s), C.byref(o), int(reps), sh, _stream_ptr(stream)),
+               "nep_autotune")
+        return self.SHAPE_NAMES[sh[0]], self.SHAPE_NAMES[sh[1]]
+
+    def nep_set_precision(self, mode):
+        """0: FP32 hidden layer (vector ALUs); 1: BF16 hidden layer on the matrix cores."""
+        _check(lib().nep_set_precision(self._ptr, int(mode)), "nep_set_precision")
 
     def nep_num_params(self):
         return int(lib().nep_num_params(self._ptr))

@@ -12,9 +12,11 @@
 
 namespace nep {
 // kernels (nep_kernels.hip)
+template <int BS, bool PE, int NNMODE>
 __global__ void k_descriptor(PairConsts, AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
                              const int32_t *, const uint32_t *, const float *, float4 *, float4 *, float *,
                              double *, int32_t *, int);
+template <int BS, bool PE>
 __global__ void k_force(PairConsts, const AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
                         const int32_t *, const uint32_t *, const uint8_t *, const float4 *, const float4 *,
                         const int32_t *, float *, float *, float *, float *, int32_t *, int);
@@ -109,6 +111,15 @@ struct nep_ctx {
     unsigned long long *counts = nullptr;
     double *pg_part = nullptr;       // parameter-gradient block partials
     int pg_blocks = 0;
+    // launch shapes of the two evaluation kernels (index into SHAPES), per
+    // size bucket floor(log2 n_atoms) once the autotuner has run
+    int shape_desc = 2, shape_force = 2;
+    int nn_mode = 0;                 // hidden layer: 0 FP32 vector ALU, 1 BF16 matrix cores
+    int tuned_desc[32], tuned_force[32];
+    // captured evaluation graph and the arguments it was captured with
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<uintptr_t> graph_key;
     int32_t *h_status = nullptr;     // pinned
     double *h_md = nullptr;          // pinned
     unsigned long long *h_counts = nullptr;
@@ -124,6 +135,14 @@ struct nep_ctx {
 };
 
 static int grid_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+
+static int bucket_of(int64_t n)
+{
+    int b = 0;
+    while ((int64_t(1) << (b + 1)) <= n && b < 31) ++b;
+    return b;
+}
+
 static int xcd_grid(int tiles) { return 8 * ((tiles + 7) / 8); }
 // grid of the streaming (grid-stride) kernels: enough blocks to fill the chip
 static int stream_grid(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 2048); }
@@ -172,6 +191,8 @@ void nep_destroy(nep_ctx *c)
     if (c->h_status) hipHostFree(c->h_status);
     if (c->h_md) hipHostFree(c->h_md);
     if (c->h_counts) hipHostFree(c->h_counts);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
     delete c;
 }
 
@@ -191,6 +212,7 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
         cfg->max_neigh_rad > 255 || !(cfg->skin >= 0.0))
         return NEP_E_ARG;
     nep_ctx *c = new nep_ctx();
+    for (int k = 0; k < 32; ++k) c->tuned_desc[k] = c->tuned_force[k] = -1;
     c->hp = *hp;
     c->cfg = *cfg;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return NEP_E_HIP; }
@@ -435,6 +457,11 @@ static int setup_system(nep_ctx *c, const nep_system *s, hipStream_t st)
     // the host vectors above are released on return: wait for the copies
     HIP_TRY(hipStreamSynchronize(st));
 
+    {
+        const int b = bucket_of(n);
+        c->shape_desc = c->tuned_desc[b] >= 0 ? c->tuned_desc[b] : 2;
+        c->shape_force = c->tuned_force[b] >= 0 ? c->tuned_force[b] : 2;
+    }
     c->built_n = n;
     c->built_cells = nc;
     c->built_h.assign(s->h, s->h + 9 * nc);
@@ -492,6 +519,79 @@ int nep_build_neighbors(nep_ctx *c, const nep_system *s, void *stream)
     return NEP_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------ launch shapes
+struct Shape {
+    int bs;
+    bool persistent;
+};
+static const Shape SHAPES[6] = {{64, false}, {128, false}, {256, false}, {64, true}, {128, true}, {256, true}};
+static const int N_SHAPES = 6;
+
+template <int BS, bool PE, int NNMODE>
+static void launch_desc_t(nep_ctx *c, hipStream_t st)
+{
+    const int n = c->pc.n, tiles = (n + BS - 1) / BS;
+    int grid = xcd_grid(tiles);
+    if (PE) {
+        int per_cu = 1;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_descriptor<BS, PE, NNMODE>, BS, 0);
+        grid = std::max(1, std::min(tiles, 256 * std::max(per_cu, 1)));
+    }
+    k_descriptor<BS, PE, NNMODE><<<grid, BS, 0, st>>>(c->pc, c->xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
+                                                      c->ncnt, c->params, c->pair_grad, c->f_own, c->w_atom,
+                                                      c->e_atom, c->status, tiles);
+}
+
+template <int BS, bool PE>
+static void launch_desc_m(nep_ctx *c, hipStream_t st)
+{
+    if (c->nn_mode == 1) launch_desc_t<BS, PE, 1>(c, st);
+    else launch_desc_t<BS, PE, 0>(c, st);
+}
+
+template <int BS, bool PE>
+static void launch_force_t(nep_ctx *c, const nep_efv *o, hipStream_t st)
+{
+    const int n = c->pc.n, tiles = (n + BS - 1) / BS;
+    int grid = xcd_grid(tiles);
+    if (PE) {
+        int per_cu = 1;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_force<BS, PE>, BS, 0);
+        grid = std::max(1, std::min(tiles, 256 * std::max(per_cu, 1)));
+    }
+    k_force<BS, PE><<<grid, BS, 0, st>>>(c->pc, c->xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->rev,
+                                         c->pair_grad, c->f_own, c->perm, o->fx, o->fy, o->fz, c->w_atom, c->status,
+                                         tiles);
+}
+
+static void launch_desc(nep_ctx *c, int shape, hipStream_t st)
+{
+    switch (shape) {
+    case 0: launch_desc_m<64, false>(c, st); break;
+    case 1: launch_desc_m<128, false>(c, st); break;
+    case 3: launch_desc_m<64, true>(c, st); break;
+    case 4: launch_desc_m<128, true>(c, st); break;
+    case 5: launch_desc_m<256, true>(c, st); break;
+    default: launch_desc_m<256, false>(c, st); break;
+    }
+}
+
+static void launch_force(nep_ctx *c, int shape, const nep_efv *o, hipStream_t st)
+{
+    switch (shape) {
+    case 0: launch_force_t<64, false>(c, o, st); break;
+    case 1: launch_force_t<128, false>(c, o, st); break;
+    case 3: launch_force_t<64, true>(c, o, st); break;
+    case 4: launch_force_t<128, true>(c, o, st); break;
+    case 5: launch_force_t<256, true>(c, o, st); break;
+    default: launch_force_t<256, false>(c, o, st); break;
+    }
+}
+
+extern "C" {
+
 // One evaluation: sorted positions, descriptor + network, forces, reductions.
 static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t st, bool refresh_positions)
 {
@@ -500,13 +600,8 @@ static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t s
     if (refresh_positions)
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
                                                            c->cells, xp, c->status);
-    const int tiles = grid_for(n, 256);
-    k_descriptor<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
-                                                  c->ncnt, c->params, c->pair_grad, c->f_own, c->w_atom,
-                                                  c->e_atom, c->status, tiles);
-    k_force<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
-                                             c->ncnt, c->rev, c->pair_grad, c->f_own, c->perm, o->fx, o->fy,
-                                             o->fz, c->w_atom, c->status, tiles);
+    launch_desc(c, c->shape_desc, st);
+    launch_force(c, c->shape_force, o, st);
     k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom, c->part,
                                                  c->status);
     k_reduce_cells<<<c->built_cells, 256, 0, st>>>(c->built_cells, c->cell_chunk, c->part,
@@ -543,7 +638,6 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)s->n_atoms;
     AtomRec *xp = c->xp;
-    const int tiles = grid_for(n, 256);
     hipEvent_t ev[5];
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     double acc[4] = {0, 0, 0, 0};
@@ -552,13 +646,9 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
                                                            c->cells, xp, c->status);
         HIP_TRY(hipEventRecord(ev[1], st));
-        k_descriptor<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xp, c->cell_of, c->cells, c->nl_ang,
-                                                      c->nl_rad, c->ncnt, c->params, c->pair_grad,
-                                                      c->f_own, c->w_atom, c->e_atom, c->status, tiles);
+        launch_desc(c, c->shape_desc, st);
         HIP_TRY(hipEventRecord(ev[2], st));
-        k_force<<<xcd_grid(tiles), 256, 0, st>>>(c->pc, xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
-                                                 c->ncnt, c->rev, c->pair_grad, c->f_own, c->perm, o->fx,
-                                                 o->fy, o->fz, c->w_atom, c->status, tiles);
+        launch_force(c, c->shape_force, o, st);
         HIP_TRY(hipEventRecord(ev[3], st));
         k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom,
                                                      c->part, c->status);
@@ -579,6 +669,13 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
 }
 
 static constexpr int N_PARAMS = NR * KB + NA * KB + NH * DIM + NH + NH + 1;
+
+int nep_set_precision(nep_ctx *c, int32_t mode)
+{
+    if (!c || mode < 0 || mode > 1) return NEP_E_ARG;
+    c->nn_mode = mode;
+    return NEP_OK;
+}
 
 int nep_num_params(const nep_ctx *c)
 {
@@ -616,6 +713,84 @@ int nep_backward(nep_ctx *c, const nep_system *s, const nep_efv *o, const double
         k_grad_cell<<<c->built_cells, 256, 0, st>>>(c->cells, s->x, s->y, s->z, o->fx, o->fy, o->fz, o->virial,
                                                     gE, gh);
     HIP_TRY(hipGetLastError());
+    return NEP_OK;
+}
+
+int nep_autotune(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, int32_t *shape_out, void *stream)
+{
+    if (!c || reps <= 0) return NEP_E_ARG;
+    int rc = check_system(c, s, false);
+    if (rc) return rc;
+    if ((rc = check_out(o))) return rc;
+    if (!same_system(c, s)) return NEP_E_STATE;
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)s->n_atoms;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
+                                                       c->cells, c->xp, c->status);
+    auto time_it = [&](auto &&launch) -> float {
+        launch();   // warm-up
+        HIP_TRY(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) launch();
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        return ms;
+    };
+    int best_d = 2, best_f = 2;
+    float t_best = 1e30f;
+    for (int k = 0; k < N_SHAPES; ++k) {
+        const float t = time_it([&] { launch_desc(c, k, st); });
+        if (t < t_best) { t_best = t; best_d = k; }
+    }
+    launch_desc(c, best_d, st);
+    t_best = 1e30f;
+    for (int k = 0; k < N_SHAPES; ++k) {
+        const float t = time_it([&] { launch_force(c, k, o, st); });
+        if (t < t_best) { t_best = t; best_f = k; }
+    }
+    HIP_TRY(hipEventDestroy(e0));
+    HIP_TRY(hipEventDestroy(e1));
+    HIP_TRY(hipGetLastError());
+    const int b = bucket_of(n);
+    c->tuned_desc[b] = c->shape_desc = best_d;
+    c->tuned_force[b] = c->shape_force = best_f;
+    if (shape_out) { shape_out[0] = best_d; shape_out[1] = best_f; }
+    return NEP_OK;
+}
+
+int nep_compute_efv_graph(nep_ctx *c, const nep_system *s, nep_efv *o, void *stream)
+{
+    if (!c || !stream) return NEP_E_ARG;
+    int rc = check_system(c, s, false);
+    if (rc) return rc;
+    if ((rc = check_out(o))) return rc;
+    if (!same_system(c, s)) return NEP_E_STATE;
+    hipStream_t st = (hipStream_t)stream;
+    const std::vector<uintptr_t> key = {
+        (uintptr_t)s->n_atoms, (uintptr_t)s->x, (uintptr_t)s->y, (uintptr_t)s->z, (uintptr_t)o->energy,
+        (uintptr_t)o->fx, (uintptr_t)o->fy, (uintptr_t)o->fz, (uintptr_t)o->virial, (uintptr_t)o->energy_atom,
+        (uintptr_t)c->shape_desc, (uintptr_t)c->shape_force, (uintptr_t)c->n_chunks, (uintptr_t)c->built_cells,
+        (uintptr_t)c->nn_mode};
+    if (!c->graph_exec || key != c->graph_key) {
+        if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+        if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const int lrc = launch_efv(c, s, o, st, true);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(st, &g);
+        if (lrc != NEP_OK || ec != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return lrc != NEP_OK ? lrc : NEP_E_HIP;
+        }
+        c->graph = g;
+        HIP_TRY(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+        c->graph_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(c->graph_exec, st));
     return NEP_OK;
 }
 

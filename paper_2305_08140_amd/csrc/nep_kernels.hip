@@ -229,6 +229,90 @@ __device__ __forceinline__ void angular_coef_sums(const float *__restrict__ P, f
     }
 }
 
+// ------------------------------------------------------------------ MFMA hidden layer (BF16)
+// The hidden layer of a whole wavefront (64 atoms) as matrix products on the
+// matrix cores, BF16 inputs with FP32 accumulation:
+//   forward   Z^T  [32 x 64] = W0 [32 x 32] . Qs^T [32 x 64]     (Qs = scaled descriptors)
+//   backward  Fp^T [32 x 64] = W0^T [32 x 32] . dZ^T [32 x 64]   (dZ = dU/dz)
+// with v_mfma_f32_32x32x16_bf16 (two 32-atom column tiles, two K steps each).
+// Operand layouts (lane l, v = 0..7 / 0..15):  A[l%32][8(l/32)+v],
+// B[8(l/32)+v][l%32], D[8(v/4)+4(l/32)+v%4][l%32].  Rows of the padded
+// 32 x 32 weight (30 neurons x 29 descriptors) beyond the model are zero.
+// Each lane owns one atom; the operands are exchanged through a per-wave LDS
+// area (a wave's LDS accesses complete in program order).
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+struct NNLds {
+    __bf16 q[64][40];    // rows of 32 used; stride 80 B keeps 16 B alignment
+    float z[64][33];
+};
+
+__device__ __forceinline__ float network_mfma(const float *__restrict__ P, const float q[DIM], float Fp[DIM],
+                                              NNLds *L)
+{
+    const int lane = threadIdx.x & 63;
+    const int hi = lane >> 5, lo = lane & 31;
+    // own scaled descriptor row
+#pragma unroll
+    for (int nu = 0; nu < 32; ++nu) L->q[lane][nu] = (__bf16)(nu < DIM ? P[P_QS + nu] * q[nu] : 0.0f);
+    // weight operands: forward A[mu = lo][nu = 16 s + 8 hi + v], backward A[nu = lo][mu = 16 s + 8 hi + v]
+    bf16x8 wf[2], wb[2];
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int k = 16 * st + 8 * hi + v;
+            wf[st][v] = (__bf16)((lo < NH && k < DIM) ? P[P_W0 + lo * DIM + k] : 0.0f);
+            wb[st][v] = (__bf16)((k < NH && lo < DIM) ? P[P_W0 + k * DIM + lo] : 0.0f);
+        }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int T = 0; T < 2; ++T) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&L->q[32 * T + lo][16 * st + 8 * hi]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[st], b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) L->z[32 * T + lo][8 * (v >> 2) + 4 * hi + (v & 3)] = acc[v];
+    }
+    __builtin_amdgcn_wave_barrier();
+    float U = -P[P_B1];
+    float dz[32];
+#pragma unroll
+    for (int mu = 0; mu < 32; ++mu) {
+        if (mu < NH) {
+            const float th = ftanh(L->z[lane][mu] - P[P_B0 + mu]);
+            U = fmaf(P[P_W1 + mu], th, U);
+            dz[mu] = P[P_W1 + mu] * fmaf(-th, th, 1.0f);
+        } else {
+            dz[mu] = 0.0f;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int mu = 0; mu < 32; ++mu) L->q[lane][mu] = (__bf16)dz[mu];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int T = 0; T < 2; ++T) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&L->q[32 * T + lo][16 * st + 8 * hi]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wb[st], b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) L->z[32 * T + lo][8 * (v >> 2) + 4 * hi + (v & 3)] = acc[v];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int nu = 0; nu < DIM; ++nu) Fp[nu] = L->z[lane][nu] * P[P_QS + nu];
+    __builtin_amdgcn_wave_barrier();
+    return U;
+}
+
 // Descriptor, site energy, network forward and backward, the radial adjoint
 // dU_i/dF_k (stored in the atom's record), and then, with
 // B_{n,lm} = dU_i/ds_{n,lm} kept in registers, the gradient of U_i with
@@ -236,24 +320,22 @@ __device__ __forceinline__ void angular_coef_sums(const float *__restrict__ P, f
 // stored per list slot (the force kernel subtracts them at the other end of
 // the pair), their sum is this atom's own angular force term, and
 // -sum_j dU_i/dr_ij (x) r_ij is its angular virial.
-__global__ __launch_bounds__(256) void k_descriptor(
-    PairConsts pc, AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
-    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
+template <int NNMODE>
+__device__ __forceinline__ void descriptor_atom(
+    int t, bool valid, NNLds *L, const PairConsts &pc, AtomRec *__restrict__ xp,
+    const int32_t *__restrict__ cell_of, const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     const float *__restrict__ P, float4 *__restrict__ pair_grad,
     float4 *__restrict__ f_own, float *__restrict__ w_atom, double *__restrict__ e_atom,
-    int32_t *__restrict__ status, int ntiles)
+    int32_t *__restrict__ status)
 {
-    const int tile = xcd_block(ntiles);
-    if (tile >= ntiles) return;
-    const int t = tile * 256 + threadIdx.x;
-    if (t >= pc.n) return;
-    if (status[ST_ERR] != 0) return;
-
+    // With the MFMA hidden layer every lane of a wave takes part; lanes past
+    // the last atom compute on an empty neighbourhood of atom 0 and store nothing.
+    if (!valid) t = 0;
     const double xi = xp[t].x, yi = xp[t].y, zi = xp[t].z;
     const CellGeom *cg = cells + cell_of[t];
     const int base = cg->atom_start;
-    const uint32_t cnt = ncnt[t];
+    const uint32_t cnt = valid ? ncnt[t] : 0u;
     const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
     const int nA = naf + nab;
 
@@ -269,7 +351,8 @@ __global__ __launch_bounds__(256) void k_descriptor(
     float q[DIM];
     descriptor_vector(P, F, S, q);
     float Fp[DIM];
-    const float U = network(P, q, Fp);
+    const float U = NNMODE == 1 ? network_mfma(P, q, Fp, L) : network(P, q, Fp);
+    if (!valid) return;
     e_atom[t] = (double)U + ezbl;
     // radial adjoint a_k = dU_i / dF_k, into this atom's record
 #pragma unroll
@@ -360,6 +443,38 @@ __global__ __launch_bounds__(256) void k_descriptor(
     for (int k = 0; k < 9; ++k) w[k] = -W[k];
 }
 
+// Launch shapes: BS threads per block; PERSISTENT = a fixed grid whose blocks
+// stride over the atom tiles (chosen per size bucket by the autotuner),
+// otherwise one block per tile in XCD-aware order.  NNMODE 0: hidden layer on
+// the vector ALUs in FP32; 1: on the matrix cores in BF16 (FP32 accumulation).
+template <int BS, bool PERSISTENT, int NNMODE>
+__global__ __launch_bounds__(BS, NNMODE == 1 ? 1 : 2) void k_descriptor(
+    PairConsts pc, AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
+    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
+    const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
+    const float *__restrict__ P, float4 *__restrict__ pair_grad,
+    float4 *__restrict__ f_own, float *__restrict__ w_atom, double *__restrict__ e_atom,
+    int32_t *__restrict__ status, int ntiles)
+{
+    __shared__ NNLds lds[NNMODE == 1 ? BS / 64 : 1];
+    NNLds *L = &lds[NNMODE == 1 ? threadIdx.x / 64 : 0];
+    if (status[ST_ERR] != 0) return;
+    if (PERSISTENT) {
+        for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+            const int t = tile * BS + threadIdx.x;
+            if (NNMODE == 1 || t < pc.n)
+                descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, pair_grad,
+                                        f_own, w_atom, e_atom, status);
+        }
+    } else {
+        const int tile = xcd_block(ntiles);
+        const int t = tile * BS + threadIdx.x;
+        if (tile < ntiles && (NNMODE == 1 || t < pc.n))
+            descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, pair_grad,
+                                    f_own, w_atom, e_atom, status);
+    }
+}
+
 // ------------------------------------------------------------------ forces + virial
 
 // F_i = sum_j (a^i + a^j) . f'(r_ij) u_ij + U'_ZBL(r_ij) u_ij        (radial + ZBL)
@@ -367,20 +482,14 @@ __global__ __launch_bounds__(256) void k_descriptor(
 // and the radial + ZBL virial -1/2 sum_j f_ij (x) r_ij added to the angular one.
 // Each neighbour costs one 64-byte record gather (position and adjoint) and,
 // for angular entries, one 16-byte pair-gradient gather.
-__global__ __launch_bounds__(256) void k_force(
-    PairConsts pc, const AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
+__device__ __forceinline__ void force_atom(
+    int t, const PairConsts &pc, const AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     const uint8_t *__restrict__ rev, const float4 *__restrict__ pair_grad, const float4 *__restrict__ f_own,
     const int32_t *__restrict__ perm, float *__restrict__ fx, float *__restrict__ fy,
-    float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status, int ntiles)
+    float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status)
 {
-    const int tile = xcd_block(ntiles);
-    if (tile >= ntiles) return;
-    const int t = tile * 256 + threadIdx.x;
-    if (t >= pc.n) return;
-    if (status[ST_ERR] != 0) return;
-
     const double xi = xp[t].x, yi = xp[t].y, zi = xp[t].z;
     const CellGeom *cg = cells + cell_of[t];
     const int base = cg->atom_start;
@@ -467,6 +576,50 @@ __global__ __launch_bounds__(256) void k_force(
 #pragma unroll
     for (int k = 0; k < 9; ++k) w[k] = fmaf(-0.5f, W[k], w[k]);
 }
+
+template <int BS, bool PERSISTENT>
+__global__ __launch_bounds__(BS) void k_force(
+    PairConsts pc, const AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
+    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
+    const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
+    const uint8_t *__restrict__ rev, const float4 *__restrict__ pair_grad, const float4 *__restrict__ f_own,
+    const int32_t *__restrict__ perm, float *__restrict__ fx, float *__restrict__ fy,
+    float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status, int ntiles)
+{
+    if (status[ST_ERR] != 0) return;
+    if (PERSISTENT) {
+        for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+            const int t = tile * BS + threadIdx.x;
+            if (t < pc.n)
+                force_atom(t, pc, xp, cell_of, cells, nl_ang, nl_rad, ncnt, rev, pair_grad, f_own, perm, fx, fy, fz,
+                           w_atom, status);
+        }
+    } else {
+        const int tile = xcd_block(ntiles);
+        const int t = tile * BS + threadIdx.x;
+        if (tile < ntiles && t < pc.n)
+            force_atom(t, pc, xp, cell_of, cells, nl_ang, nl_rad, ncnt, rev, pair_grad, f_own, perm, fx, fy, fz,
+                       w_atom, status);
+    }
+}
+
+// Instantiated launch shapes.
+#define NEP_SHAPES(X) X(64, false) X(128, false) X(256, false) X(64, true) X(128, true) X(256, true)
+#define NEP_INST(BS, PE)                                                                                           \
+    template __global__ void k_descriptor<BS, PE, 0>(PairConsts, AtomRec *, const int32_t *, const CellGeom *,     \
+                                                     const int32_t *, const int32_t *, const uint32_t *,           \
+                                                     const float *, float4 *, float4 *, float *, double *, int32_t *, \
+                                                     int);                                                           \
+    template __global__ void k_descriptor<BS, PE, 1>(PairConsts, AtomRec *, const int32_t *, const CellGeom *,     \
+                                                     const int32_t *, const int32_t *, const uint32_t *,           \
+                                                     const float *, float4 *, float4 *, float *, double *, int32_t *, \
+                                                     int);                                                           \
+    template __global__ void k_force<BS, PE>(PairConsts, const AtomRec *, const int32_t *, const CellGeom *,       \
+                                             const int32_t *, const int32_t *, const uint32_t *, const uint8_t *,   \
+                                             const float4 *, const float4 *, const int32_t *, float *, float *,      \
+                                             float *, float *, int32_t *, int);
+NEP_SHAPES(NEP_INST)
+#undef NEP_INST
 
 // ------------------------------------------------------------------ parameter gradients
 
