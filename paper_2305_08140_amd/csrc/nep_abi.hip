@@ -13,7 +13,7 @@
 namespace nep {
 // kernels (nep_kernels.hip)
 template <int BS, bool PE, int NNMODE>
-__global__ void k_descriptor(PairConsts, AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
+__global__ void k_descriptor(PairConsts, const double4 *, AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
                              const int32_t *, const uint32_t *, const float *, float4 *, float4 *, float *,
                              double *, int32_t *, int);
 template <int BS, bool PE>
@@ -24,7 +24,7 @@ __global__ void k_reduce_chunks(const int32_t *, const int32_t *, const double *
                                 const int32_t *);
 __global__ void k_reduce_cells(int, const int32_t *, const double *, double *, double *, const int32_t *);
 __global__ void k_energy_atom_out(int, const int32_t *, const double *, float *);
-__global__ void k_param_grad(PairConsts, const AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
+__global__ void k_param_grad(PairConsts, const double4 *, const int32_t *, const CellGeom *, const int32_t *,
                              const int32_t *, const uint32_t *, const float *, const double *, double *,
                              const int32_t *, int);
 __global__ void k_param_reduce(int, const double *, double *);
@@ -32,7 +32,7 @@ __global__ void k_grad_pos(int, const int32_t *, const double *, const float *, 
                            double *, double *, double *);
 __global__ void k_grad_cell(const CellGeom *, const double *, const double *, const double *, const float *,
                             const float *, const float *, const double *, const double *, double *);
-__global__ void k_count_inside(PairConsts, const AtomRec *, const int32_t *,
+__global__ void k_count_inside(PairConsts, const double4 *, const int32_t *,
                                const CellGeom *, const int32_t *, const int32_t *, const uint32_t *,
                                unsigned long long *);
 // kernels (nep_build.hip)
@@ -47,8 +47,8 @@ __global__ void k_bin_scatter(int, const int32_t *, const int32_t *, int32_t *, 
 __global__ void k_bin_rank(int, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
                            const CellGeom *, int32_t *, int32_t *, const int32_t *, const int32_t *);
 __global__ void k_sort_positions(int, const int32_t *, const double *, const double *, const double *,
-                                 const int32_t *, const int32_t *, const CellGeom *, AtomRec *, int32_t *);
-__global__ void k_build_lists(PairConsts, double, double, double, double, const AtomRec *, const int32_t *,
+                                 const int32_t *, const int32_t *, const CellGeom *, double4 *, int32_t *);
+__global__ void k_build_lists(PairConsts, double, double, double, double, const double4 *, const int32_t *,
                               const CellGeom *, const int32_t *, const int32_t *, const int32_t *, int32_t *,
                               int32_t *, uint32_t *, int32_t *, const int32_t *);
 __global__ void k_build_reverse(PairConsts, const int32_t *, const CellGeom *, const int32_t *,
@@ -83,6 +83,7 @@ struct nep_ctx {
     float *params = nullptr;
     // per-atom storage (capacity cfg.max_atoms)
     AtomRec *xp = nullptr;       // [N] sorted wrapped positions and radial adjoints
+    double4 *xq = nullptr;       // [N] sorted wrapped positions, compact copy
     double *xref = nullptr;      // [3][N] caller-order positions at the last build
     int32_t *perm = nullptr, *bin_of = nullptr, *wrap = nullptr, *cell_of = nullptr, *tmp = nullptr,
             *bin_sorted = nullptr;
@@ -178,19 +179,19 @@ const char *nep_strerror(int code)
 void nep_destroy(nep_ctx *c)
 {
     if (!c) return;
-    hipSetDevice(c->device);
-    hipDeviceSynchronize();
-    void *bufs[] = {c->params, c->xp, c->xref, c->bin_rank, c->bin_lin, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    void *bufs[] = {c->params, c->xp, c->xq, c->xref, c->bin_rank, c->bin_lin, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
                     c->bin_sorted, c->ncnt, c->nl_ang, c->nl_rad, c->pair_grad, c->f_own, c->rev,
                     c->w_atom,
                     c->e_atom, c->cells, c->cell_start_d, c->chunk_begin, c->chunk_end, c->cell_chunk,
                     c->part, c->bin_count, c->bin_start, c->bin_fill, c->scan_sums, c->status, c->flag,
                     c->md, c->counts, c->pg_part};
     for (void *p : bufs)
-        if (p) hipFree(p);
-    if (c->h_status) hipHostFree(c->h_status);
-    if (c->h_md) hipHostFree(c->h_md);
-    if (c->h_counts) hipHostFree(c->h_counts);
+        if (p) (void)hipFree(p);
+    if (c->h_status) (void)hipHostFree(c->h_status);
+    if (c->h_md) (void)hipHostFree(c->h_md);
+    if (c->h_counts) (void)hipHostFree(c->h_counts);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     delete c;
@@ -223,6 +224,7 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     };
     A((void **)&c->params, P_SIZE * sizeof(float));
     A((void **)&c->xp, N * sizeof(AtomRec));
+    A((void **)&c->xq, N * sizeof(double4));
     A((void **)&c->xref, 3 * N * sizeof(double));
     A((void **)&c->perm, N * 4);
     A((void **)&c->bin_of, N * 4);
@@ -360,6 +362,8 @@ static int setup_system(nep_ctx *c, const nep_system *s, hipStream_t st)
     pc.rc_ang = (float)c->hp.rc_ang;
     pc.rc_rad2 = pc.rc_rad * pc.rc_rad;
     pc.rc_ang2 = pc.rc_ang * pc.rc_ang;
+    pc.rc_ang2_write = pc.rc_ang2 * (1.0f + 0x1p-16f);
+    pc.rc_ang2_read = pc.rc_ang2 * (1.0f + 0x1p-17f);
     pc.inv_rc_rad = (float)(1.0 / c->hp.rc_rad);
     pc.inv_rc_ang = (float)(1.0 / c->hp.rc_ang);
     pc.inv_rc_rad_lo = (float)(1.0 / c->hp.rc_rad - (double)pc.inv_rc_rad);
@@ -436,7 +440,11 @@ static int setup_system(nep_ctx *c, const nep_system *s, hipStream_t st)
     cc[nc] = (int32_t)cb.size();
     const int nch = (int)cb.size();
     if (nch > c->chunk_cap) {
-        if (c->chunk_begin) { hipFree(c->chunk_begin); hipFree(c->chunk_end); hipFree(c->part); }
+        if (c->chunk_begin) {
+            (void)hipFree(c->chunk_begin);
+            (void)hipFree(c->chunk_end);
+            (void)hipFree(c->part);
+        }
         c->chunk_begin = c->chunk_end = nullptr;
         c->part = nullptr;
         HIP_TRY(hipMalloc(&c->chunk_begin, nch * 4));
@@ -490,10 +498,10 @@ static int launch_build(nep_ctx *c, const nep_system *s, hipStream_t st, const i
     // sorted positions are needed by the list build; unconditional is fine
     // (every evaluation refreshes them anyway)
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                       c->cells, c->xp, c->status);
+                                                       c->cells, c->xq, c->status);
     const double lA = c->hp.rc_ang + c->cfg.skin, lR = c->hp.rc_rad + c->cfg.skin;
     k_build_lists<<<grid_for(n, 256), 256, 0, st>>>(
-        c->pc, lA * lA, lR * lR, c->hp.rc_ang * c->hp.rc_ang, c->hp.rc_rad * c->hp.rc_rad, c->xp, c->cell_of,
+        c->pc, lA * lA, lR * lR, c->hp.rc_ang * c->hp.rc_ang, c->hp.rc_rad * c->hp.rc_rad, c->xq, c->cell_of,
         c->cells, c->bin_sorted, c->bin_start, c->bin_rank, c->nl_ang, c->nl_rad, c->ncnt, c->status, flag);
     k_build_reverse<<<grid_for(n, 256), 256, 0, st>>>(c->pc, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->rev,
                                                       c->status, flag);
@@ -539,7 +547,7 @@ static void launch_desc_t(nep_ctx *c, hipStream_t st)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_descriptor<BS, PE, NNMODE>, BS, 0);
         grid = std::max(1, std::min(tiles, 256 * std::max(per_cu, 1)));
     }
-    k_descriptor<BS, PE, NNMODE><<<grid, BS, 0, st>>>(c->pc, c->xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
+    k_descriptor<BS, PE, NNMODE><<<grid, BS, 0, st>>>(c->pc, c->xq, c->xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
                                                       c->ncnt, c->params, c->pair_grad, c->f_own, c->w_atom,
                                                       c->e_atom, c->status, tiles);
 }
@@ -596,10 +604,9 @@ extern "C" {
 static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t st, bool refresh_positions)
 {
     const int n = (int)s->n_atoms;
-    AtomRec *xp = c->xp;
     if (refresh_positions)
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                           c->cells, xp, c->status);
+                                                           c->cells, c->xq, c->status);
     launch_desc(c, c->shape_desc, st);
     launch_force(c, c->shape_force, o, st);
     k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom, c->part,
@@ -637,14 +644,13 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
     if (!same_system(c, s)) return NEP_E_STATE;
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)s->n_atoms;
-    AtomRec *xp = c->xp;
     hipEvent_t ev[5];
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     double acc[4] = {0, 0, 0, 0};
     for (int r = 0; r < reps; ++r) {
         HIP_TRY(hipEventRecord(ev[0], st));
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                           c->cells, xp, c->status);
+                                                           c->cells, c->xq, c->status);
         HIP_TRY(hipEventRecord(ev[1], st));
         launch_desc(c, c->shape_desc, st);
         HIP_TRY(hipEventRecord(ev[2], st));
@@ -704,8 +710,8 @@ int nep_backward(nep_ctx *c, const nep_system *s, const nep_efv *o, const double
         c->pg_blocks = blocks;
     }
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                       c->cells, c->xp, c->status);
-    k_param_grad<<<blocks, 64, 0, st>>>(c->pc, c->xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
+                                                       c->cells, c->xq, c->status);
+    k_param_grad<<<blocks, 64, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
                                         c->params, gE, c->pg_part, c->status, tiles);
     k_param_reduce<<<grid_for(N_PARAMS, 256), 256, 0, st>>>(blocks, c->pg_part, grad_params);
     if (gx) k_grad_pos<<<grid_for(n, 256), 256, 0, st>>>(n, c->cell_of, gE, o->fx, o->fy, o->fz, gx, gy, gz);
@@ -729,7 +735,7 @@ int nep_autotune(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, int3
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                       c->cells, c->xp, c->status);
+                                                       c->cells, c->xq, c->status);
     auto time_it = [&](auto &&launch) -> float {
         launch();   // warm-up
         HIP_TRY(hipEventRecord(e0, st));
@@ -824,7 +830,7 @@ int nep_mean_neighbors(nep_ctx *c, void *stream, double *mean_rad, double *mean_
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(hipMemsetAsync(c->counts, 0, 16, st));
     const int n = c->pc.n;
-    k_count_inside<<<grid_for(n, 256), 256, 0, st>>>(c->pc, c->xp, c->cell_of, c->cells,
+    k_count_inside<<<grid_for(n, 256), 256, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells,
                                                      c->nl_ang, c->nl_rad, c->ncnt, c->counts);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(c->h_counts, c->counts, 16, hipMemcpyDeviceToHost, st));

@@ -190,13 +190,14 @@ __global__ void k_bin_rank(int n, const int32_t *__restrict__ bin_of,
     bin_sorted[b0 + rank] = bin_lin[b];   // x-fastest linear index of the bin within its cell
 }
 
-// Wrapped positions in sorted order: xs[t] = x[perm[t]] - w . h.  Runs at
-// every evaluation; non-finite positions latch NEP_E_NONFINITE.
+// Wrapped positions in sorted order: xq[t] = x[perm[t]] - w . h, 32-byte
+// records (four atoms per 128-byte line).  Runs at every evaluation;
+// non-finite positions latch NEP_E_NONFINITE.
 __global__ void k_sort_positions(int n, const int32_t *__restrict__ perm,
                                  const double *__restrict__ x, const double *__restrict__ y,
                                  const double *__restrict__ z, const int32_t *__restrict__ wrap,
                                  const int32_t *__restrict__ cell_of,
-                                 const CellGeom *__restrict__ cells, AtomRec *__restrict__ xp,
+                                 const CellGeom *__restrict__ cells, double4 *__restrict__ xq,
                                  int32_t *__restrict__ status)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -207,14 +208,15 @@ __global__ void k_sort_positions(int n, const int32_t *__restrict__ perm,
     const double *h = cells[cell_of[t]].h;
     const double px = x[i], py = y[i], pz = z[i];
     if (!isfinite(px) || !isfinite(py) || !isfinite(pz)) latch_error(status, -5);
-    xp[t].x = px - (w0 * h[0] + w1 * h[3] + w2 * h[6]);
-    xp[t].y = py - (w0 * h[1] + w1 * h[4] + w2 * h[7]);
-    xp[t].z = pz - (w0 * h[2] + w1 * h[5] + w2 * h[8]);
+    const double wx = px - (w0 * h[0] + w1 * h[3] + w2 * h[6]);
+    const double wy = py - (w0 * h[1] + w1 * h[4] + w2 * h[7]);
+    const double wz = pz - (w0 * h[2] + w1 * h[5] + w2 * h[8]);
+    xq[t] = make_double4(wx, wy, wz, 0.0);
 }
 
 // Neighbour lists of every sorted atom (see the file comment for the layout).
 __global__ __launch_bounds__(256) void k_build_lists(
-    PairConsts pc, double lA2, double lR2, double cA2, double cR2, const AtomRec *__restrict__ xp,
+    PairConsts pc, double lA2, double lR2, double cA2, double cR2, const double4 *__restrict__ xq,
     const int32_t *__restrict__ cell_of, const CellGeom *__restrict__ cells,
     const int32_t *__restrict__ bin_sorted, const int32_t *__restrict__ bin_start,
     const int32_t *__restrict__ bin_rank,
@@ -225,7 +227,8 @@ __global__ __launch_bounds__(256) void k_build_lists(
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= pc.n) return;
     const CellGeom &cg = cells[cell_of[t]];
-    const double xi = xp[t].x, yi = xp[t].y, zi = xp[t].z;
+    const double4 pi = xq[t];
+    const double xi = pi.x, yi = pi.y, zi = pi.z;
     const int lb = bin_sorted[t];
     const int bc[3] = {lb % cg.nb[0], (lb / cg.nb[0]) % cg.nb[1], lb / (cg.nb[0] * cg.nb[1])};
     int lo[3], hi[3];
@@ -266,7 +269,8 @@ __global__ __launch_bounds__(256) void k_build_lists(
                 for (int u = bin_start[gb]; u < bin_start[gb + 1]; ++u) {
                     if (u == t && self_image) continue;
                     // (x_u - x_i) + shift: exactly the negative of the vector seen from u
-                    const double dx = (xp[u].x - xi) + sx, dy = (xp[u].y - yi) + sy, dz = (xp[u].z - zi) + sz;
+                    const double4 pu = xq[u];
+                    const double dx = (pu.x - xi) + sx, dy = (pu.y - yi) + sy, dz = (pu.z - zi) + sz;
                     const double r2 = dx * dx + dy * dy + dz * dz;
                     if (r2 >= lR2) continue;
                     const uint32_t jl = (uint32_t)(u - cg.atom_start);

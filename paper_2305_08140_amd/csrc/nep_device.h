@@ -44,6 +44,11 @@ static_assert(sizeof(AtomRec) == 64, "AtomRec must be 64 bytes");
 struct PairConsts {
     float rc_rad, rc_ang;             // cutoffs
     float rc_rad2, rc_ang2;           // squared
+    // angular pair gradients: the descriptor kernel stores a slot when
+    // r^2 < rc_ang2_write (zero beyond rc_ang2), the force kernel reads the
+    // other end's slot when r^2 < rc_ang2_read; write > read by a margin of
+    // many ulps, so every slot read was written in the same evaluation
+    float rc_ang2_write, rc_ang2_read;
     float inv_rc_rad, inv_rc_ang;     // 1/rc rounded to FP32 ...
     float inv_rc_rad_lo, inv_rc_ang_lo;   // ... and the rounding remainder 1/rc - inv_rc
     float zbl_r1, zbl_r2, zbl_r2sq;

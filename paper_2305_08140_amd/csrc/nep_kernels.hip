@@ -42,10 +42,28 @@ namespace nep {
 
 // slot of the s-th entry of a list stored front-to-back (nf entries) and
 // back-to-front (nb entries) in a column of capacity cap
-__device__ inline int list_slot(int s, int nf, int nb, int cap)
+__host__ __device__ inline int list_slot(int s, int nf, int nb, int cap)
 {
     return s < nf ? s : s + (cap - nf - nb);
 }
+
+// The same slots walked in order as element offsets slot * n + t of a
+// [slot][atom] array, with one 64-bit add per entry instead of a multiply:
+//   for (ListWalk w(t, n, nf, nb, cap); w.s < nf + nb; w.next()) ... a[w.off] ...
+struct ListWalk {
+    size_t off, n, jump;
+    int s, nf;
+    __host__ __device__ ListWalk(int t, int n_, int nf_, int nb, int cap)
+        : off(0), n((size_t)n_), jump((size_t)(cap - nf_ - nb) * (size_t)n_), s(0), nf(nf_)
+    {
+        off = (size_t)t + (nf_ == 0 ? jump : 0);
+    }
+    __host__ __device__ void next()
+    {
+        ++s;
+        off += n + (s == nf ? jump : 0);
+    }
+};
 
 __device__ inline float ftanh(float z)
 {
@@ -60,16 +78,17 @@ __device__ inline float ftanh(float z)
 // other end of the pair is its exact negative: (x_j - x_i) first, then the
 // image shift n.h (which is exactly negated for -n).
 __device__ inline void pair_vector_d(int32_t e, const PairConsts &pc, int base, double xi, double yi,
-                                     double zi, const AtomRec *__restrict__ xp,
+                                     double zi, const double4 *__restrict__ xq,
                                      const CellGeom *__restrict__ cg, int &j, double &dx, double &dy,
                                      double &dz)
 {
     int n0, n1, n2;
     decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
     j += base;
-    dx = xp[j].x - xi;
-    dy = xp[j].y - yi;
-    dz = xp[j].z - zi;
+    const double4 pj = xq[j];
+    dx = pj.x - xi;
+    dy = pj.y - yi;
+    dz = pj.z - zi;
     if (n0 | n1 | n2) {
         const double *h = cg->h;
         dx += n0 * h[0] + n1 * h[3] + n2 * h[6];
@@ -90,7 +109,7 @@ __device__ inline double dist_d(double r2)
 // Descriptor of one atom: FP64 pair geometry and Chebyshev basis, FP32
 // harmonics and sums.  Returns the radial sums F_k = sum_j f_k(r_ij), the
 // angular sums S[n][lm] = sum_j g_n(r_ij) Y_lm(u_ij), and the ZBL half-energy.
-__device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const AtomRec *__restrict__ xp, int t,
+__device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const double4 *__restrict__ xq, int t,
                                                 double xi, double yi, double zi, const CellGeom *cg, int base,
                                                 const int32_t *__restrict__ nl_ang,
                                                 const int32_t *__restrict__ nl_rad, int naf, int nab, int nrf,
@@ -109,12 +128,17 @@ __device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const Atom
     ezbl = 0.0;
     overlap = false;
 
+    // list entries are loaded one neighbour ahead
     const int nA = naf + nab;
-    for (int s = 0; s < nA; ++s) {
-        const int32_t e = nl_ang[(size_t)list_slot(s, naf, nab, pc.capA) * pc.n + t];
+    ListWalk wa(t, pc.n, naf, nab, pc.capA);
+    int32_t e_nx = nA > 0 ? nl_ang[wa.off] : 0;
+    while (wa.s < nA) {
+        const int32_t e = e_nx;
+        wa.next();
+        if (wa.s < nA) e_nx = nl_ang[wa.off];
         int j;
         double dx, dy, dz;
-        pair_vector_d(e, pc, base, xi, yi, zi, xp, cg, j, dx, dy, dz);
+        pair_vector_d(e, pc, base, xi, yi, zi, xq, cg, j, dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 >= rcR2) continue;
         const double r = dist_d(r2);
@@ -128,13 +152,19 @@ __device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const Atom
         if (r2 < rcA2) {
             double fc, T[KB];
             basis_d(r, inv_rA, fc, T);
+            // T_k carry the FP64 argument's accuracy; rounded once to FP32
+            // they enter g_n = sum_k c_nk f_k in single precision
+            float Tf[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) Tf[k] = (float)T[k];
+            const float hfc = (float)(0.5 * fc);
             float g[NA];
 #pragma unroll
             for (int n = 0; n < NA; ++n) {
-                double s2 = (double)csA[n];
+                float s2 = csA[n];
 #pragma unroll
-                for (int k = 0; k < KB; ++k) s2 = fma((double)P[P_CA + n * KB + k], T[k], s2);
-                g[n] = (float)(0.5 * fc * s2);
+                for (int k = 0; k < KB; ++k) s2 = fmaf(P[P_CA + n * KB + k], Tf[k], s2);
+                g[n] = hfc * s2;
             }
             const float rinv = frcp((float)r);
             float Y[NLM];
@@ -151,11 +181,15 @@ __device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const Atom
         }
     }
     const int nRl = nrf + nrb;
-    for (int s = 0; s < nRl; ++s) {
-        const int32_t e = nl_rad[(size_t)list_slot(s, nrf, nrb, pc.capR) * pc.n + t];
+    ListWalk wr(t, pc.n, nrf, nrb, pc.capR);
+    e_nx = nRl > 0 ? nl_rad[wr.off] : 0;
+    while (wr.s < nRl) {
+        const int32_t e = e_nx;
+        wr.next();
+        if (wr.s < nRl) e_nx = nl_rad[wr.off];
         int j;
         double dx, dy, dz;
-        pair_vector_d(e, pc, base, xi, yi, zi, xp, cg, j, dx, dy, dz);
+        pair_vector_d(e, pc, base, xi, yi, zi, xq, cg, j, dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 >= rcR2) continue;
         double fc, T[KB];
@@ -322,7 +356,7 @@ __device__ __forceinline__ float network_mfma(const float *__restrict__ P, const
 // -sum_j dU_i/dr_ij (x) r_ij is its angular virial.
 template <int NNMODE>
 __device__ __forceinline__ void descriptor_atom(
-    int t, bool valid, NNLds *L, const PairConsts &pc, AtomRec *__restrict__ xp,
+    int t, bool valid, NNLds *L, const PairConsts &pc, const double4 *__restrict__ xq, AtomRec *__restrict__ xp,
     const int32_t *__restrict__ cell_of, const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     const float *__restrict__ P, float4 *__restrict__ pair_grad,
@@ -332,7 +366,8 @@ __device__ __forceinline__ void descriptor_atom(
     // With the MFMA hidden layer every lane of a wave takes part; lanes past
     // the last atom compute on an empty neighbourhood of atom 0 and store nothing.
     if (!valid) t = 0;
-    const double xi = xp[t].x, yi = xp[t].y, zi = xp[t].z;
+    const double4 pi = xq[t];
+    const double xi = pi.x, yi = pi.y, zi = pi.z;
     const CellGeom *cg = cells + cell_of[t];
     const int base = cg->atom_start;
     const uint32_t cnt = valid ? ncnt[t] : 0u;
@@ -345,7 +380,7 @@ __device__ __forceinline__ void descriptor_atom(
     float S[NA][NLM];
     double ezbl;
     bool overlap;
-    descriptor_sums(pc, xp, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, P, csA, F, S, ezbl,
+    descriptor_sums(pc, xq, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, P, csA, F, S, ezbl,
                     overlap);
     if (overlap) latch_error(status, -4);
     float q[DIM];
@@ -354,14 +389,21 @@ __device__ __forceinline__ void descriptor_atom(
     const float U = NNMODE == 1 ? network_mfma(P, q, Fp, L) : network(P, q, Fp);
     if (!valid) return;
     e_atom[t] = (double)U + ezbl;
-    // radial adjoint a_k = dU_i / dF_k, into this atom's record
+    // this atom's record for the force kernel: position and radial adjoint
+    // a_k = dU_i / dF_k, written whole (four 16-byte stores)
+    AtomRec rec;
+    rec.x = xi;
+    rec.y = yi;
+    rec.z = zi;
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         float s = 0.0f;
 #pragma unroll
         for (int n = 0; n < NR; ++n) s = fmaf(Fp[n], P[P_CR + n * KB + k], s);
-        xp[t].a[k] = s;
+        rec.a[k] = s;
     }
+    rec.pad = 0.0f;
+    xp[t] = rec;
     // angular adjoint B_{n,lm} = 2 (dU/dq_nl) s_{n,lm}, in place of S
 #pragma unroll
     for (int n = 0; n < NA; ++n)
@@ -376,17 +418,22 @@ __device__ __forceinline__ void descriptor_atom(
     float W[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) W[k] = 0.0f;
-    for (int s = 0; s < nA; ++s) {
-        const int slot = list_slot(s, naf, nab, pc.capA);
-        const int32_t e = nl_ang[(size_t)slot * pc.n + t];
+    ListWalk wg(t, pc.n, naf, nab, pc.capA);
+    int32_t e_nx = nA > 0 ? nl_ang[wg.off] : 0;
+    while (wg.s < nA) {
+        const int32_t e = e_nx;
+        const size_t off = wg.off;
+        wg.next();
+        if (wg.s < nA) e_nx = nl_ang[wg.off];
         int j;
         double ddx, ddy, ddz;
-        pair_vector_d(e, pc, base, xi, yi, zi, xp, cg, j, ddx, ddy, ddz);
+        pair_vector_d(e, pc, base, xi, yi, zi, xq, cg, j, ddx, ddy, ddz);
         const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
         const float r2 = dx * dx + dy * dy + dz * dz;
         if (r2 >= pc.rc_ang2) {
-            // outside the angular cutoff now: the other end subtracts a zero
-            pair_grad[(size_t)slot * pc.n + t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            // outside the angular cutoff; just outside, the other end may
+            // still read this slot and subtracts a zero
+            if (r2 < pc.rc_ang2_write) pair_grad[off] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             continue;
         }
         const float r = fsqrt(r2);
@@ -431,7 +478,7 @@ __device__ __forceinline__ void descriptor_atom(
         const float gx = fmaf(s1, ux, (vx - uv * ux) * rinv);
         const float gy = fmaf(s1, uy, (vy - uv * uy) * rinv);
         const float gz = fmaf(s1, uz, (vz - uv * uz) * rinv);
-        pair_grad[(size_t)slot * pc.n + t] = make_float4(gx, gy, gz, 0.0f);
+        pair_grad[off] = make_float4(gx, gy, gz, 0.0f);
         Fx += gx; Fy += gy; Fz += gz;
         W[0] = fmaf(gx, dx, W[0]); W[1] = fmaf(gx, dy, W[1]); W[2] = fmaf(gx, dz, W[2]);
         W[3] = fmaf(gy, dx, W[3]); W[4] = fmaf(gy, dy, W[4]); W[5] = fmaf(gy, dz, W[5]);
@@ -449,7 +496,7 @@ __device__ __forceinline__ void descriptor_atom(
 // the vector ALUs in FP32; 1: on the matrix cores in BF16 (FP32 accumulation).
 template <int BS, bool PERSISTENT, int NNMODE>
 __global__ __launch_bounds__(BS, NNMODE == 1 ? 1 : 2) void k_descriptor(
-    PairConsts pc, AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
+    PairConsts pc, const double4 *__restrict__ xq, AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     const float *__restrict__ P, float4 *__restrict__ pair_grad,
@@ -463,14 +510,14 @@ __global__ __launch_bounds__(BS, NNMODE == 1 ? 1 : 2) void k_descriptor(
         for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
             const int t = tile * BS + threadIdx.x;
             if (NNMODE == 1 || t < pc.n)
-                descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, pair_grad,
+                descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xq, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, pair_grad,
                                         f_own, w_atom, e_atom, status);
         }
     } else {
         const int tile = xcd_block(ntiles);
         const int t = tile * BS + threadIdx.x;
         if (tile < ntiles && (NNMODE == 1 || t < pc.n))
-            descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, pair_grad,
+            descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xq, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, pair_grad,
                                     f_own, w_atom, e_atom, status);
     }
 }
@@ -507,11 +554,9 @@ __device__ __forceinline__ void force_atom(
     bool bad = false;
 
     // radial + ZBL force of one pair (both ends); returns false outside rc_rad
-    auto radial = [&](int32_t e) -> bool {
+    auto radial = [&](int32_t e, const AtomRec &rj, float &r2out) -> bool {
         int n0, n1, n2, j;
         decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
-        j += base;
-        const AtomRec rj = xp[j];
         double ddx = rj.x - xi, ddy = rj.y - yi, ddz = rj.z - zi;
         if (n0 | n1 | n2) {
             const double *h = cg->h;
@@ -521,6 +566,7 @@ __device__ __forceinline__ void force_atom(
         }
         const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
         const float r2 = dx * dx + dy * dy + dz * dz;
+        r2out = r2;
         if (r2 >= pc.rc_rad2) return false;
         const float r = fsqrt(r2);
         const float tt = scaled_minus_one(r, pc.inv_rc_rad, pc.inv_rc_rad_lo);
@@ -552,20 +598,51 @@ __device__ __forceinline__ void force_atom(
         return true;
     };
 
+    // the list entries (and reverse slots) of the next neighbour are loaded
+    // one iteration ahead: they do not depend on the current neighbour
     const int nA = naf + nab;
-    for (int s = 0; s < nA; ++s) {
-        const int slot = list_slot(s, naf, nab, pc.capA);
-        const int32_t e = nl_ang[(size_t)slot * pc.n + t];
-        if (!radial(e)) continue;
+    ListWalk wa(t, pc.n, naf, nab, pc.capA);
+    int32_t e_nx = 0;
+    int sj_nx = 255;
+    if (nA > 0) { e_nx = nl_ang[wa.off]; sj_nx = rev[wa.off]; }
+    while (wa.s < nA) {
+        const int32_t e = e_nx;
+        const int sj = sj_nx;
+        wa.next();
+        if (wa.s < nA) { e_nx = nl_ang[wa.off]; sj_nx = rev[wa.off]; }
+        float r2;
+        const AtomRec rj = xp[(int)((uint32_t)e & ((1u << pc.jbits) - 1u)) + base];
+        if (!radial(e, rj, r2) || r2 >= pc.rc_ang2_read) continue;
         // angular: subtract the other end's stored dU_j/dr_ji (zero outside rc_ang)
-        const int sj = rev[(size_t)slot * pc.n + t];
         if (sj == 255) { bad = true; continue; }
         const int j = (int)((uint32_t)e & ((1u << pc.jbits) - 1u)) + base;
         const float4 gj = pair_grad[(size_t)sj * pc.n + j];
         Fx -= gj.x; Fy -= gj.y; Fz -= gj.z;
     }
+    // radial list: entries two ahead, the neighbour's record one ahead
     const int nRl = nrf + nrb;
-    for (int s = 0; s < nRl; ++s) radial(nl_rad[(size_t)list_slot(s, nrf, nrb, pc.capR) * pc.n + t]);
+    const uint32_t jmask = (1u << pc.jbits) - 1u;
+    ListWalk wr(t, pc.n, nrf, nrb, pc.capR);
+    int32_t e_cur = 0;
+    AtomRec r_cur;
+    if (nRl > 0) {
+        e_cur = nl_rad[wr.off];
+        r_cur = xp[(int)((uint32_t)e_cur & jmask) + base];
+    }
+    wr.next();
+    if (wr.s < nRl) e_nx = nl_rad[wr.off];
+    for (int s = 0; s < nRl; ++s) {
+        const int32_t e = e_cur;
+        const AtomRec rj = r_cur;
+        if (s + 1 < nRl) {
+            e_cur = e_nx;
+            r_cur = xp[(int)((uint32_t)e_cur & jmask) + base];
+            wr.next();
+            if (wr.s < nRl) e_nx = nl_rad[wr.off];
+        }
+        float r2;
+        radial(e, rj, r2);
+    }
 
     if (bad) latch_error(status, -9);
     const int i = perm[t];
@@ -606,11 +683,13 @@ __global__ __launch_bounds__(BS) void k_force(
 // Instantiated launch shapes.
 #define NEP_SHAPES(X) X(64, false) X(128, false) X(256, false) X(64, true) X(128, true) X(256, true)
 #define NEP_INST(BS, PE)                                                                                           \
-    template __global__ void k_descriptor<BS, PE, 0>(PairConsts, AtomRec *, const int32_t *, const CellGeom *,     \
+    template __global__ void k_descriptor<BS, PE, 0>(PairConsts, const double4 *, AtomRec *, const int32_t *,      \
+                                                     const CellGeom *,                                             \
                                                      const int32_t *, const int32_t *, const uint32_t *,           \
                                                      const float *, float4 *, float4 *, float *, double *, int32_t *, \
                                                      int);                                                           \
-    template __global__ void k_descriptor<BS, PE, 1>(PairConsts, AtomRec *, const int32_t *, const CellGeom *,     \
+    template __global__ void k_descriptor<BS, PE, 1>(PairConsts, const double4 *, AtomRec *, const int32_t *,      \
+                                                     const CellGeom *,                                             \
                                                      const int32_t *, const int32_t *, const uint32_t *,           \
                                                      const float *, float4 *, float4 *, float *, double *, int32_t *, \
                                                      int);                                                           \
@@ -639,7 +718,7 @@ constexpr int PG_DZ = 0, PG_TH = PG_DZ + NH, PG_QT = PG_TH + NH, PG_FPR = PG_QT 
 // LDS, then every thread sums its own outputs (o = lane + 64 k) over the
 // tile; one FP64 partial per block and output, reduced afterwards in order.
 __global__ __launch_bounds__(64) void k_param_grad(
-    PairConsts pc, const AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
+    PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt, const float *__restrict__ P,
     const double *__restrict__ gE, double *__restrict__ part, const int32_t *__restrict__ status, int ntiles)
@@ -658,7 +737,8 @@ __global__ __launch_bounds__(64) void k_param_grad(
         const int t = tile * PG_TILE + lane;
         float *r = rec[lane];
         if (t < pc.n) {
-            const double xi = xp[t].x, yi = xp[t].y, zi = xp[t].z;
+            const double4 pi = xq[t];
+            const double xi = pi.x, yi = pi.y, zi = pi.z;
             const CellGeom *cg = cells + cell_of[t];
             const int base = cg->atom_start;
             const uint32_t cnt = ncnt[t];
@@ -668,7 +748,7 @@ __global__ __launch_bounds__(64) void k_param_grad(
             float S[NA][NLM];
             double ezbl;
             bool overlap;
-            descriptor_sums(pc, xp, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, P, csA, F, S,
+            descriptor_sums(pc, xq, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, P, csA, F, S,
                             ezbl, overlap);
             float q[DIM];
             descriptor_vector(P, F, S, q);
@@ -712,11 +792,11 @@ __global__ __launch_bounds__(64) void k_param_grad(
             for (int n = 0; n < NA; ++n)
 #pragma unroll
                 for (int k = 0; k < KB; ++k) G[n][k] = 0.0f;
-            for (int s = 0; s < naf + nab; ++s) {
-                const int32_t e = nl_ang[(size_t)list_slot(s, naf, nab, pc.capA) * pc.n + t];
+            for (ListWalk w(t, pc.n, naf, nab, pc.capA); w.s < naf + nab; w.next()) {
+                const int32_t e = nl_ang[w.off];
                 int j;
                 double ddx, ddy, ddz;
-                pair_vector_d(e, pc, base, xi, yi, zi, xp, cg, j, ddx, ddy, ddz);
+                pair_vector_d(e, pc, base, xi, yi, zi, xq, cg, j, ddx, ddy, ddz);
                 const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 if (r2 >= pc.rc_ang2) continue;
@@ -925,7 +1005,7 @@ __global__ void k_energy_atom_out(int n, const int32_t *__restrict__ perm,
 
 // Neighbour counts inside the cutoffs (diagnostics for flop accounting).
 __global__ __launch_bounds__(256) void k_count_inside(
-    PairConsts pc, const AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
+    PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     unsigned long long *__restrict__ counts)
@@ -933,7 +1013,7 @@ __global__ __launch_bounds__(256) void k_count_inside(
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long nr = 0, na = 0;
     if (t < pc.n) {
-        const double xi = xp[t].x, yi = xp[t].y, zi = xp[t].z;
+        const double xi = xq[t].x, yi = xq[t].y, zi = xq[t].z;
         const CellGeom *cg = cells + cell_of[t];
         const uint32_t cnt = ncnt[t];
         const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
@@ -942,7 +1022,7 @@ __global__ __launch_bounds__(256) void k_count_inside(
             int j;
             double dx, dy, dz;
             pair_vector_d(nl_ang[(size_t)list_slot(s, naf, nab, pc.capA) * pc.n + t], pc, cg->atom_start,
-                          xi, yi, zi, xp, cg, j, dx, dy, dz);
+                          xi, yi, zi, xq, cg, j, dx, dy, dz);
             const double r2 = dx * dx + dy * dy + dz * dz;
             nr += r2 < rcR2;
             na += r2 < rcA2;
@@ -951,7 +1031,7 @@ __global__ __launch_bounds__(256) void k_count_inside(
             int j;
             double dx, dy, dz;
             pair_vector_d(nl_rad[(size_t)list_slot(s, nrf, nrb, pc.capR) * pc.n + t], pc, cg->atom_start,
-                          xi, yi, zi, xp, cg, j, dx, dy, dz);
+                          xi, yi, zi, xq, cg, j, dx, dy, dz);
             nr += (dx * dx + dy * dy + dz * dz) < rcR2;
         }
     }
