@@ -97,6 +97,60 @@ __device__ inline void pair_vector_d(int32_t e, const PairConsts &pc, int base, 
     }
 }
 
+// The same pair vector from a neighbour position already gathered.
+__device__ inline void pair_vector_p(int32_t e, const PairConsts &pc, double px, double py, double pz, double xi,
+                                     double yi, double zi, const CellGeom *__restrict__ cg, double &dx, double &dy,
+                                     double &dz)
+{
+    int n0, n1, n2, j;
+    decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
+    dx = px - xi;
+    dy = py - yi;
+    dz = pz - zi;
+    if (n0 | n1 | n2) {
+        const double *h = cg->h;
+        dx += n0 * h[0] + n1 * h[3] + n2 * h[6];
+        dy += n0 * h[1] + n1 * h[4] + n2 * h[7];
+        dz += n0 * h[2] + n1 * h[5] + n2 * h[8];
+    }
+}
+
+// Software pipeline over one atom's list: entries are loaded two neighbours
+// ahead and the neighbour's position one ahead, so the dependent gathers of
+// the next neighbours overlap the arithmetic of the current one.
+//   for (NeighbourPipe q(...); q.s < q.count;) { q.pop(...); ... }
+struct NeighbourPipe {
+    ListWalk w;
+    int count, s;
+    int32_t e_cur, e_nx;
+    double x_cur, y_cur, z_cur;
+    __device__ NeighbourPipe(const int32_t *__restrict__ nl, const double4 *__restrict__ xq, int base,
+                             uint32_t jmask, int t, int n, int nf, int nb, int cap)
+        : w(t, n, nf, nb, cap), count(nf + nb), s(0), e_cur(0), e_nx(0), x_cur(0.0), y_cur(0.0), z_cur(0.0)
+    {
+        if (count > 0) {
+            e_cur = nl[w.off];
+            const double4 *q = xq + ((int)((uint32_t)e_cur & jmask) + base);
+            x_cur = q->x; y_cur = q->y; z_cur = q->z;
+        }
+        w.next();
+        if (w.s < count) e_nx = nl[w.off];
+    }
+    __device__ void pop(const int32_t *__restrict__ nl, const double4 *__restrict__ xq, int base, uint32_t jmask,
+                        int32_t &e, double &px, double &py, double &pz)
+    {
+        e = e_cur; px = x_cur; py = y_cur; pz = z_cur;
+        if (s + 1 < count) {
+            e_cur = e_nx;
+            const double4 *q = xq + ((int)((uint32_t)e_cur & jmask) + base);
+            x_cur = q->x; y_cur = q->y; z_cur = q->z;
+            w.next();
+            if (w.s < count) e_nx = nl[w.off];
+        }
+        ++s;
+    }
+};
+
 // |r| in double precision from r^2: FP32 square root refined by one
 // Newton step (relative error ~1e-15).
 __device__ inline double dist_d(double r2)
@@ -128,17 +182,13 @@ __device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const doub
     ezbl = 0.0;
     overlap = false;
 
-    // list entries are loaded one neighbour ahead
-    const int nA = naf + nab;
-    ListWalk wa(t, pc.n, naf, nab, pc.capA);
-    int32_t e_nx = nA > 0 ? nl_ang[wa.off] : 0;
-    while (wa.s < nA) {
-        const int32_t e = e_nx;
-        wa.next();
-        if (wa.s < nA) e_nx = nl_ang[wa.off];
-        int j;
+    const uint32_t jmask = (1u << pc.jbits) - 1u;
+    for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
+        int32_t e;
+        double px, py, pz;
+        q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
         double dx, dy, dz;
-        pair_vector_d(e, pc, base, xi, yi, zi, xq, cg, j, dx, dy, dz);
+        pair_vector_p(e, pc, px, py, pz, xi, yi, zi, cg, dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 >= rcR2) continue;
         const double r = dist_d(r2);
@@ -180,16 +230,12 @@ __device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const doub
             ezbl += 0.5 * U;
         }
     }
-    const int nRl = nrf + nrb;
-    ListWalk wr(t, pc.n, nrf, nrb, pc.capR);
-    e_nx = nRl > 0 ? nl_rad[wr.off] : 0;
-    while (wr.s < nRl) {
-        const int32_t e = e_nx;
-        wr.next();
-        if (wr.s < nRl) e_nx = nl_rad[wr.off];
-        int j;
+    for (NeighbourPipe q(nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.s < q.count;) {
+        int32_t e;
+        double px, py, pz;
+        q.pop(nl_rad, xq, base, jmask, e, px, py, pz);
         double dx, dy, dz;
-        pair_vector_d(e, pc, base, xi, yi, zi, xq, cg, j, dx, dy, dz);
+        pair_vector_p(e, pc, px, py, pz, xi, yi, zi, cg, dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 >= rcR2) continue;
         double fc, T[KB];
@@ -418,16 +464,14 @@ __device__ __forceinline__ void descriptor_atom(
     float W[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) W[k] = 0.0f;
-    ListWalk wg(t, pc.n, naf, nab, pc.capA);
-    int32_t e_nx = nA > 0 ? nl_ang[wg.off] : 0;
-    while (wg.s < nA) {
-        const int32_t e = e_nx;
-        const size_t off = wg.off;
-        wg.next();
-        if (wg.s < nA) e_nx = nl_ang[wg.off];
-        int j;
+    const uint32_t jmask = (1u << pc.jbits) - 1u;
+    for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
+        const size_t off = (size_t)list_slot(q.s, naf, nab, pc.capA) * pc.n + t;
+        int32_t e;
+        double px, py, pz;
+        q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
         double ddx, ddy, ddz;
-        pair_vector_d(e, pc, base, xi, yi, zi, xq, cg, j, ddx, ddy, ddz);
+        pair_vector_p(e, pc, px, py, pz, xi, yi, zi, cg, ddx, ddy, ddz);
         const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
         const float r2 = dx * dx + dy * dy + dz * dz;
         if (r2 >= pc.rc_ang2) {
@@ -598,33 +642,44 @@ __device__ __forceinline__ void force_atom(
         return true;
     };
 
-    // the list entries (and reverse slots) of the next neighbour are loaded
-    // one iteration ahead: they do not depend on the current neighbour
+    // both lists are software-pipelined: entries (and reverse slots) two
+    // neighbours ahead, the neighbour's record one ahead
+    const uint32_t jmask = (1u << pc.jbits) - 1u;
     const int nA = naf + nab;
     ListWalk wa(t, pc.n, naf, nab, pc.capA);
-    int32_t e_nx = 0;
-    int sj_nx = 255;
-    if (nA > 0) { e_nx = nl_ang[wa.off]; sj_nx = rev[wa.off]; }
-    while (wa.s < nA) {
-        const int32_t e = e_nx;
-        const int sj = sj_nx;
-        wa.next();
-        if (wa.s < nA) { e_nx = nl_ang[wa.off]; sj_nx = rev[wa.off]; }
+    int32_t e_cur = 0, e_nx = 0;
+    int sj_cur = 255, sj_nx = 255;
+    AtomRec r_cur;
+    if (nA > 0) {
+        e_cur = nl_ang[wa.off];
+        sj_cur = rev[wa.off];
+        r_cur = xp[(int)((uint32_t)e_cur & jmask) + base];
+    }
+    wa.next();
+    if (wa.s < nA) { e_nx = nl_ang[wa.off]; sj_nx = rev[wa.off]; }
+    for (int s = 0; s < nA; ++s) {
+        const int32_t e = e_cur;
+        const int sj = sj_cur;
+        const AtomRec rj = r_cur;
+        if (s + 1 < nA) {
+            e_cur = e_nx;
+            sj_cur = sj_nx;
+            r_cur = xp[(int)((uint32_t)e_cur & jmask) + base];
+            wa.next();
+            if (wa.s < nA) { e_nx = nl_ang[wa.off]; sj_nx = rev[wa.off]; }
+        }
         float r2;
-        const AtomRec rj = xp[(int)((uint32_t)e & ((1u << pc.jbits) - 1u)) + base];
         if (!radial(e, rj, r2) || r2 >= pc.rc_ang2_read) continue;
         // angular: subtract the other end's stored dU_j/dr_ji (zero outside rc_ang)
         if (sj == 255) { bad = true; continue; }
-        const int j = (int)((uint32_t)e & ((1u << pc.jbits) - 1u)) + base;
+        const int j = (int)((uint32_t)e & jmask) + base;
         const float4 gj = pair_grad[(size_t)sj * pc.n + j];
         Fx -= gj.x; Fy -= gj.y; Fz -= gj.z;
     }
     // radial list: entries two ahead, the neighbour's record one ahead
     const int nRl = nrf + nrb;
-    const uint32_t jmask = (1u << pc.jbits) - 1u;
     ListWalk wr(t, pc.n, nrf, nrb, pc.capR);
-    int32_t e_cur = 0;
-    AtomRec r_cur;
+    e_nx = 0;
     if (nRl > 0) {
         e_cur = nl_rad[wr.off];
         r_cur = xp[(int)((uint32_t)e_cur & jmask) + base];
