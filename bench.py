@@ -85,11 +85,16 @@ def cpu_baseline(model, s, seconds_target=15.0):
     oracle.efv_cell(model, s.pos, s.h[0], targets=np.arange(sample), virial=False)
     t_probe = time.time() - t0
     per_atom = t_probe / sample
-    sample = int(min(s.n_atoms, max(2000, seconds_target / max(per_atom, 1e-9))))
-    sample = min(sample, 400000)
-    t0 = time.time()
-    oracle.efv_cell(model, s.pos, s.h[0], targets=np.arange(sample), virial=False)
-    dt = time.time() - t0
+    # the probe includes the fixed cost of binning all atoms, so resize once
+    # more from the first sized run
+    for _ in range(2):
+        sample = int(min(s.n_atoms, 2_000_000, max(2000, seconds_target / max(per_atom, 1e-9))))
+        t0 = time.time()
+        oracle.efv_cell(model, s.pos, s.h[0], targets=np.arange(sample), virial=False)
+        dt = time.time() - t0
+        per_atom = dt / sample
+        if dt > 0.5 * seconds_target or sample >= min(s.n_atoms, 2_000_000):
+            break
     return {"value": sample / dt, "unit": "atom-steps/s", "cores": n_thr, "kind": "oracle",
             "sample": f"FP64 energies+forces of {sample} atoms of the 8,192,000-atom configuration "
                       f"(one evaluation, neighbours found afresh; the integrator update is negligible), "
@@ -125,7 +130,9 @@ def summarize_rocprof(kt_dir, fetch_dir, write_dir, n_atoms, command, out_dir):
         for r in csv.DictReader(open(one(d, "*counter_collection.csv"))):
             if r["Counter_Name"] != cname:
                 continue
-            acc.setdefault(r["Kernel_Name"].split("(")[0], []).append(float(r["Counter_Value"]))
+            name = r["Kernel_Name"].split("(")[0]
+            name = (name[5:] if name.startswith("void ") else name).split("<")[0]
+            acc.setdefault(name, []).append(float(r["Counter_Value"]))
         return acc
     fe = counters(fetch_dir, "FETCH_SIZE")
     wr = counters(write_dir, "WRITE_SIZE")
@@ -269,14 +276,15 @@ def main():
     args = ap.parse_args()
     if args.summarize_rocprof:
         n = 2 * args.cells ** 3
-        cmd = {"kt": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_kt -o kt --output-format csv -- "
-                     "python3 bench.py --steps 20 --warmup 3 --no-cpu-baseline",
-               "fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o f --output-format csv -- "
-                        "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-calibration-mib 1024 "
-                        "--timing-reps 1",
-               "write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o w --output-format csv -- "
-                        "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-calibration-mib 1024 "
-                        "--timing-reps 1"}
+        kt_dir, fetch_dir, write_dir = args.summarize_rocprof
+        cmd = {"kt": "rocprofv3 --kernel-trace --stats -d %s -o kt --output-format csv -- "
+                     "python3 bench.py --steps 20 --warmup 3 --no-cpu-baseline --no-batches" % kt_dir,
+               "fetch": "rocprofv3 --pmc FETCH_SIZE -d %s -o f --output-format csv -- "
+                        "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batches "
+                        "--copy-calibration-mib 1024 --timing-reps 1" % fetch_dir,
+               "write": "rocprofv3 --pmc WRITE_SIZE -d %s -o w --output-format csv -- "
+                        "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batches "
+                        "--copy-calibration-mib 1024 --timing-reps 1" % write_dir}
         summarize_rocprof(*args.summarize_rocprof, n, cmd, os.path.join(ROOT, "profiles"))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -194,10 +194,12 @@ int nep_compute_efv_graph(nep_ctx *ctx, const nep_system *sys, nep_efv *out, voi
 int nep_autotune(nep_ctx *ctx, const nep_system *sys, nep_efv *out, int32_t reps, int32_t *shape_out,
                  void *stream);
 
-/* Precision of the network's hidden layer in later evaluations:
+/* Precision and unit of the network's hidden layer in later evaluations:
  *   0 (default) FP32 on the vector ALUs;
  *   1 BF16 inputs on the matrix cores (v_mfma_f32_32x32x16_bf16) with FP32
- *     accumulation, for the forward z = w0 s q and the backward dU/dq.
+ *     accumulation, for the forward z = w0 s q and the backward dU/dq;
+ *   2 FP32 inputs on the matrix cores (v_mfma_f32_32x32x2_f32), FP32
+ *     accumulation: the precision of mode 0 in another summation order.
  * Descriptors, forces and reductions are unaffected.  Returns NEP_OK or NEP_E_ARG. */
 int nep_set_precision(nep_ctx *ctx, int32_t mode);
 

@@ -309,7 +309,7 @@ class Context:
         return self.SHAPE_NAMES[sh[0]], self.SHAPE_NAMES[sh[1]]
 
     def nep_set_precision(self, mode):
-        """0: FP32 hidden layer (vector ALUs); 1: BF16 hidden layer on the matrix cores."""
+        """0: FP32 hidden layer (vector ALUs); 1: BF16 and 2: FP32 hidden layer on the matrix cores."""
         _check(lib().nep_set_precision(self._ptr, int(mode)), "nep_set_precision")
 
     def nep_num_params(self):

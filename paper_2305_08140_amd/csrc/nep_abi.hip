@@ -14,8 +14,8 @@ namespace nep {
 // kernels (nep_kernels.hip)
 template <int BS, bool PE, int NNMODE>
 __global__ void k_descriptor(PairConsts, const double4 *, AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
-                             const int32_t *, const uint32_t *, const float *, float4 *, float4 *, float *,
-                             double *, int32_t *, int);
+                             const int32_t *, const uint32_t *, const float *, const double *, float4 *, float4 *,
+                             float *, double *, int32_t *, int);
 template <int BS, bool PE>
 __global__ void k_force(PairConsts, const AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
                         const int32_t *, const uint32_t *, const uint8_t *, const float4 *, const float4 *,
@@ -25,8 +25,9 @@ __global__ void k_reduce_chunks(const int32_t *, const int32_t *, const double *
 __global__ void k_reduce_cells(int, const int32_t *, const double *, double *, double *, const int32_t *);
 __global__ void k_energy_atom_out(int, const int32_t *, const double *, float *);
 __global__ void k_param_grad(PairConsts, const double4 *, const int32_t *, const CellGeom *, const int32_t *,
-                             const int32_t *, const uint32_t *, const float *, const double *, double *,
-                             const int32_t *, int);
+                             const int32_t *, const uint32_t *, const float *, const double *, const double *,
+                             double *, const int32_t *, int);
+__global__ void k_params64(const float *, double *);
 __global__ void k_param_reduce(int, const double *, double *);
 __global__ void k_grad_pos(int, const int32_t *, const double *, const float *, const float *, const float *,
                            double *, double *, double *);
@@ -47,7 +48,8 @@ __global__ void k_bin_scatter(int, const int32_t *, const int32_t *, int32_t *, 
 __global__ void k_bin_rank(int, const int32_t *, const int32_t *, const int32_t *, const int32_t *,
                            const CellGeom *, int32_t *, int32_t *, const int32_t *, const int32_t *);
 __global__ void k_sort_positions(int, const int32_t *, const double *, const double *, const double *,
-                                 const int32_t *, const int32_t *, const CellGeom *, double4 *, int32_t *);
+                                 const int32_t *, const int32_t *, const CellGeom *, double4 *, int32_t *,
+                                 const int32_t *);
 __global__ void k_build_lists(PairConsts, double, double, double, double, const double4 *, const int32_t *,
                               const CellGeom *, const int32_t *, const int32_t *, const int32_t *, int32_t *,
                               int32_t *, uint32_t *, int32_t *, const int32_t *);
@@ -84,6 +86,7 @@ struct nep_ctx {
     // per-atom storage (capacity cfg.max_atoms)
     AtomRec *xp = nullptr;       // [N] sorted wrapped positions and radial adjoints
     double4 *xq = nullptr;       // [N] sorted wrapped positions, compact copy
+    double *c64 = nullptr;       // angular coefficients and their row sums, double precision
     double *xref = nullptr;      // [3][N] caller-order positions at the last build
     int32_t *perm = nullptr, *bin_of = nullptr, *wrap = nullptr, *cell_of = nullptr, *tmp = nullptr,
             *bin_sorted = nullptr;
@@ -115,7 +118,7 @@ struct nep_ctx {
     // launch shapes of the two evaluation kernels (index into SHAPES), per
     // size bucket floor(log2 n_atoms) once the autotuner has run
     int shape_desc = 2, shape_force = 2;
-    int nn_mode = 0;                 // hidden layer: 0 FP32 vector ALU, 1 BF16 matrix cores
+    int nn_mode = 0;                 // hidden layer: 0 FP32 vector ALU, 1 BF16 / 2 FP32 matrix cores
     int tuned_desc[32], tuned_force[32];
     // captured evaluation graph and the arguments it was captured with
     hipGraphExec_t graph_exec = nullptr;
@@ -181,7 +184,7 @@ void nep_destroy(nep_ctx *c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    void *bufs[] = {c->params, c->xp, c->xq, c->xref, c->bin_rank, c->bin_lin, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
+    void *bufs[] = {c->params, c->c64, c->xp, c->xq, c->xref, c->bin_rank, c->bin_lin, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
                     c->bin_sorted, c->ncnt, c->nl_ang, c->nl_rad, c->pair_grad, c->f_own, c->rev,
                     c->w_atom,
                     c->e_atom, c->cells, c->cell_start_d, c->chunk_begin, c->chunk_end, c->cell_chunk,
@@ -223,6 +226,7 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
         if (ok && hipMalloc(p, bytes > 0 ? bytes : 16) != hipSuccess) ok = false;
     };
     A((void **)&c->params, P_SIZE * sizeof(float));
+    A((void **)&c->c64, (NA * KB + NA) * sizeof(double));
     A((void **)&c->xp, N * sizeof(AtomRec));
     A((void **)&c->xq, N * sizeof(double4));
     A((void **)&c->xref, 3 * N * sizeof(double));
@@ -277,10 +281,12 @@ int nep_set_weights(nep_ctx *c, const nep_weights *w, int32_t on_device, void *s
     if (on_device) {
         // b1 is a host scalar even when the arrays live on the device
         HIP_TRY(hipMemcpyAsync(c->params + P_B1, &w->b1, 4, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));
     } else {
         HIP_TRY(hipMemcpy(c->params + P_B1, &w->b1, 4, hipMemcpyHostToDevice));
     }
+    k_params64<<<1, 64, 0, s>>>(c->params, c->c64);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
     return NEP_OK;
 }
 
@@ -495,10 +501,10 @@ static int launch_build(nep_ctx *c, const nep_system *s, hipStream_t st, const i
     k_bin_scatter<<<grid_for(n, 256), 256, 0, st>>>(n, c->bin_of, c->bin_start, c->bin_fill, c->tmp, flag);
     k_bin_rank<<<grid_for(n, 256), 256, 0, st>>>(n, c->bin_of, c->bin_start, c->tmp, c->cell_of, c->cells,
                                                  c->perm, c->bin_sorted, c->bin_lin, flag);
-    // sorted positions are needed by the list build; unconditional is fine
-    // (every evaluation refreshes them anyway)
+    // sorted positions for the list build (skipped with the rest of the
+    // build when the flag says no rebuild; every evaluation refreshes them)
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                       c->cells, c->xq, c->status);
+                                                       c->cells, c->xq, c->status, flag);
     const double lA = c->hp.rc_ang + c->cfg.skin, lR = c->hp.rc_rad + c->cfg.skin;
     k_build_lists<<<grid_for(n, 256), 256, 0, st>>>(
         c->pc, lA * lA, lR * lR, c->hp.rc_ang * c->hp.rc_ang, c->hp.rc_rad * c->hp.rc_rad, c->xq, c->cell_of,
@@ -548,7 +554,7 @@ static void launch_desc_t(nep_ctx *c, hipStream_t st)
         grid = std::max(1, std::min(tiles, 256 * std::max(per_cu, 1)));
     }
     k_descriptor<BS, PE, NNMODE><<<grid, BS, 0, st>>>(c->pc, c->xq, c->xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
-                                                      c->ncnt, c->params, c->pair_grad, c->f_own, c->w_atom,
+                                                      c->ncnt, c->params, c->c64, c->pair_grad, c->f_own, c->w_atom,
                                                       c->e_atom, c->status, tiles);
 }
 
@@ -556,6 +562,7 @@ template <int BS, bool PE>
 static void launch_desc_m(nep_ctx *c, hipStream_t st)
 {
     if (c->nn_mode == 1) launch_desc_t<BS, PE, 1>(c, st);
+    else if (c->nn_mode == 2) launch_desc_t<BS, PE, 2>(c, st);
     else launch_desc_t<BS, PE, 0>(c, st);
 }
 
@@ -606,7 +613,7 @@ static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t s
     const int n = (int)s->n_atoms;
     if (refresh_positions)
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                           c->cells, c->xq, c->status);
+                                                           c->cells, c->xq, c->status, nullptr);
     launch_desc(c, c->shape_desc, st);
     launch_force(c, c->shape_force, o, st);
     k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom, c->part,
@@ -650,7 +657,7 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
     for (int r = 0; r < reps; ++r) {
         HIP_TRY(hipEventRecord(ev[0], st));
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                           c->cells, c->xq, c->status);
+                                                           c->cells, c->xq, c->status, nullptr);
         HIP_TRY(hipEventRecord(ev[1], st));
         launch_desc(c, c->shape_desc, st);
         HIP_TRY(hipEventRecord(ev[2], st));
@@ -678,7 +685,7 @@ static constexpr int N_PARAMS = NR * KB + NA * KB + NH * DIM + NH + NH + 1;
 
 int nep_set_precision(nep_ctx *c, int32_t mode)
 {
-    if (!c || mode < 0 || mode > 1) return NEP_E_ARG;
+    if (!c || mode < 0 || mode > 2) return NEP_E_ARG;
     c->nn_mode = mode;
     return NEP_OK;
 }
@@ -710,9 +717,9 @@ int nep_backward(nep_ctx *c, const nep_system *s, const nep_efv *o, const double
         c->pg_blocks = blocks;
     }
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                       c->cells, c->xq, c->status);
+                                                       c->cells, c->xq, c->status, nullptr);
     k_param_grad<<<blocks, 64, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
-                                        c->params, gE, c->pg_part, c->status, tiles);
+                                        c->params, c->c64, gE, c->pg_part, c->status, tiles);
     k_param_reduce<<<grid_for(N_PARAMS, 256), 256, 0, st>>>(blocks, c->pg_part, grad_params);
     if (gx) k_grad_pos<<<grid_for(n, 256), 256, 0, st>>>(n, c->cell_of, gE, o->fx, o->fy, o->fz, gx, gy, gz);
     if (gh)
@@ -735,7 +742,7 @@ int nep_autotune(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, int3
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                       c->cells, c->xq, c->status);
+                                                       c->cells, c->xq, c->status, nullptr);
     auto time_it = [&](auto &&launch) -> float {
         launch();   // warm-up
         HIP_TRY(hipEventRecord(e0, st));

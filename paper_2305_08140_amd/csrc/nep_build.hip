@@ -191,15 +191,17 @@ __global__ void k_bin_rank(int n, const int32_t *__restrict__ bin_of,
 }
 
 // Wrapped positions in sorted order: xq[t] = x[perm[t]] - w . h, 32-byte
-// records (four atoms per 128-byte line).  Runs at every evaluation;
-// non-finite positions latch NEP_E_NONFINITE.
+// records (four atoms per 128-byte line).  Runs at every evaluation (and
+// in a build, when `flag` is non-null and set); non-finite positions latch
+// NEP_E_NONFINITE.
 __global__ void k_sort_positions(int n, const int32_t *__restrict__ perm,
                                  const double *__restrict__ x, const double *__restrict__ y,
                                  const double *__restrict__ z, const int32_t *__restrict__ wrap,
                                  const int32_t *__restrict__ cell_of,
                                  const CellGeom *__restrict__ cells, double4 *__restrict__ xq,
-                                 int32_t *__restrict__ status)
+                                 int32_t *__restrict__ status, const int32_t *__restrict__ flag)
 {
+    if (flag && *flag == 0) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int i = perm[t];

@@ -238,6 +238,45 @@ __host__ __device__ inline void sph(float x, float y, float z, float Y[NLM])
 
 // v = sum_lm Dc[lm] * grad_u p_lm(u), the gradient of the polynomials above
 // taken with x, y, z independent (the caller projects out the radial part).
+// The same harmonics in double precision, one degree l at a time: the 2l+1
+// values that sph stores at offsets l*l-1 .. l*l+2l-1, in the same order.
+template <int L>
+__host__ __device__ inline void sph_degree_d(double x, double y, double z, double *Y)
+{
+    constexpr double S3 = 1.7320508075688772, S5 = 2.2360679774997896, S6 = 2.4494897427831781;
+    constexpr double S10 = 3.1622776601683795, S15 = 3.8729833462074170, S35 = 5.9160797830996160;
+    constexpr double S70 = 8.3666002653407555;
+    const double x2 = x * x, y2 = y * y, z2 = z * z;
+    if constexpr (L == 1) {
+        Y[0] = y; Y[1] = z; Y[2] = x;
+    } else if constexpr (L == 2) {
+        Y[0] = S3 * x * y;
+        Y[1] = S3 * y * z;
+        Y[2] = 0.5 * (3.0 * z2 - 1.0);
+        Y[3] = S3 * x * z;
+        Y[4] = 0.5 * S3 * (x2 - y2);
+    } else if constexpr (L == 3) {
+        Y[0] = 0.25 * S10 * y * (3.0 * x2 - y2);
+        Y[1] = S15 * x * y * z;
+        Y[2] = 0.25 * S6 * y * (5.0 * z2 - 1.0);
+        Y[3] = 0.5 * z * (5.0 * z2 - 3.0);
+        Y[4] = 0.25 * S6 * x * (5.0 * z2 - 1.0);
+        Y[5] = 0.5 * S15 * z * (x2 - y2);
+        Y[6] = 0.25 * S10 * x * (x2 - 3.0 * y2);
+    } else {
+        static_assert(L == 4, "degrees 1..4");
+        Y[0] = 0.5 * S35 * x * y * (x2 - y2);
+        Y[1] = 0.25 * S70 * y * z * (3.0 * x2 - y2);
+        Y[2] = 0.5 * S5 * x * y * (7.0 * z2 - 1.0);
+        Y[3] = 0.25 * S10 * y * z * (7.0 * z2 - 3.0);
+        Y[4] = 0.125 * (35.0 * z2 * z2 - 30.0 * z2 + 3.0);
+        Y[5] = 0.25 * S10 * x * z * (7.0 * z2 - 3.0);
+        Y[6] = 0.25 * S5 * (x2 - y2) * (7.0 * z2 - 1.0);
+        Y[7] = 0.25 * S70 * x * z * (x2 - 3.0 * y2);
+        Y[8] = 0.125 * S35 * (x2 * x2 - 6.0 * x2 * y2 + y2 * y2);
+    }
+}
+
 __host__ __device__ inline void sph_grad_contract(float x, float y, float z, const float Dc[NLM],
                                          float &vx, float &vy, float &vz)
 {

@@ -22,6 +22,14 @@ void nep_test_basis_d(double r, double rc, double *fc, double *T) { basis_d(r, 1
 
 void nep_test_sph(float x, float y, float z, float *Y) { sph(x, y, z, Y); }
 
+void nep_test_sph_d(double x, double y, double z, double *Y)
+{
+    sph_degree_d<1>(x, y, z, Y);
+    sph_degree_d<2>(x, y, z, Y + 3);
+    sph_degree_d<3>(x, y, z, Y + 8);
+    sph_degree_d<4>(x, y, z, Y + 15);
+}
+
 void nep_test_sph_grad(float x, float y, float z, const float *Dc, float *v)
 {
     sph_grad_contract(x, y, z, Dc, v[0], v[1], v[2]);

@@ -160,29 +160,51 @@ __device__ inline double dist_d(double r2)
     return rd + fma(-rd, rd, r2) * (double)(0.5f * frcp(rf));
 }
 
-// Descriptor of one atom: FP64 pair geometry and Chebyshev basis, FP32
-// harmonics and sums.  Returns the radial sums F_k = sum_j f_k(r_ij), the
-// angular sums S[n][lm] = sum_j g_n(r_ij) Y_lm(u_ij), and the ZBL half-energy.
-__device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const double4 *__restrict__ xq, int t,
-                                                double xi, double yi, double zi, const CellGeom *cg, int base,
-                                                const int32_t *__restrict__ nl_ang,
-                                                const int32_t *__restrict__ nl_rad, int naf, int nab, int nrf,
-                                                int nrb, const float *__restrict__ P, const float csA[NA],
-                                                float F[KB], float S[NA][NLM], double &ezbl, bool &overlap)
+// Angular radial functions g_n(r) = sum_k c_nk f_k(r) and the unit vector,
+// in double precision (C64: c^A_nk [NA][KB], then the row sums [NA]).
+__device__ inline void angular_g_d(double r, double dx, double dy, double dz, double inv_rA,
+                                   const double *__restrict__ C64, double g[NA], double &ux, double &uy,
+                                   double &uz)
 {
-    const double inv_rR = 1.0 / (double)pc.rc_rad, inv_rA = 1.0 / (double)pc.rc_ang;
-    const double rcR2 = (double)pc.rc_rad * pc.rc_rad, rcA2 = (double)pc.rc_ang * pc.rc_ang;
-    double AR[KB];
+    const float rf = (float)r;
+    double rinv = (double)frcp(rf);
+    rinv = rinv * fma(-r, rinv, 2.0);        // one Newton step: relative error ~1e-14
+    rinv = rinv * fma(-r, rinv, 2.0);
+    ux = dx * rinv;
+    uy = dy * rinv;
+    uz = dz * rinv;
+    double fc, T[KB];
+    basis_d(r, inv_rA, fc, T);
+    const double hfc = 0.5 * fc;
 #pragma unroll
-    for (int k = 0; k < KB; ++k) AR[k] = 0.0;
+    for (int n = 0; n < NA; ++n) {
+        double sn = C64[NA * KB + n];
 #pragma unroll
-    for (int n = 0; n < NA; ++n)
-#pragma unroll
-        for (int lm = 0; lm < NLM; ++lm) S[n][lm] = 0.0f;
-    ezbl = 0.0;
-    overlap = false;
+        for (int k = 0; k < KB; ++k) sn = fma(C64[n * KB + k], T[k], sn);
+        g[n] = hfc * sn;
+    }
+}
 
+// The l = 3 and l = 4 angular sums, S[n][lm] = sum_j g_n(r_ij) Y_lm(u_ij),
+// over the angular list: l = 3 formed and accumulated in double precision,
+// l = 4 in single precision (its sums do not cancel to the same degree near
+// a lattice site), both rounded once into S.
+__device__ __forceinline__ void angular_sums_l34(const PairConsts &pc, const double4 *__restrict__ xq, int t,
+                                                 double xi, double yi, double zi, const CellGeom *cg, int base,
+                                                 const int32_t *__restrict__ nl_ang, int naf, int nab,
+                                                 const double *__restrict__ C64, float S[NA][NLM])
+{
+    const double inv_rA = 1.0 / (double)pc.rc_ang, rcA2 = (double)pc.rc_ang * pc.rc_ang;
     const uint32_t jmask = (1u << pc.jbits) - 1u;
+    double A3[NA][7];
+    float A4[NA][9];
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+#pragma unroll
+        for (int m = 0; m < 7; ++m) A3[n][m] = 0.0;
+#pragma unroll
+        for (int m = 0; m < 9; ++m) A4[n][m] = 0.0f;
+    }
     for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
         int32_t e;
         double px, py, pz;
@@ -190,45 +212,98 @@ __device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const doub
         double dx, dy, dz;
         pair_vector_p(e, pc, px, py, pz, xi, yi, zi, cg, dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 >= rcR2) continue;
-        const double r = dist_d(r2);
-        overlap |= (r < 1e-3);
-        {
-            double fc, T[KB];
-            basis_d(r, inv_rR, fc, T);
+        if (r2 >= rcA2) continue;
+        double g[NA], ux, uy, uz;
+        angular_g_d(dist_d(r2), dx, dy, dz, inv_rA, C64, g, ux, uy, uz);
+        double Y3[7];
+        sph_degree_d<3>(ux, uy, uz, Y3);
+        float Y[NLM];
+        sph((float)ux, (float)uy, (float)uz, Y);
 #pragma unroll
-            for (int k = 0; k < KB; ++k) AR[k] = fma(fc, T[k], AR[k]);
+        for (int n = 0; n < NA; ++n) {
+#pragma unroll
+            for (int m = 0; m < 7; ++m) A3[n][m] = fma(g[n], Y3[m], A3[n][m]);
+            const float gf = (float)g[n];
+#pragma unroll
+            for (int m = 0; m < 9; ++m) A4[n][m] = fmaf(gf, Y[15 + m], A4[n][m]);
         }
-        if (r2 < rcA2) {
-            double fc, T[KB];
-            basis_d(r, inv_rA, fc, T);
-            // T_k carry the FP64 argument's accuracy; rounded once to FP32
-            // they enter g_n = sum_k c_nk f_k in single precision
-            float Tf[KB];
+    }
 #pragma unroll
-            for (int k = 0; k < KB; ++k) Tf[k] = (float)T[k];
-            const float hfc = (float)(0.5 * fc);
-            float g[NA];
+    for (int n = 0; n < NA; ++n) {
 #pragma unroll
-            for (int n = 0; n < NA; ++n) {
-                float s2 = csA[n];
+        for (int m = 0; m < 7; ++m) S[n][8 + m] = (float)A3[n][m];
 #pragma unroll
-                for (int k = 0; k < KB; ++k) s2 = fmaf(P[P_CA + n * KB + k], Tf[k], s2);
-                g[n] = hfc * s2;
+        for (int m = 0; m < 9; ++m) S[n][15 + m] = A4[n][m];
+    }
+}
+
+// Descriptor sums of one atom.  The radial sums F_k = sum_j f_k(r_ij) and
+// the angular sums S[n][lm] = sum_j g_n(r_ij) Y_lm(u_ij) for l <= 3 are
+// formed and accumulated in double precision: near a lattice site the odd-l
+// (and, in cubic crystals, the l = 2) sums are small differences of large
+// terms.  To keep the accumulators in registers the angular list is walked
+// twice: l = 1, 2 together with the radial and ZBL terms of that list, then
+// l = 3 (and l = 4 in single precision); the sums are rounded to single
+// precision after each pass.  Returns F, S and the ZBL half-energy.
+__device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const double4 *__restrict__ xq, int t,
+                                                double xi, double yi, double zi, const CellGeom *cg, int base,
+                                                const int32_t *__restrict__ nl_ang,
+                                                const int32_t *__restrict__ nl_rad, int naf, int nab, int nrf,
+                                                int nrb, const double *__restrict__ C64, float F[KB],
+                                                float S[NA][NLM], double &ezbl, bool &overlap)
+{
+    const double inv_rR = 1.0 / (double)pc.rc_rad, inv_rA = 1.0 / (double)pc.rc_ang;
+    const double rcR2 = (double)pc.rc_rad * pc.rc_rad, rcA2 = (double)pc.rc_ang * pc.rc_ang;
+    const uint32_t jmask = (1u << pc.jbits) - 1u;
+    double AR[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) AR[k] = 0.0;
+    ezbl = 0.0;
+    overlap = false;
+
+    {
+        double A[NA][8];
+#pragma unroll
+        for (int n = 0; n < NA; ++n)
+#pragma unroll
+            for (int m = 0; m < 8; ++m) A[n][m] = 0.0;
+        for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
+            int32_t e;
+            double px, py, pz;
+            q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
+            double dx, dy, dz;
+            pair_vector_p(e, pc, px, py, pz, xi, yi, zi, cg, dx, dy, dz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 >= rcR2) continue;
+            const double r = dist_d(r2);
+            overlap |= (r < 1e-3);
+            {
+                double fc, T[KB];
+                basis_d(r, inv_rR, fc, T);
+#pragma unroll
+                for (int k = 0; k < KB; ++k) AR[k] = fma(fc, T[k], AR[k]);
             }
-            const float rinv = frcp((float)r);
-            float Y[NLM];
-            sph((float)dx * rinv, (float)dy * rinv, (float)dz * rinv, Y);
+            if (r2 < rcA2) {
+                double g[NA], ux, uy, uz;
+                angular_g_d(r, dx, dy, dz, inv_rA, C64, g, ux, uy, uz);
+                double Y[8];
+                sph_degree_d<1>(ux, uy, uz, Y);
+                sph_degree_d<2>(ux, uy, uz, Y + 3);
 #pragma unroll
-            for (int n = 0; n < NA; ++n)
+                for (int n = 0; n < NA; ++n)
 #pragma unroll
-                for (int lm = 0; lm < NLM; ++lm) S[n][lm] = fmaf(g[n], Y[lm], S[n][lm]);
+                    for (int m = 0; m < 8; ++m) A[n][m] = fma(g[n], Y[m], A[n][m]);
+            }
+            if (r < (double)pc.zbl_r2) {
+                double U, dU;
+                zbl_pair(r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
+                ezbl += 0.5 * U;
+            }
         }
-        if (r < (double)pc.zbl_r2) {
-            double U, dU;
-            zbl_pair(r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
-            ezbl += 0.5 * U;
-        }
+#pragma unroll
+        for (int n = 0; n < NA; ++n)
+#pragma unroll
+            for (int m = 0; m < 8; ++m) S[n][m] = (float)A[n][m];
     }
     for (NeighbourPipe q(nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.s < q.count;) {
         int32_t e;
@@ -245,6 +320,7 @@ __device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const doub
     }
 #pragma unroll
     for (int k = 0; k < KB; ++k) F[k] = (float)(0.5 * (AR[k] + AR[0]));
+    angular_sums_l34(pc, xq, t, xi, yi, zi, cg, base, nl_ang, naf, nab, C64, S);
 }
 
 // Descriptor vector q from the sums (radial q_n = sum_k c_nk F_k, angular q_nl = sum_m S^2).
@@ -324,7 +400,10 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 struct NNLds {
-    __bf16 q[64][40];    // rows of 32 used; stride 80 B keeps 16 B alignment
+    union {
+        __bf16 q[64][40];    // BF16 operands: rows of 32 used; stride 80 B keeps 16 B alignment
+        float qf[64][33];    // FP32 operands
+    };
     float z[64][33];
 };
 
@@ -393,6 +472,66 @@ __device__ __forceinline__ float network_mfma(const float *__restrict__ P, const
     return U;
 }
 
+// The same two products with FP32 operands on the matrix cores
+// (v_mfma_f32_32x32x2_f32: exact FP32 products, FP32 accumulation), sixteen
+// K steps of two per 32 x 32 tile.  Operand layouts (lane l): A[l%32][l/32],
+// B[l/32][l%32]; the result layout is that of the BF16 product.
+__device__ __forceinline__ float network_mfma32(const float *__restrict__ P, const float q[DIM], float Fp[DIM],
+                                                NNLds *L)
+{
+    const int lane = threadIdx.x & 63;
+    const int hi = lane >> 5, lo = lane & 31;
+#pragma unroll
+    for (int nu = 0; nu < 32; ++nu) L->qf[lane][nu] = nu < DIM ? P[P_QS + nu] * q[nu] : 0.0f;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int T = 0; T < 2; ++T) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            const int k = 2 * st + hi;
+            const float a = (lo < NH && k < DIM) ? P[P_W0 + lo * DIM + k] : 0.0f;
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, L->qf[32 * T + lo][k], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) L->z[32 * T + lo][8 * (v >> 2) + 4 * hi + (v & 3)] = acc[v];
+    }
+    __builtin_amdgcn_wave_barrier();
+    float U = -P[P_B1];
+    float dz[32];
+#pragma unroll
+    for (int mu = 0; mu < 32; ++mu) {
+        if (mu < NH) {
+            const float th = ftanh(L->z[lane][mu] - P[P_B0 + mu]);
+            U = fmaf(P[P_W1 + mu], th, U);
+            dz[mu] = P[P_W1 + mu] * fmaf(-th, th, 1.0f);
+        } else {
+            dz[mu] = 0.0f;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int mu = 0; mu < 32; ++mu) L->qf[lane][mu] = dz[mu];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int T = 0; T < 2; ++T) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            const int k = 2 * st + hi;
+            const float a = (k < NH && lo < DIM) ? P[P_W0 + k * DIM + lo] : 0.0f;
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, L->qf[32 * T + lo][k], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) L->z[32 * T + lo][8 * (v >> 2) + 4 * hi + (v & 3)] = acc[v];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int nu = 0; nu < DIM; ++nu) Fp[nu] = L->z[lane][nu] * P[P_QS + nu];
+    __builtin_amdgcn_wave_barrier();
+    return U;
+}
+
 // Descriptor, site energy, network forward and backward, the radial adjoint
 // dU_i/dF_k (stored in the atom's record), and then, with
 // B_{n,lm} = dU_i/ds_{n,lm} kept in registers, the gradient of U_i with
@@ -405,7 +544,7 @@ __device__ __forceinline__ void descriptor_atom(
     int t, bool valid, NNLds *L, const PairConsts &pc, const double4 *__restrict__ xq, AtomRec *__restrict__ xp,
     const int32_t *__restrict__ cell_of, const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
-    const float *__restrict__ P, float4 *__restrict__ pair_grad,
+    const float *__restrict__ P, const double *__restrict__ C64, float4 *__restrict__ pair_grad,
     float4 *__restrict__ f_own, float *__restrict__ w_atom, double *__restrict__ e_atom,
     int32_t *__restrict__ status)
 {
@@ -426,13 +565,14 @@ __device__ __forceinline__ void descriptor_atom(
     float S[NA][NLM];
     double ezbl;
     bool overlap;
-    descriptor_sums(pc, xq, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, P, csA, F, S, ezbl,
+    descriptor_sums(pc, xq, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, C64, F, S, ezbl,
                     overlap);
     if (overlap) latch_error(status, -4);
     float q[DIM];
     descriptor_vector(P, F, S, q);
     float Fp[DIM];
-    const float U = NNMODE == 1 ? network_mfma(P, q, Fp, L) : network(P, q, Fp);
+    const float U = NNMODE == 1 ? network_mfma(P, q, Fp, L)
+                                : (NNMODE == 2 ? network_mfma32(P, q, Fp, L) : network(P, q, Fp));
     if (!valid) return;
     e_atom[t] = (double)U + ezbl;
     // this atom's record for the force kernel: position and radial adjoint
@@ -543,25 +683,25 @@ __global__ __launch_bounds__(BS, NNMODE == 1 ? 1 : 2) void k_descriptor(
     PairConsts pc, const double4 *__restrict__ xq, AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
-    const float *__restrict__ P, float4 *__restrict__ pair_grad,
+    const float *__restrict__ P, const double *__restrict__ C64, float4 *__restrict__ pair_grad,
     float4 *__restrict__ f_own, float *__restrict__ w_atom, double *__restrict__ e_atom,
     int32_t *__restrict__ status, int ntiles)
 {
-    __shared__ NNLds lds[NNMODE == 1 ? BS / 64 : 1];
-    NNLds *L = &lds[NNMODE == 1 ? threadIdx.x / 64 : 0];
+    __shared__ NNLds lds[NNMODE != 0 ? BS / 64 : 1];
+    NNLds *L = &lds[NNMODE != 0 ? threadIdx.x / 64 : 0];
     if (status[ST_ERR] != 0) return;
     if (PERSISTENT) {
         for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
             const int t = tile * BS + threadIdx.x;
-            if (NNMODE == 1 || t < pc.n)
-                descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xq, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, pair_grad,
+            if (NNMODE != 0 || t < pc.n)
+                descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xq, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, C64, pair_grad,
                                         f_own, w_atom, e_atom, status);
         }
     } else {
         const int tile = xcd_block(ntiles);
         const int t = tile * BS + threadIdx.x;
-        if (tile < ntiles && (NNMODE == 1 || t < pc.n))
-            descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xq, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, pair_grad,
+        if (tile < ntiles && (NNMODE != 0 || t < pc.n))
+            descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xq, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, C64, pair_grad,
                                     f_own, w_atom, e_atom, status);
     }
 }
@@ -741,12 +881,17 @@ __global__ __launch_bounds__(BS) void k_force(
     template __global__ void k_descriptor<BS, PE, 0>(PairConsts, const double4 *, AtomRec *, const int32_t *,      \
                                                      const CellGeom *,                                             \
                                                      const int32_t *, const int32_t *, const uint32_t *,           \
-                                                     const float *, float4 *, float4 *, float *, double *, int32_t *, \
+                                                     const float *, const double *, float4 *, float4 *, float *, double *, int32_t *, \
                                                      int);                                                           \
     template __global__ void k_descriptor<BS, PE, 1>(PairConsts, const double4 *, AtomRec *, const int32_t *,      \
                                                      const CellGeom *,                                             \
                                                      const int32_t *, const int32_t *, const uint32_t *,           \
-                                                     const float *, float4 *, float4 *, float *, double *, int32_t *, \
+                                                     const float *, const double *, float4 *, float4 *, float *, double *, int32_t *, \
+                                                     int);                                                           \
+    template __global__ void k_descriptor<BS, PE, 2>(PairConsts, const double4 *, AtomRec *, const int32_t *,      \
+                                                     const CellGeom *,                                             \
+                                                     const int32_t *, const int32_t *, const uint32_t *,           \
+                                                     const float *, const double *, float4 *, float4 *, float *, double *, int32_t *, \
                                                      int);                                                           \
     template __global__ void k_force<BS, PE>(PairConsts, const AtomRec *, const int32_t *, const CellGeom *,       \
                                              const int32_t *, const int32_t *, const uint32_t *, const uint8_t *,   \
@@ -754,6 +899,19 @@ __global__ __launch_bounds__(BS) void k_force(
                                              float *, float *, int32_t *, int);
 NEP_SHAPES(NEP_INST)
 #undef NEP_INST
+
+// Double-precision copy of the angular coefficients for the descriptor sums:
+// C64 = (c^A_nk [NA][KB], sum_k c^A_nk [NA]).  One block of 64 threads.
+__global__ void k_params64(const float *__restrict__ P, double *__restrict__ C64)
+{
+    const int i = threadIdx.x;
+    if (i < NA * KB) C64[i] = (double)P[P_CA + i];
+    if (i < NA) {
+        double s = 0.0;
+        for (int k = 0; k < KB; ++k) s += (double)P[P_CA + i * KB + k];
+        C64[NA * KB + i] = s;
+    }
+}
 
 // ------------------------------------------------------------------ parameter gradients
 
@@ -776,7 +934,7 @@ __global__ __launch_bounds__(64) void k_param_grad(
     PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt, const float *__restrict__ P,
-    const double *__restrict__ gE, double *__restrict__ part, const int32_t *__restrict__ status, int ntiles)
+    const double *__restrict__ C64, const double *__restrict__ gE, double *__restrict__ part, const int32_t *__restrict__ status, int ntiles)
 {
     __shared__ float rec[PG_TILE][PG_REC + 1];
     constexpr int NOWN = (NPARAM + PG_TILE - 1) / PG_TILE;
@@ -803,7 +961,7 @@ __global__ __launch_bounds__(64) void k_param_grad(
             float S[NA][NLM];
             double ezbl;
             bool overlap;
-            descriptor_sums(pc, xq, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, P, csA, F, S,
+            descriptor_sums(pc, xq, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, C64, F, S,
                             ezbl, overlap);
             float q[DIM];
             descriptor_vector(P, F, S, q);

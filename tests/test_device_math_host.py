@@ -26,6 +26,7 @@ def L():
     lib.nep_test_cheb.argtypes = [F, FP, FP]
     lib.nep_test_basis_d.argtypes = [C.c_double, C.c_double, DP, DP]
     lib.nep_test_sph.argtypes = [F, F, F, FP]
+    lib.nep_test_sph_d.argtypes = [C.c_double, C.c_double, C.c_double, DP]
     lib.nep_test_sph_grad.argtypes = [F, F, F, FP, FP]
     lib.nep_test_zbl.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, DP, DP]
     lib.nep_test_decode.argtypes = [C.c_int32, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
@@ -103,6 +104,27 @@ def test_harmonics_addition_theorem(L):
             # same span as scipy's complex harmonics: sum_m |Y_lm|^2 agree
             ca = _real_sh_scaled(l, u)
             assert abs(np.sum(Ya[lo[l - 1]:lo[l]] ** 2) - 4 * math.pi / (2 * l + 1) * np.sum(np.abs(ca) ** 2)) < 2e-6
+
+
+def test_double_harmonics_addition_theorem_and_single_agreement(L):
+    # the FP64 degree-by-degree harmonics used for the descriptor sums: the
+    # addition theorem to FP64 accuracy, and the same functions as sph
+    rng = np.random.default_rng(4)
+    Ya, Yb = np.zeros(24), np.zeros(24)
+    Yf = _f32(24)
+    lo = [0, 3, 8, 15, 24]
+    for _ in range(50):
+        u = rng.normal(size=3); u /= np.linalg.norm(u)
+        v = rng.normal(size=3); v /= np.linalg.norm(v)
+        L.nep_test_sph_d(*u, Ya.ctypes.data_as(DP))
+        L.nep_test_sph_d(*v, Yb.ctypes.data_as(DP))
+        for l in range(1, 5):
+            got = float(np.dot(Ya[lo[l - 1]:lo[l]], Yb[lo[l - 1]:lo[l]]))
+            assert abs(got - sp.eval_legendre(l, float(u @ v))) < 1e-13
+        uf = u.astype(np.float32)
+        L.nep_test_sph(*uf, _fp(Yf))
+        L.nep_test_sph_d(*uf.astype(np.float64), Ya.ctypes.data_as(DP))
+        assert np.allclose(Yf, Ya, atol=3e-6)
 
 
 def test_harmonics_parity(L):

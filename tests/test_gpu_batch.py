@@ -110,3 +110,24 @@ def test_bf16_hidden_layer_error_vs_fp64():
     assert eb <= 3e-2
     assert eb > e32        # the reduced precision is visible, i.e. the MFMA path really ran
     ctx.nep_set_precision(0)
+
+
+def test_fp32_matrix_core_hidden_layer_matches_oracle():
+    # mode 2 keeps FP32 operands (exact products, FP32 sums in another
+    # order), so it meets the same bars as the vector-ALU path
+    import torch
+    m = nep_synth.random_model()
+    full = nep_synth.batch()
+    s = _subset(full, range(5, 4096, 64))
+    sysd, ctx, out = _setup(s, m)
+    ctx.nep_set_precision(2)
+    ctx.nep_compute_efv(sysd, out)
+    torch.cuda.synchronize()
+    E, F, W = _snap(out)
+    ctx.nep_set_precision(0)
+    ref = oracle.efv_system(m, s)
+    counts = np.diff(s.cell_start)
+    assert np.all(np.abs(E - ref["energy"]) / counts <= E_ATOM_TOL)
+    err = np.linalg.norm(F - ref["forces"]) / np.linalg.norm(ref["forces"])
+    print(f"[precision] force rel err FP32-MFMA {err:.2e}", flush=True)
+    assert err <= F_REL_TOL
