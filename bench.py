@@ -347,6 +347,9 @@ def main():
     idx = np.unique(np.concatenate([idx, [pka]]))
     ref = oracle.efv_cell(model, pos_now, s.h[0], targets=idx, virial=False)
     ferr = float(np.linalg.norm(F_gpu[idx] - ref["forces"]) / np.linalg.norm(ref["forces"]))
+    # the PKA's force dominates that norm: the sampled thermal atoms on their own
+    th = idx != pka
+    ferr_th = float(np.linalg.norm(F_gpu[idx[th]] - ref["forces"][th]) / np.linalg.norm(ref["forces"][th]))
     eerr = float(np.max(np.abs(out.energy_atom.cpu().numpy()[idx].astype(np.float64) - ref["energy_atom"])))
 
     batches = None
@@ -376,7 +379,8 @@ def main():
         "kernel_tflops": {"descriptor": f_desc * N / (ktimes["descriptor"] * 1e-3) / 1e12,
                           "force": f_force * N / (ktimes["force"] * 1e-3) / 1e12},
         "md": {"n_rebuilds": stats["n_rebuilds"], "dt_last_fs": stats["dt_last"], "time_fs": stats["time"]},
-        "force_rel_err_vs_fp64": ferr, "site_energy_max_abs_err_eV": eerr,
+        "force_rel_err_vs_fp64": ferr, "force_rel_err_vs_fp64_thermal_atoms": ferr_th,
+        "site_energy_max_abs_err_eV": eerr,
         "batches": batches,
     }
     print(json.dumps(line), flush=True)
