@@ -352,6 +352,23 @@ def main():
     ferr_th = float(np.linalg.norm(F_gpu[idx[th]] - ref["forces"][th]) / np.linalg.norm(ref["forces"][th]))
     eerr = float(np.max(np.abs(out.energy_atom.cpu().numpy()[idx].astype(np.float64) - ref["energy_atom"])))
 
+    # Wigner-Seitz defect analysis of the final configuration (HBM-bound:
+    # positions read, one occupancy update per atom, occupancy cleared and scanned)
+    ws_ref_cells = (args.cells, args.cells, args.cells)
+    res_ws = nep.wigner_seitz(sysd, nep_synth.A_W, ws_ref_cells)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        res_ws = nep.wigner_seitz(sysd, nep_synth.A_W, ws_ref_cells)
+    torch.cuda.synchronize()
+    t_ws = (time.perf_counter() - t0) / 5
+    m_sites = 2 * args.cells ** 3
+    ws_bytes = 24 * N + 8 * N + 3 * 4 * m_sites
+    defects = {"ms": t_ws * 1e3, "algorithmic_bytes": ws_bytes, "GB_per_s": ws_bytes / t_ws / 1e9,
+               "n_vacancies": res_ws["n_vacancies"], "n_interstitials": res_ws["n_interstitials"],
+               "n_vacancy_clusters": res_ws["n_vacancy_clusters"],
+               "n_interstitial_clusters": res_ws["n_interstitial_clusters"]}
+
     batches = None
     if not args.no_batches:
         del ctx, sysd, out
@@ -381,6 +398,7 @@ def main():
         "md": {"n_rebuilds": stats["n_rebuilds"], "dt_last_fs": stats["dt_last"], "time_fs": stats["time"]},
         "force_rel_err_vs_fp64": ferr, "force_rel_err_vs_fp64_thermal_atoms": ferr_th,
         "site_energy_max_abs_err_eV": eerr,
+        "defects": defects,
         "batches": batches,
     }
     print(json.dumps(line), flush=True)

@@ -49,6 +49,7 @@ extern "C" {
 #define NEP_E_STATE           -7  /* call order: nep_compute_efv before nep_build_neighbors on this system */
 #define NEP_E_UNSUPPORTED     -8  /* hyperparameters for which no kernel is compiled */
 #define NEP_E_INTERNAL        -9  /* internal consistency check failed (neighbour lists not symmetric) */
+#define NEP_E_CAPACITY       -10  /* more defect sites than the caller's arrays hold */
 
 typedef struct nep_ctx nep_ctx;
 
@@ -231,6 +232,57 @@ int nep_backward(nep_ctx *ctx, const nep_system *sys, const nep_efv *out, const 
  *   ms[2] force + virial kernel, ms[3] energy / virial reductions.
  * Synchronises `stream`.  Same preconditions as nep_compute_efv. */
 int nep_time_efv(nep_ctx *ctx, const nep_system *sys, nep_efv *out, int32_t reps, double *ms, void *stream);
+
+/* ---- defect analysis -------------------------------------------------- */
+
+/* Reference lattice of the Wigner-Seitz analysis: perfect bcc, lattice
+ * constant a, n[0] x n[1] x n[2] conventional cells filling the periodic box
+ * diag(n[0] a, n[1] a, n[2] a).  Site ids: 2 ((k n1 + j) n0 + i) + b with
+ * b = 0 for the corner (i, j, k) a and b = 1 for the body centre
+ * (i + 1/2, j + 1/2, k + 1/2) a. */
+typedef struct {
+    double a;
+    int32_t n[3];
+    int32_t pad_;
+} nep_bcc_ref;
+
+typedef struct {
+    int64_t n_vacancies;             /* sites holding no atom */
+    int64_t n_interstitial_sites;    /* sites holding more than one atom */
+    int64_t n_interstitials;         /* atoms beyond one per site */
+    int32_t n_vacancy_clusters, largest_vacancy_cluster;           /* sizes in vacancies */
+    int32_t n_interstitial_clusters, largest_interstitial_cluster; /* sizes in interstitial atoms */
+} nep_defects;
+
+#define NEP_WS_WORK_INTS 8
+
+/* Wigner-Seitz defect analysis (the paper's identification of vacancies and
+ * interstitials and their clustering, Methods): every atom is assigned to
+ * the nearest reference site; a site with no atom is a vacancy, a site with
+ * k > 1 atoms holds k - 1 interstitials.  Vacancy sites within the
+ * second-neighbour distance a of each other, and interstitial sites within
+ * the third-neighbour distance a sqrt(2), form clusters (connected
+ * components, minimum-image distances).
+ *   sys           one periodic cell (cell_start NULL or one cell) whose h is
+ *                 diag(n a) to 1e-9 relative; positions DEVICE, any image
+ *   occupancy     DEVICE int32[2 n0 n1 n2], written (atoms per site)
+ *   site_of_atom  DEVICE int32[n_atoms] or NULL, written (site of every atom)
+ *   capacity      length of each of the five arrays below
+ *   vacancy_sites, interstitial_sites   DEVICE int32[capacity], written,
+ *                 ascending site ids; interstitial_mult: atoms beyond one
+ *   vacancy_cluster, interstitial_cluster  DEVICE int32[capacity], written:
+ *                 cluster label of each listed site (index of the first
+ *                 site of its cluster in the list)
+ *   work          DEVICE int32[NEP_WS_WORK_INTS], scratch
+ *   out           HOST, written
+ * Exact ties between two sites go to the corner site.  Synchronises
+ * `stream`.  Returns NEP_OK, NEP_E_ARG, NEP_E_NONFINITE (a position is not
+ * finite or is beyond 1e8 a), NEP_E_CAPACITY (more vacancy or interstitial
+ * sites than capacity; out holds the counts) or NEP_E_HIP. */
+int nep_wigner_seitz(const nep_system *sys, const nep_bcc_ref *ref, int32_t *occupancy, int32_t *site_of_atom,
+                     int32_t capacity, int32_t *vacancy_sites, int32_t *vacancy_cluster,
+                     int32_t *interstitial_sites, int32_t *interstitial_mult, int32_t *interstitial_cluster,
+                     int32_t *work, nep_defects *out, void *stream);
 
 /* Static description of an error code. */
 const char *nep_strerror(int code);

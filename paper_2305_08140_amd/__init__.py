@@ -28,11 +28,13 @@ NEP_E_DT_UNDERFLOW = -6
 NEP_E_STATE = -7
 NEP_E_UNSUPPORTED = -8
 NEP_E_INTERNAL = -9
+NEP_E_CAPACITY = -10
+NEP_WS_WORK_INTS = 8
 
 EXPORTED = ("nep_create", "nep_destroy", "nep_set_weights", "nep_build_neighbors", "nep_compute_efv",
             "nep_step_verlet", "nep_status", "nep_required_neighbors", "nep_mean_neighbors",
             "nep_time_efv", "nep_num_params", "nep_backward", "nep_compute_efv_graph", "nep_autotune",
-            "nep_set_precision", "nep_strerror")
+            "nep_set_precision", "nep_wigner_seitz", "nep_strerror")
 
 
 class NepError(RuntimeError):
@@ -75,6 +77,16 @@ class Md(C.Structure):
                 ("forces_valid", C.c_int32), ("pad_", C.c_int32)]
 
 
+class BccRef(C.Structure):
+    _fields_ = [("a", C.c_double), ("n", C.c_int32 * 3), ("pad_", C.c_int32)]
+
+
+class Defects(C.Structure):
+    _fields_ = [("n_vacancies", C.c_int64), ("n_interstitial_sites", C.c_int64), ("n_interstitials", C.c_int64),
+                ("n_vacancy_clusters", C.c_int32), ("largest_vacancy_cluster", C.c_int32),
+                ("n_interstitial_clusters", C.c_int32), ("largest_interstitial_cluster", C.c_int32)]
+
+
 class MdStats(C.Structure):
     _fields_ = [("n_rebuilds", C.c_int64), ("dt_last", C.c_double), ("time", C.c_double)]
 
@@ -107,6 +119,8 @@ def lib():
         L.nep_compute_efv_graph.argtypes = [P, C.POINTER(System), C.POINTER(Efv), P]
         L.nep_autotune.argtypes = [P, C.POINTER(System), C.POINTER(Efv), C.c_int32, C.POINTER(C.c_int32), P]
         L.nep_backward.argtypes = [P, C.POINTER(System), C.POINTER(Efv), P, P, P, P, P, P, P]
+        L.nep_wigner_seitz.argtypes = [C.POINTER(System), C.POINTER(BccRef), P, P, C.c_int32, P, P, P, P, P, P,
+                                       C.POINTER(Defects), P]
         L.nep_strerror.argtypes = [C.c_int]
         L.nep_strerror.restype = C.c_char_p
         for name in EXPORTED:
@@ -351,3 +365,33 @@ def efv(model, system: DeviceSystem, ctx: Context | None = None, max_neigh_ang=4
     ctx.nep_build_neighbors(system)
     ctx.nep_compute_efv(system, out)
     return out, ctx
+
+
+def wigner_seitz(system: "DeviceSystem", a: float, n_cells, capacity: int = 65536, site_of_atom: bool = False,
+                 stream=None):
+    """nep_wigner_seitz on a one-cell system against the perfect bcc lattice of
+    n_cells conventional cells of constant a.  Returns the summary and device
+    tensors: occupancy, sorted vacancy / interstitial sites, interstitial
+    multiplicities, cluster labels (and the site of every atom if asked)."""
+    torch = _torch()
+    n0, n1, n2 = (int(v) for v in n_cells)
+    dev = system.x.device
+    i32 = dict(dtype=torch.int32, device=dev)
+    occ = torch.empty(2 * n0 * n1 * n2, **i32)
+    site = torch.empty(system.n_atoms, **i32) if site_of_atom else None
+    arr = [torch.empty(max(capacity, 1), **i32) for _ in range(5)]
+    work = torch.empty(NEP_WS_WORK_INTS, **i32)
+    ref = BccRef(float(a), (C.c_int32 * 3)(n0, n1, n2), 0)
+    out = Defects()
+    s = system.c_struct()
+    code = lib().nep_wigner_seitz(C.byref(s), C.byref(ref), occ.data_ptr(), site.data_ptr() if site is not None
+                                  else None, int(capacity), arr[0].data_ptr(), arr[1].data_ptr(),
+                                  arr[2].data_ptr(), arr[3].data_ptr(), arr[4].data_ptr(), work.data_ptr(),
+                                  C.byref(out), _stream_ptr(stream))
+    _check(code, "nep_wigner_seitz")
+    nv, ni = int(out.n_vacancies), int(out.n_interstitial_sites)
+    res = {k: getattr(out, k) for k, _ in Defects._fields_}
+    res.update(occupancy=occ, vacancy_sites=arr[0][:nv], vacancy_cluster=arr[1][:nv],
+               interstitial_sites=arr[2][:ni], interstitial_mult=arr[3][:ni], interstitial_cluster=arr[4][:ni],
+               site_of_atom=site)
+    return res

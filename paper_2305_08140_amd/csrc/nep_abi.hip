@@ -36,6 +36,15 @@ __global__ void k_grad_cell(const CellGeom *, const double *, const double *, co
 __global__ void k_count_inside(PairConsts, const double4 *, const int32_t *,
                                const CellGeom *, const int32_t *, const int32_t *, const uint32_t *,
                                unsigned long long *);
+// kernels (nep_defects.hip)
+__global__ void k_ws_fill(int, int32_t *, int32_t);
+__global__ void k_ws_assign(int, const double *, const double *, const double *, BccRef, int32_t *, int32_t *,
+                            int32_t *);
+__global__ void k_ws_collect(int, const int32_t *, int, int32_t *, int32_t *, int32_t *);
+__global__ void k_ws_sort(int, const int32_t *, int32_t *, const int32_t *, int32_t *);
+__global__ void k_ws_label_init(int, int32_t *);
+__global__ void k_ws_label_step(int, const int32_t *, double, BccRef, int32_t *, int32_t *);
+__global__ void k_ws_cluster_sizes(int, const int32_t *, const int32_t *, int32_t *);
 // kernels (nep_build.hip)
 __global__ void k_fill_i32(int, int32_t *, int32_t, const int32_t *);
 __global__ void k_bin_assign(int, const double *, const double *, const double *, const int32_t *,
@@ -175,6 +184,7 @@ const char *nep_strerror(int code)
     case NEP_E_STATE: return "neighbour lists not built for this system";
     case NEP_E_UNSUPPORTED: return "hyperparameters not supported by the compiled kernels";
     case NEP_E_INTERNAL: return "internal consistency check failed (asymmetric neighbour lists)";
+    case NEP_E_CAPACITY: return "more defect sites than the arrays hold";
     default: return "unknown error";
     }
 }
@@ -911,6 +921,91 @@ int nep_step_verlet(nep_ctx *c, nep_system *s, const nep_md *md, int32_t n_steps
         HIP_TRY(hipMemcpy(c->status + ST_ERR, &zero, 4, hipMemcpyHostToDevice));
     }
     return code;
+}
+
+
+// ---------------------------------------------------------------- defects
+
+// Minimum-label propagation until no label changes (at most d_n rounds:
+// every round that changes something lowers some label).
+static int ws_cluster(int d_n, const int32_t *sites, double cut2, const BccRef &r, int32_t *label,
+                      int32_t *flag_d, int32_t *flag_h, hipStream_t st)
+{
+    if (d_n == 0) return NEP_OK;
+    const int g = (d_n + 255) / 256;
+    k_ws_label_init<<<g, 256, 0, st>>>(d_n, label);
+    for (int it = 0; it <= d_n; ++it) {
+        k_ws_fill<<<1, 64, 0, st>>>(1, flag_d, 0);
+        k_ws_label_step<<<g, 256, 0, st>>>(d_n, sites, cut2, r, label, flag_d);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(flag_h, flag_d, 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (*flag_h == 0) return NEP_OK;
+    }
+    return NEP_E_INTERNAL;
+}
+
+int nep_wigner_seitz(const nep_system *s, const nep_bcc_ref *ref, int32_t *occ, int32_t *site_of_atom,
+                     int32_t cap, int32_t *vac_sites, int32_t *vac_label, int32_t *int_sites, int32_t *int_mult,
+                     int32_t *int_label, int32_t *work, nep_defects *out, void *stream)
+{
+    if (!s || !ref || !occ || !work || !out || !s->x || !s->y || !s->z || !s->h) return NEP_E_ARG;
+    if (cap < 0 || (cap > 0 && (!vac_sites || !vac_label || !int_sites || !int_mult || !int_label))) return NEP_E_ARG;
+    if (s->cell_start && s->n_cells != 1) return NEP_E_ARG;
+    if (s->n_atoms <= 0 || s->n_atoms > (1LL << 30) || !(ref->a > 0.0)) return NEP_E_ARG;
+    for (int a = 0; a < 3; ++a)
+        if (ref->n[a] <= 0 || ref->n[a] > (1 << 10)) return NEP_E_ARG;
+    if (2LL * ref->n[0] * ref->n[1] * ref->n[2] > (1LL << 30)) return NEP_E_ARG;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const double want = a == b ? ref->n[a] * ref->a : 0.0;
+            if (fabs(s->h[3 * a + b] - want) > 1e-9 * ref->n[a] * ref->a) return NEP_E_ARG;
+        }
+    hipStream_t st = (hipStream_t)stream;
+    BccRef r;
+    r.a = ref->a;
+    r.inv_a = 1.0 / ref->a;
+    for (int a = 0; a < 3; ++a) r.n[a] = ref->n[a];
+    const int m = 2 * ref->n[0] * ref->n[1] * ref->n[2];
+    const int n = (int)s->n_atoms;
+    // work: [0..2] collect counters, [3] bad position (then the propagation
+    // flag), [4..5] vacancy cluster count / largest, [6..7] the same for
+    // interstitials
+    int32_t h[NEP_WS_WORK_INTS];
+    k_ws_fill<<<(m + 255) / 256, 256, 0, st>>>(m, occ, 0);
+    k_ws_fill<<<1, 64, 0, st>>>(NEP_WS_WORK_INTS, work, 0);
+    k_ws_assign<<<(n + 255) / 256, 256, 0, st>>>(n, s->x, s->y, s->z, r, occ, site_of_atom, work + 3);
+    k_ws_collect<<<(m + 255) / 256, 256, 0, st>>>(m, occ, cap, vac_label, int_label, work);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(h, work, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    out->n_vacancies = h[0];
+    out->n_interstitial_sites = h[1];
+    out->n_interstitials = h[2];
+    out->n_vacancy_clusters = out->largest_vacancy_cluster = 0;
+    out->n_interstitial_clusters = out->largest_interstitial_cluster = 0;
+    if (h[3]) return NEP_E_NONFINITE;
+    if (h[0] > cap || h[1] > cap) return NEP_E_CAPACITY;
+    const int nv = h[0], ni = h[1];
+    // sorted lists (the label arrays held the unsorted ones)
+    if (nv) k_ws_sort<<<(nv + 255) / 256, 256, 0, st>>>(nv, vac_label, vac_sites, occ, nullptr);
+    if (ni) k_ws_sort<<<(ni + 255) / 256, 256, 0, st>>>(ni, int_label, int_sites, occ, int_mult);
+    HIP_TRY(hipGetLastError());
+    int32_t flag_h = 0;
+    const double a2 = ref->a * ref->a * (1.0 + 1e-9);
+    int rc = ws_cluster(nv, vac_sites, a2, r, vac_label, work + 3, &flag_h, st);
+    if (rc == NEP_OK) rc = ws_cluster(ni, int_sites, 2.0 * a2, r, int_label, work + 3, &flag_h, st);
+    if (rc != NEP_OK) return rc;
+    if (nv) k_ws_cluster_sizes<<<(nv + 255) / 256, 256, 0, st>>>(nv, vac_label, nullptr, work + 4);
+    if (ni) k_ws_cluster_sizes<<<(ni + 255) / 256, 256, 0, st>>>(ni, int_label, int_mult, work + 6);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(h, work, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    out->n_vacancy_clusters = h[4];
+    out->largest_vacancy_cluster = h[5];
+    out->n_interstitial_clusters = h[6];
+    out->largest_interstitial_cluster = h[7];
+    return NEP_OK;
 }
 
 }  // extern "C"

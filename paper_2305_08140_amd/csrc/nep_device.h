@@ -58,6 +58,13 @@ struct PairConsts {
     int n;                            // atoms (list stride)
 };
 
+// Reference lattice of the Wigner-Seitz analysis (perfect bcc, cubic
+// constant a, n[0] x n[1] x n[2] conventional cells).
+struct BccRef {
+    double a, inv_a;
+    int n[3];
+};
+
 struct CellGeom {
     double h[9];       // rows: lattice vectors
     double hinv[9];    // x = s h  =>  s = x hinv
