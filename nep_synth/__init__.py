@@ -113,7 +113,13 @@ def load_scales(path: str = SCALES_PATH):
         return json.load(f)
 
 
-def random_model(seed: int = SEEDS["model"], scaled: bool = True) -> Model:
+# The paper's own hyperparameters (Sec. III.A): Chebyshev expansion orders
+# n_max^R = 15 and n_max^A = 10 (16 and 11 radial functions on as many basis
+# functions), l_max = 4, 100 hidden neurons; same cutoffs.
+PAPER_DIMS = {"n_rad": 16, "n_ang": 11, "k_rad": 16, "k_ang": 11, "l_max": 4, "n_hidden": 100}
+
+
+def random_model(seed: int = SEEDS["model"], scaled: bool = True, size: str = "small") -> Model:
     """Random NEP model.
 
     c ~ U(-1, 1); w0 ~ N(0, 1/D); b0 ~ N(0, 0.1^2); w1 ~ N(0, 1/H); b1 = 0.
@@ -121,8 +127,11 @@ def random_model(seed: int = SEEDS["model"], scaled: bool = True) -> Model:
     w1 are taken from ``model_scales.json`` (q_scale = 1 / RMS descriptor on
     the tiny workload; kappa chosen so that the RMS non-ZBL force there is
     1 eV/A and the lattice is restoring).  Without it q_scale = 1, kappa = 1.
+    ``size="paper"`` gives the paper's hyperparameters (PAPER_DIMS).
     """
-    m = Model()
+    if size not in ("small", "paper"):
+        raise ValueError(size)
+    m = Model() if size == "small" else Model(**PAPER_DIMS)
     rng = np.random.Generator(np.random.PCG64(seed))
     D, H = m.dim, m.n_hidden
     m.c_rad = rng.uniform(-1.0, 1.0, size=(m.n_rad, m.k_rad))
@@ -134,8 +143,10 @@ def random_model(seed: int = SEEDS["model"], scaled: bool = True) -> Model:
     m.q_scale = np.ones(D)
     if scaled:
         sc = load_scales()
-        if sc is None:
-            raise FileNotFoundError(f"{SCALES_PATH} missing: run oracle/calibrate.py")
+        if sc is None or (size == "paper" and "paper" not in sc):
+            raise FileNotFoundError(f"{SCALES_PATH} missing or incomplete: run oracle/calibrate.py")
+        if size == "paper":
+            sc = sc["paper"]
         m.q_scale = np.asarray(sc["q_scale"], dtype=np.float64)
         m.w1 = m.w1 * float(sc["kappa"])
     return m

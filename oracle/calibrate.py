@@ -8,6 +8,9 @@ of the network part on that workload is 1 eV/A; the sign of kappa makes the
 lattice restoring on average (sum_i F_i . u_i < 0 for the displacements
 u_i from the lattice sites of atoms that are not in a ZBL pair).
 
+Both the default model and the paper-size one (nep_synth.PAPER_DIMS) are
+calibrated; the latter under the key "paper".
+
 Usage:  python -m oracle.calibrate
 """
 from __future__ import annotations
@@ -20,8 +23,8 @@ import nep_synth
 import oracle
 
 
-def calibrate():
-    m = nep_synth.random_model(scaled=False)
+def calibrate(size="small"):
+    m = nep_synth.random_model(scaled=False, size=size)
     m.zbl_r2 = m.zbl_r1 = 0.0   # network part only
     sysm = nep_synth.tiny()
     pos, h = sysm.pos, sysm.h[0]
@@ -47,6 +50,7 @@ def calibrate():
 
 if __name__ == "__main__":
     out = calibrate()
+    out["paper"] = calibrate("paper")
     with open(nep_synth.SCALES_PATH, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))

@@ -1,0 +1,129 @@
+// Neighbour-list walking and pair geometry shared by the kernel files:
+// list slot order, multiply-free slot walks, the software pipeline over a
+// list, FP64 pair vectors (exactly antisymmetric) and distances.
+#pragma once
+#include "nep_device.h"
+
+namespace nep {
+
+// slot of the s-th entry of a list stored front-to-back (nf entries) and
+// back-to-front (nb entries) in a column of capacity cap
+__host__ __device__ inline int list_slot(int s, int nf, int nb, int cap)
+{
+    return s < nf ? s : s + (cap - nf - nb);
+}
+
+// The same slots walked in order as element offsets slot * n + t of a
+// [slot][atom] array, with one 64-bit add per entry instead of a multiply:
+//   for (ListWalk w(t, n, nf, nb, cap); w.s < nf + nb; w.next()) ... a[w.off] ...
+struct ListWalk {
+    size_t off, n, jump;
+    int s, nf;
+    __host__ __device__ ListWalk(int t, int n_, int nf_, int nb, int cap)
+        : off(0), n((size_t)n_), jump((size_t)(cap - nf_ - nb) * (size_t)n_), s(0), nf(nf_)
+    {
+        off = (size_t)t + (nf_ == 0 ? jump : 0);
+    }
+    __host__ __device__ void next()
+    {
+        ++s;
+        off += n + (s == nf ? jump : 0);
+    }
+};
+
+__device__ inline float ftanh(float z)
+{
+    // tanh z = 1 - 2 / (exp(2z) + 1); exp via the hardware base-2 exponential
+    const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * z);   // 2 log2(e) z
+    return 1.0f - 2.0f * frcp(e + 1.0f);
+}
+
+// ------------------------------------------------------------------ descriptor + network
+
+// Pair vector in double precision, computed so that the vector seen from the
+// other end of the pair is its exact negative: (x_j - x_i) first, then the
+// image shift n.h (which is exactly negated for -n).
+__device__ inline void pair_vector_d(int32_t e, const PairConsts &pc, int base, double xi, double yi,
+                                     double zi, const double4 *__restrict__ xq,
+                                     const CellGeom *__restrict__ cg, int &j, double &dx, double &dy,
+                                     double &dz)
+{
+    int n0, n1, n2;
+    decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
+    j += base;
+    const double4 pj = xq[j];
+    dx = pj.x - xi;
+    dy = pj.y - yi;
+    dz = pj.z - zi;
+    if (n0 | n1 | n2) {
+        const double *h = cg->h;
+        dx += n0 * h[0] + n1 * h[3] + n2 * h[6];
+        dy += n0 * h[1] + n1 * h[4] + n2 * h[7];
+        dz += n0 * h[2] + n1 * h[5] + n2 * h[8];
+    }
+}
+
+// The same pair vector from a neighbour position already gathered.
+__device__ inline void pair_vector_p(int32_t e, const PairConsts &pc, double px, double py, double pz, double xi,
+                                     double yi, double zi, const CellGeom *__restrict__ cg, double &dx, double &dy,
+                                     double &dz)
+{
+    int n0, n1, n2, j;
+    decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
+    dx = px - xi;
+    dy = py - yi;
+    dz = pz - zi;
+    if (n0 | n1 | n2) {
+        const double *h = cg->h;
+        dx += n0 * h[0] + n1 * h[3] + n2 * h[6];
+        dy += n0 * h[1] + n1 * h[4] + n2 * h[7];
+        dz += n0 * h[2] + n1 * h[5] + n2 * h[8];
+    }
+}
+
+// Software pipeline over one atom's list: entries are loaded two neighbours
+// ahead and the neighbour's position one ahead, so the dependent gathers of
+// the next neighbours overlap the arithmetic of the current one.
+//   for (NeighbourPipe q(...); q.s < q.count;) { q.pop(...); ... }
+struct NeighbourPipe {
+    ListWalk w;
+    int count, s;
+    int32_t e_cur, e_nx;
+    double x_cur, y_cur, z_cur;
+    __device__ NeighbourPipe(const int32_t *__restrict__ nl, const double4 *__restrict__ xq, int base,
+                             uint32_t jmask, int t, int n, int nf, int nb, int cap)
+        : w(t, n, nf, nb, cap), count(nf + nb), s(0), e_cur(0), e_nx(0), x_cur(0.0), y_cur(0.0), z_cur(0.0)
+    {
+        if (count > 0) {
+            e_cur = nl[w.off];
+            const double4 *q = xq + ((int)((uint32_t)e_cur & jmask) + base);
+            x_cur = q->x; y_cur = q->y; z_cur = q->z;
+        }
+        w.next();
+        if (w.s < count) e_nx = nl[w.off];
+    }
+    __device__ void pop(const int32_t *__restrict__ nl, const double4 *__restrict__ xq, int base, uint32_t jmask,
+                        int32_t &e, double &px, double &py, double &pz)
+    {
+        e = e_cur; px = x_cur; py = y_cur; pz = z_cur;
+        if (s + 1 < count) {
+            e_cur = e_nx;
+            const double4 *q = xq + ((int)((uint32_t)e_cur & jmask) + base);
+            x_cur = q->x; y_cur = q->y; z_cur = q->z;
+            w.next();
+            if (w.s < count) e_nx = nl[w.off];
+        }
+        ++s;
+    }
+};
+
+// |r| in double precision from r^2: FP32 square root refined by one
+// Newton step (relative error ~1e-15).
+__device__ inline double dist_d(double r2)
+{
+    const float rf = fsqrt((float)r2);
+    const double rd = (double)rf;
+    return rd + fma(-rd, rd, r2) * (double)(0.5f * frcp(rf));
+}
+
+}  // namespace nep

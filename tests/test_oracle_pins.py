@@ -454,3 +454,37 @@ def test_parameter_gradient_linear_in_output_weights():
     g = oracle.param_grad_cell(m, pos, h)
     E = oracle.efv_cell(m, pos, h)["energy"]
     assert abs(E - (m.w1 @ g[1026:1056] + m.b1 * g[1056])) < 1e-9 * max(1.0, abs(E))
+
+
+def test_paper_size_model_forces_virial_and_identity_dimer():
+    # the paper's hyperparameters (16 radial and 11 angular functions on as
+    # many Chebyshev terms, 100 neurons): forces and virial by finite
+    # differences, and the NEP1 special case c = I on a dimer
+    m = nep_synth.random_model(size="paper")
+    assert m.dim == 60 and m.w0.shape == (100, 60)
+    pos, hc = nep_synth.bcc_lattice(3, 3, 3)
+    pos = pos + np.random.default_rng(12).normal(0.0, 0.08, pos.shape)
+    out = oracle.efv_cell(m, pos, hc)
+    h = 1e-4
+    for i in (0, 13, 40):
+        for a in range(3):
+            p = pos.copy(); p[i, a] += h
+            ep = _energy(m, p, hc)
+            p[i, a] -= 2 * h
+            em = _energy(m, p, hc)
+            assert abs(out["forces"][i, a] + (ep - em) / (2 * h)) <= 1e-6 * max(1.0, abs(out["forces"][i, a]))
+    hs = 1e-5
+    for a, b in ((0, 0), (1, 2)):
+        eps = np.zeros((3, 3)); eps[b, a] = hs
+        ep = _energy(m, pos @ (np.eye(3) + eps), hc @ (np.eye(3) + eps))
+        em = _energy(m, pos @ (np.eye(3) - eps), hc @ (np.eye(3) - eps))
+        assert abs(out["virial"][a, b] + (ep - em) / (2 * hs)) <= 2e-6 * max(1.0, np.abs(out["virial"]).max())
+    mi = m.copy()
+    mi.c_rad, mi.c_ang = np.eye(16), np.eye(11)
+    for r in (2.3, 3.7, 5.5):
+        s = nep_synth.dimer(r)
+        q = oracle.efv_cell(mi, s.pos, s.h[0], desc=True)["desc"]
+        assert np.allclose(q[0, :16], _basis_np(16, r, 6.0), atol=1e-13)
+        fA = _basis_np(11, r, 4.0)
+        for l in range(1, 5):
+            assert np.allclose(q[0, 16 + 11 * (l - 1):16 + 11 * l], fA ** 2, atol=1e-13)
