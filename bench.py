@@ -183,6 +183,40 @@ def _timed(fn, reps, torch, stream=None):
     return (time.perf_counter() - t0) / reps
 
 
+def bench_paper_model(args, s, N):
+    """MD of the same 8,192,000-atom workload with the paper-size model
+    (n_max^R = 15, n_max^A = 10, l_max = 4, 100 neurons; random weights): the
+    model size of the paper's own speed figure (Table IV: 1.3e7 atom-steps/s
+    on one A100, quoted as context)."""
+    import torch
+    import nep_synth
+    import oracle
+    import paper_2305_08140_amd as nep
+    pm = nep_synth.random_model(size="paper")
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(pm, N, 1, max_neigh_ang=48, max_neigh_rad=96, skin=1.0)
+    out = nep.EFV(N, 1)
+    md = dict(dt_max=1.0, max_disp=0.015)
+    ctx.nep_step_verlet(sysd, 5, out, forces_valid=False, **md)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.nep_step_verlet(sysd, args.paper_steps, out, forces_valid=True, **md)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.nep_time_efv(sysd, out, reps=3)
+    pos_now = sysd.positions().cpu().numpy()
+    F = out.forces().cpu().numpy().astype(np.float64)
+    idx = np.sort(np.random.default_rng(0).choice(N, size=256, replace=False))
+    ref = oracle.efv_cell(pm, pos_now, s.h[0], targets=idx, virial=False)
+    err = float(np.linalg.norm(F[idx] - ref["forces"]) / np.linalg.norm(ref["forces"]))
+    res = {"atom_steps_per_s": N * args.paper_steps / wall, "ms_per_step": wall / args.paper_steps * 1e3,
+           "steps": args.paper_steps, "kernels_ms": kt, "force_rel_err_vs_fp64_thermal_atoms": err,
+           "paper_a100_atom_steps_per_s": 1.3e7}
+    del ctx, out, sysd
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_batches(model, reps=20, n_percell=128):
     """Batched evaluation of many small cells against per-cell launches.
 
@@ -268,6 +302,8 @@ def main():
     ap.add_argument("--cells", type=int, default=160, help="conventional cells per edge")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batches", action="store_true", help="skip the batched small-cell workloads")
+    ap.add_argument("--paper-steps", type=int, default=50,
+                    help="MD steps of the paper-size model on the same workload (0 skips it)")
     ap.add_argument("--timing-reps", type=int, default=5)
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ summaries from rocprofv3 output directories and exit")
@@ -369,10 +405,12 @@ def main():
                "n_vacancy_clusters": res_ws["n_vacancy_clusters"],
                "n_interstitial_clusters": res_ws["n_interstitial_clusters"]}
 
+    del ctx, sysd, out
+    torch.cuda.empty_cache()
+    paper = bench_paper_model(args, s, N) if args.paper_steps > 0 else None
+
     batches = None
     if not args.no_batches:
-        del ctx, sysd, out
-        torch.cuda.empty_cache()
         batches = bench_batches(model)
 
     cpu = None
@@ -399,6 +437,7 @@ def main():
         "force_rel_err_vs_fp64": ferr, "force_rel_err_vs_fp64_thermal_atoms": ferr_th,
         "site_energy_max_abs_err_eV": eerr,
         "defects": defects,
+        "paper_model": paper,
         "batches": batches,
     }
     print(json.dumps(line), flush=True)

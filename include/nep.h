@@ -54,9 +54,13 @@ extern "C" {
 typedef struct nep_ctx nep_ctx;
 
 /* Model hyperparameters (names as in Sec. III.A).  Compiled kernels exist for
- * n_rad = 9 (n_max^R = 8), n_ang = 5 (n_max^A = 4), k_rad = k_ang = 9
- * (Chebyshev k = 0..8), l_max = 4, n_hidden = 30; other values give
- * NEP_E_UNSUPPORTED. */
+ *   the default model: n_rad = 9 (n_max^R = 8), n_ang = 5 (n_max^A = 4),
+ *     k_rad = k_ang = 9 (Chebyshev k = 0..8), l_max = 4, n_hidden = 30;
+ *   the paper's model size: n_rad = k_rad = 16 (n_max^R = 15), n_ang = k_ang
+ *     = 11 (n_max^A = 10), l_max = 4, n_hidden = 100.  It supports every call
+ *     except nep_backward, nep_autotune and nep_set_precision modes 1 and 2,
+ *     which return NEP_E_UNSUPPORTED for it.
+ * Other values give NEP_E_UNSUPPORTED. */
 typedef struct {
     int32_t n_rad;      /* radial descriptor components */
     int32_t n_ang;      /* radial functions of the angular components */

@@ -9,6 +9,7 @@
 
 #include "nep.h"
 #include "nep_device.h"
+#include "nep_wide.h"
 
 namespace nep {
 // kernels (nep_kernels.hip)
@@ -96,6 +97,10 @@ struct nep_ctx {
     AtomRec *xp = nullptr;       // [N] sorted wrapped positions and radial adjoints
     double4 *xq = nullptr;       // [N] sorted wrapped positions, compact copy
     double *c64 = nullptr;       // angular coefficients and their row sums, double precision
+    // the paper-size model (nep_wide.h): staged sums, descriptors, adjoints, records
+    bool wide = false;
+    float *w_S = nullptr, *w_Q = nullptr, *w_FpA = nullptr;
+    WAtomRec *xw = nullptr;
     double *xref = nullptr;      // [3][N] caller-order positions at the last build
     int32_t *perm = nullptr, *bin_of = nullptr, *wrap = nullptr, *cell_of = nullptr, *tmp = nullptr,
             *bin_sorted = nullptr;
@@ -194,7 +199,7 @@ void nep_destroy(nep_ctx *c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    void *bufs[] = {c->params, c->c64, c->xp, c->xq, c->xref, c->bin_rank, c->bin_lin, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
+    void *bufs[] = {c->params, c->c64, c->w_S, c->w_Q, c->w_FpA, c->xw, c->xp, c->xq, c->xref, c->bin_rank, c->bin_lin, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
                     c->bin_sorted, c->ncnt, c->nl_ang, c->nl_rad, c->pair_grad, c->f_own, c->rev,
                     c->w_atom,
                     c->e_atom, c->cells, c->cell_start_d, c->chunk_begin, c->chunk_end, c->cell_chunk,
@@ -215,9 +220,11 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     if (!out) return NEP_E_ARG;
     *out = nullptr;
     if (!hp || !cfg) return NEP_E_ARG;
-    if (hp->n_rad != NR || hp->n_ang != NA || hp->k_rad != KB || hp->k_ang != KB || hp->l_max != LMAX ||
-        hp->n_hidden != NH)
-        return NEP_E_UNSUPPORTED;
+    const bool small = hp->n_rad == NR && hp->n_ang == NA && hp->k_rad == KB && hp->k_ang == KB &&
+                       hp->l_max == LMAX && hp->n_hidden == NH;
+    const bool wide = hp->n_rad == WR && hp->n_ang == WA && hp->k_rad == WKR && hp->k_ang == WKA &&
+                      hp->l_max == LMAX && hp->n_hidden == WH;
+    if (!small && !wide) return NEP_E_UNSUPPORTED;
     if (!(hp->rc_rad > 0 && hp->rc_ang > 0 && hp->rc_ang <= hp->rc_rad && hp->zbl_r1 >= 0 &&
           hp->zbl_r2 > hp->zbl_r1 && hp->zbl_r2 <= hp->rc_ang && hp->Z > 0))
         return NEP_E_ARG;
@@ -229,14 +236,22 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     for (int k = 0; k < 32; ++k) c->tuned_desc[k] = c->tuned_force[k] = -1;
     c->hp = *hp;
     c->cfg = *cfg;
+    c->wide = wide;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return NEP_E_HIP; }
     const size_t N = (size_t)cfg->max_atoms;
     bool ok = true;
     auto A = [&](void **p, size_t bytes) {
         if (ok && hipMalloc(p, bytes > 0 ? bytes : 16) != hipSuccess) ok = false;
     };
-    A((void **)&c->params, P_SIZE * sizeof(float));
-    A((void **)&c->c64, (NA * KB + NA) * sizeof(double));
+    const size_t p_size = wide ? W_SIZE : P_SIZE;
+    A((void **)&c->params, p_size * sizeof(float));
+    A((void **)&c->c64, (wide ? W_C64 : NA * KB + NA) * sizeof(double));
+    if (wide) {
+        A((void **)&c->xw, N * sizeof(WAtomRec));
+        A((void **)&c->w_S, N * WA * NLM * sizeof(float));
+        A((void **)&c->w_Q, N * WDIM * sizeof(float));
+        A((void **)&c->w_FpA, N * WA * LMAX * sizeof(float));
+    }
     A((void **)&c->xp, N * sizeof(AtomRec));
     A((void **)&c->xq, N * sizeof(double4));
     A((void **)&c->xref, 3 * N * sizeof(double));
@@ -265,7 +280,7 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     if (ok && hipHostMalloc((void **)&c->h_counts, 2 * 8, hipHostMallocDefault) != hipSuccess) ok = false;
     if (ok && hipMemset(c->status, 0, 8 * 4) != hipSuccess) ok = false;
     if (ok && hipMemset(c->md, 0, 8 * 8) != hipSuccess) ok = false;
-    if (ok && hipMemset(c->params, 0, P_SIZE * sizeof(float)) != hipSuccess) ok = false;
+    if (ok && hipMemset(c->params, 0, p_size * sizeof(float)) != hipSuccess) ok = false;
     // index arrays start in range, so that no kernel can ever see garbage indices
     if (ok && hipMemset(c->perm, 0, N * 4) != hipSuccess) ok = false;
     if (ok && hipMemset(c->ncnt, 0, N * 4) != hipSuccess) ok = false;
@@ -281,20 +296,28 @@ int nep_set_weights(nep_ctx *c, const nep_weights *w, int32_t on_device, void *s
     if (!c || !w || !w->c_rad || !w->c_ang || !w->q_scale || !w->w0 || !w->b0 || !w->w1) return NEP_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    struct { const float *src; int off, n; } parts[] = {
+    struct Part { const float *src; int off, n; };
+    const Part small_parts[] = {
         {w->c_rad, P_CR, NR * KB}, {w->c_ang, P_CA, NA * KB}, {w->q_scale, P_QS, DIM},
         {w->w0, P_W0, NH * DIM},   {w->b0, P_B0, NH},         {w->w1, P_W1, NH}};
-    for (auto &p : parts) {
+    const Part wide_parts[] = {
+        {w->c_rad, W_CR, WR * WKR}, {w->c_ang, W_CA, WA * WKA}, {w->q_scale, W_QS, WDIM},
+        {w->w0, W_W0, WH * WDIM},   {w->b0, W_B0, WH},          {w->w1, W_W1, WH}};
+    const Part *parts = c->wide ? wide_parts : small_parts;
+    for (int k = 0; k < 6; ++k) {
+        const Part &p = parts[k];
         if (on_device) HIP_TRY(hipMemcpyAsync(c->params + p.off, p.src, p.n * 4, kind, s));
         else HIP_TRY(hipMemcpy(c->params + p.off, p.src, p.n * 4, kind));
     }
+    const int b1_off = c->wide ? W_B1 : P_B1;
     if (on_device) {
         // b1 is a host scalar even when the arrays live on the device
-        HIP_TRY(hipMemcpyAsync(c->params + P_B1, &w->b1, 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(c->params + b1_off, &w->b1, 4, hipMemcpyHostToDevice, s));
     } else {
-        HIP_TRY(hipMemcpy(c->params + P_B1, &w->b1, 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->params + b1_off, &w->b1, 4, hipMemcpyHostToDevice));
     }
-    k_params64<<<1, 64, 0, s>>>(c->params, c->c64);
+    if (c->wide) k_w_params64<<<1, 128, 0, s>>>(c->params, c->c64);
+    else k_params64<<<1, 64, 0, s>>>(c->params, c->c64);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     return NEP_OK;
@@ -617,6 +640,39 @@ static void launch_force(nep_ctx *c, int shape, const nep_efv *o, hipStream_t st
 
 extern "C" {
 
+// The paper-size model's descriptor phases and force kernel (nep_wide.h).
+static void launch_wide_desc(nep_ctx *c, hipStream_t st)
+{
+    const int n = c->pc.n, grid = xcd_grid((n + 255) / 256);
+    k_w_radial<<<grid, 256, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->params,
+                                     c->w_Q, c->e_atom, c->status);
+    for (int g = 0; g < WNG; ++g)
+        k_w_angular<<<grid, 256, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->c64, g,
+                                          c->w_S, c->w_Q);
+    k_w_network<<<grid, 256, 0, st>>>(n, c->xq, c->params, c->w_Q, c->xw, c->w_FpA, c->e_atom);
+    k_w_grad<<<grid, 256, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->params, c->w_S,
+                                   c->w_FpA, c->pair_grad, c->f_own, c->w_atom);
+}
+
+static void launch_wide_force(nep_ctx *c, const nep_efv *o, hipStream_t st)
+{
+    const int n = c->pc.n, grid = xcd_grid((n + 255) / 256);
+    k_w_force<<<grid, 256, 0, st>>>(c->pc, c->xw, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->rev,
+                                    c->pair_grad, c->f_own, c->perm, o->fx, o->fy, o->fz, c->w_atom, c->status);
+}
+
+static void launch_desc_any(nep_ctx *c, hipStream_t st)
+{
+    if (c->wide) launch_wide_desc(c, st);
+    else launch_desc(c, c->shape_desc, st);
+}
+
+static void launch_force_any(nep_ctx *c, const nep_efv *o, hipStream_t st)
+{
+    if (c->wide) launch_wide_force(c, o, st);
+    else launch_force(c, c->shape_force, o, st);
+}
+
 // One evaluation: sorted positions, descriptor + network, forces, reductions.
 static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t st, bool refresh_positions)
 {
@@ -624,8 +680,8 @@ static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t s
     if (refresh_positions)
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
                                                            c->cells, c->xq, c->status, nullptr);
-    launch_desc(c, c->shape_desc, st);
-    launch_force(c, c->shape_force, o, st);
+    launch_desc_any(c, st);
+    launch_force_any(c, o, st);
     k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom, c->part,
                                                  c->status);
     k_reduce_cells<<<c->built_cells, 256, 0, st>>>(c->built_cells, c->cell_chunk, c->part,
@@ -669,9 +725,9 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
                                                            c->cells, c->xq, c->status, nullptr);
         HIP_TRY(hipEventRecord(ev[1], st));
-        launch_desc(c, c->shape_desc, st);
+        launch_desc_any(c, st);
         HIP_TRY(hipEventRecord(ev[2], st));
-        launch_force(c, c->shape_force, o, st);
+        launch_force_any(c, o, st);
         HIP_TRY(hipEventRecord(ev[3], st));
         k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom,
                                                      c->part, c->status);
@@ -696,6 +752,7 @@ static constexpr int N_PARAMS = NR * KB + NA * KB + NH * DIM + NH + NH + 1;
 int nep_set_precision(nep_ctx *c, int32_t mode)
 {
     if (!c || mode < 0 || mode > 2) return NEP_E_ARG;
+    if (c->wide && mode != 0) return NEP_E_UNSUPPORTED;
     c->nn_mode = mode;
     return NEP_OK;
 }
@@ -703,6 +760,7 @@ int nep_set_precision(nep_ctx *c, int32_t mode)
 int nep_num_params(const nep_ctx *c)
 {
     if (!c) return NEP_E_ARG;
+    if (c->wide) return WR * WKR + WA * WKA + WH * WDIM + WH + WH + 1;
     return N_PARAMS;
 }
 
@@ -710,6 +768,7 @@ int nep_backward(nep_ctx *c, const nep_system *s, const nep_efv *o, const double
                  double *gx, double *gy, double *gz, double *gh, void *stream)
 {
     if (!c || !gE || !grad_params) return NEP_E_ARG;
+    if (c->wide) return NEP_E_UNSUPPORTED;
     int rc = check_system(c, s, false);
     if (rc) return rc;
     if ((rc = check_out(o))) return rc;
@@ -742,6 +801,7 @@ int nep_backward(nep_ctx *c, const nep_system *s, const nep_efv *o, const double
 int nep_autotune(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, int32_t *shape_out, void *stream)
 {
     if (!c || reps <= 0) return NEP_E_ARG;
+    if (c->wide) return NEP_E_UNSUPPORTED;
     int rc = check_system(c, s, false);
     if (rc) return rc;
     if ((rc = check_out(o))) return rc;

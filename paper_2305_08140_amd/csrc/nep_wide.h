@@ -1,0 +1,64 @@
+// The paper-size model (Sec. III.A: Chebyshev expansion orders n_max^R = 15
+// and n_max^A = 10, l_max = 4, 100 hidden neurons; cutoffs as the default
+// model): 16 radial functions on 16 Chebyshev terms, 11 angular functions on
+// 11 terms, 60 descriptor components.  Its 11 x 24 angular sums do not fit
+// one lane's registers, so the evaluation runs in phases with the sums and
+// descriptors staged in HBM, [component][atom] (coalesced per wavefront):
+//   k_w_radial    radial sums and descriptors, ZBL half energies
+//   k_w_angular   angular sums of one group of WG channels per launch
+//                 (l <= 3 in FP64, l = 4 in FP32, as in the default model)
+//   k_w_network   network forward and backward per atom, site energy, the
+//                 atom's record (position + 16 radial adjoints, 128 bytes)
+//   k_w_grad      dU_i/dr_ij of every angular slot, channel group by group
+//   k_w_force     radial + ZBL pair forces, angular assembly, virial
+#pragma once
+#include "nep_device.h"
+
+namespace nep {
+
+constexpr int WR = 16, WKR = 16;         // radial functions, radial Chebyshev terms
+constexpr int WA = 11, WKA = 11;         // angular functions, angular Chebyshev terms
+constexpr int WH = 100;                  // hidden neurons
+constexpr int WDIM = WR + WA * LMAX;     // 60
+constexpr int WG = 3;                    // angular channels per group
+constexpr int WNG = (WA + WG - 1) / WG;  // 4 groups (3, 3, 3, 2)
+
+// parameter block (floats): c_rad [WR][WKR], c_ang [WA][WKA], q_scale [WDIM],
+// w0 [WH][WDIM], b0 [WH], w1 [WH], b1
+constexpr int W_CR = 0;
+constexpr int W_CA = W_CR + WR * WKR;
+constexpr int W_QS = W_CA + WA * WKA;
+constexpr int W_W0 = W_QS + WDIM;
+constexpr int W_B0 = W_W0 + WH * WDIM;
+constexpr int W_W1 = W_B0 + WH;
+constexpr int W_B1 = W_W1 + WH;
+constexpr int W_SIZE = W_B1 + 1;
+// double copy of the angular coefficients and their row sums
+constexpr int W_C64 = WA * WKA + WA;
+
+// one 128-byte line per atom for the force kernel's gathers
+struct __attribute__((aligned(128))) WAtomRec {
+    double x, y, z;
+    float a[WKR];
+    float pad[10];
+};
+static_assert(sizeof(WAtomRec) == 128, "WAtomRec must be 128 bytes");
+
+__global__ void k_w_params64(const float *P, double *C64);
+__global__ void k_w_radial(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
+                           const int32_t *nl_ang, const int32_t *nl_rad, const uint32_t *ncnt, const float *P,
+                           float *Q, double *e_atom, int32_t *status);
+__global__ void k_w_angular(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
+                            const int32_t *nl_ang, const uint32_t *ncnt, const double *C64, int group, float *S,
+                            float *Q);
+__global__ void k_w_network(int n, const double4 *xq, const float *P, const float *Q, WAtomRec *xw, float *FpA,
+                            double *e_atom);
+__global__ void k_w_grad(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
+                         const int32_t *nl_ang, const uint32_t *ncnt, const float *P, const float *S,
+                         const float *FpA, float4 *pair_grad, float4 *f_own, float *w_atom);
+__global__ void k_w_force(PairConsts pc, const WAtomRec *xw, const int32_t *cell_of, const CellGeom *cells,
+                          const int32_t *nl_ang, const int32_t *nl_rad, const uint32_t *ncnt, const uint8_t *rev,
+                          const float4 *pair_grad, const float4 *f_own, const int32_t *perm, float *fx, float *fy,
+                          float *fz, float *w_atom, int32_t *status);
+
+}  // namespace nep

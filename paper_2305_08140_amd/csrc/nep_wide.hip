@@ -1,0 +1,491 @@
+// Kernels of the paper-size model (see nep_wide.h for the phases).  The
+// arithmetic follows the default model's kernels (nep_kernels.hip) term by
+// term: FP64 pair geometry, Chebyshev basis, radial sums and l <= 3 angular
+// sums; FP32 l = 4 sums, network, gradient walk and force kernel.  One lane
+// per atom, 256-thread blocks in XCD-aware order.
+#include "nep_wide.h"
+#include "nep_pairs.h"
+
+namespace nep {
+
+// FP64 basis f_k = (T_k(x) + 1) fc / 2 without the halving: fc and T_k,
+// k < K, x = 2 (r/rc - 1)^2 - 1 (the default model's basis_d for any K).
+template <int K>
+__device__ inline void basis_w(double r, double inv_rc, double &fc, double T[K])
+{
+    const double PI = 3.14159265358979323846;
+    const double tt = r * inv_rc - 1.0;
+    fc = 0.5 - 0.5 * sin_halfpi_d(PI * (tt + 0.5));
+    const double x = 2.0 * tt * tt - 1.0;
+    T[0] = 1.0;
+    T[1] = x;
+    const double x2 = 2.0 * x;
+#pragma unroll
+    for (int k = 2; k < K; ++k) T[k] = fma(x2, T[k - 1], -T[k - 2]);
+}
+
+// FP32 T_k and dT_k/dx, k < K.
+template <int K>
+__device__ inline void cheb_w(float x, float T[K], float dT[K])
+{
+    T[0] = 1.0f;
+    T[1] = x;
+    dT[0] = 0.0f;
+    dT[1] = 1.0f;
+    const float x2 = 2.0f * x;
+#pragma unroll
+    for (int k = 2; k < K; ++k) {
+        T[k] = fmaf(x2, T[k - 1], -T[k - 2]);
+        dT[k] = fmaf(x2, dT[k - 1], fmaf(2.0f, T[k - 1], -dT[k - 2]));
+    }
+}
+
+__device__ inline int tile_atom(int n)
+{
+    const int ntiles = (n + 255) / 256;
+    const int tile = xcd_block(ntiles);
+    return tile < ntiles ? tile * 256 + (int)threadIdx.x : n;
+}
+
+__global__ void k_w_params64(const float *__restrict__ P, double *__restrict__ C64)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < WA * WKA) C64[i] = (double)P[W_CA + i];
+    if (i < WA) {
+        double s = 0.0;
+        for (int k = 0; k < WKA; ++k) s += (double)P[W_CA + i * WKA + k];
+        C64[WA * WKA + i] = s;
+    }
+}
+
+// Radial sums F_k = sum_j f_k(r_ij) over both lists (FP64), descriptors
+// q_n = sum_k c_nk F_k -> Q[n][t]; ZBL half energies -> e_atom[t].
+__global__ __launch_bounds__(256) void k_w_radial(
+    PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
+    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const int32_t *__restrict__ nl_rad,
+    const uint32_t *__restrict__ ncnt, const float *__restrict__ P, float *__restrict__ Q,
+    double *__restrict__ e_atom, int32_t *__restrict__ status)
+{
+    const int t = tile_atom(pc.n);
+    if (t >= pc.n || status[ST_ERR] != 0) return;
+    const double4 pi = xq[t];
+    const CellGeom *cg = cells + cell_of[t];
+    const int base = cg->atom_start;
+    const uint32_t cnt = ncnt[t];
+    const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
+    const double inv_rR = 1.0 / (double)pc.rc_rad, rcR2 = (double)pc.rc_rad * pc.rc_rad;
+    const uint32_t jmask = (1u << pc.jbits) - 1u;
+    double AR[WKR];
+#pragma unroll
+    for (int k = 0; k < WKR; ++k) AR[k] = 0.0;
+    double ezbl = 0.0;
+    bool overlap = false;
+    for (int list = 0; list < 2; ++list) {
+        const int32_t *nl = list == 0 ? nl_ang : nl_rad;
+        const int nf = list == 0 ? naf : nrf, nb = list == 0 ? nab : nrb;
+        const int cap = list == 0 ? pc.capA : pc.capR;
+        for (NeighbourPipe q(nl, xq, base, jmask, t, pc.n, nf, nb, cap); q.s < q.count;) {
+            int32_t e;
+            double px, py, pz;
+            q.pop(nl, xq, base, jmask, e, px, py, pz);
+            double dx, dy, dz;
+            pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 >= rcR2) continue;
+            const double r = dist_d(r2);
+            overlap |= (r < 1e-3);
+            double fc, T[WKR];
+            basis_w<WKR>(r, inv_rR, fc, T);
+#pragma unroll
+            for (int k = 0; k < WKR; ++k) AR[k] = fma(fc, T[k], AR[k]);
+            if (r < (double)pc.zbl_r2) {
+                double U, dU;
+                zbl_pair(r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
+                ezbl += 0.5 * U;
+            }
+        }
+    }
+    if (overlap) latch_error(status, -4);
+    const size_t n = (size_t)pc.n;
+#pragma unroll 1
+    for (int m = 0; m < WR; ++m) {
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < WKR; ++k) s = fmaf(P[W_CR + m * WKR + k], (float)(0.5 * (AR[k] + AR[0])), s);
+        Q[m * n + t] = s;
+    }
+    e_atom[t] = ezbl;
+}
+
+// Angular sums of the channels c0 .. c0+NC-1 over the angular list:
+// S[(c*24 + lm)][t] (l <= 3 in FP64, l = 4 in FP32, rounded once) and the
+// descriptors q_cl = sum_m S^2 -> Q[WR + WA (l-1) + c][t].
+template <int NC>
+__device__ __forceinline__ void w_angular_group(const PairConsts &pc, const double4 *__restrict__ xq, int t,
+                                                const CellGeom *cg, const int32_t *__restrict__ nl_ang, int naf,
+                                                int nab, const double *__restrict__ C64, int c0,
+                                                float *__restrict__ S, float *__restrict__ Q)
+{
+    const double4 pi = xq[t];
+    const int base = cg->atom_start;
+    const double inv_rA = 1.0 / (double)pc.rc_ang, rcA2 = (double)pc.rc_ang * pc.rc_ang;
+    const uint32_t jmask = (1u << pc.jbits) - 1u;
+    double A[NC][15];
+    float A4[NC][9];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+#pragma unroll
+        for (int m = 0; m < 15; ++m) A[c][m] = 0.0;
+#pragma unroll
+        for (int m = 0; m < 9; ++m) A4[c][m] = 0.0f;
+    }
+    for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
+        int32_t e;
+        double px, py, pz;
+        q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
+        double dx, dy, dz;
+        pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= rcA2) continue;
+        const double r = dist_d(r2);
+        double rinv = (double)frcp((float)r);
+        rinv = rinv * fma(-r, rinv, 2.0);
+        rinv = rinv * fma(-r, rinv, 2.0);
+        const double ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+        double fc, T[WKA];
+        basis_w<WKA>(r, inv_rA, fc, T);
+        double g[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double sn = C64[WA * WKA + c0 + c];
+#pragma unroll
+            for (int k = 0; k < WKA; ++k) sn = fma(C64[(c0 + c) * WKA + k], T[k], sn);
+            g[c] = 0.5 * fc * sn;
+        }
+        double Y[15];
+        sph_degree_d<1>(ux, uy, uz, Y);
+        sph_degree_d<2>(ux, uy, uz, Y + 3);
+        sph_degree_d<3>(ux, uy, uz, Y + 8);
+        float Yf[NLM];
+        sph((float)ux, (float)uy, (float)uz, Yf);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+#pragma unroll
+            for (int m = 0; m < 15; ++m) A[c][m] = fma(g[c], Y[m], A[c][m]);
+            const float gf = (float)g[c];
+#pragma unroll
+            for (int m = 0; m < 9; ++m) A4[c][m] = fmaf(gf, Yf[15 + m], A4[c][m]);
+        }
+    }
+    const size_t n = (size_t)pc.n;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        float ql[LMAX] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int lm = 0; lm < NLM; ++lm) {
+            const float v = lm < 15 ? (float)A[c][lm] : A4[c][lm - 15];
+            const int l = lm < 3 ? 1 : (lm < 8 ? 2 : (lm < 15 ? 3 : 4));
+            ql[l - 1] = fmaf(v, v, ql[l - 1]);
+            S[((size_t)(c0 + c) * NLM + lm) * n + t] = v;
+        }
+#pragma unroll
+        for (int l = 1; l <= LMAX; ++l) Q[(size_t)(WR + WA * (l - 1) + c0 + c) * n + t] = ql[l - 1];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_w_angular(
+    PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
+    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const uint32_t *__restrict__ ncnt,
+    const double *__restrict__ C64, int group, float *__restrict__ S, float *__restrict__ Q)
+{
+    const int t = tile_atom(pc.n);
+    if (t >= pc.n) return;
+    const CellGeom *cg = cells + cell_of[t];
+    const uint32_t cnt = ncnt[t];
+    const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff;
+    const int c0 = group * WG;
+    if (WA - c0 >= WG) w_angular_group<WG>(pc, xq, t, cg, nl_ang, naf, nab, C64, c0, S, Q);
+    else w_angular_group<WA - (WNG - 1) * WG>(pc, xq, t, cg, nl_ang, naf, nab, C64, c0, S, Q);
+}
+
+// Network forward and backward of one atom: U (added to the ZBL half
+// energies in e_atom), dU/dq; the radial adjoints a_k = sum_n dU/dq_n c_nk
+// go into the atom's record, the angular dU/dq into FpA[(nu - WR)][t].
+__global__ __launch_bounds__(256) void k_w_network(int n_atoms, const double4 *__restrict__ xq,
+                                                   const float *__restrict__ P, const float *__restrict__ Q,
+                                                   WAtomRec *__restrict__ xw, float *__restrict__ FpA,
+                                                   double *__restrict__ e_atom)
+{
+    const int t = tile_atom(n_atoms);
+    if (t >= n_atoms) return;
+    const size_t n = (size_t)n_atoms;
+    float qt[WDIM], Fp[WDIM];
+#pragma unroll
+    for (int nu = 0; nu < WDIM; ++nu) {
+        qt[nu] = P[W_QS + nu] * Q[nu * n + t];
+        Fp[nu] = 0.0f;
+    }
+    float U = -P[W_B1];
+#pragma unroll 1
+    for (int mu = 0; mu < WH; ++mu) {
+        const float *w = P + W_W0 + mu * WDIM;
+        float z = -P[W_B0 + mu];
+#pragma unroll
+        for (int nu = 0; nu < WDIM; ++nu) z = fmaf(w[nu], qt[nu], z);
+        const float e2 = __builtin_amdgcn_exp2f(2.8853900817779268f * z);   // exp(2z)
+        const float th = 1.0f - 2.0f / (e2 + 1.0f);
+        const float w1 = P[W_W1 + mu];
+        U = fmaf(w1, th, U);
+        const float dz = w1 * fmaf(-th, th, 1.0f);
+#pragma unroll
+        for (int nu = 0; nu < WDIM; ++nu) Fp[nu] = fmaf(dz, w[nu], Fp[nu]);
+    }
+#pragma unroll
+    for (int nu = 0; nu < WDIM; ++nu) Fp[nu] *= P[W_QS + nu];
+    e_atom[t] += (double)U;
+    WAtomRec rec;
+    const double4 p = xq[t];
+    rec.x = p.x;
+    rec.y = p.y;
+    rec.z = p.z;
+#pragma unroll
+    for (int k = 0; k < WKR; ++k) {
+        float s = 0.0f;
+#pragma unroll
+        for (int m = 0; m < WR; ++m) s = fmaf(Fp[m], P[W_CR + m * WKR + k], s);
+        rec.a[k] = s;
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) rec.pad[k] = 0.0f;
+    xw[t] = rec;
+#pragma unroll
+    for (int nu = WR; nu < WDIM; ++nu) FpA[(nu - WR) * n + t] = Fp[nu];
+}
+
+// Contributions of the channels c0 .. c0+NC-1 to dU_i/dr_ij of every angular
+// slot, added into pair_grad (the first group writes), and to the atom's own
+// force and virial sums.
+template <int NC>
+__device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4 *__restrict__ xq, int t,
+                                             const CellGeom *cg, const int32_t *__restrict__ nl_ang, int naf,
+                                             int nab, const float *__restrict__ P, const float *__restrict__ S,
+                                             const float *__restrict__ FpA, int c0, float4 *__restrict__ pair_grad,
+                                             float &Fx, float &Fy, float &Fz, float W[9])
+{
+    const size_t n = (size_t)pc.n;
+    const double4 pi = xq[t];
+    const int base = cg->atom_start;
+    const uint32_t jmask = (1u << pc.jbits) - 1u;
+    // B_{c,lm} = 2 (dU/dq_cl) s_{c,lm}
+    float B[NC][NLM];
+    float csA[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        float cs = 0.0f;
+#pragma unroll
+        for (int k = 0; k < WKA; ++k) cs += P[W_CA + (c0 + c) * WKA + k];
+        csA[c] = cs;
+#pragma unroll
+        for (int lm = 0; lm < NLM; ++lm) {
+            const int l = lm < 3 ? 1 : (lm < 8 ? 2 : (lm < 15 ? 3 : 4));
+            B[c][lm] = 2.0f * FpA[(WA * (l - 1) + c0 + c) * n + t] * S[((size_t)(c0 + c) * NLM + lm) * n + t];
+        }
+    }
+    const bool first = c0 == 0;
+    for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
+        const size_t off = (size_t)list_slot(q.s, naf, nab, pc.capA) * n + t;
+        int32_t e;
+        double px, py, pz;
+        q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
+        double ddx, ddy, ddz;
+        pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, ddx, ddy, ddz);
+        const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= pc.rc_ang2) {
+            if (first && r2 < pc.rc_ang2_write) pair_grad[off] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            continue;
+        }
+        const float r = fsqrt(r2);
+        const float rinv = frcp(r);
+        const float tt = scaled_minus_one(r, pc.inv_rc_ang, pc.inv_rc_ang_lo);
+        float fc, dfc;
+        cutoff(tt, pc.inv_rc_ang, fc, dfc);
+        const float dxdr = 4.0f * tt * pc.inv_rc_ang;
+        float T[WKA], dT[WKA];
+        cheb_w<WKA>(fmaf(2.0f * tt, tt, -1.0f), T, dT);
+        float g[NC], gp[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            float sn = csA[c], sp = 0.0f;
+#pragma unroll
+            for (int k = 0; k < WKA; ++k) {
+                sn = fmaf(P[W_CA + (c0 + c) * WKA + k], T[k], sn);
+                sp = fmaf(P[W_CA + (c0 + c) * WKA + k], dT[k], sp);
+            }
+            g[c] = 0.5f * fc * sn;
+            gp[c] = 0.5f * fmaf(dxdr * fc, sp, dfc * sn);
+        }
+        const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+        float Y[NLM];
+        sph(ux, uy, uz, Y);
+        float Dc[NLM];
+        float s1 = 0.0f;
+#pragma unroll
+        for (int lm = 0; lm < NLM; ++lm) {
+            float D = 0.0f, Dp = 0.0f;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                D = fmaf(B[c][lm], g[c], D);
+                Dp = fmaf(B[c][lm], gp[c], Dp);
+            }
+            Dc[lm] = D;
+            s1 = fmaf(Dp, Y[lm], s1);
+        }
+        float vx, vy, vz;
+        sph_grad_contract(ux, uy, uz, Dc, vx, vy, vz);
+        const float uv = ux * vx + uy * vy + uz * vz;
+        const float gx = fmaf(s1, ux, (vx - uv * ux) * rinv);
+        const float gy = fmaf(s1, uy, (vy - uv * uy) * rinv);
+        const float gz = fmaf(s1, uz, (vz - uv * uz) * rinv);
+        float4 acc = make_float4(gx, gy, gz, 0.0f);
+        if (!first) {
+            const float4 old = pair_grad[off];
+            acc.x += old.x;
+            acc.y += old.y;
+            acc.z += old.z;
+        }
+        pair_grad[off] = acc;
+        Fx += gx; Fy += gy; Fz += gz;
+        W[0] = fmaf(gx, dx, W[0]); W[1] = fmaf(gx, dy, W[1]); W[2] = fmaf(gx, dz, W[2]);
+        W[3] = fmaf(gy, dx, W[3]); W[4] = fmaf(gy, dy, W[4]); W[5] = fmaf(gy, dz, W[5]);
+        W[6] = fmaf(gz, dx, W[6]); W[7] = fmaf(gz, dy, W[7]); W[8] = fmaf(gz, dz, W[8]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_w_grad(
+    PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
+    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const uint32_t *__restrict__ ncnt,
+    const float *__restrict__ P, const float *__restrict__ S, const float *__restrict__ FpA,
+    float4 *__restrict__ pair_grad, float4 *__restrict__ f_own, float *__restrict__ w_atom)
+{
+    const int t = tile_atom(pc.n);
+    if (t >= pc.n) return;
+    const CellGeom *cg = cells + cell_of[t];
+    const uint32_t cnt = ncnt[t];
+    const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff;
+    float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f, W[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) W[k] = 0.0f;
+#pragma unroll 1
+    for (int g = 0; g < WNG; ++g) {
+        if (WA - g * WG >= WG)
+            w_grad_group<WG>(pc, xq, t, cg, nl_ang, naf, nab, P, S, FpA, g * WG, pair_grad, Fx, Fy, Fz, W);
+        else
+            w_grad_group<WA - (WNG - 1) * WG>(pc, xq, t, cg, nl_ang, naf, nab, P, S, FpA, g * WG, pair_grad, Fx,
+                                              Fy, Fz, W);
+    }
+    f_own[t] = make_float4(Fx, Fy, Fz, 0.0f);
+    float *w = w_atom + (size_t)t * 9;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k] = -W[k];
+}
+
+// Forces: the default model's force kernel with 16 radial adjoints.
+__global__ __launch_bounds__(256) void k_w_force(
+    PairConsts pc, const WAtomRec *__restrict__ xw, const int32_t *__restrict__ cell_of,
+    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const int32_t *__restrict__ nl_rad,
+    const uint32_t *__restrict__ ncnt, const uint8_t *__restrict__ rev, const float4 *__restrict__ pair_grad,
+    const float4 *__restrict__ f_own, const int32_t *__restrict__ perm, float *__restrict__ fx,
+    float *__restrict__ fy, float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status)
+{
+    const int t = tile_atom(pc.n);
+    if (t >= pc.n || status[ST_ERR] != 0) return;
+    const double xi = xw[t].x, yi = xw[t].y, zi = xw[t].z;
+    const CellGeom *cg = cells + cell_of[t];
+    const int base = cg->atom_start;
+    const uint32_t cnt = ncnt[t];
+    const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
+    const uint32_t jmask = (1u << pc.jbits) - 1u;
+    float ai[WKR];
+#pragma unroll
+    for (int k = 0; k < WKR; ++k) ai[k] = xw[t].a[k];
+    const float4 fo = f_own[t];
+    float Fx = fo.x, Fy = fo.y, Fz = fo.z;
+    float W[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) W[k] = 0.0f;
+    bool bad = false;
+
+    auto radial = [&](int32_t e, const WAtomRec &rj, float &r2out) -> bool {
+        int n0, n1, n2, j;
+        decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
+        double ddx = rj.x - xi, ddy = rj.y - yi, ddz = rj.z - zi;
+        if (n0 | n1 | n2) {
+            const double *h = cg->h;
+            ddx += n0 * h[0] + n1 * h[3] + n2 * h[6];
+            ddy += n0 * h[1] + n1 * h[4] + n2 * h[7];
+            ddz += n0 * h[2] + n1 * h[5] + n2 * h[8];
+        }
+        const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        r2out = r2;
+        if (r2 >= pc.rc_rad2) return false;
+        const float r = fsqrt(r2);
+        const float tt = scaled_minus_one(r, pc.inv_rc_rad, pc.inv_rc_rad_lo);
+        float fc, dfc;
+        cutoff(tt, pc.inv_rc_rad, fc, dfc);
+        const float dxdr = 4.0f * tt * pc.inv_rc_rad;
+        float T[WKR], dT[WKR];
+        cheb_w<WKR>(fmaf(2.0f * tt, tt, -1.0f), T, dT);
+        float s0 = 0.0f, s1 = 0.0f, sa = 0.0f;
+#pragma unroll
+        for (int k = 0; k < WKR; ++k) {
+            const float ah = ai[k] + rj.a[k];
+            s0 = fmaf(ah, T[k], s0);
+            s1 = fmaf(ah, dT[k], s1);
+            sa += ah;
+        }
+        float dGdr = 0.5f * (dxdr * fc * s1 + dfc * (s0 + sa));
+        if (r < pc.zbl_r2) {
+            double U, dU;
+            zbl_pair((double)r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
+            dGdr += (float)dU;
+        }
+        const float c = dGdr * frcp(r);
+        const float px = c * dx, py = c * dy, pz = c * dz;
+        Fx += px; Fy += py; Fz += pz;
+        W[0] = fmaf(px, dx, W[0]); W[1] = fmaf(px, dy, W[1]); W[2] = fmaf(px, dz, W[2]);
+        W[3] = fmaf(py, dx, W[3]); W[4] = fmaf(py, dy, W[4]); W[5] = fmaf(py, dz, W[5]);
+        W[6] = fmaf(pz, dx, W[6]); W[7] = fmaf(pz, dy, W[7]); W[8] = fmaf(pz, dz, W[8]);
+        return true;
+    };
+
+    const int nA = naf + nab;
+    for (ListWalk wa(t, pc.n, naf, nab, pc.capA); wa.s < nA; wa.next()) {
+        const int32_t e = nl_ang[wa.off];
+        const WAtomRec rj = xw[(int)((uint32_t)e & jmask) + base];
+        float r2;
+        if (!radial(e, rj, r2) || r2 >= pc.rc_ang2_read) continue;
+        const int sj = rev[wa.off];
+        if (sj == 255) { bad = true; continue; }
+        const float4 gj = pair_grad[(size_t)sj * pc.n + (int)((uint32_t)e & jmask) + base];
+        Fx -= gj.x; Fy -= gj.y; Fz -= gj.z;
+    }
+    const int nRl = nrf + nrb;
+    for (ListWalk wr(t, pc.n, nrf, nrb, pc.capR); wr.s < nRl; wr.next()) {
+        const int32_t e = nl_rad[wr.off];
+        const WAtomRec rj = xw[(int)((uint32_t)e & jmask) + base];
+        float r2;
+        radial(e, rj, r2);
+    }
+    if (bad) latch_error(status, -9);
+    const int i = perm[t];
+    fx[i] = Fx;
+    fy[i] = Fy;
+    fz[i] = Fz;
+    float *w = w_atom + (size_t)t * 9;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k] = fmaf(-0.5f, W[k], w[k]);
+}
+
+}  // namespace nep
