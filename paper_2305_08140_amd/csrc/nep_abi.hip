@@ -650,7 +650,7 @@ static void launch_wide_desc(nep_ctx *c, hipStream_t st)
         k_w_angular<<<grid, 256, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->c64, g,
                                           c->w_S, c->w_Q);
     k_w_network<<<grid, 256, 0, st>>>(n, c->xq, c->params, c->w_Q, c->xw, c->w_FpA, c->e_atom);
-    k_w_grad<<<grid, 256, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->params, c->w_S,
+    k_w_grad<<<grid, 256, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->params, c->c64, c->w_S,
                                    c->w_FpA, c->pair_grad, c->f_own, c->w_atom);
 }
 

@@ -54,8 +54,8 @@ __global__ void k_w_angular(PairConsts pc, const double4 *xq, const int32_t *cel
 __global__ void k_w_network(int n, const double4 *xq, const float *P, const float *Q, WAtomRec *xw, float *FpA,
                             double *e_atom);
 __global__ void k_w_grad(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
-                         const int32_t *nl_ang, const uint32_t *ncnt, const float *P, const float *S,
-                         const float *FpA, float4 *pair_grad, float4 *f_own, float *w_atom);
+                         const int32_t *nl_ang, const uint32_t *ncnt, const float *P, const double *C64,
+                         const float *S, const float *FpA, float4 *pair_grad, float4 *f_own, float *w_atom);
 __global__ void k_w_force(PairConsts pc, const WAtomRec *xw, const int32_t *cell_of, const CellGeom *cells,
                           const int32_t *nl_ang, const int32_t *nl_rad, const uint32_t *ncnt, const uint8_t *rev,
                           const float4 *pair_grad, const float4 *f_own, const int32_t *perm, float *fx, float *fy,

@@ -268,7 +268,8 @@ __global__ __launch_bounds__(256) void k_w_network(int n_atoms, const double4 *_
 template <int NC>
 __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4 *__restrict__ xq, int t,
                                              const CellGeom *cg, const int32_t *__restrict__ nl_ang, int naf,
-                                             int nab, const float *__restrict__ P, const float *__restrict__ S,
+                                             int nab, const float *__restrict__ P, const double *__restrict__ C64,
+                                             const float *__restrict__ S,
                                              const float *__restrict__ FpA, int c0, float4 *__restrict__ pair_grad,
                                              float &Fx, float &Fy, float &Fz, float W[9])
 {
@@ -292,6 +293,7 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
         }
     }
     const bool first = c0 == 0;
+    const double inv_rA = 1.0 / (double)pc.rc_ang;
     for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
         const size_t off = (size_t)list_slot(q.s, naf, nab, pc.capA) * n + t;
         int32_t e;
@@ -310,20 +312,36 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
         const float tt = scaled_minus_one(r, pc.inv_rc_ang, pc.inv_rc_ang_lo);
         float fc, dfc;
         cutoff(tt, pc.inv_rc_ang, fc, dfc);
-        const float dxdr = 4.0f * tt * pc.inv_rc_ang;
-        float T[WKA], dT[WKA];
-        cheb_w<WKA>(fmaf(2.0f * tt, tt, -1.0f), T, dT);
+        // x and the Chebyshev terms in FP64 (their rounding is amplified
+        // ~k^4 in dT_k near x = -1), the channel sums rounded once
+        const double ttd = dist_d(ddx * ddx + ddy * ddy + ddz * ddz) * inv_rA - 1.0;
+        const double xd = 2.0 * ttd * ttd - 1.0;
+        const float dxdr = (float)(4.0 * ttd * inv_rA);
+        double sn[NC], sp[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double *cc = C64 + (c0 + c) * WKA;
+            sn[c] = C64[WA * WKA + c0 + c] + cc[0] + cc[1] * xd;
+            sp[c] = cc[1];
+        }
+        double Tm2 = 1.0, Tm1 = xd, dTm2 = 0.0, dTm1 = 1.0;
+#pragma unroll
+        for (int k = 2; k < WKA; ++k) {
+            const double Tk = fma(2.0 * xd, Tm1, -Tm2);
+            const double dTk = fma(2.0 * xd, dTm1, fma(2.0, Tm1, -dTm2));
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double ck = C64[(c0 + c) * WKA + k];
+                sn[c] = fma(ck, Tk, sn[c]);
+                sp[c] = fma(ck, dTk, sp[c]);
+            }
+            Tm2 = Tm1; Tm1 = Tk; dTm2 = dTm1; dTm1 = dTk;
+        }
         float g[NC], gp[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            float sn = csA[c], sp = 0.0f;
-#pragma unroll
-            for (int k = 0; k < WKA; ++k) {
-                sn = fmaf(P[W_CA + (c0 + c) * WKA + k], T[k], sn);
-                sp = fmaf(P[W_CA + (c0 + c) * WKA + k], dT[k], sp);
-            }
-            g[c] = 0.5f * fc * sn;
-            gp[c] = 0.5f * fmaf(dxdr * fc, sp, dfc * sn);
+            g[c] = 0.5f * fc * (float)sn[c];
+            gp[c] = 0.5f * fmaf(dxdr * fc, (float)sp[c], dfc * (float)sn[c]);
         }
         const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
         float Y[NLM];
@@ -362,11 +380,12 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
     }
 }
 
-__global__ __launch_bounds__(256) void k_w_grad(
+__global__ __launch_bounds__(256, 2) void k_w_grad(
     PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const uint32_t *__restrict__ ncnt,
-    const float *__restrict__ P, const float *__restrict__ S, const float *__restrict__ FpA,
-    float4 *__restrict__ pair_grad, float4 *__restrict__ f_own, float *__restrict__ w_atom)
+    const float *__restrict__ P, const double *__restrict__ C64, const float *__restrict__ S,
+    const float *__restrict__ FpA, float4 *__restrict__ pair_grad, float4 *__restrict__ f_own,
+    float *__restrict__ w_atom)
 {
     const int t = tile_atom(pc.n);
     if (t >= pc.n) return;
@@ -379,9 +398,9 @@ __global__ __launch_bounds__(256) void k_w_grad(
 #pragma unroll 1
     for (int g = 0; g < WNG; ++g) {
         if (WA - g * WG >= WG)
-            w_grad_group<WG>(pc, xq, t, cg, nl_ang, naf, nab, P, S, FpA, g * WG, pair_grad, Fx, Fy, Fz, W);
+            w_grad_group<WG>(pc, xq, t, cg, nl_ang, naf, nab, P, C64, S, FpA, g * WG, pair_grad, Fx, Fy, Fz, W);
         else
-            w_grad_group<WA - (WNG - 1) * WG>(pc, xq, t, cg, nl_ang, naf, nab, P, S, FpA, g * WG, pair_grad, Fx,
+            w_grad_group<WA - (WNG - 1) * WG>(pc, xq, t, cg, nl_ang, naf, nab, P, C64, S, FpA, g * WG, pair_grad, Fx,
                                               Fy, Fz, W);
     }
     f_own[t] = make_float4(Fx, Fy, Fz, 0.0f);
@@ -415,6 +434,7 @@ __global__ __launch_bounds__(256) void k_w_force(
 #pragma unroll
     for (int k = 0; k < 9; ++k) W[k] = 0.0f;
     bool bad = false;
+    const double inv_rR = 1.0 / (double)pc.rc_rad;
 
     auto radial = [&](int32_t e, const WAtomRec &rj, float &r2out) -> bool {
         int n0, n1, n2, j;
@@ -434,18 +454,26 @@ __global__ __launch_bounds__(256) void k_w_force(
         const float tt = scaled_minus_one(r, pc.inv_rc_rad, pc.inv_rc_rad_lo);
         float fc, dfc;
         cutoff(tt, pc.inv_rc_rad, fc, dfc);
-        const float dxdr = 4.0f * tt * pc.inv_rc_rad;
-        float T[WKR], dT[WKR];
-        cheb_w<WKR>(fmaf(2.0f * tt, tt, -1.0f), T, dT);
-        float s0 = 0.0f, s1 = 0.0f, sa = 0.0f;
+        // with 16 Chebyshev terms the rounding of x is amplified ~k^4 in dT_k
+        // near x = -1 (the outer shells): x and the series in FP64
+        const double ttd = dist_d(ddx * ddx + ddy * ddy + ddz * ddz) * inv_rR - 1.0;
+        const double xd = 2.0 * ttd * ttd - 1.0;
+        double Tm2 = 1.0, Tm1 = xd, dTm2 = 0.0, dTm1 = 1.0;
+        double s0d = (double)(ai[0] + rj.a[0]) + (double)(ai[1] + rj.a[1]) * xd;
+        double s1d = (double)(ai[1] + rj.a[1]);
+        float sa = (ai[0] + rj.a[0]) + (ai[1] + rj.a[1]);
 #pragma unroll
-        for (int k = 0; k < WKR; ++k) {
+        for (int k = 2; k < WKR; ++k) {
+            const double Tk = fma(2.0 * xd, Tm1, -Tm2);
+            const double dTk = fma(2.0 * xd, dTm1, fma(2.0, Tm1, -dTm2));
             const float ah = ai[k] + rj.a[k];
-            s0 = fmaf(ah, T[k], s0);
-            s1 = fmaf(ah, dT[k], s1);
+            s0d = fma((double)ah, Tk, s0d);
+            s1d = fma((double)ah, dTk, s1d);
             sa += ah;
+            Tm2 = Tm1; Tm1 = Tk; dTm2 = dTm1; dTm1 = dTk;
         }
-        float dGdr = 0.5f * (dxdr * fc * s1 + dfc * (s0 + sa));
+        const float dxdr = (float)(4.0 * ttd * inv_rR);
+        float dGdr = 0.5f * (dxdr * fc * (float)s1d + dfc * ((float)s0d + sa));
         if (r < pc.zbl_r2) {
             double U, dU;
             zbl_pair((double)r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
