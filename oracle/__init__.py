@@ -234,4 +234,5 @@ def num_threads():
     return int(lib().orc_num_threads())
 
 
-from .md import velocity_verlet, kinetic_energy, EV_PER_U_TO_A2_PER_FS2  # noqa: E402,F401
+from .md import (velocity_verlet, velocity_verlet_nhc, kinetic_energy, border_mask,  # noqa: E402,F401
+                 NoseHooverChain, EV_PER_U_TO_A2_PER_FS2, K_B_EV)
