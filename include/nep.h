@@ -120,19 +120,42 @@ typedef struct {
     float *energy_atom;   /* [n_atoms] site energies U_i, eV; may be NULL */
 } nep_efv;
 
-/* Molecular-dynamics controls. */
+/* Molecular-dynamics controls.
+ *
+ * Border thermostat (Sec. II.B: the cascade runs hold a layer of about 3 a0
+ * at the periodic faces at the target temperature with a Nose-Hoover chain,
+ * Martyna, Klein and Tuckerman 1992).  With thermo_chain = M > 0, the atoms
+ * whose wrapped coordinate along an axis selected by thermo_axes lies within
+ * thermo_border of a face of the (orthorhombic, single) cell are coupled to a
+ * chain of M thermostats at thermo_T with masses Q_1 = N_f k T tau^2,
+ * Q_j = k T tau^2 (N_f = 3 x border atoms).  Each step is: half a chain step
+ * (the border velocities are scaled), the velocity-Verlet step, half a chain
+ * step.  The border set and the chain state persist between calls on the same
+ * system; they are (re)initialised (chain at rest) on the first thermostatted
+ * call for a system, when thermo_reset is nonzero, or when thermo_chain,
+ * thermo_axes or thermo_border change.  thermo_T and thermo_tau may change
+ * between calls. */
 typedef struct {
     double dt_max;        /* fs, upper limit of the step (Sec. II.B: 1 fs) */
     double max_disp;      /* A, the fastest atom moves at most this far per step; 0 = fixed dt_max */
     double dt_min;        /* fs, a step below this latches NEP_E_DT_UNDERFLOW */
     int32_t forces_valid; /* nonzero: out->f* already hold the forces of the current positions */
-    int32_t pad_;
+    int32_t thermo_chain; /* chain length M of the border thermostat, 0 = none, at most 8 */
+    double thermo_T;      /* K, target temperature (> 0 when thermo_chain > 0) */
+    double thermo_tau;    /* fs, chain time constant (> 0) */
+    double thermo_border; /* A, layer thickness at each selected face (>= 0; 0 selects no atom) */
+    int32_t thermo_axes;  /* bit a (0..2) set: the two faces normal to lattice vector a; 1..7 */
+    int32_t thermo_reset; /* nonzero: rebuild the border set and put the chain at rest first */
 } nep_md;
 
 typedef struct {
     int64_t n_rebuilds;   /* neighbour rebuilds during the chunk */
-    double dt_last;       /* fs, the last step length */
+    double dt_last;       /* fs, the step length for a following step */
     double time;          /* fs, simulated time of the chunk */
+    int64_t n_border;     /* atoms in the thermostatted layer (0 without thermostat) */
+    double thermo_energy; /* eV, chain energy sum_j Q_j v_j^2 / 2 + N_f kT xi_1 + kT sum_{j>1} xi_j;
+                             total energy + kinetic energy + this is conserved */
+    double border_temperature; /* K, 2 K_border / (N_f k_B) of the final velocities */
 } nep_md_stats;
 
 /* Create a context for the given hyperparameters and capacities; weights are
@@ -161,11 +184,13 @@ int nep_build_neighbors(nep_ctx *ctx, const nep_system *sys, void *stream);
 int nep_compute_efv(nep_ctx *ctx, const nep_system *sys, nep_efv *out, void *stream);
 
 /* Advance `sys` by n_steps velocity-Verlet steps (x, v updated in place), with
- * the adaptive step of `md`, rebuilding the neighbour lists on the device when
- * an atom has moved more than skin/2 since the last build.  On return `out`
- * holds energy, forces and virial of the final positions.  Synchronises
- * `stream` at the end; returns NEP_OK or the first latched device error, or
- * NEP_E_ARG / NEP_E_HIP.  `stats` may be NULL. */
+ * the adaptive step of `md` (Sec. II.B), rebuilding the neighbour lists on the
+ * device when an atom has moved more than skin/2 since the last build, and
+ * with the border thermostat when md->thermo_chain > 0 (one cell only, and
+ * its h must be diagonal, else NEP_E_UNSUPPORTED).  On return `out` holds
+ * energy, forces and virial of the final positions.  Synchronises `stream` at
+ * the end; returns NEP_OK or the first latched device error, or NEP_E_ARG /
+ * NEP_E_UNSUPPORTED / NEP_E_HIP.  `stats` may be NULL. */
 int nep_step_verlet(nep_ctx *ctx, nep_system *sys, const nep_md *md, int32_t n_steps,
                     nep_efv *out, nep_md_stats *stats, void *stream);
 

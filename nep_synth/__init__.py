@@ -44,7 +44,7 @@ _E_C = 1.602176634e-19                       # elementary charge, C
 _AMU = 1.66053906660e-27                     # atomic mass unit, kg
 _EV_PER_U_TO_A2_PER_FS2 = _E_C / _AMU * 1e-10  # (eV/u) -> (A/fs)^2
 
-SEEDS = {"model": 8140, "tiny": 1, "mid": 2, "large": 3, "diffbatch": 4, "batch": 5}
+SEEDS = {"model": 8140, "tiny": 1, "mid": 2, "large": 3, "diffbatch": 4, "batch": 5, "cascade": 6}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SCALES_PATH = os.path.join(_HERE, "model_scales.json")
@@ -272,6 +272,39 @@ def large(seed: int = SEEDS["large"], n_cells: int = 160, temperature: float = 3
     return _single(pos, h, vel, name="large",
                    meta={"seed": seed, "T": temperature, "pka": int(pka), "pka_dir": d.tolist(),
                          "pka_ev": pka_ev})
+
+
+def direction_135(rng, into_negative_z: bool = False):
+    """A member of the <135> family (a permutation of (1, 3, 5) with random
+    signs), unit length; with into_negative_z its z component is negative."""
+    perm = rng.permutation(3)
+    d = np.array([1.0, 3.0, 5.0])[perm] * rng.choice([-1.0, 1.0], size=3)
+    if into_negative_z and d[2] > 0:
+        d[2] = -d[2]
+    return d / np.linalg.norm(d)
+
+
+def cascade(n_cells=(150, 150, 180), foil: bool = True, pka_ev: float = 200e3, temperature: float = 300.0,
+            seed: int = SEEDS["cascade"], depth_cells: int = 4) -> System:
+    """Cascade set-up of Sec. II.B / Table I: bcc W of nx x ny x nz conventional
+    cells at `temperature`, one PKA of `pka_ev` along a seeded <135> direction.
+    foil: open boundaries along z (free surfaces at z = 0 and the top), the
+    PKA is the corner atom of the central column `depth_cells` cells below the
+    top surface, heading into the foil; bulk: periodic, the PKA is the corner
+    atom of the central cell.  The default is the 200 keV foil (8,100,000 atoms)."""
+    nx, ny, nz = n_cells
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos, h = bcc_lattice(nx, ny, nz)
+    vel = maxwell_boltzmann(rng, pos.shape[0], temperature)
+    cz = nz - 1 - depth_cells if foil else nz // 2
+    pka = 2 * ((cz * ny + ny // 2) * nx + nx // 2)
+    d = direction_135(rng, into_negative_z=foil)
+    vel[pka] = speed_for_energy(pka_ev) * d
+    s = _single(pos, h, vel, name="foil" if foil else "bulk",
+                meta={"seed": seed, "T": temperature, "pka": int(pka), "pka_dir": d.tolist(), "pka_ev": pka_ev,
+                      "n_cells": (nx, ny, nz)})
+    s.pbc = (1, 1, 0) if foil else (1, 1, 1)
+    return s
 
 
 def most_cubic_cells(n_target: int):

@@ -10,7 +10,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["nep_kernels.hip", "nep_build.hip", "nep_defects.hip", "nep_wide.hip", "nep_abi.hip"]
+SOURCES = ["nep_kernels.hip", "nep_build.hip", "nep_defects.hip", "nep_wide.hip", "nep_thermostat.hip",
+           "nep_abi.hip"]
 LIB = os.path.join(HERE, "libnep_hip.so")
 HOSTMATH_LIB = os.path.join(HERE, "libnep_hostmath.so")
 

@@ -66,15 +66,22 @@ __global__ void k_build_lists(PairConsts, double, double, double, double, const 
 __global__ void k_build_reverse(PairConsts, const int32_t *, const CellGeom *, const int32_t *,
                                 const uint32_t *, uint8_t *, int32_t *, const int32_t *);
 __global__ void k_kick_drift(int, double *, double *, double *, double *, double *, double *, const float *,
-                             const float *, const float *, double, const double *, double *, int32_t *);
+                             const float *, const float *, double, const double *, const uint8_t *, double *,
+                             int32_t *);
 __global__ void k_kick(int, double *, double *, double *, const float *, const float *, const float *, double,
-                       double *, const int32_t *);
-__global__ void k_vmax(int, const double *, const double *, const double *, double *);
+                       const uint8_t *, double *, double *, const int32_t *);
+__global__ void k_vmax(int, const double *, const double *, const double *, const uint8_t *, double *, double *);
 __global__ void k_dt_update(double, double, double, double *, int32_t *, int);
 __global__ void k_rebuild_flag(double, double *, int32_t *);
 __global__ void k_disp(int, const double *, const double *, const double *, const double *, double *);
 __global__ void k_set_flag(int32_t *, int32_t);
 __global__ void k_cell_of(int, int, const int64_t *, int32_t *);
+// kernels (nep_thermostat.hip)
+__global__ void k_border_mask(int, const double *, const double *, const double *, double, double, double, int,
+                              double, uint8_t *, int32_t *);
+__global__ void k_scale_border(int, double *, double *, double *, const uint8_t *, const double *);
+__global__ void k_nhc(const double *, int, double, int, double, double, double, double, double, const int32_t *,
+                      double *, int32_t *, int);
 }  // namespace nep
 
 using namespace nep;
@@ -82,6 +89,8 @@ using namespace nep;
 // (eV / u) -> (A / fs)^2, i.e. an acceleration F/m in eV/(u A) to A/fs^2
 // (e = 1.602176634e-19 C, u = 1.66053906660e-27 kg).
 static const double ACC_EV_U_A = 9.6485332156653280e-3;
+// Boltzmann constant, eV/K (CODATA 2018)
+static const double K_B_EV = 8.617333262e-5;
 
 #define HIP_TRY(x)                                   \
     do {                                             \
@@ -125,7 +134,15 @@ struct nep_ctx {
     // status and md state
     int32_t *status = nullptr;       // [8]
     int32_t *flag = nullptr;         // rebuild flag
-    double *md = nullptr;            // [8]
+    double *md = nullptr;            // [MD_WORDS]
+    // border thermostat: one byte per atom, block partials of the border
+    // |v|^2, the border count, and what the set was selected with
+    uint8_t *border = nullptr;
+    double *ke_part = nullptr;       // [MAX_STREAM_BLOCKS]
+    int32_t *n_border = nullptr;
+    bool border_valid = false;
+    int th_chain = 0, th_axes = 0;
+    double th_border = 0.0;
     unsigned long long *counts = nullptr;
     double *pg_part = nullptr;       // parameter-gradient block partials
     int pg_blocks = 0;
@@ -163,7 +180,8 @@ static int bucket_of(int64_t n)
 
 static int xcd_grid(int tiles) { return 8 * ((tiles + 7) / 8); }
 // grid of the streaming (grid-stride) kernels: enough blocks to fill the chip
-static int stream_grid(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 2048); }
+static const int MAX_STREAM_BLOCKS = 2048;
+static int stream_grid(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, MAX_STREAM_BLOCKS); }
 
 static void inv3(const double *h, double *hi)
 {
@@ -204,7 +222,7 @@ void nep_destroy(nep_ctx *c)
                     c->w_atom,
                     c->e_atom, c->cells, c->cell_start_d, c->chunk_begin, c->chunk_end, c->cell_chunk,
                     c->part, c->bin_count, c->bin_start, c->bin_fill, c->scan_sums, c->status, c->flag,
-                    c->md, c->counts, c->pg_part};
+                    c->md, c->counts, c->pg_part, c->border, c->ke_part, c->n_border};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     if (c->h_status) (void)hipHostFree(c->h_status);
@@ -273,13 +291,16 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     A((void **)&c->cell_start_d, ((size_t)cfg->max_cells + 1) * 8);
     A((void **)&c->status, 8 * 4);
     A((void **)&c->flag, 4);
-    A((void **)&c->md, 8 * 8);
+    A((void **)&c->md, MD_WORDS * 8);
+    A((void **)&c->border, N);
+    A((void **)&c->ke_part, MAX_STREAM_BLOCKS * 8);
+    A((void **)&c->n_border, 4);
     A((void **)&c->counts, 2 * 8);
     if (ok && hipHostMalloc((void **)&c->h_status, 8 * 4, hipHostMallocDefault) != hipSuccess) ok = false;
-    if (ok && hipHostMalloc((void **)&c->h_md, 8 * 8, hipHostMallocDefault) != hipSuccess) ok = false;
+    if (ok && hipHostMalloc((void **)&c->h_md, MD_WORDS * 8, hipHostMallocDefault) != hipSuccess) ok = false;
     if (ok && hipHostMalloc((void **)&c->h_counts, 2 * 8, hipHostMallocDefault) != hipSuccess) ok = false;
     if (ok && hipMemset(c->status, 0, 8 * 4) != hipSuccess) ok = false;
-    if (ok && hipMemset(c->md, 0, 8 * 8) != hipSuccess) ok = false;
+    if (ok && hipMemset(c->md, 0, MD_WORDS * 8) != hipSuccess) ok = false;
     if (ok && hipMemset(c->params, 0, p_size * sizeof(float)) != hipSuccess) ok = false;
     // index arrays start in range, so that no kernel can ever see garbage indices
     if (ok && hipMemset(c->perm, 0, N * 4) != hipSuccess) ok = false;
@@ -352,6 +373,7 @@ static bool same_system(const nep_ctx *c, const nep_system *s)
 // Geometry, bins and reduction chunks of a new system (host decisions).
 static int setup_system(nep_ctx *c, const nep_system *s, hipStream_t st)
 {
+    c->border_valid = false;
     const int nc = s->cell_start ? s->n_cells : 1;
     const int64_t n = s->n_atoms;
     std::vector<int64_t> start(nc + 1);
@@ -925,15 +947,27 @@ int nep_step_verlet(nep_ctx *c, nep_system *s, const nep_md *md, int32_t n_steps
     if (rc) return rc;
     if ((rc = check_out(o))) return rc;
     if (!(md->dt_max > 0) || !(md->max_disp >= 0) || !(md->dt_min >= 0)) return NEP_E_ARG;
+    const bool thermo = md->thermo_chain != 0;
+    if (thermo) {
+        if (md->thermo_chain < 0 || md->thermo_chain > MD_NHC_MAX || !(md->thermo_T > 0) ||
+            !(md->thermo_tau > 0) || !(md->thermo_border >= 0) || md->thermo_axes < 1 || md->thermo_axes > 7)
+            return NEP_E_ARG;
+        if ((s->cell_start ? s->n_cells : 1) != 1) return NEP_E_UNSUPPORTED;
+        const double *h = s->h;
+        if (h[1] != 0 || h[2] != 0 || h[3] != 0 || h[5] != 0 || h[6] != 0 || h[7] != 0 || !(h[0] > 0) ||
+            !(h[4] > 0) || !(h[8] > 0))
+            return NEP_E_UNSUPPORTED;
+    }
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)s->n_atoms;
     const double acc = ACC_EV_U_A / s->mass;
     const double half_skin2 = 0.25 * c->cfg.skin * c->cfg.skin;
+    const int sg = stream_grid(n);
 
     // reset the step state (the pinned staging buffer is idle: the previous
-    // chunk synchronised before reading it)
-    for (int k = 0; k < 8; ++k) c->h_md[k] = 0.0;
-    HIP_TRY(hipMemcpyAsync(c->md, c->h_md, 8 * 8, hipMemcpyHostToDevice, st));
+    // chunk synchronised before reading it); the chain state is kept
+    for (int k = 0; k < MD_WORDS; ++k) c->h_md[k] = 0.0;
+    HIP_TRY(hipMemcpyAsync(c->md, c->h_md, MD_STEP_WORDS * 8, hipMemcpyHostToDevice, st));
     // lists valid for the current positions?
     bool fresh = false;
     if (!same_system(c, s)) {
@@ -943,37 +977,64 @@ int nep_step_verlet(nep_ctx *c, nep_system *s, const nep_md *md, int32_t n_steps
         c->built = true;
         fresh = true;
     } else {
-        k_disp<<<stream_grid(n), 256, 0, st>>>(n, s->x, s->y, s->z, c->xref, c->md);
+        k_disp<<<sg, 256, 0, st>>>(n, s->x, s->y, s->z, c->xref, c->md);
         k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag);
         if ((rc = launch_build(c, s, st, c->flag))) return rc;
     }
     if (!md->forces_valid || fresh) {
         if ((rc = launch_efv(c, s, o, st, true))) return rc;
     }
-    (void)fresh;
-    // first step length from the initial velocities
-    k_vmax<<<stream_grid(n), 256, 0, st>>>(n, s->vx, s->vy, s->vz, c->md);
-    k_dt_update<<<1, 64, 0, st>>>(md->dt_max, md->max_disp, md->dt_min, c->md, c->status, 0);
+    // border set and chain at rest, from the positions at this call's start
+    const bool th = thermo && n_steps > 0;
+    if (th && (md->thermo_reset || !c->border_valid || c->th_chain != md->thermo_chain ||
+               c->th_axes != md->thermo_axes || c->th_border != md->thermo_border)) {
+        HIP_TRY(hipMemcpyAsync(c->md + MD_STEP_WORDS, c->h_md + MD_STEP_WORDS, (MD_WORDS - MD_STEP_WORDS) * 8,
+                               hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemsetAsync(c->n_border, 0, 4, st));
+        k_border_mask<<<sg, 256, 0, st>>>(n, s->x, s->y, s->z, s->h[0], s->h[4], s->h[8], md->thermo_axes,
+                                          md->thermo_border, c->border, c->n_border);
+        c->border_valid = true;
+        c->th_chain = md->thermo_chain;
+        c->th_axes = md->thermo_axes;
+        c->th_border = md->thermo_border;
+    }
+    const uint8_t *bd = th ? c->border : nullptr;
+    const double mass_conv = s->mass / ACC_EV_U_A;   // 2K (eV) = mass_conv * sum |v|^2
+    const double kT = K_B_EV * md->thermo_T;
+    auto chain = [&](int phase) {
+        k_nhc<<<1, 256, 0, st>>>(c->ke_part, sg, mass_conv, md->thermo_chain, kT, md->thermo_tau, md->dt_max,
+                                 md->max_disp, md->dt_min, c->n_border, c->md, c->status, phase);
+    };
+    // first step length (and first chain half step) from the initial velocities
+    k_vmax<<<sg, 256, 0, st>>>(n, s->vx, s->vy, s->vz, bd, c->ke_part, c->md);
+    if (th) chain(0);
+    else k_dt_update<<<1, 64, 0, st>>>(md->dt_max, md->max_disp, md->dt_min, c->md, c->status, 0);
     // the rebuild counter counts rebuilds inside the chunk only
     HIP_TRY(hipMemsetAsync(c->md + MD_NREB, 0, 8, st));
     for (int k = 0; k < n_steps; ++k) {
-        k_kick_drift<<<stream_grid(n), 256, 0, st>>>(n, s->x, s->y, s->z, s->vx, s->vy, s->vz, o->fx, o->fy,
-                                                       o->fz, acc, c->xref, c->md, c->status);
+        k_kick_drift<<<sg, 256, 0, st>>>(n, s->x, s->y, s->z, s->vx, s->vy, s->vz, o->fx, o->fy, o->fz, acc,
+                                         c->xref, bd, c->md, c->status);
         k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag);
         if ((rc = launch_build(c, s, st, c->flag))) return rc;
         if ((rc = launch_efv(c, s, o, st, true))) return rc;
-        k_kick<<<stream_grid(n), 256, 0, st>>>(n, s->vx, s->vy, s->vz, o->fx, o->fy, o->fz, acc, c->md,
-                                                 c->status);
-        k_dt_update<<<1, 64, 0, st>>>(md->dt_max, md->max_disp, md->dt_min, c->md, c->status, 1);
+        k_kick<<<sg, 256, 0, st>>>(n, s->vx, s->vy, s->vz, o->fx, o->fy, o->fz, acc, bd, c->ke_part, c->md,
+                                   c->status);
+        if (th) chain(k + 1 < n_steps ? 1 : 2);
+        else k_dt_update<<<1, 64, 0, st>>>(md->dt_max, md->max_disp, md->dt_min, c->md, c->status, 1);
     }
+    if (th) k_scale_border<<<sg, 256, 0, st>>>(n, s->vx, s->vy, s->vz, c->border, c->md);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(c->h_md, c->md, 8 * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(c->h_md, c->md, MD_WORDS * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(c->h_status, c->status, 8 * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (stats) {
         stats->n_rebuilds = (int64_t)c->h_md[MD_NREB];
         stats->dt_last = c->h_md[MD_DT];
         stats->time = c->h_md[MD_TIME];
+        stats->n_border = th ? (int64_t)c->h_md[MD_NBORDER] : 0;
+        stats->thermo_energy = th ? c->h_md[MD_ENHC] : 0.0;
+        stats->border_temperature =
+            stats->n_border > 0 ? c->h_md[MD_TWOK] / (3.0 * (double)stats->n_border * K_B_EV) : 0.0;
     }
     const int code = c->h_status[ST_ERR];
     if (code != 0) {

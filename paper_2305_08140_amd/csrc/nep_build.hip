@@ -368,22 +368,42 @@ __device__ inline void block_max_atomic(double v, double *dst)
     }
 }
 
+// Block sum of a double in a fixed order (waves by shuffles, then the four
+// wave sums in order); thread 0 stores it to dst.  Blocks of 256 threads.
+__device__ inline void block_sum_store(double v, double *dst)
+{
+    __shared__ double sh[4];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+        *dst = t;
+    }
+}
+
 // v += dt/2 F/m ; x += dt v ; track the largest displacement since the last
-// build.  Grid-stride loop over atoms (blocks of 256 threads).
+// build.  With a border set, the velocities of border atoms are first scaled
+// by md[MD_SCALE] (the thermostat's factors since the last kick).
+// Grid-stride loop over atoms (blocks of 256 threads).
 __global__ __launch_bounds__(256) void k_kick_drift(int n, double *__restrict__ x, double *__restrict__ y,
                                                     double *__restrict__ z, double *__restrict__ vx,
                                                     double *__restrict__ vy, double *__restrict__ vz,
                                                     const float *__restrict__ fx, const float *__restrict__ fy,
                                                     const float *__restrict__ fz, double acc_per_mass,
-                                                    const double *__restrict__ xref, double *__restrict__ md,
-                                                    int32_t *__restrict__ status)
+                                                    const double *__restrict__ xref, const uint8_t *__restrict__ border,
+                                                    double *__restrict__ md, int32_t *__restrict__ status)
 {
     double dmax = 0.0;
     if (status[ST_ERR] == 0) {
         const double dt = md[MD_DT];
         const double c = 0.5 * dt * acc_per_mass;
+        const double scale = border ? md[MD_SCALE] : 1.0;
         for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-            const double v0 = vx[i] + c * fx[i], v1 = vy[i] + c * fy[i], v2 = vz[i] + c * fz[i];
+            double u0 = vx[i], u1 = vy[i], u2 = vz[i];
+            if (border && border[i]) { u0 *= scale; u1 *= scale; u2 *= scale; }
+            const double v0 = u0 + c * fx[i], v1 = u1 + c * fy[i], v2 = u2 + c * fz[i];
             vx[i] = v0; vy[i] = v1; vz[i] = v2;
             const double p0 = x[i] + dt * v0, p1 = y[i] + dt * v1, p2 = z[i] + dt * v2;
             x[i] = p0; y[i] = p1; z[i] = p2;
@@ -396,33 +416,57 @@ __global__ __launch_bounds__(256) void k_kick_drift(int n, double *__restrict__ 
     block_max_atomic(dmax, md + MD_DISP2);
 }
 
+// Largest |v|^2 (of the non-border atoms when a border set is given; then
+// also the border maximum and the border sum of |v|^2, for the thermostat).
+struct VelStats {
+    double vmax = 0.0, vmax_b = 0.0, sum_b = 0.0;
+    __device__ void add(double v2, bool b)
+    {
+        if (b) { vmax_b = fmax(vmax_b, v2); sum_b += v2; }
+        else vmax = fmax(vmax, v2);
+    }
+    // block results: maxima into md, the border sum into ke_part[blockIdx.x]
+    __device__ void store(bool has_border, double *__restrict__ ke_part, double *__restrict__ md) const
+    {
+        block_max_atomic(vmax, md + MD_VMAX2);
+        if (has_border) {
+            __syncthreads();
+            block_max_atomic(vmax_b, md + MD_VMAX2B);
+            __syncthreads();
+            block_sum_store(sum_b, ke_part + blockIdx.x);
+        }
+    }
+};
+
 // v += dt/2 F/m ; track max |v|^2 for the next step length.
 __global__ __launch_bounds__(256) void k_kick(int n, double *__restrict__ vx, double *__restrict__ vy,
                                               double *__restrict__ vz, const float *__restrict__ fx,
                                               const float *__restrict__ fy, const float *__restrict__ fz,
-                                              double acc_per_mass, double *__restrict__ md,
+                                              double acc_per_mass, const uint8_t *__restrict__ border,
+                                              double *__restrict__ ke_part, double *__restrict__ md,
                                               const int32_t *__restrict__ status)
 {
-    double vmax = 0.0;
+    VelStats vs;
     if (status[ST_ERR] == 0) {
         const double c = 0.5 * md[MD_DT] * acc_per_mass;
         for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
             const double v0 = vx[i] + c * fx[i], v1 = vy[i] + c * fy[i], v2 = vz[i] + c * fz[i];
             vx[i] = v0; vy[i] = v1; vz[i] = v2;
-            vmax = fmax(vmax, v0 * v0 + v1 * v1 + v2 * v2);
+            vs.add(v0 * v0 + v1 * v1 + v2 * v2, border && border[i]);
         }
     }
-    block_max_atomic(vmax, md + MD_VMAX2);
+    vs.store(border != nullptr, ke_part, md);
 }
 
-// max |v|^2 of the current velocities.
+// max |v|^2 of the current velocities (and the border statistics).
 __global__ __launch_bounds__(256) void k_vmax(int n, const double *__restrict__ vx, const double *__restrict__ vy,
-                                              const double *__restrict__ vz, double *__restrict__ md)
+                                              const double *__restrict__ vz, const uint8_t *__restrict__ border,
+                                              double *__restrict__ ke_part, double *__restrict__ md)
 {
-    double vmax = 0.0;
+    VelStats vs;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        vmax = fmax(vmax, vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
-    block_max_atomic(vmax, md + MD_VMAX2);
+        vs.add(vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i], border && border[i]);
+    vs.store(border != nullptr, ke_part, md);
 }
 
 // Step length for the next step: dt = min(dt_max, max_disp / max|v|) (Sec. II.B).
@@ -437,6 +481,7 @@ __global__ void k_dt_update(double dt_max, double max_disp, double dt_min, doubl
     if (!(dt >= dt_min)) latch_error(status, -6);
     md[MD_DT] = dt;
     md[MD_VMAX2] = 0.0;
+    md[MD_VMAX2B] = 0.0;
 }
 
 // Rebuild decision: an atom moved more than skin/2 since the last build.

@@ -86,8 +86,18 @@ constexpr int ST_NEED_R = 2;
 
 // velocity-Verlet state (doubles): step length (fs), max |v|^2, max
 // displacement^2 since the last build (both as ordered bit patterns of
-// non-negative doubles), simulated time, rebuild count.
-constexpr int MD_DT = 0, MD_VMAX2 = 1, MD_DISP2 = 2, MD_TIME = 3, MD_NREB = 4;
+// non-negative doubles), simulated time, rebuild count.  With the border
+// thermostat: max |v|^2 of the border atoms, the factor the next kick applies
+// to border velocities first, 2K of the border atoms (eV) after the last
+// scaling, the chain positions and velocities (MD_NHC_MAX each) and the
+// chain's energy.  MD_STEP_WORDS words are reset at every call; the chain
+// state after them persists.
+constexpr int MD_DT = 0, MD_VMAX2 = 1, MD_DISP2 = 2, MD_TIME = 3, MD_NREB = 4, MD_VMAX2B = 5, MD_SCALE = 6,
+              MD_TWOK = 7;
+constexpr int MD_STEP_WORDS = 8;
+constexpr int MD_NHC_MAX = 8;
+constexpr int MD_XI = 8, MD_VXI = MD_XI + MD_NHC_MAX, MD_ENHC = MD_VXI + MD_NHC_MAX, MD_NBORDER = MD_ENHC + 1;
+constexpr int MD_WORDS = 32;
 
 __device__ inline void latch_error(int *status, int code)
 {

@@ -63,3 +63,35 @@ def test_strerror_covers_codes():
         s = nep.strerror(code)
         assert s and s != "unknown error"
     assert nep.strerror(-99) == "unknown error"
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # sizeof and every field offset of the header's structs, compiled with the
+    # host C compiler, against the ctypes mirrors of the binding
+    import shutil
+    import subprocess
+    import paper_2305_08140_amd as nep
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = {"nep_hparams": nep.Hparams, "nep_weights": nep.Weights, "nep_config": nep.Config,
+             "nep_system": nep.System, "nep_efv": nep.Efv, "nep_md": nep.Md, "nep_md_stats": nep.MdStats,
+             "nep_bcc_ref": nep.BccRef, "nep_defects": nep.Defects}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "nep.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        a, b, v = ln.split()
+        got[(a, b)] = int(v)
+    for cname, py in pairs.items():
+        assert got[(cname, "sizeof")] == C.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])

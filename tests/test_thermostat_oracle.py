@@ -5,6 +5,8 @@ integrated to high accuracy (a symmetric splitting has a local error of third
 order), the full integrator against its conserved quantity and its second-order
 convergence, and the border selection against lattice counts.
 """
+import os
+
 import numpy as np
 import pytest
 from scipy.integrate import solve_ivp
@@ -101,3 +103,69 @@ def test_slow_chain_reduces_to_plain_verlet():
     p1, v1, _, _, _, _ = oracle.velocity_verlet_nhc(m, s.pos, s.vel, s.h[0], s.mass, 20, dt_max=1.0,
                                                     temperature=300.0, tau=1e9, thickness=0.6 * nep_synth.A_W)
     assert np.abs(p1 - p0).max() < 1e-12 and np.abs(v1 - v0).max() < 1e-12
+
+
+# ------------------------------------------------------------------ planted mistakes
+
+_MD_SRC = os.path.join(os.path.dirname(oracle.__file__), "md.py")
+
+MUTATIONS = {
+    "G1_sign": ("return (twoK - self.n_dof * self.kT) / self.Q[0]", "return (self.n_dof * self.kT - twoK) / self.Q[0]"),
+    "G_chain_index": ("return (self.Q[j - 1] * self.v[j - 1] ** 2 - self.kT) / self.Q[j]",
+                      "return (self.Q[j] * self.v[j] ** 2 - self.kT) / self.Q[j]"),
+    "scale_sign": ("s = np.exp(-v[0] * dt / 2.0)", "s = np.exp(v[0] * dt / 2.0)"),
+    "twoK_not_rescaled": ("        twoK *= s * s\n", "\n"),
+    "xi_full_step": ("self.xi += v * dt / 2.0", "self.xi += v * dt"),
+    "inner_factor_dropped": ("        for j in range(M - 1):\n            v[j] *= np.exp(-v[j + 1] * d8)\n",
+                             "        for j in range(M - 1):\n"),
+    "energy_xi_weight": ("+ self.kT * np.sum(self.xi[1:]))", "+ self.n_dof * self.kT * np.sum(self.xi[1:]))"),
+}
+
+
+def _mutated_md(name):
+    import importlib.util
+    src = open(_MD_SRC).read()
+    old, new = MUTATIONS[name]
+    assert old in src, name
+    spec = importlib.util.spec_from_loader("oracle._md_mutant", loader=None)
+    mod = importlib.util.module_from_spec(spec)
+    mod.__package__ = "oracle"
+    exec(compile(src.replace(old, new, 1), f"<md mutant {name}>", "exec"), mod.__dict__)
+    return mod
+
+
+def _pins_hold(md):
+    """The fast pins above, run against a module providing the chain and integrator."""
+    # flow: third-order local error and small at dt = 1 (M = 3)
+    errs = []
+    for dt in (2.0, 1.0):
+        ch = md.NoseHooverChain(30, 600.0, 10.0, 3)
+        ch.v[:] = np.linspace(0.02, -0.01, 3)
+        twoK = 30 * oracle.K_B_EV * 300.0
+        y0 = np.concatenate([[twoK], ch.v.copy(), ch.xi.copy()])
+        y = solve_ivp(_thermostat_flow(30, ch.kT, ch.Q, 3), (0.0, dt / 2), y0, rtol=1e-13, atol=1e-16,
+                      method="DOP853").y[:, -1]
+        s = ch.half_step(twoK, dt)
+        errs.append(max(abs(s - np.sqrt(y[0] / twoK)), np.abs(ch.v - y[1:4]).max() * dt,
+                        np.abs(ch.xi - y[4:]).max()))
+    if not (6.5 < errs[0] / errs[1] < 9.0 and errs[1] < 2e-4):
+        return False
+    # conserved quantity and heating over 150 steps
+    m = nep_synth.random_model()
+    s = nep_synth.mid(n_cells=4)
+    _, _, _, log, _, _ = md.velocity_verlet_nhc(m, s.pos, s.vel * np.sqrt(100.0 / 300.0), s.h[0], s.mass, 150,
+                                                dt_max=1.0, temperature=900.0, tau=20.0, chain=3,
+                                                thickness=0.6 * nep_synth.A_W, axes=(0,), record=True)
+    c = np.array([x["conserved"] for x in log])
+    T = np.array([x["T_border"] for x in log])
+    return bool(np.abs(c - c[0]).max() / s.n_atoms < 1e-4 and T[100:].mean() > 300.0)
+
+
+def test_pins_hold_on_the_real_thermostat():
+    import oracle.md as md
+    assert _pins_hold(md)
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_thermostat_mistake_is_caught(name):
+    assert not _pins_hold(_mutated_md(name))
