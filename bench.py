@@ -217,6 +217,46 @@ def bench_paper_model(args, s, N):
     return res
 
 
+def bench_foil(args, model):
+    """The paper's production cascade set-up (Sec. II.B, Table I foil row):
+    a 150 x 150 x 180-cell W foil (8,100,000 atoms), open along z, 300 K, the
+    3 a0 layers at the x and y faces held at 300 K by a Nose-Hoover chain of 3
+    (tau = 100 fs, not stated in the paper), one 200 keV PKA along <135> into
+    the foil 4 cells below the top surface, adaptive step (0.01 A, <= 1 fs)."""
+    import torch
+    import nep_synth
+    import oracle
+    import paper_2305_08140_amd as nep
+    f = nep_synth.cascade((150, 150, 180), foil=True, pka_ev=200e3)
+    N = f.n_atoms
+    sysd = nep.DeviceSystem.from_synth(f)
+    ctx = nep.Context(model, N, 1, max_neigh_ang=48, max_neigh_rad=96, skin=1.0)
+    out = nep.EFV(N, 1)
+    th = dict(T=300.0, tau=100.0, border=3 * nep_synth.A_W, axes=(0, 1), chain=3)
+    md = dict(dt_max=1.0, max_disp=0.01, dt_min=1e-7)
+    ctx.nep_step_verlet(sysd, 5, out, forces_valid=False, thermostat=th, **md)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.nep_step_verlet(sysd, args.foil_steps, out, forces_valid=True, thermostat=th, **md)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pos_now = sysd.positions().cpu().numpy()
+    F = out.forces().cpu().numpy().astype(np.float64)
+    pka = f.meta["pka"]
+    idx = np.sort(np.random.default_rng(1).choice(N, size=256, replace=False))
+    ref = oracle.efv_cell(model, pos_now, f.h[0], f.pbc, targets=idx, virial=False)
+    err = float(np.linalg.norm(F[idx] - ref["forces"]) / np.linalg.norm(ref["forces"]))
+    res = {"atom_steps_per_s": N * args.foil_steps / wall, "ms_per_step": wall / args.foil_steps * 1e3,
+           "steps": args.foil_steps, "n_atoms": N, "n_border": st["n_border"],
+           "border_temperature_K": st["border_temperature"], "dt_last_fs": st["dt_last"],
+           "time_fs": st["time"], "n_rebuilds": st["n_rebuilds"],
+           "pka_speed_A_per_fs": float(np.linalg.norm(sysd.velocities()[pka].cpu().numpy())),
+           "force_rel_err_vs_fp64_sampled": err}
+    del ctx, out, sysd
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_batches(model, reps=20, n_percell=128):
     """Batched evaluation of many small cells against per-cell launches.
 
@@ -304,6 +344,8 @@ def main():
     ap.add_argument("--no-batches", action="store_true", help="skip the batched small-cell workloads")
     ap.add_argument("--paper-steps", type=int, default=50,
                     help="MD steps of the paper-size model on the same workload (0 skips it)")
+    ap.add_argument("--foil-steps", type=int, default=50,
+                    help="MD steps of the 8,100,000-atom foil cascade with the border thermostat (0 skips it)")
     ap.add_argument("--timing-reps", type=int, default=5)
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ summaries from rocprofv3 output directories and exit")
@@ -314,12 +356,12 @@ def main():
         n = 2 * args.cells ** 3
         kt_dir, fetch_dir, write_dir = args.summarize_rocprof
         cmd = {"kt": "rocprofv3 --kernel-trace --stats -d %s -o kt --output-format csv -- "
-                     "python3 bench.py --steps 20 --warmup 3 --no-cpu-baseline --no-batches" % kt_dir,
+                     "python3 bench.py --steps 20 --warmup 3 --no-cpu-baseline --no-batches --foil-steps 0" % kt_dir,
                "fetch": "rocprofv3 --pmc FETCH_SIZE -d %s -o f --output-format csv -- "
-                        "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batches "
+                        "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batches --foil-steps 0 "
                         "--copy-calibration-mib 1024 --timing-reps 1" % fetch_dir,
                "write": "rocprofv3 --pmc WRITE_SIZE -d %s -o w --output-format csv -- "
-                        "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batches "
+                        "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batches --foil-steps 0 "
                         "--copy-calibration-mib 1024 --timing-reps 1" % write_dir}
         summarize_rocprof(*args.summarize_rocprof, n, cmd, os.path.join(ROOT, "profiles"))
         return
@@ -408,6 +450,7 @@ def main():
     del ctx, sysd, out
     torch.cuda.empty_cache()
     paper = bench_paper_model(args, s, N) if args.paper_steps > 0 else None
+    foil = bench_foil(args, model) if args.foil_steps > 0 else None
 
     batches = None
     if not args.no_batches:
@@ -438,6 +481,7 @@ def main():
         "site_energy_max_abs_err_eV": eerr,
         "defects": defects,
         "paper_model": paper,
+        "foil_cascade": foil,
         "batches": batches,
     }
     print(json.dumps(line), flush=True)

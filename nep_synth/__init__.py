@@ -285,17 +285,22 @@ def direction_135(rng, into_negative_z: bool = False):
 
 
 def cascade(n_cells=(150, 150, 180), foil: bool = True, pka_ev: float = 200e3, temperature: float = 300.0,
-            seed: int = SEEDS["cascade"], depth_cells: int = 4) -> System:
+            seed: int = SEEDS["cascade"], depth_cells: int = 4, sigma: float = 0.045) -> System:
     """Cascade set-up of Sec. II.B / Table I: bcc W of nx x ny x nz conventional
     cells at `temperature`, one PKA of `pka_ev` along a seeded <135> direction.
     foil: open boundaries along z (free surfaces at z = 0 and the top), the
     PKA is the corner atom of the central column `depth_cells` cells below the
     top surface, heading into the foil; bulk: periodic, the PKA is the corner
-    atom of the central cell.  The default is the 200 keV foil (8,100,000 atoms)."""
+    atom of the central cell.  The default is the 200 keV foil (8,100,000 atoms).
+    Atoms sit on lattice sites displaced by N(0, sigma^2) per component
+    (0.045 A: about the root-mean-square thermal displacement of W at 300 K),
+    standing in for the paper's 30 ps equilibration."""
     nx, ny, nz = n_cells
     rng = np.random.Generator(np.random.PCG64(seed))
     pos, h = bcc_lattice(nx, ny, nz)
     vel = maxwell_boltzmann(rng, pos.shape[0], temperature)
+    if sigma > 0:
+        pos = pos + rng.normal(0.0, sigma, size=pos.shape)
     cz = nz - 1 - depth_cells if foil else nz // 2
     pka = 2 * ((cz * ny + ny // 2) * nx + nx // 2)
     d = direction_135(rng, into_negative_z=foil)
