@@ -316,6 +316,68 @@ int nep_wigner_seitz(const nep_system *sys, const nep_bcc_ref *ref, int32_t *occ
 /* Static description of an error code. */
 const char *nep_strerror(int code);
 
+/* ---- SNES population evaluation --------------------------------------- */
+
+/* The paper trains its model with the separable natural evolution strategy
+ * (SNES, Schaul et al. 2011) with a population of 50, on a loss with weights
+ * lambda_e = lambda_f = 1, lambda_v = 0.1, lambda_1 = lambda_2 = 0.05
+ * (Sec. III.A; the loss itself is the NEP one the paper cites):
+ *   L = le RMSE(E/N) + lf RMSE(F components) + lv RMSE(W/N, six components,
+ *       cells with a virial target) + l1 mean|theta| + l2 sqrt(mean theta^2).
+ * Parameter vectors theta use the layout of nep_backward's grad_params:
+ * (c_rad [n_rad][k_rad], c_ang [n_ang][k_ang], w0 [n_hidden][D], b0, w1, b1),
+ * nep_num_params() floats; the descriptor scale q_scale is not trained and is
+ * taken from the weights last set with nep_set_weights. */
+
+#define NEP_MAX_POPULATION 1024
+#define NEP_LOSS_TERMS 6   /* total, rmse_e, rmse_f, rmse_v, mean|theta|, rms theta */
+
+typedef struct {
+    const double *energy;        /* DEVICE [n_cells] target energies, eV */
+    const float *fx, *fy, *fz;   /* DEVICE [n_atoms] target forces, eV/A, caller order */
+    const double *virial;        /* DEVICE [n_cells][9] target virials, eV; NULL: no virial term */
+    const uint8_t *has_virial;   /* DEVICE [n_cells], nonzero where the cell has a virial target;
+                                    NULL: every cell (when virial is given) */
+    double lambda_e, lambda_f, lambda_v, lambda_1, lambda_2;
+} nep_targets;
+
+/* Allocate the per-member evaluation buffers of up to n_pop (1..1024)
+ * members at the context's capacity (about 0.9 KB per atom and member with
+ * max_neigh_ang = 48), replacing earlier ones.  Synchronises the device.
+ * Returns NEP_OK, NEP_E_ARG, NEP_E_UNSUPPORTED (paper-size model) or
+ * NEP_E_HIP. */
+int nep_population_reserve(nep_ctx *ctx, int32_t n_pop);
+
+/* Energies, forces and virials of the batch `sys` for n_pop parameter
+ * vectors at once (one launch over members x atom tiles), and, with targets,
+ * each member's loss terms.  Same preconditions as nep_compute_efv (lists
+ * built for `sys`); n_pop <= the reserved population.
+ *   theta   DEVICE float [n_pop][nep_num_params()]
+ *   energy  DEVICE double [n_pop][n_cells] or NULL
+ *   forces  DEVICE float [n_pop][3][n_atoms] (fx, fy, fz rows, caller order) or NULL
+ *   virial  DEVICE double [n_pop][n_cells][9] or NULL
+ *   tg      targets (required with loss), read on the device
+ *   loss    DEVICE double [n_pop][NEP_LOSS_TERMS] or NULL
+ * Asynchronous on `stream`.  Returns NEP_OK, NEP_E_ARG, NEP_E_STATE,
+ * NEP_E_UNSUPPORTED or NEP_E_HIP; device errors latch as for nep_compute_efv. */
+int nep_population_efv(nep_ctx *ctx, const nep_system *sys, int32_t n_pop, const float *theta, double *energy,
+                       float *forces, double *virial, const nep_targets *tg, double *loss, void *stream);
+
+/* SNES sampling: theta[k][p] = mu[p] + sigma[p] draws[k][p] (all DEVICE float;
+ * draws are the caller's standard-normal numbers).  Asynchronous. */
+int nep_snes_sample(int32_t n_pop, int32_t n_params, const float *mu, const float *sigma, const float *draws,
+                    float *theta, void *stream);
+
+/* SNES update from the members' losses (DEVICE double, member k's loss at
+ * loss[k loss_stride]; lower is better, NaN is worst, ties keep the member
+ * order): rank-based utilities u (best first, summing to zero),
+ * mu += eta_mu sigma sum_k u_k s_k, sigma *= exp(eta_sigma / 2 sum_k u_k (s_k^2 - 1)),
+ * in place on DEVICE float mu, sigma [n_params].  eta_mu <= 0 selects 1,
+ * eta_sigma <= 0 selects (3 + ln n_params) / (5 sqrt n_params).
+ * 2 <= n_pop <= 1024.  Asynchronous. */
+int nep_snes_update(int32_t n_pop, int32_t n_params, const double *loss, int32_t loss_stride, const float *draws,
+                    float *mu, float *sigma, double eta_mu, double eta_sigma, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

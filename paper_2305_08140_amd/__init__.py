@@ -30,11 +30,16 @@ NEP_E_UNSUPPORTED = -8
 NEP_E_INTERNAL = -9
 NEP_E_CAPACITY = -10
 NEP_WS_WORK_INTS = 8
+NEP_MAX_POPULATION = 1024
+NEP_LOSS_TERMS = 6
+# loss weights of Sec. III.A
+PAPER_LAMBDAS = {"e": 1.0, "f": 1.0, "v": 0.1, "l1": 0.05, "l2": 0.05}
 
 EXPORTED = ("nep_create", "nep_destroy", "nep_set_weights", "nep_build_neighbors", "nep_compute_efv",
             "nep_step_verlet", "nep_status", "nep_required_neighbors", "nep_mean_neighbors",
             "nep_time_efv", "nep_num_params", "nep_backward", "nep_compute_efv_graph", "nep_autotune",
-            "nep_set_precision", "nep_wigner_seitz", "nep_strerror")
+            "nep_set_precision", "nep_wigner_seitz", "nep_population_reserve", "nep_population_efv",
+            "nep_snes_sample", "nep_snes_update", "nep_strerror")
 
 
 class NepError(RuntimeError):
@@ -89,6 +94,13 @@ class Defects(C.Structure):
                 ("n_interstitial_clusters", C.c_int32), ("largest_interstitial_cluster", C.c_int32)]
 
 
+class Targets(C.Structure):
+    _fields_ = [("energy", C.c_void_p), ("fx", C.c_void_p), ("fy", C.c_void_p), ("fz", C.c_void_p),
+                ("virial", C.c_void_p), ("has_virial", C.c_void_p), ("lambda_e", C.c_double),
+                ("lambda_f", C.c_double), ("lambda_v", C.c_double), ("lambda_1", C.c_double),
+                ("lambda_2", C.c_double)]
+
+
 class MdStats(C.Structure):
     _fields_ = [("n_rebuilds", C.c_int64), ("dt_last", C.c_double), ("time", C.c_double),
                 ("n_border", C.c_int64), ("thermo_energy", C.c_double), ("border_temperature", C.c_double)]
@@ -124,6 +136,10 @@ def lib():
         L.nep_backward.argtypes = [P, C.POINTER(System), C.POINTER(Efv), P, P, P, P, P, P, P]
         L.nep_wigner_seitz.argtypes = [C.POINTER(System), C.POINTER(BccRef), P, P, C.c_int32, P, P, P, P, P, P,
                                        C.POINTER(Defects), P]
+        L.nep_population_reserve.argtypes = [P, C.c_int32]
+        L.nep_population_efv.argtypes = [P, C.POINTER(System), C.c_int32, P, P, P, P, C.POINTER(Targets), P, P]
+        L.nep_snes_sample.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P]
+        L.nep_snes_update.argtypes = [C.c_int32, C.c_int32, P, C.c_int32, P, P, P, C.c_double, C.c_double, P]
         L.nep_strerror.argtypes = [C.c_int]
         L.nep_strerror.restype = C.c_char_p
         for name in EXPORTED:
@@ -345,6 +361,45 @@ class Context:
     def nep_num_params(self):
         return int(lib().nep_num_params(self._ptr))
 
+    def nep_population_reserve(self, n_pop):
+        _check(lib().nep_population_reserve(self._ptr, int(n_pop)), "nep_population_reserve")
+        self.pop_cap = int(n_pop)
+
+    def nep_population_efv(self, system: DeviceSystem, theta, targets=None, lambdas=PAPER_LAMBDAS,
+                           want_energy=True, want_forces=True, want_virial=True, stream=None):
+        """Evaluate every row of theta (device float32 [P, n_params]) on the
+        batch; returns device tensors energy [P, C], forces [P, 3, N],
+        virial [P, C, 9] (None where not wanted) and, with targets (a dict of
+        device tensors energy [C] f64, forces [3, N] f32, virial [C, 9] f64 or
+        None, has_virial [C] uint8 or None), loss [P, 6]."""
+        torch = _torch()
+        theta = theta.contiguous()
+        P_ = int(theta.shape[0])
+        dev = theta.device
+        N, Cc = system.n_atoms, system.n_cells
+        E = torch.empty(P_, Cc, dtype=torch.float64, device=dev) if want_energy else None
+        F = torch.empty(P_, 3, N, dtype=torch.float32, device=dev) if want_forces else None
+        W = torch.empty(P_, Cc, 9, dtype=torch.float64, device=dev) if want_virial else None
+        loss = None
+        tg = None
+        if targets is not None:
+            loss = torch.empty(P_, NEP_LOSS_TERMS, dtype=torch.float64, device=dev)
+            tf = targets["forces"]
+            tv = targets.get("virial")
+            hv = targets.get("has_virial")
+            tg = Targets(targets["energy"].data_ptr(), tf[0].data_ptr(), tf[1].data_ptr(), tf[2].data_ptr(),
+                         tv.data_ptr() if tv is not None else None, hv.data_ptr() if hv is not None else None,
+                         float(lambdas["e"]), float(lambdas["f"]), float(lambdas["v"]), float(lambdas["l1"]),
+                         float(lambdas["l2"]))
+        s = system.c_struct()
+        ptr = (lambda t: t.data_ptr() if t is not None else None)
+        _check(lib().nep_population_efv(self._ptr, C.byref(s), P_, theta.data_ptr(), ptr(E), ptr(F), ptr(W),
+                                        C.byref(tg) if tg is not None else None, ptr(loss), _stream_ptr(stream)),
+               "nep_population_efv")
+        if self.check:
+            self.nep_status(stream)
+        return {"energy": E, "forces": F, "virial": W, "loss": loss}
+
     def nep_backward(self, system: DeviceSystem, out: EFV, gE, grad_pos=True, grad_cell=True, stream=None):
         """dL/dtheta [P], dL/dx [N,3] and dL/dh [C,3,3] for L = sum_c gE[c] E_c (device FP64 tensors)."""
         torch = _torch()
@@ -381,6 +436,38 @@ def efv(model, system: DeviceSystem, ctx: Context | None = None, max_neigh_ang=4
     ctx.nep_build_neighbors(system)
     ctx.nep_compute_efv(system, out)
     return out, ctx
+
+
+def snes_sample(mu, sigma, draws, stream=None):
+    """theta = mu + sigma * draws on the device (float32 tensors; draws [P, n])."""
+    torch = _torch()
+    P_, n = (int(v) for v in draws.shape)
+    theta = torch.empty(P_, n, dtype=torch.float32, device=draws.device)
+    _check(lib().nep_snes_sample(P_, n, mu.data_ptr(), sigma.data_ptr(), draws.contiguous().data_ptr(),
+                                 theta.data_ptr(), _stream_ptr(stream)), "nep_snes_sample")
+    return theta
+
+
+def snes_update(mu, sigma, draws, loss, eta_mu=0.0, eta_sigma=0.0, stream=None):
+    """In-place SNES update of mu and sigma (device float32) from the members'
+    losses (device float64 [P] or [P, k], the first column is used)."""
+    P_, n = (int(v) for v in draws.shape)
+    stride = 1 if loss.dim() == 1 else int(loss.stride(0))
+    _check(lib().nep_snes_update(P_, n, loss.data_ptr(), stride, draws.contiguous().data_ptr(), mu.data_ptr(),
+                                 sigma.data_ptr(), float(eta_mu), float(eta_sigma), _stream_ptr(stream)),
+           "nep_snes_update")
+
+
+def snes_generation(ctx: "Context", system: "DeviceSystem", mu, sigma, draws, targets, lambdas=PAPER_LAMBDAS,
+                    stream=None):
+    """One SNES generation on the device: sample the population from (mu,
+    sigma) with the given standard-normal draws, evaluate every member's loss
+    on the batch, update mu and sigma in place.  Returns the loss terms [P, 6]."""
+    theta = snes_sample(mu, sigma, draws, stream)
+    res = ctx.nep_population_efv(system, theta, targets, lambdas, want_energy=False, want_forces=False,
+                                 want_virial=False, stream=stream)
+    snes_update(mu, sigma, draws, res["loss"], stream=stream)
+    return res["loss"]
 
 
 def wigner_seitz(system: "DeviceSystem", a: float, n_cells, capacity: int = 65536, site_of_atom: bool = False,

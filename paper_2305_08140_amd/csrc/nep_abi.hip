@@ -37,6 +37,23 @@ __global__ void k_grad_cell(const CellGeom *, const double *, const double *, co
 __global__ void k_count_inside(PairConsts, const double4 *, const int32_t *,
                                const CellGeom *, const int32_t *, const int32_t *, const uint32_t *,
                                unsigned long long *);
+__global__ void k_pop_params(const float *, const float *, float *, double *);
+__global__ void k_pop_descriptor(PairConsts, const double4 *, AtomRec *, const int32_t *, const CellGeom *,
+                                 const int32_t *, const int32_t *, const uint32_t *, const float *, const double *,
+                                 float4 *, float4 *, float *, double *, int32_t *, int, int);
+__global__ void k_pop_force(PairConsts, const AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
+                            const int32_t *, const uint32_t *, const uint8_t *, const float4 *, const float4 *,
+                            const int32_t *, float *, float *, int32_t *, int, int);
+__global__ void k_pop_reduce_chunks(int, int, const int32_t *, const int32_t *, const double *, const float *,
+                                    double *, const int32_t *);
+__global__ void k_pop_reduce_cells(int, int, const int32_t *, const double *, double *, double *,
+                                   const int32_t *);
+__global__ void k_pop_force_err(int, const float *, const float *, const float *, const float *, double *);
+__global__ void k_pop_loss(int, int, int, int, const int64_t *, const double *, const double *, const double *,
+                           const double *, const uint8_t *, const double *, const float *, double, double, double,
+                           double, double, double *);
+__global__ void k_snes_sample(int, int, const float *, const float *, const float *, float *);
+__global__ void k_snes_update(int, int, const double *, int, const float *, float *, float *, double, double);
 // kernels (nep_defects.hip)
 __global__ void k_ws_fill(int, int32_t *, int32_t);
 __global__ void k_ws_assign(int, const double *, const double *, const double *, BccRef, int32_t *, int32_t *,
@@ -143,6 +160,16 @@ struct nep_ctx {
     bool border_valid = false;
     int th_chain = 0, th_axes = 0;
     double th_border = 0.0;
+    // population evaluation (SNES): per-member parameters and evaluation
+    // buffers for up to pop_cap members at the context's capacity
+    int pop_cap = 0;
+    int64_t pop_chunk_cap = 0;
+    float *pop_P = nullptr;
+    double *pop_c64 = nullptr;
+    AtomRec *pop_xp = nullptr;
+    float4 *pop_pg = nullptr, *pop_fown = nullptr;
+    float *pop_w = nullptr, *pop_F = nullptr;
+    double *pop_e = nullptr, *pop_E = nullptr, *pop_W = nullptr, *pop_part = nullptr, *pop_fpart = nullptr;
     unsigned long long *counts = nullptr;
     double *pg_part = nullptr;       // parameter-gradient block partials
     int pg_blocks = 0;
@@ -212,11 +239,24 @@ const char *nep_strerror(int code)
     }
 }
 
+static void free_population(nep_ctx *c)
+{
+    void *bufs[] = {c->pop_P, c->pop_c64, c->pop_xp, c->pop_pg, c->pop_fown, c->pop_w, c->pop_F,
+                    c->pop_e, c->pop_E, c->pop_W, c->pop_part, c->pop_fpart};
+    for (void *p : bufs)
+        if (p) (void)hipFree(p);
+    c->pop_P = nullptr; c->pop_c64 = nullptr; c->pop_xp = nullptr; c->pop_pg = c->pop_fown = nullptr;
+    c->pop_w = c->pop_F = nullptr;
+    c->pop_e = c->pop_E = c->pop_W = c->pop_part = c->pop_fpart = nullptr;
+    c->pop_cap = 0;
+}
+
 void nep_destroy(nep_ctx *c)
 {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
+    free_population(c);
     void *bufs[] = {c->params, c->c64, c->w_S, c->w_Q, c->w_FpA, c->xw, c->xp, c->xq, c->xref, c->bin_rank, c->bin_lin, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
                     c->bin_sorted, c->ncnt, c->nl_ang, c->nl_rad, c->pair_grad, c->f_own, c->rev,
                     c->w_atom,
@@ -1126,6 +1166,110 @@ int nep_wigner_seitz(const nep_system *s, const nep_bcc_ref *ref, int32_t *occ, 
     out->largest_vacancy_cluster = h[5];
     out->n_interstitial_clusters = h[6];
     out->largest_interstitial_cluster = h[7];
+    return NEP_OK;
+}
+
+
+// ---------------------------------------------------------------- SNES population
+
+static const int POP_FBLK = 256;    // blocks of the force-error reduction per member
+
+int nep_population_reserve(nep_ctx *c, int32_t n_pop)
+{
+    if (!c || n_pop < 1 || n_pop > NEP_MAX_POPULATION) return NEP_E_ARG;
+    if (c->wide) return NEP_E_UNSUPPORTED;
+    if (hipSetDevice(c->device) != hipSuccess) return NEP_E_HIP;
+    if (hipDeviceSynchronize() != hipSuccess) return NEP_E_HIP;
+    free_population(c);
+    const size_t P = (size_t)n_pop, N = (size_t)c->cfg.max_atoms, C = (size_t)c->cfg.max_cells;
+    // chunks never span cells and hold at most 4096 atoms
+    const int64_t chunks = (int64_t)C + (int64_t)(N / 4096) + 1;
+    bool ok = true;
+    auto A = [&](void **p, size_t bytes) {
+        if (ok && hipMalloc(p, bytes > 0 ? bytes : 16) != hipSuccess) ok = false;
+    };
+    A((void **)&c->pop_P, P * P_SIZE * sizeof(float));
+    A((void **)&c->pop_c64, P * C64N * sizeof(double));
+    A((void **)&c->pop_xp, P * N * sizeof(AtomRec));
+    A((void **)&c->pop_pg, P * N * c->cfg.max_neigh_ang * sizeof(float4));
+    A((void **)&c->pop_fown, P * N * sizeof(float4));
+    A((void **)&c->pop_w, P * N * 9 * sizeof(float));
+    A((void **)&c->pop_F, P * N * 3 * sizeof(float));
+    A((void **)&c->pop_e, P * N * sizeof(double));
+    A((void **)&c->pop_E, P * C * sizeof(double));
+    A((void **)&c->pop_W, P * C * 9 * sizeof(double));
+    A((void **)&c->pop_part, P * (size_t)chunks * 10 * sizeof(double));
+    A((void **)&c->pop_fpart, P * POP_FBLK * sizeof(double));
+    if (!ok) { free_population(c); return NEP_E_HIP; }
+    c->pop_cap = n_pop;
+    c->pop_chunk_cap = chunks;
+    return NEP_OK;
+}
+
+int nep_population_efv(nep_ctx *c, const nep_system *s, int32_t n_pop, const float *theta, double *energy,
+                       float *forces, double *virial, const nep_targets *tg, double *loss, void *stream)
+{
+    if (!c || !theta || n_pop < 1) return NEP_E_ARG;
+    if (c->wide) return NEP_E_UNSUPPORTED;
+    if (n_pop > c->pop_cap) return NEP_E_ARG;
+    int rc = check_system(c, s, false);
+    if (rc) return rc;
+    if (!same_system(c, s)) return NEP_E_STATE;
+    if (c->n_chunks > c->pop_chunk_cap) return NEP_E_INTERNAL;
+    if (loss && (!tg || !tg->energy || !tg->fx || !tg->fy || !tg->fz)) return NEP_E_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)s->n_atoms;
+    const int nc = c->built_cells;
+    k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of, c->cells,
+                                                       c->xq, c->status, nullptr);
+    k_pop_params<<<n_pop, 256, 0, st>>>(theta, c->params, c->pop_P, c->pop_c64);
+    const int tiles = (n + 255) / 256;
+    const int grid = xcd_grid((int)((int64_t)tiles * n_pop));
+    float *F = forces ? forces : c->pop_F;
+    double *E = energy ? energy : c->pop_E;
+    double *W = virial ? virial : c->pop_W;
+    k_pop_descriptor<<<grid, 256, 0, st>>>(c->pc, c->xq, c->pop_xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
+                                           c->ncnt, c->pop_P, c->pop_c64, c->pop_pg, c->pop_fown, c->pop_w,
+                                           c->pop_e, c->status, tiles, n_pop);
+    k_pop_force<<<grid, 256, 0, st>>>(c->pc, c->pop_xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->rev,
+                                      c->pop_pg, c->pop_fown, c->perm, F, c->pop_w, c->status, tiles, n_pop);
+    k_pop_reduce_chunks<<<dim3(c->n_chunks, n_pop), 256, 0, st>>>(n, c->n_chunks, c->chunk_begin, c->chunk_end,
+                                                                   c->pop_e, c->pop_w, c->pop_part, c->status);
+    k_pop_reduce_cells<<<dim3(nc, n_pop), 256, 0, st>>>(nc, c->n_chunks, c->cell_chunk, c->pop_part, E, W,
+                                                        c->status);
+    if (loss) {
+        const int nblk = std::min(POP_FBLK, grid_for(n, 256));
+        k_pop_force_err<<<dim3(nblk, n_pop), 256, 0, st>>>(n, F, tg->fx, tg->fy, tg->fz, c->pop_fpart);
+        k_pop_loss<<<n_pop, 256, 0, st>>>(nc, n, N_PARAMS, nblk, c->cell_start_d, E, W, tg->energy, tg->virial,
+                                          tg->has_virial, c->pop_fpart, theta, tg->lambda_e, tg->lambda_f,
+                                          tg->lambda_v, tg->lambda_1, tg->lambda_2, loss);
+    }
+    HIP_TRY(hipGetLastError());
+    return NEP_OK;
+}
+
+int nep_snes_sample(int32_t n_pop, int32_t n_params, const float *mu, const float *sigma, const float *draws,
+                    float *theta, void *stream)
+{
+    if (n_pop < 1 || n_params < 1 || !mu || !sigma || !draws || !theta) return NEP_E_ARG;
+    const int64_t total = (int64_t)n_pop * n_params;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    k_snes_sample<<<grid, 256, 0, (hipStream_t)stream>>>(n_pop, n_params, mu, sigma, draws, theta);
+    HIP_TRY(hipGetLastError());
+    return NEP_OK;
+}
+
+int nep_snes_update(int32_t n_pop, int32_t n_params, const double *loss, int32_t loss_stride, const float *draws,
+                    float *mu, float *sigma, double eta_mu, double eta_sigma, void *stream)
+{
+    if (n_pop < 2 || n_pop > NEP_MAX_POPULATION || n_params < 1 || loss_stride < 1 || !loss || !draws || !mu ||
+        !sigma)
+        return NEP_E_ARG;
+    if (!(eta_mu > 0)) eta_mu = 1.0;
+    if (!(eta_sigma > 0)) eta_sigma = (3.0 + std::log((double)n_params)) / (5.0 * std::sqrt((double)n_params));
+    k_snes_update<<<grid_for(n_params, 256), 256, 0, (hipStream_t)stream>>>(n_pop, n_params, loss, loss_stride,
+                                                                             draws, mu, sigma, eta_mu, eta_sigma);
+    HIP_TRY(hipGetLastError());
     return NEP_OK;
 }
 

@@ -28,6 +28,8 @@ constexpr int P_B0 = P_W0 + NH * DIM;    // [NH]
 constexpr int P_W1 = P_B0 + NH;          // [NH]
 constexpr int P_B1 = P_W1 + NH;          // [1]
 constexpr int P_SIZE = P_B1 + 1;
+// FP64 copy of the angular coefficients and their row sums
+constexpr int C64N = NA * KB + NA;
 
 // Per-atom record in sorted order, one 64-byte half cache line: the wrapped
 // FP64 position (written by the position refresh) and the radial adjoint

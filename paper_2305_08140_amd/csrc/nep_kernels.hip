@@ -1026,19 +1026,16 @@ __global__ __launch_bounds__(256) void k_grad_cell(const CellGeom *__restrict__ 
 
 // One block per chunk of atoms of a single cell: FP64 sums of the site
 // energies and the per-atom virials, written to part[chunk][10].
-__global__ __launch_bounds__(256) void k_reduce_chunks(const int32_t *__restrict__ chunk_begin,
-                                                       const int32_t *__restrict__ chunk_end,
-                                                       const double *__restrict__ e_atom,
-                                                       const float *__restrict__ w_atom,
-                                                       double *__restrict__ part,
-                                                       const int32_t *__restrict__ status)
+__device__ __forceinline__ void reduce_chunk(int k, const int32_t *__restrict__ chunk_begin,
+                                             const int32_t *__restrict__ chunk_end,
+                                             const double *__restrict__ e_atom, const float *__restrict__ w_atom,
+                                             double *__restrict__ part, bool ok)
 {
     __shared__ double sh[10][256];
-    const int k = blockIdx.x;
     double acc[10];
 #pragma unroll
     for (int q = 0; q < 10; ++q) acc[q] = 0.0;
-    if (status[ST_ERR] == 0) {
+    if (ok) {
         for (int t = chunk_begin[k] + threadIdx.x; t < chunk_end[k]; t += 256) {
             acc[0] += e_atom[t];
 #pragma unroll
@@ -1057,17 +1054,23 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(const int32_t *__restrict
     if (threadIdx.x < 10) part[(size_t)k * 10 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
+__global__ __launch_bounds__(256) void k_reduce_chunks(const int32_t *__restrict__ chunk_begin,
+                                                       const int32_t *__restrict__ chunk_end,
+                                                       const double *__restrict__ e_atom,
+                                                       const float *__restrict__ w_atom,
+                                                       double *__restrict__ part,
+                                                       const int32_t *__restrict__ status)
+{
+    reduce_chunk(blockIdx.x, chunk_begin, chunk_end, e_atom, w_atom, part, status[ST_ERR] == 0);
+}
+
 // One block per cell: sum of its chunk partials (fixed order: strided
 // partial sums per thread, then a fixed tree), deterministic.
-__global__ __launch_bounds__(256) void k_reduce_cells(int n_cells, const int32_t *__restrict__ cell_chunk,
-                                                      const double *__restrict__ part, double *__restrict__ energy,
-                                                      double *__restrict__ virial,
-                                                      const int32_t *__restrict__ status)
+__device__ __forceinline__ void reduce_cell(int c, const int32_t *__restrict__ cell_chunk,
+                                            const double *__restrict__ part, double *__restrict__ energy,
+                                            double *__restrict__ virial)
 {
     __shared__ double sh[10][256];
-    const int c = blockIdx.x;
-    if (c >= n_cells) return;
-    if (status[ST_ERR] != 0) return;
     double acc[10];
 #pragma unroll
     for (int q = 0; q < 10; ++q) acc[q] = 0.0;
@@ -1085,6 +1088,17 @@ __global__ __launch_bounds__(256) void k_reduce_cells(int n_cells, const int32_t
     }
     if (threadIdx.x == 0) energy[c] = sh[0][0];
     if (virial && threadIdx.x < 9) virial[(size_t)c * 9 + threadIdx.x] = sh[1 + threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_cells(int n_cells, const int32_t *__restrict__ cell_chunk,
+                                                      const double *__restrict__ part, double *__restrict__ energy,
+                                                      double *__restrict__ virial,
+                                                      const int32_t *__restrict__ status)
+{
+    const int c = blockIdx.x;
+    if (c >= n_cells) return;
+    if (status[ST_ERR] != 0) return;
+    reduce_cell(c, cell_chunk, part, energy, virial);
 }
 
 // Site energies to the caller's order (FP32 output).
@@ -1135,6 +1149,255 @@ __global__ __launch_bounds__(256) void k_count_inside(
     if ((threadIdx.x & 63) == 0) {
         atomicAdd(counts, nr);
         atomicAdd(counts + 1, na);
+    }
+}
+
+
+// ------------------------------------------------------------------ population (SNES)
+//
+// The paper trains its model by SNES with a population of 50 (Sec. III.A):
+// every generation evaluates energies, forces and virials of the whole
+// training set for each member.  Here one launch covers all members: work
+// item w (in XCD order over ntiles * n_pop) is member w % n_pop of atom tile
+// w / n_pop, so the members of one tile run side by side on one XCD and
+// share its L2 for positions and lists.  Member m reads its parameters at
+// P + m P_SIZE (C64 + m C64N) and owns records, pair gradients, own terms,
+// per-atom virials and energies at offset m (per-atom array size).
+
+// theta [n_pop][NPARAM] (c_rad, c_ang, w0, b0, w1, b1) -> parameter blocks
+// [n_pop][P_SIZE] with the descriptor scale q_scale of `base`, and the FP64
+// angular coefficients [n_pop][C64N].  One block per member.
+__global__ __launch_bounds__(256) void k_pop_params(const float *__restrict__ theta, const float *__restrict__ base,
+                                                    float *__restrict__ P, double *__restrict__ C64)
+{
+    const int m = blockIdx.x;
+    const float *th = theta + (size_t)m * NPARAM;
+    float *pm = P + (size_t)m * P_SIZE;
+    for (int i = threadIdx.x; i < P_SIZE; i += blockDim.x)
+        pm[i] = i < P_QS ? th[i] : (i < P_W0 ? base[i] : th[i - DIM]);
+    double *cm = C64 + (size_t)m * C64N;
+    const int i = threadIdx.x;
+    if (i < NA * KB) cm[i] = (double)th[P_CA + i];
+    if (i < NA) {
+        double s = 0.0;
+        for (int k = 0; k < KB; ++k) s += (double)th[P_CA + i * KB + k];
+        cm[NA * KB + i] = s;
+    }
+}
+
+__device__ inline bool pop_item(int ntiles, int n_pop, int &m, int &tile)
+{
+    const int w = xcd_block(ntiles * n_pop);
+    if (w >= ntiles * n_pop) return false;
+    m = w % n_pop;
+    tile = w / n_pop;
+    return true;
+}
+
+__global__ __launch_bounds__(256, 2) void k_pop_descriptor(
+    PairConsts pc, const double4 *__restrict__ xq, AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
+    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
+    const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
+    const float *__restrict__ P, const double *__restrict__ C64, float4 *__restrict__ pair_grad,
+    float4 *__restrict__ f_own, float *__restrict__ w_atom, double *__restrict__ e_atom,
+    int32_t *__restrict__ status, int ntiles, int n_pop)
+{
+    __shared__ NNLds lds[1];
+    if (status[ST_ERR] != 0) return;
+    int m, tile;
+    if (!pop_item(ntiles, n_pop, m, tile)) return;
+    const int t = tile * 256 + threadIdx.x;
+    if (t >= pc.n) return;
+    const size_t n = (size_t)pc.n;
+    descriptor_atom<0>(t, true, lds, pc, xq, xp + m * n, cell_of, cells, nl_ang, nl_rad, ncnt,
+                       P + (size_t)m * P_SIZE, C64 + (size_t)m * C64N, pair_grad + (size_t)m * pc.capA * n,
+                       f_own + m * n, w_atom + 9 * m * n, e_atom + m * n, status);
+}
+
+// forces of member m go to F + 3 m n (fx), + (3 m + 1) n (fy), + (3 m + 2) n (fz), caller order
+__global__ __launch_bounds__(256) void k_pop_force(
+    PairConsts pc, const AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
+    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
+    const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
+    const uint8_t *__restrict__ rev, const float4 *__restrict__ pair_grad, const float4 *__restrict__ f_own,
+    const int32_t *__restrict__ perm, float *__restrict__ F, float *__restrict__ w_atom,
+    int32_t *__restrict__ status, int ntiles, int n_pop)
+{
+    if (status[ST_ERR] != 0) return;
+    int m, tile;
+    if (!pop_item(ntiles, n_pop, m, tile)) return;
+    const int t = tile * 256 + threadIdx.x;
+    if (t >= pc.n) return;
+    const size_t n = (size_t)pc.n;
+    float *fm = F + 3 * m * n;
+    force_atom(t, pc, xp + m * n, cell_of, cells, nl_ang, nl_rad, ncnt, rev, pair_grad + (size_t)m * pc.capA * n,
+               f_own + m * n, perm, fm, fm + n, fm + 2 * n, w_atom + 9 * m * n, status);
+}
+
+// grid (n_chunks, n_pop): chunk partials of member blockIdx.y
+__global__ __launch_bounds__(256) void k_pop_reduce_chunks(int n, int n_chunks, const int32_t *__restrict__ chunk_begin,
+                                                           const int32_t *__restrict__ chunk_end,
+                                                           const double *__restrict__ e_atom,
+                                                           const float *__restrict__ w_atom,
+                                                           double *__restrict__ part,
+                                                           const int32_t *__restrict__ status)
+{
+    const size_t m = blockIdx.y;
+    reduce_chunk(blockIdx.x, chunk_begin, chunk_end, e_atom + m * n, w_atom + 9 * m * n,
+                 part + m * n_chunks * 10, status[ST_ERR] == 0);
+}
+
+// grid (n_cells, n_pop): energy [n_pop][n_cells], virial [n_pop][n_cells][9]
+__global__ __launch_bounds__(256) void k_pop_reduce_cells(int n_cells, int n_chunks,
+                                                          const int32_t *__restrict__ cell_chunk,
+                                                          const double *__restrict__ part,
+                                                          double *__restrict__ energy, double *__restrict__ virial,
+                                                          const int32_t *__restrict__ status)
+{
+    if (status[ST_ERR] != 0) return;
+    const size_t m = blockIdx.y;
+    reduce_cell(blockIdx.x, cell_chunk, part + m * n_chunks * 10, energy + m * n_cells,
+                virial + m * n_cells * 9);
+}
+
+// Fixed-order block sum of one double (blocks of 256); every thread returns it.
+__device__ inline double block_sum256(double v, double *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if ((int)threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// grid (nblk, n_pop): part[m][b] = sum over this block's atoms of |F - F_target|^2
+__global__ __launch_bounds__(256) void k_pop_force_err(int n, const float *__restrict__ F,
+                                                       const float *__restrict__ tfx, const float *__restrict__ tfy,
+                                                       const float *__restrict__ tfz, double *__restrict__ part)
+{
+    __shared__ double sh[256];
+    const size_t m = blockIdx.y;
+    const float *fm = F + 3 * m * n;
+    double acc = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const double dx = (double)fm[i] - tfx[i], dy = (double)fm[n + i] - tfy[i], dz = (double)fm[2 * n + i] - tfz[i];
+        acc += dx * dx + dy * dy + dz * dz;
+    }
+    const double s = block_sum256(acc, sh);
+    if (threadIdx.x == 0) part[m * gridDim.x + blockIdx.x] = s;
+}
+
+// One block per member: the loss terms (total, RMSE of the energy per atom,
+// of the force components, of the six virial components per atom over the
+// cells with a virial target, mean |theta|, RMS theta) into loss[m][6].
+__global__ __launch_bounds__(256) void k_pop_loss(int n_cells, int n_atoms, int n_params, int nblk,
+                                                  const int64_t *__restrict__ cell_start,
+                                                  const double *__restrict__ energy, const double *__restrict__ virial,
+                                                  const double *__restrict__ t_energy, const double *__restrict__ t_virial,
+                                                  const uint8_t *__restrict__ has_virial,
+                                                  const double *__restrict__ fpart, const float *__restrict__ theta,
+                                                  double le, double lf, double lv, double l1w, double l2w,
+                                                  double *__restrict__ loss)
+{
+    __shared__ double sh[256];
+    const size_t m = blockIdx.x;
+    double ae = 0.0, av = 0.0, nv = 0.0, af = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int c = threadIdx.x; c < n_cells; c += 256) {
+        const double na = (double)(cell_start[c + 1] - cell_start[c]);
+        const double de = (energy[m * n_cells + c] - t_energy[c]) / na;
+        ae += de * de;
+        if (t_virial && (!has_virial || has_virial[c])) {
+            nv += 1.0;
+            const double *w = virial + (m * n_cells + c) * 9;
+            const double *tw = t_virial + (size_t)c * 9;
+            const int comp[6] = {0, 4, 8, 1, 5, 6};   // xx yy zz xy yz zx
+            for (int q = 0; q < 6; ++q) {
+                const double d = (w[comp[q]] - tw[comp[q]]) / na;
+                av += d * d;
+            }
+        }
+    }
+    for (int k = threadIdx.x; k < nblk; k += 256) af += fpart[m * nblk + k];
+    const float *th = theta + m * n_params;
+    for (int p = threadIdx.x; p < n_params; p += 256) {
+        const double z = th[p];
+        a1 += fabs(z);
+        a2 += z * z;
+    }
+    ae = block_sum256(ae, sh);
+    av = block_sum256(av, sh);
+    nv = block_sum256(nv, sh);
+    af = block_sum256(af, sh);
+    a1 = block_sum256(a1, sh);
+    a2 = block_sum256(a2, sh);
+    if (threadIdx.x == 0) {
+        const double re = sqrt(ae / n_cells);
+        const double rf = sqrt(af / (3.0 * n_atoms));
+        const double rv = nv > 0.0 ? sqrt(av / (6.0 * nv)) : 0.0;
+        const double r1 = a1 / n_params;
+        const double r2 = sqrt(a2 / n_params);
+        double *o = loss + m * 6;
+        o[0] = le * re + lf * rf + lv * rv + l1w * r1 + l2w * r2;
+        o[1] = re;
+        o[2] = rf;
+        o[3] = rv;
+        o[4] = r1;
+        o[5] = r2;
+    }
+}
+
+// SNES: theta_k = mu + sigma * s_k (all [.][n_params], FP32).
+__global__ __launch_bounds__(256) void k_snes_sample(int n_pop, int n_params, const float *__restrict__ mu,
+                                                     const float *__restrict__ sigma, const float *__restrict__ s,
+                                                     float *__restrict__ theta)
+{
+    const size_t total = (size_t)n_pop * n_params;
+    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < total; q += (size_t)gridDim.x * 256) {
+        const int p = (int)(q % n_params);
+        theta[q] = fmaf(sigma[p], s[q], mu[p]);
+    }
+}
+
+// SNES update (Schaul et al. 2011).  Every block ranks the members by loss
+// (lower is better; NaN counts as worst; ties keep the member order), turns
+// ranks into utilities, then updates its share of the parameters:
+// mu += eta_mu sigma sum_k u_k s_k, sigma *= exp(eta_sigma / 2 sum_k u_k (s_k^2 - 1)),
+// sums in FP64 in member order.  n_pop <= 1024.
+__global__ __launch_bounds__(256) void k_snes_update(int n_pop, int n_params, const double *__restrict__ loss,
+                                                     int loss_stride, const float *__restrict__ s,
+                                                     float *__restrict__ mu, float *__restrict__ sigma,
+                                                     double eta_mu, double eta_sigma)
+{
+    __shared__ double u[1024];
+    const double lam = (double)n_pop;
+    double norm = 0.0;
+    for (int r = 1; r <= n_pop; ++r) norm += fmax(0.0, log(lam / 2.0 + 1.0) - log((double)r));
+    for (int k = threadIdx.x; k < n_pop; k += 256) {
+        double lk = loss[(size_t)k * loss_stride];
+        if (isnan(lk)) lk = INFINITY;
+        int rank = 0;
+        for (int j = 0; j < n_pop; ++j) {
+            double lj = loss[(size_t)j * loss_stride];
+            if (isnan(lj)) lj = INFINITY;
+            rank += (lj < lk) || (lj == lk && j < k);
+        }
+        u[k] = fmax(0.0, log(lam / 2.0 + 1.0) - log((double)(rank + 1))) / norm - 1.0 / lam;
+    }
+    __syncthreads();
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < n_params; p += gridDim.x * 256) {
+        double gm = 0.0, gs = 0.0;
+        for (int k = 0; k < n_pop; ++k) {
+            const double sk = s[(size_t)k * n_params + p];
+            gm += u[k] * sk;
+            gs += u[k] * (sk * sk - 1.0);
+        }
+        const double sg = sigma[p];
+        mu[p] = (float)((double)mu[p] + eta_mu * sg * gm);
+        sigma[p] = (float)(sg * exp(0.5 * eta_sigma * gs));
     }
 }
 

@@ -54,6 +54,11 @@ def test_argument_errors_without_device():
     assert not ptr.value
     assert L.nep_compute_efv(None, None, None, None) == nep.NEP_E_ARG
     assert L.nep_step_verlet(None, None, None, 1, None, None, None) == nep.NEP_E_ARG
+    assert L.nep_population_reserve(None, 4) == nep.NEP_E_ARG
+    assert L.nep_population_efv(None, None, 4, None, None, None, None, None, None, None) == nep.NEP_E_ARG
+    assert L.nep_snes_sample(0, 10, None, None, None, None, None) == nep.NEP_E_ARG
+    assert L.nep_snes_update(1, 10, None, 1, None, None, None, 0.0, 0.0, None) == nep.NEP_E_ARG
+    assert L.nep_snes_update(2000, 10, None, 1, None, None, None, 0.0, 0.0, None) == nep.NEP_E_ARG
     L.nep_destroy(None)
 
 
@@ -76,7 +81,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     pairs = {"nep_hparams": nep.Hparams, "nep_weights": nep.Weights, "nep_config": nep.Config,
              "nep_system": nep.System, "nep_efv": nep.Efv, "nep_md": nep.Md, "nep_md_stats": nep.MdStats,
-             "nep_bcc_ref": nep.BccRef, "nep_defects": nep.Defects}
+             "nep_bcc_ref": nep.BccRef, "nep_defects": nep.Defects, "nep_targets": nep.Targets}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "nep.h"', "int main(void) {"]
     for cname, py in pairs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
