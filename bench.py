@@ -101,6 +101,37 @@ def cpu_baseline(model, s, seconds_target=15.0):
                       f"{dt:.1f} s on {n_thr} threads"}
 
 
+def fp64_checks(checks):
+    """FP64 oracle references for the GPU results that the other sections
+    sampled (part of the CPU leg: the only place the bench runs the oracle).
+    A check is either sampled atoms of one cell (model, pos, h, pbc, idx, F,
+    optional site energies e and an atom to leave out) or a list of whole
+    cells (model, cells: [(pos, h, F)])."""
+    import oracle
+    res = {}
+    for name, c in checks.items():
+        if "cells" in c:
+            num = den = 0.0
+            for pos, h, F in c["cells"]:
+                r = oracle.efv_cell(c["model"], pos, h, virial=False)
+                num += float(np.sum((F - r["forces"]) ** 2))
+                den += float(np.sum(r["forces"] ** 2))
+            res[name] = {"force_rel_err": (num / den) ** 0.5}
+            continue
+        ref = oracle.efv_cell(c["model"], c["pos"], c["h"], c["pbc"], targets=c["idx"], virial=False)
+        F, Fr = c["F"], ref["forces"]
+        out = {"force_rel_err": float(np.linalg.norm(F - Fr) / np.linalg.norm(Fr))}
+        ex = c.get("exclude")
+        if ex is not None:
+            keep = c["idx"] != ex
+            out["force_rel_err_without_excluded"] = float(np.linalg.norm(F[keep] - Fr[keep]) /
+                                                          np.linalg.norm(Fr[keep]))
+        if c.get("e") is not None:
+            out["site_energy_max_abs_err"] = float(np.max(np.abs(c["e"] - ref["energy_atom"])))
+        res[name] = out
+    return res
+
+
 def summarize_rocprof(kt_dir, fetch_dir, write_dir, n_atoms, command, out_dir):
     """Write profiles/ summaries from rocprofv3 output: kernel-trace statistics
     and the HBM bytes per launch from FETCH_SIZE / WRITE_SIZE, scaled by what
@@ -190,7 +221,6 @@ def bench_paper_model(args, s, N):
     on one A100, quoted as context)."""
     import torch
     import nep_synth
-    import oracle
     import paper_2305_08140_amd as nep
     pm = nep_synth.random_model(size="paper")
     sysd = nep.DeviceSystem.from_synth(s)
@@ -204,17 +234,15 @@ def bench_paper_model(args, s, N):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kt = ctx.nep_time_efv(sysd, out, reps=3)
-    pos_now = sysd.positions().cpu().numpy()
-    F = out.forces().cpu().numpy().astype(np.float64)
     idx = np.sort(np.random.default_rng(0).choice(N, size=256, replace=False))
-    ref = oracle.efv_cell(pm, pos_now, s.h[0], targets=idx, virial=False)
-    err = float(np.linalg.norm(F[idx] - ref["forces"]) / np.linalg.norm(ref["forces"]))
+    check = {"model": pm, "pos": sysd.positions().cpu().numpy(), "h": s.h[0], "pbc": (1, 1, 1), "idx": idx,
+             "F": out.forces().cpu().numpy().astype(np.float64)[idx]}
     res = {"atom_steps_per_s": N * args.paper_steps / wall, "ms_per_step": wall / args.paper_steps * 1e3,
-           "steps": args.paper_steps, "kernels_ms": kt, "force_rel_err_vs_fp64_thermal_atoms": err,
+           "steps": args.paper_steps, "kernels_ms": kt, "force_rel_err_vs_fp64_thermal_atoms": None,
            "paper_a100_atom_steps_per_s": 1.3e7}
     del ctx, out, sysd
     torch.cuda.empty_cache()
-    return res
+    return res, check
 
 
 def bench_foil(args, model):
@@ -225,7 +253,6 @@ def bench_foil(args, model):
     the foil 4 cells below the top surface, adaptive step (0.01 A, <= 1 fs)."""
     import torch
     import nep_synth
-    import oracle
     import paper_2305_08140_amd as nep
     f = nep_synth.cascade((150, 150, 180), foil=True, pka_ev=200e3)
     N = f.n_atoms
@@ -240,19 +267,81 @@ def bench_foil(args, model):
     st = ctx.nep_step_verlet(sysd, args.foil_steps, out, forces_valid=True, thermostat=th, **md)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    pos_now = sysd.positions().cpu().numpy()
-    F = out.forces().cpu().numpy().astype(np.float64)
     pka = f.meta["pka"]
     idx = np.sort(np.random.default_rng(1).choice(N, size=256, replace=False))
-    ref = oracle.efv_cell(model, pos_now, f.h[0], f.pbc, targets=idx, virial=False)
-    err = float(np.linalg.norm(F[idx] - ref["forces"]) / np.linalg.norm(ref["forces"]))
+    check = {"model": model, "pos": sysd.positions().cpu().numpy(), "h": f.h[0], "pbc": f.pbc, "idx": idx,
+             "F": out.forces().cpu().numpy().astype(np.float64)[idx]}
     res = {"atom_steps_per_s": N * args.foil_steps / wall, "ms_per_step": wall / args.foil_steps * 1e3,
            "steps": args.foil_steps, "n_atoms": N, "n_border": st["n_border"],
            "border_temperature_K": st["border_temperature"], "dt_last_fs": st["dt_last"],
            "time_fs": st["time"], "n_rebuilds": st["n_rebuilds"],
            "pka_speed_A_per_fs": float(np.linalg.norm(sysd.velocities()[pka].cpu().numpy())),
-           "force_rel_err_vs_fp64_sampled": err}
+           "force_rel_err_vs_fp64_sampled": None}
     del ctx, out, sysd
+    torch.cuda.empty_cache()
+    return res, check
+
+
+def bench_snes(args, model, n_pop=50):
+    """SNES training generations (Sec. III.A: population 50, the paper's loss
+    weights) on the 4,096-cell batch standing in for the training set
+    (energies, forces and virials of every cell; targets from another random
+    model evaluated by the same library).  Timed: sampling, the population's
+    energies/forces/virials and loss terms, and the update, all on the device
+    (draws generated beforehand).  Compared with evaluating the members one at
+    a time (nep_set_weights + nep_compute_efv per member, no loss)."""
+    import torch
+    import nep_synth
+    import paper_2305_08140_amd as nep
+    s = nep_synth.batch()
+    N, C_ = s.n_atoms, s.n_cells
+    sysd = nep.DeviceSystem.from_synth(s)
+    teacher = nep_synth.random_model(seed=77)
+    ct = nep.Context(teacher, N, C_, check=False)
+    o = nep.EFV(N, C_)
+    ct.nep_build_neighbors(sysd)
+    ct.nep_compute_efv(sysd, o)
+    ct.nep_status()
+    targets = {"energy": o.energy.clone(), "forces": torch.stack([o.fx, o.fy, o.fz]).clone(),
+               "virial": o.virial.clone(), "has_virial": None}
+    del ct
+    ctx = nep.Context(model, N, C_, check=False)
+    ctx.nep_build_neighbors(sysd)
+    ctx.nep_population_reserve(n_pop)
+    n_par = ctx.nep_num_params()
+    mu = torch.tensor(model.param_vector().astype(np.float32), device="cuda")
+    sigma = torch.full_like(mu, 0.1)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    draws = torch.randn(args.snes_gens + 2, n_pop, n_par, device="cuda", generator=gen)
+    loss0 = nep.snes_generation(ctx, sysd, mu, sigma, draws[0], targets)[:, 0].min().item()
+    nep.snes_generation(ctx, sysd, mu, sigma, draws[1], targets)
+    ctx.nep_status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in range(args.snes_gens):
+        loss = nep.snes_generation(ctx, sysd, mu, sigma, draws[2 + g], targets)
+    torch.cuda.synchronize()
+    t_gen = (time.perf_counter() - t0) / args.snes_gens
+    ctx.nep_status()
+    best = loss[:, 0].min().item()
+    # members one at a time through the single-model path
+    thetas = nep.snes_sample(mu, sigma, draws[-1]).cpu().numpy().astype(np.float64)
+    single = nep.Context(model, N, C_, check=False)
+    single.nep_build_neighbors(sysd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n_pop):
+        single.nep_set_weights(model.with_param_vector(thetas[k]))
+        single.nep_compute_efv(sysd, o)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    res = {"n_pop": n_pop, "n_cells": C_, "n_atoms": N, "n_params": n_par, "generations": args.snes_gens,
+           "ms_per_generation": t_gen * 1e3, "member_cell_evaluations_per_s": n_pop * C_ / t_gen,
+           "member_atom_evaluations_per_s": n_pop * N / t_gen,
+           "one_member_at_a_time_ms": t_seq * 1e3, "speedup_vs_one_member_at_a_time": t_seq / t_gen,
+           "best_loss_first_generation": loss0, "best_loss_last_generation": best}
+    del ctx, single, sysd, o, targets, draws
     torch.cuda.empty_cache()
     return res
 
@@ -268,9 +357,8 @@ def bench_batches(model, reps=20, n_percell=128):
     with its own context, lists prebuilt, launches back to back, one sync)."""
     import torch
     import nep_synth
-    import oracle
     import paper_2305_08140_amd as nep
-    out = {}
+    out, checks = {}, {}
     rng = np.random.default_rng(0)
     for name in ("batch", "diffbatch"):
         s = nep_synth.WORKLOADS[name]()
@@ -299,15 +387,14 @@ def bench_batches(model, reps=20, n_percell=128):
             res["graph_cells_per_s"] = C_ / t_g
             res["graph_ms"] = t_g * 1e3
         ctx.nep_status()
-        # force error of sampled cells against FP64
+        # sampled cells for the FP64 check of the CPU leg
         F = o.forces().cpu().numpy().astype(np.float64)
-        num = den = 0.0
+        cells = []
         for c in rng.choice(C_, size=16, replace=False):
             a, b = int(s.cell_start[c]), int(s.cell_start[c + 1])
-            r = oracle.efv_cell(model, s.pos[a:b], s.h[c], virial=False)
-            num += float(np.sum((F[a:b] - r["forces"]) ** 2))
-            den += float(np.sum(r["forces"] ** 2))
-        res["force_rel_err_vs_fp64"] = (num / den) ** 0.5
+            cells.append((s.pos[a:b].copy(), s.h[c].copy(), F[a:b].copy()))
+        checks["batch_" + name] = {"model": model, "cells": cells}
+        res["force_rel_err_vs_fp64"] = None
         # per-cell path on a sample of cells
         picks = rng.choice(C_, size=min(n_percell, C_), replace=False)
         per = []
@@ -331,7 +418,7 @@ def bench_batches(model, reps=20, n_percell=128):
         out[name] = res
         del per, ctx, sysd, o
         torch.cuda.empty_cache()
-    return out
+    return out, checks
 
 
 def main():
@@ -346,6 +433,8 @@ def main():
                     help="MD steps of the paper-size model on the same workload (0 skips it)")
     ap.add_argument("--foil-steps", type=int, default=50,
                     help="MD steps of the 8,100,000-atom foil cascade with the border thermostat (0 skips it)")
+    ap.add_argument("--snes-gens", type=int, default=10,
+                    help="timed SNES generations (population 50) on the 4,096-cell batch (0 skips it)")
     ap.add_argument("--timing-reps", type=int, default=5)
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ summaries from rocprofv3 output directories and exit")
@@ -356,13 +445,13 @@ def main():
         n = 2 * args.cells ** 3
         kt_dir, fetch_dir, write_dir = args.summarize_rocprof
         cmd = {"kt": "rocprofv3 --kernel-trace --stats -d %s -o kt --output-format csv -- "
-                     "python3 bench.py --steps 20 --warmup 3 --no-cpu-baseline --no-batches --foil-steps 0" % kt_dir,
+                     "python3 bench.py --steps 20 --warmup 3 --no-cpu-baseline --no-batches --foil-steps 0 --snes-gens 0" % kt_dir,
                "fetch": "rocprofv3 --pmc FETCH_SIZE -d %s -o f --output-format csv -- "
                         "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batches --foil-steps 0 "
-                        "--copy-calibration-mib 1024 --timing-reps 1" % fetch_dir,
+                        "--snes-gens 0 --copy-calibration-mib 1024 --timing-reps 1" % fetch_dir,
                "write": "rocprofv3 --pmc WRITE_SIZE -d %s -o w --output-format csv -- "
                         "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batches --foil-steps 0 "
-                        "--copy-calibration-mib 1024 --timing-reps 1" % write_dir}
+                        "--snes-gens 0 --copy-calibration-mib 1024 --timing-reps 1" % write_dir}
         summarize_rocprof(*args.summarize_rocprof, n, cmd, os.path.join(ROOT, "profiles"))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -415,20 +504,16 @@ def main():
     achieved = f_dom * N / (ktimes[dom] * 1e-3) / 1e12
     traffic = _traffic("k_" + dom, N)
 
-    # force error against FP64 on a sample of atoms of the final configuration
-    import oracle
-    pos_now = sysd.positions().cpu().numpy()
-    F_gpu = out.forces().cpu().numpy().astype(np.float64)
+    # sampled atoms of the final configuration (and the PKA) for the FP64
+    # check of the CPU leg; the PKA's force would dominate the norm, so the
+    # thermal atoms are also checked on their own
     rng = np.random.default_rng(0)
     idx = np.sort(rng.choice(N, size=256, replace=False))
     pka = s.meta["pka"]
     idx = np.unique(np.concatenate([idx, [pka]]))
-    ref = oracle.efv_cell(model, pos_now, s.h[0], targets=idx, virial=False)
-    ferr = float(np.linalg.norm(F_gpu[idx] - ref["forces"]) / np.linalg.norm(ref["forces"]))
-    # the PKA's force dominates that norm: the sampled thermal atoms on their own
-    th = idx != pka
-    ferr_th = float(np.linalg.norm(F_gpu[idx[th]] - ref["forces"][th]) / np.linalg.norm(ref["forces"][th]))
-    eerr = float(np.max(np.abs(out.energy_atom.cpu().numpy()[idx].astype(np.float64) - ref["energy_atom"])))
+    checks = {"bulk": {"model": model, "pos": sysd.positions().cpu().numpy(), "h": s.h[0], "pbc": (1, 1, 1),
+                       "idx": idx, "F": out.forces().cpu().numpy().astype(np.float64)[idx],
+                       "e": out.energy_atom.cpu().numpy()[idx].astype(np.float64), "exclude": pka}}
 
     # Wigner-Seitz defect analysis of the final configuration (HBM-bound:
     # positions read, one occupancy update per atom, occupancy cleared and scanned)
@@ -449,16 +534,34 @@ def main():
 
     del ctx, sysd, out
     torch.cuda.empty_cache()
-    paper = bench_paper_model(args, s, N) if args.paper_steps > 0 else None
-    foil = bench_foil(args, model) if args.foil_steps > 0 else None
-
-    batches = None
+    paper = foil = batches = snes = None
+    if args.paper_steps > 0:
+        paper, checks["paper_model"] = bench_paper_model(args, s, N)
+    if args.foil_steps > 0:
+        foil, checks["foil"] = bench_foil(args, model)
+    if args.snes_gens > 0:
+        snes = bench_snes(args, model)
     if not args.no_batches:
-        batches = bench_batches(model)
+        batches, bc = bench_batches(model)
+        checks.update(bc)
 
+    # CPU leg: the oracle's own throughput, and the FP64 references of the
+    # sampled GPU results
     cpu = None
+    ferr = ferr_th = eerr = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(model, s)
+        acc = fp64_checks(checks)
+        ferr = acc["bulk"]["force_rel_err"]
+        ferr_th = acc["bulk"]["force_rel_err_without_excluded"]
+        eerr = acc["bulk"]["site_energy_max_abs_err"]
+        if paper is not None:
+            paper["force_rel_err_vs_fp64_thermal_atoms"] = acc["paper_model"]["force_rel_err"]
+        if foil is not None:
+            foil["force_rel_err_vs_fp64_sampled"] = acc["foil"]["force_rel_err"]
+        if batches is not None:
+            for name in batches:
+                batches[name]["force_rel_err_vs_fp64"] = acc["batch_" + name]["force_rel_err"]
 
     line = {
         "metric": "atom-steps/s NEP-ZBL E+F+virial (plain vs batched/differentiable), force err vs FP64",
@@ -482,6 +585,7 @@ def main():
         "defects": defects,
         "paper_model": paper,
         "foil_cascade": foil,
+        "snes": snes,
         "batches": batches,
     }
     print(json.dumps(line), flush=True)
