@@ -299,41 +299,127 @@ __host__ __device__ inline void sph_degree_d(double x, double y, double z, doubl
 __host__ __device__ inline void sph_grad_contract(float x, float y, float z, const float Dc[NLM],
                                          float &vx, float &vy, float &vz)
 {
+    // the gradients of the 24 polynomials share a few monomials; each term is
+    // (constant x Dc[lm]) times one of them
+    const float a3 = 0.25f * NEP_S10, b3 = NEP_S15, c3 = 0.25f * NEP_S6, e3 = 0.5f * NEP_S15;
+    const float a4 = 0.5f * NEP_S35, b4 = 0.25f * NEP_S70, c4 = 0.5f * NEP_S5, d4 = 0.25f * NEP_S10;
+    const float e4 = 0.25f * NEP_S5, f4 = 0.125f * NEP_S35;
     const float x2 = x * x, y2 = y * y, z2 = z * z;
-    float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-    // l = 1
-    gy += Dc[0]; gz += Dc[1]; gx += Dc[2];
+    const float xy = x * y, xz = x * z, yz = y * z, xyz = xy * z;
+    const float dxy = x2 - y2;
+    const float t5 = fmaf(5.0f, z2, -1.0f), t7 = fmaf(7.0f, z2, -1.0f), t73 = fmaf(7.0f, z2, -3.0f);
+    const float yt7 = y * t7, xt7 = x * t7, zt73 = z * t73, zdxy = z * dxy;
+    const float p1 = y * fmaf(3.0f, x2, -y2);   // y (3x^2 - y^2)
+    const float p2 = x * fmaf(-3.0f, y2, x2);   // x (x^2 - 3y^2)
+    float gx = Dc[2], gy = Dc[0], gz = Dc[1];
     // l = 2
-    gx += NEP_S3 * (Dc[3] * y + Dc[6] * z + Dc[7] * x);
-    gy += NEP_S3 * (Dc[3] * x + Dc[4] * z - Dc[7] * y);
-    gz += NEP_S3 * (Dc[4] * y + Dc[6] * x) + 3.0f * Dc[5] * z;
+    gx = fmaf(NEP_S3 * Dc[3], y, gx); gx = fmaf(NEP_S3 * Dc[6], z, gx); gx = fmaf(NEP_S3 * Dc[7], x, gx);
+    gy = fmaf(NEP_S3 * Dc[3], x, gy); gy = fmaf(NEP_S3 * Dc[4], z, gy); gy = fmaf(-NEP_S3 * Dc[7], y, gy);
+    gz = fmaf(NEP_S3 * Dc[4], y, gz); gz = fmaf(NEP_S3 * Dc[6], x, gz); gz = fmaf(3.0f * Dc[5], z, gz);
     // l = 3
-    {
-        const float a = 0.25f * NEP_S10, b = NEP_S15, c = 0.25f * NEP_S6, e = 0.5f * NEP_S15;
-        const float t5 = 5.0f * z2 - 1.0f;
-        gx += a * Dc[8] * 6.0f * x * y + b * Dc[9] * y * z + c * Dc[12] * t5
-              + e * Dc[13] * 2.0f * x * z + a * Dc[14] * 3.0f * (x2 - y2);
-        gy += a * Dc[8] * 3.0f * (x2 - y2) + b * Dc[9] * x * z + c * Dc[10] * t5
-              - e * Dc[13] * 2.0f * y * z - a * Dc[14] * 6.0f * x * y;
-        gz += b * Dc[9] * x * y + c * Dc[10] * 10.0f * y * z + Dc[11] * (7.5f * z2 - 1.5f)
-              + c * Dc[12] * 10.0f * x * z + e * Dc[13] * (x2 - y2);
-    }
+    gx = fmaf(6.0f * a3 * Dc[8], xy, gx);  gy = fmaf(3.0f * a3 * Dc[8], dxy, gy);
+    gx = fmaf(b3 * Dc[9], yz, gx);         gy = fmaf(b3 * Dc[9], xz, gy);          gz = fmaf(b3 * Dc[9], xy, gz);
+    gy = fmaf(c3 * Dc[10], t5, gy);        gz = fmaf(10.0f * c3 * Dc[10], yz, gz);
+    gz = fmaf(1.5f * Dc[11], t5, gz);
+    gx = fmaf(c3 * Dc[12], t5, gx);        gz = fmaf(10.0f * c3 * Dc[12], xz, gz);
+    gx = fmaf(2.0f * e3 * Dc[13], xz, gx); gy = fmaf(-2.0f * e3 * Dc[13], yz, gy); gz = fmaf(e3 * Dc[13], dxy, gz);
+    gx = fmaf(3.0f * a3 * Dc[14], dxy, gx); gy = fmaf(-6.0f * a3 * Dc[14], xy, gy);
     // l = 4
+    gx = fmaf(a4 * Dc[15], p1, gx);        gy = fmaf(a4 * Dc[15], p2, gy);
+    gx = fmaf(6.0f * b4 * Dc[16], xyz, gx); gy = fmaf(3.0f * b4 * Dc[16], zdxy, gy); gz = fmaf(b4 * Dc[16], p1, gz);
+    gx = fmaf(c4 * Dc[17], yt7, gx);       gy = fmaf(c4 * Dc[17], xt7, gy);        gz = fmaf(14.0f * c4 * Dc[17], xyz, gz);
+    gy = fmaf(d4 * Dc[18], zt73, gy);      gz = fmaf(3.0f * d4 * Dc[18], yt7, gz);
+    gz = fmaf(2.5f * Dc[19], zt73, gz);
+    gx = fmaf(d4 * Dc[20], zt73, gx);      gz = fmaf(3.0f * d4 * Dc[20], xt7, gz);
+    gx = fmaf(2.0f * e4 * Dc[21], xt7, gx); gy = fmaf(-2.0f * e4 * Dc[21], yt7, gy); gz = fmaf(14.0f * e4 * Dc[21], zdxy, gz);
+    gx = fmaf(3.0f * b4 * Dc[22], zdxy, gx); gy = fmaf(-6.0f * b4 * Dc[22], xyz, gy); gz = fmaf(b4 * Dc[22], p2, gz);
+    gx = fmaf(4.0f * f4 * Dc[23], p2, gx);  gy = fmaf(-4.0f * f4 * Dc[23], p1, gy);
+    vx = gx; vy = gy; vz = gz;
+}
+
+// The same harmonics without their normalisation: Y_lm = sph_norm(lm) y_lm
+// with y_lm polynomials of small integer coefficients.  A caller that folds
+// the constants into its coefficients (D'_lm = sph_norm(lm) D_lm) evaluates
+// sum_lm D_lm Y_lm as sum_lm D'_lm y_lm and its gradient with fewer products.
+__host__ __device__ constexpr float sph_norm(int lm)
+{
+    return lm < 3 ? 1.0f
+         : lm == 3 || lm == 4 || lm == 6 ? NEP_S3
+         : lm == 5 ? 0.5f
+         : lm == 7 ? 0.5f * NEP_S3
+         : lm == 8 || lm == 14 ? 0.25f * NEP_S10
+         : lm == 9 ? NEP_S15
+         : lm == 10 || lm == 12 ? 0.25f * NEP_S6
+         : lm == 11 ? 0.5f
+         : lm == 13 ? 0.5f * NEP_S15
+         : lm == 15 ? 0.5f * NEP_S35
+         : lm == 16 || lm == 22 ? 0.25f * NEP_S70
+         : lm == 17 ? 0.5f * NEP_S5
+         : lm == 18 || lm == 20 ? 0.25f * NEP_S10
+         : lm == 19 ? 0.125f
+         : lm == 21 ? 0.25f * NEP_S5
+         : 0.125f * NEP_S35;
+}
+
+// Monomials shared by the unnormalised harmonics and their gradients.
+struct SphMono {
+    float x, y, z, xy, xz, yz, xyz, dxy, t5, t7, t73, p1, p2;
+    __host__ __device__ SphMono(float x_, float y_, float z_) : x(x_), y(y_), z(z_)
     {
-        const float a = 0.5f * NEP_S35, b = 0.25f * NEP_S70, c = 0.5f * NEP_S5, d = 0.25f * NEP_S10;
-        const float e = 0.25f * NEP_S5, f = 0.125f * NEP_S35;
-        const float t7 = 7.0f * z2 - 1.0f, t73 = 7.0f * z2 - 3.0f;
-        gx += a * Dc[15] * (3.0f * x2 * y - y2 * y) + b * Dc[16] * 6.0f * x * y * z
-              + c * Dc[17] * y * t7 + d * Dc[20] * z * t73 + e * Dc[21] * 2.0f * x * t7
-              + b * Dc[22] * 3.0f * z * (x2 - y2) + f * Dc[23] * (4.0f * x2 * x - 12.0f * x * y2);
-        gy += a * Dc[15] * (x2 * x - 3.0f * x * y2) + b * Dc[16] * 3.0f * z * (x2 - y2)
-              + c * Dc[17] * x * t7 + d * Dc[18] * z * t73 - e * Dc[21] * 2.0f * y * t7
-              - b * Dc[22] * 6.0f * x * y * z + f * Dc[23] * (4.0f * y2 * y - 12.0f * x2 * y);
-        gz += b * Dc[16] * y * (3.0f * x2 - y2) + c * Dc[17] * 14.0f * x * y * z
-              + d * Dc[18] * y * (21.0f * z2 - 3.0f) + Dc[19] * (17.5f * z2 * z - 7.5f * z)
-              + d * Dc[20] * x * (21.0f * z2 - 3.0f) + e * Dc[21] * 14.0f * z * (x2 - y2)
-              + b * Dc[22] * x * (x2 - 3.0f * y2);
+        const float x2 = x * x, y2 = y * y, z2 = z * z;
+        xy = x * y; xz = x * z; yz = y * z; xyz = xy * z;
+        dxy = x2 - y2;
+        t5 = fmaf(5.0f, z2, -1.0f); t7 = fmaf(7.0f, z2, -1.0f); t73 = fmaf(7.0f, z2, -3.0f);
+        p1 = y * fmaf(3.0f, x2, -y2);    // 3x^2 y - y^3
+        p2 = x * fmaf(-3.0f, y2, x2);    // x^3 - 3x y^2
     }
+};
+
+__host__ __device__ inline void sph_unnorm(const SphMono &m, float y[NLM])
+{
+    y[0] = m.y; y[1] = m.z; y[2] = m.x;
+    y[3] = m.xy; y[4] = m.yz; y[5] = fmaf(3.0f, m.z * m.z, -1.0f); y[6] = m.xz; y[7] = m.dxy;
+    y[8] = m.p1; y[9] = m.xyz; y[10] = m.y * m.t5; y[11] = m.z * (m.t5 - 2.0f); y[12] = m.x * m.t5;
+    y[13] = m.z * m.dxy; y[14] = m.p2;
+    const float z2 = m.z * m.z;
+    y[15] = m.xy * m.dxy; y[16] = m.z * m.p1; y[17] = m.xy * m.t7; y[18] = m.yz * m.t73;
+    y[19] = fmaf(35.0f * z2, z2, fmaf(-30.0f, z2, 3.0f)); y[20] = m.xz * m.t73; y[21] = m.dxy * m.t7;
+    y[22] = m.z * m.p2; y[23] = fmaf(-4.0f * m.xy, m.xy, m.dxy * m.dxy);
+}
+
+// v = sum_lm Dc[lm] grad y_lm (x, y, z independent; the caller projects out
+// the radial part).
+__host__ __device__ inline void sph_unnorm_grad_contract(const SphMono &m, const float Dc[NLM], float &vx,
+                                                         float &vy, float &vz)
+{
+    const float yt7 = m.y * m.t7, xt7 = m.x * m.t7, zt73 = m.z * m.t73, zdxy = m.z * m.dxy;
+    float gx = Dc[2], gy = Dc[0], gz = Dc[1];
+    // l = 2
+    gx = fmaf(Dc[3], m.y, gx); gy = fmaf(Dc[3], m.x, gy);
+    gy = fmaf(Dc[4], m.z, gy); gz = fmaf(Dc[4], m.y, gz);
+    gz = fmaf(Dc[5], 6.0f * m.z, gz);
+    gx = fmaf(Dc[6], m.z, gx); gz = fmaf(Dc[6], m.x, gz);
+    gx = fmaf(Dc[7], 2.0f * m.x, gx); gy = fmaf(Dc[7], -2.0f * m.y, gy);
+    // l = 3
+    const float xy6 = 6.0f * m.xy, dxy3 = 3.0f * m.dxy;
+    gx = fmaf(Dc[8], xy6, gx); gy = fmaf(Dc[8], dxy3, gy);
+    gx = fmaf(Dc[9], m.yz, gx); gy = fmaf(Dc[9], m.xz, gy); gz = fmaf(Dc[9], m.xy, gz);
+    gy = fmaf(Dc[10], m.t5, gy); gz = fmaf(Dc[10], 10.0f * m.yz, gz);
+    gz = fmaf(Dc[11], 3.0f * m.t5, gz);
+    gx = fmaf(Dc[12], m.t5, gx); gz = fmaf(Dc[12], 10.0f * m.xz, gz);
+    gx = fmaf(Dc[13], 2.0f * m.xz, gx); gy = fmaf(Dc[13], -2.0f * m.yz, gy); gz = fmaf(Dc[13], m.dxy, gz);
+    gx = fmaf(Dc[14], dxy3, gx); gy = fmaf(Dc[14], -xy6, gy);
+    // l = 4
+    const float xyz6 = 6.0f * m.xyz, zdxy3 = 3.0f * zdxy;
+    gx = fmaf(Dc[15], m.p1, gx); gy = fmaf(Dc[15], m.p2, gy);
+    gx = fmaf(Dc[16], xyz6, gx); gy = fmaf(Dc[16], zdxy3, gy); gz = fmaf(Dc[16], m.p1, gz);
+    gx = fmaf(Dc[17], yt7, gx); gy = fmaf(Dc[17], xt7, gy); gz = fmaf(Dc[17], 14.0f * m.xyz, gz);
+    gy = fmaf(Dc[18], zt73, gy); gz = fmaf(Dc[18], 3.0f * yt7, gz);
+    gz = fmaf(Dc[19], 20.0f * zt73, gz);
+    gx = fmaf(Dc[20], zt73, gx); gz = fmaf(Dc[20], 3.0f * xt7, gz);
+    gx = fmaf(Dc[21], 2.0f * xt7, gx); gy = fmaf(Dc[21], -2.0f * yt7, gy); gz = fmaf(Dc[21], 14.0f * zdxy, gz);
+    gx = fmaf(Dc[22], zdxy3, gx); gy = fmaf(Dc[22], -xyz6, gy); gz = fmaf(Dc[22], m.p2, gz);
+    gx = fmaf(Dc[23], 4.0f * m.p2, gx); gy = fmaf(Dc[23], -4.0f * m.p1, gy);
     vx = gx; vy = gy; vz = gz;
 }
 

@@ -35,6 +35,18 @@ void nep_test_sph_grad(float x, float y, float z, const float *Dc, float *v)
     sph_grad_contract(x, y, z, Dc, v[0], v[1], v[2]);
 }
 
+void nep_test_sph_unnorm(float x, float y, float z, float *Y) { sph_unnorm(SphMono(x, y, z), Y); }
+
+void nep_test_sph_norm(float *K)
+{
+    for (int lm = 0; lm < NLM; ++lm) K[lm] = sph_norm(lm);
+}
+
+void nep_test_sph_unnorm_grad(float x, float y, float z, const float *Dc, float *v)
+{
+    sph_unnorm_grad_contract(SphMono(x, y, z), Dc, v[0], v[1], v[2]);
+}
+
 void nep_test_zbl(double r, double Z, double r1, double r2, double *U, double *dU) { zbl_pair(r, Z, r1, r2, *U, *dU); }
 
 void nep_test_decode(int32_t e, int jbits, int ibits, int ioff, int *out)

@@ -469,13 +469,15 @@ __device__ __forceinline__ void descriptor_atom(
     }
     rec.pad = 0.0f;
     xp[t] = rec;
-    // angular adjoint B_{n,lm} = 2 (dU/dq_nl) s_{n,lm}, in place of S
+    // angular adjoint B_{n,lm} = 2 (dU/dq_nl) s_{n,lm}, in place of S, times
+    // the harmonic's normalisation (the walk below uses the unnormalised
+    // polynomials y_lm = Y_lm / sph_norm(lm))
 #pragma unroll
     for (int n = 0; n < NA; ++n)
 #pragma unroll
         for (int lm = 0; lm < NLM; ++lm) {
             const int l = lm < 3 ? 1 : (lm < 8 ? 2 : (lm < 15 ? 3 : 4));
-            S[n][lm] *= 2.0f * Fp[NR + NA * (l - 1) + n];
+            S[n][lm] *= (2.0f * sph_norm(lm)) * Fp[NR + NA * (l - 1) + n];
         }
 
     // angular pair gradients dU_i/dr_ij = grad_r [sum_{n,lm} B_{n,lm} g_n(|r|) Y_lm(r/|r|)]
@@ -508,6 +510,7 @@ __device__ __forceinline__ void descriptor_atom(
         float T[KB], dT[KB];
         cheb_d(fmaf(2.0f * tt, tt, -1.0f), T, dT);
         float g[NA], gp[NA];
+        const float hfc = 0.5f * fc, hdx = hfc * dxdr, hdfc = 0.5f * dfc;
 #pragma unroll
         for (int n = 0; n < NA; ++n) {
             float sn = csA[n], sp = 0.0f;
@@ -516,12 +519,13 @@ __device__ __forceinline__ void descriptor_atom(
                 sn = fmaf(P[P_CA + n * KB + k], T[k], sn);
                 sp = fmaf(P[P_CA + n * KB + k], dT[k], sp);
             }
-            g[n] = 0.5f * fc * sn;
-            gp[n] = 0.5f * fmaf(dxdr * fc, sp, dfc * sn);
+            g[n] = hfc * sn;
+            gp[n] = fmaf(hdx, sp, hdfc * sn);
         }
         const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+        const SphMono mono(ux, uy, uz);
         float Y[NLM];
-        sph(ux, uy, uz, Y);
+        sph_unnorm(mono, Y);
         float Dc[NLM];
         float s1 = 0.0f;
 #pragma unroll
@@ -536,7 +540,7 @@ __device__ __forceinline__ void descriptor_atom(
             s1 = fmaf(Dp, Y[lm], s1);
         }
         float vx, vy, vz;
-        sph_grad_contract(ux, uy, uz, Dc, vx, vy, vz);
+        sph_unnorm_grad_contract(mono, Dc, vx, vy, vz);
         const float uv = ux * vx + uy * vy + uz * vz;
         const float gx = fmaf(s1, ux, (vx - uv * ux) * rinv);
         const float gy = fmaf(s1, uy, (vy - uv * uy) * rinv);

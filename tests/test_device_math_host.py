@@ -28,6 +28,9 @@ def L():
     lib.nep_test_sph.argtypes = [F, F, F, FP]
     lib.nep_test_sph_d.argtypes = [C.c_double, C.c_double, C.c_double, DP]
     lib.nep_test_sph_grad.argtypes = [F, F, F, FP, FP]
+    lib.nep_test_sph_unnorm.argtypes = [F, F, F, FP]
+    lib.nep_test_sph_norm.argtypes = [FP]
+    lib.nep_test_sph_unnorm_grad.argtypes = [F, F, F, FP, FP]
     lib.nep_test_zbl.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, DP, DP]
     lib.nep_test_decode.argtypes = [C.c_int32, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
     return lib
@@ -154,6 +157,34 @@ def test_harmonic_gradient_contraction_fd(L):
             L.nep_test_sph(*(u - e).astype(np.float32), _fp(Y)); ym = float(D.astype(np.float64) @ Y)
             fd[a] = (yp - ym) / (2 * h)
         assert np.allclose(v, fd, rtol=2e-3, atol=2e-3)
+
+
+def test_unnormalised_harmonics(L):
+    # y_lm times its constant is the normalised harmonic (on and off the unit
+    # sphere: both are the same polynomials); the contraction of the
+    # unnormalised gradients matches finite differences
+    rng = np.random.default_rng(3)
+    K = _f32(24)
+    L.nep_test_sph_norm(_fp(K))
+    Y, y, v = _f32(24), _f32(24), _f32(3)
+    for _ in range(50):
+        u = rng.normal(size=3)
+        u = (u / np.linalg.norm(u)).astype(np.float32)
+        L.nep_test_sph(*u, _fp(Y))
+        L.nep_test_sph_unnorm(*u, _fp(y))
+        assert np.allclose(K.astype(np.float64) * y, Y, rtol=0, atol=5e-6)
+    for _ in range(20):
+        D = rng.normal(size=24).astype(np.float32)
+        u = rng.normal(size=3) * 0.6
+        L.nep_test_sph_unnorm_grad(*u.astype(np.float32), _fp(D), _fp(v))
+        h = 1e-3
+        fd = np.zeros(3)
+        for a in range(3):
+            e = np.zeros(3); e[a] = h
+            L.nep_test_sph_unnorm(*(u + e).astype(np.float32), _fp(y)); yp = float(D.astype(np.float64) @ y)
+            L.nep_test_sph_unnorm(*(u - e).astype(np.float32), _fp(y)); ym = float(D.astype(np.float64) @ y)
+            fd[a] = (yp - ym) / (2 * h)
+        assert np.allclose(v, fd, rtol=2e-3, atol=5e-3)
 
 
 def test_zbl_pair_matches_oracle(L):
