@@ -277,7 +277,8 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
     const double4 pi = xq[t];
     const int base = cg->atom_start;
     const uint32_t jmask = (1u << pc.jbits) - 1u;
-    // B_{c,lm} = 2 (dU/dq_cl) s_{c,lm}
+    // B_{c,lm} = 2 (dU/dq_cl) s_{c,lm}, times the harmonic's normalisation
+    // (the walk uses the unnormalised polynomials y_lm = Y_lm / sph_norm(lm))
     float B[NC][NLM];
     float csA[NC];
 #pragma unroll
@@ -289,7 +290,8 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
 #pragma unroll
         for (int lm = 0; lm < NLM; ++lm) {
             const int l = lm < 3 ? 1 : (lm < 8 ? 2 : (lm < 15 ? 3 : 4));
-            B[c][lm] = 2.0f * FpA[(WA * (l - 1) + c0 + c) * n + t] * S[((size_t)(c0 + c) * NLM + lm) * n + t];
+            B[c][lm] = (2.0f * sph_norm(lm)) * FpA[(WA * (l - 1) + c0 + c) * n + t] *
+                       S[((size_t)(c0 + c) * NLM + lm) * n + t];
         }
     }
     const bool first = c0 == 0;
@@ -338,14 +340,16 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
             Tm2 = Tm1; Tm1 = Tk; dTm2 = dTm1; dTm1 = dTk;
         }
         float g[NC], gp[NC];
+        const float hfc = 0.5f * fc, hdx = hfc * dxdr, hdfc = 0.5f * dfc;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            g[c] = 0.5f * fc * (float)sn[c];
-            gp[c] = 0.5f * fmaf(dxdr * fc, (float)sp[c], dfc * (float)sn[c]);
+            g[c] = hfc * (float)sn[c];
+            gp[c] = fmaf(hdx, (float)sp[c], hdfc * (float)sn[c]);
         }
         const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+        const SphMono mono(ux, uy, uz);
         float Y[NLM];
-        sph(ux, uy, uz, Y);
+        sph_unnorm(mono, Y);
         float Dc[NLM];
         float s1 = 0.0f;
 #pragma unroll
@@ -360,7 +364,7 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
             s1 = fmaf(Dp, Y[lm], s1);
         }
         float vx, vy, vz;
-        sph_grad_contract(ux, uy, uz, Dc, vx, vy, vz);
+        sph_unnorm_grad_contract(mono, Dc, vx, vy, vz);
         const float uv = ux * vx + uy * vy + uz * vz;
         const float gx = fmaf(s1, ux, (vx - uv * ux) * rinv);
         const float gy = fmaf(s1, uy, (vy - uv * uy) * rinv);
