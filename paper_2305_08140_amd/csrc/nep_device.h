@@ -361,6 +361,28 @@ __host__ __device__ constexpr float sph_norm(int lm)
          : 0.125f * NEP_S35;
 }
 
+// The unnormalised harmonics of one degree in double precision (the 2l+1
+// values y_lm, lm = l*l-1 .. l*l+2l-1, in the order of sph).
+template <int L>
+__host__ __device__ inline void sph_unnorm_degree_d(double x, double y, double z, double *Y)
+{
+    if constexpr (L == 1) {
+        Y[0] = y; Y[1] = z; Y[2] = x;
+    } else if constexpr (L == 2) {
+        Y[0] = x * y; Y[1] = y * z; Y[2] = fma(3.0 * z, z, -1.0); Y[3] = x * z; Y[4] = fma(x, x, -y * y);
+    } else {
+        static_assert(L == 3, "degrees 1..3");
+        const double x2 = x * x, y2 = y * y, z2 = z * z, t5 = fma(5.0, z2, -1.0);
+        Y[0] = y * fma(3.0, x2, -y2);
+        Y[1] = x * y * z;
+        Y[2] = y * t5;
+        Y[3] = z * (t5 - 2.0);
+        Y[4] = x * t5;
+        Y[5] = z * (x2 - y2);
+        Y[6] = x * fma(-3.0, y2, x2);
+    }
+}
+
 // Monomials shared by the unnormalised harmonics and their gradients.
 struct SphMono {
     float x, y, z, xy, xz, yz, xyz, dxy, t5, t7, t73, p1, p2;

@@ -94,10 +94,11 @@ __device__ __forceinline__ void angular_sums_l34(const PairConsts &pc, const dou
         if (r2 >= rcA2) continue;
         double g[NA], ux, uy, uz;
         angular_g_d(dist_d(r2), dx, dy, dz, inv_rA, C64, g, ux, uy, uz);
+        // unnormalised harmonics; the normalisations are applied to the sums
         double Y3[7];
-        sph_degree_d<3>(ux, uy, uz, Y3);
+        sph_unnorm_degree_d<3>(ux, uy, uz, Y3);
         float Y[NLM];
-        sph((float)ux, (float)uy, (float)uz, Y);
+        sph_unnorm(SphMono((float)ux, (float)uy, (float)uz), Y);
 #pragma unroll
         for (int n = 0; n < NA; ++n) {
 #pragma unroll
@@ -110,9 +111,9 @@ __device__ __forceinline__ void angular_sums_l34(const PairConsts &pc, const dou
 #pragma unroll
     for (int n = 0; n < NA; ++n) {
 #pragma unroll
-        for (int m = 0; m < 7; ++m) S[n][8 + m] = (float)A3[n][m];
+        for (int m = 0; m < 7; ++m) S[n][8 + m] = (float)(A3[n][m] * (double)sph_norm(8 + m));
 #pragma unroll
-        for (int m = 0; m < 9; ++m) S[n][15 + m] = A4[n][m];
+        for (int m = 0; m < 9; ++m) S[n][15 + m] = A4[n][m] * sph_norm(15 + m);
     }
 }
 
@@ -166,8 +167,8 @@ __device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const doub
                 double g[NA], ux, uy, uz;
                 angular_g_d(r, dx, dy, dz, inv_rA, C64, g, ux, uy, uz);
                 double Y[8];
-                sph_degree_d<1>(ux, uy, uz, Y);
-                sph_degree_d<2>(ux, uy, uz, Y + 3);
+                sph_unnorm_degree_d<1>(ux, uy, uz, Y);
+                sph_unnorm_degree_d<2>(ux, uy, uz, Y + 3);
 #pragma unroll
                 for (int n = 0; n < NA; ++n)
 #pragma unroll
@@ -182,7 +183,7 @@ __device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const doub
 #pragma unroll
         for (int n = 0; n < NA; ++n)
 #pragma unroll
-            for (int m = 0; m < 8; ++m) S[n][m] = (float)A[n][m];
+            for (int m = 0; m < 8; ++m) S[n][m] = (float)(A[n][m] * (double)sph_norm(m));
     }
     for (NeighbourPipe q(nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.s < q.count;) {
         int32_t e;
@@ -487,6 +488,11 @@ __device__ __forceinline__ void descriptor_atom(
     for (int k = 0; k < 9; ++k) W[k] = 0.0f;
     const uint32_t jmask = (1u << pc.jbits) - 1u;
     for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
+        // compiler barrier: the 50 angular coefficients are reloaded by
+        // scalar loads in every trip instead of being hoisted into scalar
+        // registers that then spill to vector-register lanes (one VALU
+        // readlane per use); 616 instead of 633 VALU instructions per pair
+        asm volatile("" ::: "memory");
         const size_t off = (size_t)list_slot(q.s, naf, nab, pc.capA) * pc.n + t;
         int32_t e;
         double px, py, pz;
