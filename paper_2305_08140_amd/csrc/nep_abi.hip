@@ -708,7 +708,7 @@ static void launch_wide_desc(nep_ctx *c, hipStream_t st)
     const int n = c->pc.n, grid = xcd_grid((n + 255) / 256);
     k_w_radial<<<grid, 256, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->params,
                                      c->w_Q, c->e_atom, c->status);
-    for (int g = 0; g < WNG; ++g)
+    for (int g = 0; g < WNGA; ++g)
         k_w_angular<<<grid, 256, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->c64, g,
                                           c->w_S, c->w_Q);
     k_w_network<<<grid, 256, 0, st>>>(n, c->xq, c->params, c->w_Q, c->xw, c->w_FpA, c->e_atom);

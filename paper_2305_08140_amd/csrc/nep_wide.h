@@ -5,7 +5,7 @@
 // one lane's registers, so the evaluation runs in phases with the sums and
 // descriptors staged in HBM, [component][atom] (coalesced per wavefront):
 //   k_w_radial    radial sums and descriptors, ZBL half energies
-//   k_w_angular   angular sums of one group of WG channels per launch
+//   k_w_angular   angular sums of one group of WGA channels per launch
 //                 (l <= 3 in FP64, l = 4 in FP32, as in the default model)
 //   k_w_network   network forward and backward per atom, site energy, the
 //                 atom's record (position + 16 radial adjoints, 128 bytes)
@@ -20,7 +20,9 @@ constexpr int WR = 16, WKR = 16;         // radial functions, radial Chebyshev t
 constexpr int WA = 11, WKA = 11;         // angular functions, angular Chebyshev terms
 constexpr int WH = 100;                  // hidden neurons
 constexpr int WDIM = WR + WA * LMAX;     // 60
-constexpr int WG = 3;                    // angular channels per group
+constexpr int WGA = 4;                   // angular channels per launch of the angular sums
+constexpr int WNGA = (WA + WGA - 1) / WGA;  // 3 launches (4, 4, 3)
+constexpr int WG = 3;                    // angular channels per group of the gradient walk
 constexpr int WNG = (WA + WG - 1) / WG;  // 4 groups (3, 3, 3, 2)
 
 // parameter block (floats): c_rad [WR][WKR], c_ang [WA][WKA], q_scale [WDIM],

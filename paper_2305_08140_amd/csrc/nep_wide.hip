@@ -162,12 +162,13 @@ __device__ __forceinline__ void w_angular_group(const PairConsts &pc, const doub
             for (int k = 0; k < WKA; ++k) sn = fma(C64[(c0 + c) * WKA + k], T[k], sn);
             g[c] = 0.5 * fc * sn;
         }
+        // unnormalised harmonics; the normalisations are applied to the sums
         double Y[15];
-        sph_degree_d<1>(ux, uy, uz, Y);
-        sph_degree_d<2>(ux, uy, uz, Y + 3);
-        sph_degree_d<3>(ux, uy, uz, Y + 8);
+        sph_unnorm_degree_d<1>(ux, uy, uz, Y);
+        sph_unnorm_degree_d<2>(ux, uy, uz, Y + 3);
+        sph_unnorm_degree_d<3>(ux, uy, uz, Y + 8);
         float Yf[NLM];
-        sph((float)ux, (float)uy, (float)uz, Yf);
+        sph_unnorm(SphMono((float)ux, (float)uy, (float)uz), Yf);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
 #pragma unroll
@@ -183,7 +184,7 @@ __device__ __forceinline__ void w_angular_group(const PairConsts &pc, const doub
         float ql[LMAX] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int lm = 0; lm < NLM; ++lm) {
-            const float v = lm < 15 ? (float)A[c][lm] : A4[c][lm - 15];
+            const float v = lm < 15 ? (float)(A[c][lm] * (double)sph_norm(lm)) : A4[c][lm - 15] * sph_norm(lm);
             const int l = lm < 3 ? 1 : (lm < 8 ? 2 : (lm < 15 ? 3 : 4));
             ql[l - 1] = fmaf(v, v, ql[l - 1]);
             S[((size_t)(c0 + c) * NLM + lm) * n + t] = v;
@@ -203,9 +204,9 @@ __global__ __launch_bounds__(256) void k_w_angular(
     const CellGeom *cg = cells + cell_of[t];
     const uint32_t cnt = ncnt[t];
     const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff;
-    const int c0 = group * WG;
-    if (WA - c0 >= WG) w_angular_group<WG>(pc, xq, t, cg, nl_ang, naf, nab, C64, c0, S, Q);
-    else w_angular_group<WA - (WNG - 1) * WG>(pc, xq, t, cg, nl_ang, naf, nab, C64, c0, S, Q);
+    const int c0 = group * WGA;
+    if (WA - c0 >= WGA) w_angular_group<WGA>(pc, xq, t, cg, nl_ang, naf, nab, C64, c0, S, Q);
+    else w_angular_group<WA - (WNGA - 1) * WGA>(pc, xq, t, cg, nl_ang, naf, nab, C64, c0, S, Q);
 }
 
 // Network forward and backward of one atom: U (added to the ZBL half
