@@ -245,6 +245,49 @@ def bench_paper_model(args, s, N):
     return res, check
 
 
+def bench_nve(args, model):
+    """NVE of the 128,000-atom cell (40^3 bcc W cells, Maxwell-Boltzmann
+    300 K on lattice sites): args.nve_steps velocity-Verlet steps of 1 fs in
+    chunks of 50; the total energy after every chunk gives its drift (slope of
+    a linear fit, eV/atom/ps) and its largest excursion."""
+    import torch
+    import nep_synth
+    import paper_2305_08140_amd as nep
+    ev_per_u = 1.602176634e-19 / 1.66053906660e-27 * 1e-10   # (eV/u) -> (A/fs)^2, CODATA 2018
+    s = nep_synth.mid()
+    N = s.n_atoms
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(model, N, 1, max_neigh_ang=48, max_neigh_rad=96, skin=1.0, check=False)
+    out = nep.EFV(N, 1)
+    chunk = 50
+    n_chunks = max(1, args.nve_steps // chunk)
+    etot = []
+
+    def total_energy():
+        v = sysd.velocities().double()
+        return out.energy.item() + 0.5 * s.mass * float((v * v).sum()) / ev_per_u
+
+    ctx.nep_step_verlet(sysd, 0, out, dt_max=1.0)
+    torch.cuda.synchronize()
+    etot.append(total_energy())
+    wall = 0.0
+    for k in range(n_chunks):
+        t0 = time.perf_counter()
+        ctx.nep_step_verlet(sysd, chunk, out, dt_max=1.0, forces_valid=True)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        etot.append(total_energy())
+    ctx.nep_status()
+    e = np.array(etot) / N
+    t_ps = np.arange(len(e)) * chunk * 1e-3
+    slope = float(np.polyfit(t_ps, e, 1)[0])
+    res = {"n_atoms": N, "steps": n_chunks * chunk, "dt_fs": 1.0, "atom_steps_per_s": N * n_chunks * chunk / wall,
+           "drift_eV_per_atom_per_ps": slope, "max_abs_excursion_eV_per_atom": float(np.max(np.abs(e - e[0])))}
+    del ctx, out, sysd
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_foil(args, model):
     """The paper's production cascade set-up (Sec. II.B, Table I foil row):
     a 150 x 150 x 180-cell W foil (8,100,000 atoms), open along z, 300 K, the
@@ -388,13 +431,29 @@ def bench_batches(model, reps=20, n_percell=128):
             res["graph_ms"] = t_g * 1e3
         ctx.nep_status()
         # sampled cells for the FP64 check of the CPU leg
-        F = o.forces().cpu().numpy().astype(np.float64)
-        cells = []
-        for c in rng.choice(C_, size=16, replace=False):
-            a, b = int(s.cell_start[c]), int(s.cell_start[c + 1])
-            cells.append((s.pos[a:b].copy(), s.h[c].copy(), F[a:b].copy()))
-        checks["batch_" + name] = {"model": model, "cells": cells}
+        picks16 = rng.choice(C_, size=16, replace=False)
+
+        def sampled_cells():
+            F = o.forces().cpu().numpy().astype(np.float64)
+            cells = []
+            for c in picks16:
+                a, b = int(s.cell_start[c]), int(s.cell_start[c + 1])
+                cells.append((s.pos[a:b].copy(), s.h[c].copy(), F[a:b].copy()))
+            return cells
+        ctx.nep_compute_efv(sysd, o)
+        checks["batch_" + name] = {"model": model, "cells": sampled_cells()}
         res["force_rel_err_vs_fp64"] = None
+        if not diff:
+            # hidden layer on the matrix cores: BF16 (mode 1) and FP32 (mode 2)
+            res["precision_variants"] = {}
+            for mode, label in ((1, "bf16_mfma"), (2, "fp32_mfma")):
+                ctx.nep_set_precision(mode)
+                t_m = _timed(lambda: ctx.nep_compute_efv(sysd, o), reps, torch)
+                ctx.nep_status()
+                checks[f"batch_{name}_{label}"] = {"model": model, "cells": sampled_cells()}
+                res["precision_variants"][label] = {"cells_per_s": C_ / t_m, "ms": t_m * 1e3,
+                                                    "force_rel_err_vs_fp64": None}
+            ctx.nep_set_precision(0)
         # per-cell path on a sample of cells
         picks = rng.choice(C_, size=min(n_percell, C_), replace=False)
         per = []
@@ -433,6 +492,8 @@ def main():
                     help="MD steps of the paper-size model on the same workload (0 skips it)")
     ap.add_argument("--foil-steps", type=int, default=50,
                     help="MD steps of the 8,100,000-atom foil cascade with the border thermostat (0 skips it)")
+    ap.add_argument("--nve-steps", type=int, default=1000,
+                    help="NVE steps of 1 fs on the 128,000-atom cell for the energy drift (0 skips it)")
     ap.add_argument("--snes-gens", type=int, default=10,
                     help="timed SNES generations (population 50) on the 4,096-cell batch (0 skips it)")
     ap.add_argument("--timing-reps", type=int, default=5)
@@ -445,13 +506,13 @@ def main():
         n = 2 * args.cells ** 3
         kt_dir, fetch_dir, write_dir = args.summarize_rocprof
         cmd = {"kt": "rocprofv3 --kernel-trace --stats -d %s -o kt --output-format csv -- "
-                     "python3 bench.py --steps 20 --warmup 3 --no-cpu-baseline --no-batches --foil-steps 0 --snes-gens 0" % kt_dir,
+                     "python3 bench.py --steps 20 --warmup 3 --no-cpu-baseline --no-batches --foil-steps 0 --snes-gens 0 --nve-steps 0" % kt_dir,
                "fetch": "rocprofv3 --pmc FETCH_SIZE -d %s -o f --output-format csv -- "
                         "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batches --foil-steps 0 "
-                        "--snes-gens 0 --copy-calibration-mib 1024 --timing-reps 1" % fetch_dir,
+                        "--snes-gens 0 --nve-steps 0 --copy-calibration-mib 1024 --timing-reps 1" % fetch_dir,
                "write": "rocprofv3 --pmc WRITE_SIZE -d %s -o w --output-format csv -- "
                         "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batches --foil-steps 0 "
-                        "--snes-gens 0 --copy-calibration-mib 1024 --timing-reps 1" % write_dir}
+                        "--snes-gens 0 --nve-steps 0 --copy-calibration-mib 1024 --timing-reps 1" % write_dir}
         summarize_rocprof(*args.summarize_rocprof, n, cmd, os.path.join(ROOT, "profiles"))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -534,7 +595,9 @@ def main():
 
     del ctx, sysd, out
     torch.cuda.empty_cache()
-    paper = foil = batches = snes = None
+    paper = foil = batches = snes = nve = None
+    if args.nve_steps > 0:
+        nve = bench_nve(args, model)
     if args.paper_steps > 0:
         paper, checks["paper_model"] = bench_paper_model(args, s, N)
     if args.foil_steps > 0:
@@ -562,6 +625,8 @@ def main():
         if batches is not None:
             for name in batches:
                 batches[name]["force_rel_err_vs_fp64"] = acc["batch_" + name]["force_rel_err"]
+                for label, v in batches[name].get("precision_variants", {}).items():
+                    v["force_rel_err_vs_fp64"] = acc[f"batch_{name}_{label}"]["force_rel_err"]
 
     line = {
         "metric": "atom-steps/s NEP-ZBL E+F+virial (plain vs batched/differentiable), force err vs FP64",
@@ -585,6 +650,7 @@ def main():
         "defects": defects,
         "paper_model": paper,
         "foil_cascade": foil,
+        "nve_128000": nve,
         "snes": snes,
         "batches": batches,
     }

@@ -199,6 +199,33 @@ def test_verlet_trajectory_thermal():
     assert abs(out.energy.item() - log[-1]["epot"]) / s.n_atoms <= E_ATOM_TOL
 
 
+def test_verlet_trajectory_128000_atoms():
+    # the 128,000-atom cell (40^3 bcc cells, 300 K): 10 steps of 1 fs against
+    # the oracle's trajectory (about a minute of oracle time on the host)
+    import torch
+    import paper_2305_08140_amd as nep
+    m = model()
+    s = nep_synth.mid()
+    assert s.n_atoms == 128000
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(m, s.n_atoms, 1)
+    out = nep.EFV(s.n_atoms, 1)
+    ctx.nep_step_verlet(sysd, 10, out, dt_max=1.0)
+    torch.cuda.synchronize()
+    print("[128000] GPU done, oracle trajectory next", flush=True)
+    pos_ref, vel_ref, F_ref, log = oracle.velocity_verlet(m, s.pos, s.vel, s.h[0], s.mass, 10, dt_max=1.0,
+                                                          record=True)
+    dp = np.abs(sysd.positions().cpu().numpy() - pos_ref).max()
+    dv = np.abs(sysd.velocities().cpu().numpy() - vel_ref).max()
+    e_all, _ = force_errors(out.forces().cpu().numpy().astype(np.float64), F_ref)
+    de = abs(out.energy.item() - log[-1]["epot"]) / s.n_atoms
+    print(f"[128000] max |dx| {dp:.2e}, max |dv| {dv:.2e}, force rel err {e_all:.2e}, energy err {de:.2e}",
+          flush=True)
+    assert dp < 1e-7 and dv < 1e-8
+    assert e_all <= F_REL_TOL
+    assert de <= E_ATOM_TOL
+
+
 def test_near_lattice_forces():
     # 16,000-atom bcc W displaced by only 0.004 A from the lattice sites: the
     # forces (~0.05 eV/A) are small differences of large pair terms, the
