@@ -30,6 +30,8 @@ constexpr int P_B1 = P_W1 + NH;          // [1]
 constexpr int P_SIZE = P_B1 + 1;
 // FP64 copy of the angular coefficients and their row sums
 constexpr int C64N = NA * KB + NA;
+// threads per block of the population descriptor kernel
+constexpr int POP_DESC_BS = 64;
 
 // Per-atom record in sorted order, one 64-byte half cache line: the wrapped
 // FP64 position (written by the position refresh) and the radial adjoint

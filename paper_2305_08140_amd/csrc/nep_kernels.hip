@@ -1204,7 +1204,9 @@ __device__ inline bool pop_item(int ntiles, int n_pop, int &m, int &tile)
     return true;
 }
 
-__global__ __launch_bounds__(256, 2) void k_pop_descriptor(
+// POP_DESC_BS threads per block: 64-thread tiles, as for the single-model
+// default (a block retires with its slowest wave)
+__global__ __launch_bounds__(POP_DESC_BS, 2) void k_pop_descriptor(
     PairConsts pc, const double4 *__restrict__ xq, AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
@@ -1216,7 +1218,7 @@ __global__ __launch_bounds__(256, 2) void k_pop_descriptor(
     if (status[ST_ERR] != 0) return;
     int m, tile;
     if (!pop_item(ntiles, n_pop, m, tile)) return;
-    const int t = tile * 256 + threadIdx.x;
+    const int t = tile * POP_DESC_BS + threadIdx.x;
     if (t >= pc.n) return;
     const size_t n = (size_t)pc.n;
     descriptor_atom<0>(t, true, lds, pc, xq, xp + m * n, cell_of, cells, nl_ang, nl_rad, ncnt,
