@@ -712,21 +712,21 @@ extern "C" {
 // The paper-size model's descriptor phases and force kernel (nep_wide.h).
 static void launch_wide_desc(nep_ctx *c, hipStream_t st)
 {
-    const int n = c->pc.n, grid = xcd_grid((n + 255) / 256);
-    k_w_radial<<<grid, 256, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->params,
+    const int n = c->pc.n, grid = xcd_grid((n + WBS - 1) / WBS);
+    k_w_radial<<<grid, WBS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->params,
                                      c->w_Q, c->e_atom, c->status);
     for (int g = 0; g < WNGA; ++g)
-        k_w_angular<<<grid, 256, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->c64, g,
+        k_w_angular<<<grid, WBS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->c64, g,
                                           c->w_S, c->w_Q);
-    k_w_network<<<grid, 256, 0, st>>>(n, c->xq, c->params, c->w_Q, c->xw, c->w_FpA, c->e_atom);
-    k_w_grad<<<grid, 256, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->params, c->c64, c->w_S,
+    k_w_network<<<grid, WBS, 0, st>>>(n, c->xq, c->params, c->w_Q, c->xw, c->w_FpA, c->e_atom);
+    k_w_grad<<<grid, WBS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->params, c->c64, c->w_S,
                                    c->w_FpA, c->pair_grad, c->f_own, c->w_atom);
 }
 
 static void launch_wide_force(nep_ctx *c, const nep_efv *o, hipStream_t st)
 {
-    const int n = c->pc.n, grid = xcd_grid((n + 255) / 256);
-    k_w_force<<<grid, 256, 0, st>>>(c->pc, c->xw, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->rev,
+    const int n = c->pc.n, grid = xcd_grid((n + WBS_F - 1) / WBS_F);
+    k_w_force<<<grid, WBS_F, 0, st>>>(c->pc, c->xw, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->rev,
                                     c->pair_grad, c->f_own, c->perm, o->fx, o->fy, o->fz, c->w_atom, c->status);
 }
 

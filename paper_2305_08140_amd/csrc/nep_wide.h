@@ -22,6 +22,10 @@ constexpr int WH = 100;                  // hidden neurons
 constexpr int WDIM = WR + WA * LMAX;     // 60
 constexpr int WGA = 4;                   // angular channels per launch of the angular sums
 constexpr int WNGA = (WA + WGA - 1) / WGA;  // 3 launches (4, 4, 3)
+// threads per block (one atom per lane): the descriptor phases in 64-thread
+// blocks (a block retires with its slowest wave; 24.7 -> 24.3 ms at 8,192,000
+// atoms), the force kernel in 256-thread blocks (11.2 -> 10.7 ms)
+constexpr int WBS = 64, WBS_F = 256;
 constexpr int WG = 3;                    // angular channels per group of the gradient walk
 constexpr int WNG = (WA + WG - 1) / WG;  // 4 groups (3, 3, 3, 2)
 

@@ -2,7 +2,7 @@
 // arithmetic follows the default model's kernels (nep_kernels.hip) term by
 // term: FP64 pair geometry, Chebyshev basis, radial sums and l <= 3 angular
 // sums; FP32 l = 4 sums, network, gradient walk and force kernel.  One lane
-// per atom, 256-thread blocks in XCD-aware order.
+// per atom, blocks in XCD-aware order.
 #include "nep_wide.h"
 #include "nep_pairs.h"
 
@@ -40,11 +40,12 @@ __device__ inline void cheb_w(float x, float T[K], float dT[K])
     }
 }
 
+template <int BS = WBS>
 __device__ inline int tile_atom(int n)
 {
-    const int ntiles = (n + 255) / 256;
+    const int ntiles = (n + BS - 1) / BS;
     const int tile = xcd_block(ntiles);
-    return tile < ntiles ? tile * 256 + (int)threadIdx.x : n;
+    return tile < ntiles ? tile * BS + (int)threadIdx.x : n;
 }
 
 __global__ void k_w_params64(const float *__restrict__ P, double *__restrict__ C64)
@@ -60,7 +61,7 @@ __global__ void k_w_params64(const float *__restrict__ P, double *__restrict__ C
 
 // Radial sums F_k = sum_j f_k(r_ij) over both lists (FP64), descriptors
 // q_n = sum_k c_nk F_k -> Q[n][t]; ZBL half energies -> e_atom[t].
-__global__ __launch_bounds__(256) void k_w_radial(
+__global__ __launch_bounds__(WBS) void k_w_radial(
     PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const int32_t *__restrict__ nl_rad,
     const uint32_t *__restrict__ ncnt, const float *__restrict__ P, float *__restrict__ Q,
@@ -194,7 +195,7 @@ __device__ __forceinline__ void w_angular_group(const PairConsts &pc, const doub
     }
 }
 
-__global__ __launch_bounds__(256) void k_w_angular(
+__global__ __launch_bounds__(WBS) void k_w_angular(
     PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const uint32_t *__restrict__ ncnt,
     const double *__restrict__ C64, int group, float *__restrict__ S, float *__restrict__ Q)
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(256) void k_w_angular(
 // Network forward and backward of one atom: U (added to the ZBL half
 // energies in e_atom), dU/dq; the radial adjoints a_k = sum_n dU/dq_n c_nk
 // go into the atom's record, the angular dU/dq into FpA[(nu - WR)][t].
-__global__ __launch_bounds__(256) void k_w_network(int n_atoms, const double4 *__restrict__ xq,
+__global__ __launch_bounds__(WBS) void k_w_network(int n_atoms, const double4 *__restrict__ xq,
                                                    const float *__restrict__ P, const float *__restrict__ Q,
                                                    WAtomRec *__restrict__ xw, float *__restrict__ FpA,
                                                    double *__restrict__ e_atom)
@@ -385,7 +386,7 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
     }
 }
 
-__global__ __launch_bounds__(256, 2) void k_w_grad(
+__global__ __launch_bounds__(WBS, 2) void k_w_grad(
     PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const uint32_t *__restrict__ ncnt,
     const float *__restrict__ P, const double *__restrict__ C64, const float *__restrict__ S,
@@ -415,14 +416,14 @@ __global__ __launch_bounds__(256, 2) void k_w_grad(
 }
 
 // Forces: the default model's force kernel with 16 radial adjoints.
-__global__ __launch_bounds__(256) void k_w_force(
+__global__ __launch_bounds__(WBS_F) void k_w_force(
     PairConsts pc, const WAtomRec *__restrict__ xw, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const int32_t *__restrict__ nl_rad,
     const uint32_t *__restrict__ ncnt, const uint8_t *__restrict__ rev, const float4 *__restrict__ pair_grad,
     const float4 *__restrict__ f_own, const int32_t *__restrict__ perm, float *__restrict__ fx,
     float *__restrict__ fy, float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status)
 {
-    const int t = tile_atom(pc.n);
+    const int t = tile_atom<WBS_F>(pc.n);
     if (t >= pc.n || status[ST_ERR] != 0) return;
     const double xi = xw[t].x, yi = xw[t].y, zi = xw[t].z;
     const CellGeom *cg = cells + cell_of[t];
