@@ -60,6 +60,10 @@ struct PairConsts {
     int capA, capR;                   // list capacities
     int jbits, ibits, ioff;           // neighbour entry encoding
     int n;                            // atoms (list stride)
+    // [word][atom]: bit s of word s/32 is set when the s-th entry of the
+    // radial list was inside rc_rad at the last descriptor evaluation (the
+    // force kernel walks only those entries)
+    uint32_t *rmask;
 };
 
 // Reference lattice of the Wigner-Seitz analysis (perfect bcc, cubic

@@ -185,13 +185,16 @@ __device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const doub
 #pragma unroll
             for (int m = 0; m < 8; ++m) S[n][m] = (float)(A[n][m] * (double)sph_norm(m));
     }
+    MaskWriter mw;
     for (NeighbourPipe q(nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.s < q.count;) {
+        const int s = q.s;
         int32_t e;
         double px, py, pz;
         q.pop(nl_rad, xq, base, jmask, e, px, py, pz);
         double dx, dy, dz;
         pair_vector_p(e, pc, px, py, pz, xi, yi, zi, cg, dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
+        mw.add(pc.rmask, pc.n, t, s, q.count, r2 < rcR2);
         if (r2 >= rcR2) continue;
         double fc, T[KB];
         basis_d(dist_d(r2), inv_rR, fc, T);
@@ -705,24 +708,29 @@ __device__ __forceinline__ void force_atom(
         const float4 gj = pair_grad[(size_t)sj * pc.n + j];
         Fx -= gj.x; Fy -= gj.y; Fz -= gj.z;
     }
-    // radial list: entries two ahead, the neighbour's record one ahead
-    const int nRl = nrf + nrb;
-    ListWalk wr(t, pc.n, nrf, nrb, pc.capR);
+    // radial list: only the entries the descriptor kernel found inside
+    // rc_rad (the skin entries are not loaded); entries two ahead, the
+    // neighbour's record one ahead
+    const size_t nsz = (size_t)pc.n;
+    auto rad_off = [&](int s) { return (size_t)list_slot(s, nrf, nrb, pc.capR) * nsz + t; };
+    MaskWalk mr(pc.rmask, pc.n, t, nrf + nrb);
+    int s_cur = mr.next();
     e_nx = 0;
-    if (nRl > 0) {
-        e_cur = nl_rad[wr.off];
+    if (s_cur >= 0) {
+        e_cur = nl_rad[rad_off(s_cur)];
         r_cur = xp[(int)((uint32_t)e_cur & jmask) + base];
     }
-    wr.next();
-    if (wr.s < nRl) e_nx = nl_rad[wr.off];
-    for (int s = 0; s < nRl; ++s) {
+    int s_nx = mr.next();
+    if (s_nx >= 0) e_nx = nl_rad[rad_off(s_nx)];
+    while (s_cur >= 0) {
         const int32_t e = e_cur;
         const AtomRec rj = r_cur;
-        if (s + 1 < nRl) {
+        s_cur = s_nx;
+        if (s_cur >= 0) {
             e_cur = e_nx;
             r_cur = xp[(int)((uint32_t)e_cur & jmask) + base];
-            wr.next();
-            if (wr.s < nRl) e_nx = nl_rad[wr.off];
+            s_nx = mr.next();
+            if (s_nx >= 0) e_nx = nl_rad[rad_off(s_nx)];
         }
         float r2;
         radial(e, rj, r2);

@@ -117,6 +117,44 @@ struct NeighbourPipe {
     }
 };
 
+// Inside-cutoff bits of a list walked in order: bit s of word s/32 for entry
+// s, each word stored once to mask[word * n + t] when complete.
+struct MaskWriter {
+    uint32_t word = 0;
+    __device__ void add(uint32_t *__restrict__ mask, size_t n, int t, int s, int count, bool inside)
+    {
+        word |= (uint32_t)inside << (s & 31);
+        if ((s & 31) == 31 || s + 1 == count) {
+            mask[(size_t)(s >> 5) * n + t] = word;
+            word = 0;
+        }
+    }
+};
+
+// The set bits of those words in order: next() returns the next entry index
+// inside the cutoff, or -1.
+struct MaskWalk {
+    const uint32_t *__restrict__ mask;
+    size_t n;
+    int t, nw, w;
+    uint32_t bits;
+    __device__ MaskWalk(const uint32_t *__restrict__ m, int n_, int t_, int count)
+        : mask(m), n((size_t)n_), t(t_), nw((count + 31) >> 5), w(0), bits(0)
+    {
+        if (nw > 0) bits = mask[(size_t)t];
+    }
+    __device__ int next()
+    {
+        while (bits == 0) {
+            if (++w >= nw) return -1;
+            bits = mask[(size_t)w * n + t];
+        }
+        const int b = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        return (w << 5) + b;
+    }
+};
+
 // |r| in double precision from r^2: FP32 square root refined by one
 // Newton step (relative error ~1e-15).
 __device__ inline double dist_d(double r2)
