@@ -85,13 +85,17 @@ __global__ __launch_bounds__(WBS) void k_w_radial(
         const int32_t *nl = list == 0 ? nl_ang : nl_rad;
         const int nf = list == 0 ? naf : nrf, nb = list == 0 ? nab : nrb;
         const int cap = list == 0 ? pc.capA : pc.capR;
+        MaskWriter mw;
         for (NeighbourPipe q(nl, xq, base, jmask, t, pc.n, nf, nb, cap); q.s < q.count;) {
+            const int s = q.s;
             int32_t e;
             double px, py, pz;
             q.pop(nl, xq, base, jmask, e, px, py, pz);
             double dx, dy, dz;
             pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
             const double r2 = dx * dx + dy * dy + dz * dz;
+            // the force kernel walks the radial list's inside entries only
+            if (list == 1) mw.add(pc.rmask, pc.n, t, s, q.count, r2 < rcR2);
             if (r2 >= rcR2) continue;
             const double r = dist_d(r2);
             overlap |= (r < 1e-3);
@@ -505,9 +509,10 @@ __global__ __launch_bounds__(WBS_F) void k_w_force(
         const float4 gj = pair_grad[(size_t)sj * pc.n + (int)((uint32_t)e & jmask) + base];
         Fx -= gj.x; Fy -= gj.y; Fz -= gj.z;
     }
-    const int nRl = nrf + nrb;
-    for (ListWalk wr(t, pc.n, nrf, nrb, pc.capR); wr.s < nRl; wr.next()) {
-        const int32_t e = nl_rad[wr.off];
+    // radial list: only the entries k_w_radial found inside rc_rad
+    MaskWalk mr(pc.rmask, pc.n, t, nrf + nrb);
+    for (int sr = mr.next(); sr >= 0; sr = mr.next()) {
+        const int32_t e = nl_rad[(size_t)list_slot(sr, nrf, nrb, pc.capR) * pc.n + t];
         const WAtomRec rj = xw[(int)((uint32_t)e & jmask) + base];
         float r2;
         radial(e, rj, r2);
