@@ -143,6 +143,7 @@ struct nep_ctx {
     float4 *f_own = nullptr;      // [N] sum_j dU_i/dr_ij (angular)
     uint8_t *rev = nullptr;       // [capA][N] reverse slot index
     uint32_t *rmask = nullptr;    // [ceil(capR/32)][N] radial entries inside rc_rad
+    uint32_t *amask = nullptr;    // [ceil(capA/32)][N] angular entries within the write radius
     double *e_atom = nullptr;
     // per-cell storage
     CellGeom *cells = nullptr;
@@ -270,7 +271,7 @@ void nep_destroy(nep_ctx *c)
                     c->w_atom,
                     c->e_atom, c->cells, c->cell_start_d, c->chunk_begin, c->chunk_end, c->cell_chunk,
                     c->part, c->bin_count, c->bin_start, c->bin_fill, c->scan_sums, c->status, c->flag,
-                    c->md, c->counts, c->pg_part, c->border, c->ke_part, c->n_border, c->rmask};
+                    c->md, c->counts, c->pg_part, c->border, c->ke_part, c->n_border, c->rmask, c->amask};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     if (c->h_status) (void)hipHostFree(c->h_status);
@@ -334,6 +335,7 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     A((void **)&c->f_own, N * sizeof(float4));
     A((void **)&c->rev, N * cfg->max_neigh_ang);
     A((void **)&c->rmask, N * ((cfg->max_neigh_rad + 31) / 32) * 4);
+    A((void **)&c->amask, N * ((cfg->max_neigh_ang + 31) / 32) * 4);
     A((void **)&c->w_atom, N * 9 * 4);
     A((void **)&c->e_atom, N * 8);
     A((void **)&c->cells, (size_t)cfg->max_cells * sizeof(CellGeom));
@@ -489,6 +491,7 @@ static int setup_system(nep_ctx *c, const nep_system *s, hipStream_t st)
     if (max_cell_atoms > (1LL << pc.jbits)) return NEP_E_ARG;
     pc.n = (int)n;
     pc.rmask = c->rmask;
+    pc.amask = c->amask;
 
     // bins
     if (nbins + 1 > c->bin_cap) {

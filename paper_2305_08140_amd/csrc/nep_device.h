@@ -64,6 +64,10 @@ struct PairConsts {
     // radial list was inside rc_rad at the last descriptor evaluation (the
     // force kernel walks only those entries)
     uint32_t *rmask;
+    // [word][atom]: bit s set when the s-th angular-list entry was within
+    // the pair-gradient write radius (rc_ang2_write, with a margin) at the
+    // last evaluation's first walk; the later angular walks take only those
+    uint32_t *amask;
 };
 
 // Reference lattice of the Wigner-Seitz analysis (perfect bcc, cubic

@@ -84,10 +84,11 @@ __device__ __forceinline__ void angular_sums_l34(const PairConsts &pc, const dou
 #pragma unroll
         for (int m = 0; m < 9; ++m) A4[n][m] = 0.0f;
     }
-    for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
+    for (MaskPipe q(pc.amask, nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.valid();) {
         int32_t e;
         double px, py, pz;
-        q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
+        int s;
+        q.pop(nl_ang, xq, base, jmask, e, px, py, pz, s);
         double dx, dy, dz;
         pair_vector_p(e, pc, px, py, pz, xi, yi, zi, cg, dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
@@ -147,13 +148,19 @@ __device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const doub
         for (int n = 0; n < NA; ++n)
 #pragma unroll
             for (int m = 0; m < 8; ++m) A[n][m] = 0.0;
+        // entries within the pair-gradient write radius (with a margin over
+        // the FP32 radius the gradient walk tests) for the later angular walks
+        const double awr = (double)pc.rc_ang2_write * (1.0 + 0x1p-15);
+        MaskWriter amw;
         for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
+            const int s = q.s;
             int32_t e;
             double px, py, pz;
             q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
             double dx, dy, dz;
             pair_vector_p(e, pc, px, py, pz, xi, yi, zi, cg, dx, dy, dz);
             const double r2 = dx * dx + dy * dy + dz * dz;
+            amw.add(pc.amask, pc.n, t, s, q.count, r2 < awr);
             if (r2 >= rcR2) continue;
             const double r = dist_d(r2);
             overlap |= (r < 1e-3);
@@ -490,16 +497,19 @@ __device__ __forceinline__ void descriptor_atom(
 #pragma unroll
     for (int k = 0; k < 9; ++k) W[k] = 0.0f;
     const uint32_t jmask = (1u << pc.jbits) - 1u;
-    for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
+    // the entries within the write radius only (the first walk's mask):
+    // a slot left out is one the other end never reads
+    for (MaskPipe q(pc.amask, nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.valid();) {
         // compiler barrier: the 50 angular coefficients are reloaded by
         // scalar loads in every trip instead of being hoisted into scalar
         // registers that then spill to vector-register lanes (one VALU
         // readlane per use); 616 instead of 633 VALU instructions per pair
         asm volatile("" ::: "memory");
-        const size_t off = (size_t)list_slot(q.s, naf, nab, pc.capA) * pc.n + t;
         int32_t e;
         double px, py, pz;
-        q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
+        int s;
+        q.pop(nl_ang, xq, base, jmask, e, px, py, pz, s);
+        const size_t off = q.off(s);
         double ddx, ddy, ddz;
         pair_vector_p(e, pc, px, py, pz, xi, yi, zi, cg, ddx, ddy, ddz);
         const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;

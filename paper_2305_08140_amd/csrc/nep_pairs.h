@@ -155,6 +155,48 @@ struct MaskWalk {
     }
 };
 
+// The software pipeline of NeighbourPipe over the entries a MaskWalk yields
+// (entry index s, slot offset off(s) = slot * n + t).
+//   for (MaskPipe q(...); q.valid();) { q.pop(..., s); ... }
+struct MaskPipe {
+    MaskWalk mw;
+    size_t n;
+    int t, nf, nb, cap;
+    int s_cur, s_nx;
+    int32_t e_cur, e_nx;
+    double x_cur, y_cur, z_cur;
+    __device__ size_t off(int s) const { return (size_t)list_slot(s, nf, nb, cap) * n + t; }
+    __device__ MaskPipe(const uint32_t *__restrict__ mask, const int32_t *__restrict__ nl,
+                        const double4 *__restrict__ xq, int base, uint32_t jmask, int t_, int n_, int nf_, int nb_,
+                        int cap_)
+        : mw(mask, n_, t_, nf_ + nb_), n((size_t)n_), t(t_), nf(nf_), nb(nb_), cap(cap_), e_cur(0), e_nx(0),
+          x_cur(0.0), y_cur(0.0), z_cur(0.0)
+    {
+        s_cur = mw.next();
+        if (s_cur >= 0) {
+            e_cur = nl[off(s_cur)];
+            const double4 *q = xq + ((int)((uint32_t)e_cur & jmask) + base);
+            x_cur = q->x; y_cur = q->y; z_cur = q->z;
+        }
+        s_nx = mw.next();
+        if (s_nx >= 0) e_nx = nl[off(s_nx)];
+    }
+    __device__ bool valid() const { return s_cur >= 0; }
+    __device__ void pop(const int32_t *__restrict__ nl, const double4 *__restrict__ xq, int base, uint32_t jmask,
+                        int32_t &e, double &px, double &py, double &pz, int &s)
+    {
+        e = e_cur; px = x_cur; py = y_cur; pz = z_cur; s = s_cur;
+        s_cur = s_nx;
+        if (s_cur >= 0) {
+            e_cur = e_nx;
+            const double4 *q = xq + ((int)((uint32_t)e_cur & jmask) + base);
+            x_cur = q->x; y_cur = q->y; z_cur = q->z;
+            s_nx = mw.next();
+            if (s_nx >= 0) e_nx = nl[off(s_nx)];
+        }
+    }
+};
+
 // |r| in double precision from r^2: FP32 square root refined by one
 // Newton step (relative error ~1e-15).
 __device__ inline double dist_d(double r2)

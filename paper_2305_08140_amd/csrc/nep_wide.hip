@@ -86,6 +86,10 @@ __global__ __launch_bounds__(WBS) void k_w_radial(
         const int nf = list == 0 ? naf : nrf, nb = list == 0 ? nab : nrb;
         const int cap = list == 0 ? pc.capA : pc.capR;
         MaskWriter mw;
+        // angular list: the entries within the pair-gradient write radius
+        // (with a margin) for the angular phases; radial list: the entries
+        // inside rc_rad for the force kernel
+        const double awr = (double)pc.rc_ang2_write * (1.0 + 0x1p-15);
         for (NeighbourPipe q(nl, xq, base, jmask, t, pc.n, nf, nb, cap); q.s < q.count;) {
             const int s = q.s;
             int32_t e;
@@ -94,8 +98,8 @@ __global__ __launch_bounds__(WBS) void k_w_radial(
             double dx, dy, dz;
             pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
             const double r2 = dx * dx + dy * dy + dz * dz;
-            // the force kernel walks the radial list's inside entries only
-            if (list == 1) mw.add(pc.rmask, pc.n, t, s, q.count, r2 < rcR2);
+            if (list == 0) mw.add(pc.amask, pc.n, t, s, q.count, r2 < awr);
+            else mw.add(pc.rmask, pc.n, t, s, q.count, r2 < rcR2);
             if (r2 >= rcR2) continue;
             const double r = dist_d(r2);
             overlap |= (r < 1e-3);
@@ -144,10 +148,11 @@ __device__ __forceinline__ void w_angular_group(const PairConsts &pc, const doub
 #pragma unroll
         for (int m = 0; m < 9; ++m) A4[c][m] = 0.0f;
     }
-    for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
+    for (MaskPipe q(pc.amask, nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.valid();) {
         int32_t e;
         double px, py, pz;
-        q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
+        int s;
+        q.pop(nl_ang, xq, base, jmask, e, px, py, pz, s);
         double dx, dy, dz;
         pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
@@ -302,11 +307,12 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
     }
     const bool first = c0 == 0;
     const double inv_rA = 1.0 / (double)pc.rc_ang;
-    for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
-        const size_t off = (size_t)list_slot(q.s, naf, nab, pc.capA) * n + t;
+    for (MaskPipe q(pc.amask, nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.valid();) {
         int32_t e;
         double px, py, pz;
-        q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
+        int s;
+        q.pop(nl_ang, xq, base, jmask, e, px, py, pz, s);
+        const size_t off = q.off(s);
         double ddx, ddy, ddz;
         pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, ddx, ddy, ddz);
         const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
