@@ -29,6 +29,11 @@
 //     dU_i/dr_ij for every angular pair (16 bytes per pair) and the force
 //     kernel subtracts the stored dU_j/dr_ji found through a reverse index
 //     built with the lists.
+// Inside-cutoff bitmasks: the descriptor kernel records which radial-list
+// entries lie inside rc_rad (the force kernel then walks only those) and,
+// in its first angular walk, which angular-list entries lie within the
+// pair-gradient write radius (its later angular walks take only those), so
+// the skin entries of the lists are loaded once per evaluation.
 // No atomics: every atom gathers its own force, deterministically.  The pair
 // vector seen from j is the exact negative of the one seen from i, so both
 // ends agree bit for bit on which pairs are inside a cutoff.
