@@ -243,8 +243,7 @@ __global__ __launch_bounds__(WBS) void k_w_network(int n_atoms, const double4 *_
         float z = -P[W_B0 + mu];
 #pragma unroll
         for (int nu = 0; nu < WDIM; ++nu) z = fmaf(w[nu], qt[nu], z);
-        const float e2 = __builtin_amdgcn_exp2f(2.8853900817779268f * z);   // exp(2z)
-        const float th = 1.0f - 2.0f / (e2 + 1.0f);
+        const float th = ftanh(z);
         const float w1 = P[W_W1 + mu];
         U = fmaf(w1, th, U);
         const float dz = w1 * fmaf(-th, th, 1.0f);
