@@ -146,6 +146,10 @@ typedef struct {
     double thermo_border; /* A, layer thickness at each selected face (>= 0; 0 selects no atom) */
     int32_t thermo_axes;  /* bit a (0..2) set: the two faces normal to lattice vector a; 1..7 */
     int32_t thermo_reset; /* nonzero: rebuild the border set and put the chain at rest first */
+    int32_t time_kernels; /* nonzero: HIP events on `stream` around the descriptor and force
+                             kernels of each step (the first 4096 steps of the call); the mean
+                             durations are returned in nep_md_stats */
+    int32_t pad_;
 } nep_md;
 
 typedef struct {
@@ -156,6 +160,9 @@ typedef struct {
     double thermo_energy; /* eV, chain energy sum_j Q_j v_j^2 / 2 + N_f kT xi_1 + kT sum_{j>1} xi_j;
                              total energy + kinetic energy + this is conserved */
     double border_temperature; /* K, 2 K_border / (N_f k_B) of the final velocities */
+    double ms_descriptor;  /* with md->time_kernels: mean ms per step of the descriptor kernel(s) */
+    double ms_force;       /* ... and of the force kernel */
+    int64_t n_timed_steps; /* steps those means cover (0 without time_kernels) */
 } nep_md_stats;
 
 /* Create a context for the given hyperparameters and capacities; weights are

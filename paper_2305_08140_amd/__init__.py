@@ -81,7 +81,7 @@ class Md(C.Structure):
     _fields_ = [("dt_max", C.c_double), ("max_disp", C.c_double), ("dt_min", C.c_double),
                 ("forces_valid", C.c_int32), ("thermo_chain", C.c_int32), ("thermo_T", C.c_double),
                 ("thermo_tau", C.c_double), ("thermo_border", C.c_double), ("thermo_axes", C.c_int32),
-                ("thermo_reset", C.c_int32)]
+                ("thermo_reset", C.c_int32), ("time_kernels", C.c_int32), ("pad_", C.c_int32)]
 
 
 class BccRef(C.Structure):
@@ -103,7 +103,8 @@ class Targets(C.Structure):
 
 class MdStats(C.Structure):
     _fields_ = [("n_rebuilds", C.c_int64), ("dt_last", C.c_double), ("time", C.c_double),
-                ("n_border", C.c_int64), ("thermo_energy", C.c_double), ("border_temperature", C.c_double)]
+                ("n_border", C.c_int64), ("thermo_energy", C.c_double), ("border_temperature", C.c_double),
+                ("ms_descriptor", C.c_double), ("ms_force", C.c_double), ("n_timed_steps", C.c_int64)]
 
 
 _lib = None
@@ -294,14 +295,14 @@ class Context:
         return out
 
     def nep_step_verlet(self, system: DeviceSystem, n_steps, out: EFV, dt_max=1.0, max_disp=0.0, dt_min=1e-6,
-                        forces_valid=False, thermostat=None, stream=None):
+                        forces_valid=False, thermostat=None, time_kernels=False, stream=None):
         """thermostat: None, or a dict with keys T (K), tau (fs), border (A),
         axes (tuple of lattice-vector indices), chain (length, default 3) and
         reset (bool) for the Nose-Hoover chain on the border atoms."""
         s = system.c_struct()
         o = out.c_struct()
         md = Md(dt_max=float(dt_max), max_disp=float(max_disp), dt_min=float(dt_min),
-                forces_valid=int(bool(forces_valid)))
+                forces_valid=int(bool(forces_valid)), time_kernels=int(bool(time_kernels)))
         if thermostat is not None:
             md.thermo_chain = int(thermostat.get("chain", 3))
             md.thermo_T = float(thermostat["T"])
@@ -314,7 +315,8 @@ class Context:
                                      _stream_ptr(stream)), "nep_step_verlet")
         return {"n_rebuilds": int(st.n_rebuilds), "dt_last": float(st.dt_last), "time": float(st.time),
                 "n_border": int(st.n_border), "thermo_energy": float(st.thermo_energy),
-                "border_temperature": float(st.border_temperature)}
+                "border_temperature": float(st.border_temperature), "ms_descriptor": float(st.ms_descriptor),
+                "ms_force": float(st.ms_force), "n_timed_steps": int(st.n_timed_steps)}
 
     def nep_status(self, stream=None):
         _check(lib().nep_status(self._ptr, _stream_ptr(stream)), "device status")

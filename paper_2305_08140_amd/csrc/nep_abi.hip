@@ -749,14 +749,20 @@ static void launch_force_any(nep_ctx *c, const nep_efv *o, hipStream_t st)
 }
 
 // One evaluation: sorted positions, descriptor + network, forces, reductions.
-static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t st, bool refresh_positions)
+// ev (may be NULL): three events recorded on st before the descriptor
+// kernel(s), between them and the force kernel, and after it.
+static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t st, bool refresh_positions,
+                      hipEvent_t *ev = nullptr)
 {
     const int n = (int)s->n_atoms;
     if (refresh_positions)
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
                                                            c->cells, c->xq, c->status, nullptr);
+    if (ev) HIP_TRY(hipEventRecord(ev[0], st));
     launch_desc_any(c, st);
+    if (ev) HIP_TRY(hipEventRecord(ev[1], st));
     launch_force_any(c, o, st);
+    if (ev) HIP_TRY(hipEventRecord(ev[2], st));
     k_reduce_chunks<<<c->n_chunks, 256, 0, st>>>(c->chunk_begin, c->chunk_end, c->e_atom, c->w_atom, c->part,
                                                  c->status);
     k_reduce_cells<<<c->built_cells, 256, 0, st>>>(c->built_cells, c->cell_chunk, c->part,
@@ -1064,22 +1070,51 @@ int nep_step_verlet(nep_ctx *c, nep_system *s, const nep_md *md, int32_t n_steps
     else k_dt_update<<<1, 64, 0, st>>>(md->dt_max, md->max_disp, md->dt_min, c->md, c->status, 0);
     // the rebuild counter counts rebuilds inside the chunk only
     HIP_TRY(hipMemsetAsync(c->md + MD_NREB, 0, 8, st));
+    // kernel timing: three events per step for the first MAX_TIMED steps
+    const int MAX_TIMED = 4096;
+    const int n_timed = md->time_kernels ? std::min(n_steps, MAX_TIMED) : 0;
+    std::vector<hipEvent_t> ev(3 * (size_t)n_timed);
+    auto free_events = [&]() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (auto &e : ev) {
+        e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) { free_events(); return NEP_E_HIP; }
+    }
     for (int k = 0; k < n_steps; ++k) {
         k_kick_drift<<<sg, 256, 0, st>>>(n, s->x, s->y, s->z, s->vx, s->vy, s->vz, o->fx, o->fy, o->fz, acc,
                                          c->xref, bd, c->md, c->status);
         k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag);
-        if ((rc = launch_build(c, s, st, c->flag))) return rc;
-        if ((rc = launch_efv(c, s, o, st, true))) return rc;
+        if ((rc = launch_build(c, s, st, c->flag))) { free_events(); return rc; }
+        if ((rc = launch_efv(c, s, o, st, true, k < n_timed ? &ev[3 * (size_t)k] : nullptr))) {
+            free_events();
+            return rc;
+        }
         k_kick<<<sg, 256, 0, st>>>(n, s->vx, s->vy, s->vz, o->fx, o->fy, o->fz, acc, bd, c->ke_part, c->md,
                                    c->status);
         if (th) chain(k + 1 < n_steps ? 1 : 2);
         else k_dt_update<<<1, 64, 0, st>>>(md->dt_max, md->max_disp, md->dt_min, c->md, c->status, 1);
     }
     if (th) k_scale_border<<<sg, 256, 0, st>>>(n, s->vx, s->vy, s->vz, c->border, c->md);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(c->h_md, c->md, MD_WORDS * 8, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(c->h_status, c->status, 8 * 4, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    if (hipGetLastError() != hipSuccess || hipMemcpyAsync(c->h_md, c->md, MD_WORDS * 8, hipMemcpyDeviceToHost, st) ||
+        hipMemcpyAsync(c->h_status, c->status, 8 * 4, hipMemcpyDeviceToHost, st) ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        free_events();
+        return NEP_E_HIP;
+    }
+    double ms_d = 0.0, ms_f = 0.0;
+    for (int k = 0; k < n_timed; ++k) {
+        float a = 0.0f, b = 0.0f;
+        if (hipEventElapsedTime(&a, ev[3 * (size_t)k], ev[3 * (size_t)k + 1]) != hipSuccess ||
+            hipEventElapsedTime(&b, ev[3 * (size_t)k + 1], ev[3 * (size_t)k + 2]) != hipSuccess) {
+            free_events();
+            return NEP_E_HIP;
+        }
+        ms_d += a;
+        ms_f += b;
+    }
+    free_events();
     if (stats) {
         stats->n_rebuilds = (int64_t)c->h_md[MD_NREB];
         stats->dt_last = c->h_md[MD_DT];
@@ -1088,6 +1123,9 @@ int nep_step_verlet(nep_ctx *c, nep_system *s, const nep_md *md, int32_t n_steps
         stats->thermo_energy = th ? c->h_md[MD_ENHC] : 0.0;
         stats->border_temperature =
             stats->n_border > 0 ? c->h_md[MD_TWOK] / (3.0 * (double)stats->n_border * K_B_EV) : 0.0;
+        stats->n_timed_steps = n_timed;
+        stats->ms_descriptor = n_timed > 0 ? ms_d / n_timed : 0.0;
+        stats->ms_force = n_timed > 0 ? ms_f / n_timed : 0.0;
     }
     const int code = c->h_status[ST_ERR];
     if (code != 0) {

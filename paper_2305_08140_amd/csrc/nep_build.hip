@@ -342,10 +342,18 @@ __global__ __launch_bounds__(256) void k_build_reverse(PairConsts pc, const int3
                                      ((uint32_t)(-n2 + pc.ioff) << (2 * pc.ibits))) << pc.jbits);
         const uint32_t cj = ncnt[j];
         const int jf = cj & 0xff, jb = (cj >> 8) & 0xff;
+        // both ends classify the pair from the same r^2 (exactly negated FP64
+        // pair vectors), so a front entry's partner is in j's front part and
+        // a back entry's in j's back part; the other part is searched only if
+        // that fails (after a capacity overflow, for instance)
+        const int f0 = 0, f1 = jf, b0 = pc.capA - jb, b1 = pc.capA;
+        const bool front = s < naf;
         int found = 255;
-        for (int q = 0; q < jf + jb; ++q) {
-            const int sq = q < jf ? q : q + (pc.capA - jf - jb);
-            if ((uint32_t)nl_ang[(size_t)sq * pc.n + j] == want) { found = sq; break; }
+        for (int pass = 0; pass < 2 && found == 255; ++pass) {
+            const bool in_front = (pass == 0) == front;
+            const int q0 = in_front ? f0 : b0, q1 = in_front ? f1 : b1;
+            for (int sq = q0; sq < q1; ++sq)
+                if ((uint32_t)nl_ang[(size_t)sq * pc.n + j] == want) { found = sq; break; }
         }
         rev[(size_t)slot * pc.n + t] = (uint8_t)found;
     }

@@ -188,8 +188,10 @@ def test_verlet_trajectory_thermal():
     sysd = nep.DeviceSystem.from_synth(s)
     ctx = nep.Context(m, s.n_atoms, 1)
     out = nep.EFV(s.n_atoms, 1)
-    ctx.nep_step_verlet(sysd, 10, out, dt_max=1.0)
+    st = ctx.nep_step_verlet(sysd, 10, out, dt_max=1.0, time_kernels=True)
     torch.cuda.synchronize()
+    # kernel timing on the library's stream: recorded for every step, results unchanged
+    assert st["n_timed_steps"] == 10 and st["ms_descriptor"] > 0.0 and st["ms_force"] > 0.0
     pos_ref, vel_ref, F_ref, log = oracle.velocity_verlet(m, s.pos, s.vel, s.h[0], s.mass, 10, dt_max=1.0,
                                                           record=True)
     assert np.abs(sysd.positions().cpu().numpy() - pos_ref).max() < 1e-7
