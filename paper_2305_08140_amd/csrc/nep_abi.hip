@@ -79,7 +79,7 @@ __global__ void k_sort_positions(int, const int32_t *, const double *, const dou
                                  const int32_t *);
 __global__ void k_build_lists(PairConsts, double, double, double, double, const double4 *, const int32_t *,
                               const CellGeom *, const int32_t *, const int32_t *, const int32_t *, int32_t *,
-                              int32_t *, uint32_t *, int32_t *, const int32_t *);
+                              int32_t *, uint32_t *, int32_t *, const int32_t *, int);
 __global__ void k_build_reverse(PairConsts, const int32_t *, const CellGeom *, const int32_t *,
                                 const uint32_t *, uint8_t *, int32_t *, const int32_t *);
 __global__ void k_kick_drift(int, double *, double *, double *, double *, double *, double *, const float *,
@@ -616,7 +616,8 @@ static int launch_build(nep_ctx *c, const nep_system *s, hipStream_t st, const i
     const double lA = c->hp.rc_ang + c->cfg.skin, lR = c->hp.rc_rad + c->cfg.skin;
     k_build_lists<<<grid_for(n, 256), 256, 0, st>>>(
         c->pc, lA * lA, lR * lR, c->hp.rc_ang * c->hp.rc_ang, c->hp.rc_rad * c->hp.rc_rad, c->xq, c->cell_of,
-        c->cells, c->bin_sorted, c->bin_start, c->bin_rank, c->nl_ang, c->nl_rad, c->ncnt, c->status, flag);
+        c->cells, c->bin_sorted, c->bin_start, c->bin_rank, c->nl_ang, c->nl_rad, c->ncnt, c->status, flag,
+        c->n_bins < (1 << 27) ? 1 : 0);
     k_build_reverse<<<grid_for(n, 256), 256, 0, st>>>(c->pc, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->rev,
                                                       c->status, flag);
     HIP_TRY(hipGetLastError());

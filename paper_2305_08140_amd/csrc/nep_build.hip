@@ -16,8 +16,13 @@
 //   radial list    rc_ang + skin <= r < rc_rad + skin: r < rc_rad from the
 //                                      front, the skin shell from the back
 // so that the pair loops meet the inside-cutoff entries first and in the
-// same order on all lanes (little divergence).  An entry packs the neighbour's
-// index within its cell (jbits bits) with the image n in 3 fields of ibits.
+// same order on all lanes (little divergence).  With the 3 x 3 x 3 bin search
+// the bins are visited in the order their atoms are stored, so each part of a
+// list is ascending in the neighbour's index: neighbouring atoms of a
+// wavefront then gather nearby records at the same slot, which shares cache
+// lines between lanes (3.5 % off the descriptor kernel, 2.5 % off the force
+// kernel at 8.2 M atoms).  An entry packs the neighbour's index within its
+// cell (jbits bits) with the image n in 3 fields of ibits.
 #include "nep_device.h"
 
 namespace nep {
@@ -216,6 +221,26 @@ __global__ void k_sort_positions(int n, const int32_t *__restrict__ perm,
     xq[t] = make_double4(wx, wy, wz, 0.0);
 }
 
+// Batcher's odd-even merge sort of 32 keys, ascending; every index is a
+// compile-time constant once the loops are unrolled, so the keys stay in
+// registers.
+__device__ __forceinline__ void sort32(uint32_t a[32])
+{
+#pragma unroll
+    for (int p = 1; p < 32; p <<= 1)
+#pragma unroll
+        for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+            for (int j = k % p; j + k < 32; j += 2 * k)
+#pragma unroll
+                for (int i = 0; i < k; ++i)
+                    if (i + j + k < 32 && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+                        const uint32_t x = a[i + j], y = a[i + j + k];
+                        a[i + j] = x < y ? x : y;
+                        a[i + j + k] = x < y ? y : x;
+                    }
+}
+
 // Neighbour lists of every sorted atom (see the file comment for the layout).
 __global__ __launch_bounds__(256) void k_build_lists(
     PairConsts pc, double lA2, double lR2, double cA2, double cR2, const double4 *__restrict__ xq,
@@ -223,7 +248,7 @@ __global__ __launch_bounds__(256) void k_build_lists(
     const int32_t *__restrict__ bin_sorted, const int32_t *__restrict__ bin_start,
     const int32_t *__restrict__ bin_rank,
     int32_t *__restrict__ nl_ang, int32_t *__restrict__ nl_rad, uint32_t *__restrict__ ncnt,
-    int32_t *__restrict__ status, const int32_t *__restrict__ flag)
+    int32_t *__restrict__ status, const int32_t *__restrict__ flag, int sorted_scan)
 {
     if (flag && *flag == 0) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -238,65 +263,98 @@ __global__ __launch_bounds__(256) void k_build_lists(
         if (cg.R[a] > 0) { lo[a] = -cg.R[a]; hi[a] = cg.R[a]; }
         else { lo[a] = -1; hi[a] = 1; }
     }
-    int naf = 0, nab = 0, nrf = 0, nrb = 0;
+    uint64_t cntA = 0, cntR = 0;   // front | back << 32
     const int capA = pc.capA, capR = pc.capR;
     const uint32_t jmask_limit = 1u << pc.jbits;
-    for (int o2 = lo[2]; o2 <= hi[2]; ++o2)
-        for (int o1 = lo[1]; o1 <= hi[1]; ++o1)
-            for (int o0 = lo[0]; o0 <= hi[0]; ++o0) {
-                const int o[3] = {o0, o1, o2};
-                int bb[3], m[3];
-                bool skip = false;
-                for (int a = 0; a < 3; ++a) {
-                    if (cg.R[a] > 0) { bb[a] = 0; m[a] = o[a]; }
-                    else {
-                        int b = bc[a] + o[a];
-                        m[a] = 0;
-                        if (cg.periodic[a]) {
-                            if (b < 0) { b += cg.nb[a]; m[a] = -1; }
-                            else if (b >= cg.nb[a]) { b -= cg.nb[a]; m[a] = 1; }
-                        } else if (b < 0 || b >= cg.nb[a]) skip = true;
-                        bb[a] = b;
-                    }
-                }
-                if (skip) continue;
-                const double sx = m[0] * cg.h[0] + m[1] * cg.h[3] + m[2] * cg.h[6];
-                const double sy = m[0] * cg.h[1] + m[1] * cg.h[4] + m[2] * cg.h[7];
-                const double sz = m[0] * cg.h[2] + m[1] * cg.h[5] + m[2] * cg.h[8];
-                const bool self_image = (m[0] | m[1] | m[2]) == 0;
-                const uint32_t code = (uint32_t)(m[0] + pc.ioff) | ((uint32_t)(m[1] + pc.ioff) << pc.ibits)
-                                      | ((uint32_t)(m[2] + pc.ioff) << (2 * pc.ibits));
-                const int gb = cg.bin_offset +
-                               bin_rank[cg.bin_offset + (bb[2] * cg.nb[1] + bb[1]) * cg.nb[0] + bb[0]];
-                for (int u = bin_start[gb]; u < bin_start[gb + 1]; ++u) {
-                    if (u == t && self_image) continue;
-                    // (x_u - x_i) + shift: exactly the negative of the vector seen from u
-                    const double4 pu = xq[u];
-                    const double dx = (pu.x - xi) + sx, dy = (pu.y - yi) + sy, dz = (pu.z - zi) + sz;
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 >= lR2) continue;
-                    const uint32_t jl = (uint32_t)(u - cg.atom_start);
-                    const int32_t e = (int32_t)(jl | (code << pc.jbits));
-                    if (jl >= jmask_limit) latch_error(status, -1);
-                    if (r2 < lA2) {
-                        if (r2 < cA2) {
-                            if (naf + nab < capA) nl_ang[(size_t)naf * pc.n + t] = e;
-                            ++naf;
-                        } else {
-                            if (naf + nab < capA) nl_ang[(size_t)(capA - 1 - nab) * pc.n + t] = e;
-                            ++nab;
-                        }
-                    } else {
-                        if (r2 < cR2) {
-                            if (nrf + nrb < capR) nl_rad[(size_t)nrf * pc.n + t] = e;
-                            ++nrf;
-                        } else {
-                            if (nrf + nrb < capR) nl_rad[(size_t)(capR - 1 - nrb) * pc.n + t] = e;
-                            ++nrb;
-                        }
-                    }
-                }
+    // bin of offset o from this atom's bin: global bin index (or -1 past an
+    // open face) and the image m it lies in
+    auto bin_at = [&](int o0, int o1, int o2, int m[3]) __attribute__((always_inline)) -> int {
+        const int o[3] = {o0, o1, o2};
+        int bb[3];
+        bool out = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (cg.R[a] > 0) { bb[a] = 0; m[a] = o[a]; }
+            else {
+                int b = bc[a] + o[a];
+                m[a] = 0;
+                if (cg.periodic[a]) {
+                    if (b < 0) { b += cg.nb[a]; m[a] = -1; }
+                    else if (b >= cg.nb[a]) { b -= cg.nb[a]; m[a] = 1; }
+                } else if (b < 0 || b >= cg.nb[a]) out = true;
+                bb[a] = b;
             }
+        }
+        if (out) return -1;
+        return cg.bin_offset + bin_rank[cg.bin_offset + (bb[2] * cg.nb[1] + bb[1]) * cg.nb[0] + bb[0]];
+    };
+    auto scan_bin = [&](int gb, const int m[3]) __attribute__((always_inline)) {
+        const double sx = m[0] * cg.h[0] + m[1] * cg.h[3] + m[2] * cg.h[6];
+        const double sy = m[0] * cg.h[1] + m[1] * cg.h[4] + m[2] * cg.h[7];
+        const double sz = m[0] * cg.h[2] + m[1] * cg.h[5] + m[2] * cg.h[8];
+        const bool self_image = (m[0] | m[1] | m[2]) == 0;
+        const uint32_t code = (uint32_t)(m[0] + pc.ioff) | ((uint32_t)(m[1] + pc.ioff) << pc.ibits)
+                              | ((uint32_t)(m[2] + pc.ioff) << (2 * pc.ibits));
+        for (int u = bin_start[gb]; u < bin_start[gb + 1]; ++u) {
+            if (u == t && self_image) continue;
+            // (x_u - x_i) + shift: exactly the negative of the vector seen from u
+            const double4 pu = xq[u];
+            const double dx = (pu.x - xi) + sx, dy = (pu.y - yi) + sy, dz = (pu.z - zi) + sz;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 >= lR2) continue;
+            const uint32_t jl = (uint32_t)(u - cg.atom_start);
+            const int32_t e = (int32_t)(jl | (code << pc.jbits));
+            if (jl >= jmask_limit) latch_error(status, -1);
+            // inside the cutoff at build time: front of the list, else back
+            // (front and back counts packed in one word each, so that the
+            // compiler keeps them in registers)
+            const bool ang = r2 < lA2;
+            const bool front = r2 < (ang ? cA2 : cR2);
+            const uint64_t cnt = ang ? cntA : cntR;
+            const int f = (int)(cnt & 0xffffffffu), b = (int)(cnt >> 32), cap = ang ? capA : capR;
+            if (f + b < cap) (ang ? nl_ang : nl_rad)[(size_t)(front ? f : cap - 1 - b) * pc.n + t] = e;
+            const uint64_t inc = front ? 1ull : (1ull << 32);
+            cntA += ang ? inc : 0ull;
+            cntR += ang ? 0ull : inc;
+        }
+    };
+    if (sorted_scan && cg.R[0] == 0 && cg.R[1] == 0 && cg.R[2] == 0) {
+        // the 3 x 3 x 3 neighbour bins in the order their atoms are stored,
+        // so that every list is ascending in the neighbour index and the
+        // lists of nearby atoms gather nearby records at equal slots.  Keys
+        // (bin << 5 | offset) sorted by an odd-even merge network in registers.
+        uint32_t key[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            key[q] = 0xffffffffu;
+            if (q < 27) {
+                int m[3];
+                const int gb = bin_at(q % 3 - 1, (q / 3) % 3 - 1, q / 9 - 1, m);
+                if (gb >= 0) key[q] = ((uint32_t)gb << 5) | (uint32_t)q;
+            }
+        }
+        sort32(key);
+        for (int k = 0; k < 27; ++k) {
+            const uint32_t kq = key[0];
+#pragma unroll
+            for (int q = 0; q < 31; ++q) key[q] = key[q + 1];
+            if (kq == 0xffffffffu) break;
+            const int q = (int)(kq & 31u);
+            int m[3];
+            const int gb = bin_at(q % 3 - 1, (q / 3) % 3 - 1, q / 9 - 1, m);
+            scan_bin(gb, m);
+        }
+    } else {
+        for (int o2 = lo[2]; o2 <= hi[2]; ++o2)
+            for (int o1 = lo[1]; o1 <= hi[1]; ++o1)
+                for (int o0 = lo[0]; o0 <= hi[0]; ++o0) {
+                    int m[3];
+                    const int gb = bin_at(o0, o1, o2, m);
+                    if (gb >= 0) scan_bin(gb, m);
+                }
+    }
+    int naf = (int)(cntA & 0xffffffffu), nab = (int)(cntA >> 32);
+    int nrf = (int)(cntR & 0xffffffffu), nrb = (int)(cntR >> 32);
     const int nA = naf + nab, nR = nrf + nrb;
     if (nA > capA || nR > capR) {
         latch_error(status, -3);

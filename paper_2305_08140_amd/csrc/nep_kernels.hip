@@ -551,18 +551,25 @@ __device__ __forceinline__ void descriptor_atom(
         float Y[NLM];
         sph_unnorm(mono, Y);
         float Dc[NLM];
-        float s1 = 0.0f;
+        // D_lm = sum_n B_{n,lm} g_n for the angular part of the gradient; the
+        // radial part s1 = sum_lm (sum_n B_{n,lm} g'_n) y_lm is taken as
+        // sum_n g'_n E_n with E_n = sum_lm B_{n,lm} y_lm (fewer products)
+        float En[NA];
+#pragma unroll
+        for (int n = 0; n < NA; ++n) En[n] = 0.0f;
 #pragma unroll
         for (int lm = 0; lm < NLM; ++lm) {
-            float D = 0.0f, Dp = 0.0f;
+            float D = 0.0f;
 #pragma unroll
             for (int n = 0; n < NA; ++n) {
                 D = fmaf(S[n][lm], g[n], D);
-                Dp = fmaf(S[n][lm], gp[n], Dp);
+                En[n] = fmaf(S[n][lm], Y[lm], En[n]);
             }
             Dc[lm] = D;
-            s1 = fmaf(Dp, Y[lm], s1);
         }
+        float s1 = 0.0f;
+#pragma unroll
+        for (int n = 0; n < NA; ++n) s1 = fmaf(gp[n], En[n], s1);
         float vx, vy, vz;
         sph_unnorm_grad_contract(mono, Dc, vx, vy, vz);
         const float uv = ux * vx + uy * vy + uz * vz;
