@@ -361,19 +361,24 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
         const SphMono mono(ux, uy, uz);
         float Y[NLM];
         sph_unnorm(mono, Y);
-        float Dc[NLM];
-        float s1 = 0.0f;
+        // D_lm = sum_c B_{c,lm} g_c; the radial term sum_c g'_c E_c with
+        // E_c = sum_lm B_{c,lm} y_lm
+        float Dc[NLM], Ec[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Ec[c] = 0.0f;
 #pragma unroll
         for (int lm = 0; lm < NLM; ++lm) {
-            float D = 0.0f, Dp = 0.0f;
+            float D = 0.0f;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 D = fmaf(B[c][lm], g[c], D);
-                Dp = fmaf(B[c][lm], gp[c], Dp);
+                Ec[c] = fmaf(B[c][lm], Y[lm], Ec[c]);
             }
             Dc[lm] = D;
-            s1 = fmaf(Dp, Y[lm], s1);
         }
+        float s1 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) s1 = fmaf(gp[c], Ec[c], s1);
         float vx, vy, vz;
         sph_unnorm_grad_contract(mono, Dc, vx, vy, vz);
         const float uv = ux * vx + uy * vy + uz * vz;
