@@ -221,26 +221,6 @@ __global__ void k_sort_positions(int n, const int32_t *__restrict__ perm,
     xq[t] = make_double4(wx, wy, wz, 0.0);
 }
 
-// Batcher's odd-even merge sort of 32 keys, ascending; every index is a
-// compile-time constant once the loops are unrolled, so the keys stay in
-// registers.
-__device__ __forceinline__ void sort32(uint32_t a[32])
-{
-#pragma unroll
-    for (int p = 1; p < 32; p <<= 1)
-#pragma unroll
-        for (int k = p; k >= 1; k >>= 1)
-#pragma unroll
-            for (int j = k % p; j + k < 32; j += 2 * k)
-#pragma unroll
-                for (int i = 0; i < k; ++i)
-                    if (i + j + k < 32 && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
-                        const uint32_t x = a[i + j], y = a[i + j + k];
-                        a[i + j] = x < y ? x : y;
-                        a[i + j + k] = x < y ? y : x;
-                    }
-}
-
 // Neighbour lists of every sorted atom (see the file comment for the layout).
 __global__ __launch_bounds__(256) void k_build_lists(
     PairConsts pc, double lA2, double lR2, double cA2, double cR2, const double4 *__restrict__ xq,

@@ -500,6 +500,26 @@ __host__ __device__ inline void decode_entry(int32_t e, int jbits, int ibits, in
 // tile (b % 8) * per + b / 8 gives every XCD one contiguous run of tiles, so
 // spatially adjacent atom tiles share one L2.  The grid must be launched with
 // 8 * per blocks (per = ceil(tiles / 8)); logical tiles >= tiles do nothing.
+// Batcher's odd-even merge sort of 32 keys, ascending (191 compare-exchange
+// steps); every index is a compile-time constant once the loops are
+// unrolled, so on the GPU the keys stay in registers.
+__host__ __device__ inline void sort32(uint32_t a[32])
+{
+#pragma unroll
+    for (int p = 1; p < 32; p <<= 1)
+#pragma unroll
+        for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+            for (int j = k % p; j + k < 32; j += 2 * k)
+#pragma unroll
+                for (int i = 0; i < k; ++i)
+                    if (i + j + k < 32 && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+                        const uint32_t x = a[i + j], y = a[i + j + k];
+                        a[i + j] = x < y ? x : y;
+                        a[i + j + k] = x < y ? y : x;
+                    }
+}
+
 __device__ inline int xcd_block(int ntiles)
 {
     const int b = blockIdx.x;

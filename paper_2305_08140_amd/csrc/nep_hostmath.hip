@@ -54,4 +54,6 @@ void nep_test_decode(int32_t e, int jbits, int ibits, int ioff, int *out)
     decode_entry(e, jbits, ibits, ioff, out[0], out[1], out[2], out[3]);
 }
 
+void nep_test_sort32(uint32_t *a) { sort32(a); }
+
 }  // extern "C"

@@ -33,6 +33,7 @@ def L():
     lib.nep_test_sph_unnorm_grad.argtypes = [F, F, F, FP, FP]
     lib.nep_test_zbl.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, DP, DP]
     lib.nep_test_decode.argtypes = [C.c_int32, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
+    lib.nep_test_sort32.argtypes = [C.POINTER(C.c_uint32)]
     return lib
 
 
@@ -205,3 +206,23 @@ def test_neighbour_entry_decoding(L):
             e = np.int32(np.uint32(j | (code << jbits)))
             L.nep_test_decode(int(e), jbits, ibits, ioff, out)
             assert tuple(out) == (j,) + n
+
+
+def test_sort32_network(L):
+    # the list build's bin order: 27 keys (bin << 5 | offset) padded with
+    # 0xffffffff to 32, sorted ascending by the odd-even merge network; also
+    # duplicates, reversed and all-equal inputs
+    rng = np.random.default_rng(11)
+    cases = [rng.integers(0, 2**32 - 1, 32, dtype=np.uint64).astype(np.uint32) for _ in range(300)]
+    cases += [rng.integers(0, 4, 32).astype(np.uint32) for _ in range(100)]
+    for _ in range(200):
+        k = np.full(32, 0xFFFFFFFF, dtype=np.uint32)
+        n = int(rng.integers(0, 28))
+        k[:n] = (rng.integers(0, 2**27, n).astype(np.uint32) << 5) | rng.permutation(27)[:n].astype(np.uint32)
+        cases.append(rng.permutation(k))
+    cases += [np.arange(32, dtype=np.uint32)[::-1].copy(), np.full(32, 7, dtype=np.uint32)]
+    for a in cases:
+        a = np.ascontiguousarray(a, dtype=np.uint32)
+        ref = np.sort(a)
+        L.nep_test_sort32(a.ctypes.data_as(C.POINTER(C.c_uint32)))
+        assert np.array_equal(a, ref)
