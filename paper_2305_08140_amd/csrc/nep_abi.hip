@@ -871,7 +871,7 @@ int nep_backward(nep_ctx *c, const nep_system *s, const nep_efv *o, const double
                                                        c->cells, c->xq, c->status, nullptr);
     k_param_grad<<<blocks, 64, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
                                         c->params, c->c64, gE, c->pg_part, c->status, tiles);
-    k_param_reduce<<<grid_for(N_PARAMS, 256), 256, 0, st>>>(blocks, c->pg_part, grad_params);
+    k_param_reduce<<<(N_PARAMS + 31) / 32, 256, 0, st>>>(blocks, c->pg_part, grad_params);
     if (gx) k_grad_pos<<<grid_for(n, 256), 256, 0, st>>>(n, c->cell_of, gE, o->fx, o->fy, o->fz, gx, gy, gz);
     if (gh)
         k_grad_cell<<<c->built_cells, 256, 0, st>>>(c->cells, s->x, s->y, s->z, o->fx, o->fy, o->fz, o->virial,

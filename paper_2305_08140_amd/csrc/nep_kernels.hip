@@ -837,167 +837,207 @@ __global__ void k_params64(const float *__restrict__ P, double *__restrict__ C64
 // theta = (c_rad [NR][KB], c_ang [NA][KB], w0 [NH][DIM], b0 [NH], w1 [NH], b1)
 constexpr int NPARAM = NR * KB + NA * KB + NH * DIM + NH + NH + 1;
 constexpr int PG_TILE = 64;
-// per-atom factors kept in LDS: g dz_mu, g tanh z_mu, s q (unweighted),
-// g dU/dq_n (radial), F_k (unweighted), g G_nk, g
-constexpr int PG_DZ = 0, PG_TH = PG_DZ + NH, PG_QT = PG_TH + NH, PG_FPR = PG_QT + DIM, PG_F = PG_FPR + NR,
-              PG_G = PG_F + KB, PG_W = PG_G + NA * KB, PG_REC = PG_W + 1;
+// Per-atom factors of the two outer-product blocks, kept in LDS per tile:
+// g dz_mu, s q (unweighted), g dU/dq_n (radial), F_k (unweighted).  The
+// row stride is odd (no bank conflicts) and 64 rows take 19.7 KB, so eight
+// one-wave blocks fit a CU.
+constexpr int PG_DZ = 0, PG_QT = PG_DZ + NH, PG_FPR = PG_QT + DIM, PG_F = PG_FPR + NR, PG_REC = PG_F + KB;
+// Tile sums of the factors that enter the gradient linearly: g tanh z_mu,
+// g G_nk, g (one value per tile, summed across the wave in a fixed order).
+constexpr int PS_TH = 0, PS_G = PS_TH + NH, PS_W = PS_G + NA * KB, PS_N = PS_W + 1;
+
+// Sum over the 64 lanes of a wavefront, the same total in every lane (xor
+// butterfly: a fixed order of additions, so the result is deterministic).
+__device__ __forceinline__ float wave_sum64(float v)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
 
 // Gradient of sum_i gE[cell(i)] U_i with respect to theta.  Per atom:
 //   dU/dw1_mu = tanh z_mu, dU/db0_mu = -dz_mu, dU/dw0_mu,nu = dz_mu s_nu q_nu,
 //   dU/db1 = -1, dU/dc^R_nk = (dU/dq_n) F_k,
 //   dU/dc^A_nk = sum_{lm} B_{n,lm} sum_j f_k(r_ij) Y_lm(u_ij)   (B = dU/ds_{n,lm}),
-// with dz_mu = w1_mu (1 - tanh^2 z_mu).  64-atom tiles: the factors go to
-// LDS, then every thread sums its own outputs (o = lane + 64 k) over the
-// tile; one FP64 partial per block and output, reduced afterwards in order.
+// with dz_mu = w1_mu (1 - tanh^2 z_mu).  64-atom tiles, one wavefront each:
+// the factors of the outer products go to LDS and every thread sums its own
+// outputs (o = lane + 64 k) over the tile; the linear factors are summed
+// across the wave.  Lanes past the last atom evaluate atom 0 with weight 0.
+// One FP64 partial per block and output, reduced afterwards in order.
 __global__ __launch_bounds__(64) void k_param_grad(
     PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt, const float *__restrict__ P,
     const double *__restrict__ C64, const double *__restrict__ gE, double *__restrict__ part, const int32_t *__restrict__ status, int ntiles)
 {
-    __shared__ float rec[PG_TILE][PG_REC + 1];
+    __shared__ float rec[PG_TILE][PG_REC];
+    __shared__ float tsum[PS_N];
     constexpr int NOWN = (NPARAM + PG_TILE - 1) / PG_TILE;
     const int lane = threadIdx.x;
-    double acc[NOWN];
-#pragma unroll
-    for (int k = 0; k < NOWN; ++k) acc[k] = 0.0;
+    double *pb = part + (size_t)blockIdx.x * NPARAM;   // this block's partials, added tile by tile
     const bool ok = status[ST_ERR] == 0;
+    for (int k = 0; k < NOWN; ++k) {
+        const int o = lane + PG_TILE * k;
+        if (o < NPARAM) pb[o] = 0.0;
+    }
     float csA[NA];
     angular_coef_sums(P, csA);
 
     for (int tile = blockIdx.x; tile < ntiles && ok; tile += gridDim.x) {
-        const int t = tile * PG_TILE + lane;
+        const bool valid = tile * PG_TILE + lane < pc.n;
+        const int t = valid ? tile * PG_TILE + lane : 0;
         float *r = rec[lane];
-        if (t < pc.n) {
-            const double4 pi = xq[t];
-            const double xi = pi.x, yi = pi.y, zi = pi.z;
-            const CellGeom *cg = cells + cell_of[t];
-            const int base = cg->atom_start;
-            const uint32_t cnt = ncnt[t];
-            const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
-            const float g = (float)gE[cell_of[t]];
-            float F[KB];
-            float S[NA][NLM];
-            double ezbl;
-            bool overlap;
-            descriptor_sums(pc, xq, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, C64, F, S,
-                            ezbl, overlap);
-            float q[DIM];
-            descriptor_vector(P, F, S, q);
-            // network with the per-neuron factors written to LDS
-            float Fp[DIM];
+        const double4 pi = xq[t];
+        const double xi = pi.x, yi = pi.y, zi = pi.z;
+        const CellGeom *cg = cells + cell_of[t];
+        const int base = cg->atom_start;
+        const uint32_t cnt = ncnt[t];
+        const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
+        const float g = valid ? (float)gE[cell_of[t]] : 0.0f;
+        float F[KB];
+        float S[NA][NLM];
+        double ezbl;
+        bool overlap;
+        descriptor_sums(pc, xq, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, C64, F, S, ezbl,
+                        overlap);
+        float q[DIM];
+        descriptor_vector(P, F, S, q);
+        // network with the per-neuron factors (outer-product ones to LDS,
+        // tanh summed over the tile)
+        float Fp[DIM];
 #pragma unroll
-            for (int nu = 0; nu < DIM; ++nu) {
-                Fp[nu] = 0.0f;
-                r[PG_QT + nu] = P[P_QS + nu] * q[nu];
-            }
-#pragma unroll 1
-            for (int mu = 0; mu < NH; ++mu) {
-                const float *w = P + P_W0 + mu * DIM;
-                float z = -P[P_B0 + mu];
-#pragma unroll
-                for (int nu = 0; nu < DIM; ++nu) z = fmaf(w[nu], P[P_QS + nu] * q[nu], z);
-                const float th = ftanh(z);
-                const float dz = P[P_W1 + mu] * fmaf(-th, th, 1.0f);
-                r[PG_TH + mu] = g * th;
-                r[PG_DZ + mu] = g * dz;
-#pragma unroll
-                for (int nu = 0; nu < DIM; ++nu) Fp[nu] = fmaf(dz, w[nu], Fp[nu]);
-            }
-#pragma unroll
-            for (int nu = 0; nu < DIM; ++nu) Fp[nu] *= P[P_QS + nu];
-#pragma unroll
-            for (int n = 0; n < NR; ++n) r[PG_FPR + n] = g * Fp[n];
-#pragma unroll
-            for (int k = 0; k < KB; ++k) r[PG_F + k] = F[k];
-            // B = 2 (dU/dq_nl) s_{n,lm} in place of S
-#pragma unroll
-            for (int n = 0; n < NA; ++n)
-#pragma unroll
-                for (int lm = 0; lm < NLM; ++lm) {
-                    const int l = lm < 3 ? 1 : (lm < 8 ? 2 : (lm < 15 ? 3 : 4));
-                    S[n][lm] *= 2.0f * Fp[NR + NA * (l - 1) + n];
-                }
-            // G_nk = sum_j f_k(r_ij) sum_lm B_{n,lm} Y_lm(u_ij)
-            float G[NA][KB];
-#pragma unroll
-            for (int n = 0; n < NA; ++n)
-#pragma unroll
-                for (int k = 0; k < KB; ++k) G[n][k] = 0.0f;
-            for (ListWalk w(t, pc.n, naf, nab, pc.capA); w.s < naf + nab; w.next()) {
-                const int32_t e = nl_ang[w.off];
-                int j;
-                double ddx, ddy, ddz;
-                pair_vector_d(e, pc, base, xi, yi, zi, xq, cg, j, ddx, ddy, ddz);
-                const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 >= pc.rc_ang2) continue;
-                const float rr = fsqrt(r2);
-                const float rinv = frcp(rr);
-                const float tt = scaled_minus_one(rr, pc.inv_rc_ang, pc.inv_rc_ang_lo);
-                float fc;
-                cutoff_value(tt, fc);
-                float T[KB];
-                cheb(fmaf(2.0f * tt, tt, -1.0f), T);
-                float Y[NLM];
-                sph(dx * rinv, dy * rinv, dz * rinv, Y);
-#pragma unroll
-                for (int n = 0; n < NA; ++n) {
-                    float D = 0.0f;
-#pragma unroll
-                    for (int lm = 0; lm < NLM; ++lm) D = fmaf(S[n][lm], Y[lm], D);
-                    const float hD = 0.5f * fc * D;      // f_k = (T_k + 1) fc / 2
-#pragma unroll
-                    for (int k = 0; k < KB; ++k) G[n][k] = fmaf(hD, T[k] + 1.0f, G[n][k]);
-                }
-            }
-#pragma unroll
-            for (int n = 0; n < NA; ++n)
-#pragma unroll
-                for (int k = 0; k < KB; ++k) r[PG_G + n * KB + k] = g * G[n][k];
-            r[PG_W] = g;
-        } else {
-            for (int k = 0; k < PG_REC; ++k) r[k] = 0.0f;
+        for (int nu = 0; nu < DIM; ++nu) {
+            Fp[nu] = 0.0f;
+            r[PG_QT + nu] = P[P_QS + nu] * q[nu];
         }
-        __syncthreads();
+#pragma unroll 1
+        for (int mu = 0; mu < NH; ++mu) {
+            const float *w = P + P_W0 + mu * DIM;
+            float z = -P[P_B0 + mu];
 #pragma unroll
+            for (int nu = 0; nu < DIM; ++nu) z = fmaf(w[nu], P[P_QS + nu] * q[nu], z);
+            const float th = ftanh(z);
+            const float dz = P[P_W1 + mu] * fmaf(-th, th, 1.0f);
+            const float sth = wave_sum64(g * th);
+            if (lane == 0) tsum[PS_TH + mu] = sth;
+            r[PG_DZ + mu] = g * dz;
+#pragma unroll
+            for (int nu = 0; nu < DIM; ++nu) Fp[nu] = fmaf(dz, w[nu], Fp[nu]);
+        }
+#pragma unroll
+        for (int nu = 0; nu < DIM; ++nu) Fp[nu] *= P[P_QS + nu];
+#pragma unroll
+        for (int n = 0; n < NR; ++n) r[PG_FPR + n] = g * Fp[n];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) r[PG_F + k] = F[k];
+        // B = 2 (dU/dq_nl) s_{n,lm} in place of S
+#pragma unroll
+        for (int n = 0; n < NA; ++n)
+#pragma unroll
+            for (int lm = 0; lm < NLM; ++lm) {
+                const int l = lm < 3 ? 1 : (lm < 8 ? 2 : (lm < 15 ? 3 : 4));
+                S[n][lm] *= 2.0f * Fp[NR + NA * (l - 1) + n];
+            }
+        // G_nk = sum_j f_k(r_ij) sum_lm B_{n,lm} Y_lm(u_ij)
+        float G[NA][KB];
+#pragma unroll
+        for (int n = 0; n < NA; ++n)
+#pragma unroll
+            for (int k = 0; k < KB; ++k) G[n][k] = 0.0f;
+        // the entries the first angular walk above marked (within the write
+        // radius), software-pipelined
+        const uint32_t jmask = (1u << pc.jbits) - 1u;
+        for (MaskPipe q(pc.amask, nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.valid();) {
+            int32_t e;
+            double px, py, pz;
+            int s;
+            q.pop(nl_ang, xq, base, jmask, e, px, py, pz, s);
+            double ddx, ddy, ddz;
+            pair_vector_p(e, pc, px, py, pz, xi, yi, zi, cg, ddx, ddy, ddz);
+            const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 >= pc.rc_ang2) continue;
+            const float rr = fsqrt(r2);
+            const float rinv = frcp(rr);
+            const float tt = scaled_minus_one(rr, pc.inv_rc_ang, pc.inv_rc_ang_lo);
+            float fc;
+            cutoff_value(tt, fc);
+            float T[KB];
+            cheb(fmaf(2.0f * tt, tt, -1.0f), T);
+            float Y[NLM];
+            sph(dx * rinv, dy * rinv, dz * rinv, Y);
+#pragma unroll
+            for (int n = 0; n < NA; ++n) {
+                float D = 0.0f;
+#pragma unroll
+                for (int lm = 0; lm < NLM; ++lm) D = fmaf(S[n][lm], Y[lm], D);
+                const float hD = 0.5f * fc * D;      // f_k = (T_k + 1) fc / 2
+#pragma unroll
+                for (int k = 0; k < KB; ++k) G[n][k] = fmaf(hD, T[k] + 1.0f, G[n][k]);
+            }
+        }
+#pragma unroll
+        for (int n = 0; n < NA; ++n)
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const float sg = wave_sum64(g * G[n][k]);
+                if (lane == 0) tsum[PS_G + n * KB + k] = sg;
+            }
+        const float sw = wave_sum64(g);
+        if (lane == 0) tsum[PS_W] = sw;
+        __syncthreads();
         for (int k = 0; k < NOWN; ++k) {
             const int o = lane + PG_TILE * k;
             if (o >= NPARAM) break;
-            int i1, i2 = -1;
-            float sign = 1.0f;
-            if (o < NR * KB) { i1 = PG_FPR + o / KB; i2 = PG_F + o % KB; }
-            else if (o < NR * KB + NA * KB) { i1 = PG_G + (o - NR * KB); }
-            else if (o < NR * KB + NA * KB + NH * DIM) {
-                const int p = o - NR * KB - NA * KB;
-                i1 = PG_DZ + p / DIM; i2 = PG_QT + p % DIM;
-            } else if (o < NR * KB + NA * KB + NH * DIM + NH) { i1 = PG_DZ + (o - (NPARAM - 1 - 2 * NH)); sign = -1.0f; }
-            else if (o < NPARAM - 1) { i1 = PG_TH + (o - (NPARAM - 1 - NH)); }
-            else { i1 = PG_W; sign = -1.0f; }
             float sum = 0.0f;
-            if (i2 >= 0)
+            if (o < NR * KB) {
+                const int i1 = PG_FPR + o / KB, i2 = PG_F + o % KB;
                 for (int a = 0; a < PG_TILE; ++a) sum = fmaf(rec[a][i1], rec[a][i2], sum);
-            else
+            } else if (o < NR * KB + NA * KB) {
+                sum = tsum[PS_G + (o - NR * KB)];
+            } else if (o < NR * KB + NA * KB + NH * DIM) {
+                const int p = o - NR * KB - NA * KB;
+                const int i1 = PG_DZ + p / DIM, i2 = PG_QT + p % DIM;
+                for (int a = 0; a < PG_TILE; ++a) sum = fmaf(rec[a][i1], rec[a][i2], sum);
+            } else if (o < NR * KB + NA * KB + NH * DIM + NH) {
+                const int i1 = PG_DZ + (o - (NPARAM - 1 - 2 * NH));
                 for (int a = 0; a < PG_TILE; ++a) sum += rec[a][i1];
-            acc[k] += (double)(sign * sum);
+                sum = -sum;
+            } else if (o < NPARAM - 1) {
+                sum = tsum[PS_TH + (o - (NPARAM - 1 - NH))];
+            } else {
+                sum = -tsum[PS_W];
+            }
+            pb[o] += (double)sum;
         }
         __syncthreads();
     }
-#pragma unroll
-    for (int k = 0; k < NOWN; ++k) {
-        const int o = lane + PG_TILE * k;
-        if (o < NPARAM) part[(size_t)blockIdx.x * NPARAM + o] = acc[k];
-    }
 }
 
-// grad[o] = sum over blocks of part[b][o], in block order.
-__global__ void k_param_reduce(int nblocks, const double *__restrict__ part, double *__restrict__ grad)
+// grad[o] = sum over blocks of part[b][o] in a fixed order (deterministic):
+// a block of 256 threads takes 32 consecutive outputs; thread (c, p) sums the
+// partials b = c, c + 8, c + 16, ... of output p (each step reads 32
+// consecutive doubles per c), and the eight chunk sums of an output are then
+// added in chunk order.
+__global__ __launch_bounds__(256) void k_param_reduce(int nblocks, const double *__restrict__ part,
+                                                      double *__restrict__ grad)
 {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= NPARAM) return;
+    __shared__ double sh[8][33];
+    const int p = threadIdx.x & 31, c = threadIdx.x >> 5;
+    const int o = blockIdx.x * 32 + p;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * NPARAM + o];
-    grad[o] = s;
+    if (o < NPARAM) {
+#pragma unroll 4
+        for (int b = c; b < nblocks; b += 8) s += part[(size_t)b * NPARAM + o];
+    }
+    sh[c][p] = s;
+    __syncthreads();
+    if (c == 0 && o < NPARAM) {
+        double t = sh[0][p];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) t += sh[k][p];
+        grad[o] = t;
+    }
 }
 
 // dL/dx_i = -gE[cell(i)] F_i (caller order, FP64).
