@@ -90,3 +90,41 @@ def test_cell_gradient_matches_finite_differences():
         err = np.linalg.norm(gh[c] - fd) / np.linalg.norm(fd)
         print(f"[cell grad] cell {c}: rel err {err:.2e}", flush=True)
         assert err <= 1e-4
+
+
+def test_parameter_gradient_over_many_tiles():
+    # the 512-cell batch has more 64-atom tiles than the 1024 blocks of the
+    # parameter-gradient launch, so blocks add several tiles into their
+    # partial rows: two calls agree bit for bit, and the gradient of the whole
+    # batch is the sum of the gradients of its two halves (each under 1024
+    # tiles) to FP32 rounding
+    import torch
+    import paper_2305_08140_amd as nep
+    m = nep_synth.random_model()
+    full = nep_synth.diffbatch()
+    assert (full.n_atoms + 63) // 64 > 1024
+    rng = np.random.default_rng(21)
+    g_all = rng.uniform(0.5, 1.5, size=full.n_cells)
+
+    def grad(s, g):
+        sysd = nep.DeviceSystem.from_synth(s)
+        ctx = nep.Context(m, s.n_atoms, s.n_cells)
+        o = nep.EFV(s.n_atoms, s.n_cells)
+        ctx.nep_build_neighbors(sysd)
+        ctx.nep_compute_efv(sysd, o)
+        gE = torch.tensor(g, device="cuda", dtype=torch.float64)
+        a = ctx.nep_backward(sysd, o, gE, grad_pos=False, grad_cell=False)[0].clone()
+        b = ctx.nep_backward(sysd, o, gE, grad_pos=False, grad_cell=False)[0]
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        return a.cpu().numpy()
+
+    gp = grad(full, g_all)
+    lo, hi = range(0, 256), range(256, 512)
+    parts = grad(_subset(full, lo), g_all[:256]) + grad(_subset(full, hi), g_all[256:])
+    groups = {"c_rad": (0, 81), "c_ang": (81, 126), "w0": (126, 996), "b0": (996, 1026), "w1": (1026, 1056),
+              "b1": (1056, 1057)}
+    for name, (a, b) in groups.items():
+        err = np.linalg.norm(gp[a:b] - parts[a:b]) / np.linalg.norm(parts[a:b])
+        print(f"[param grad, 1111 tiles] {name}: whole vs halves rel diff {err:.2e}", flush=True)
+        assert err <= 1e-6, name
