@@ -255,7 +255,12 @@ int nep_num_params(const nep_ctx *ctx);
  *               gE[c] h^-T (sum_i x_i (x) F_i - W^T); may be NULL
  * The forces and virial follow from Eq. 1; the parameter gradient is what a
  * gradient-based fit of the model would use (the paper trains by a
- * gradient-free evolution strategy, Sec. III.A).  Returns NEP_OK, NEP_E_ARG,
+ * gradient-free evolution strategy, Sec. III.A).  grad_params is
+ * deterministic: FP32 sums over 64-atom tiles, FP64 partials per block (at
+ * most 1024 blocks), the partials summed in a fixed tree.  The first call,
+ * or a call on more atoms than any before, allocates those partials in the
+ * context (min(ceil(n_atoms / 64), 1024) x nep_num_params doubles, at most
+ * 8.7 MB); they are freed by nep_destroy.  Returns NEP_OK, NEP_E_ARG,
  * NEP_E_STATE or NEP_E_HIP; device errors are latched as for nep_compute_efv. */
 int nep_backward(nep_ctx *ctx, const nep_system *sys, const nep_efv *out, const double *gE,
                  double *grad_params, double *grad_x, double *grad_y, double *grad_z, double *grad_h,
