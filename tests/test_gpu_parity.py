@@ -43,6 +43,21 @@ def test_perfect_lattice_zero_force():
     assert abs(res["energy"][0] - ref["energy"][0]) / s.n_atoms <= E_ATOM_TOL
 
 
+@pytest.mark.parametrize("dims", [(8, 8, 8), (8, 10, 12)])
+def test_narrow_bin_grids(dims):
+    # 3 x 3 x 3 and 3 x 4 x 5 bins of >= r_c + skin: the 27 bins of the list
+    # search, visited in storage order, wrap around every face (with 3 bins an
+    # atom's neighbour bins are the whole cell); displaced atoms against the
+    # oracle
+    m = model()
+    pos, h = nep_synth.bcc_lattice(*dims)
+    pos = pos + np.random.default_rng(sum(dims)).normal(0.0, 0.05, pos.shape)
+    s = nep_synth._single(pos, h)
+    ref = oracle.efv_system(m, s)
+    res, *_ = run_gpu(m, s)
+    _compare(s, m, ref, res, None, f"bcc {dims}")
+
+
 def test_small_strained_cells_with_images():
     # cells of 8-60 atoms: several periodic images of the same neighbour, own images
     m = model()
