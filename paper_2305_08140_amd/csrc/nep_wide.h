@@ -8,7 +8,7 @@
 //   k_w_angular   angular sums of one group of WGA channels per launch
 //                 (l <= 3 in FP64, l = 4 in FP32, as in the default model)
 //   k_w_network   network forward and backward per atom, site energy, the
-//                 atom's record (position + 16 radial adjoints, 128 bytes)
+//                 atom's record (position + 16 radial adjoints, 96 bytes)
 //   k_w_grad      dU_i/dr_ij of every angular slot, channel group by group
 //   k_w_force     radial + ZBL pair forces, angular assembly, virial
 #pragma once
@@ -42,13 +42,15 @@ constexpr int W_SIZE = W_B1 + 1;
 // double copy of the angular coefficients and their row sums
 constexpr int W_C64 = WA * WKA + WA;
 
-// one 128-byte line per atom for the force kernel's gathers
-struct __attribute__((aligned(128))) WAtomRec {
+// the force kernel's per-neighbour record: 88 bytes padded to 96, six
+// 16-byte pieces per gather (a 128-byte stride would cost eight, and
+// power-of-two strides gather more slowly)
+struct __attribute__((aligned(16))) WAtomRec {
     double x, y, z;
     float a[WKR];
-    float pad[10];
+    float pad[2];
 };
-static_assert(sizeof(WAtomRec) == 128, "WAtomRec must be 128 bytes");
+static_assert(sizeof(WAtomRec) == 96, "WAtomRec must be 96 bytes");
 
 __global__ void k_w_params64(const float *P, double *C64);
 __global__ void k_w_radial(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,

@@ -266,7 +266,7 @@ __global__ __launch_bounds__(WBS) void k_w_network(int n_atoms, const double4 *_
         rec.a[k] = s;
     }
 #pragma unroll
-    for (int k = 0; k < 10; ++k) rec.pad[k] = 0.0f;
+    for (int k = 0; k < 2; ++k) rec.pad[k] = 0.0f;
     xw[t] = rec;
 #pragma unroll
     for (int nu = WR; nu < WDIM; ++nu) FpA[(nu - WR) * n + t] = Fp[nu];
