@@ -58,6 +58,21 @@ def test_narrow_bin_grids(dims):
     _compare(s, m, ref, res, None, f"bcc {dims}")
 
 
+def test_batch_mixing_binned_and_imaged_cells():
+    # one launch over three cells: two large enough for the 3 x 3 x 3 bin
+    # search (bins numbered after the first cell's), and a small cell that
+    # loops over explicit images
+    m = model()
+    rng = np.random.default_rng(31)
+    parts = [nep_synth.bcc_lattice(8, 8, 8), nep_synth.bcc_lattice(3, 3, 2), nep_synth.bcc_lattice(8, 10, 12)]
+    pos = np.concatenate([p + rng.normal(0.0, 0.05, p.shape) for p, _ in parts])
+    starts = np.concatenate([[0], np.cumsum([p.shape[0] for p, _ in parts])]).astype(np.int64)
+    s = nep_synth.System(pos=pos, vel=np.zeros_like(pos), cell_start=starts, h=np.stack([h for _, h in parts]))
+    ref = oracle.efv_system(m, s)
+    res, *_ = run_gpu(m, s)
+    _compare(s, m, ref, res, None, "binned + imaged cells")
+
+
 def test_small_strained_cells_with_images():
     # cells of 8-60 atoms: several periodic images of the same neighbour, own images
     m = model()
