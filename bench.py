@@ -74,19 +74,20 @@ def _traffic(kernel: str, n_launch_atoms: int):
     return float(k["bytes_per_launch"])
 
 
-def cpu_baseline(model, s, seconds_target=15.0):
+def cpu_baseline(model, s, seconds_target=5.0):
     """FP64 oracle (untuned, all host threads) on a bounded sample of the same
-    workload: energies and forces of a contiguous block of atoms."""
+    workload: energies and forces of a contiguous block of atoms.  The sample
+    is sized for ~seconds_target per run; one warm-up run, then the median of
+    three timed runs."""
     import oracle
     n_thr = oracle.num_threads()
     # probe with a small sample, then size the sample for ~seconds_target
     sample = 2000
     t0 = time.time()
     oracle.efv_cell(model, s.pos, s.h[0], targets=np.arange(sample), virial=False)
-    t_probe = time.time() - t0
-    per_atom = t_probe / sample
+    per_atom = (time.time() - t0) / sample
     # the probe includes the fixed cost of binning all atoms, so resize once
-    # more from the first sized run
+    # more from the first sized run (which is also the warm-up)
     for _ in range(2):
         sample = int(min(s.n_atoms, 2_000_000, max(2000, seconds_target / max(per_atom, 1e-9))))
         t0 = time.time()
@@ -95,10 +96,48 @@ def cpu_baseline(model, s, seconds_target=15.0):
         per_atom = dt / sample
         if dt > 0.5 * seconds_target or sample >= min(s.n_atoms, 2_000_000):
             break
+    runs = []
+    for _ in range(3):
+        t0 = time.time()
+        oracle.efv_cell(model, s.pos, s.h[0], targets=np.arange(sample), virial=False)
+        runs.append(time.time() - t0)
+    dt = float(np.median(runs))
     return {"value": sample / dt, "unit": "atom-steps/s", "cores": n_thr, "kind": "oracle",
             "sample": f"FP64 energies+forces of {sample} atoms of the 8,192,000-atom configuration "
                       f"(one evaluation, neighbours found afresh; the integrator update is negligible), "
-                      f"{dt:.1f} s on {n_thr} threads"}
+                      f"median of 3 runs after a warm-up: {dt:.2f} s on {n_thr} threads"}
+
+
+def oracle_rates(model, nve_system, cell_samples):
+    """The oracle timed beside the GPU figures of the other workloads (median
+    of 3 after a warm-up, all host threads): one energy + forces + virial
+    evaluation of the whole 128,000-atom cell (atom-steps/s; the integrator
+    update is negligible), and the sampled cells of each batch (cells/s; with
+    dE/dtheta for the differentiable batch)."""
+    import oracle
+
+    def med(fn):
+        fn()
+        runs = []
+        for _ in range(3):
+            t0 = time.time()
+            fn()
+            runs.append(time.time() - t0)
+        return float(np.median(runs))
+    out = {"threads": oracle.num_threads()}
+    if nve_system is not None:
+        t = med(lambda: oracle.efv_cell(model, nve_system.pos, nve_system.h[0]))
+        out["mid_128000"] = {"atom_steps_per_s": nve_system.n_atoms / t, "seconds": t}
+    for name, (cells, with_grad) in cell_samples.items():
+        def run():
+            for pos, h in cells:
+                oracle.efv_cell(model, pos, h)
+                if with_grad:
+                    oracle.param_grad_cell(model, pos, h)
+        t = med(run)
+        out[name] = {"cells_per_s": len(cells) / t, "n_cells": len(cells), "with_param_grad": with_grad,
+                     "seconds": t}
+    return out
 
 
 def fp64_checks(checks):
@@ -497,6 +536,8 @@ def main():
     ap.add_argument("--snes-gens", type=int, default=10,
                     help="timed SNES generations (population 50) on the 4,096-cell batch (0 skips it)")
     ap.add_argument("--timing-reps", type=int, default=5)
+    ap.add_argument("--rebuild-probe-steps", type=int, default=300,
+                    help="MD steps after the timed region that measure the rebuild rate (0 skips it)")
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ summaries from rocprofv3 output directories and exit")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -554,6 +595,38 @@ def main():
     t1 = time.perf_counter()
     wall = t1 - t0
     value = N * args.steps / wall
+
+    # neighbour rebuilds: the cost of one (HIP events around a forced
+    # rebuild of the current configuration, the same kernels the MD loop
+    # runs when an atom has moved more than skin / 2), and their rate over a
+    # longer probe chunk that carries its rebuilds, timed as a whole
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reb_ms = []
+    for _ in range(3):
+        ev0.record()
+        ctx.nep_build_neighbors(sysd)
+        ev1.record()
+        torch.cuda.synchronize()
+        reb_ms.append(ev0.elapsed_time(ev1))
+    rebuild_ms = float(np.median(reb_ms))
+    ctx.nep_compute_efv(sysd, out)          # forces of the current positions again
+    torch.cuda.synchronize()
+    rebuild = None
+    if args.rebuild_probe_steps > 0:
+        t0 = time.perf_counter()
+        pst = ctx.nep_step_verlet(sysd, args.rebuild_probe_steps, out, forces_valid=True, **md)
+        torch.cuda.synchronize()
+        t_probe = time.perf_counter() - t0
+        rps = pst["n_rebuilds"] / args.rebuild_probe_steps
+        # per-step time of the timed chunk without its own rebuilds, plus the
+        # probe's rebuild rate at the measured rebuild cost
+        t_step_plain = (wall - stats["n_rebuilds"] * rebuild_ms * 1e-3) / args.steps
+        t_step_amort = t_step_plain + rps * rebuild_ms * 1e-3
+        rebuild = {"ms_per_rebuild": rebuild_ms, "rebuilds_in_timed_steps": stats["n_rebuilds"],
+                   "probe_steps": args.rebuild_probe_steps, "probe_rebuilds": pst["n_rebuilds"],
+                   "rebuilds_per_step": rps, "probe_atom_steps_per_s": N * args.rebuild_probe_steps / t_probe,
+                   "amortised_atom_steps_per_s": N / t_step_amort,
+                   "amortised_ms_per_step": t_step_amort * 1e3}
 
     # per-kernel durations: HIP events on the library's stream around the
     # descriptor and force kernels of every timed step (live), and a
@@ -618,6 +691,20 @@ def main():
     ferr = ferr_th = eerr = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(model, s)
+        samples = {k[len("batch_"):]: ([(pos, h) for pos, h, _ in v["cells"]], k == "batch_diffbatch")
+                   for k, v in checks.items() if k in ("batch_batch", "batch_diffbatch")}
+        rates = oracle_rates(model, nep_synth.mid() if nve is not None else None, samples)
+        if nve is not None:
+            nve["cpu_oracle_atom_steps_per_s"] = rates["mid_128000"]["atom_steps_per_s"]
+            nve["cpu_oracle_threads"] = rates["threads"]
+        if batches is not None:
+            for name in batches:
+                if name in rates:
+                    batches[name]["cpu_oracle_cells_per_s"] = rates[name]["cells_per_s"]
+                    batches[name]["cpu_oracle_sample"] = (
+                        f"{rates[name]['n_cells']} sampled cells, energy + forces + virial"
+                        + (" + dE/dtheta" if rates[name]["with_param_grad"] else "")
+                        + f", median of 3 after a warm-up on {rates['threads']} threads")
         acc = fp64_checks(checks)
         ferr = acc["bulk"]["force_rel_err"]
         ferr_th = acc["bulk"]["force_rel_err_without_excluded"]
@@ -650,6 +737,7 @@ def main():
         "kernel_tflops": {"descriptor": f_desc * N / (klive["descriptor"] * 1e-3) / 1e12,
                           "force": f_force * N / (klive["force"] * 1e-3) / 1e12},
         "md": {"n_rebuilds": stats["n_rebuilds"], "dt_last_fs": stats["dt_last"], "time_fs": stats["time"]},
+        "rebuild": rebuild,
         "force_rel_err_vs_fp64": ferr, "force_rel_err_vs_fp64_thermal_atoms": ferr_th,
         "site_energy_max_abs_err_eV": eerr,
         "defects": defects,

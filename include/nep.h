@@ -178,16 +178,34 @@ void nep_destroy(nep_ctx *ctx);
  * asynchronously on `stream`).  Returns NEP_OK, NEP_E_ARG or NEP_E_HIP. */
 int nep_set_weights(nep_ctx *ctx, const nep_weights *w, int32_t weights_on_device, void *stream);
 
-/* Build the cell list and the neighbour lists (radius rc + skin) of `sys`.
- * Positions may lie anywhere; they are wrapped into the cell internally.
- * Overflow of a list capacity latches NEP_E_NEIGH_OVERFLOW.
+/* Build the cell list and the neighbour lists of `sys`: the pair sets that
+ * the sums of Eq. 1 run over, every periodic image of every atom j != i (and
+ * the atom's own images) within the radial cutoff rc_rad (6 A) for the radial
+ * descriptor and within rc_ang (4 A) for the angular one (Sec. III.A, the
+ * cutoffs of the model), widened by the skin so the lists stay valid until an
+ * atom has moved skin/2.  Positions (DEVICE, caller order) may lie anywhere;
+ * they are wrapped into the cell internally, and open axes (pbc = 0) take no
+ * images.  The lists, the cell list and the sorted atom order are stored in
+ * the context (memory allocated by nep_create; nothing is allocated here).
+ * Overflow of a list capacity latches NEP_E_NEIGH_OVERFLOW (the lengths needed
+ * are returned by nep_required_neighbors) and non-finite positions latch
+ * NEP_E_NONFINITE; after such a build the lists stay unusable, and evaluations
+ * on them latch NEP_E_STATE until a build succeeds.
  * Returns NEP_OK, NEP_E_ARG or NEP_E_HIP. */
 int nep_build_neighbors(nep_ctx *ctx, const nep_system *sys, void *stream);
 
-/* Energy, forces and virial of `sys` at its current positions, using the
- * neighbour lists of the last nep_build_neighbors on the same system (atoms
- * may have moved by less than skin/2 since).  Returns NEP_OK, NEP_E_ARG,
- * NEP_E_STATE or NEP_E_HIP. */
+/* Energy, forces and virial of `sys` at its current positions (Eq. 1: the
+ * network site energies of the radial and angular descriptors plus half of
+ * the ZBL pair energy of Eqs. 2-4 for every pair closer than the outer
+ * switch radius; forces F_i = -dE/dx_i; virial W_ab = -sum_i sum_j
+ * (dU_i/dr_ij)_a (r_ij)_b), using the neighbour lists of the last
+ * nep_build_neighbors on the same system (atoms may have moved by less than
+ * skin/2 since).  Inputs: the DEVICE positions of `sys`; outputs: the DEVICE
+ * arrays of `out` (caller-owned; energy and virial per cell, forces and site
+ * energies in the caller's atom order).  Work buffers are the context's.
+ * Asynchronous on `stream`; device errors (overlapping atoms, unusable
+ * lists) are latched as described above.  Returns NEP_OK, NEP_E_ARG,
+ * NEP_E_STATE (no lists built for this system) or NEP_E_HIP. */
 int nep_compute_efv(nep_ctx *ctx, const nep_system *sys, nep_efv *out, void *stream);
 
 /* Advance `sys` by n_steps velocity-Verlet steps (x, v updated in place), with

@@ -264,6 +264,14 @@ class Context:
         ptr = C.c_void_p()
         _check(L.nep_create(C.byref(hp), C.byref(cfg), C.byref(ptr)), "nep_create")
         self._ptr = ptr
+        # sizes of the parameter blocks (c_rad, c_ang, w0, b0, w1, b1) of
+        # this context's model, in the flat layout of nep_backward
+        dim = model.n_rad + model.n_ang * model.l_max
+        self.theta_sizes = (model.n_rad * model.k_rad, model.n_ang * model.k_ang, model.n_hidden * dim,
+                            model.n_hidden, model.n_hidden, 1)
+        # which forward's weights and neighbour lists the context holds (the
+        # differentiable energy restores them before its backward)
+        self.state_token = None
         self.nep_set_weights(model)
 
     def __del__(self):
@@ -277,10 +285,12 @@ class Context:
     def nep_set_weights(self, model):
         arrs = [np.ascontiguousarray(getattr(model, k), dtype=np.float32)
                 for k in ("c_rad", "c_ang", "q_scale", "w0", "b0", "w1")]
+        self.state_token = None
         w = Weights(*[a.ctypes.data for a in arrs], float(model.b1), 0)
         _check(lib().nep_set_weights(self._ptr, C.byref(w), 0, None), "nep_set_weights")
 
     def nep_build_neighbors(self, system: DeviceSystem, stream=None):
+        self.state_token = None
         s = system.c_struct()
         _check(lib().nep_build_neighbors(self._ptr, C.byref(s), _stream_ptr(stream)), "nep_build_neighbors")
         if self.check:
@@ -299,6 +309,7 @@ class Context:
         """thermostat: None, or a dict with keys T (K), tau (fs), border (A),
         axes (tuple of lattice-vector indices), chain (length, default 3) and
         reset (bool) for the Nose-Hoover chain on the border atoms."""
+        self.state_token = None
         s = system.c_struct()
         o = out.c_struct()
         md = Md(dt_max=float(dt_max), max_disp=float(max_disp), dt_min=float(dt_min),

@@ -27,7 +27,7 @@ __global__ void k_reduce_cells(int, const int32_t *, const double *, double *, d
 __global__ void k_energy_atom_out(int, const int32_t *, const double *, float *);
 __global__ void k_param_grad(PairConsts, const double4 *, const int32_t *, const CellGeom *, const int32_t *,
                              const int32_t *, const uint32_t *, const float *, const double *, const double *,
-                             double *, const int32_t *, int);
+                             double *, int32_t *, int);
 __global__ void k_params64(const float *, double *);
 __global__ void k_param_reduce(int, const double *, double *);
 __global__ void k_grad_pos(int, const int32_t *, const double *, const float *, const float *, const float *,
@@ -89,7 +89,8 @@ __global__ void k_kick(int, double *, double *, double *, const float *, const f
                        const uint8_t *, double *, double *, const int32_t *);
 __global__ void k_vmax(int, const double *, const double *, const double *, const uint8_t *, double *, double *);
 __global__ void k_dt_update(double, double, double, double *, int32_t *, int);
-__global__ void k_rebuild_flag(double, double *, int32_t *);
+__global__ void k_rebuild_flag(double, double *, int32_t *, const int32_t *);
+__global__ void k_lists_commit(int32_t *, const int32_t *);
 __global__ void k_disp(int, const double *, const double *, const double *, const double *, double *);
 __global__ void k_set_flag(int32_t *, int32_t);
 __global__ void k_cell_of(int, int, const int64_t *, int32_t *);
@@ -201,6 +202,9 @@ struct nep_ctx {
     std::vector<int64_t> built_start;
     int pbc[3] = {1, 1, 1};
     PairConsts pc;
+    // incremented by every setup_system: the captured graph holds the pair
+    // constants and per-cell tables of the setup it was captured under
+    uint64_t setup_gen = 0;
     std::vector<CellGeom> geom;
 };
 
@@ -357,6 +361,9 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     if (ok && hipMemset(c->perm, 0, N * 4) != hipSuccess) ok = false;
     if (ok && hipMemset(c->ncnt, 0, N * 4) != hipSuccess) ok = false;
     if (ok && hipMemset(c->cell_of, 0, N * 4) != hipSuccess) ok = false;
+    // reverse slots start as "absent"; no list is usable before a build
+    if (ok && hipMemset(c->rev, 0xff, N * cfg->max_neigh_ang) != hipSuccess) ok = false;
+    if (ok && hipMemset(c->status + ST_LBAD, 0xff, 4) != hipSuccess) ok = false;
     if (ok && hipDeviceSynchronize() != hipSuccess) ok = false;
     if (!ok) { nep_destroy(c); return NEP_E_HIP; }
     *out = c;
@@ -425,6 +432,7 @@ static bool same_system(const nep_ctx *c, const nep_system *s)
 static int setup_system(nep_ctx *c, const nep_system *s, hipStream_t st)
 {
     c->border_valid = false;
+    ++c->setup_gen;
     const int nc = s->cell_start ? s->n_cells : 1;
     const int64_t n = s->n_atoms;
     std::vector<int64_t> start(nc + 1);
@@ -620,6 +628,8 @@ static int launch_build(nep_ctx *c, const nep_system *s, hipStream_t st, const i
         c->n_bins < (1 << 27) ? 1 : 0);
     k_build_reverse<<<grid_for(n, 256), 256, 0, st>>>(c->pc, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->rev,
                                                       c->status, flag);
+    // the lists are usable only if the build latched no error
+    k_lists_commit<<<1, 64, 0, st>>>(c->status, flag);
     HIP_TRY(hipGetLastError());
     return NEP_OK;
 }
@@ -939,7 +949,7 @@ int nep_compute_efv_graph(nep_ctx *c, const nep_system *s, nep_efv *o, void *str
         (uintptr_t)s->n_atoms, (uintptr_t)s->x, (uintptr_t)s->y, (uintptr_t)s->z, (uintptr_t)o->energy,
         (uintptr_t)o->fx, (uintptr_t)o->fy, (uintptr_t)o->fz, (uintptr_t)o->virial, (uintptr_t)o->energy_atom,
         (uintptr_t)c->shape_desc, (uintptr_t)c->shape_force, (uintptr_t)c->n_chunks, (uintptr_t)c->built_cells,
-        (uintptr_t)c->nn_mode};
+        (uintptr_t)c->nn_mode, (uintptr_t)c->setup_gen};
     if (!c->graph_exec || key != c->graph_key) {
         if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
         if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
@@ -1038,7 +1048,7 @@ int nep_step_verlet(nep_ctx *c, nep_system *s, const nep_md *md, int32_t n_steps
         fresh = true;
     } else {
         k_disp<<<sg, 256, 0, st>>>(n, s->x, s->y, s->z, c->xref, c->md);
-        k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag);
+        k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag, c->status);
         if ((rc = launch_build(c, s, st, c->flag))) return rc;
     }
     if (!md->forces_valid || fresh) {
@@ -1086,7 +1096,7 @@ int nep_step_verlet(nep_ctx *c, nep_system *s, const nep_md *md, int32_t n_steps
     for (int k = 0; k < n_steps; ++k) {
         k_kick_drift<<<sg, 256, 0, st>>>(n, s->x, s->y, s->z, s->vx, s->vy, s->vz, o->fx, o->fy, o->fz, acc,
                                          c->xref, bd, c->md, c->status);
-        k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag);
+        k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag, c->status);
         if ((rc = launch_build(c, s, st, c->flag))) { free_events(); return rc; }
         if ((rc = launch_efv(c, s, o, st, true, k < n_timed ? &ev[3 * (size_t)k] : nullptr))) {
             free_events();

@@ -531,13 +531,25 @@ __global__ void k_dt_update(double dt_max, double max_disp, double dt_min, doubl
 }
 
 // Rebuild decision: an atom moved more than skin/2 since the last build.
-__global__ void k_rebuild_flag(double half_skin2, double *__restrict__ md, int32_t *__restrict__ flag)
+__global__ void k_rebuild_flag(double half_skin2, double *__restrict__ md, int32_t *__restrict__ flag,
+                               const int32_t *__restrict__ status)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int r = md[MD_DISP2] > half_skin2;
+    // unusable lists (a build that ended with an error) are rebuilt too
+    const int r = md[MD_DISP2] > half_skin2 || status[ST_LBAD] != 0;
     *flag = r;
     if (r) md[MD_NREB] += 1.0;
     md[MD_DISP2] = 0.0;
+}
+
+// End of a list build: the lists are usable if no error was latched while
+// they were built (an overflow truncates them and skips the reverse index).
+// Skipped with the rest of the build when *flag is 0.
+__global__ void k_lists_commit(int32_t *__restrict__ status, const int32_t *__restrict__ flag)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (flag && *flag == 0) return;
+    status[ST_LBAD] = status[ST_ERR] != 0 ? 1 : 0;
 }
 
 // Largest displacement since the last build (for the rebuild decision at a

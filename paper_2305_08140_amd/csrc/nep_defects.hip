@@ -10,7 +10,10 @@
 // b = 1 for the body centre (i + 1/2, j + 1/2, k + 1/2) a.  The nearest site
 // of a point is the nearer of its nearest corner (coordinates rounded) and
 // its nearest body centre (coordinates floored, plus one half): each
-// sublattice is simple cubic.  Exact ties go to the corner.
+// sublattice is simple cubic.  Exact ties go to the lowest site id: along an
+// axis where a coordinate lies exactly halfway between two sites of a
+// sublattice the lower (wrapped) index is taken (the id grows with each
+// index), and between equidistant corner and body sites the lower id.
 #include "nep_device.h"
 
 namespace nep {
@@ -72,16 +75,21 @@ __global__ void k_ws_assign(int n_atoms, const double *__restrict__ x, const dou
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double s = pos[a] * r.inv_a;            // lattice units, not wrapped
-        const double c = rint(s), b = floor(s) + 0.5;
-        const double dc = (s - c) * r.a, db = (s - b) * r.a;
+        const double fl = floor(s), f = s - fl;
+        // nearest corner: fl or fl + 1 (both when f is exactly 1/2)
+        const double c = f < 0.5 ? fl : fl + 1.0;
+        const double dc = (s - c) * r.a, db = (f - 0.5) * r.a;
         dc2 += dc * dc;
         db2 += db * db;
-        ci[a] = wrap_index((int)c, r.n[a]);
-        bi[a] = wrap_index((int)floor(s), r.n[a]);
+        const int c0 = wrap_index((int)fl, r.n[a]), c1 = wrap_index((int)fl + 1, r.n[a]);
+        ci[a] = f == 0.5 ? min(c0, c1) : (f < 0.5 ? c0 : c1);
+        // nearest body centre: fl + 1/2, or also fl - 1/2 when s is an integer
+        const int b1 = wrap_index((int)fl - 1, r.n[a]);
+        bi[a] = f == 0.0 ? min(c0, b1) : c0;
     }
-    const bool corner = dc2 <= db2;
-    const int *g = corner ? ci : bi;
-    const int site = 2 * ((g[2] * r.n[1] + g[1]) * r.n[0] + g[0]) + (corner ? 0 : 1);
+    const int cid = 2 * ((ci[2] * r.n[1] + ci[1]) * r.n[0] + ci[0]);
+    const int bid = 2 * ((bi[2] * r.n[1] + bi[1]) * r.n[0] + bi[0]) + 1;
+    const int site = dc2 < db2 ? cid : (db2 < dc2 ? bid : min(cid, bid));
     atomicAdd(&occ[site], 1);
     if (site_of) site_of[t] = site;
 }

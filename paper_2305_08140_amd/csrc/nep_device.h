@@ -91,10 +91,13 @@ struct CellGeom {
 
 // ---------------------------------------------------------------- status word
 // status[0]: latched error code (0 = none); status[1], status[2]: required
-// angular / radial list lengths seen by the last build.
+// angular / radial list lengths seen by the last build; status[3]: nonzero
+// while the lists are unusable (the last build ended with an error, so the
+// lists may be truncated and the reverse index unwritten).
 constexpr int ST_ERR = 0;
 constexpr int ST_NEED_A = 1;
 constexpr int ST_NEED_R = 2;
+constexpr int ST_LBAD = 3;
 
 // velocity-Verlet state (doubles): step length (fs), max |v|^2, max
 // displacement^2 since the last build (both as ordered bit patterns of
@@ -114,6 +117,20 @@ constexpr int MD_WORDS = 32;
 __device__ inline void latch_error(int *status, int code)
 {
     atomicCAS(status + ST_ERR, 0, code);
+}
+
+// Entry check of the kernels that walk the neighbour lists: true if they
+// must do nothing, either because an error is latched or because the lists
+// are unusable (then NEP_E_STATE is latched, so the call reports an error
+// instead of numbers computed on truncated lists).
+__device__ inline bool lists_blocked(int *status)
+{
+    if (status[ST_ERR] != 0) return true;
+    if (status[ST_LBAD] != 0) {
+        latch_error(status, -7);
+        return true;
+    }
+    return false;
 }
 
 // ---------------------------------------------------------------- fast math

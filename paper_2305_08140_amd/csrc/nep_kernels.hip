@@ -603,7 +603,7 @@ __global__ __launch_bounds__(BS, NNMODE == 1 ? 1 : 2) void k_descriptor(
 {
     __shared__ NNLds lds[NNMODE != 0 ? BS / 64 : 1];
     NNLds *L = &lds[NNMODE != 0 ? threadIdx.x / 64 : 0];
-    if (status[ST_ERR] != 0) return;
+    if (lists_blocked(status)) return;
     if (PERSISTENT) {
         for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
             const int t = tile * BS + threadIdx.x;
@@ -777,7 +777,7 @@ __global__ __launch_bounds__(BS) void k_force(
     const int32_t *__restrict__ perm, float *__restrict__ fx, float *__restrict__ fy,
     float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status, int ntiles)
 {
-    if (status[ST_ERR] != 0) return;
+    if (lists_blocked(status)) return;
     if (PERSISTENT) {
         for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
             const int t = tile * BS + threadIdx.x;
@@ -868,14 +868,14 @@ __global__ __launch_bounds__(64) void k_param_grad(
     PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt, const float *__restrict__ P,
-    const double *__restrict__ C64, const double *__restrict__ gE, double *__restrict__ part, const int32_t *__restrict__ status, int ntiles)
+    const double *__restrict__ C64, const double *__restrict__ gE, double *__restrict__ part, int32_t *__restrict__ status, int ntiles)
 {
     __shared__ float rec[PG_TILE][PG_REC];
     __shared__ float tsum[PS_N];
     constexpr int NOWN = (NPARAM + PG_TILE - 1) / PG_TILE;
     const int lane = threadIdx.x;
     double *pb = part + (size_t)blockIdx.x * NPARAM;   // this block's partials, added tile by tile
-    const bool ok = status[ST_ERR] == 0;
+    const bool ok = !lists_blocked(status);
     for (int k = 0; k < NOWN; ++k) {
         const int o = lane + PG_TILE * k;
         if (o < NPARAM) pb[o] = 0.0;
@@ -1285,7 +1285,7 @@ __global__ __launch_bounds__(POP_DESC_BS, 2) void k_pop_descriptor(
     int32_t *__restrict__ status, int ntiles, int n_pop)
 {
     __shared__ NNLds lds[1];
-    if (status[ST_ERR] != 0) return;
+    if (lists_blocked(status)) return;
     int m, tile;
     if (!pop_item(ntiles, n_pop, m, tile)) return;
     const int t = tile * POP_DESC_BS + threadIdx.x;
@@ -1305,7 +1305,7 @@ __global__ __launch_bounds__(256) void k_pop_force(
     const int32_t *__restrict__ perm, float *__restrict__ F, float *__restrict__ w_atom,
     int32_t *__restrict__ status, int ntiles, int n_pop)
 {
-    if (status[ST_ERR] != 0) return;
+    if (lists_blocked(status)) return;
     int m, tile;
     if (!pop_item(ntiles, n_pop, m, tile)) return;
     const int t = tile * 256 + threadIdx.x;

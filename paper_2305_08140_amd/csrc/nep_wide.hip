@@ -68,7 +68,7 @@ __global__ __launch_bounds__(WBS) void k_w_radial(
     double *__restrict__ e_atom, int32_t *__restrict__ status)
 {
     const int t = tile_atom(pc.n);
-    if (t >= pc.n || status[ST_ERR] != 0) return;
+    if (t >= pc.n || lists_blocked(status)) return;
     const double4 pi = xq[t];
     const CellGeom *cg = cells + cell_of[t];
     const int base = cg->atom_start;
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(WBS_F) void k_w_force(
     float *__restrict__ fy, float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status)
 {
     const int t = tile_atom<WBS_F>(pc.n);
-    if (t >= pc.n || status[ST_ERR] != 0) return;
+    if (t >= pc.n || lists_blocked(status)) return;
     const double xi = xw[t].x, yi = xw[t].y, zi = xw[t].z;
     const CellGeom *cg = cells + cell_of[t];
     const int base = cg->atom_start;

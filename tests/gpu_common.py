@@ -13,6 +13,13 @@ E_ATOM_TOL = 1e-6     # |E - E_ref| / N  (eV/atom), per cell
 # ||W - W_ref||_F <= 1e-5 ||W_ref||_F + 1e-6 N  (eV).
 W_REL_TOL = 1e-5
 W_ATOM_TOL = 1e-6
+# Per atom: |F_i - F_ref_i| <= F_ATOM_TOL max(|F_ref_i|, RMS |F_ref|) (an
+# atom's FP32 error is set by its ~60 pair terms, not by its net force, so
+# atoms whose net force is far below the RMS are measured against the RMS).
+F_ATOM_TOL = 5e-5
+# Site energies U_i of atoms in no pair closer than the ZBL outer radius
+# (the network output in FP32 on FP64-accurate descriptors), eV.
+U_SITE_TOL = 1e-6
 
 
 def gpu_available():
@@ -33,6 +40,27 @@ def force_errors(F, Fref, exclude=None):
     m = np.ones(F.shape[0], bool)
     m[list(exclude)] = False
     return e_all, np.linalg.norm(F[m] - Fref[m]) / np.linalg.norm(Fref[m])
+
+
+def atom_force_error(F, Fref):
+    """max_i |F_i - F_ref_i| / max(|F_ref_i|, RMS |F_ref|)."""
+    nref = np.linalg.norm(Fref, axis=1)
+    rms = np.sqrt(np.mean(nref ** 2))
+    return float(np.max(np.linalg.norm(F - Fref, axis=1) / np.maximum(nref, rms)))
+
+
+def zbl_atoms_system(s, r2=2.0):
+    """Atoms (global indices) of a multi-cell system in a pair closer than r2."""
+    import oracle
+    out = set()
+    for c in range(s.n_cells):
+        a, b = int(s.cell_start[c]), int(s.cell_start[c + 1])
+        pbc = tuple(getattr(s, "pbc", (1, 1, 1)))
+        start, j, n, r = oracle.pairs(s.pos[a:b], s.h[c], pbc, r2, method=0 if b - a < 3000 else 1)
+        for i in range(b - a):
+            if start[i + 1] > start[i]:
+                out.add(a + i)
+    return out
 
 
 def zbl_atoms(pos, h, r2=2.0):

@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -100,3 +101,22 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "sizeof")] == C.sizeof(py), cname
         for f in py._fields_:
             assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
+
+
+def test_split_theta_follows_the_model_layout():
+    # the flat parameter vector is split by the context's model sizes: the
+    # default model (1057 values) and the paper-size one (16/11 functions on
+    # 16/11 Chebyshev terms, 60 descriptors, 100 neurons)
+    import torch
+    from paper_2305_08140_amd.autograd import split_theta
+    import nep_synth
+    for m in (nep_synth.random_model(), nep_synth.random_model(size="paper")):
+        dim = m.n_rad + m.n_ang * m.l_max
+        sizes = (m.n_rad * m.k_rad, m.n_ang * m.k_ang, m.n_hidden * dim, m.n_hidden, m.n_hidden, 1)
+        theta = torch.tensor(m.param_vector())
+        parts = split_theta(theta, sizes)
+        for got, want in zip(parts, (m.c_rad, m.c_ang, m.w0, m.b0, m.w1)):
+            assert np.array_equal(got.numpy(), np.asarray(want, dtype=theta.numpy().dtype).ravel())
+        assert float(parts[5]) == float(np.asarray(m.b1, dtype=theta.numpy().dtype))
+        with pytest.raises(ValueError):
+            split_theta(theta[:-1], sizes)

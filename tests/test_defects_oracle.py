@@ -91,3 +91,25 @@ def test_frenkel_pairs_conserve_atoms():
     assert int(r["occupancy"].sum()) == pos.shape[0]
     assert r["n_vacancies"] - r["n_interstitials"] == M - pos.shape[0]
     assert 0 < r["n_vacancies"] <= 7
+
+
+def test_exact_ties_go_to_the_lowest_site_id():
+    # with a = 4 A every distance below is exact; the expected sites are the
+    # lowest ids among the equidistant ones, listed by hand
+    n = (6, 5, 4)
+    a = 4.0
+
+    def sid(i, j, k, b):
+        return 2 * ((k * n[1] + j) * n[0] + i) + b
+
+    cases = [
+        ((2.0, 0.0, 0.0), sid(0, 0, 0, 0)),
+        ((4.0 * n[0] - 2.0, 0.0, 0.0), sid(0, 0, 0, 0)),
+        ((1.0, 1.0, 1.0), sid(0, 0, 0, 0)),
+        ((3.0, 3.0, 3.0), sid(0, 0, 0, 1)),
+        ((8.0, 6.0, 6.0), sid(1, 1, 1, 1)),
+        ((0.0, 6.0, 6.0), sid(0, 1, 1, 1)),
+    ]
+    pos = np.array([p for p, _ in cases])
+    got = D.nearest_sites(pos, a, n)
+    assert got.tolist() == [w for _, w in cases]

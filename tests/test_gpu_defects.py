@@ -130,3 +130,34 @@ def test_large_cascade_sampled():
                             best, bd = sid, dd
         assert sgot == best
     print(f"[defects large] vacancies {g['n_vacancies']} interstitials {g['n_interstitials']}", flush=True)
+
+
+def _tie_points(n):
+    """Points exactly equidistant from two or more sites of the bcc lattice
+    with a = 4 A (every coordinate and distance exact in binary)."""
+    pts = [
+        (2.0, 0.0, 0.0),            # corners (0,0,0) / (1,0,0)
+        (4.0 * n - 2.0, 0.0, 0.0),  # corners (n-1,0,0) / (0,0,0) across the face
+        (2.0, 2.0 + 8.0, 0.0),      # four corners
+        (1.0, 1.0, 1.0),            # corner (0,0,0) / body (0,0,0): corner has the lower id
+        (3.0, 3.0, 3.0),            # corner (1,1,1) / body (0,0,0): body has the lower id
+        (8.0, 6.0, 6.0),            # bodies (1,1,1) / (2,1,1) (x on a corner plane) and corner ties
+        (0.0, 6.0, 6.0),            # bodies (n-1,1,1) / (0,1,1) across the face
+        (12.0, 2.0, 2.0),           # bodies (2,0,0) / (3,0,0), corners (3,0,0)/(3,1,0)/(3,0,1)/(3,1,1)
+    ]
+    return np.array(pts, dtype=np.float64)
+
+
+def test_exact_ties_go_to_the_lowest_site_id():
+    import paper_2305_08140_amd as nep
+    n = (6, 5, 4)
+    a = 4.0
+    pos = _tie_points(n[0])
+    h = np.diag([n[0] * a, n[1] * a, n[2] * a])
+    s = nep_synth._single(pos, h)
+    g = nep.wigner_seitz(nep.DeviceSystem.from_synth(s), a, n, capacity=4096, site_of_atom=True)
+    r = D.wigner_seitz(pos, a, n)
+    got = g["site_of_atom"].cpu().numpy()
+    print("[ws ties] gpu", got.tolist(), "oracle", r["assign"].tolist(), flush=True)
+    assert np.array_equal(got, r["assign"])
+    assert np.array_equal(g["occupancy"].cpu().numpy(), r["occupancy"])

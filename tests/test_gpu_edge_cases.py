@@ -27,6 +27,17 @@ def test_list_capacity_overflow_is_reported_then_recovered():
     with pytest.raises(nep.NepError) as e:
         small.nep_build_neighbors(sysd)
     assert e.value.code == nep.NEP_E_NEIGH_OVERFLOW
+    # the error was reported (and cleared); the truncated lists stay unusable:
+    # an evaluation on them reports an error instead of returning numbers
+    out_small = nep.EFV(s.n_atoms, 1)
+    for _ in range(2):
+        with pytest.raises(nep.NepError) as e:
+            small.nep_compute_efv(sysd, out_small)
+        assert e.value.code == nep.NEP_E_STATE
+    # and an MD chunk on them rebuilds first (overflowing again)
+    with pytest.raises(nep.NepError) as e:
+        small.nep_step_verlet(sysd, 1, out_small, dt_max=1.0, forces_valid=True)
+    assert e.value.code == nep.NEP_E_NEIGH_OVERFLOW
     need_a, need_r = small.nep_required_neighbors()
     # bcc within 5 A and between 5 and 7 A, plus thermal spread
     assert 26 <= need_a <= 40 and 55 <= need_r <= 80

@@ -4,8 +4,9 @@ import pytest
 
 import nep_synth
 import oracle
-from gpu_common import (E_ATOM_TOL, F_REL_TOL, W_ATOM_TOL, W_REL_TOL, force_errors, gpu_available,
-                        model, run_gpu, zbl_atoms)
+from gpu_common import (E_ATOM_TOL, F_ATOM_TOL, F_REL_TOL, U_SITE_TOL, W_ATOM_TOL, W_REL_TOL,
+                        atom_force_error, force_errors, gpu_available, model, run_gpu, zbl_atoms,
+                        zbl_atoms_system)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
@@ -20,9 +21,21 @@ def _compare(s, m, ref, res, zbl=None, label=""):
         dW = np.linalg.norm(res["virial"][c] - ref["virial"][c])
         assert dW <= W_REL_TOL * np.linalg.norm(ref["virial"][c]) + W_ATOM_TOL * n_c, (label, c, dW)
     e_all, e_rest = force_errors(res["forces"], ref["forces"], zbl)
-    print(f"[{label}] force rel err all={e_all:.3e} non-ZBL={e_rest:.3e}", flush=True)
+    e_atom = atom_force_error(res["forces"], ref["forces"])
+    if zbl is None:
+        zbl = zbl_atoms_system(s)
+    far = np.ones(N, bool)
+    far[list(zbl)] = False
+    dU = np.abs(res["energy_atom"] - ref["energy_atom"])
+    du_far = float(dU[far].max()) if far.any() else 0.0
+    print(f"[{label}] force rel err all={e_all:.3e} non-ZBL={e_rest:.3e} per-atom max={e_atom:.3e}; "
+          f"site energy max err {du_far:.2e} eV (no ZBL pair), {dU.max():.2e} eV (all)", flush=True)
     assert e_all <= F_REL_TOL and e_rest <= F_REL_TOL
-    assert np.abs(res["energy_atom"] - ref["energy_atom"]).max() <= 1e-4 * max(1.0, np.abs(ref["energy_atom"]).max())
+    assert e_atom <= F_ATOM_TOL
+    # site energies: absolute bound away from the ZBL pairs, relative to the
+    # (FP64) ZBL half energies on the atoms of those pairs
+    assert du_far <= U_SITE_TOL
+    assert np.all(dU[~far] <= U_SITE_TOL + 1e-7 * np.abs(ref["energy_atom"][~far]))
 
 
 def test_tiny_matches_oracle():
