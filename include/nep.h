@@ -284,6 +284,24 @@ int nep_backward(nep_ctx *ctx, const nep_system *sys, const nep_efv *out, const 
                  double *grad_params, double *grad_x, double *grad_y, double *grad_z, double *grad_h,
                  void *stream);
 
+/* nep_backward for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, preconditions, results (bit for bit) and errors as
+ * nep_backward, and it calls no allocating routine.  The block partials live
+ * in one file-scope device array per GPU instead of the context: 1024 rows of
+ * nep_num_params doubles (8.7 MB), the most any launch uses, so every system
+ * the context accepts fits (NEP_E_CAPACITY would report a launch wider than
+ * the array).  The array's address on a GPU is resolved by nep_create with
+ * that GPU current and held until the process ends.  All calls on one GPU
+ * share the array, which keeps the last call's partials (each call zeroes
+ * the rows it uses before adding to them): two calls that overlap in time on
+ * the same GPU, on different streams or from different threads, race and
+ * give wrong gradients; serialise them.  The default model only
+ * (NEP_E_UNSUPPORTED for the paper-size model, as nep_backward). */
+int nep_backward_noalloc(nep_ctx *ctx, const nep_system *sys, const nep_efv *out, const double *gE,
+                         double *grad_params, double *grad_x, double *grad_y, double *grad_z,
+                         double *grad_h, void *stream);
+
 /* Measurement support: run the evaluation path of nep_compute_efv `reps`
  * times, each kernel bracketed by HIP events recorded on `stream`, and return
  * the mean duration per launch in milliseconds:

@@ -37,7 +37,7 @@ PAPER_LAMBDAS = {"e": 1.0, "f": 1.0, "v": 0.1, "l1": 0.05, "l2": 0.05}
 
 EXPORTED = ("nep_create", "nep_destroy", "nep_set_weights", "nep_build_neighbors", "nep_compute_efv",
             "nep_step_verlet", "nep_status", "nep_required_neighbors", "nep_mean_neighbors",
-            "nep_time_efv", "nep_num_params", "nep_backward", "nep_compute_efv_graph", "nep_autotune",
+            "nep_time_efv", "nep_num_params", "nep_backward", "nep_backward_noalloc", "nep_compute_efv_graph", "nep_autotune",
             "nep_set_precision", "nep_wigner_seitz", "nep_population_reserve", "nep_population_efv",
             "nep_snes_sample", "nep_snes_update", "nep_strerror")
 
@@ -135,6 +135,7 @@ def lib():
         L.nep_compute_efv_graph.argtypes = [P, C.POINTER(System), C.POINTER(Efv), P]
         L.nep_autotune.argtypes = [P, C.POINTER(System), C.POINTER(Efv), C.c_int32, C.POINTER(C.c_int32), P]
         L.nep_backward.argtypes = [P, C.POINTER(System), C.POINTER(Efv), P, P, P, P, P, P, P]
+        L.nep_backward_noalloc.argtypes = [P, C.POINTER(System), C.POINTER(Efv), P, P, P, P, P, P, P]
         L.nep_wigner_seitz.argtypes = [C.POINTER(System), C.POINTER(BccRef), P, P, C.c_int32, P, P, P, P, P, P,
                                        C.POINTER(Defects), P]
         L.nep_population_reserve.argtypes = [P, C.c_int32]
@@ -415,20 +416,37 @@ class Context:
 
     def nep_backward(self, system: DeviceSystem, out: EFV, gE, grad_pos=True, grad_cell=True, stream=None):
         """dL/dtheta [P], dL/dx [N,3] and dL/dh [C,3,3] for L = sum_c gE[c] E_c (device FP64 tensors)."""
+        return self._backward("nep_backward", system, out, gE, grad_pos, grad_cell, stream, None)
+
+    def nep_backward_noalloc(self, system: DeviceSystem, out: EFV, gE, grad_pos=True, grad_cell=True,
+                             stream=None, outputs=None):
+        """nep_backward through the library's allocation-free entry point.  `outputs`, if given, is a
+        dict of preallocated device FP64 tensors {"params": [P], "x", "y", "z": [N], "h": [C, 9]}
+        (so that the call allocates nothing at all); otherwise they are allocated here."""
+        return self._backward("nep_backward_noalloc", system, out, gE, grad_pos, grad_cell, stream, outputs)
+
+    def _backward(self, name, system, out, gE, grad_pos, grad_cell, stream, outputs):
         torch = _torch()
         dev = out.fx.device
         gE = gE.to(device=dev, dtype=torch.float64).contiguous()
-        gp = torch.empty(self.nep_num_params(), dtype=torch.float64, device=dev)
+        outputs = outputs or {}
+        gp = outputs.get("params")
+        if gp is None:
+            gp = torch.empty(self.nep_num_params(), dtype=torch.float64, device=dev)
         gx = gy = gz = gh = None
         if grad_pos:
-            gx, gy, gz = (torch.empty(system.n_atoms, dtype=torch.float64, device=dev) for _ in range(3))
+            gx, gy, gz = (outputs.get(k) for k in ("x", "y", "z"))
+            if gx is None or gy is None or gz is None:
+                gx, gy, gz = (torch.empty(system.n_atoms, dtype=torch.float64, device=dev) for _ in range(3))
         if grad_cell:
-            gh = torch.empty(system.n_cells, 9, dtype=torch.float64, device=dev)
+            gh = outputs.get("h")
+            if gh is None:
+                gh = torch.empty(system.n_cells, 9, dtype=torch.float64, device=dev)
         s = system.c_struct()
         o = out.c_struct()
         ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
-        _check(lib().nep_backward(self._ptr, C.byref(s), C.byref(o), ptr(gE), ptr(gp), ptr(gx), ptr(gy), ptr(gz),
-                                  ptr(gh), _stream_ptr(stream)), "nep_backward")
+        _check(getattr(lib(), name)(self._ptr, C.byref(s), C.byref(o), ptr(gE), ptr(gp), ptr(gx), ptr(gy),
+                                    ptr(gz), ptr(gh), _stream_ptr(stream)), name)
         if self.check:
             self.nep_status(stream)
         gpos = torch.stack([gx, gy, gz], dim=1) if grad_pos else None

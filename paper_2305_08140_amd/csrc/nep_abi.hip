@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "nep.h"
@@ -232,6 +233,39 @@ static void inv3(const double *h, double *hi)
     hi[6] = (d * k - e * g) / det; hi[7] = (b * g - a * k) / det; hi[8] = (a * e - b * d) / det;
 }
 
+static constexpr int N_PARAMS = NR * KB + NA * KB + NH * DIM + NH + NH + 1;
+
+// Allocation-free backward: the parameter-gradient block partials live in a
+// file-scope device array instead of the context.  It holds the partials of
+// the widest launch the backward makes (PG_MAX_BLOCKS rows of N_PARAMS
+// doubles, 8.7 MB), so every system a context accepts fits.  Each device
+// keeps its own copy until the process ends; host code reaches it only
+// through the address resolved per device below, never through the name.
+static constexpr int PG_MAX_BLOCKS = 1024;
+static __device__ __align__(256) double scratch[PG_MAX_BLOCKS * N_PARAMS];
+static constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// The scratch address on `dev`, resolved once per device; the first call for
+// a device must run with that device current (nep_create does it).
+static int scratch_address(int dev, double **p)
+{
+    *p = nullptr;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return NEP_E_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) return NEP_E_HIP;
+        if (cur != dev) return NEP_E_ARG;
+        void *q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return NEP_E_HIP;
+        g_scratch_ptr[dev] = (double *)q;
+    }
+    *p = g_scratch_ptr[dev];
+    return NEP_OK;
+}
+
 extern "C" {
 
 const char *nep_strerror(int code)
@@ -309,6 +343,12 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     c->cfg = *cfg;
     c->wide = wide;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return NEP_E_HIP; }
+    if (!wide) {
+        // the allocation-free backward's scratch address on this device
+        double *sp = nullptr;
+        const int src = scratch_address(c->device, &sp);
+        if (src != NEP_OK) { delete c; return src; }
+    }
     const size_t N = (size_t)cfg->max_atoms;
     bool ok = true;
     auto A = [&](void **p, size_t bytes) {
@@ -839,7 +879,6 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
     return NEP_OK;
 }
 
-static constexpr int N_PARAMS = NR * KB + NA * KB + NH * DIM + NH + NH + 1;
 
 int nep_set_precision(nep_ctx *c, int32_t mode)
 {
@@ -856,8 +895,9 @@ int nep_num_params(const nep_ctx *c)
     return N_PARAMS;
 }
 
-int nep_backward(nep_ctx *c, const nep_system *s, const nep_efv *o, const double *gE, double *grad_params,
-                 double *gx, double *gy, double *gz, double *gh, void *stream)
+static int backward_checks(nep_ctx *c, const nep_system *s, const nep_efv *o, const double *gE,
+                           const double *grad_params, const double *gx, const double *gy, const double *gz,
+                           const double *gh)
 {
     if (!c || !gE || !grad_params) return NEP_E_ARG;
     if (c->wide) return NEP_E_UNSUPPORTED;
@@ -867,27 +907,58 @@ int nep_backward(nep_ctx *c, const nep_system *s, const nep_efv *o, const double
     if ((gx || gy || gz) && !(gx && gy && gz)) return NEP_E_ARG;
     if (gh && !o->virial) return NEP_E_ARG;
     if (!same_system(c, s)) return NEP_E_STATE;
-    hipStream_t st = (hipStream_t)stream;
+    return NEP_OK;
+}
+
+// The backward's launches, with `part` holding at least `blocks` partial rows.
+static int backward_launch(nep_ctx *c, const nep_system *s, const nep_efv *o, const double *gE,
+                           double *grad_params, double *gx, double *gy, double *gz, double *gh, double *part,
+                           int blocks, int tiles, hipStream_t st)
+{
     const int n = (int)s->n_atoms;
-    const int tiles = (n + 63) / 64;
-    const int blocks = std::min(tiles, 1024);
-    if (blocks > c->pg_blocks) {
-        if (c->pg_part) (void)hipFree(c->pg_part);
-        c->pg_part = nullptr;
-        HIP_TRY(hipMalloc(&c->pg_part, (size_t)blocks * N_PARAMS * sizeof(double)));
-        c->pg_blocks = blocks;
-    }
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
                                                        c->cells, c->xq, c->status, nullptr);
     k_param_grad<<<blocks, 64, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
-                                        c->params, c->c64, gE, c->pg_part, c->status, tiles);
-    k_param_reduce<<<(N_PARAMS + 31) / 32, 256, 0, st>>>(blocks, c->pg_part, grad_params);
+                                        c->params, c->c64, gE, part, c->status, tiles);
+    k_param_reduce<<<(N_PARAMS + 31) / 32, 256, 0, st>>>(blocks, part, grad_params);
     if (gx) k_grad_pos<<<grid_for(n, 256), 256, 0, st>>>(n, c->cell_of, gE, o->fx, o->fy, o->fz, gx, gy, gz);
     if (gh)
         k_grad_cell<<<c->built_cells, 256, 0, st>>>(c->cells, s->x, s->y, s->z, o->fx, o->fy, o->fz, o->virial,
                                                     gE, gh);
     HIP_TRY(hipGetLastError());
     return NEP_OK;
+}
+
+int nep_backward(nep_ctx *c, const nep_system *s, const nep_efv *o, const double *gE, double *grad_params,
+                 double *gx, double *gy, double *gz, double *gh, void *stream)
+{
+    int rc = backward_checks(c, s, o, gE, grad_params, gx, gy, gz, gh);
+    if (rc) return rc;
+    const int tiles = (int)((s->n_atoms + 63) / 64);
+    const int blocks = std::min(tiles, PG_MAX_BLOCKS);
+    if (blocks > c->pg_blocks) {
+        if (c->pg_part) (void)hipFree(c->pg_part);
+        c->pg_part = nullptr;
+        HIP_TRY(hipMalloc(&c->pg_part, (size_t)blocks * N_PARAMS * sizeof(double)));
+        c->pg_blocks = blocks;
+    }
+    return backward_launch(c, s, o, gE, grad_params, gx, gy, gz, gh, c->pg_part, blocks, tiles,
+                           (hipStream_t)stream);
+}
+
+int nep_backward_noalloc(nep_ctx *c, const nep_system *s, const nep_efv *o, const double *gE,
+                         double *grad_params, double *gx, double *gy, double *gz, double *gh, void *stream)
+{
+    int rc = backward_checks(c, s, o, gE, grad_params, gx, gy, gz, gh);
+    if (rc) return rc;
+    const int tiles = (int)((s->n_atoms + 63) / 64);
+    const int blocks = std::min(tiles, PG_MAX_BLOCKS);
+    if (blocks > PG_MAX_BLOCKS) return NEP_E_CAPACITY;
+    double *part = nullptr;
+    if ((rc = scratch_address(c->device, &part))) return rc;
+    // every block zeroes its own rows before adding to them, so the rows a
+    // previous call left behind need no clearing
+    return backward_launch(c, s, o, gE, grad_params, gx, gy, gz, gh, part, blocks, tiles, (hipStream_t)stream);
 }
 
 int nep_autotune(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, int32_t *shape_out, void *stream)
