@@ -29,24 +29,29 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (256 CUs x 2.4 GHz x 256 
 PEAK_HBM_GBS = 8000.0
 
 
-def flops_per_atom(n_rad: float, n_ang: float):
-    """Algorithmic flops per atom of the two evaluation kernels for this model
-    (9 radial + 5x4 angular descriptors, Chebyshev k = 0..8, 30 tanh neurons),
-    counted on the minimal formulation: FMA = 2, any other arithmetic
-    operation and each sqrt / reciprocal / cos / sin / tanh = 1.
-    n_rad, n_ang: neighbours inside the radial (6 A) and angular (4 A) cutoffs.
+def flops_per_atom(n_rad: float, n_ang: float, kr: int = 9, nr: int = 9, ka: int = 9, na: int = 5, nh: int = 30):
+    """Algorithmic flops per atom of the evaluation, split into its descriptor
+    side and its force kernel, counted on the minimal formulation: FMA = 2, any
+    other arithmetic operation and each sqrt / reciprocal / cos / sin / tanh = 1.
+    n_rad, n_ang: neighbours inside the radial (6 A) and angular (4 A) cutoffs;
+    kr, ka: Chebyshev basis sizes; nr radial descriptors; na angular channels
+    (l = 1..4, 24 harmonics); nh hidden neurons.  The defaults are the 8.2M-atom
+    workload's model (9 + 5 x 4 descriptors, k = 0..8, 30 neurons); the
+    paper-size model of Sec. III.A is kr = nr = 16, ka = na = 11, nh = 100.
 
-    descriptor kernel: descriptor, network forward + backward, adjoints, and
+    descriptor side: descriptor, network forward + backward, adjoints, and
       the gradient of U_i with respect to every angular pair vector;
     force kernel: radial + ZBL pair forces of both ends, the assembly of the
       angular pair gradients, and the virial."""
-    geom = 9                                         # r_ij (3), r^2 (5), sqrt (1)
-    rad_fwd = geom + 3 + 3 + 3 + 14 + 18             # t, fc, x, T_2..T_8, sum fc T_k
-    ang_fwd = 23 + 100 + 4 + 60 + 240                # basis, g_n, u, Y_lm, s += g Y
-    per_atom = 180 + 240 + 1900 + 1830 + 162 + 240   # q_n, q_nl, network fwd, bwd, a_k, B
-    ang_grad = geom + 1 + 56 + 210 + 60 + 480 + 48 + 150 + 20 + 3 + 18   # one pair gradient
+    dim = nr + 4 * na
+    geom = 9                                                     # r_ij (3), r^2 (5), sqrt (1)
+    rad_fwd = geom + 9 + 2 * (kr - 2) + 2 * kr                   # t, fc, x, T_2.., sum fc T_k
+    ang_fwd = 9 + 2 * (ka - 2) + na * (2 * ka + 2) + 4 + 60 + 48 * na   # basis, g_n, u, Y_lm, s += g Y
+    per_atom = (2 * nr * kr + 2 * nr) + 48 * na + (nh * (2 * dim + 5) + 10) + nh * (2 * dim + 3) \
+        + 2 * nr * kr + 48 * na                                  # q_n, q_nl, network fwd (+ output), bwd, a_k, B
+    ang_grad = geom + 1 + (14 + 6 * (ka - 2)) + na * (4 * ka + 6) + 60 + 96 * na + 48 + 150 + 20 + 3 + 18
     desc = rad_fwd * n_rad + ang_fwd * n_ang + per_atom + ang_grad * n_ang
-    rad_pair = geom + 1 + 3 + 6 + 3 + 14 + 28 + 2 + 9 + 36 + 9 + 6 + 3 + 18 + 3
+    rad_pair = 54 + 6 * (kr - 2) + 6 * kr
     force = rad_pair * n_rad + 3 * n_ang + 20
     return desc, force
 
@@ -273,11 +278,19 @@ def bench_paper_model(args, s, N):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kt = ctx.nep_time_efv(sysd, out, reps=3)
+    n_rad, n_ang = ctx.nep_mean_neighbors()
+    f_desc, f_force = flops_per_atom(n_rad, n_ang, kr=16, nr=16, ka=11, na=11, nh=100)
+    roof = {}
+    for part, f, ms in (("descriptor_phases", f_desc, kt["descriptor"]), ("force", f_force, kt["force"])):
+        ach = f * N / (ms * 1e-3) / 1e12
+        roof[part] = {"bound": "alu", "flop_per_atom": f, "ms": ms, "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                      "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS}
     idx = np.sort(np.random.default_rng(0).choice(N, size=256, replace=False))
     check = {"model": pm, "pos": sysd.positions().cpu().numpy(), "h": s.h[0], "pbc": (1, 1, 1), "idx": idx,
              "F": out.forces().cpu().numpy().astype(np.float64)[idx]}
     res = {"atom_steps_per_s": N * args.paper_steps / wall, "ms_per_step": wall / args.paper_steps * 1e3,
-           "steps": args.paper_steps, "kernels_ms": kt, "force_rel_err_vs_fp64_thermal_atoms": None,
+           "steps": args.paper_steps, "kernels_ms": kt, "roofline": roof,
+           "force_rel_err_vs_fp64_thermal_atoms": None,
            "paper_a100_atom_steps_per_s": 1.3e7}
     del ctx, out, sysd
     torch.cuda.empty_cache()

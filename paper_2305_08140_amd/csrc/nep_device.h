@@ -243,6 +243,27 @@ __host__ __device__ inline void cheb_d(float x, float T[KB], float dT[KB])
     }
 }
 
+// T_k and dT_k/dx evaluated in double precision from x, rounded to single
+// (near x = -1 the recurrences amplify a rounding of x by up to k^2 in T_k
+// and k^4 in dT_k, so x must not be rounded before them).
+__host__ __device__ inline void cheb_d_from_d(double x, float T[KB], float dT[KB])
+{
+    double t2 = 1.0, t1 = x, d2 = 0.0, d1 = 1.0;
+    T[0] = 1.0f;
+    T[1] = (float)x;
+    dT[0] = 0.0f;
+    dT[1] = 1.0f;
+    const double x2 = 2.0 * x;
+#pragma unroll
+    for (int k = 2; k < KB; ++k) {
+        const double t = fma(x2, t1, -t2);
+        const double d = fma(x2, d1, fma(2.0, t1, -d2));
+        T[k] = (float)t;
+        dT[k] = (float)d;
+        t2 = t1; t1 = t; d2 = d1; d1 = d;
+    }
+}
+
 // ---------------------------------------------------------------- harmonics
 // Real spherical harmonics scaled by sqrt(4 pi / (2l+1)), so that
 // sum_m Y_lm(u) Y_lm(v) = P_l(u.v) (addition theorem).  Index lm = l^2 - 1 + (m + l).

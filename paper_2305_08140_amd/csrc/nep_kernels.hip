@@ -525,14 +525,19 @@ __device__ __forceinline__ void descriptor_atom(
             if (r2 < pc.rc_ang2_write) pair_grad[off] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             continue;
         }
-        const float r = fsqrt(r2);
+        // distance and Chebyshev argument from the FP64 pair vector (a
+        // rounded x would be amplified by up to k^2 and k^4 near x = -1, where
+        // the outer neighbour shells sit)
+        const double rd = dist_d(ddx * ddx + ddy * ddy + ddz * ddz);
+        const double ttd = rd * (1.0 / (double)pc.rc_ang) - 1.0;
+        const float r = (float)rd;
         const float rinv = frcp(r);
-        const float tt = scaled_minus_one(r, pc.inv_rc_ang, pc.inv_rc_ang_lo);
+        const float tt = (float)ttd;
         float fc, dfc;
         cutoff(tt, pc.inv_rc_ang, fc, dfc);
         const float dxdr = 4.0f * tt * pc.inv_rc_ang;
         float T[KB], dT[KB];
-        cheb_d(fmaf(2.0f * tt, tt, -1.0f), T, dT);
+        cheb_d_from_d(fma(2.0 * ttd, ttd, -1.0), T, dT);
         float g[NA], gp[NA];
         const float hfc = 0.5f * fc, hdx = hfc * dxdr, hdfc = 0.5f * dfc;
 #pragma unroll
@@ -622,6 +627,66 @@ __global__ __launch_bounds__(BS, NNMODE == 1 ? 1 : 2) void k_descriptor(
 
 // ------------------------------------------------------------------ forces + virial
 
+// Radial + ZBL force of one pair from its FP64 pair vector d = r_j - r_i and
+// both ends' radial adjoints: (a^i + a^j) . f'(r) d/r + U'_ZBL(r) d/r, added to
+// F and, as its outer product with d, to W.  The distance, the Chebyshev
+// argument x = 2 (r/rc - 1)^2 - 1, the series T_k, dT_k and their sums with
+// the adjoints are in FP64: near x = -1, where the outer neighbour shells sit,
+// the recurrences amplify a rounding of x by up to k^2 in T_k and k^4 in
+// dT_k, and close to a lattice site the net force is a small difference of
+// such pair terms.  The cutoff factor and the products with d are FP32, the
+// force sums FP64.  Returns false (and adds nothing) outside rc_rad; r2out
+// receives |d|^2.
+__device__ __forceinline__ bool radial_pair_force(const PairConsts &pc, double dx, double dy, double dz,
+                                                  const float ai[KB], const float aj[KB], double &Fx, double &Fy,
+                                                  double &Fz, float W[9], float &r2out)
+{
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    r2out = (float)r2;
+    const double rc = (double)pc.rc_rad;
+    if (r2 >= rc * rc) return false;
+    const double r = dist_d(r2);
+    const double inv = 1.0 / rc;
+    const double tt = r * inv - 1.0;
+    float fc, dfc;
+    cutoff((float)tt, pc.inv_rc_rad, fc, dfc);
+    const double x = 2.0 * tt * tt - 1.0, x2 = 2.0 * x;
+    double Tm2 = 1.0, Tm1 = x, dTm2 = 0.0, dTm1 = 1.0;
+    double ah = (double)ai[0] + (double)aj[0];
+    double s0 = ah, s1 = 0.0, sa = ah;
+    ah = (double)ai[1] + (double)aj[1];
+    s0 = fma(ah, x, s0);
+    s1 += ah;
+    sa += ah;
+#pragma unroll
+    for (int k = 2; k < KB; ++k) {
+        const double T = fma(x2, Tm1, -Tm2);
+        const double dT = fma(x2, dTm1, fma(2.0, Tm1, -dTm2));
+        ah = (double)ai[k] + (double)aj[k];
+        s0 = fma(ah, T, s0);
+        s1 = fma(ah, dT, s1);
+        sa += ah;
+        Tm2 = Tm1; Tm1 = T; dTm2 = dTm1; dTm1 = dT;
+    }
+    double dGdr = 0.5 * (4.0 * tt * inv * (double)fc * s1 + (double)dfc * (s0 + sa));
+    if (r < (double)pc.zbl_r2) {
+        double U, dU;
+        zbl_pair(r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
+        dGdr += dU;
+    }
+    double rinv = (double)frcp((float)r);
+    rinv = rinv * fma(-r, rinv, 2.0);
+    rinv = rinv * fma(-r, rinv, 2.0);
+    const float c = (float)(dGdr * rinv);
+    const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+    const float px = c * fdx, py = c * fdy, pz = c * fdz;
+    Fx += px; Fy += py; Fz += pz;
+    W[0] = fmaf(px, fdx, W[0]); W[1] = fmaf(px, fdy, W[1]); W[2] = fmaf(px, fdz, W[2]);
+    W[3] = fmaf(py, fdx, W[3]); W[4] = fmaf(py, fdy, W[4]); W[5] = fmaf(py, fdz, W[5]);
+    W[6] = fmaf(pz, fdx, W[6]); W[7] = fmaf(pz, fdy, W[7]); W[8] = fmaf(pz, fdz, W[8]);
+    return true;
+}
+
 // F_i = sum_j (a^i + a^j) . f'(r_ij) u_ij + U'_ZBL(r_ij) u_ij        (radial + ZBL)
 //     + sum_j [dU_i/dr_ij - dU_j/dr_ji]_angular                       (stored pair gradients)
 // and the radial + ZBL virial -1/2 sum_j f_ij (x) r_ij added to the angular one.
@@ -645,7 +710,7 @@ __device__ __forceinline__ void force_atom(
 #pragma unroll
     for (int k = 0; k < KB; ++k) ai[k] = xp[t].a[k];
     const float4 fo = f_own[t];
-    float Fx = fo.x, Fy = fo.y, Fz = fo.z;
+    double Fx = fo.x, Fy = fo.y, Fz = fo.z;
     float W[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) W[k] = 0.0f;
@@ -662,38 +727,7 @@ __device__ __forceinline__ void force_atom(
             ddy += n0 * h[1] + n1 * h[4] + n2 * h[7];
             ddz += n0 * h[2] + n1 * h[5] + n2 * h[8];
         }
-        const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        r2out = r2;
-        if (r2 >= pc.rc_rad2) return false;
-        const float r = fsqrt(r2);
-        const float tt = scaled_minus_one(r, pc.inv_rc_rad, pc.inv_rc_rad_lo);
-        float fc, dfc;
-        cutoff(tt, pc.inv_rc_rad, fc, dfc);
-        const float dxdr = 4.0f * tt * pc.inv_rc_rad;
-        float T[KB], dT[KB];
-        cheb_d(fmaf(2.0f * tt, tt, -1.0f), T, dT);
-        float s0 = 0.0f, s1 = 0.0f, sa = 0.0f;
-#pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            const float ah = ai[k] + rj.a[k];
-            s0 = fmaf(ah, T[k], s0);
-            s1 = fmaf(ah, dT[k], s1);
-            sa += ah;
-        }
-        float dGdr = 0.5f * (dxdr * fc * s1 + dfc * (s0 + sa));
-        if (r < pc.zbl_r2) {
-            double U, dU;
-            zbl_pair((double)r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
-            dGdr += (float)dU;
-        }
-        const float c = dGdr * frcp(r);
-        const float px = c * dx, py = c * dy, pz = c * dz;
-        Fx += px; Fy += py; Fz += pz;
-        W[0] = fmaf(px, dx, W[0]); W[1] = fmaf(px, dy, W[1]); W[2] = fmaf(px, dz, W[2]);
-        W[3] = fmaf(py, dx, W[3]); W[4] = fmaf(py, dy, W[4]); W[5] = fmaf(py, dz, W[5]);
-        W[6] = fmaf(pz, dx, W[6]); W[7] = fmaf(pz, dy, W[7]); W[8] = fmaf(pz, dz, W[8]);
-        return true;
+        return radial_pair_force(pc, ddx, ddy, ddz, ai, rj.a, Fx, Fy, Fz, W, r2out);
     };
 
     // both lists are software-pipelined: entries (and reverse slots) two
@@ -768,8 +802,10 @@ __device__ __forceinline__ void force_atom(
     for (int k = 0; k < 9; ++k) w[k] = fmaf(-0.5f, W[k], w[k]);
 }
 
+// (three waves per SIMD: the FP64 pair term needs more registers than the
+// default allocation for this block size would leave)
 template <int BS, bool PERSISTENT>
-__global__ __launch_bounds__(BS) void k_force(
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_force(
     PairConsts pc, const AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
@@ -1297,7 +1333,7 @@ __global__ __launch_bounds__(POP_DESC_BS, 2) void k_pop_descriptor(
 }
 
 // forces of member m go to F + 3 m n (fx), + (3 m + 1) n (fy), + (3 m + 2) n (fz), caller order
-__global__ __launch_bounds__(256) void k_pop_force(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_pop_force(
     PairConsts pc, const AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,

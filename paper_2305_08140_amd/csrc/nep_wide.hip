@@ -1,8 +1,9 @@
 // Kernels of the paper-size model (see nep_wide.h for the phases).  The
 // arithmetic follows the default model's kernels (nep_kernels.hip) term by
 // term: FP64 pair geometry, Chebyshev basis, radial sums and l <= 3 angular
-// sums; FP32 l = 4 sums, network, gradient walk and force kernel.  One lane
-// per atom, blocks in XCD-aware order.
+// sums; FP32 l = 4 sums, network, gradient walk and force kernel, whose
+// distance, Chebyshev argument and series stay FP64.  One lane per atom,
+// blocks in XCD-aware order.
 #include "nep_wide.h"
 #include "nep_pairs.h"
 
@@ -470,36 +471,37 @@ __global__ __launch_bounds__(WBS_F) void k_w_force(
         const float r2 = dx * dx + dy * dy + dz * dz;
         r2out = r2;
         if (r2 >= pc.rc_rad2) return false;
-        const float r = fsqrt(r2);
-        const float tt = scaled_minus_one(r, pc.inv_rc_rad, pc.inv_rc_rad_lo);
-        float fc, dfc;
-        cutoff(tt, pc.inv_rc_rad, fc, dfc);
         // with 16 Chebyshev terms the rounding of x is amplified ~k^4 in dT_k
-        // near x = -1 (the outer shells): x and the series in FP64
-        const double ttd = dist_d(ddx * ddx + ddy * ddy + ddz * ddz) * inv_rR - 1.0;
+        // near x = -1 (the outer shells): the distance, x, the series and
+        // their sums with the adjoints in FP64, the cutoff factor in FP32
+        const double rd = dist_d(ddx * ddx + ddy * ddy + ddz * ddz);
+        const double ttd = rd * inv_rR - 1.0;
+        float fc, dfc;
+        cutoff((float)ttd, pc.inv_rc_rad, fc, dfc);
         const double xd = 2.0 * ttd * ttd - 1.0;
         double Tm2 = 1.0, Tm1 = xd, dTm2 = 0.0, dTm1 = 1.0;
-        double s0d = (double)(ai[0] + rj.a[0]) + (double)(ai[1] + rj.a[1]) * xd;
-        double s1d = (double)(ai[1] + rj.a[1]);
-        float sa = (ai[0] + rj.a[0]) + (ai[1] + rj.a[1]);
+        const double a0 = (double)ai[0] + (double)rj.a[0], a1 = (double)ai[1] + (double)rj.a[1];
+        double s0d = fma(a1, xd, a0), s1d = a1, sa = a0 + a1;
 #pragma unroll
         for (int k = 2; k < WKR; ++k) {
             const double Tk = fma(2.0 * xd, Tm1, -Tm2);
             const double dTk = fma(2.0 * xd, dTm1, fma(2.0, Tm1, -dTm2));
-            const float ah = ai[k] + rj.a[k];
-            s0d = fma((double)ah, Tk, s0d);
-            s1d = fma((double)ah, dTk, s1d);
+            const double ah = (double)ai[k] + (double)rj.a[k];
+            s0d = fma(ah, Tk, s0d);
+            s1d = fma(ah, dTk, s1d);
             sa += ah;
             Tm2 = Tm1; Tm1 = Tk; dTm2 = dTm1; dTm1 = dTk;
         }
-        const float dxdr = (float)(4.0 * ttd * inv_rR);
-        float dGdr = 0.5f * (dxdr * fc * (float)s1d + dfc * ((float)s0d + sa));
-        if (r < pc.zbl_r2) {
+        double dGdr = 0.5 * (4.0 * ttd * inv_rR * (double)fc * s1d + (double)dfc * (s0d + sa));
+        if (rd < (double)pc.zbl_r2) {
             double U, dU;
-            zbl_pair((double)r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
-            dGdr += (float)dU;
+            zbl_pair(rd, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
+            dGdr += dU;
         }
-        const float c = dGdr * frcp(r);
+        double rinv = (double)frcp((float)rd);
+        rinv = rinv * fma(-rd, rinv, 2.0);
+        rinv = rinv * fma(-rd, rinv, 2.0);
+        const float c = (float)(dGdr * rinv);
         const float px = c * dx, py = c * dy, pz = c * dz;
         Fx += px; Fy += py; Fz += pz;
         W[0] = fmaf(px, dx, W[0]); W[1] = fmaf(px, dy, W[1]); W[2] = fmaf(px, dz, W[2]);

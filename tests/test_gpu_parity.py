@@ -222,6 +222,29 @@ def test_large_sampled_after_md():
     assert np.abs(W - W.T).max() <= 1e-5 * np.abs(W).max()
 
 
+def test_large_cascade_start_thermal_margin():
+    # the first steps of the 8,192,000-atom cascade (5 + 20 steps as the
+    # benchmark runs them): the lattice is displaced by ~1e-3 A, so the
+    # thermal forces (~0.026 eV/A RMS) are small differences of pair terms
+    # ~1 eV/A, the worst-conditioned point of the run.  The bar is half the
+    # 1e-5 tolerance, a stated margin for the FP32 stages.
+    import paper_2305_08140_amd as nep
+    m = model()
+    s = nep_synth.large()
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(m, s.n_atoms, 1, max_neigh_ang=48, max_neigh_rad=96, skin=1.0)
+    out = nep.EFV(s.n_atoms, 1)
+    md = dict(dt_max=1.0, max_disp=0.015, dt_min=1e-6)
+    ctx.nep_step_verlet(sysd, 5, out, forces_valid=False, **md)
+    st = ctx.nep_step_verlet(sysd, 20, out, forces_valid=True, **md)
+    ferr_th, uerr, ref = _sampled(m, s, sysd, out, n_sample=512)
+    rms = float(np.sqrt(np.mean(np.sum(ref["forces"] ** 2, axis=1))))
+    print(f"[large start] thermal force rel err {ferr_th:.3e} (RMS force {rms:.4f} eV/A), site energy max err "
+          f"{uerr:.2e}, time {st['time']:.3f} fs", flush=True)
+    assert ferr_th <= 0.5 * F_REL_TOL
+    assert uerr <= U_SITE_TOL
+
+
 def test_verlet_trajectory_thermal():
     # 16,000-atom bcc W at 300 K: 10 steps against the oracle's trajectory
     import torch
