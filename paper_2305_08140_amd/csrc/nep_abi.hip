@@ -82,7 +82,10 @@ __global__ void k_build_lists(PairConsts, double, double, double, double, const 
                               const CellGeom *, const int32_t *, const int32_t *, const int32_t *, int32_t *,
                               int32_t *, uint32_t *, int32_t *, const int32_t *, int);
 __global__ void k_build_reverse(PairConsts, const int32_t *, const CellGeom *, const int32_t *,
-                                const uint32_t *, uint8_t *, int32_t *, const int32_t *);
+                                const uint32_t *, uint8_t *, int32_t *, const int32_t *, int);
+__global__ void k_build_lists_blocks(PairConsts, double, double, double, double, const double4 *, const CellGeom *,
+                                     const int32_t *, const int32_t *, const int32_t *, const uint32_t *, int,
+                                     int32_t *, int32_t *, uint32_t *, int32_t *, const int32_t *);
 __global__ void k_kick_drift(int, double *, double *, double *, double *, double *, double *, const float *,
                              const float *, const float *, double, const double *, const uint8_t *, double *,
                              int32_t *);
@@ -183,6 +186,11 @@ struct nep_ctx {
     unsigned long long *counts = nullptr;
     double *pg_part = nullptr;       // parameter-gradient block partials
     int pg_blocks = 0;
+    // list build by bin blocks (one binned cell): the blocks in Morton order
+    // of their coordinates (packed), 0 when the system is not eligible
+    int lb_blocks = 0;
+    int64_t lb_cap = 0;
+    uint32_t *blk_coord = nullptr;
     // launch shapes of the two evaluation kernels (index into SHAPES), per
     // size bucket floor(log2 n_atoms) once the autotuner has run
     int shape_desc = DEFAULT_SHAPE_DESC, shape_force = DEFAULT_SHAPE_FORCE;
@@ -309,7 +317,8 @@ void nep_destroy(nep_ctx *c)
                     c->w_atom,
                     c->e_atom, c->cells, c->cell_start_d, c->chunk_begin, c->chunk_end, c->cell_chunk,
                     c->part, c->bin_count, c->bin_start, c->bin_fill, c->scan_sums, c->status, c->flag,
-                    c->md, c->counts, c->pg_part, c->border, c->ke_part, c->n_border, c->rmask, c->amask};
+                    c->md, c->counts, c->pg_part, c->border, c->ke_part, c->n_border, c->rmask, c->amask,
+                    c->blk_coord};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     if (c->h_status) (void)hipHostFree(c->h_status);
@@ -621,6 +630,48 @@ static int setup_system(nep_ctx *c, const nep_system *s, hipStream_t st)
     HIP_TRY(hipMemcpyAsync(c->cell_chunk, cc.data(), (nc + 1) * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(c->cells, c->geom.data(), nc * sizeof(CellGeom), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(c->cell_start_d, start.data(), (nc + 1) * 8, hipMemcpyHostToDevice, st));
+    // bin blocks of the list build: one cell binned along every axis (its
+    // halo bins are then distinct), bin keys within the sort's 27 bits
+    c->lb_blocks = 0;
+    if (nc == 1 && nbins < (1 << 27)) {
+        const CellGeom &g = c->geom[0];
+        bool ok = true;
+        for (int a = 0; a < 3; ++a)
+            if (g.R[a] != 0 || g.nb[a] > 2046) ok = false;
+        if (ok) {
+            int nk[3];
+            for (int a = 0; a < 3; ++a) nk[a] = (g.nb[a] + 1) / 2;
+            const int64_t nblk = (int64_t)nk[0] * nk[1] * nk[2];
+            auto spread = [](uint64_t v) {   // interleave the low 21 bits with two zero bits
+                v &= 0x1fffff;
+                v = (v | v << 32) & 0x1f00000000ffffULL;
+                v = (v | v << 16) & 0x1f0000ff0000ffULL;
+                v = (v | v << 8) & 0x100f00f00f00f00fULL;
+                v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+                v = (v | v << 2) & 0x1249249249249249ULL;
+                return v;
+            };
+            std::vector<std::pair<uint64_t, uint32_t>> key(nblk);
+            for (int64_t l = 0; l < nblk; ++l) {
+                const int b0 = (int)(l % nk[0]), b1 = (int)((l / nk[0]) % nk[1]);
+                const int b2 = (int)(l / ((int64_t)nk[0] * nk[1]));
+                key[l] = {spread(b0) | spread(b1) << 1 | spread(b2) << 2, pack_block(b0, b1, b2)};
+            }
+            std::sort(key.begin(), key.end());
+            std::vector<uint32_t> coord(nblk);
+            for (int64_t r = 0; r < nblk; ++r) coord[r] = key[r].second;
+            if (nblk > c->lb_cap) {
+                if (c->blk_coord) (void)hipFree(c->blk_coord);
+                c->blk_coord = nullptr;
+                c->lb_cap = 0;
+                HIP_TRY(hipMalloc(&c->blk_coord, nblk * 4));
+                c->lb_cap = nblk;
+            }
+            HIP_TRY(hipMemcpyAsync(c->blk_coord, coord.data(), nblk * 4, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            c->lb_blocks = (int)nblk;
+        }
+    }
     // cell index of every atom
     k_cell_of<<<grid_for(n, 256), 256, 0, st>>>((int)n, nc, c->cell_start_d, c->cell_of);
     HIP_TRY(hipGetLastError());
@@ -662,12 +713,18 @@ static int launch_build(nep_ctx *c, const nep_system *s, hipStream_t st, const i
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
                                                        c->cells, c->xq, c->status, flag);
     const double lA = c->hp.rc_ang + c->cfg.skin, lR = c->hp.rc_rad + c->cfg.skin;
-    k_build_lists<<<grid_for(n, 256), 256, 0, st>>>(
-        c->pc, lA * lA, lR * lR, c->hp.rc_ang * c->hp.rc_ang, c->hp.rc_rad * c->hp.rc_rad, c->xq, c->cell_of,
-        c->cells, c->bin_sorted, c->bin_start, c->bin_rank, c->nl_ang, c->nl_rad, c->ncnt, c->status, flag,
-        c->n_bins < (1 << 27) ? 1 : 0);
+    if (c->lb_blocks > 0)
+        k_build_lists_blocks<<<xcd_grid(c->lb_blocks), LB_BS, 0, st>>>(
+            c->pc, lA * lA, lR * lR, c->hp.rc_ang * c->hp.rc_ang, c->hp.rc_rad * c->hp.rc_rad, c->xq, c->cells,
+            c->bin_sorted, c->bin_start, c->bin_rank, c->blk_coord, c->lb_blocks, c->nl_ang, c->nl_rad, c->ncnt,
+            c->status, flag);
+    else
+        k_build_lists<<<grid_for(n, 256), 256, 0, st>>>(
+            c->pc, lA * lA, lR * lR, c->hp.rc_ang * c->hp.rc_ang, c->hp.rc_rad * c->hp.rc_rad, c->xq, c->cell_of,
+            c->cells, c->bin_sorted, c->bin_start, c->bin_rank, c->nl_ang, c->nl_rad, c->ncnt, c->status, flag,
+            c->n_bins < (1 << 27) ? 1 : 0);
     k_build_reverse<<<grid_for(n, 256), 256, 0, st>>>(c->pc, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->rev,
-                                                      c->status, flag);
+                                                      c->status, flag, c->n_bins < (1 << 27) ? 1 : 0);
     // the lists are usable only if the build latched no error
     k_lists_commit<<<1, 64, 0, st>>>(c->status, flag);
     HIP_TRY(hipGetLastError());

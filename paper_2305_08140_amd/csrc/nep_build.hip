@@ -221,6 +221,66 @@ __global__ void k_sort_positions(int n, const int32_t *__restrict__ perm,
     xq[t] = make_double4(wx, wy, wz, 0.0);
 }
 
+// One atom's list build: the candidates of each visited bin are offered in
+// turn, and the entries are written to the front (inside the cutoff at build
+// time) or the back (skin shell) of the atom's angular or radial column.
+struct ListBuilder {
+    const PairConsts &pc;
+    double lA2, lR2, cA2, cR2;
+    int t, atom_start;
+    double xi, yi, zi;
+    int32_t *nl_ang, *nl_rad;
+    int32_t *status;
+    uint64_t cntA = 0, cntR = 0;   // front | back << 32 (kept in registers)
+    __device__ ListBuilder(const PairConsts &pc_, double lA2_, double lR2_, double cA2_, double cR2_, int t_,
+                           int atom_start_, double4 pi, int32_t *nl_ang_, int32_t *nl_rad_, int32_t *status_)
+        : pc(pc_), lA2(lA2_), lR2(lR2_), cA2(cA2_), cR2(cR2_), t(t_), atom_start(atom_start_), xi(pi.x), yi(pi.y),
+          zi(pi.z), nl_ang(nl_ang_), nl_rad(nl_rad_), status(status_)
+    {
+    }
+    // candidate u (sorted index) at position pu, seen through the image
+    // shift (sx, sy, sz) whose entry code is `code`
+    __device__ __forceinline__ void offer(int u, const double4 &pu, double sx, double sy, double sz, uint32_t code)
+    {
+        // (x_u - x_i) + shift: exactly the negative of the vector seen from u
+        const double dx = (pu.x - xi) + sx, dy = (pu.y - yi) + sy, dz = (pu.z - zi) + sz;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= lR2) return;
+        const uint32_t jl = (uint32_t)(u - atom_start);
+        const int32_t e = (int32_t)(jl | (code << pc.jbits));
+        if (jl >= (1u << pc.jbits)) latch_error(status, -1);
+        const bool ang = r2 < lA2;
+        const bool front = r2 < (ang ? cA2 : cR2);
+        const uint64_t cnt = ang ? cntA : cntR;
+        const int f = (int)(cnt & 0xffffffffu), b = (int)(cnt >> 32), cap = ang ? pc.capA : pc.capR;
+        if (f + b < cap) (ang ? nl_ang : nl_rad)[(size_t)(front ? f : cap - 1 - b) * pc.n + t] = e;
+        const uint64_t inc = front ? 1ull : (1ull << 32);
+        cntA += ang ? inc : 0ull;
+        cntR += ang ? 0ull : inc;
+    }
+    __device__ uint32_t image_code(const int m[3]) const
+    {
+        return (uint32_t)(m[0] + pc.ioff) | ((uint32_t)(m[1] + pc.ioff) << pc.ibits) |
+               ((uint32_t)(m[2] + pc.ioff) << (2 * pc.ibits));
+    }
+    // counts (clamped to the capacities after an overflow, which is latched
+    // with the lengths needed)
+    __device__ void finish(uint32_t *ncnt)
+    {
+        int naf = (int)(cntA & 0xffffffffu), nab = (int)(cntA >> 32);
+        int nrf = (int)(cntR & 0xffffffffu), nrb = (int)(cntR >> 32);
+        const int nA = naf + nab, nR = nrf + nrb;
+        if (nA > pc.capA || nR > pc.capR) {
+            latch_error(status, -3);
+            if (nA > pc.capA) { naf = naf < pc.capA ? naf : pc.capA; nab = pc.capA - naf; }
+            if (nR > pc.capR) { nrf = nrf < pc.capR ? nrf : pc.capR; nrb = pc.capR - nrf; }
+        }
+        atomicMax(status + ST_NEED_A, nA);
+        atomicMax(status + ST_NEED_R, nR);
+        ncnt[t] = (uint32_t)naf | ((uint32_t)nab << 8) | ((uint32_t)nrf << 16) | ((uint32_t)nrb << 24);
+    }
+};
+
 // Neighbour lists of every sorted atom (see the file comment for the layout).
 __global__ __launch_bounds__(256) void k_build_lists(
     PairConsts pc, double lA2, double lR2, double cA2, double cR2, const double4 *__restrict__ xq,
@@ -234,18 +294,14 @@ __global__ __launch_bounds__(256) void k_build_lists(
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= pc.n) return;
     const CellGeom &cg = cells[cell_of[t]];
-    const double4 pi = xq[t];
-    const double xi = pi.x, yi = pi.y, zi = pi.z;
-    const int lb = bin_sorted[t];
-    const int bc[3] = {lb % cg.nb[0], (lb / cg.nb[0]) % cg.nb[1], lb / (cg.nb[0] * cg.nb[1])};
+    ListBuilder lb(pc, lA2, lR2, cA2, cR2, t, cg.atom_start, xq[t], nl_ang, nl_rad, status);
+    const int lbin = bin_sorted[t];
+    const int bc[3] = {lbin % cg.nb[0], (lbin / cg.nb[0]) % cg.nb[1], lbin / (cg.nb[0] * cg.nb[1])};
     int lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
         if (cg.R[a] > 0) { lo[a] = -cg.R[a]; hi[a] = cg.R[a]; }
         else { lo[a] = -1; hi[a] = 1; }
     }
-    uint64_t cntA = 0, cntR = 0;   // front | back << 32
-    const int capA = pc.capA, capR = pc.capR;
-    const uint32_t jmask_limit = 1u << pc.jbits;
     // bin of offset o from this atom's bin: global bin index (or -1 past an
     // open face) and the image m it lies in
     auto bin_at = [&](int o0, int o1, int o2, int m[3]) __attribute__((always_inline)) -> int {
@@ -273,29 +329,10 @@ __global__ __launch_bounds__(256) void k_build_lists(
         const double sy = m[0] * cg.h[1] + m[1] * cg.h[4] + m[2] * cg.h[7];
         const double sz = m[0] * cg.h[2] + m[1] * cg.h[5] + m[2] * cg.h[8];
         const bool self_image = (m[0] | m[1] | m[2]) == 0;
-        const uint32_t code = (uint32_t)(m[0] + pc.ioff) | ((uint32_t)(m[1] + pc.ioff) << pc.ibits)
-                              | ((uint32_t)(m[2] + pc.ioff) << (2 * pc.ibits));
+        const uint32_t code = lb.image_code(m);
         for (int u = bin_start[gb]; u < bin_start[gb + 1]; ++u) {
             if (u == t && self_image) continue;
-            // (x_u - x_i) + shift: exactly the negative of the vector seen from u
-            const double4 pu = xq[u];
-            const double dx = (pu.x - xi) + sx, dy = (pu.y - yi) + sy, dz = (pu.z - zi) + sz;
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 >= lR2) continue;
-            const uint32_t jl = (uint32_t)(u - cg.atom_start);
-            const int32_t e = (int32_t)(jl | (code << pc.jbits));
-            if (jl >= jmask_limit) latch_error(status, -1);
-            // inside the cutoff at build time: front of the list, else back
-            // (front and back counts packed in one word each, so that the
-            // compiler keeps them in registers)
-            const bool ang = r2 < lA2;
-            const bool front = r2 < (ang ? cA2 : cR2);
-            const uint64_t cnt = ang ? cntA : cntR;
-            const int f = (int)(cnt & 0xffffffffu), b = (int)(cnt >> 32), cap = ang ? capA : capR;
-            if (f + b < cap) (ang ? nl_ang : nl_rad)[(size_t)(front ? f : cap - 1 - b) * pc.n + t] = e;
-            const uint64_t inc = front ? 1ull : (1ull << 32);
-            cntA += ang ? inc : 0ull;
-            cntR += ang ? 0ull : inc;
+            lb.offer(u, xq[u], sx, sy, sz, code);
         }
     };
     if (sorted_scan && cg.R[0] == 0 && cg.R[1] == 0 && cg.R[2] == 0) {
@@ -333,38 +370,170 @@ __global__ __launch_bounds__(256) void k_build_lists(
                     if (gb >= 0) scan_bin(gb, m);
                 }
     }
-    int naf = (int)(cntA & 0xffffffffu), nab = (int)(cntA >> 32);
-    int nrf = (int)(cntR & 0xffffffffu), nrb = (int)(cntR >> 32);
-    const int nA = naf + nab, nR = nrf + nrb;
-    if (nA > capA || nR > capR) {
-        latch_error(status, -3);
-        atomicMax(status + ST_NEED_A, nA);
-        atomicMax(status + ST_NEED_R, nR);
-        // keep the stored counts consistent with what was written
-        if (nA > capA) { naf = naf < capA ? naf : capA; nab = capA - naf; }
-        if (nR > capR) { nrf = nrf < capR ? nrf : capR; nrb = capR - nrf; }
-    } else {
-        atomicMax(status + ST_NEED_A, nA);
-        atomicMax(status + ST_NEED_R, nR);
+    lb.finish(ncnt);
+}
+
+// The same lists for one large binned cell (at least 4 bins along every
+// periodic axis), built by bin blocks: a workgroup takes the aligned
+// 2 x 2 x 2 block of bins k (8 consecutive Morton codes, so its atoms are one
+// contiguous run), copies the positions of the block's halo (the bins within
+// one bin of it, up to 4 x 4 x 4, each a contiguous run) into LDS once, and
+// every atom of the block then scans its 27 neighbour bins there instead of
+// gathering each candidate from memory (~600 candidates per atom, 22 atoms
+// per bin at the bcc density).  Bins are visited in storage order and every
+// candidate goes through the same ListBuilder as above, so the lists are
+// identical to k_build_lists's.  A block whose halo exceeds the LDS copy
+// gathers from memory.
+constexpr int LB_CAP = 1600;     // halo positions per block in LDS (51 KB)
+__global__ __launch_bounds__(LB_BS) void k_build_lists_blocks(
+    PairConsts pc, double lA2, double lR2, double cA2, double cR2, const double4 *__restrict__ xq,
+    const CellGeom *__restrict__ cells, const int32_t *__restrict__ bin_sorted,
+    const int32_t *__restrict__ bin_start, const int32_t *__restrict__ bin_rank,
+    const uint32_t *__restrict__ blk_coord, int nblocks, int32_t *__restrict__ nl_ang,
+    int32_t *__restrict__ nl_rad, uint32_t *__restrict__ ncnt, int32_t *__restrict__ status,
+    const int32_t *__restrict__ flag)
+{
+    __shared__ double4 pos[LB_CAP];
+    __shared__ int s_off[65], s_gst[64], s_gb[64], s_a[2];
+    if (flag && *flag == 0) return;
+    const int k = xcd_block(nblocks);
+    if (k >= nblocks) return;
+    const int tid = threadIdx.x;
+    const CellGeom &cg = cells[0];
+    int B[3];
+    unpack_block(blk_coord[k], B);
+    if (tid < 64) {
+        // halo bin hb = tid at halo coordinates d (bin 2 B - 1 + d): absent
+        // beyond an open face and past the far side of a block one bin wide
+        const int hb = tid;
+        const int d[3] = {hb & 3, (hb >> 2) & 3, hb >> 4};
+        bool present = true, own = true;
+        int bb[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int width = min(2, cg.nb[a] - 2 * B[a]);
+            if (d[a] > width + 1) present = false;
+            if (d[a] < 1 || d[a] > width) own = false;
+            int u = 2 * B[a] - 1 + d[a];
+            if (cg.periodic[a]) u = u < 0 ? u + cg.nb[a] : (u >= cg.nb[a] ? u - cg.nb[a] : u);
+            else if (u < 0 || u >= cg.nb[a]) present = false;
+            bb[a] = u;
+        }
+        int cnt = 0, gst = 0, gb = -1;
+        if (present) {
+            gb = cg.bin_offset + bin_rank[cg.bin_offset + (bb[2] * cg.nb[1] + bb[1]) * cg.nb[0] + bb[0]];
+            gst = bin_start[gb];
+            cnt = bin_start[gb + 1] - gst;
+        }
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o);
+            if (hb >= o) incl += v;
+        }
+        int a0 = own ? gst : INT32_MAX, a1 = own ? gst + cnt : INT32_MIN;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            a0 = min(a0, __shfl_xor(a0, o));
+            a1 = max(a1, __shfl_xor(a1, o));
+        }
+        s_off[hb] = incl - cnt;
+        s_gst[hb] = gst;
+        s_gb[hb] = gb;
+        if (hb == 63) s_off[64] = incl;
+        if (hb == 0) { s_a[0] = a0 <= a1 ? a0 : 0; s_a[1] = a0 <= a1 ? a1 : 0; }
     }
-    ncnt[t] = (uint32_t)naf | ((uint32_t)nab << 8) | ((uint32_t)nrf << 16) | ((uint32_t)nrb << 24);
+    __syncthreads();
+    const int total = s_off[64];
+    const bool staged = total <= LB_CAP;
+    if (staged) {
+        for (int r = tid; r < total; r += LB_BS) {
+            // halo bin holding record r: the last hb with s_off[hb] <= r
+            int lo = 0, hi = 64;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_off[mid] <= r) lo = mid;
+                else hi = mid;
+            }
+            pos[r] = xq[s_gst[lo] + (r - s_off[lo])];
+        }
+    }
+    __syncthreads();
+    for (int t = s_a[0] + tid; t < s_a[1]; t += LB_BS) {
+        ListBuilder lb(pc, lA2, lR2, cA2, cR2, t, cg.atom_start, xq[t], nl_ang, nl_rad, status);
+        const int lbin = bin_sorted[t];
+        const int bc[3] = {lbin % cg.nb[0], (lbin / cg.nb[0]) % cg.nb[1], lbin / (cg.nb[0] * cg.nb[1])};
+        // the 27 neighbour bins in storage order (keys gb << 5 | offset)
+        uint32_t key[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            key[q] = 0xffffffffu;
+            if (q < 27) {
+                const int o[3] = {q % 3 - 1, (q / 3) % 3 - 1, q / 9 - 1};
+                const int hb = halo_index(bc[0] - 2 * B[0] + 1 + o[0], bc[1] - 2 * B[1] + 1 + o[1],
+                                          bc[2] - 2 * B[2] + 1 + o[2]);
+                if (s_gb[hb] >= 0) key[q] = ((uint32_t)s_gb[hb] << 5) | (uint32_t)q;
+            }
+        }
+        sort32(key);
+        for (int kk = 0; kk < 27; ++kk) {
+            const uint32_t kq = key[0];
+#pragma unroll
+            for (int q = 0; q < 31; ++q) key[q] = key[q + 1];
+            if (kq == 0xffffffffu) break;
+            const int q = (int)(kq & 31u);
+            const int o[3] = {q % 3 - 1, (q / 3) % 3 - 1, q / 9 - 1};
+            int m[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int u = bc[a] + o[a];
+                m[a] = cg.periodic[a] ? (u < 0 ? -1 : (u >= cg.nb[a] ? 1 : 0)) : 0;
+            }
+            const int hb = halo_index(bc[0] - 2 * B[0] + 1 + o[0], bc[1] - 2 * B[1] + 1 + o[1],
+                                      bc[2] - 2 * B[2] + 1 + o[2]);
+            const double sx = m[0] * cg.h[0] + m[1] * cg.h[3] + m[2] * cg.h[6];
+            const double sy = m[0] * cg.h[1] + m[1] * cg.h[4] + m[2] * cg.h[7];
+            const double sz = m[0] * cg.h[2] + m[1] * cg.h[5] + m[2] * cg.h[8];
+            const bool self_image = (m[0] | m[1] | m[2]) == 0;
+            const uint32_t code = lb.image_code(m);
+            const int r0 = s_off[hb], r1 = s_off[hb + 1], u0 = s_gst[hb] - r0;
+            // (two loops, so that the LDS one issues no memory loads)
+            if (staged) {
+                for (int r = r0; r < r1; ++r) {
+                    const int u = u0 + r;
+                    if (u == t && self_image) continue;
+                    lb.offer(u, pos[r], sx, sy, sz, code);
+                }
+            } else {
+                for (int r = r0; r < r1; ++r) {
+                    const int u = u0 + r;
+                    if (u == t && self_image) continue;
+                    lb.offer(u, xq[u], sx, sy, sz, code);
+                }
+            }
+        }
+        lb.finish(ncnt);
+    }
 }
 
 // Reverse index of the angular lists: for entry (t, slot) naming atom j with
 // image n, the slot of j's list that names t with image -n (255 if absent,
-// which symmetric lists never produce).
+// which symmetric lists never produce).  sorted_scan: the lists of binned
+// cells were built in storage order (as k_build_lists with that flag).
 __global__ __launch_bounds__(256) void k_build_reverse(PairConsts pc, const int32_t *__restrict__ cell_of,
                                                        const CellGeom *__restrict__ cells,
                                                        const int32_t *__restrict__ nl_ang,
                                                        const uint32_t *__restrict__ ncnt,
                                                        uint8_t *__restrict__ rev, int32_t *__restrict__ status,
-                                                       const int32_t *__restrict__ flag)
+                                                       const int32_t *__restrict__ flag, int sorted_scan)
 {
     if (flag && *flag == 0) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= pc.n) return;
     if (status[ST_ERR] != 0) return;
-    const int base = cells[cell_of[t]].atom_start;
+    const CellGeom &cg = cells[cell_of[t]];
+    const int base = cg.atom_start;
+    const bool sorted = sorted_scan && cg.R[0] == 0 && cg.R[1] == 0 && cg.R[2] == 0;
     const uint32_t cnt = ncnt[t];
     const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff;
     const uint32_t jmask = (1u << pc.jbits) - 1u, imask = (1u << pc.ibits) - 1u;
@@ -387,6 +556,21 @@ __global__ __launch_bounds__(256) void k_build_reverse(PairConsts pc, const int3
         const int f0 = 0, f1 = jf, b0 = pc.capA - jb, b1 = pc.capA;
         const bool front = s < naf;
         int found = 255;
+        if (sorted) {
+            // a list built in storage order holds each neighbour once per
+            // part, ascending in its index (the front part in slot order, the
+            // back part in reverse slot order): bisect on the index field
+            const int q0 = front ? f0 : b0, q1 = front ? f1 : b1;
+            int lo = 0, hi = q1 - q0;        // rank in ascending index order
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const int sq = front ? q0 + mid : q1 - 1 - mid;
+                if (((uint32_t)nl_ang[(size_t)sq * pc.n + j] & jmask) < tl) lo = mid + 1;
+                else hi = mid;
+            }
+            const int sq = front ? q0 + lo : q1 - 1 - lo;
+            if (lo < q1 - q0 && (uint32_t)nl_ang[(size_t)sq * pc.n + j] == want) found = sq;
+        }
         for (int pass = 0; pass < 2 && found == 255; ++pass) {
             const bool in_front = (pass == 0) == front;
             const int q0 = in_front ? f0 : b0, q1 = in_front ? f1 : b1;

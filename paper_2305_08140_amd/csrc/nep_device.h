@@ -565,4 +565,24 @@ __device__ inline int xcd_block(int ntiles)
     return (b % 8) * per + b / 8;
 }
 
+
+// ---------------------------------------------------------------- bin blocks
+// The aligned 2 x 2 x 2 blocks of a cell's bin grid (8 consecutive Morton
+// codes) and their halo, the bins within one bin of a block: halo
+// coordinates d = 0..3 per axis name bin 2 B - 1 + d of block B.
+__host__ __device__ inline int halo_index(int d0, int d1, int d2) { return (d2 * 4 + d1) * 4 + d0; }
+constexpr int LB_BS = 256;   // threads per block of the list build by bin blocks
+
+__host__ __device__ inline uint32_t pack_block(int b0, int b1, int b2)
+{
+    return (uint32_t)b0 | ((uint32_t)b1 << 10) | ((uint32_t)b2 << 20);
+}
+
+__host__ __device__ inline void unpack_block(uint32_t p, int b[3])
+{
+    b[0] = (int)(p & 1023u);
+    b[1] = (int)((p >> 10) & 1023u);
+    b[2] = (int)(p >> 20);
+}
+
 }  // namespace nep

@@ -86,6 +86,40 @@ def test_batch_mixing_binned_and_imaged_cells():
     _compare(s, m, ref, res, None, "binned + imaged cells")
 
 
+@pytest.mark.parametrize("pbc", [(1, 1, 1), (1, 1, 0)])
+def test_block_list_build_matches_gather_build(pbc):
+    # one binned cell builds its lists by bin blocks (halo positions in LDS);
+    # the same atoms as the first cell of a two-cell batch take the per-atom
+    # build that gathers every candidate.  Identical lists give bitwise
+    # identical forces and energies: 7 x 7 x 7 bins (odd, so the last blocks
+    # are one bin wide), displaced atoms, periodic and open along z.
+    import torch
+    import paper_2305_08140_amd as nep
+    m = model()
+    pos, h = nep_synth.bcc_lattice(16, 16, 16)
+    pos = pos + np.random.default_rng(41).normal(0.0, 0.1, pos.shape)
+    one = nep_synth._single(pos, h)
+    one.pbc = pbc
+    small, hs = nep_synth.bcc_lattice(3, 3, 3)
+    two = nep_synth.System(pos=np.concatenate([pos, small]), vel=np.zeros((pos.shape[0] + small.shape[0], 3)),
+                           cell_start=np.array([0, pos.shape[0], pos.shape[0] + small.shape[0]], dtype=np.int64),
+                           h=np.stack([h, hs]))
+    two.pbc = pbc
+    res = []
+    for s in (one, two):
+        sysd = nep.DeviceSystem.from_synth(s)
+        ctx = nep.Context(m, s.n_atoms, s.n_cells)
+        out = nep.EFV(s.n_atoms, s.n_cells)
+        ctx.nep_build_neighbors(sysd)
+        ctx.nep_compute_efv(sysd, out)
+        torch.cuda.synchronize()
+        res.append((out.forces().cpu().numpy(), out.energy.cpu().numpy(), out.virial.cpu().numpy()))
+    n = pos.shape[0]
+    assert np.array_equal(res[0][0], res[1][0][:n])
+    assert res[0][1][0] == res[1][1][0]
+    assert np.array_equal(res[0][2].reshape(-1)[:9], res[1][2].reshape(-1)[:9])
+
+
 def test_small_strained_cells_with_images():
     # cells of 8-60 atoms: several periodic images of the same neighbour, own images
     m = model()
