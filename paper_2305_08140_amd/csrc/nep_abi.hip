@@ -17,7 +17,7 @@ namespace nep {
 template <int BS, bool PE, int NNMODE>
 __global__ void k_descriptor(PairConsts, const double4 *, AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
                              const int32_t *, const uint32_t *, const float *, const double *, float4 *, float4 *,
-                             float *, double *, int32_t *, int);
+                             float *, double *, int32_t *, int, const int32_t *);
 template <int BS, bool PE>
 __global__ void k_force(PairConsts, const AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
                         const int32_t *, const uint32_t *, const uint8_t *, const float4 *, const float4 *,
@@ -97,6 +97,8 @@ __global__ void k_rebuild_flag(double, double *, int32_t *, const int32_t *);
 __global__ void k_lists_commit(int32_t *, const int32_t *);
 __global__ void k_disp(int, const double *, const double *, const double *, const double *, double *);
 __global__ void k_set_flag(int32_t *, int32_t);
+__global__ void k_cand_update(double, double *, const int32_t *, int32_t *);
+__global__ void k_cand_set(double *, double);
 __global__ void k_cell_of(int, int, const int64_t *, int32_t *);
 // kernels (nep_thermostat.hip)
 __global__ void k_border_mask(int, const double *, const double *, const double *, double, double, double, int,
@@ -149,6 +151,8 @@ struct nep_ctx {
     uint8_t *rev = nullptr;       // [capA][N] reverse slot index
     uint32_t *rmask = nullptr;    // [ceil(capR/32)][N] radial entries inside rc_rad
     uint32_t *amask = nullptr;    // [ceil(capA/32)][N] angular entries within the write radius
+    uint32_t *cmask = nullptr;    // [ceil(capR/32)][N] radial entries within the candidate radius
+    int32_t *cflag = nullptr;     // next evaluation's radial walk: 1 full, 0 candidates only
     double *e_atom = nullptr;
     // per-cell storage
     CellGeom *cells = nullptr;
@@ -317,7 +321,7 @@ void nep_destroy(nep_ctx *c)
                     c->w_atom,
                     c->e_atom, c->cells, c->cell_start_d, c->chunk_begin, c->chunk_end, c->cell_chunk,
                     c->part, c->bin_count, c->bin_start, c->bin_fill, c->scan_sums, c->status, c->flag,
-                    c->md, c->counts, c->pg_part, c->border, c->ke_part, c->n_border, c->rmask, c->amask,
+                    c->md, c->counts, c->pg_part, c->border, c->ke_part, c->n_border, c->rmask, c->amask, c->cmask, c->cflag,
                     c->blk_coord};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
@@ -388,6 +392,8 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     A((void **)&c->f_own, N * sizeof(float4));
     A((void **)&c->rev, N * cfg->max_neigh_ang);
     A((void **)&c->rmask, N * ((cfg->max_neigh_rad + 31) / 32) * 4);
+    A((void **)&c->cmask, N * ((cfg->max_neigh_rad + 31) / 32) * 4);
+    A((void **)&c->cflag, 4);
     A((void **)&c->amask, N * ((cfg->max_neigh_ang + 31) / 32) * 4);
     A((void **)&c->w_atom, N * 9 * 4);
     A((void **)&c->e_atom, N * 8);
@@ -548,6 +554,8 @@ static int setup_system(nep_ctx *c, const nep_system *s, hipStream_t st)
     if (max_cell_atoms > (1LL << pc.jbits)) return NEP_E_ARG;
     pc.n = (int)n;
     pc.rmask = c->rmask;
+    pc.cmask = c->cmask;
+    pc.rc_cand = (float)(c->hp.rc_rad + CAND_MARGIN);
     pc.amask = c->amask;
 
     // bins
@@ -771,7 +779,7 @@ static void launch_desc_t(nep_ctx *c, hipStream_t st)
     }
     k_descriptor<BS, PE, NNMODE><<<grid, BS, 0, st>>>(c->pc, c->xq, c->xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
                                                       c->ncnt, c->params, c->c64, c->pair_grad, c->f_own, c->w_atom,
-                                                      c->e_atom, c->status, tiles);
+                                                      c->e_atom, c->status, tiles, c->cflag);
 }
 
 template <int BS, bool PE>
@@ -859,10 +867,15 @@ static void launch_force_any(nep_ctx *c, const nep_efv *o, hipStream_t st)
 // One evaluation: sorted positions, descriptor + network, forces, reductions.
 // ev (may be NULL): three events recorded on st before the descriptor
 // kernel(s), between them and the force kernel, and after it.
+// One evaluation.  md_step: inside the MD loop, where k_cand_update has
+// decided whether the descriptor's radial walk goes over every entry or only
+// over the candidates of the last full walk; any other evaluation walks in
+// full (and writes the candidate mask).
 static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t st, bool refresh_positions,
-                      hipEvent_t *ev = nullptr)
+                      hipEvent_t *ev = nullptr, bool md_step = false)
 {
     const int n = (int)s->n_atoms;
+    if (!md_step) k_set_flag<<<1, 64, 0, st>>>(c->cflag, 1);
     if (refresh_positions)
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
                                                            c->cells, c->xq, c->status, nullptr);
@@ -909,6 +922,7 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
     hipEvent_t ev[5];
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     double acc[4] = {0, 0, 0, 0};
+    k_set_flag<<<1, 64, 0, st>>>(c->cflag, 1);   // full radial walks
     for (int r = 0; r < reps; ++r) {
         HIP_TRY(hipEventRecord(ev[0], st));
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
@@ -1031,6 +1045,7 @@ int nep_autotune(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, int3
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    k_set_flag<<<1, 64, 0, st>>>(c->cflag, 1);   // full radial walks
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
                                                        c->cells, c->xq, c->status, nullptr);
     auto time_it = [&](auto &&launch) -> float {
@@ -1179,9 +1194,13 @@ int nep_step_verlet(nep_ctx *c, nep_system *s, const nep_md *md, int32_t n_steps
         k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag, c->status);
         if ((rc = launch_build(c, s, st, c->flag))) return rc;
     }
-    if (!md->forces_valid || fresh) {
+    const bool initial = !md->forces_valid || fresh;
+    if (initial) {
         if ((rc = launch_efv(c, s, o, st, true))) return rc;
     }
+    // the candidate bound starts from that full walk, or forces one at the
+    // first step (the positions may have changed since the last call)
+    k_cand_set<<<1, 64, 0, st>>>(c->md, initial ? 0.0 : 1e30);
     // border set and chain at rest, from the positions at this call's start
     const bool th = thermo && n_steps > 0;
     if (th && (md->thermo_reset || !c->border_valid || c->th_chain != md->thermo_chain ||
@@ -1225,8 +1244,9 @@ int nep_step_verlet(nep_ctx *c, nep_system *s, const nep_md *md, int32_t n_steps
         k_kick_drift<<<sg, 256, 0, st>>>(n, s->x, s->y, s->z, s->vx, s->vy, s->vz, o->fx, o->fy, o->fz, acc,
                                          c->xref, bd, c->md, c->status);
         k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag, c->status);
+        k_cand_update<<<1, 64, 0, st>>>(CAND_TRIGGER, c->md, c->flag, c->cflag);
         if ((rc = launch_build(c, s, st, c->flag))) { free_events(); return rc; }
-        if ((rc = launch_efv(c, s, o, st, true, k < n_timed ? &ev[3 * (size_t)k] : nullptr))) {
+        if ((rc = launch_efv(c, s, o, st, true, k < n_timed ? &ev[3 * (size_t)k] : nullptr, true))) {
             free_events();
             return rc;
         }

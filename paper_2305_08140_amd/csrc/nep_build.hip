@@ -625,7 +625,7 @@ __global__ __launch_bounds__(256) void k_kick_drift(int n, double *__restrict__ 
                                                     const double *__restrict__ xref, const uint8_t *__restrict__ border,
                                                     double *__restrict__ md, int32_t *__restrict__ status)
 {
-    double dmax = 0.0;
+    double dmax = 0.0, smax = 0.0;
     if (status[ST_ERR] == 0) {
         const double dt = md[MD_DT];
         const double c = 0.5 * dt * acc_per_mass;
@@ -641,9 +641,38 @@ __global__ __launch_bounds__(256) void k_kick_drift(int n, double *__restrict__ 
             double d2 = e0 * e0 + e1 * e1 + e2 * e2;
             if (!isfinite(d2)) { latch_error(status, -5); d2 = 0.0; }
             dmax = fmax(dmax, d2);
+            const double s2 = dt * dt * (v0 * v0 + v1 * v1 + v2 * v2);
+            if (isfinite(s2)) smax = fmax(smax, s2);
         }
     }
     block_max_atomic(dmax, md + MD_DISP2);
+    __syncthreads();
+    block_max_atomic(smax, md + MD_STEP2);
+}
+
+// The radial walk's candidate bound after a drift: the largest step of this
+// drift is added to the bound on any atom's displacement since the last full
+// radial walk; the next evaluation walks in full (and restarts the bound)
+// after a rebuild or once the bound reaches half the candidate margin.
+__global__ void k_cand_update(double half_margin, double *__restrict__ md, const int32_t *__restrict__ rebuilt,
+                              int32_t *__restrict__ cflag)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = md[MD_CACC] + sqrt(md[MD_STEP2]);
+    md[MD_STEP2] = 0.0;
+    const int full = *rebuilt != 0 || !(acc < half_margin);
+    if (full) acc = 0.0;
+    md[MD_CACC] = acc;
+    *cflag = full;
+}
+
+// The bound's start value: 0 right after a full radial walk, huge when the
+// candidate mask is not known to match the positions.
+__global__ void k_cand_set(double *__restrict__ md, double acc)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    md[MD_CACC] = acc;
+    md[MD_STEP2] = 0.0;
 }
 
 // Largest |v|^2 (of the non-border atoms when a border set is given; then

@@ -68,6 +68,12 @@ struct PairConsts {
     // the pair-gradient write radius (rc_ang2_write, with a margin) at the
     // last evaluation's first walk; the later angular walks take only those
     uint32_t *amask;
+    // [word][atom]: bit s set when the s-th radial-list entry was within
+    // rc_cand (rc_rad plus a margin) at the last full radial walk; between
+    // full walks, while no atom can have moved by half the margin, the
+    // descriptor's radial walk takes only those entries
+    uint32_t *cmask;
+    float rc_cand;
 };
 
 // Reference lattice of the Wigner-Seitz analysis (perfect bcc, cubic
@@ -112,6 +118,16 @@ constexpr int MD_DT = 0, MD_VMAX2 = 1, MD_DISP2 = 2, MD_TIME = 3, MD_NREB = 4, M
 constexpr int MD_STEP_WORDS = 8;
 constexpr int MD_NHC_MAX = 8;
 constexpr int MD_XI = 8, MD_VXI = MD_XI + MD_NHC_MAX, MD_ENHC = MD_VXI + MD_NHC_MAX, MD_NBORDER = MD_ENHC + 1;
+// bound on any atom's displacement since the last full radial walk (sum of
+// the steps' largest displacements), and the current step's largest
+// displacement squared
+constexpr int MD_CACC = MD_NBORDER + 1, MD_STEP2 = MD_CACC + 1;
+// candidate radius of the descriptor's radial walk: rc_rad + CAND_MARGIN;
+// between full walks no atom may have moved more than CAND_TRIGGER (below
+// half the margin, which keeps every pair that can be inside rc_rad among the
+// candidates)
+constexpr double CAND_MARGIN = 0.2, CAND_TRIGGER = 0.09;
+static_assert(MD_STEP2 < 32, "MD state words");
 constexpr int MD_WORDS = 32;
 
 __device__ inline void latch_error(int *status, int code)

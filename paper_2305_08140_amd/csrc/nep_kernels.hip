@@ -123,6 +123,12 @@ __device__ __forceinline__ void angular_sums_l34(const PairConsts &pc, const dou
     }
 }
 
+// Radial walk modes of descriptor_sums: every entry of the radial list, or
+// every entry and the candidate mask (entries within rc_cand) written, or the
+// candidates of the last full walk only (valid while no atom has moved by
+// half of rc_cand - rc_rad since then).
+constexpr int CAND_OFF = 0, CAND_WRITE = 1, CAND_READ = 2;
+
 // Descriptor sums of one atom.  The radial sums F_k = sum_j f_k(r_ij) and
 // the angular sums S[n][lm] = sum_j g_n(r_ij) Y_lm(u_ij) for l <= 3 are
 // formed and accumulated in double precision: near a lattice site the odd-l
@@ -136,7 +142,7 @@ __device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const doub
                                                 const int32_t *__restrict__ nl_ang,
                                                 const int32_t *__restrict__ nl_rad, int naf, int nab, int nrf,
                                                 int nrb, const double *__restrict__ C64, float F[KB],
-                                                float S[NA][NLM], double &ezbl, bool &overlap)
+                                                float S[NA][NLM], double &ezbl, bool &overlap, int cand_mode)
 {
     const double inv_rR = 1.0 / (double)pc.rc_rad, inv_rA = 1.0 / (double)pc.rc_ang;
     const double rcR2 = (double)pc.rc_rad * pc.rc_rad, rcA2 = (double)pc.rc_ang * pc.rc_ang;
@@ -197,21 +203,45 @@ __device__ __forceinline__ void descriptor_sums(const PairConsts &pc, const doub
 #pragma unroll
             for (int m = 0; m < 8; ++m) S[n][m] = (float)(A[n][m] * (double)sph_norm(m));
     }
-    MaskWriter mw;
-    for (NeighbourPipe q(nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.s < q.count;) {
-        const int s = q.s;
-        int32_t e;
-        double px, py, pz;
-        q.pop(nl_rad, xq, base, jmask, e, px, py, pz);
-        double dx, dy, dz;
-        pair_vector_p(e, pc, px, py, pz, xi, yi, zi, cg, dx, dy, dz);
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        mw.add(pc.rmask, pc.n, t, s, q.count, r2 < rcR2);
-        if (r2 >= rcR2) continue;
-        double fc, T[KB];
-        basis_d(dist_d(r2), inv_rR, fc, T);
+    if (cand_mode == CAND_READ) {
+        // the candidates of the last full walk: every entry inside rc_rad now
+        // is among them; the inside bits of the others are stored as zero
+        SparseMaskWriter mw(pc.rmask, pc.n, t, nrf + nrb);
+        for (MaskPipe q(pc.cmask, nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.valid();) {
+            int32_t e;
+            double px, py, pz;
+            int s;
+            q.pop(nl_rad, xq, base, jmask, e, px, py, pz, s);
+            double dx, dy, dz;
+            pair_vector_p(e, pc, px, py, pz, xi, yi, zi, cg, dx, dy, dz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 >= rcR2) continue;
+            mw.set(s);
+            double fc, T[KB];
+            basis_d(dist_d(r2), inv_rR, fc, T);
 #pragma unroll
-        for (int k = 0; k < KB; ++k) AR[k] = fma(fc, T[k], AR[k]);
+            for (int k = 0; k < KB; ++k) AR[k] = fma(fc, T[k], AR[k]);
+        }
+        mw.finish();
+    } else {
+        const double rcC2 = (double)pc.rc_cand * pc.rc_cand;
+        MaskWriter mw, cw;
+        for (NeighbourPipe q(nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.s < q.count;) {
+            const int s = q.s;
+            int32_t e;
+            double px, py, pz;
+            q.pop(nl_rad, xq, base, jmask, e, px, py, pz);
+            double dx, dy, dz;
+            pair_vector_p(e, pc, px, py, pz, xi, yi, zi, cg, dx, dy, dz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            mw.add(pc.rmask, pc.n, t, s, q.count, r2 < rcR2);
+            if (cand_mode == CAND_WRITE) cw.add(pc.cmask, pc.n, t, s, q.count, r2 < rcC2);
+            if (r2 >= rcR2) continue;
+            double fc, T[KB];
+            basis_d(dist_d(r2), inv_rR, fc, T);
+#pragma unroll
+            for (int k = 0; k < KB; ++k) AR[k] = fma(fc, T[k], AR[k]);
+        }
     }
 #pragma unroll
     for (int k = 0; k < KB; ++k) F[k] = (float)(0.5 * (AR[k] + AR[0]));
@@ -441,7 +471,7 @@ __device__ __forceinline__ void descriptor_atom(
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     const float *__restrict__ P, const double *__restrict__ C64, float4 *__restrict__ pair_grad,
     float4 *__restrict__ f_own, float *__restrict__ w_atom, double *__restrict__ e_atom,
-    int32_t *__restrict__ status)
+    int32_t *__restrict__ status, int cand_mode)
 {
     // With the MFMA hidden layer every lane of a wave takes part; lanes past
     // the last atom compute on an empty neighbourhood of atom 0 and store nothing.
@@ -461,7 +491,7 @@ __device__ __forceinline__ void descriptor_atom(
     double ezbl;
     bool overlap;
     descriptor_sums(pc, xq, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, C64, F, S, ezbl,
-                    overlap);
+                    overlap, cand_mode);
     if (overlap) latch_error(status, -4);
     float q[DIM];
     descriptor_vector(P, F, S, q);
@@ -604,24 +634,26 @@ __global__ __launch_bounds__(BS, NNMODE == 1 ? 1 : 2) void k_descriptor(
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     const float *__restrict__ P, const double *__restrict__ C64, float4 *__restrict__ pair_grad,
     float4 *__restrict__ f_own, float *__restrict__ w_atom, double *__restrict__ e_atom,
-    int32_t *__restrict__ status, int ntiles)
+    int32_t *__restrict__ status, int ntiles, const int32_t *__restrict__ cflag)
 {
     __shared__ NNLds lds[NNMODE != 0 ? BS / 64 : 1];
     NNLds *L = &lds[NNMODE != 0 ? threadIdx.x / 64 : 0];
     if (lists_blocked(status)) return;
+    // radial walk: in full (and the candidate mask written) when *cflag is set
+    const int cand_mode = *cflag ? CAND_WRITE : CAND_READ;
     if (PERSISTENT) {
         for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
             const int t = tile * BS + threadIdx.x;
             if (NNMODE != 0 || t < pc.n)
                 descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xq, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, C64, pair_grad,
-                                        f_own, w_atom, e_atom, status);
+                                        f_own, w_atom, e_atom, status, cand_mode);
         }
     } else {
         const int tile = xcd_block(ntiles);
         const int t = tile * BS + threadIdx.x;
         if (tile < ntiles && (NNMODE != 0 || t < pc.n))
             descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xq, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, C64, pair_grad,
-                                    f_own, w_atom, e_atom, status);
+                                    f_own, w_atom, e_atom, status, cand_mode);
     }
 }
 
@@ -837,17 +869,17 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_
                                                      const CellGeom *,                                             \
                                                      const int32_t *, const int32_t *, const uint32_t *,           \
                                                      const float *, const double *, float4 *, float4 *, float *, double *, int32_t *, \
-                                                     int);                                                           \
+                                                     int, const int32_t *);                                          \
     template __global__ void k_descriptor<BS, PE, 1>(PairConsts, const double4 *, AtomRec *, const int32_t *,      \
                                                      const CellGeom *,                                             \
                                                      const int32_t *, const int32_t *, const uint32_t *,           \
                                                      const float *, const double *, float4 *, float4 *, float *, double *, int32_t *, \
-                                                     int);                                                           \
+                                                     int, const int32_t *);                                          \
     template __global__ void k_descriptor<BS, PE, 2>(PairConsts, const double4 *, AtomRec *, const int32_t *,      \
                                                      const CellGeom *,                                             \
                                                      const int32_t *, const int32_t *, const uint32_t *,           \
                                                      const float *, const double *, float4 *, float4 *, float *, double *, int32_t *, \
-                                                     int);                                                           \
+                                                     int, const int32_t *);                                          \
     template __global__ void k_force<BS, PE>(PairConsts, const AtomRec *, const int32_t *, const CellGeom *,       \
                                              const int32_t *, const int32_t *, const uint32_t *, const uint8_t *,   \
                                              const float4 *, const float4 *, const int32_t *, float *, float *,      \
@@ -935,7 +967,7 @@ __global__ __launch_bounds__(64) void k_param_grad(
         double ezbl;
         bool overlap;
         descriptor_sums(pc, xq, t, xi, yi, zi, cg, base, nl_ang, nl_rad, naf, nab, nrf, nrb, C64, F, S, ezbl,
-                        overlap);
+                        overlap, CAND_OFF);
         float q[DIM];
         descriptor_vector(P, F, S, q);
         // network with the per-neuron factors (outer-product ones to LDS,
@@ -1329,7 +1361,7 @@ __global__ __launch_bounds__(POP_DESC_BS, 2) void k_pop_descriptor(
     const size_t n = (size_t)pc.n;
     descriptor_atom<0>(t, true, lds, pc, xq, xp + m * n, cell_of, cells, nl_ang, nl_rad, ncnt,
                        P + (size_t)m * P_SIZE, C64 + (size_t)m * C64N, pair_grad + (size_t)m * pc.capA * n,
-                       f_own + m * n, w_atom + 9 * m * n, e_atom + m * n, status);
+                       f_own + m * n, w_atom + 9 * m * n, e_atom + m * n, status, CAND_OFF);
 }
 
 // forces of member m go to F + 3 m n (fx), + (3 m + 1) n (fy), + (3 m + 2) n (fz), caller order

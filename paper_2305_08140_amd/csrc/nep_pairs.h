@@ -131,6 +131,37 @@ struct MaskWriter {
     }
 };
 
+// The same bits when only some entries are visited (in increasing order):
+// set(s) marks entry s, and every word up to the last is stored once.
+struct SparseMaskWriter {
+    uint32_t *__restrict__ mask;
+    size_t n;
+    int t, nw, w;
+    uint32_t bits;
+    __device__ SparseMaskWriter(uint32_t *__restrict__ m, int n_, int t_, int count)
+        : mask(m), n((size_t)n_), t(t_), nw((count + 31) >> 5), w(0), bits(0)
+    {
+    }
+    __device__ void set(int s)
+    {
+        const int ws = s >> 5;
+        while (w < ws) {
+            mask[(size_t)w * n + t] = bits;
+            bits = 0;
+            ++w;
+        }
+        bits |= 1u << (s & 31);
+    }
+    __device__ void finish()
+    {
+        while (w < nw) {
+            mask[(size_t)w * n + t] = bits;
+            bits = 0;
+            ++w;
+        }
+    }
+};
+
 // The set bits of those words in order: next() returns the next entry index
 // inside the cutoff, or -1.
 struct MaskWalk {

@@ -279,6 +279,32 @@ def test_large_cascade_start_thermal_margin():
     assert uerr <= U_SITE_TOL
 
 
+def test_md_candidate_walk_matches_full_walk():
+    # between full radial walks the MD loop's descriptor visits only the
+    # radial-list entries that were within rc + 0.2 A at the last full walk;
+    # while no atom has moved 0.09 A since then every pair inside rc is among
+    # them, so the last MD evaluation must equal a fresh evaluation (full
+    # walk) of the same positions bit for bit.  128,000 atoms at 300 K, 40
+    # steps of 1 fs (a full walk about every 18 steps, the last step a
+    # candidate walk).
+    import torch
+    import paper_2305_08140_amd as nep
+    m = model()
+    s = nep_synth.mid()
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(m, s.n_atoms, 1)
+    out = nep.EFV(s.n_atoms, 1)
+    ctx.nep_step_verlet(sysd, 40, out, dt_max=1.0, max_disp=0.0)
+    torch.cuda.synchronize()
+    F_md = out.forces().cpu().numpy().copy()
+    E_md, W_md = out.energy.cpu().numpy().copy(), out.virial.cpu().numpy().copy()
+    ctx.nep_compute_efv(sysd, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(F_md, out.forces().cpu().numpy())
+    assert np.array_equal(E_md, out.energy.cpu().numpy())
+    assert np.array_equal(W_md, out.virial.cpu().numpy())
+
+
 def test_verlet_trajectory_thermal():
     # 16,000-atom bcc W at 300 K: 10 steps against the oracle's trajectory
     import torch
