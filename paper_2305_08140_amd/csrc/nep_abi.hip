@@ -836,7 +836,8 @@ static void launch_wide_desc(nep_ctx *c, hipStream_t st)
 {
     const int n = c->pc.n, grid = xcd_grid((n + WBS - 1) / WBS);
     k_w_radial<<<grid, WBS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->params,
-                                     c->w_Q, c->e_atom, c->status);
+                                     c->w_Q, c->e_atom, c->status,
+                                     c->cflag);
     for (int g = 0; g < WNGA; ++g)
         k_w_angular<<<grid, WBS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->c64, g,
                                           c->w_S, c->w_Q);

@@ -55,7 +55,7 @@ static_assert(sizeof(WAtomRec) == 96, "WAtomRec must be 96 bytes");
 __global__ void k_w_params64(const float *P, double *C64);
 __global__ void k_w_radial(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
                            const int32_t *nl_ang, const int32_t *nl_rad, const uint32_t *ncnt, const float *P,
-                           float *Q, double *e_atom, int32_t *status);
+                           float *Q, double *e_atom, int32_t *status, const int32_t *cflag);
 __global__ void k_w_angular(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
                             const int32_t *nl_ang, const uint32_t *ncnt, const double *C64, int group, float *S,
                             float *Q);

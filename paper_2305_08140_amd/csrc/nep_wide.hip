@@ -61,12 +61,14 @@ __global__ void k_w_params64(const float *__restrict__ P, double *__restrict__ C
 }
 
 // Radial sums F_k = sum_j f_k(r_ij) over both lists (FP64), descriptors
-// q_n = sum_k c_nk F_k -> Q[n][t]; ZBL half energies -> e_atom[t].
+// q_n = sum_k c_nk F_k -> Q[n][t]; ZBL half energies -> e_atom[t].  The
+// radial list is walked in full when *cflag is set, else over the candidates
+// of the last full walk (see the default model's descriptor_sums).
 __global__ __launch_bounds__(WBS) void k_w_radial(
     PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const int32_t *__restrict__ nl_rad,
     const uint32_t *__restrict__ ncnt, const float *__restrict__ P, float *__restrict__ Q,
-    double *__restrict__ e_atom, int32_t *__restrict__ status)
+    double *__restrict__ e_atom, int32_t *__restrict__ status, const int32_t *__restrict__ cflag)
 {
     const int t = tile_atom(pc.n);
     if (t >= pc.n || lists_blocked(status)) return;
@@ -82,37 +84,68 @@ __global__ __launch_bounds__(WBS) void k_w_radial(
     for (int k = 0; k < WKR; ++k) AR[k] = 0.0;
     double ezbl = 0.0;
     bool overlap = false;
-    for (int list = 0; list < 2; ++list) {
-        const int32_t *nl = list == 0 ? nl_ang : nl_rad;
-        const int nf = list == 0 ? naf : nrf, nb = list == 0 ? nab : nrb;
-        const int cap = list == 0 ? pc.capA : pc.capR;
-        MaskWriter mw;
-        // angular list: the entries within the pair-gradient write radius
-        // (with a margin) for the angular phases; radial list: the entries
-        // inside rc_rad for the force kernel
+    auto radial_term = [&](double r2) {
+        const double r = dist_d(r2);
+        overlap |= (r < 1e-3);
+        double fc, T[WKR];
+        basis_w<WKR>(r, inv_rR, fc, T);
+#pragma unroll
+        for (int k = 0; k < WKR; ++k) AR[k] = fma(fc, T[k], AR[k]);
+        if (r < (double)pc.zbl_r2) {
+            double U, dU;
+            zbl_pair(r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
+            ezbl += 0.5 * U;
+        }
+    };
+    {
+        // angular list: every entry, marking those within the pair-gradient
+        // write radius (with a margin) for the angular phases
         const double awr = (double)pc.rc_ang2_write * (1.0 + 0x1p-15);
-        for (NeighbourPipe q(nl, xq, base, jmask, t, pc.n, nf, nb, cap); q.s < q.count;) {
+        MaskWriter mw;
+        for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
             const int s = q.s;
             int32_t e;
             double px, py, pz;
-            q.pop(nl, xq, base, jmask, e, px, py, pz);
+            q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
             double dx, dy, dz;
             pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
             const double r2 = dx * dx + dy * dy + dz * dz;
-            if (list == 0) mw.add(pc.amask, pc.n, t, s, q.count, r2 < awr);
-            else mw.add(pc.rmask, pc.n, t, s, q.count, r2 < rcR2);
+            mw.add(pc.amask, pc.n, t, s, q.count, r2 < awr);
+            if (r2 < rcR2) radial_term(r2);
+        }
+    }
+    // radial list: the entries inside rc_rad marked for the force kernel; in
+    // full (with the candidate mask written, as the default model's
+    // descriptor) or over the last full walk's candidates
+    if (*cflag == 0) {
+        SparseMaskWriter mw(pc.rmask, pc.n, t, nrf + nrb);
+        for (MaskPipe q(pc.cmask, nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.valid();) {
+            int32_t e;
+            double px, py, pz;
+            int s;
+            q.pop(nl_rad, xq, base, jmask, e, px, py, pz, s);
+            double dx, dy, dz;
+            pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
             if (r2 >= rcR2) continue;
-            const double r = dist_d(r2);
-            overlap |= (r < 1e-3);
-            double fc, T[WKR];
-            basis_w<WKR>(r, inv_rR, fc, T);
-#pragma unroll
-            for (int k = 0; k < WKR; ++k) AR[k] = fma(fc, T[k], AR[k]);
-            if (r < (double)pc.zbl_r2) {
-                double U, dU;
-                zbl_pair(r, (double)pc.zbl_z, (double)pc.zbl_r1, (double)pc.zbl_r2, U, dU);
-                ezbl += 0.5 * U;
-            }
+            mw.set(s);
+            radial_term(r2);
+        }
+        mw.finish();
+    } else {
+        const double rcC2 = (double)pc.rc_cand * pc.rc_cand;
+        MaskWriter mw, cw;
+        for (NeighbourPipe q(nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.s < q.count;) {
+            const int s = q.s;
+            int32_t e;
+            double px, py, pz;
+            q.pop(nl_rad, xq, base, jmask, e, px, py, pz);
+            double dx, dy, dz;
+            pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            mw.add(pc.rmask, pc.n, t, s, q.count, r2 < rcR2);
+            cw.add(pc.cmask, pc.n, t, s, q.count, r2 < rcC2);
+            if (r2 < rcR2) radial_term(r2);
         }
     }
     if (overlap) latch_error(status, -4);

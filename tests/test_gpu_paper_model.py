@@ -91,3 +91,23 @@ def test_unsupported_calls_are_refused():
     with pytest.raises(nep.NepError) as e:
         ctx.nep_backward(sysd, out, torch.ones(1, dtype=torch.float64, device="cuda"))
     assert e.value.code == nep.NEP_E_UNSUPPORTED
+
+
+def test_md_candidate_walk_matches_full_walk():
+    # the radial walk over the last full walk's candidates (as in the default
+    # model): the last MD evaluation equals a fresh full evaluation bit for bit
+    import torch
+    import paper_2305_08140_amd as nep
+    m = pmodel()
+    s = nep_synth.mid(n_cells=24)
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(m, s.n_atoms, 1)
+    out = nep.EFV(s.n_atoms, 1)
+    ctx.nep_step_verlet(sysd, 30, out, dt_max=1.0, max_disp=0.0)
+    torch.cuda.synchronize()
+    F_md = out.forces().cpu().numpy().copy()
+    E_md = out.energy.cpu().numpy().copy()
+    ctx.nep_compute_efv(sysd, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(F_md, out.forces().cpu().numpy())
+    assert np.array_equal(E_md, out.energy.cpu().numpy())
