@@ -197,6 +197,21 @@ def summarize_rocprof(kt_dir, fetch_dir, write_dir, n_atoms, command, out_dir):
         name = r["Name"].split("(")[0]
         lines.append("| %s | %s | %.3f | %.1f |" % (name, r["Calls"], float(r["AverageNs"]) / 1e6,
                                                     float(r["Percentage"])))
+    # the list-build kernels are launched every step and return at once
+    # unless an atom moved more than skin/2: their cost per actual rebuild
+    trace = glob.glob(os.path.join(kt_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if trace:
+        dur = {}
+        for r in csv.DictReader(open(trace[0])):
+            name = r["Kernel_Name"].split("(")[0]
+            if "build" in name:
+                dur.setdefault(name, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
+        lines += ["", "List build per rebuild (launches longer than 0.5 ms; the others found no rebuild due):", "",
+                  "| kernel | rebuilds | avg ms per rebuild |", "|---|---|---|"]
+        for name, d in sorted(dur.items()):
+            big = [x for x in d if x > 0.5]
+            if big:
+                lines.append("| %s | %d | %.3f |" % (name, len(big), float(np.mean(big))))
     with open(os.path.join(out_dir, "nep_md_%d_kernel_stats.md" % n_atoms), "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -223,12 +238,13 @@ def summarize_rocprof(kt_dir, fetch_dir, write_dir, n_atoms, command, out_dir):
              "its true bytes; all values below are scaled by those factors." % (1 / f_fac, 1 / w_fac), "",
              "| kernel | launches | GB read | GB written | bytes/atom |", "|---|---|---|---|---|"]
     for k in ("nep::k_descriptor", "nep::k_force", "nep::k_sort_positions", "nep::k_kick_drift",
-              "nep::k_kick", "nep::k_reduce_chunks", "nep::k_build_lists", "nep::k_build_reverse"):
+              "nep::k_kick", "nep::k_reduce_chunks", "nep::k_build_lists_blocks", "nep::k_build_lists",
+              "nep::k_build_reverse"):
         if k not in fe or k not in wr:
             continue
         rd = float(np.median(fe[k])) * 1024 * f_fac
         wb = float(np.median(wr[k])) * 1024 * w_fac
-        if k in ("nep::k_build_lists", "nep::k_build_reverse"):
+        if k in ("nep::k_build_lists_blocks", "nep::k_build_lists", "nep::k_build_reverse"):
             rd = max(fe[k]) * 1024 * f_fac
             wb = max(wr[k]) * 1024 * w_fac
         out["kernels"][k.split("::")[1]] = {"read_bytes": rd, "write_bytes": wb, "bytes_per_launch": rd + wb}
@@ -564,10 +580,12 @@ def main():
                      "--nve-steps 0 --paper-steps 0" % kt_dir,
                "fetch": "rocprofv3 --pmc FETCH_SIZE -d %s -o f --output-format csv -- "
                         "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batches --foil-steps 0 "
-                        "--snes-gens 0 --nve-steps 0 --copy-calibration-mib 1024 --timing-reps 1" % fetch_dir,
+                        "--snes-gens 0 --nve-steps 0 --paper-steps 0 --rebuild-probe-steps 0 "
+                        "--copy-calibration-mib 1024 --timing-reps 1" % fetch_dir,
                "write": "rocprofv3 --pmc WRITE_SIZE -d %s -o w --output-format csv -- "
                         "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batches --foil-steps 0 "
-                        "--snes-gens 0 --nve-steps 0 --copy-calibration-mib 1024 --timing-reps 1" % write_dir}
+                        "--snes-gens 0 --nve-steps 0 --paper-steps 0 --rebuild-probe-steps 0 "
+                        "--copy-calibration-mib 1024 --timing-reps 1" % write_dir}
         summarize_rocprof(*args.summarize_rocprof, n, cmd, os.path.join(ROOT, "profiles"))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
