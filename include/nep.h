@@ -58,8 +58,9 @@ typedef struct nep_ctx nep_ctx;
  *     k_rad = k_ang = 9 (Chebyshev k = 0..8), l_max = 4, n_hidden = 30;
  *   the paper's model size: n_rad = k_rad = 16 (n_max^R = 15), n_ang = k_ang
  *     = 11 (n_max^A = 10), l_max = 4, n_hidden = 100.  It supports every call
- *     except nep_backward, nep_autotune and nep_set_precision modes 1 and 2,
- *     which return NEP_E_UNSUPPORTED for it.
+ *     except nep_autotune and nep_set_precision modes 1 and 2, which return
+ *     NEP_E_UNSUPPORTED for it, and the population (evolution-strategy)
+ *     calls noted below.
  * Other values give NEP_E_UNSUPPORTED. */
 typedef struct {
     int32_t n_rad;      /* radial descriptor components */
@@ -278,8 +279,11 @@ int nep_num_params(const nep_ctx *ctx);
  * most 1024 blocks), the partials summed in a fixed tree.  The first call,
  * or a call on more atoms than any before, allocates those partials in the
  * context (min(ceil(n_atoms / 64), 1024) x nep_num_params doubles, at most
- * 8.7 MB); they are freed by nep_destroy.  Returns NEP_OK, NEP_E_ARG,
- * NEP_E_STATE or NEP_E_HIP; device errors are latched as for nep_compute_efv. */
+ * 8.7 MB for the default model, 53.9 MB for the paper-size one); they are
+ * freed by nep_destroy.  For the paper-size model the call first recomputes
+ * the staged descriptor sums of the current positions (as nep_compute_efv
+ * does before its force kernel).  Returns NEP_OK, NEP_E_ARG, NEP_E_STATE or
+ * NEP_E_HIP; device errors are latched as for nep_compute_efv. */
 int nep_backward(nep_ctx *ctx, const nep_system *sys, const nep_efv *out, const double *gE,
                  double *grad_params, double *grad_x, double *grad_y, double *grad_z, double *grad_h,
                  void *stream);
@@ -289,15 +293,14 @@ int nep_backward(nep_ctx *ctx, const nep_system *sys, const nep_efv *out, const 
  * Same arguments, preconditions, results (bit for bit) and errors as
  * nep_backward, and it calls no allocating routine.  The block partials live
  * in one file-scope device array per GPU instead of the context: 1024 rows of
- * nep_num_params doubles (8.7 MB), the most any launch uses, so every system
- * the context accepts fits (NEP_E_CAPACITY would report a launch wider than
- * the array).  The array's address on a GPU is resolved by nep_create with
+ * 6,578 doubles (53.9 MB; the paper-size model's parameter count, the larger
+ * one), the most any launch uses, so every system a context of either model
+ * accepts fits (NEP_E_CAPACITY would report a launch wider than the array).  The array's address on a GPU is resolved by nep_create with
  * that GPU current and held until the process ends.  All calls on one GPU
  * share the array, which keeps the last call's partials (each call zeroes
  * the rows it uses before adding to them): two calls that overlap in time on
  * the same GPU, on different streams or from different threads, race and
- * give wrong gradients; serialise them.  The default model only
- * (NEP_E_UNSUPPORTED for the paper-size model, as nep_backward). */
+ * give wrong gradients; serialise them. */
 int nep_backward_noalloc(nep_ctx *ctx, const nep_system *sys, const nep_efv *out, const double *gE,
                          double *grad_params, double *grad_x, double *grad_y, double *grad_z,
                          double *grad_h, void *stream);

@@ -30,7 +30,7 @@ __global__ void k_param_grad(PairConsts, const double4 *, const int32_t *, const
                              const int32_t *, const uint32_t *, const float *, const double *, const double *,
                              double *, int32_t *, int);
 __global__ void k_params64(const float *, double *);
-__global__ void k_param_reduce(int, const double *, double *);
+__global__ void k_param_reduce(int, int, const double *, double *);
 __global__ void k_grad_pos(int, const int32_t *, const double *, const float *, const float *, const float *,
                            double *, double *, double *);
 __global__ void k_grad_cell(const CellGeom *, const double *, const double *, const double *, const float *,
@@ -249,12 +249,15 @@ static constexpr int N_PARAMS = NR * KB + NA * KB + NH * DIM + NH + NH + 1;
 
 // Allocation-free backward: the parameter-gradient block partials live in a
 // file-scope device array instead of the context.  It holds the partials of
-// the widest launch the backward makes (PG_MAX_BLOCKS rows of N_PARAMS
-// doubles, 8.7 MB), so every system a context accepts fits.  Each device
-// keeps its own copy until the process ends; host code reaches it only
-// through the address resolved per device below, never through the name.
+// the widest launch the backward makes (PG_MAX_BLOCKS rows of the larger
+// model's parameter count, W_NPARAM doubles: 53.9 MB), so every system a
+// context of either model accepts fits, with the same rows as nep_backward.
+// Each device keeps its own copy until the process ends; host code reaches
+// it only through the address resolved per device below, never through the
+// name.
 static constexpr int PG_MAX_BLOCKS = 1024;
-static __device__ __align__(256) double scratch[PG_MAX_BLOCKS * N_PARAMS];
+static constexpr int PG_MAX_PARAMS = N_PARAMS > W_NPARAM ? N_PARAMS : W_NPARAM;
+static __device__ __align__(256) double scratch[(size_t)PG_MAX_BLOCKS * PG_MAX_PARAMS];
 static constexpr int SCRATCH_MAX_DEVICES = 64;
 static std::mutex g_scratch_mu;
 static double *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
@@ -356,7 +359,7 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     c->cfg = *cfg;
     c->wide = wide;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return NEP_E_HIP; }
-    if (!wide) {
+    {
         // the allocation-free backward's scratch address on this device
         double *sp = nullptr;
         const int src = scratch_address(c->device, &sp);
@@ -831,8 +834,9 @@ static void launch_force(nep_ctx *c, int shape, const nep_efv *o, hipStream_t st
 
 extern "C" {
 
-// The paper-size model's descriptor phases and force kernel (nep_wide.h).
-static void launch_wide_desc(nep_ctx *c, hipStream_t st)
+// The paper-size model's descriptor phases and force kernel (nep_wide.h):
+// the staged sums, descriptors and network adjoints ...
+static void launch_wide_sums(nep_ctx *c, hipStream_t st)
 {
     const int n = c->pc.n, grid = xcd_grid((n + WBS - 1) / WBS);
     k_w_radial<<<grid, WBS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->params,
@@ -842,6 +846,13 @@ static void launch_wide_desc(nep_ctx *c, hipStream_t st)
         k_w_angular<<<grid, WBS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->c64, g,
                                           c->w_S, c->w_Q);
     k_w_network<<<grid, WBS, 0, st>>>(n, c->xq, c->params, c->w_Q, c->xw, c->w_FpA, c->e_atom);
+}
+
+// ... then the pair gradients
+static void launch_wide_desc(nep_ctx *c, hipStream_t st)
+{
+    const int n = c->pc.n, grid = xcd_grid((n + WBS - 1) / WBS);
+    launch_wide_sums(c, st);
     k_w_grad<<<grid, WBS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->params, c->c64, c->w_S,
                                    c->w_FpA, c->pair_grad, c->f_own, c->w_atom);
 }
@@ -963,7 +974,7 @@ int nep_set_precision(nep_ctx *c, int32_t mode)
 int nep_num_params(const nep_ctx *c)
 {
     if (!c) return NEP_E_ARG;
-    if (c->wide) return WR * WKR + WA * WKA + WH * WDIM + WH + WH + 1;
+    if (c->wide) return W_NPARAM;
     return N_PARAMS;
 }
 
@@ -972,7 +983,6 @@ static int backward_checks(nep_ctx *c, const nep_system *s, const nep_efv *o, co
                            const double *gh)
 {
     if (!c || !gE || !grad_params) return NEP_E_ARG;
-    if (c->wide) return NEP_E_UNSUPPORTED;
     int rc = check_system(c, s, false);
     if (rc) return rc;
     if ((rc = check_out(o))) return rc;
@@ -990,9 +1000,19 @@ static int backward_launch(nep_ctx *c, const nep_system *s, const nep_efv *o, co
     const int n = (int)s->n_atoms;
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
                                                        c->cells, c->xq, c->status, nullptr);
-    k_param_grad<<<blocks, 64, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
-                                        c->params, c->c64, gE, part, c->status, tiles);
-    k_param_reduce<<<(N_PARAMS + 31) / 32, 256, 0, st>>>(blocks, part, grad_params);
+    if (c->wide) {
+        // the staged sums, descriptors and adjoints of these positions (a
+        // full radial walk, as in any evaluation outside the MD loop)
+        k_set_flag<<<1, 64, 0, st>>>(c->cflag, 1);
+        launch_wide_sums(c, st);
+        k_w_param_grad<<<blocks, 64, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
+                                              c->params, c->w_Q, c->w_S, c->w_FpA, gE, part, c->status, tiles);
+    } else {
+        k_param_grad<<<blocks, 64, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
+                                            c->params, c->c64, gE, part, c->status, tiles);
+    }
+    const int np = nep_num_params(c);
+    k_param_reduce<<<(np + 31) / 32, 256, 0, st>>>(blocks, np, part, grad_params);
     if (gx) k_grad_pos<<<grid_for(n, 256), 256, 0, st>>>(n, c->cell_of, gE, o->fx, o->fy, o->fz, gx, gy, gz);
     if (gh)
         k_grad_cell<<<c->built_cells, 256, 0, st>>>(c->cells, s->x, s->y, s->z, o->fx, o->fy, o->fz, o->virial,
@@ -1011,7 +1031,7 @@ int nep_backward(nep_ctx *c, const nep_system *s, const nep_efv *o, const double
     if (blocks > c->pg_blocks) {
         if (c->pg_part) (void)hipFree(c->pg_part);
         c->pg_part = nullptr;
-        HIP_TRY(hipMalloc(&c->pg_part, (size_t)blocks * N_PARAMS * sizeof(double)));
+        HIP_TRY(hipMalloc(&c->pg_part, (size_t)blocks * nep_num_params(c) * sizeof(double)));
         c->pg_blocks = blocks;
     }
     return backward_launch(c, s, o, gE, grad_params, gx, gy, gz, gh, c->pg_part, blocks, tiles,
@@ -1025,7 +1045,7 @@ int nep_backward_noalloc(nep_ctx *c, const nep_system *s, const nep_efv *o, cons
     if (rc) return rc;
     const int tiles = (int)((s->n_atoms + 63) / 64);
     const int blocks = std::min(tiles, PG_MAX_BLOCKS);
-    if (blocks > PG_MAX_BLOCKS) return NEP_E_CAPACITY;
+    if ((size_t)blocks * nep_num_params(c) > (size_t)PG_MAX_BLOCKS * PG_MAX_PARAMS) return NEP_E_CAPACITY;
     double *part = nullptr;
     if ((rc = scratch_address(c->device, &part))) return rc;
     // every block zeroes its own rows before adding to them, so the rows a

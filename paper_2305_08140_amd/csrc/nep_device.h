@@ -135,6 +135,15 @@ __device__ inline void latch_error(int *status, int code)
     atomicCAS(status + ST_ERR, 0, code);
 }
 
+// Sum over the 64 lanes of a wavefront, the same total in every lane (xor
+// butterfly: a fixed order of additions, so the result is deterministic).
+__device__ __forceinline__ float wave_sum64(float v)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
 // Entry check of the kernels that walk the neighbour lists: true if they
 // must do nothing, either because an error is latched or because the lists
 // are unusable (then NEP_E_STATE is latched, so the call reports an error

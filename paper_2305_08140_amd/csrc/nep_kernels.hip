@@ -914,15 +914,6 @@ constexpr int PG_DZ = 0, PG_QT = PG_DZ + NH, PG_FPR = PG_QT + DIM, PG_F = PG_FPR
 // g G_nk, g (one value per tile, summed across the wave in a fixed order).
 constexpr int PS_TH = 0, PS_G = PS_TH + NH, PS_W = PS_G + NA * KB, PS_N = PS_W + 1;
 
-// Sum over the 64 lanes of a wavefront, the same total in every lane (xor
-// butterfly: a fixed order of additions, so the result is deterministic).
-__device__ __forceinline__ float wave_sum64(float v)
-{
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
-
 // Gradient of sum_i gE[cell(i)] U_i with respect to theta.  Per atom:
 //   dU/dw1_mu = tanh z_mu, dU/db0_mu = -dz_mu, dU/dw0_mu,nu = dz_mu s_nu q_nu,
 //   dU/db1 = -1, dU/dc^R_nk = (dU/dq_n) F_k,
@@ -1087,20 +1078,21 @@ __global__ __launch_bounds__(64) void k_param_grad(
 // partials b = c, c + 8, c + 16, ... of output p (each step reads 32
 // consecutive doubles per c), and the eight chunk sums of an output are then
 // added in chunk order.
-__global__ __launch_bounds__(256) void k_param_reduce(int nblocks, const double *__restrict__ part,
+// Rows of `nparam` doubles (either model's parameter count).
+__global__ __launch_bounds__(256) void k_param_reduce(int nblocks, int nparam, const double *__restrict__ part,
                                                       double *__restrict__ grad)
 {
     __shared__ double sh[8][33];
     const int p = threadIdx.x & 31, c = threadIdx.x >> 5;
     const int o = blockIdx.x * 32 + p;
     double s = 0.0;
-    if (o < NPARAM) {
+    if (o < nparam) {
 #pragma unroll 4
-        for (int b = c; b < nblocks; b += 8) s += part[(size_t)b * NPARAM + o];
+        for (int b = c; b < nblocks; b += 8) s += part[(size_t)b * nparam + o];
     }
     sh[c][p] = s;
     __syncthreads();
-    if (c == 0 && o < NPARAM) {
+    if (c == 0 && o < nparam) {
         double t = sh[0][p];
 #pragma unroll
         for (int k = 1; k < 8; ++k) t += sh[k][p];

@@ -11,6 +11,7 @@
 //                 atom's record (position + 16 radial adjoints, 96 bytes)
 //   k_w_grad      dU_i/dr_ij of every angular slot, channel group by group
 //   k_w_force     radial + ZBL pair forces, angular assembly, virial
+// and, for the parameter gradient, k_w_param_grad after the first three.
 #pragma once
 #include "nep_device.h"
 
@@ -41,6 +42,8 @@ constexpr int W_B1 = W_W1 + WH;
 constexpr int W_SIZE = W_B1 + 1;
 // double copy of the angular coefficients and their row sums
 constexpr int W_C64 = WA * WKA + WA;
+// trainable parameters, in the order of the gradient: c_rad, c_ang, w0, b0, w1, b1
+constexpr int W_NPARAM = WR * WKR + WA * WKA + WH * WDIM + WH + WH + 1;
 
 // the force kernel's per-neighbour record: 88 bytes padded to 96, six
 // 16-byte pieces per gather (a 128-byte stride would cost eight, and
@@ -68,5 +71,9 @@ __global__ void k_w_force(PairConsts pc, const WAtomRec *xw, const int32_t *cell
                           const int32_t *nl_ang, const int32_t *nl_rad, const uint32_t *ncnt, const uint8_t *rev,
                           const float4 *pair_grad, const float4 *f_own, const int32_t *perm, float *fx, float *fy,
                           float *fz, float *w_atom, int32_t *status);
+__global__ void k_w_param_grad(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
+                               const int32_t *nl_ang, const int32_t *nl_rad, const uint32_t *ncnt, const float *P,
+                               const float *Q, const float *S, const float *FpA, const double *gE, double *part,
+                               int32_t *status, int ntiles);
 
 }  // namespace nep

@@ -572,4 +572,215 @@ __global__ __launch_bounds__(WBS_F) void k_w_force(
     for (int k = 0; k < 9; ++k) w[k] = fmaf(-0.5f, W[k], w[k]);
 }
 
+
+// ------------------------------------------------------------------ parameter gradients
+
+// Per-atom factors of the two outer-product blocks in LDS (odd row stride):
+// g dz_mu, s q (unweighted), g dU/dq_n (radial), F_k (unweighted); and the
+// tile sums of the factors that enter linearly: g tanh z_mu, g G_ck, g.
+constexpr int WPG_DZ = 0, WPG_QT = WPG_DZ + WH, WPG_FPR = WPG_QT + WDIM, WPG_F = WPG_FPR + WR,
+              WPG_REC = WPG_F + WKR + 1;
+constexpr int WPS_TH = 0, WPS_G = WPS_TH + WH, WPS_W = WPS_G + WA * WKA, WPS_N = WPS_W + 1;
+
+// G_ck = sum_j f_k(r_ij) sum_lm B_{c,lm} y_lm(u_ij) of the channels
+// c0 .. c0+NC-1 over the marked angular entries, with B_{c,lm} =
+// 2 sph_norm(lm) (dU/dq_cl) s_{c,lm}; the tile sums of g G_ck go to tsum.
+template <int NC>
+__device__ __forceinline__ void w_pg_angular_group(const PairConsts &pc, const double4 *__restrict__ xq, int t,
+                                                   const CellGeom *cg, const int32_t *__restrict__ nl_ang,
+                                                   int naf, int nab, const float *__restrict__ S,
+                                                   const float *__restrict__ FpA, int c0, float g,
+                                                   float *__restrict__ tsum)
+{
+    const size_t n = (size_t)pc.n;
+    const double4 pi = xq[t];
+    const int base = cg->atom_start;
+    const uint32_t jmask = (1u << pc.jbits) - 1u;
+    const double inv_rA = 1.0 / (double)pc.rc_ang, rcA2 = (double)pc.rc_ang * pc.rc_ang;
+    float B[NC][NLM], G[NC][WKA];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+#pragma unroll
+        for (int lm = 0; lm < NLM; ++lm) {
+            const int l = lm < 3 ? 1 : (lm < 8 ? 2 : (lm < 15 ? 3 : 4));
+            B[c][lm] = (2.0f * sph_norm(lm)) * FpA[(WA * (l - 1) + c0 + c) * n + t] *
+                       S[((size_t)(c0 + c) * NLM + lm) * n + t];
+        }
+#pragma unroll
+        for (int k = 0; k < WKA; ++k) G[c][k] = 0.0f;
+    }
+    for (MaskPipe q(pc.amask, nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.valid();) {
+        int32_t e;
+        double px, py, pz;
+        int s;
+        q.pop(nl_ang, xq, base, jmask, e, px, py, pz, s);
+        double dx, dy, dz;
+        pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= rcA2) continue;
+        const double r = dist_d(r2);
+        double rinv = (double)frcp((float)r);
+        rinv = rinv * fma(-r, rinv, 2.0);
+        rinv = rinv * fma(-r, rinv, 2.0);
+        double fc, T[WKA];
+        basis_w<WKA>(r, inv_rA, fc, T);
+        float Y[NLM];
+        sph_unnorm(SphMono((float)(dx * rinv), (float)(dy * rinv), (float)(dz * rinv)), Y);
+        const float hfc = (float)(0.5 * fc);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            float E = 0.0f;
+#pragma unroll
+            for (int lm = 0; lm < NLM; ++lm) E = fmaf(B[c][lm], Y[lm], E);
+            const float hE = hfc * E;      // f_k = (T_k + 1) fc / 2
+#pragma unroll
+            for (int k = 0; k < WKA; ++k) G[c][k] = fmaf(hE, (float)(T[k] + 1.0), G[c][k]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < WKA; ++k) {
+            const float sg = wave_sum64(g * G[c][k]);
+            if (threadIdx.x == 0) tsum[WPS_G + (c0 + c) * WKA + k] = sg;
+        }
+}
+
+// Gradient of sum_i gE[cell(i)] U_i with respect to theta for the
+// paper-size model, from the staged descriptors Q, angular sums S and
+// angular adjoints FpA of the current positions (the first three phases):
+//   dU/dw1_mu = tanh z_mu, dU/db0_mu = -dz_mu, dU/dw0_mu,nu = dz_mu s_nu q_nu,
+//   dU/db1 = -1, dU/dc^R_nk = (dU/dq_n) F_k,
+//   dU/dc^A_ck = sum_j f_k(r_ij) sum_lm B_{c,lm} y_lm(u_ij),
+// with dz_mu = w1_mu (1 - tanh^2 z_mu), F_k = sum_j f_k(r_ij) over rc_rad
+// (Eqs. 2-4; the same decomposition as the default model's gradient).
+// 64-atom tiles, one wavefront per block; the outer products are summed
+// per output over the tile from LDS, one FP64 partial row per block.  Lanes
+// past the last atom evaluate atom 0 with weight 0.
+__global__ __launch_bounds__(64) void k_w_param_grad(
+    PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
+    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const int32_t *__restrict__ nl_rad,
+    const uint32_t *__restrict__ ncnt, const float *__restrict__ P, const float *__restrict__ Q,
+    const float *__restrict__ S, const float *__restrict__ FpA, const double *__restrict__ gE,
+    double *__restrict__ part, int32_t *__restrict__ status, int ntiles)
+{
+    __shared__ float rec[64][WPG_REC];
+    __shared__ float tsum[WPS_N];
+    constexpr int NOWN = (W_NPARAM + 63) / 64;
+    const int lane = threadIdx.x;
+    const size_t n = (size_t)pc.n;
+    double *pb = part + (size_t)blockIdx.x * W_NPARAM;
+    const bool ok = !lists_blocked(status);
+    for (int k = 0; k < NOWN; ++k) {
+        const int o = lane + 64 * k;
+        if (o < W_NPARAM) pb[o] = 0.0;
+    }
+    const double inv_rR = 1.0 / (double)pc.rc_rad, rcR2 = (double)pc.rc_rad * pc.rc_rad;
+    const uint32_t jmask = (1u << pc.jbits) - 1u;
+
+    for (int tile = blockIdx.x; tile < ntiles && ok; tile += gridDim.x) {
+        const bool valid = tile * 64 + lane < pc.n;
+        const int t = valid ? tile * 64 + lane : 0;
+        float *r = rec[lane];
+        const float g = valid ? (float)gE[cell_of[t]] : 0.0f;
+        // network forward and backward
+        float qt[WDIM], Fp[WDIM];
+#pragma unroll
+        for (int nu = 0; nu < WDIM; ++nu) {
+            qt[nu] = P[W_QS + nu] * Q[nu * n + t];
+            r[WPG_QT + nu] = qt[nu];
+            Fp[nu] = 0.0f;
+        }
+#pragma unroll 1
+        for (int mu = 0; mu < WH; ++mu) {
+            const float *w = P + W_W0 + mu * WDIM;
+            float z = -P[W_B0 + mu];
+#pragma unroll
+            for (int nu = 0; nu < WDIM; ++nu) z = fmaf(w[nu], qt[nu], z);
+            const float th = ftanh(z);
+            const float dz = P[W_W1 + mu] * fmaf(-th, th, 1.0f);
+            const float sth = wave_sum64(g * th);
+            if (lane == 0) tsum[WPS_TH + mu] = sth;
+            r[WPG_DZ + mu] = g * dz;
+#pragma unroll
+            for (int nu = 0; nu < WR; ++nu) Fp[nu] = fmaf(dz, w[nu], Fp[nu]);
+        }
+#pragma unroll
+        for (int m = 0; m < WR; ++m) r[WPG_FPR + m] = g * (Fp[m] * P[W_QS + m]);
+        // radial basis sums F_k over both lists (FP64, as the radial phase)
+        const CellGeom *cg = cells + cell_of[t];
+        const int base = cg->atom_start;
+        const double4 pi = xq[t];
+        const uint32_t cnt = ncnt[t];
+        const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
+        double AR[WKR];
+#pragma unroll
+        for (int k = 0; k < WKR; ++k) AR[k] = 0.0;
+        auto radial_term = [&](double r2) {
+            double fc, T[WKR];
+            basis_w<WKR>(dist_d(r2), inv_rR, fc, T);
+#pragma unroll
+            for (int k = 0; k < WKR; ++k) AR[k] = fma(fc, T[k], AR[k]);
+        };
+        for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
+            int32_t e;
+            double px, py, pz;
+            q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
+            double dx, dy, dz;
+            pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < rcR2) radial_term(r2);
+        }
+        for (MaskPipe q(pc.rmask, nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.valid();) {
+            int32_t e;
+            double px, py, pz;
+            int s;
+            q.pop(nl_rad, xq, base, jmask, e, px, py, pz, s);
+            double dx, dy, dz;
+            pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < rcR2) radial_term(r2);
+        }
+#pragma unroll
+        for (int k = 0; k < WKR; ++k) r[WPG_F + k] = (float)(0.5 * (AR[k] + AR[0]));
+        // angular coefficient sums, channel group by channel group
+#pragma unroll 1
+        for (int grp = 0; grp < WNG; ++grp) {
+            const int c0 = grp * WG;
+            if (WA - c0 >= WG) w_pg_angular_group<WG>(pc, xq, t, cg, nl_ang, naf, nab, S, FpA, c0, g, tsum);
+            else w_pg_angular_group<WA - (WNG - 1) * WG>(pc, xq, t, cg, nl_ang, naf, nab, S, FpA, c0, g, tsum);
+        }
+        const float sw = wave_sum64(g);
+        if (lane == 0) tsum[WPS_W] = sw;
+        __syncthreads();
+        constexpr int O_CA = WR * WKR, O_W0 = O_CA + WA * WKA, O_B0 = O_W0 + WH * WDIM, O_W1 = O_B0 + WH,
+                      O_B1 = O_W1 + WH;
+        for (int k = 0; k < NOWN; ++k) {
+            const int o = lane + 64 * k;
+            if (o >= W_NPARAM) break;
+            float sum = 0.0f;
+            if (o < O_CA) {
+                const int i1 = WPG_FPR + o / WKR, i2 = WPG_F + o % WKR;
+                for (int a = 0; a < 64; ++a) sum = fmaf(rec[a][i1], rec[a][i2], sum);
+            } else if (o < O_W0) {
+                sum = tsum[WPS_G + (o - O_CA)];
+            } else if (o < O_B0) {
+                const int p = o - O_W0;
+                const int i1 = WPG_DZ + p / WDIM, i2 = WPG_QT + p % WDIM;
+                for (int a = 0; a < 64; ++a) sum = fmaf(rec[a][i1], rec[a][i2], sum);
+            } else if (o < O_W1) {
+                const int i1 = WPG_DZ + (o - O_B0);
+                for (int a = 0; a < 64; ++a) sum += rec[a][i1];
+                sum = -sum;
+            } else if (o < O_B1) {
+                sum = tsum[WPS_TH + (o - O_W1)];
+            } else {
+                sum = -tsum[WPS_W];
+            }
+            pb[o] += (double)sum;
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace nep

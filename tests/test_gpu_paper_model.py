@@ -89,7 +89,7 @@ def test_unsupported_calls_are_refused():
         ctx.nep_set_precision(1)
     assert e.value.code == nep.NEP_E_UNSUPPORTED
     with pytest.raises(nep.NepError) as e:
-        ctx.nep_backward(sysd, out, torch.ones(1, dtype=torch.float64, device="cuda"))
+        ctx.nep_autotune(sysd, out)
     assert e.value.code == nep.NEP_E_UNSUPPORTED
 
 
@@ -111,3 +111,83 @@ def test_md_candidate_walk_matches_full_walk():
     torch.cuda.synchronize()
     assert np.array_equal(F_md, out.forces().cpu().numpy())
     assert np.array_equal(E_md, out.energy.cpu().numpy())
+
+
+# parameter gradients: FP32 products summed per 64-atom tile, FP64 across
+# tiles (the default model's bar)
+P_REL_TOL = 1e-5
+P_SIZES = (256, 121, 6000, 100, 100, 1)
+P_NAMES = ("c_rad", "c_ang", "w0", "b0", "w1", "b1")
+
+
+def _subset(full, picks):
+    sizes = np.diff(full.cell_start)
+    pos = np.concatenate([full.cell(c)[0] for c in picks])
+    starts = np.concatenate([[0], np.cumsum([sizes[c] for c in picks])]).astype(np.int64)
+    return nep_synth.System(pos=pos, vel=np.zeros_like(pos), cell_start=starts, h=full.h[list(picks)].copy())
+
+
+def test_backward_matches_oracle_gradients():
+    # dE/dtheta, dE/dpos through the differentiable energy on strained cells
+    # with images (several tiles, a ragged tail), against the FP64 oracle
+    import torch
+    import paper_2305_08140_amd as nep
+    from paper_2305_08140_amd.autograd import nep_energy
+    m = pmodel()
+    full = nep_synth.diffbatch()
+    s = _subset(full, range(0, 512, 32))
+    ctx = nep.Context(m, s.n_atoms, s.n_cells)
+    pos = torch.tensor(s.pos, device="cuda", requires_grad=True)
+    cell = torch.tensor(s.h, device="cuda", requires_grad=True)
+    theta = torch.tensor(m.param_vector(), device="cuda", dtype=torch.float32, requires_grad=True)
+    q_scale = torch.tensor(m.q_scale, device="cuda", dtype=torch.float32)
+    E = nep_energy(ctx, pos, cell, theta, q_scale, cell_start=s.cell_start)
+    gE = torch.tensor(np.random.default_rng(3).normal(size=s.n_cells), device="cuda")
+    (E * gE).sum().backward()
+    g_np = gE.cpu().numpy()
+    ref_gp = np.zeros(theta.numel())
+    ref_gx = np.zeros((s.n_atoms, 3))
+    for c in range(s.n_cells):
+        a, b = int(s.cell_start[c]), int(s.cell_start[c + 1])
+        ref_gx[a:b] = -g_np[c] * oracle.efv_cell(m, s.pos[a:b], s.h[c], virial=False)["forces"]
+        ref_gp += g_np[c] * oracle.param_grad_cell(m, s.pos[a:b], s.h[c])
+    gx = pos.grad.cpu().numpy()
+    assert np.linalg.norm(gx - ref_gx) / np.linalg.norm(ref_gx) <= F_REL_TOL
+    gp = theta.grad.double().cpu().numpy()
+    o = np.concatenate([[0], np.cumsum(P_SIZES)])
+    for name, a, b in zip(P_NAMES, o[:-1], o[1:]):
+        err = np.linalg.norm(gp[a:b] - ref_gp[a:b]) / np.linalg.norm(ref_gp[a:b])
+        print(f"[paper model param grad] {name}: rel err {err:.2e}", flush=True)
+        assert err <= P_REL_TOL, name
+
+
+def test_parameter_gradient_over_many_tiles():
+    # more 64-atom tiles than blocks: two calls agree bit for bit, and the
+    # whole batch's gradient is the sum of its halves' to FP32 rounding
+    import torch
+    import paper_2305_08140_amd as nep
+    m = pmodel()
+    full = nep_synth.diffbatch()
+    assert (full.n_atoms + 63) // 64 > 1024
+    g_all = np.random.default_rng(21).uniform(0.5, 1.5, size=full.n_cells)
+
+    def grad(s, g):
+        sysd = nep.DeviceSystem.from_synth(s)
+        ctx = nep.Context(m, s.n_atoms, s.n_cells)
+        o = nep.EFV(s.n_atoms, s.n_cells)
+        ctx.nep_build_neighbors(sysd)
+        ctx.nep_compute_efv(sysd, o)
+        gE = torch.tensor(g, device="cuda", dtype=torch.float64)
+        a = ctx.nep_backward(sysd, o, gE, grad_pos=False, grad_cell=False)[0].clone()
+        b = ctx.nep_backward(sysd, o, gE, grad_pos=False, grad_cell=False)[0]
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        return a.cpu().numpy()
+
+    gp = grad(full, g_all)
+    parts = grad(_subset(full, range(0, 256)), g_all[:256]) + grad(_subset(full, range(256, 512)), g_all[256:])
+    o = np.concatenate([[0], np.cumsum(P_SIZES)])
+    for name, a, b in zip(P_NAMES, o[:-1], o[1:]):
+        err = np.linalg.norm(gp[a:b] - parts[a:b]) / np.linalg.norm(parts[a:b])
+        print(f"[paper model param grad, 1111 tiles] {name}: whole vs halves rel diff {err:.2e}", flush=True)
+        assert err <= 1e-6, name

@@ -488,3 +488,32 @@ def test_paper_size_model_forces_virial_and_identity_dimer():
         fA = _basis_np(11, r, 4.0)
         for l in range(1, 5):
             assert np.allclose(q[0, 16 + 11 * (l - 1):16 + 11 * l], fA ** 2, atol=1e-13)
+
+
+def test_paper_size_model_parameter_gradient_matches_finite_differences():
+    # dE/dtheta of the paper-size model (16 x 16 radial and 11 x 11 angular
+    # coefficients, 100 x 60 input weights) against central differences of
+    # the energy on sampled parameters of every group, and dE/db1 = -N
+    m = nep_synth.random_model(size="paper")
+    pos, hc = nep_synth.bcc_lattice(3, 3, 3)
+    pos = pos + np.random.default_rng(6).normal(0.0, 0.06, pos.shape)
+    g = oracle.param_grad_cell(m, pos, hc)
+    theta = m.param_vector()
+    sizes = (256, 121, 6000, 100, 100, 1)
+    assert g.shape == theta.shape == (sum(sizes),)
+    o = np.concatenate([[0], np.cumsum(sizes)])
+    rng = np.random.default_rng(8)
+    for name, a, b in zip(("c_rad", "c_ang", "w0", "b0", "w1", "b1"), o[:-1], o[1:]):
+        for p in rng.choice(np.arange(a, b), size=min(5, b - a), replace=False):
+            h = 1e-5 * max(1.0, abs(theta[p]))
+            tp, tm = theta.copy(), theta.copy()
+            tp[p] += h
+            tm[p] -= h
+            ep = oracle.efv_cell(m.with_param_vector(tp), pos, hc, virial=False)["energy"]
+            em = oracle.efv_cell(m.with_param_vector(tm), pos, hc, virial=False)["energy"]
+            fd = (ep - em) / (2 * h)
+            assert abs(g[p] - fd) <= 1e-6 * max(1.0, abs(fd)), (name, p, g[p], fd)
+    assert g[-1] == -pos.shape[0]
+    # E is linear in w1 and b1 apart from the ZBL part (none at these spacings)
+    E = oracle.efv_cell(m, pos, hc)["energy"]
+    assert abs(E - (m.w1 @ g[o[4]:o[5]] + m.b1 * g[-1])) < 1e-9 * max(1.0, abs(E))

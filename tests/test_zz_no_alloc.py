@@ -80,11 +80,22 @@ def test_noalloc_backward_argument_checks():
     with pytest.raises(nep.NepError) as e2:
         ctx.nep_backward(sysd, out, gE)
     assert e2.value.code == nep.NEP_E_STATE
-    # the paper-size model has no backward
+    # the paper-size model's backward: checked before any build as well
     mw = nep_synth.random_model(size="paper")
     ctxw = nep.Context(mw, s.n_atoms, 1)
-    ctxw.nep_build_neighbors(sysd)
-    ctxw.nep_compute_efv(sysd, out)
     with pytest.raises(nep.NepError) as e3:
         ctxw.nep_backward_noalloc(sysd, out, gE)
-    assert e3.value.code == nep.NEP_E_UNSUPPORTED
+    assert e3.value.code == nep.NEP_E_STATE
+
+
+def test_noalloc_backward_paper_model_twice_then_smaller():
+    # the paper-size model (6,578 parameters per partial row): all 1024 rows
+    # of the device array in use, then a smaller system on the same context
+    import paper_2305_08140_amd as nep
+    m = nep_synth.random_model(size="paper")
+    full = nep_synth.diffbatch()
+    ctx = nep.Context(m, full.n_atoms, full.n_cells)
+    big = _compare(ctx, full, 3)
+    small = _compare(ctx, _subset(full, range(5, 512, 40)), 4)
+    assert big.shape == small.shape == (6578,)
+    assert not np.array_equal(big, small)
