@@ -283,34 +283,46 @@ def bench_paper_model(args, s, N):
     import nep_synth
     import paper_2305_08140_amd as nep
     pm = nep_synth.random_model(size="paper")
-    sysd = nep.DeviceSystem.from_synth(s)
-    ctx = nep.Context(pm, N, 1, max_neigh_ang=48, max_neigh_rad=96, skin=1.0)
-    out = nep.EFV(N, 1)
-    md = dict(dt_max=1.0, max_disp=0.015)
-    ctx.nep_step_verlet(sysd, 5, out, forces_valid=False, **md)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.nep_step_verlet(sysd, args.paper_steps, out, forces_valid=True, **md)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kt = ctx.nep_time_efv(sysd, out, reps=3)
-    n_rad, n_ang = ctx.nep_mean_neighbors()
+    idx = np.sort(np.random.default_rng(0).choice(N, size=256, replace=False))
+
+    def run(mode):
+        # the same start for both network units: a fresh copy of the workload
+        sysd = nep.DeviceSystem.from_synth(s)
+        ctx = nep.Context(pm, N, 1, max_neigh_ang=48, max_neigh_rad=96, skin=1.0)
+        ctx.nep_set_precision(mode)
+        out = nep.EFV(N, 1)
+        md = dict(dt_max=1.0, max_disp=0.015)
+        ctx.nep_step_verlet(sysd, 5, out, forces_valid=False, **md)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.nep_step_verlet(sysd, args.paper_steps, out, forces_valid=True, **md)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kt = ctx.nep_time_efv(sysd, out, reps=3)
+        n_rad, n_ang = ctx.nep_mean_neighbors()
+        check = {"model": pm, "pos": sysd.positions().cpu().numpy(), "h": s.h[0], "pbc": (1, 1, 1), "idx": idx,
+                 "F": out.forces().cpu().numpy().astype(np.float64)[idx]}
+        del ctx, out, sysd
+        torch.cuda.empty_cache()
+        return wall, kt, (n_rad, n_ang), check
+
+    wall, kt, (n_rad, n_ang), check = run(0)
     f_desc, f_force = flops_per_atom(n_rad, n_ang, kr=16, nr=16, ka=11, na=11, nh=100)
     roof = {}
     for part, f, ms in (("descriptor_phases", f_desc, kt["descriptor"]), ("force", f_force, kt["force"])):
         ach = f * N / (ms * 1e-3) / 1e12
         roof[part] = {"bound": "alu", "flop_per_atom": f, "ms": ms, "achieved": ach, "peak": PEAK_FP32_TFLOPS,
                       "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS}
-    idx = np.sort(np.random.default_rng(0).choice(N, size=256, replace=False))
-    check = {"model": pm, "pos": sysd.positions().cpu().numpy(), "h": s.h[0], "pbc": (1, 1, 1), "idx": idx,
-             "F": out.forces().cpu().numpy().astype(np.float64)[idx]}
     res = {"atom_steps_per_s": N * args.paper_steps / wall, "ms_per_step": wall / args.paper_steps * 1e3,
-           "steps": args.paper_steps, "kernels_ms": kt, "roofline": roof,
+           "steps": args.paper_steps, "kernels_ms": kt, "roofline": roof, "network": "fp32_vector",
            "force_rel_err_vs_fp64_thermal_atoms": None,
            "paper_a100_atom_steps_per_s": 1.3e7}
-    del ctx, out, sysd
-    torch.cuda.empty_cache()
-    return res, check
+    # the hidden layer on the matrix cores (precision mode 2: FP32 operands)
+    wall2, kt2, _, check2 = run(2)
+    res["matrix_core_network"] = {"atom_steps_per_s": N * args.paper_steps / wall2,
+                                  "ms_per_step": wall2 / args.paper_steps * 1e3, "kernels_ms": kt2,
+                                  "network": "fp32_mfma", "force_rel_err_vs_fp64_thermal_atoms": None}
+    return res, {"paper_model": check, "paper_model_mfma": check2}
 
 
 def bench_nve(args, model):
@@ -707,7 +719,8 @@ def main():
     if args.nve_steps > 0:
         nve = bench_nve(args, model)
     if args.paper_steps > 0:
-        paper, checks["paper_model"] = bench_paper_model(args, s, N)
+        paper, pc = bench_paper_model(args, s, N)
+        checks.update(pc)
     if args.foil_steps > 0:
         foil, checks["foil"] = bench_foil(args, model)
     if args.snes_gens > 0:
@@ -742,6 +755,8 @@ def main():
         eerr = acc["bulk"]["site_energy_max_abs_err"]
         if paper is not None:
             paper["force_rel_err_vs_fp64_thermal_atoms"] = acc["paper_model"]["force_rel_err"]
+            paper["matrix_core_network"]["force_rel_err_vs_fp64_thermal_atoms"] = \
+                acc["paper_model_mfma"]["force_rel_err"]
         if foil is not None:
             foil["force_rel_err_vs_fp64_sampled"] = acc["foil"]["force_rel_err"]
         if batches is not None:

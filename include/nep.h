@@ -58,7 +58,7 @@ typedef struct nep_ctx nep_ctx;
  *     k_rad = k_ang = 9 (Chebyshev k = 0..8), l_max = 4, n_hidden = 30;
  *   the paper's model size: n_rad = k_rad = 16 (n_max^R = 15), n_ang = k_ang
  *     = 11 (n_max^A = 10), l_max = 4, n_hidden = 100.  It supports every call
- *     except nep_autotune and nep_set_precision modes 1 and 2, which return
+ *     except nep_autotune and nep_set_precision mode 1, which return
  *     NEP_E_UNSUPPORTED for it, and the population (evolution-strategy)
  *     calls noted below.
  * Other values give NEP_E_UNSUPPORTED. */
@@ -256,7 +256,9 @@ int nep_autotune(nep_ctx *ctx, const nep_system *sys, nep_efv *out, int32_t reps
  *     accumulation, for the forward z = w0 s q and the backward dU/dq;
  *   2 FP32 inputs on the matrix cores (v_mfma_f32_32x32x2_f32), FP32
  *     accumulation: the precision of mode 0 in another summation order.
- * Descriptors, forces and reductions are unaffected.  Returns NEP_OK or NEP_E_ARG. */
+ * Descriptors, forces and reductions are unaffected.  The paper-size model
+ * takes modes 0 and 2 (mode 1: NEP_E_UNSUPPORTED).  Returns NEP_OK,
+ * NEP_E_ARG or NEP_E_UNSUPPORTED. */
 int nep_set_precision(nep_ctx *ctx, int32_t mode);
 
 /* Number of trainable model parameters, theta = (c_rad, c_ang, w0, b0, w1, b1)

@@ -845,7 +845,16 @@ static void launch_wide_sums(nep_ctx *c, hipStream_t st)
     for (int g = 0; g < WNGA; ++g)
         k_w_angular<<<grid, WBS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->c64, g,
                                           c->w_S, c->w_Q);
-    k_w_network<<<grid, WBS, 0, st>>>(n, c->xq, c->params, c->w_Q, c->xw, c->w_FpA, c->e_atom);
+    if (c->nn_mode == 2) {
+        // the hidden layer on the matrix cores: a persistent grid, three
+        // blocks of four wavefronts per CU
+        const int ntiles = (n + 63) / 64;
+        const int blocks = std::max(1, std::min((ntiles + 3) / 4, 3 * 256));
+        k_w_network_mfma<<<blocks, WN_BS, 0, st>>>(n, ntiles, c->xq, c->params, c->w_Q, c->xw, c->w_FpA,
+                                                   c->e_atom);
+    } else {
+        k_w_network<<<grid, WBS, 0, st>>>(n, c->xq, c->params, c->w_Q, c->xw, c->w_FpA, c->e_atom);
+    }
 }
 
 // ... then the pair gradients
@@ -966,7 +975,7 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
 int nep_set_precision(nep_ctx *c, int32_t mode)
 {
     if (!c || mode < 0 || mode > 2) return NEP_E_ARG;
-    if (c->wide && mode != 0) return NEP_E_UNSUPPORTED;
+    if (c->wide && mode == 1) return NEP_E_UNSUPPORTED;
     c->nn_mode = mode;
     return NEP_OK;
 }

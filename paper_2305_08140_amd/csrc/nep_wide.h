@@ -27,6 +27,7 @@ constexpr int WNGA = (WA + WGA - 1) / WGA;  // 3 launches (4, 4, 3)
 // blocks (a block retires with its slowest wave; 24.7 -> 24.3 ms at 8,192,000
 // atoms), the force kernel in 256-thread blocks (11.2 -> 10.7 ms)
 constexpr int WBS = 64, WBS_F = 256;
+constexpr int WN_BS = 256;               // threads per block of the matrix-core network
 constexpr int WG = 3;                    // angular channels per group of the gradient walk
 constexpr int WNG = (WA + WG - 1) / WG;  // 4 groups (3, 3, 3, 2)
 
@@ -64,6 +65,8 @@ __global__ void k_w_angular(PairConsts pc, const double4 *xq, const int32_t *cel
                             float *Q);
 __global__ void k_w_network(int n, const double4 *xq, const float *P, const float *Q, WAtomRec *xw, float *FpA,
                             double *e_atom);
+__global__ void k_w_network_mfma(int n_atoms, int ntiles, const double4 *xq, const float *P, const float *Q,
+                                 WAtomRec *xw, float *FpA, double *e_atom);
 __global__ void k_w_grad(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
                          const int32_t *nl_ang, const uint32_t *ncnt, const float *P, const double *C64,
                          const float *S, const float *FpA, float4 *pair_grad, float4 *f_own, float *w_atom);

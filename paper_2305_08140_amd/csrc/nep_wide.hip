@@ -306,6 +306,145 @@ __global__ __launch_bounds__(WBS) void k_w_network(int n_atoms, const double4 *_
     for (int nu = WR; nu < WDIM; ++nu) FpA[(nu - WR) * n + t] = Fp[nu];
 }
 
+// The same network on the matrix cores with FP32 operands
+// (v_mfma_f32_32x32x2_f32: FP32 products and accumulation, the precision of
+// the vector version in another summation order).  Per 32-atom column tile:
+//   forward   Z^T  [128 x 32] = W0 [128 x 60] . Qs^T [60 x 32]
+//             (four 32-neuron row tiles, the rows past 100 zero; 30 K steps)
+//   backward  Fp^T [64 x 32]  = W0^T [64 x 128] . dZ^T [128 x 32]
+// Operand layouts (lane l, hi = l/32, lo = l%32): A[lo][hi], B[hi][lo],
+// result D[8(v/4) + 4 hi + v%4][lo], v = 0..15.  The backward's K order is
+// the forward result's own layout: K step (mt, v) pairs the neurons
+// mt*32 + 8(v/4) + 4 hi + v%4 of the two half-waves, so every lane feeds
+// its own dU/dz values as the B operand, straight from registers; the steps
+// whose neurons are all past 100 are skipped (52 of 64).  w0 is staged in
+// LDS once per block (row stride 65 floats: conflict-free in both
+// orientations) and the grid is persistent over 64-atom tiles, one per
+// wavefront at a time.
+constexpr int WN_MT = 4;          // 32-neuron tiles of the forward
+constexpr int WN_LD = 65;         // LDS row stride of w0 (floats)
+typedef __attribute__((ext_vector_type(16))) float w_f32x16;
+
+__global__ __launch_bounds__(WN_BS) __attribute__((amdgpu_waves_per_eu(3))) void k_w_network_mfma(
+    int n_atoms, int ntiles, const double4 *__restrict__ xq, const float *__restrict__ P, const float *__restrict__ Q,
+    WAtomRec *__restrict__ xw, float *__restrict__ FpA, double *__restrict__ e_atom)
+{
+    __shared__ float w0s[WN_MT * 32 * WN_LD];      // w0[mu][nu] at mu * WN_LD + nu, zero past 100 x 60
+    __shared__ float b0s[WN_MT * 32], w1s[WN_MT * 32];
+    __shared__ float qss[64];
+    __shared__ float crs[WR * WKR];
+    for (int i = threadIdx.x; i < WN_MT * 32 * WN_LD; i += WN_BS) {
+        const int mu = i / WN_LD, nu = i - mu * WN_LD;
+        w0s[i] = (mu < WH && nu < WDIM) ? P[W_W0 + mu * WDIM + nu] : 0.0f;
+    }
+    for (int i = threadIdx.x; i < WN_MT * 32; i += WN_BS) {
+        b0s[i] = i < WH ? P[W_B0 + i] : 0.0f;
+        w1s[i] = i < WH ? P[W_W1 + i] : 0.0f;
+    }
+    for (int i = threadIdx.x; i < WR * WKR; i += WN_BS) crs[i] = P[W_CR + i];
+    if (threadIdx.x < 64) qss[threadIdx.x] = threadIdx.x < WDIM ? P[W_QS + threadIdx.x] : 0.0f;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int hi = lane >> 5, lo = lane & 31;
+    const float b1 = P[W_B1];
+    for (int tile = blockIdx.x * (WN_BS / 64) + wave; tile < ntiles; tile += gridDim.x * (WN_BS / 64)) {
+#pragma unroll 1
+        for (int nt = 0; nt < 2; ++nt) {
+            const int atom = tile * 64 + nt * 32 + lo;
+            const bool valid = atom < n_atoms;
+            const int a = valid ? atom : n_atoms - 1;
+            // The component stride and the lane's LDS offsets, opaque to the
+            // compiler inside the loop: the per-component addresses it would
+            // otherwise hoist out of the loop hold ~100 registers (here they
+            // are recomputed with an add each).
+            size_t ns = (size_t)n_atoms;
+            int of = lo * WN_LD + hi;       // forward A: w0[mt*32 + lo][2 st + hi]
+            int ob = 4 * hi * WN_LD + lo;   // backward A: w0[mu][dt*32 + lo], mu = mt*32 + 8j + 4 hi + r
+            int oh = 4 * hi;                // neuron (and descriptor) offset of this half-wave
+            asm volatile("" : "+s"(ns), "+v"(of), "+v"(ob), "+v"(oh));
+            // B operand of the forward: Qs[atom lo][nu = 2 st + hi]
+            float qb[WDIM / 2];
+            const float *qp = Q + (size_t)hi * ns + a;
+#pragma unroll
+            for (int st = 0; st < WDIM / 2; ++st) {
+                qb[st] = qss[2 * st + hi] * *qp;
+                qp += 2 * ns;
+            }
+            w_f32x16 z[WN_MT];
+#pragma unroll
+            for (int mt = 0; mt < WN_MT; ++mt) {
+                w_f32x16 acc = {};
+#pragma unroll
+                for (int st = 0; st < WDIM / 2; ++st) {
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w0s[of + mt * 32 * WN_LD + 2 * st], qb[st], acc, 0, 0,
+                                                               0);
+                    // bound the scheduler's window (it would otherwise hoist
+                    // every LDS operand of the tile into registers)
+                    if ((st & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                }
+                z[mt] = acc;
+            }
+            // activation in the result layout: tanh, the energy, dU/dz in place
+            float Up = 0.0f;
+#pragma unroll
+            for (int mt = 0; mt < WN_MT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int mu = oh + mt * 32 + 8 * (v >> 2) + (v & 3);
+                    const float th = ftanh(z[mt][v] - b0s[mu]);
+                    Up = fmaf(w1s[mu], th, Up);
+                    z[mt][v] = w1s[mu] * fmaf(-th, th, 1.0f);
+                }
+            w_f32x16 f[2] = {};
+#pragma unroll
+            for (int mt = 0; mt < WN_MT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    if (mt * 32 + 8 * (v >> 2) >= WH) continue;     // both half-waves' neurons past 100
+                    const int row = mt * 32 + 8 * (v >> 2) + (v & 3);
+#pragma unroll
+                    for (int dt = 0; dt < 2; ++dt)
+                        f[dt] = __builtin_amdgcn_mfma_f32_32x32x2f32(w0s[ob + row * WN_LD + dt * 32], z[mt][v], f[dt],
+                                                                     0, 0, 0);
+                    if ((v & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+                }
+            const float U = (Up + __shfl_xor(Up, 32, 64)) - b1;
+            // dU/dq in the result layout: descriptor nu = dt*32 + 8(v/4) + 4 hi + v%4
+            float ak[WKR];
+#pragma unroll
+            for (int k = 0; k < WKR; ++k) ak[k] = 0.0f;
+#pragma unroll
+            for (int dt = 0; dt < 2; ++dt)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int nu0 = dt * 32 + 8 * (v >> 2) + (v & 3);   // this component, less 4 hi
+                    const float fp = f[dt][v] * qss[oh + nu0];
+                    if (dt == 0 && v < 8) {
+                        // radial components nu < 16: this half-wave's share of a_k
+#pragma unroll
+                        for (int k = 0; k < WKR; ++k) ak[k] = fmaf(fp, crs[oh * WKR + nu0 * WKR + k], ak[k]);
+                    } else if (valid && oh + nu0 < WDIM) {
+                        FpA[(size_t)(oh + nu0 - WR) * ns + atom] = fp;
+                    }
+                }
+#pragma unroll
+            for (int k = 0; k < WKR; ++k) ak[k] += __shfl_xor(ak[k], 32, 64);
+            if (valid && hi == 0) {
+                e_atom[atom] += (double)U;
+                const double4 p = xq[atom];
+                WAtomRec rec;
+                rec.x = p.x;
+                rec.y = p.y;
+                rec.z = p.z;
+#pragma unroll
+                for (int k = 0; k < WKR; ++k) rec.a[k] = ak[k];
+                rec.pad[0] = rec.pad[1] = 0.0f;
+                xw[atom] = rec;
+            }
+        }
+    }
+}
+
 // Contributions of the channels c0 .. c0+NC-1 to dU_i/dr_ij of every angular
 // slot, added into pair_grad (the first group writes), and to the atom's own
 // force and virial sums.

@@ -191,3 +191,58 @@ def test_parameter_gradient_over_many_tiles():
         err = np.linalg.norm(gp[a:b] - parts[a:b]) / np.linalg.norm(parts[a:b])
         print(f"[paper model param grad, 1111 tiles] {name}: whole vs halves rel diff {err:.2e}", flush=True)
         assert err <= 1e-6, name
+
+
+def test_matrix_core_network_matches_oracle_and_vector_path():
+    # precision mode 2: the 60 -> 100 -> 1 network on the matrix cores (FP32
+    # operands and accumulation) against the FP64 oracle at the same bars,
+    # and against the vector-ALU network to FP32 summation-order rounding;
+    # strained cells with images and a ragged last tile (several tiles, so
+    # the persistent grid strides)
+    import torch
+    m = pmodel()
+    full = nep_synth.batch()
+    sizes = np.diff(full.cell_start)
+    pick = [int(c) for c in np.argsort(sizes)[:24]] + list(range(100, 4096, 400))
+    pos = np.concatenate([full.cell(c)[0] for c in pick])
+    starts = np.concatenate([[0], np.cumsum([sizes[c] for c in pick])]).astype(np.int64)
+    s = nep_synth.System(pos=pos, vel=np.zeros_like(pos), cell_start=starts, h=full.h[pick].copy())
+    assert s.n_atoms % 64 != 0
+    ref = oracle.efv_system(m, s)
+    res0, ctx, sysd, out = run_gpu(m, s)
+    ctx.nep_set_precision(2)
+    ctx.nep_compute_efv(sysd, out)
+    torch.cuda.synchronize()
+    res2 = {"energy": out.energy.cpu().numpy(), "forces": out.forces().cpu().numpy().astype(np.float64),
+            "virial": out.virial.cpu().numpy().reshape(-1, 3, 3), "energy_atom": out.energy_atom.cpu().numpy()}
+    _compare(s, ref, res2, None, "matrix-core network")
+    d = np.linalg.norm(res2["forces"] - res0["forces"]) / np.linalg.norm(res0["forces"])
+    du = np.abs(res2["energy_atom"] - res0["energy_atom"]).max()
+    print(f"[paper model] matrix-core vs vector network: force rel diff {d:.2e}, site energy {du:.2e} eV", flush=True)
+    assert d <= 1e-6 and du <= 1e-5
+    import paper_2305_08140_amd as nep
+    with pytest.raises(nep.NepError) as e:
+        ctx.nep_set_precision(1)
+    assert e.value.code == nep.NEP_E_UNSUPPORTED
+
+
+def test_matrix_core_network_md_sampled():
+    # 128,000 atoms, 20 MD steps with the matrix-core network, sampled atoms
+    # against FP64
+    import torch
+    import paper_2305_08140_amd as nep
+    m = pmodel()
+    s = nep_synth.mid()
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(m, s.n_atoms, 1)
+    ctx.nep_set_precision(2)
+    out = nep.EFV(s.n_atoms, 1)
+    ctx.nep_step_verlet(sysd, 20, out, dt_max=1.0)
+    torch.cuda.synchronize()
+    pos = sysd.positions().cpu().numpy()
+    F = out.forces().cpu().numpy().astype(np.float64)
+    idx = np.sort(np.random.default_rng(8).choice(s.n_atoms, 256, replace=False))
+    ref = oracle.efv_cell(m, pos, s.h[0], targets=idx, virial=False)
+    err = np.linalg.norm(F[idx] - ref["forces"]) / np.linalg.norm(ref["forces"])
+    print(f"[paper model mid, matrix-core network] sampled force rel err {err:.3e}", flush=True)
+    assert err <= F_REL_TOL
