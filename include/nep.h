@@ -58,9 +58,8 @@ typedef struct nep_ctx nep_ctx;
  *     k_rad = k_ang = 9 (Chebyshev k = 0..8), l_max = 4, n_hidden = 30;
  *   the paper's model size: n_rad = k_rad = 16 (n_max^R = 15), n_ang = k_ang
  *     = 11 (n_max^A = 10), l_max = 4, n_hidden = 100.  It supports every call
- *     except nep_autotune and nep_set_precision mode 1, which return
- *     NEP_E_UNSUPPORTED for it, and the population (evolution-strategy)
- *     calls noted below.
+ *     except the population (evolution-strategy) calls noted below, which
+ *     return NEP_E_UNSUPPORTED for it.
  * Other values give NEP_E_UNSUPPORTED. */
 typedef struct {
     int32_t n_rad;      /* radial descriptor components */
@@ -245,8 +244,10 @@ int nep_compute_efv_graph(nep_ctx *ctx, const nep_system *sys, nep_efv *out, voi
  * events on `stream`; the fastest pair is kept for this system size bucket
  * (floor(log2 n_atoms)) and used by later evaluations in that bucket.
  * shape_out (host int32[2], may be NULL) receives the chosen shape indices
- * (0..2: 64/128/256 threads, one block per tile; 3..5: the same, persistent).
- * Synchronises `stream`.  Same preconditions as nep_compute_efv. */
+ * (0..2: 64/128/256 threads, one block per tile; 3..5: the same, persistent;
+ * the paper-size model's phase kernels come in shapes 0..2 only, and its
+ * matrix-core hidden layer keeps its own persistent grid).  Synchronises
+ * `stream`.  Same preconditions as nep_compute_efv. */
 int nep_autotune(nep_ctx *ctx, const nep_system *sys, nep_efv *out, int32_t reps, int32_t *shape_out,
                  void *stream);
 
@@ -256,9 +257,8 @@ int nep_autotune(nep_ctx *ctx, const nep_system *sys, nep_efv *out, int32_t reps
  *     accumulation, for the forward z = w0 s q and the backward dU/dq;
  *   2 FP32 inputs on the matrix cores (v_mfma_f32_32x32x2_f32), FP32
  *     accumulation: the precision of mode 0 in another summation order.
- * Descriptors, forces and reductions are unaffected.  The paper-size model
- * takes modes 0 and 2 (mode 1: NEP_E_UNSUPPORTED).  Returns NEP_OK,
- * NEP_E_ARG or NEP_E_UNSUPPORTED. */
+ * Descriptors, forces and reductions are unaffected; both model sizes take
+ * every mode.  Returns NEP_OK or NEP_E_ARG. */
 int nep_set_precision(nep_ctx *ctx, int32_t mode);
 
 /* Number of trainable model parameters, theta = (c_rad, c_ang, w0, b0, w1, b1)

@@ -832,56 +832,87 @@ static void launch_force(nep_ctx *c, int shape, const nep_efv *o, hipStream_t st
     }
 }
 
-extern "C" {
-
-// The paper-size model's descriptor phases and force kernel (nep_wide.h):
-// the staged sums, descriptors and network adjoints ...
-static void launch_wide_sums(nep_ctx *c, hipStream_t st)
+// The paper-size model's descriptor phases and force kernel (nep_wide.h), in
+// blocks of BS threads (shapes 0, 1, 2: 64, 128, 256; the persistent shapes
+// of the default model's kernels do not exist here): the staged sums,
+// descriptors and network adjoints ...
+template <int BS>
+static void launch_wide_sums_t(nep_ctx *c, hipStream_t st)
 {
-    const int n = c->pc.n, grid = xcd_grid((n + WBS - 1) / WBS);
-    k_w_radial<<<grid, WBS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->params,
-                                     c->w_Q, c->e_atom, c->status,
-                                     c->cflag);
+    const int n = c->pc.n, grid = xcd_grid((n + BS - 1) / BS);
+    k_w_radial<BS><<<grid, BS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
+                                        c->params, c->w_Q, c->e_atom, c->status, c->cflag);
     for (int g = 0; g < WNGA; ++g)
-        k_w_angular<<<grid, WBS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->c64, g,
-                                          c->w_S, c->w_Q);
-    if (c->nn_mode == 2) {
-        // the hidden layer on the matrix cores: a persistent grid, three
-        // blocks of four wavefronts per CU
+        k_w_angular<BS><<<grid, BS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->c64, g,
+                                             c->w_S, c->w_Q);
+    if (c->nn_mode != 0) {
+        // the hidden layer on the matrix cores (FP32 or BF16 operands): a
+        // persistent grid, three blocks of four wavefronts per CU
         const int ntiles = (n + 63) / 64;
         const int blocks = std::max(1, std::min((ntiles + 3) / 4, 3 * 256));
-        k_w_network_mfma<<<blocks, WN_BS, 0, st>>>(n, ntiles, c->xq, c->params, c->w_Q, c->xw, c->w_FpA,
-                                                   c->e_atom);
+        if (c->nn_mode == 2)
+            k_w_network_mfma<false><<<blocks, WN_BS, 0, st>>>(n, ntiles, c->xq, c->params, c->w_Q, c->xw, c->w_FpA,
+                                                              c->e_atom);
+        else
+            k_w_network_mfma<true><<<blocks, WN_BS, 0, st>>>(n, ntiles, c->xq, c->params, c->w_Q, c->xw, c->w_FpA,
+                                                             c->e_atom);
     } else {
-        k_w_network<<<grid, WBS, 0, st>>>(n, c->xq, c->params, c->w_Q, c->xw, c->w_FpA, c->e_atom);
+        k_w_network<BS><<<grid, BS, 0, st>>>(n, c->xq, c->params, c->w_Q, c->xw, c->w_FpA, c->e_atom);
     }
 }
 
 // ... then the pair gradients
-static void launch_wide_desc(nep_ctx *c, hipStream_t st)
+template <int BS>
+static void launch_wide_desc_t(nep_ctx *c, hipStream_t st)
 {
-    const int n = c->pc.n, grid = xcd_grid((n + WBS - 1) / WBS);
-    launch_wide_sums(c, st);
-    k_w_grad<<<grid, WBS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->params, c->c64, c->w_S,
-                                   c->w_FpA, c->pair_grad, c->f_own, c->w_atom);
+    const int n = c->pc.n, grid = xcd_grid((n + BS - 1) / BS);
+    launch_wide_sums_t<BS>(c, st);
+    k_w_grad<BS><<<grid, BS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->params, c->c64,
+                                      c->w_S, c->w_FpA, c->pair_grad, c->f_own, c->w_atom);
 }
 
-static void launch_wide_force(nep_ctx *c, const nep_efv *o, hipStream_t st)
+template <int BS>
+static void launch_wide_force_t(nep_ctx *c, const nep_efv *o, hipStream_t st)
 {
-    const int n = c->pc.n, grid = xcd_grid((n + WBS_F - 1) / WBS_F);
-    k_w_force<<<grid, WBS_F, 0, st>>>(c->pc, c->xw, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->rev,
-                                    c->pair_grad, c->f_own, c->perm, o->fx, o->fy, o->fz, c->w_atom, c->status);
+    const int n = c->pc.n, grid = xcd_grid((n + BS - 1) / BS);
+    k_w_force<BS><<<grid, BS, 0, st>>>(c->pc, c->xw, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->rev,
+                                       c->pair_grad, c->f_own, c->perm, o->fx, o->fy, o->fz, c->w_atom, c->status);
 }
+
+static const int N_WIDE_SHAPES = 3;
+
+static void launch_wide_sums(nep_ctx *c, hipStream_t st)
+{
+    if (c->shape_desc == 1) launch_wide_sums_t<128>(c, st);
+    else if (c->shape_desc == 2) launch_wide_sums_t<256>(c, st);
+    else launch_wide_sums_t<64>(c, st);
+}
+
+static void launch_wide_desc(nep_ctx *c, int shape, hipStream_t st)
+{
+    if (shape == 1) launch_wide_desc_t<128>(c, st);
+    else if (shape == 2) launch_wide_desc_t<256>(c, st);
+    else launch_wide_desc_t<64>(c, st);
+}
+
+static void launch_wide_force(nep_ctx *c, int shape, const nep_efv *o, hipStream_t st)
+{
+    if (shape == 0) launch_wide_force_t<64>(c, o, st);
+    else if (shape == 1) launch_wide_force_t<128>(c, o, st);
+    else launch_wide_force_t<256>(c, o, st);
+}
+
+extern "C" {
 
 static void launch_desc_any(nep_ctx *c, hipStream_t st)
 {
-    if (c->wide) launch_wide_desc(c, st);
+    if (c->wide) launch_wide_desc(c, c->shape_desc, st);
     else launch_desc(c, c->shape_desc, st);
 }
 
 static void launch_force_any(nep_ctx *c, const nep_efv *o, hipStream_t st)
 {
-    if (c->wide) launch_wide_force(c, o, st);
+    if (c->wide) launch_wide_force(c, c->shape_force, o, st);
     else launch_force(c, c->shape_force, o, st);
 }
 
@@ -975,7 +1006,6 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
 int nep_set_precision(nep_ctx *c, int32_t mode)
 {
     if (!c || mode < 0 || mode > 2) return NEP_E_ARG;
-    if (c->wide && mode == 1) return NEP_E_UNSUPPORTED;
     c->nn_mode = mode;
     return NEP_OK;
 }
@@ -1065,7 +1095,6 @@ int nep_backward_noalloc(nep_ctx *c, const nep_system *s, const nep_efv *o, cons
 int nep_autotune(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, int32_t *shape_out, void *stream)
 {
     if (!c || reps <= 0) return NEP_E_ARG;
-    if (c->wide) return NEP_E_UNSUPPORTED;
     int rc = check_system(c, s, false);
     if (rc) return rc;
     if ((rc = check_out(o))) return rc;
@@ -1088,16 +1117,26 @@ int nep_autotune(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, int3
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
         return ms;
     };
+    // the paper-size model's phases come in the three non-persistent shapes
+    const int n_shapes = c->wide ? N_WIDE_SHAPES : N_SHAPES;
+    auto desc = [&](int k) {
+        if (c->wide) launch_wide_desc(c, k, st);
+        else launch_desc(c, k, st);
+    };
+    auto force = [&](int k) {
+        if (c->wide) launch_wide_force(c, k, o, st);
+        else launch_force(c, k, o, st);
+    };
     int best_d = 2, best_f = 2;
     float t_best = 1e30f;
-    for (int k = 0; k < N_SHAPES; ++k) {
-        const float t = time_it([&] { launch_desc(c, k, st); });
+    for (int k = 0; k < n_shapes; ++k) {
+        const float t = time_it([&] { desc(k); });
         if (t < t_best) { t_best = t; best_d = k; }
     }
-    launch_desc(c, best_d, st);
+    desc(best_d);
     t_best = 1e30f;
-    for (int k = 0; k < N_SHAPES; ++k) {
-        const float t = time_it([&] { launch_force(c, k, o, st); });
+    for (int k = 0; k < n_shapes; ++k) {
+        const float t = time_it([&] { force(k); });
         if (t < t_best) { t_best = t; best_f = k; }
     }
     HIP_TRY(hipEventDestroy(e0));

@@ -23,9 +23,10 @@ constexpr int WH = 100;                  // hidden neurons
 constexpr int WDIM = WR + WA * LMAX;     // 60
 constexpr int WGA = 4;                   // angular channels per launch of the angular sums
 constexpr int WNGA = (WA + WGA - 1) / WGA;  // 3 launches (4, 4, 3)
-// threads per block (one atom per lane): the descriptor phases in 64-thread
-// blocks (a block retires with its slowest wave; 24.7 -> 24.3 ms at 8,192,000
-// atoms), the force kernel in 256-thread blocks (11.2 -> 10.7 ms)
+// default threads per block (one atom per lane; nep_autotune may pick 64, 128
+// or 256 for a system size): the descriptor phases in 64-thread blocks (a
+// block retires with its slowest wave; 24.7 -> 24.3 ms at 8,192,000 atoms),
+// the force kernel in 256-thread blocks (11.2 -> 10.7 ms)
 constexpr int WBS = 64, WBS_F = 256;
 constexpr int WN_BS = 256;               // threads per block of the matrix-core network
 constexpr int WG = 3;                    // angular channels per group of the gradient walk
@@ -57,19 +58,25 @@ struct __attribute__((aligned(16))) WAtomRec {
 static_assert(sizeof(WAtomRec) == 96, "WAtomRec must be 96 bytes");
 
 __global__ void k_w_params64(const float *P, double *C64);
+template <int BS>
 __global__ void k_w_radial(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
                            const int32_t *nl_ang, const int32_t *nl_rad, const uint32_t *ncnt, const float *P,
                            float *Q, double *e_atom, int32_t *status, const int32_t *cflag);
+template <int BS>
 __global__ void k_w_angular(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
                             const int32_t *nl_ang, const uint32_t *ncnt, const double *C64, int group, float *S,
                             float *Q);
+template <int BS>
 __global__ void k_w_network(int n, const double4 *xq, const float *P, const float *Q, WAtomRec *xw, float *FpA,
                             double *e_atom);
+template <bool BF16>
 __global__ void k_w_network_mfma(int n_atoms, int ntiles, const double4 *xq, const float *P, const float *Q,
                                  WAtomRec *xw, float *FpA, double *e_atom);
+template <int BS>
 __global__ void k_w_grad(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
                          const int32_t *nl_ang, const uint32_t *ncnt, const float *P, const double *C64,
                          const float *S, const float *FpA, float4 *pair_grad, float4 *f_own, float *w_atom);
+template <int BS>
 __global__ void k_w_force(PairConsts pc, const WAtomRec *xw, const int32_t *cell_of, const CellGeom *cells,
                           const int32_t *nl_ang, const int32_t *nl_rad, const uint32_t *ncnt, const uint8_t *rev,
                           const float4 *pair_grad, const float4 *f_own, const int32_t *perm, float *fx, float *fy,

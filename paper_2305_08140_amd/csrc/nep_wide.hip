@@ -64,13 +64,14 @@ __global__ void k_w_params64(const float *__restrict__ P, double *__restrict__ C
 // q_n = sum_k c_nk F_k -> Q[n][t]; ZBL half energies -> e_atom[t].  The
 // radial list is walked in full when *cflag is set, else over the candidates
 // of the last full walk (see the default model's descriptor_sums).
-__global__ __launch_bounds__(WBS) void k_w_radial(
+template <int BS>
+__global__ __launch_bounds__(BS) void k_w_radial(
     PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const int32_t *__restrict__ nl_rad,
     const uint32_t *__restrict__ ncnt, const float *__restrict__ P, float *__restrict__ Q,
     double *__restrict__ e_atom, int32_t *__restrict__ status, const int32_t *__restrict__ cflag)
 {
-    const int t = tile_atom(pc.n);
+    const int t = tile_atom<BS>(pc.n);
     if (t >= pc.n || lists_blocked(status)) return;
     const double4 pi = xq[t];
     const CellGeom *cg = cells + cell_of[t];
@@ -238,12 +239,13 @@ __device__ __forceinline__ void w_angular_group(const PairConsts &pc, const doub
     }
 }
 
-__global__ __launch_bounds__(WBS) void k_w_angular(
+template <int BS>
+__global__ __launch_bounds__(BS) void k_w_angular(
     PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const uint32_t *__restrict__ ncnt,
     const double *__restrict__ C64, int group, float *__restrict__ S, float *__restrict__ Q)
 {
-    const int t = tile_atom(pc.n);
+    const int t = tile_atom<BS>(pc.n);
     if (t >= pc.n) return;
     const CellGeom *cg = cells + cell_of[t];
     const uint32_t cnt = ncnt[t];
@@ -256,12 +258,13 @@ __global__ __launch_bounds__(WBS) void k_w_angular(
 // Network forward and backward of one atom: U (added to the ZBL half
 // energies in e_atom), dU/dq; the radial adjoints a_k = sum_n dU/dq_n c_nk
 // go into the atom's record, the angular dU/dq into FpA[(nu - WR)][t].
-__global__ __launch_bounds__(WBS) void k_w_network(int n_atoms, const double4 *__restrict__ xq,
+template <int BS>
+__global__ __launch_bounds__(BS) void k_w_network(int n_atoms, const double4 *__restrict__ xq,
                                                    const float *__restrict__ P, const float *__restrict__ Q,
                                                    WAtomRec *__restrict__ xw, float *__restrict__ FpA,
                                                    double *__restrict__ e_atom)
 {
-    const int t = tile_atom(n_atoms);
+    const int t = tile_atom<BS>(n_atoms);
     if (t >= n_atoms) return;
     const size_t n = (size_t)n_atoms;
     float qt[WDIM], Fp[WDIM];
@@ -324,7 +327,16 @@ __global__ __launch_bounds__(WBS) void k_w_network(int n_atoms, const double4 *_
 constexpr int WN_MT = 4;          // 32-neuron tiles of the forward
 constexpr int WN_LD = 65;         // LDS row stride of w0 (floats)
 typedef __attribute__((ext_vector_type(16))) float w_f32x16;
+typedef __attribute__((ext_vector_type(8))) __bf16 w_bf16x8;
 
+// With BF16 operands (precision mode 1: v_mfma_f32_32x32x16_bf16, FP32
+// accumulation) the same products take K steps of 16: operand layouts
+// A[lo][8 hi + u], B[8 hi + u][lo] (u = 0..7), the result layout unchanged.
+// The forward takes four steps over the 60 (+4 zero) descriptors; the
+// backward's step (mt, h) pairs the result registers v = 8h .. 8h+7 of each
+// half-wave (neurons mt*32 + 8(v/4) + 4 hi + v%4), seven steps with a real
+// neuron.
+template <bool BF16>
 __global__ __launch_bounds__(WN_BS) __attribute__((amdgpu_waves_per_eu(3))) void k_w_network_mfma(
     int n_atoms, int ntiles, const double4 *__restrict__ xq, const float *__restrict__ P, const float *__restrict__ Q,
     WAtomRec *__restrict__ xw, float *__restrict__ FpA, double *__restrict__ e_atom)
@@ -362,27 +374,57 @@ __global__ __launch_bounds__(WN_BS) __attribute__((amdgpu_waves_per_eu(3))) void
             int ob = 4 * hi * WN_LD + lo;   // backward A: w0[mu][dt*32 + lo], mu = mt*32 + 8j + 4 hi + r
             int oh = 4 * hi;                // neuron (and descriptor) offset of this half-wave
             asm volatile("" : "+s"(ns), "+v"(of), "+v"(ob), "+v"(oh));
-            // B operand of the forward: Qs[atom lo][nu = 2 st + hi]
-            float qb[WDIM / 2];
-            const float *qp = Q + (size_t)hi * ns + a;
-#pragma unroll
-            for (int st = 0; st < WDIM / 2; ++st) {
-                qb[st] = qss[2 * st + hi] * *qp;
-                qp += 2 * ns;
-            }
             w_f32x16 z[WN_MT];
-#pragma unroll
-            for (int mt = 0; mt < WN_MT; ++mt) {
-                w_f32x16 acc = {};
+            if constexpr (!BF16) {
+                // B operand of the forward: Qs[atom lo][nu = 2 st + hi]
+                float qb[WDIM / 2];
+                const float *qp = Q + (size_t)hi * ns + a;
 #pragma unroll
                 for (int st = 0; st < WDIM / 2; ++st) {
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w0s[of + mt * 32 * WN_LD + 2 * st], qb[st], acc, 0, 0,
-                                                               0);
-                    // bound the scheduler's window (it would otherwise hoist
-                    // every LDS operand of the tile into registers)
-                    if ((st & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                    qb[st] = qss[2 * st + hi] * *qp;
+                    qp += 2 * ns;
                 }
-                z[mt] = acc;
+#pragma unroll
+                for (int mt = 0; mt < WN_MT; ++mt) {
+                    w_f32x16 acc = {};
+#pragma unroll
+                    for (int st = 0; st < WDIM / 2; ++st) {
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w0s[of + mt * 32 * WN_LD + 2 * st], qb[st], acc, 0,
+                                                                   0, 0);
+                        // bound the scheduler's window (it would otherwise
+                        // hoist every LDS operand of the tile into registers)
+                        if ((st & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                    }
+                    z[mt] = acc;
+                }
+            } else {
+                // B operand: Qs[atom lo][nu = 16 st + 8 hi + u], zero past 60
+                w_bf16x8 qb[4];
+                const float *qp = Q + (size_t)(8 * hi) * ns + a;
+#pragma unroll
+                for (int st = 0; st < 4; ++st)
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        // (components past 60 read the last one's row and
+                        // are multiplied by their zero scale)
+                        const int nu = 16 * st + 8 * hi + u;
+                        const int rowq = nu < WDIM ? 16 * st + u : WDIM - 1 - 8 * hi;
+                        qb[st][u] = (__bf16)(qss[nu] * qp[(size_t)rowq * ns]);
+                    }
+                // A operand rows start at w0[mt*32 + lo][16 st + 8 hi]
+                const int ofb = of - hi + 8 * hi;
+#pragma unroll
+                for (int mt = 0; mt < WN_MT; ++mt) {
+                    w_f32x16 acc = {};
+#pragma unroll
+                    for (int st = 0; st < 4; ++st) {
+                        w_bf16x8 wa;
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) wa[u] = (__bf16)w0s[ofb + mt * 32 * WN_LD + 16 * st + u];
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, qb[st], acc, 0, 0, 0);
+                    }
+                    z[mt] = acc;
+                }
             }
             // activation in the result layout: tanh, the energy, dU/dz in place
             float Up = 0.0f;
@@ -396,18 +438,40 @@ __global__ __launch_bounds__(WN_BS) __attribute__((amdgpu_waves_per_eu(3))) void
                     z[mt][v] = w1s[mu] * fmaf(-th, th, 1.0f);
                 }
             w_f32x16 f[2] = {};
+            if constexpr (!BF16) {
 #pragma unroll
-            for (int mt = 0; mt < WN_MT; ++mt)
+                for (int mt = 0; mt < WN_MT; ++mt)
 #pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    if (mt * 32 + 8 * (v >> 2) >= WH) continue;     // both half-waves' neurons past 100
-                    const int row = mt * 32 + 8 * (v >> 2) + (v & 3);
+                    for (int v = 0; v < 16; ++v) {
+                        if (mt * 32 + 8 * (v >> 2) >= WH) continue;     // both half-waves' neurons past 100
+                        const int row = mt * 32 + 8 * (v >> 2) + (v & 3);
 #pragma unroll
-                    for (int dt = 0; dt < 2; ++dt)
-                        f[dt] = __builtin_amdgcn_mfma_f32_32x32x2f32(w0s[ob + row * WN_LD + dt * 32], z[mt][v], f[dt],
-                                                                     0, 0, 0);
-                    if ((v & 1) == 1) __builtin_amdgcn_sched_barrier(0);
-                }
+                        for (int dt = 0; dt < 2; ++dt)
+                            f[dt] = __builtin_amdgcn_mfma_f32_32x32x2f32(w0s[ob + row * WN_LD + dt * 32], z[mt][v],
+                                                                         f[dt], 0, 0, 0);
+                        if ((v & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+                    }
+            } else {
+#pragma unroll
+                for (int mt = 0; mt < WN_MT; ++mt)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        if (mt * 32 + 16 * h >= WH) continue;           // every neuron of the step past 100
+                        w_bf16x8 dzb;
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) dzb[u] = (__bf16)z[mt][8 * h + u];
+#pragma unroll
+                        for (int dt = 0; dt < 2; ++dt) {
+                            w_bf16x8 wa;
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const int row = mt * 32 + 8 * ((8 * h + u) >> 2) + (u & 3);
+                                wa[u] = (__bf16)w0s[ob + row * WN_LD + dt * 32];
+                            }
+                            f[dt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, dzb, f[dt], 0, 0, 0);
+                        }
+                    }
+            }
             const float U = (Up + __shfl_xor(Up, 32, 64)) - b1;
             // dU/dq in the result layout: descriptor nu = dt*32 + 8(v/4) + 4 hi + v%4
             float ak[WKR];
@@ -444,6 +508,11 @@ __global__ __launch_bounds__(WN_BS) __attribute__((amdgpu_waves_per_eu(3))) void
         }
     }
 }
+
+template __global__ void k_w_network_mfma<false>(int, int, const double4 *, const float *, const float *, WAtomRec *,
+                                                  float *, double *);
+template __global__ void k_w_network_mfma<true>(int, int, const double4 *, const float *, const float *, WAtomRec *,
+                                                 float *, double *);
 
 // Contributions of the channels c0 .. c0+NC-1 to dU_i/dr_ij of every angular
 // slot, added into pair_grad (the first group writes), and to the atom's own
@@ -573,14 +642,15 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
     }
 }
 
-__global__ __launch_bounds__(WBS, 2) void k_w_grad(
+template <int BS>
+__global__ __launch_bounds__(BS, 2) void k_w_grad(
     PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const uint32_t *__restrict__ ncnt,
     const float *__restrict__ P, const double *__restrict__ C64, const float *__restrict__ S,
     const float *__restrict__ FpA, float4 *__restrict__ pair_grad, float4 *__restrict__ f_own,
     float *__restrict__ w_atom)
 {
-    const int t = tile_atom(pc.n);
+    const int t = tile_atom<BS>(pc.n);
     if (t >= pc.n) return;
     const CellGeom *cg = cells + cell_of[t];
     const uint32_t cnt = ncnt[t];
@@ -603,14 +673,15 @@ __global__ __launch_bounds__(WBS, 2) void k_w_grad(
 }
 
 // Forces: the default model's force kernel with 16 radial adjoints.
-__global__ __launch_bounds__(WBS_F) void k_w_force(
+template <int BS>
+__global__ __launch_bounds__(BS) void k_w_force(
     PairConsts pc, const WAtomRec *__restrict__ xw, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const int32_t *__restrict__ nl_rad,
     const uint32_t *__restrict__ ncnt, const uint8_t *__restrict__ rev, const float4 *__restrict__ pair_grad,
     const float4 *__restrict__ f_own, const int32_t *__restrict__ perm, float *__restrict__ fx,
     float *__restrict__ fy, float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status)
 {
-    const int t = tile_atom<WBS_F>(pc.n);
+    const int t = tile_atom<BS>(pc.n);
     if (t >= pc.n || lists_blocked(status)) return;
     const double xi = xw[t].x, yi = xw[t].y, zi = xw[t].z;
     const CellGeom *cg = cells + cell_of[t];
@@ -921,5 +992,26 @@ __global__ __launch_bounds__(64) void k_w_param_grad(
         __syncthreads();
     }
 }
+
+// launch shapes: 64, 128 and 256 threads per block (chosen by nep_autotune)
+#define NEP_W_INST(BS)                                                                                               \
+    template __global__ void k_w_radial<BS>(PairConsts, const double4 *, const int32_t *, const CellGeom *,            \
+                                            const int32_t *, const int32_t *, const uint32_t *, const float *,        \
+                                            float *, double *, int32_t *, const int32_t *);                           \
+    template __global__ void k_w_angular<BS>(PairConsts, const double4 *, const int32_t *, const CellGeom *,           \
+                                             const int32_t *, const uint32_t *, const double *, int, float *,         \
+                                             float *);                                                                \
+    template __global__ void k_w_network<BS>(int, const double4 *, const float *, const float *, WAtomRec *, float *, \
+                                             double *);                                                               \
+    template __global__ void k_w_grad<BS>(PairConsts, const double4 *, const int32_t *, const CellGeom *,             \
+                                          const int32_t *, const uint32_t *, const float *, const double *,           \
+                                          const float *, const float *, float4 *, float4 *, float *);                 \
+    template __global__ void k_w_force<BS>(PairConsts, const WAtomRec *, const int32_t *, const CellGeom *,           \
+                                           const int32_t *, const int32_t *, const uint32_t *, const uint8_t *,       \
+                                           const float4 *, const float4 *, const int32_t *, float *, float *,         \
+                                           float *, float *, int32_t *);
+NEP_W_INST(64)
+NEP_W_INST(128)
+NEP_W_INST(256)
 
 }  // namespace nep
