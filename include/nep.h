@@ -57,9 +57,7 @@ typedef struct nep_ctx nep_ctx;
  *   the default model: n_rad = 9 (n_max^R = 8), n_ang = 5 (n_max^A = 4),
  *     k_rad = k_ang = 9 (Chebyshev k = 0..8), l_max = 4, n_hidden = 30;
  *   the paper's model size: n_rad = k_rad = 16 (n_max^R = 15), n_ang = k_ang
- *     = 11 (n_max^A = 10), l_max = 4, n_hidden = 100.  It supports every call
- *     except the population (evolution-strategy) calls noted below, which
- *     return NEP_E_UNSUPPORTED for it.
+ *     = 11 (n_max^A = 10), l_max = 4, n_hidden = 100.  It supports every call.
  * Other values give NEP_E_UNSUPPORTED. */
 typedef struct {
     int32_t n_rad;      /* radial descriptor components */
@@ -396,13 +394,16 @@ typedef struct {
 
 /* Allocate the per-member evaluation buffers of up to n_pop (1..1024)
  * members at the context's capacity (about 0.9 KB per atom and member with
- * max_neigh_ang = 48), replacing earlier ones.  Synchronises the device.
- * Returns NEP_OK, NEP_E_ARG, NEP_E_UNSUPPORTED (paper-size model) or
- * NEP_E_HIP. */
+ * max_neigh_ang = 48; for the paper-size model, whose members are evaluated
+ * one after another, the parameter blocks and 12 bytes per atom and member),
+ * replacing earlier ones.  Synchronises the device.  Returns NEP_OK,
+ * NEP_E_ARG or NEP_E_HIP. */
 int nep_population_reserve(nep_ctx *ctx, int32_t n_pop);
 
 /* Energies, forces and virials of the batch `sys` for n_pop parameter
- * vectors at once (one launch over members x atom tiles), and, with targets,
+ * vectors at once (one launch over members x atom tiles; the paper-size
+ * model runs its staged evaluation once per member, with the same results
+ * as nep_compute_efv under that member's parameters), and, with targets,
  * each member's loss terms.  Same preconditions as nep_compute_efv (lists
  * built for `sys`); n_pop <= the reserved population.
  *   theta   DEVICE float [n_pop][nep_num_params()]

@@ -1456,7 +1456,6 @@ static const int POP_FBLK = 256;    // blocks of the force-error reduction per m
 int nep_population_reserve(nep_ctx *c, int32_t n_pop)
 {
     if (!c || n_pop < 1 || n_pop > NEP_MAX_POPULATION) return NEP_E_ARG;
-    if (c->wide) return NEP_E_UNSUPPORTED;
     if (hipSetDevice(c->device) != hipSuccess) return NEP_E_HIP;
     if (hipDeviceSynchronize() != hipSuccess) return NEP_E_HIP;
     free_population(c);
@@ -1467,6 +1466,20 @@ int nep_population_reserve(nep_ctx *c, int32_t n_pop)
     auto A = [&](void **p, size_t bytes) {
         if (ok && hipMalloc(p, bytes > 0 ? bytes : 16) != hipSuccess) ok = false;
     };
+    if (c->wide) {
+        // members evaluated one after another through the staged phases:
+        // parameter blocks and the per-member results only
+        A((void **)&c->pop_P, P * W_SIZE * sizeof(float));
+        A((void **)&c->pop_c64, P * W_C64 * sizeof(double));
+        A((void **)&c->pop_F, P * N * 3 * sizeof(float));
+        A((void **)&c->pop_E, P * C * sizeof(double));
+        A((void **)&c->pop_W, P * C * 9 * sizeof(double));
+        A((void **)&c->pop_fpart, P * POP_FBLK * sizeof(double));
+        if (!ok) { free_population(c); return NEP_E_HIP; }
+        c->pop_cap = n_pop;
+        c->pop_chunk_cap = chunks;
+        return NEP_OK;
+    }
     A((void **)&c->pop_P, P * P_SIZE * sizeof(float));
     A((void **)&c->pop_c64, P * C64N * sizeof(double));
     A((void **)&c->pop_xp, P * N * sizeof(AtomRec));
@@ -1489,7 +1502,6 @@ int nep_population_efv(nep_ctx *c, const nep_system *s, int32_t n_pop, const flo
                        float *forces, double *virial, const nep_targets *tg, double *loss, void *stream)
 {
     if (!c || !theta || n_pop < 1) return NEP_E_ARG;
-    if (c->wide) return NEP_E_UNSUPPORTED;
     if (n_pop > c->pop_cap) return NEP_E_ARG;
     int rc = check_system(c, s, false);
     if (rc) return rc;
@@ -1499,6 +1511,36 @@ int nep_population_efv(nep_ctx *c, const nep_system *s, int32_t n_pop, const flo
     hipStream_t st = (hipStream_t)stream;
     const int n = (int)s->n_atoms;
     const int nc = c->built_cells;
+    if (c->wide) {
+        // the paper-size model: each member's evaluation in turn, with the
+        // context's parameter block swapped for the member's (the launches
+        // take the pointers by value); results into the member's rows
+        k_w_pop_params<<<n_pop, 256, 0, st>>>(theta, c->params, c->pop_P, c->pop_c64);
+        float *F = forces ? forces : c->pop_F;
+        double *E = energy ? energy : c->pop_E;
+        double *W = virial ? virial : c->pop_W;
+        float *const params0 = c->params;
+        double *const c640 = c->c64;
+        for (int m = 0; m < n_pop && rc == NEP_OK; ++m) {
+            c->params = c->pop_P + (size_t)m * W_SIZE;
+            c->c64 = c->pop_c64 + (size_t)m * W_C64;
+            float *fm = F + 3 * (size_t)m * n;
+            nep_efv om = {E + (size_t)m * nc, fm, fm + n, fm + 2 * (size_t)n, W + (size_t)m * nc * 9, nullptr};
+            rc = launch_efv(c, s, &om, st, m == 0);
+        }
+        c->params = params0;
+        c->c64 = c640;
+        if (rc) return rc;
+        if (loss) {
+            const int nblk = std::min(POP_FBLK, grid_for(n, 256));
+            k_pop_force_err<<<dim3(nblk, n_pop), 256, 0, st>>>(n, F, tg->fx, tg->fy, tg->fz, c->pop_fpart);
+            k_pop_loss<<<n_pop, 256, 0, st>>>(nc, n, W_NPARAM, nblk, c->cell_start_d, E, W, tg->energy, tg->virial,
+                                              tg->has_virial, c->pop_fpart, theta, tg->lambda_e, tg->lambda_f,
+                                              tg->lambda_v, tg->lambda_1, tg->lambda_2, loss);
+        }
+        HIP_TRY(hipGetLastError());
+        return NEP_OK;
+    }
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of, c->cells,
                                                        c->xq, c->status, nullptr);
     k_pop_params<<<n_pop, 256, 0, st>>>(theta, c->params, c->pop_P, c->pop_c64);

@@ -58,6 +58,7 @@ struct __attribute__((aligned(16))) WAtomRec {
 static_assert(sizeof(WAtomRec) == 96, "WAtomRec must be 96 bytes");
 
 __global__ void k_w_params64(const float *P, double *C64);
+__global__ void k_w_pop_params(const float *theta, const float *base, float *P, double *C64);
 template <int BS>
 __global__ void k_w_radial(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
                            const int32_t *nl_ang, const int32_t *nl_rad, const uint32_t *ncnt, const float *P,

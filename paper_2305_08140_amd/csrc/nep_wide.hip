@@ -60,6 +60,27 @@ __global__ void k_w_params64(const float *__restrict__ P, double *__restrict__ C
     }
 }
 
+// Parameter blocks of population members: theta[m] (the gradient's layout,
+// W_NPARAM floats) with the descriptor scales of `base`, and their double
+// angular coefficients and row sums (as k_w_params64).
+__global__ __launch_bounds__(256) void k_w_pop_params(const float *__restrict__ theta, const float *__restrict__ base,
+                                                      float *__restrict__ P, double *__restrict__ C64)
+{
+    const int m = blockIdx.x;
+    const float *th = theta + (size_t)m * W_NPARAM;
+    float *pm = P + (size_t)m * W_SIZE;
+    for (int i = threadIdx.x; i < W_SIZE; i += blockDim.x)
+        pm[i] = i < W_QS ? th[i] : (i < W_W0 ? base[i] : th[i - WDIM]);
+    double *cm = C64 + (size_t)m * W_C64;
+    for (int i = threadIdx.x; i < WA * WKA; i += blockDim.x) cm[i] = (double)th[W_CA + i];
+    const int i = threadIdx.x;
+    if (i < WA) {
+        double s = 0.0;
+        for (int k = 0; k < WKA; ++k) s += (double)th[W_CA + i * WKA + k];
+        cm[WA * WKA + i] = s;
+    }
+}
+
 // Radial sums F_k = sum_j f_k(r_ij) over both lists (FP64), descriptors
 // q_n = sum_k c_nk F_k -> Q[n][t]; ZBL half energies -> e_atom[t].  The
 // radial list is walked in full when *cflag is set, else over the candidates

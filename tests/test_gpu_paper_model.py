@@ -78,11 +78,10 @@ def test_md_steps_then_sampled():
     assert err <= F_REL_TOL
 
 
-def test_autotune_keeps_results_and_population_calls_are_refused():
+def test_autotune_keeps_results():
     # the phase kernels in 64/128/256-thread blocks: whichever shapes the
     # autotuner keeps, every atom's arithmetic is the same, so the results
-    # are bitwise those of the default shapes; the population (SNES) calls
-    # exist for the default model only
+    # are bitwise those of the default shapes
     import torch
     import paper_2305_08140_amd as nep
     m = pmodel()
@@ -102,9 +101,6 @@ def test_autotune_keeps_results_and_population_calls_are_refused():
     assert np.array_equal(out.forces().cpu().numpy().astype(np.float64), res["forces"])
     assert np.array_equal(out.energy.cpu().numpy(), res["energy"])
     assert np.array_equal(out.virial.cpu().numpy().reshape(-1, 3, 3), res["virial"])
-    with pytest.raises(nep.NepError) as e:
-        ctx.nep_population_reserve(4)
-    assert e.value.code == nep.NEP_E_UNSUPPORTED
 
 
 def test_md_candidate_walk_matches_full_walk():

@@ -188,7 +188,67 @@ def test_population_limits():
     assert e.value.code == nep.NEP_E_ARG
     one = ctx.nep_population_efv(sysd, torch.tensor(th[:1], device="cuda"))
     assert one["energy"].shape == (1, s.n_cells)
-    wide = nep.Context(nep_synth.random_model(size="paper"), s.n_atoms, s.n_cells)
+    # the paper-size model's members: the same limits
+    sysw, wide = _setup(s, nep_synth.random_model(size="paper"), 2)
+    thw = _population(nep_synth.random_model(size="paper"), 3, 0.05, 4)
     with pytest.raises(nep.NepError) as e:
-        wide.nep_population_reserve(2)
-    assert e.value.code == nep.NEP_E_UNSUPPORTED
+        wide.nep_population_efv(sysw, torch.tensor(thw, device="cuda"))
+    assert e.value.code == nep.NEP_E_ARG
+    assert wide.nep_population_efv(sysw, torch.tensor(thw[:2], device="cuda"))["energy"].shape == (2, s.n_cells)
+
+
+def test_paper_size_members_equal_the_single_model_path():
+    # the paper-size model (Sec. III.A: the model the paper trains with SNES)
+    # evaluates its members one after another through its staged phases:
+    # each member's results are bitwise those of nep_compute_efv with that
+    # member's parameters
+    import torch
+    import paper_2305_08140_amd as nep
+    m = nep_synth.random_model(size="paper")
+    s = nep_synth.diffbatch(n_cells=24)
+    th = _population(m, 4, 0.05, 11)
+    sysd, ctx = _setup(s, m, 4)
+    res = ctx.nep_population_efv(sysd, torch.tensor(th, device="cuda"))
+    torch.cuda.synchronize()
+    single = nep.Context(m, s.n_atoms, s.n_cells)
+    out = nep.EFV(s.n_atoms, s.n_cells)
+    single.nep_build_neighbors(sysd)
+    for k in range(th.shape[0]):
+        single.nep_set_weights(m.with_param_vector(th[k].astype(np.float64)))
+        single.nep_compute_efv(sysd, out)
+        torch.cuda.synchronize()
+        assert torch.equal(res["energy"][k], out.energy), k
+        assert torch.equal(res["virial"][k], out.virial.reshape(-1, 9)), k
+        assert torch.equal(res["forces"][k, 0], out.fx) and torch.equal(res["forces"][k, 1], out.fy), k
+        assert torch.equal(res["forces"][k, 2], out.fz), k
+    # the context's own weights are untouched by the population call
+    ctx_out = nep.EFV(s.n_atoms, s.n_cells)
+    ctx.nep_compute_efv(sysd, ctx_out)
+    single.nep_set_weights(m)
+    single.nep_compute_efv(sysd, out)
+    torch.cuda.synchronize()
+    assert torch.equal(ctx_out.energy, out.energy)
+
+
+def test_paper_size_population_loss_against_the_oracle():
+    import torch
+    m = nep_synth.random_model(size="paper")
+    teacher = nep_synth.random_model(size="paper", seed=78)
+    s = nep_synth.diffbatch(n_cells=6)
+    E_t, F_t, W_t = S.evaluate_cells(teacher, s)
+    tg = {"energy": E_t, "forces": F_t, "virial": W_t, "has_virial": np.arange(s.n_cells) % 2 == 0}
+    th = _population(m, 3, 0.05, 12)
+    sysd, ctx = _setup(s, m, 3)
+    res = ctx.nep_population_efv(sysd, torch.tensor(th, device="cuda"), _targets_device(tg, torch))
+    torch.cuda.synchronize()
+    na = np.diff(s.cell_start).astype(np.float64)
+    loss_gpu = res["loss"].cpu().numpy()
+    for k in range(th.shape[0]):
+        E, F, W = S.evaluate_cells(m, s, th[k].astype(np.float64))
+        ref = S.loss_terms(th[k].astype(np.float64), E, F, W, tg, na)
+        lg = loss_gpu[k]
+        print(f"[paper-size member {k}] loss gpu {lg[0]:.9f} oracle {ref[0]:.9f}", flush=True)
+        assert abs(lg[1] - ref[1]) <= E_ATOM_TOL
+        assert abs(lg[2] - ref[2]) <= F_REL_TOL * np.sqrt(np.mean(F ** 2))
+        assert abs(lg[3] - ref[3]) <= W_REL_TOL * np.sqrt(np.mean((W / na[:, None, None]) ** 2)) + W_ATOM_TOL
+        assert abs(lg[4] - ref[4]) <= 1e-12 * ref[4] and abs(lg[5] - ref[5]) <= 1e-12 * ref[5]
