@@ -560,8 +560,13 @@ __device__ __forceinline__ void descriptor_atom(
         // the outer neighbour shells sit)
         const double rd = dist_d(ddx * ddx + ddy * ddy + ddz * ddz);
         const double ttd = rd * (1.0 / (double)pc.rc_ang) - 1.0;
-        const float r = (float)rd;
-        const float rinv = frcp(r);
+        // 1/r and the unit vector from the FP64 pair vector as well (one
+        // Newton step on the FP32 reciprocal), each rounded once: near a
+        // lattice site the pair gradients cancel to a few per cent, and a
+        // unit vector formed in FP32 was the largest remaining error there
+        double rinvd = (double)frcp((float)rd);
+        rinvd = rinvd * fma(-rd, rinvd, 2.0);
+        const float rinv = (float)rinvd;
         const float tt = (float)ttd;
         float fc, dfc;
         cutoff(tt, pc.inv_rc_ang, fc, dfc);
@@ -581,7 +586,7 @@ __device__ __forceinline__ void descriptor_atom(
             g[n] = hfc * sn;
             gp[n] = fmaf(hdx, sp, hdfc * sn);
         }
-        const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+        const float ux = (float)(ddx * rinvd), uy = (float)(ddy * rinvd), uz = (float)(ddz * rinvd);
         const SphMono mono(ux, uy, uz);
         float Y[NLM];
         sph_unnorm(mono, Y);

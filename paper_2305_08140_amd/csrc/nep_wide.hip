@@ -584,13 +584,18 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
             continue;
         }
         const float r = fsqrt(r2);
-        const float rinv = frcp(r);
         const float tt = scaled_minus_one(r, pc.inv_rc_ang, pc.inv_rc_ang_lo);
         float fc, dfc;
         cutoff(tt, pc.inv_rc_ang, fc, dfc);
         // x and the Chebyshev terms in FP64 (their rounding is amplified
-        // ~k^4 in dT_k near x = -1), the channel sums rounded once
-        const double ttd = dist_d(ddx * ddx + ddy * ddy + ddz * ddz) * inv_rA - 1.0;
+        // ~k^4 in dT_k near x = -1), the channel sums rounded once; 1/r and
+        // the unit vector from the FP64 pair vector too (as the default
+        // model's gradient walk)
+        const double rd = dist_d(ddx * ddx + ddy * ddy + ddz * ddz);
+        const double ttd = rd * inv_rA - 1.0;
+        double rinvd = (double)frcp((float)rd);
+        rinvd = rinvd * fma(-rd, rinvd, 2.0);
+        const float rinv = (float)rinvd;
         const double xd = 2.0 * ttd * ttd - 1.0;
         const float dxdr = (float)(4.0 * ttd * inv_rA);
         double sn[NC], sp[NC];
@@ -620,7 +625,7 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
             g[c] = hfc * (float)sn[c];
             gp[c] = fmaf(hdx, (float)sp[c], hdfc * (float)sn[c]);
         }
-        const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+        const float ux = (float)(ddx * rinvd), uy = (float)(ddy * rinvd), uz = (float)(ddz * rinvd);
         const SphMono mono(ux, uy, uz);
         float Y[NLM];
         sph_unnorm(mono, Y);
