@@ -554,6 +554,7 @@ static int setup_system(nep_ctx *c, const nep_system *s, hipStream_t st)
     pc.capR = c->cfg.max_neigh_rad;
     if (small_images) { pc.ibits = 4; pc.ioff = 8; pc.jbits = 20; }
     else { pc.ibits = 2; pc.ioff = 1; pc.jbits = 26; }
+    pc.code0 = (uint32_t)pc.ioff | ((uint32_t)pc.ioff << pc.ibits) | ((uint32_t)pc.ioff << (2 * pc.ibits));
     if (max_cell_atoms > (1LL << pc.jbits)) return NEP_E_ARG;
     pc.n = (int)n;
     pc.rmask = c->rmask;

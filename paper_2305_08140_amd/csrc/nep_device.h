@@ -59,6 +59,7 @@ struct PairConsts {
     float zbl_z;                      // nuclear charge
     int capA, capR;                   // list capacities
     int jbits, ibits, ioff;           // neighbour entry encoding
+    uint32_t code0;                   // image code of an entry in the cell itself (no shift)
     int n;                            // atoms (list stride)
     // [word][atom]: bit s of word s/32 is set when the s-th entry of the
     // radial list was inside rc_rad at the last descriptor evaluation (the

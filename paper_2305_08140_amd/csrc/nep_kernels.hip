@@ -755,15 +755,8 @@ __device__ __forceinline__ void force_atom(
 
     // radial + ZBL force of one pair (both ends); returns false outside rc_rad
     auto radial = [&](int32_t e, const AtomRec &rj, float &r2out) -> bool {
-        int n0, n1, n2, j;
-        decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
         double ddx = rj.x - xi, ddy = rj.y - yi, ddz = rj.z - zi;
-        if (n0 | n1 | n2) {
-            const double *h = cg->h;
-            ddx += n0 * h[0] + n1 * h[3] + n2 * h[6];
-            ddy += n0 * h[1] + n1 * h[4] + n2 * h[7];
-            ddz += n0 * h[2] + n1 * h[5] + n2 * h[8];
-        }
+        add_image(e, pc, cg, ddx, ddy, ddz);
         return radial_pair_force(pc, ddx, ddy, ddz, ai, rj.a, Fx, Fy, Fz, W, r2out);
     };
 

@@ -40,6 +40,25 @@ __device__ inline float ftanh(float z)
 
 // ------------------------------------------------------------------ descriptor + network
 
+// The image shift n.h of a list entry added to a pair vector.  Entries in the
+// cell itself (all but those across a periodic face) carry the code code0
+// and are recognised by one comparison, before the code is decoded.
+__device__ __forceinline__ void add_image(int32_t e, const PairConsts &pc, const CellGeom *__restrict__ cg,
+                                          double &dx, double &dy, double &dz)
+{
+    const uint32_t code = (uint32_t)e >> pc.jbits;
+    if (code != pc.code0) {
+        const uint32_t m = (1u << pc.ibits) - 1u;
+        const int n0 = (int)(code & m) - pc.ioff;
+        const int n1 = (int)((code >> pc.ibits) & m) - pc.ioff;
+        const int n2 = (int)(code >> (2 * pc.ibits)) - pc.ioff;
+        const double *h = cg->h;
+        dx += n0 * h[0] + n1 * h[3] + n2 * h[6];
+        dy += n0 * h[1] + n1 * h[4] + n2 * h[7];
+        dz += n0 * h[2] + n1 * h[5] + n2 * h[8];
+    }
+}
+
 // Pair vector in double precision, computed so that the vector seen from the
 // other end of the pair is its exact negative: (x_j - x_i) first, then the
 // image shift n.h (which is exactly negated for -n).
@@ -48,19 +67,12 @@ __device__ inline void pair_vector_d(int32_t e, const PairConsts &pc, int base, 
                                      const CellGeom *__restrict__ cg, int &j, double &dx, double &dy,
                                      double &dz)
 {
-    int n0, n1, n2;
-    decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
-    j += base;
+    j = (int)((uint32_t)e & ((1u << pc.jbits) - 1u)) + base;
     const double4 pj = xq[j];
     dx = pj.x - xi;
     dy = pj.y - yi;
     dz = pj.z - zi;
-    if (n0 | n1 | n2) {
-        const double *h = cg->h;
-        dx += n0 * h[0] + n1 * h[3] + n2 * h[6];
-        dy += n0 * h[1] + n1 * h[4] + n2 * h[7];
-        dz += n0 * h[2] + n1 * h[5] + n2 * h[8];
-    }
+    add_image(e, pc, cg, dx, dy, dz);
 }
 
 // The same pair vector from a neighbour position already gathered.
@@ -68,17 +80,10 @@ __device__ inline void pair_vector_p(int32_t e, const PairConsts &pc, double px,
                                      double yi, double zi, const CellGeom *__restrict__ cg, double &dx, double &dy,
                                      double &dz)
 {
-    int n0, n1, n2, j;
-    decode_entry(e, pc.jbits, pc.ibits, pc.ioff, j, n0, n1, n2);
     dx = px - xi;
     dy = py - yi;
     dz = pz - zi;
-    if (n0 | n1 | n2) {
-        const double *h = cg->h;
-        dx += n0 * h[0] + n1 * h[3] + n2 * h[6];
-        dy += n0 * h[1] + n1 * h[4] + n2 * h[7];
-        dz += n0 * h[2] + n1 * h[5] + n2 * h[8];
-    }
+    add_image(e, pc, cg, dx, dy, dz);
 }
 
 // Software pipeline over one atom's list: entries are loaded two neighbours
