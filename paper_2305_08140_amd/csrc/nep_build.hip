@@ -238,13 +238,18 @@ struct ListBuilder {
           zi(pi.z), nl_ang(nl_ang_), nl_rad(nl_rad_), status(status_)
     {
     }
+    // squared distance to a candidate at pu seen through the image shift:
+    // (x_u - x_i) + shift, exactly the negative of the vector seen from u
+    __device__ __forceinline__ double dist2(const double4 &pu, double sx, double sy, double sz) const
+    {
+        const double dx = (pu.x - xi) + sx, dy = (pu.y - yi) + sy, dz = (pu.z - zi) + sz;
+        return dx * dx + dy * dy + dz * dz;
+    }
     // candidate u (sorted index) at position pu, seen through the image
     // shift (sx, sy, sz) whose entry code is `code`
     __device__ __forceinline__ void offer(int u, const double4 &pu, double sx, double sy, double sz, uint32_t code)
     {
-        // (x_u - x_i) + shift: exactly the negative of the vector seen from u
-        const double dx = (pu.x - xi) + sx, dy = (pu.y - yi) + sy, dz = (pu.z - zi) + sz;
-        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double r2 = dist2(pu, sx, sy, sz);
         if (r2 >= lR2) return;
         const uint32_t jl = (uint32_t)(u - atom_start);
         const int32_t e = (int32_t)(jl | (code << pc.jbits));
@@ -459,10 +464,39 @@ __global__ __launch_bounds__(LB_BS) void k_build_lists_blocks(
         }
     }
     __syncthreads();
+    // Bins out of reach: along a periodic axis of a cell with a diagonal h,
+    // a neighbour bin's atoms lie beyond the shared face (up to the rounding
+    // of the binning, covered by eps), so an atom at distance p from its own
+    // bin's lower face is at least p (offset -1) or w - p (offset +1) from
+    // them; a bin whose nearest point is outside the list cutoff holds no
+    // entry and is skipped (the lists are unchanged).
+    const bool diag = cg.h[1] == 0.0 && cg.h[2] == 0.0 && cg.h[3] == 0.0 && cg.h[5] == 0.0 && cg.h[6] == 0.0 &&
+                      cg.h[7] == 0.0;
+    double bw[3];
+    bool prune[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bw[a] = cg.h[4 * a] / cg.nb[a];
+        prune[a] = diag && cg.periodic[a];
+    }
     for (int t = s_a[0] + tid; t < s_a[1]; t += LB_BS) {
-        ListBuilder lb(pc, lA2, lR2, cA2, cR2, t, cg.atom_start, xq[t], nl_ang, nl_rad, status);
+        const double4 pt = xq[t];
+        ListBuilder lb(pc, lA2, lR2, cA2, cR2, t, cg.atom_start, pt, nl_ang, nl_rad, status);
         const int lbin = bin_sorted[t];
         const int bc[3] = {lbin % cg.nb[0], (lbin / cg.nb[0]) % cg.nb[1], lbin / (cg.nb[0] * cg.nb[1])};
+        // distances to the lower and upper faces of the own bin (0 where no
+        // pruning applies)
+        double dlo[3], dhi[3];
+        {
+            const double pa[3] = {pt.x, pt.y, pt.z};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double eps = 1e-9 * cg.h[4 * a];
+                const double p = pa[a] - bc[a] * bw[a];
+                dlo[a] = prune[a] ? fmax(p - eps, 0.0) : 0.0;
+                dhi[a] = prune[a] ? fmax(bw[a] - p - eps, 0.0) : 0.0;
+            }
+        }
         // the 27 neighbour bins in storage order (keys gb << 5 | offset)
         uint32_t key[32];
 #pragma unroll
@@ -483,6 +517,15 @@ __global__ __launch_bounds__(LB_BS) void k_build_lists_blocks(
             if (kq == 0xffffffffu) break;
             const int q = (int)(kq & 31u);
             const int o[3] = {q % 3 - 1, (q / 3) % 3 - 1, q / 9 - 1};
+            {
+                double d2 = 0.0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double d = o[a] < 0 ? dlo[a] : (o[a] > 0 ? dhi[a] : 0.0);
+                    d2 = fma(d, d, d2);
+                }
+                if (d2 >= lR2) continue;
+            }
             int m[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
