@@ -192,6 +192,17 @@ int nep_set_weights(nep_ctx *ctx, const nep_weights *w, int32_t weights_on_devic
  * Returns NEP_OK, NEP_E_ARG or NEP_E_HIP. */
 int nep_build_neighbors(nep_ctx *ctx, const nep_system *sys, void *stream);
 
+/* The lists of nep_build_neighbors kept while they are valid: for the system
+ * the lists were built for (same atom count, cells and cell sizes), the
+ * device compares the positions with those of the last build and rebuilds
+ * only if an atom has moved more than skin/2 (the skin criterion of the
+ * paper's MD, Sec. II.B) or the lists are unusable; any other system is
+ * built in full.  The decision stays on the device (no synchronisation), so
+ * repeated evaluations of slowly changing configurations (a differentiable
+ * training loop, a relaxation) pay for a build only when one is due.  Same
+ * arguments, errors and allocation behaviour as nep_build_neighbors. */
+int nep_update_neighbors(nep_ctx *ctx, const nep_system *sys, void *stream);
+
 /* Energy, forces and virial of `sys` at its current positions (Eq. 1: the
  * network site energies of the radial and angular descriptors plus half of
  * the ZBL pair energy of Eqs. 2-4 for every pair closer than the outer

@@ -35,7 +35,8 @@ NEP_LOSS_TERMS = 6
 # loss weights of Sec. III.A
 PAPER_LAMBDAS = {"e": 1.0, "f": 1.0, "v": 0.1, "l1": 0.05, "l2": 0.05}
 
-EXPORTED = ("nep_create", "nep_destroy", "nep_set_weights", "nep_build_neighbors", "nep_compute_efv",
+EXPORTED = ("nep_create", "nep_destroy", "nep_set_weights", "nep_build_neighbors", "nep_update_neighbors",
+            "nep_compute_efv",
             "nep_step_verlet", "nep_status", "nep_required_neighbors", "nep_mean_neighbors",
             "nep_time_efv", "nep_num_params", "nep_backward", "nep_backward_noalloc", "nep_compute_efv_graph", "nep_autotune",
             "nep_set_precision", "nep_wigner_seitz", "nep_population_reserve", "nep_population_efv",
@@ -123,6 +124,7 @@ def lib():
         L.nep_destroy.restype = None
         L.nep_set_weights.argtypes = [P, C.POINTER(Weights), C.c_int32, P]
         L.nep_build_neighbors.argtypes = [P, C.POINTER(System), P]
+        L.nep_update_neighbors.argtypes = [P, C.POINTER(System), P]
         L.nep_compute_efv.argtypes = [P, C.POINTER(System), C.POINTER(Efv), P]
         L.nep_step_verlet.argtypes = [P, C.POINTER(System), C.POINTER(Md), C.c_int32, C.POINTER(Efv),
                                       C.POINTER(MdStats), P]
@@ -294,6 +296,14 @@ class Context:
         self.state_token = None
         s = system.c_struct()
         _check(lib().nep_build_neighbors(self._ptr, C.byref(s), _stream_ptr(stream)), "nep_build_neighbors")
+        if self.check:
+            self.nep_status(stream)
+
+    def nep_update_neighbors(self, system: DeviceSystem, stream=None):
+        """Rebuild the lists only if an atom moved more than skin/2 since the last build (decided on the device)."""
+        self.state_token = None
+        s = system.c_struct()
+        _check(lib().nep_update_neighbors(self._ptr, C.byref(s), _stream_ptr(stream)), "nep_update_neighbors")
         if self.check:
             self.nep_status(stream)
 

@@ -55,7 +55,9 @@ class NEPEnergy(torch.autograd.Function):
         sysd.mass = float(mass)
         sysd.n_atoms = p.shape[0]
         out = EFV(sysd.n_atoms, sysd.n_cells, device=pos.device)
-        context.nep_build_neighbors(sysd)
+        # the lists are rebuilt only when due (an atom moved more than skin/2
+        # since the last build, or another system)
+        context.nep_update_neighbors(sysd)
         context.nep_compute_efv(sysd, out)
         # the context now holds this forward's weights and lists
         token = object()

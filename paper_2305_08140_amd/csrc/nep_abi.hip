@@ -743,6 +743,23 @@ static int launch_build(nep_ctx *c, const nep_system *s, hipStream_t st, const i
     return NEP_OK;
 }
 
+int nep_update_neighbors(nep_ctx *c, const nep_system *s, void *stream)
+{
+    if (!c) return NEP_E_ARG;
+    int rc = check_system(c, s, false);
+    if (rc) return rc;
+    if (!c->built || !same_system(c, s)) return nep_build_neighbors(c, s, stream);
+    // the rebuild decision on the device: the largest displacement since the
+    // last build against skin/2 (unusable lists are rebuilt as well); the
+    // build's launches skip their work when the flag says no
+    hipStream_t st = (hipStream_t)stream;
+    const int n = (int)s->n_atoms;
+    const double half_skin2 = 0.25 * c->cfg.skin * c->cfg.skin;
+    k_disp<<<stream_grid(n), 256, 0, st>>>(n, s->x, s->y, s->z, c->xref, c->md);
+    k_rebuild_flag<<<1, 64, 0, st>>>(half_skin2, c->md, c->flag, c->status);
+    return launch_build(c, s, st, c->flag);
+}
+
 int nep_build_neighbors(nep_ctx *c, const nep_system *s, void *stream)
 {
     if (!c) return NEP_E_ARG;

@@ -175,3 +175,53 @@ def test_largest_system_of_one_context():
     err = np.linalg.norm(Fs - ref["forces"]) / np.linalg.norm(ref["forces"])
     print(f"[2^26] sampled force rel err {err:.2e}", flush=True)
     assert err <= F_REL_TOL
+
+
+def test_update_neighbors_keeps_valid_lists_and_rebuilds_stale_ones():
+    # nep_update_neighbors: after moves below skin/2 the lists built before
+    # still hold every pair within the cutoffs; after a few atoms jumped by
+    # 1.6 A they do not (an evaluation on them misses pairs, and differs from
+    # the FP64 oracle), and the update must rebuild them (device decision)
+    import torch
+    import paper_2305_08140_amd as nep
+    m = model()
+    s = nep_synth.mid(n_cells=20)
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(m, s.n_atoms, 1)
+    out = nep.EFV(s.n_atoms, 1)
+    ctx.nep_build_neighbors(sysd)
+    ctx.nep_compute_efv(sysd, out)
+    rng = np.random.default_rng(31)
+
+    def set_pos(p):
+        t = torch.tensor(p, device="cuda")
+        sysd.x.copy_(t[:, 0])
+        sysd.y.copy_(t[:, 1])
+        sysd.z.copy_(t[:, 2])
+
+    def check(label, idx, expect_ok):
+        torch.cuda.synchronize()
+        pos = sysd.positions().cpu().numpy()
+        F = out.forces().cpu().numpy().astype(np.float64)[idx]
+        ref = oracle.efv_cell(m, pos, s.h[0], targets=idx, virial=False)["forces"]
+        err = np.linalg.norm(F - ref) / np.linalg.norm(ref)
+        print(f"[update neighbors] {label}: sampled force rel err {err:.3e}", flush=True)
+        assert (err <= F_REL_TOL) == expect_ok, (label, err)
+
+    # small moves (0.15 A per component at most): the kept lists are complete
+    p0 = s.pos + rng.uniform(-0.15, 0.15, s.pos.shape)
+    set_pos(p0)
+    ctx.nep_update_neighbors(sysd)
+    ctx.nep_compute_efv(sysd, out)
+    idx = np.sort(rng.choice(s.n_atoms, 128, replace=False))
+    check("moves below skin/2", idx, True)
+    # 16 atoms jump 1.6 A along x: the old lists miss pairs around them
+    movers = np.sort(rng.choice(s.n_atoms, 16, replace=False))
+    p1 = p0.copy()
+    p1[movers, 0] += 1.6
+    set_pos(p1)
+    ctx.nep_compute_efv(sysd, out)        # on the stale lists
+    check("stale lists", movers, False)
+    ctx.nep_update_neighbors(sysd)
+    ctx.nep_compute_efv(sysd, out)
+    check("after the update", movers, True)
