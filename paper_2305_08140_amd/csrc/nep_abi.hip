@@ -17,8 +17,8 @@ namespace nep {
 template <int BS, bool PE, int NNMODE>
 __global__ void k_descriptor(PairConsts, const double4 *, AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
                              const int32_t *, const uint32_t *, const float *, const double *, float4 *, float4 *,
-                             float *, double *, int32_t *, int, const int32_t *);
-template <int BS, bool PE>
+                             float *, double *, int32_t *, int, const int32_t *, const int32_t *);
+template <int BS, bool PE, bool D48>
 __global__ void k_force(PairConsts, const AtomRec *, const int32_t *, const CellGeom *, const int32_t *,
                         const int32_t *, const uint32_t *, const uint8_t *, const float4 *, const float4 *,
                         const int32_t *, float *, float *, float *, float *, int32_t *, int);
@@ -555,7 +555,35 @@ static int setup_system(nep_ctx *c, const nep_system *s, hipStream_t st)
     if (small_images) { pc.ibits = 4; pc.ioff = 8; pc.jbits = 20; }
     else { pc.ibits = 2; pc.ioff = 1; pc.jbits = 26; }
     pc.code0 = (uint32_t)pc.ioff | ((uint32_t)pc.ioff << pc.ibits) | ((uint32_t)pc.ioff << (2 * pc.ibits));
+    // bin edge vectors; bin-offset mode for one periodic cell binned along
+    // every axis with at most 2^23 atoms (23 index bits + 5 offset + 3 face)
+    for (int k = 0; k < nc; ++k)
+        for (int a = 0; a < 3; ++a)
+            for (int d = 0; d < 3; ++d) c->geom[k].bv[3 * a + d] = c->geom[k].h[3 * a + d] / c->geom[k].nb[a];
+    {
+        const CellGeom &g = c->geom[0];
+        bool delta = nc == 1 && n <= (1LL << 23);
+        for (int a = 0; a < 3; ++a) delta = delta && g.periodic[a] && g.R[a] == 0;
+        pc.delta = delta ? 1 : 0;
+        pc.qs = pc.qsinv = 1.0;
+        if (delta) {
+            pc.jbits = 23;
+            // fixed-point unit of the force records' offsets: an atom lies in
+            // its bin (sum of the edge vectors) give or take half the skin
+            // until the next build; 1 A more for safety
+            double range = 0.0;
+            for (int d = 0; d < 3; ++d)
+                range = std::max(range, std::fabs(g.bv[d]) + std::fabs(g.bv[3 + d]) + std::fabs(g.bv[6 + d]));
+            range += c->cfg.skin + 1.0;
+            const int kq = (int)std::floor(std::log2(2147483000.0 / range));
+            pc.qs = std::ldexp(1.0, -kq);
+            pc.qsinv = std::ldexp(1.0, kq);
+        }
+    }
     if (max_cell_atoms > (1LL << pc.jbits)) return NEP_E_ARG;
+    // no-image test: the crossing bits clear, or the code of the cell itself
+    pc.img_mask = pc.delta ? ~31u : 0xffffffffu;
+    pc.img_val = pc.delta ? 0u : pc.code0;
     pc.n = (int)n;
     pc.rmask = c->rmask;
     pc.cmask = c->cmask;
@@ -800,7 +828,7 @@ static void launch_desc_t(nep_ctx *c, hipStream_t st)
     }
     k_descriptor<BS, PE, NNMODE><<<grid, BS, 0, st>>>(c->pc, c->xq, c->xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad,
                                                       c->ncnt, c->params, c->c64, c->pair_grad, c->f_own, c->w_atom,
-                                                      c->e_atom, c->status, tiles, c->cflag);
+                                                      c->e_atom, c->status, tiles, c->cflag, c->bin_sorted);
 }
 
 template <int BS, bool PE>
@@ -818,12 +846,18 @@ static void launch_force_t(nep_ctx *c, const nep_efv *o, hipStream_t st)
     int grid = xcd_grid(tiles);
     if (PE) {
         int per_cu = 1;
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_force<BS, PE>, BS, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_force<BS, PE, false>, BS, 0);
         grid = std::max(1, std::min(tiles, 256 * std::max(per_cu, 1)));
     }
-    k_force<BS, PE><<<grid, BS, 0, st>>>(c->pc, c->xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->rev,
-                                         c->pair_grad, c->f_own, c->perm, o->fx, o->fy, o->fz, c->w_atom, c->status,
-                                         tiles);
+    // the descriptor kernel wrote 48-byte records in bin-offset mode
+    if (c->pc.delta)
+        k_force<BS, PE, true><<<grid, BS, 0, st>>>(c->pc, c->xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
+                                                   c->rev, c->pair_grad, c->f_own, c->perm, o->fx, o->fy, o->fz,
+                                                   c->w_atom, c->status, tiles);
+    else
+        k_force<BS, PE, false><<<grid, BS, 0, st>>>(c->pc, c->xp, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
+                                                    c->rev, c->pair_grad, c->f_own, c->perm, o->fx, o->fy, o->fz,
+                                                    c->w_atom, c->status, tiles);
 }
 
 static void launch_desc(nep_ctx *c, int shape, hipStream_t st)

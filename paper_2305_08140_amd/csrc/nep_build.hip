@@ -263,6 +263,12 @@ struct ListBuilder {
         cntA += ang ? inc : 0ull;
         cntR += ang ? 0ull : inc;
     }
+    // the entry code of a neighbour in the bin at stencil offset q (bin-offset
+    // mode) or seen through the image m (otherwise)
+    __device__ uint32_t entry_code(int q, const int m[3]) const
+    {
+        return pc.delta ? delta_code(q, m) : image_code(m);
+    }
     __device__ uint32_t image_code(const int m[3]) const
     {
         return (uint32_t)(m[0] + pc.ioff) | ((uint32_t)(m[1] + pc.ioff) << pc.ibits) |
@@ -329,12 +335,12 @@ __global__ __launch_bounds__(256) void k_build_lists(
         if (out) return -1;
         return cg.bin_offset + bin_rank[cg.bin_offset + (bb[2] * cg.nb[1] + bb[1]) * cg.nb[0] + bb[0]];
     };
-    auto scan_bin = [&](int gb, const int m[3]) __attribute__((always_inline)) {
+    auto scan_bin = [&](int gb, int q, const int m[3]) __attribute__((always_inline)) {
         const double sx = m[0] * cg.h[0] + m[1] * cg.h[3] + m[2] * cg.h[6];
         const double sy = m[0] * cg.h[1] + m[1] * cg.h[4] + m[2] * cg.h[7];
         const double sz = m[0] * cg.h[2] + m[1] * cg.h[5] + m[2] * cg.h[8];
         const bool self_image = (m[0] | m[1] | m[2]) == 0;
-        const uint32_t code = lb.image_code(m);
+        const uint32_t code = lb.entry_code(q, m);
         for (int u = bin_start[gb]; u < bin_start[gb + 1]; ++u) {
             if (u == t && self_image) continue;
             lb.offer(u, xq[u], sx, sy, sz, code);
@@ -364,7 +370,7 @@ __global__ __launch_bounds__(256) void k_build_lists(
             const int q = (int)(kq & 31u);
             int m[3];
             const int gb = bin_at(q % 3 - 1, (q / 3) % 3 - 1, q / 9 - 1, m);
-            scan_bin(gb, m);
+            scan_bin(gb, q, m);
         }
     } else {
         for (int o2 = lo[2]; o2 <= hi[2]; ++o2)
@@ -372,7 +378,8 @@ __global__ __launch_bounds__(256) void k_build_lists(
                 for (int o0 = lo[0]; o0 <= hi[0]; ++o0) {
                     int m[3];
                     const int gb = bin_at(o0, o1, o2, m);
-                    if (gb >= 0) scan_bin(gb, m);
+                    // (the stencil offset names the bin only with every axis binned)
+                    if (gb >= 0) scan_bin(gb, (o0 + 1) + 3 * (o1 + 1) + 9 * (o2 + 1), m);
                 }
     }
     lb.finish(ncnt);
@@ -538,7 +545,7 @@ __global__ __launch_bounds__(LB_BS) void k_build_lists_blocks(
             const double sy = m[0] * cg.h[1] + m[1] * cg.h[4] + m[2] * cg.h[7];
             const double sz = m[0] * cg.h[2] + m[1] * cg.h[5] + m[2] * cg.h[8];
             const bool self_image = (m[0] | m[1] | m[2]) == 0;
-            const uint32_t code = lb.image_code(m);
+            const uint32_t code = lb.entry_code(q, m);
             const int r0 = s_off[hb], r1 = s_off[hb + 1], u0 = s_gst[hb] - r0;
             // (two loops, so that the LDS one issues no memory loads)
             if (staged) {
@@ -586,10 +593,17 @@ __global__ __launch_bounds__(256) void k_build_reverse(PairConsts pc, const int3
         const uint32_t e = (uint32_t)nl_ang[(size_t)slot * pc.n + t];
         const int j = (int)(e & jmask) + base;
         const uint32_t code = e >> pc.jbits;
-        const int n0 = (int)(code & imask) - pc.ioff, n1 = (int)((code >> pc.ibits) & imask) - pc.ioff,
-                  n2 = (int)(code >> (2 * pc.ibits)) - pc.ioff;
-        const uint32_t want = tl | (((uint32_t)(-n0 + pc.ioff) | ((uint32_t)(-n1 + pc.ioff) << pc.ibits) |
-                                     ((uint32_t)(-n2 + pc.ioff) << (2 * pc.ibits))) << pc.jbits);
+        uint32_t want;
+        if (pc.delta) {
+            // the partner's bin offset is the negated one (q -> 26 - q), the
+            // same faces crossed
+            want = tl | (((26u - (code & 31u)) | (code & ~31u)) << pc.jbits);
+        } else {
+            const int n0 = (int)(code & imask) - pc.ioff, n1 = (int)((code >> pc.ibits) & imask) - pc.ioff,
+                      n2 = (int)(code >> (2 * pc.ibits)) - pc.ioff;
+            want = tl | (((uint32_t)(-n0 + pc.ioff) | ((uint32_t)(-n1 + pc.ioff) << pc.ibits) |
+                          ((uint32_t)(-n2 + pc.ioff) << (2 * pc.ibits))) << pc.jbits);
+        }
         const uint32_t cj = ncnt[j];
         const int jf = cj & 0xff, jb = (cj >> 8) & 0xff;
         // both ends classify the pair from the same r^2 (exactly negated FP64

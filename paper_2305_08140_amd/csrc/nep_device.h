@@ -44,6 +44,18 @@ struct __attribute__((aligned(64))) AtomRec {
 };
 static_assert(sizeof(AtomRec) == 64, "AtomRec must be 64 bytes");
 
+// The force kernel's record in bin-offset mode (PairConsts::delta): the
+// position as 32-bit fixed-point offsets from the corner of the atom's bin
+// at the last build (units PairConsts::qs), and the radial adjoints; 48
+// bytes, three 16-byte pieces per gather instead of four.  Pair vectors
+// formed from two records, d = sum_a o_a bv_a + qs (o_j - o_i) (o the
+// neighbour-bin offset), are exact negatives of each other.
+struct __attribute__((aligned(16))) AtomRec48 {
+    int32_t o[3];
+    float a[KB];
+};
+static_assert(sizeof(AtomRec48) == 48, "AtomRec48 must be 48 bytes");
+
 // Runtime constants shared by the pair kernels.
 struct PairConsts {
     float rc_rad, rc_ang;             // cutoffs
@@ -60,6 +72,16 @@ struct PairConsts {
     int capA, capR;                   // list capacities
     int jbits, ibits, ioff;           // neighbour entry encoding
     uint32_t code0;                   // image code of an entry in the cell itself (no shift)
+    // an entry names no image iff (code & img_mask) == img_val (either mode)
+    uint32_t img_mask, img_val;
+    // Bin-offset mode (one periodic cell, every axis binned, at most 2^23
+    // atoms): an entry is j | q << jbits | cr << (jbits + 5), q = (o0 + 1) +
+    // 3 (o1 + 1) + 9 (o2 + 1) the offset o of j's bin from i's in the 27-bin
+    // stencil and cr the axes across whose periodic face that bin lies (the
+    // image is n_a = o_a on those axes, 0 on the others); the default
+    // model's force records are then AtomRec48 with offsets in units qs.
+    int delta;
+    double qs, qsinv;
     int n;                            // atoms (list stride)
     // [word][atom]: bit s of word s/32 is set when the s-th entry of the
     // radial list was inside rc_rad at the last descriptor evaluation (the
@@ -90,6 +112,7 @@ struct CellGeom {
     int nb[3];         // bins per axis (1 for image-loop axes)
     int R[3];          // image range for image-loop axes, 0 for binned axes
     int periodic[3];
+    double bv[9];      // rows: bin edge vectors h_a / nb_a
     int bin_offset;    // first global bin of this cell
     int atom_start;    // first atom (caller and sorted order coincide per cell)
     int n_atoms;
@@ -544,6 +567,14 @@ __host__ __device__ inline void zbl_pair(double r, double Z, double r1, double r
     const double rinv = 1.0 / r;
     U = k * rinv * phi * ft;
     dU = k * rinv * (dphi * ft + phi * dft - phi * ft * rinv);
+}
+
+// Bin-offset mode: the entry code of a neighbour in the bin at stencil offset
+// q = (o0 + 1) + 3 (o1 + 1) + 9 (o2 + 1), seen through the image m (nonzero
+// only on the axes whose periodic face that bin lies across).
+__host__ __device__ inline uint32_t delta_code(int q, const int m[3])
+{
+    return (uint32_t)q | ((uint32_t)((m[0] != 0) | ((m[1] != 0) << 1) | ((m[2] != 0) << 2)) << 5);
 }
 
 // ---------------------------------------------------------------- neighbours

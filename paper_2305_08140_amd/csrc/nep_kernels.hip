@@ -39,6 +39,7 @@
 // ends agree bit for bit on which pairs are inside a cutoff.
 // Virial: W = -sum_i sum_j dU_i/dr_ij (x) r_ij (angular, per owner) plus
 // -1/2 sum_i sum_j f_ij (x) r_ij for the radial and ZBL pair forces f_ij.
+#include <type_traits>
 #include "nep_device.h"
 #include "nep_pairs.h"
 
@@ -467,6 +468,7 @@ __device__ __forceinline__ float network_mfma32(const float *__restrict__ P, con
 template <int NNMODE>
 __device__ __forceinline__ void descriptor_atom(
     int t, bool valid, NNLds *L, const PairConsts &pc, const double4 *__restrict__ xq, AtomRec *__restrict__ xp,
+    AtomRec48 *__restrict__ xp48, const int32_t *__restrict__ bin_sorted,
     const int32_t *__restrict__ cell_of, const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     const float *__restrict__ P, const double *__restrict__ C64, float4 *__restrict__ pair_grad,
@@ -514,7 +516,28 @@ __device__ __forceinline__ void descriptor_atom(
         rec.a[k] = s;
     }
     rec.pad = 0.0f;
-    xp[t] = rec;
+    if (xp48) {
+        // bin-offset mode: the position as fixed-point offsets from the
+        // corner of the atom's bin at the last build (an offset out of the
+        // 32-bit range means the atom moved far beyond the list skin)
+        const int lbin = bin_sorted[t];
+        const int b0 = lbin % cg->nb[0], b1 = (lbin / cg->nb[0]) % cg->nb[1], b2 = lbin / (cg->nb[0] * cg->nb[1]);
+        const double *bv = cg->bv;
+        const double p[3] = {xi - (b0 * bv[0] + b1 * bv[3] + b2 * bv[6]), yi - (b0 * bv[1] + b1 * bv[4] + b2 * bv[7]),
+                             zi - (b0 * bv[2] + b1 * bv[5] + b2 * bv[8])};
+        AtomRec48 r48;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double v = rint(p[d] * pc.qsinv);
+            if (!(fabs(v) < 2147483000.0)) latch_error(status, -9);
+            r48.o[d] = (int32_t)fmin(fmax(v, -2147483000.0), 2147483000.0);
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) r48.a[k] = rec.a[k];
+        xp48[t] = r48;
+    } else {
+        xp[t] = rec;
+    }
     // angular adjoint B_{n,lm} = 2 (dU/dq_nl) s_{n,lm}, in place of S, times
     // the harmonic's normalisation (the walk below uses the unnormalised
     // polynomials y_lm = Y_lm / sph_norm(lm))
@@ -639,9 +662,11 @@ __global__ __launch_bounds__(BS, NNMODE == 1 ? 1 : 2) void k_descriptor(
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     const float *__restrict__ P, const double *__restrict__ C64, float4 *__restrict__ pair_grad,
     float4 *__restrict__ f_own, float *__restrict__ w_atom, double *__restrict__ e_atom,
-    int32_t *__restrict__ status, int ntiles, const int32_t *__restrict__ cflag)
+    int32_t *__restrict__ status, int ntiles, const int32_t *__restrict__ cflag,
+    const int32_t *__restrict__ bin_sorted)
 {
     __shared__ NNLds lds[NNMODE != 0 ? BS / 64 : 1];
+    AtomRec48 *xp48 = pc.delta ? reinterpret_cast<AtomRec48 *>(xp) : nullptr;
     NNLds *L = &lds[NNMODE != 0 ? threadIdx.x / 64 : 0];
     if (lists_blocked(status)) return;
     // radial walk: in full (and the candidate mask written) when *cflag is set
@@ -650,14 +675,16 @@ __global__ __launch_bounds__(BS, NNMODE == 1 ? 1 : 2) void k_descriptor(
         for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
             const int t = tile * BS + threadIdx.x;
             if (NNMODE != 0 || t < pc.n)
-                descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xq, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, C64, pair_grad,
+                descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xq, xp, xp48, bin_sorted, cell_of, cells, nl_ang, nl_rad, ncnt,
+                                        P, C64, pair_grad,
                                         f_own, w_atom, e_atom, status, cand_mode);
         }
     } else {
         const int tile = xcd_block(ntiles);
         const int t = tile * BS + threadIdx.x;
         if (tile < ntiles && (NNMODE != 0 || t < pc.n))
-            descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xq, xp, cell_of, cells, nl_ang, nl_rad, ncnt, P, C64, pair_grad,
+            descriptor_atom<NNMODE>(t, t < pc.n, L, pc, xq, xp, xp48, bin_sorted, cell_of, cells, nl_ang, nl_rad, ncnt,
+                                    P, C64, pair_grad,
                                     f_own, w_atom, e_atom, status, cand_mode);
     }
 }
@@ -729,15 +756,21 @@ __device__ __forceinline__ bool radial_pair_force(const PairConsts &pc, double d
 // and the radial + ZBL virial -1/2 sum_j f_ij (x) r_ij added to the angular one.
 // Each neighbour costs one 64-byte record gather (position and adjoint) and,
 // for angular entries, one 16-byte pair-gradient gather.
+// D48: bin-offset mode, 48-byte records (AtomRec48): the pair vector is the
+// sum of the neighbour bin's edge vectors and the difference of the two
+// fixed-point offsets, exactly antisymmetric as the FP64 positions' one.
+template <bool D48>
 __device__ __forceinline__ void force_atom(
-    int t, const PairConsts &pc, const AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
+    int t, const PairConsts &pc, const AtomRec *__restrict__ xp_, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     const uint8_t *__restrict__ rev, const float4 *__restrict__ pair_grad, const float4 *__restrict__ f_own,
     const int32_t *__restrict__ perm, float *__restrict__ fx, float *__restrict__ fy,
     float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status)
 {
-    const double xi = xp[t].x, yi = xp[t].y, zi = xp[t].z;
+    using Rec = typename std::conditional<D48, AtomRec48, AtomRec>::type;
+    const Rec *__restrict__ xp = reinterpret_cast<const Rec *>(xp_);
+    const Rec own = xp[t];
     const CellGeom *cg = cells + cell_of[t];
     const int base = cg->atom_start;
     const uint32_t cnt = ncnt[t];
@@ -745,7 +778,7 @@ __device__ __forceinline__ void force_atom(
 
     float ai[KB];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) ai[k] = xp[t].a[k];
+    for (int k = 0; k < KB; ++k) ai[k] = own.a[k];
     const float4 fo = f_own[t];
     double Fx = fo.x, Fy = fo.y, Fz = fo.z;
     float W[9];
@@ -754,9 +787,21 @@ __device__ __forceinline__ void force_atom(
     bool bad = false;
 
     // radial + ZBL force of one pair (both ends); returns false outside rc_rad
-    auto radial = [&](int32_t e, const AtomRec &rj, float &r2out) -> bool {
-        double ddx = rj.x - xi, ddy = rj.y - yi, ddz = rj.z - zi;
-        add_image(e, pc, cg, ddx, ddy, ddz);
+    auto radial = [&](int32_t e, const Rec &rj, float &r2out) -> bool {
+        double ddx, ddy, ddz;
+        if constexpr (D48) {
+            const int q = (int)(((uint32_t)e >> pc.jbits) & 31u);
+            const double o0 = q % 3 - 1, o1 = (q / 3) % 3 - 1, o2 = q / 9 - 1;
+            const double *bv = cg->bv;
+            ddx = fma(pc.qs, (double)rj.o[0] - (double)own.o[0], o0 * bv[0] + o1 * bv[3] + o2 * bv[6]);
+            ddy = fma(pc.qs, (double)rj.o[1] - (double)own.o[1], o0 * bv[1] + o1 * bv[4] + o2 * bv[7]);
+            ddz = fma(pc.qs, (double)rj.o[2] - (double)own.o[2], o0 * bv[2] + o1 * bv[5] + o2 * bv[8]);
+        } else {
+            ddx = rj.x - own.x;
+            ddy = rj.y - own.y;
+            ddz = rj.z - own.z;
+            add_image(e, pc, cg, ddx, ddy, ddz);
+        }
         return radial_pair_force(pc, ddx, ddy, ddz, ai, rj.a, Fx, Fy, Fz, W, r2out);
     };
 
@@ -767,7 +812,7 @@ __device__ __forceinline__ void force_atom(
     ListWalk wa(t, pc.n, naf, nab, pc.capA);
     int32_t e_cur = 0, e_nx = 0;
     int sj_cur = 255, sj_nx = 255;
-    AtomRec r_cur;
+    Rec r_cur;
     if (nA > 0) {
         e_cur = nl_ang[wa.off];
         sj_cur = rev[wa.off];
@@ -778,7 +823,7 @@ __device__ __forceinline__ void force_atom(
     for (int s = 0; s < nA; ++s) {
         const int32_t e = e_cur;
         const int sj = sj_cur;
-        const AtomRec rj = r_cur;
+        const Rec rj = r_cur;
         if (s + 1 < nA) {
             e_cur = e_nx;
             sj_cur = sj_nx;
@@ -810,7 +855,7 @@ __device__ __forceinline__ void force_atom(
     if (s_nx >= 0) e_nx = nl_rad[rad_off(s_nx)];
     while (s_cur >= 0) {
         const int32_t e = e_cur;
-        const AtomRec rj = r_cur;
+        const Rec rj = r_cur;
         s_cur = s_nx;
         if (s_cur >= 0) {
             e_cur = e_nx;
@@ -834,7 +879,7 @@ __device__ __forceinline__ void force_atom(
 
 // (three waves per SIMD: the FP64 pair term needs more registers than the
 // default allocation for this block size would leave)
-template <int BS, bool PERSISTENT>
+template <int BS, bool PERSISTENT, bool D48>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_force(
     PairConsts pc, const AtomRec *__restrict__ xp, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
@@ -848,15 +893,15 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_
         for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
             const int t = tile * BS + threadIdx.x;
             if (t < pc.n)
-                force_atom(t, pc, xp, cell_of, cells, nl_ang, nl_rad, ncnt, rev, pair_grad, f_own, perm, fx, fy, fz,
-                           w_atom, status);
+                force_atom<D48>(t, pc, xp, cell_of, cells, nl_ang, nl_rad, ncnt, rev, pair_grad, f_own, perm, fx,
+                                fy, fz, w_atom, status);
         }
     } else {
         const int tile = xcd_block(ntiles);
         const int t = tile * BS + threadIdx.x;
         if (tile < ntiles && t < pc.n)
-            force_atom(t, pc, xp, cell_of, cells, nl_ang, nl_rad, ncnt, rev, pair_grad, f_own, perm, fx, fy, fz,
-                       w_atom, status);
+            force_atom<D48>(t, pc, xp, cell_of, cells, nl_ang, nl_rad, ncnt, rev, pair_grad, f_own, perm, fx, fy,
+                            fz, w_atom, status);
     }
 }
 
@@ -867,21 +912,27 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_
                                                      const CellGeom *,                                             \
                                                      const int32_t *, const int32_t *, const uint32_t *,           \
                                                      const float *, const double *, float4 *, float4 *, float *, double *, int32_t *, \
-                                                     int, const int32_t *);                                          \
+                                                     int, const int32_t *, const int32_t *);                                          \
     template __global__ void k_descriptor<BS, PE, 1>(PairConsts, const double4 *, AtomRec *, const int32_t *,      \
                                                      const CellGeom *,                                             \
                                                      const int32_t *, const int32_t *, const uint32_t *,           \
                                                      const float *, const double *, float4 *, float4 *, float *, double *, int32_t *, \
-                                                     int, const int32_t *);                                          \
+                                                     int, const int32_t *, const int32_t *);                                          \
     template __global__ void k_descriptor<BS, PE, 2>(PairConsts, const double4 *, AtomRec *, const int32_t *,      \
                                                      const CellGeom *,                                             \
                                                      const int32_t *, const int32_t *, const uint32_t *,           \
                                                      const float *, const double *, float4 *, float4 *, float *, double *, int32_t *, \
-                                                     int, const int32_t *);                                          \
-    template __global__ void k_force<BS, PE>(PairConsts, const AtomRec *, const int32_t *, const CellGeom *,       \
-                                             const int32_t *, const int32_t *, const uint32_t *, const uint8_t *,   \
-                                             const float4 *, const float4 *, const int32_t *, float *, float *,      \
-                                             float *, float *, int32_t *, int);
+                                                     int, const int32_t *, const int32_t *);                                          \
+    template __global__ void k_force<BS, PE, false>(PairConsts, const AtomRec *, const int32_t *, const CellGeom *, \
+                                                    const int32_t *, const int32_t *, const uint32_t *,            \
+                                                    const uint8_t *, const float4 *, const float4 *,               \
+                                                    const int32_t *, float *, float *, float *, float *, int32_t *,\
+                                                    int);                                                          \
+    template __global__ void k_force<BS, PE, true>(PairConsts, const AtomRec *, const int32_t *, const CellGeom *,  \
+                                                   const int32_t *, const int32_t *, const uint32_t *,             \
+                                                   const uint8_t *, const float4 *, const float4 *,                \
+                                                   const int32_t *, float *, float *, float *, float *, int32_t *, \
+                                                   int);
 NEP_SHAPES(NEP_INST)
 #undef NEP_INST
 
@@ -1349,7 +1400,7 @@ __global__ __launch_bounds__(POP_DESC_BS, 2) void k_pop_descriptor(
     const int t = tile * POP_DESC_BS + threadIdx.x;
     if (t >= pc.n) return;
     const size_t n = (size_t)pc.n;
-    descriptor_atom<0>(t, true, lds, pc, xq, xp + m * n, cell_of, cells, nl_ang, nl_rad, ncnt,
+    descriptor_atom<0>(t, true, lds, pc, xq, xp + m * n, nullptr, nullptr, cell_of, cells, nl_ang, nl_rad, ncnt,
                        P + (size_t)m * P_SIZE, C64 + (size_t)m * C64N, pair_grad + (size_t)m * pc.capA * n,
                        f_own + m * n, w_atom + 9 * m * n, e_atom + m * n, status, CAND_OFF);
 }
@@ -1370,7 +1421,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     if (t >= pc.n) return;
     const size_t n = (size_t)pc.n;
     float *fm = F + 3 * m * n;
-    force_atom(t, pc, xp + m * n, cell_of, cells, nl_ang, nl_rad, ncnt, rev, pair_grad + (size_t)m * pc.capA * n,
+    force_atom<false>(t, pc, xp + m * n, cell_of, cells, nl_ang, nl_rad, ncnt, rev, pair_grad + (size_t)m * pc.capA * n,
                f_own + m * n, perm, fm, fm + n, fm + 2 * n, w_atom + 9 * m * n, status);
 }
 

@@ -41,23 +41,33 @@ __device__ inline float ftanh(float z)
 // ------------------------------------------------------------------ descriptor + network
 
 // The image shift n.h of a list entry added to a pair vector.  Entries in the
-// cell itself (all but those across a periodic face) carry the code code0
-// and are recognised by one comparison, before the code is decoded.
+// cell itself (all but those across a periodic face) carry the code code0,
+// or in bin-offset mode no crossing bits, and are recognised by one
+// comparison before the code is decoded.
 __device__ __forceinline__ void add_image(int32_t e, const PairConsts &pc, const CellGeom *__restrict__ cg,
                                           double &dx, double &dy, double &dz)
 {
     const uint32_t code = (uint32_t)e >> pc.jbits;
-    if (code != pc.code0) {
+    if ((code & pc.img_mask) == pc.img_val) return;
+    int n0, n1, n2;
+    if (pc.delta) {
+        const uint32_t cr = code >> 5;
+        const int q = (int)(code & 31u);
+        n0 = (cr & 1u) ? q % 3 - 1 : 0;
+        n1 = (cr & 2u) ? (q / 3) % 3 - 1 : 0;
+        n2 = (cr & 4u) ? q / 9 - 1 : 0;
+    } else {
         const uint32_t m = (1u << pc.ibits) - 1u;
-        const int n0 = (int)(code & m) - pc.ioff;
-        const int n1 = (int)((code >> pc.ibits) & m) - pc.ioff;
-        const int n2 = (int)(code >> (2 * pc.ibits)) - pc.ioff;
-        const double *h = cg->h;
-        dx += n0 * h[0] + n1 * h[3] + n2 * h[6];
-        dy += n0 * h[1] + n1 * h[4] + n2 * h[7];
-        dz += n0 * h[2] + n1 * h[5] + n2 * h[8];
+        n0 = (int)(code & m) - pc.ioff;
+        n1 = (int)((code >> pc.ibits) & m) - pc.ioff;
+        n2 = (int)(code >> (2 * pc.ibits)) - pc.ioff;
     }
+    const double *h = cg->h;
+    dx += n0 * h[0] + n1 * h[3] + n2 * h[6];
+    dy += n0 * h[1] + n1 * h[4] + n2 * h[7];
+    dz += n0 * h[2] + n1 * h[5] + n2 * h[8];
 }
+
 
 // Pair vector in double precision, computed so that the vector seen from the
 // other end of the pair is its exact negative: (x_j - x_i) first, then the

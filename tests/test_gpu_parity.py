@@ -91,8 +91,12 @@ def test_block_list_build_matches_gather_build(pbc):
     # one binned cell builds its lists by bin blocks (halo positions in LDS);
     # the same atoms as the first cell of a two-cell batch take the per-atom
     # build that gathers every candidate.  Identical lists give bitwise
-    # identical forces and energies: 7 x 7 x 7 bins (odd, so the last blocks
-    # are one bin wide), displaced atoms, periodic and open along z.
+    # identical energies, forces and virials: 7 x 7 x 7 bins (odd, so the
+    # last blocks are one bin wide), displaced atoms, periodic and open along
+    # z.  The periodic single cell runs in bin-offset mode (its force kernel
+    # forms the radial pair vectors from fixed-point offsets within bins,
+    # ~1e-8 A units), so there the energies stay bitwise and the forces and
+    # virial agree to that quantisation.
     import torch
     import paper_2305_08140_amd as nep
     m = model()
@@ -115,9 +119,17 @@ def test_block_list_build_matches_gather_build(pbc):
         torch.cuda.synchronize()
         res.append((out.forces().cpu().numpy(), out.energy.cpu().numpy(), out.virial.cpu().numpy()))
     n = pos.shape[0]
-    assert np.array_equal(res[0][0], res[1][0][:n])
     assert res[0][1][0] == res[1][1][0]
-    assert np.array_equal(res[0][2].reshape(-1)[:9], res[1][2].reshape(-1)[:9])
+    if pbc == (1, 1, 1):
+        F0, F1 = res[0][0].astype(np.float64), res[1][0][:n].astype(np.float64)
+        dF = np.linalg.norm(F0 - F1) / np.linalg.norm(F1)
+        W0, W1 = res[0][2].reshape(-1)[:9], res[1][2].reshape(-1)[:9]
+        dW = np.linalg.norm(W0 - W1) / np.linalg.norm(W1)
+        print(f"[bin-offset mode] forces rel diff {dF:.2e}, virial rel diff {dW:.2e}", flush=True)
+        assert dF <= 1e-7 and dW <= 1e-9
+    else:
+        assert np.array_equal(res[0][0], res[1][0][:n])
+        assert np.array_equal(res[0][2].reshape(-1)[:9], res[1][2].reshape(-1)[:9])
 
 
 def test_small_strained_cells_with_images():
