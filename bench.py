@@ -58,7 +58,7 @@ def flops_per_atom(n_rad: float, n_ang: float, kr: int = 9, nr: int = 9, ka: int
 
 def _kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("nep_kernels.hip", "nep_device.h"):
+    for f in ("nep_kernels.hip", "nep_device.h", "nep_pairs.h"):
         with open(os.path.join(ROOT, "paper_2305_08140_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
