@@ -897,6 +897,8 @@ static void launch_wide_sums_t(nep_ctx *c, hipStream_t st)
     for (int g = 0; g < WNGA; ++g)
         k_w_angular<BS><<<grid, BS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->c64, g,
                                              c->w_S, c->w_Q);
+    // bin-offset mode: the records carry fixed-point positions (WAtomRec80)
+    const int32_t *bs = c->pc.delta ? c->bin_sorted : nullptr;
     if (c->nn_mode != 0) {
         // the hidden layer on the matrix cores (FP32 or BF16 operands): a
         // persistent grid, three blocks of four wavefronts per CU
@@ -904,12 +906,13 @@ static void launch_wide_sums_t(nep_ctx *c, hipStream_t st)
         const int blocks = std::max(1, std::min((ntiles + 3) / 4, 3 * 256));
         if (c->nn_mode == 2)
             k_w_network_mfma<false><<<blocks, WN_BS, 0, st>>>(n, ntiles, c->xq, c->params, c->w_Q, c->xw, c->w_FpA,
-                                                              c->e_atom);
+                                                              c->e_atom, c->cells, bs, c->pc.qsinv, c->status);
         else
             k_w_network_mfma<true><<<blocks, WN_BS, 0, st>>>(n, ntiles, c->xq, c->params, c->w_Q, c->xw, c->w_FpA,
-                                                             c->e_atom);
+                                                             c->e_atom, c->cells, bs, c->pc.qsinv, c->status);
     } else {
-        k_w_network<BS><<<grid, BS, 0, st>>>(n, c->xq, c->params, c->w_Q, c->xw, c->w_FpA, c->e_atom);
+        k_w_network<BS><<<grid, BS, 0, st>>>(n, c->xq, c->params, c->w_Q, c->xw, c->w_FpA, c->e_atom, c->cells, bs,
+                                             c->pc.qsinv, c->status);
     }
 }
 
@@ -927,8 +930,14 @@ template <int BS>
 static void launch_wide_force_t(nep_ctx *c, const nep_efv *o, hipStream_t st)
 {
     const int n = c->pc.n, grid = xcd_grid((n + BS - 1) / BS);
-    k_w_force<BS><<<grid, BS, 0, st>>>(c->pc, c->xw, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt, c->rev,
-                                       c->pair_grad, c->f_own, c->perm, o->fx, o->fy, o->fz, c->w_atom, c->status);
+    if (c->pc.delta)
+        k_w_force<BS, true><<<grid, BS, 0, st>>>(c->pc, c->xw, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
+                                                 c->rev, c->pair_grad, c->f_own, c->perm, o->fx, o->fy, o->fz,
+                                                 c->w_atom, c->status);
+    else
+        k_w_force<BS, false><<<grid, BS, 0, st>>>(c->pc, c->xw, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
+                                                  c->rev, c->pair_grad, c->f_own, c->perm, o->fx, o->fy, o->fz,
+                                                  c->w_atom, c->status);
 }
 
 static const int N_WIDE_SHAPES = 3;

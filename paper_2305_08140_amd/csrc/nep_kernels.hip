@@ -757,8 +757,9 @@ __device__ __forceinline__ bool radial_pair_force(const PairConsts &pc, double d
 // Each neighbour costs one 64-byte record gather (position and adjoint) and,
 // for angular entries, one 16-byte pair-gradient gather.
 // D48: bin-offset mode, 48-byte records (AtomRec48): the pair vector is the
-// sum of the neighbour bin's edge vectors and the difference of the two
-// fixed-point offsets, exactly antisymmetric as the FP64 positions' one.
+// sum of the neighbour bin's edge vectors (from the block's LDS table btab)
+// and the difference of the two fixed-point offsets, exactly antisymmetric
+// as the FP64 positions' one.
 template <bool D48>
 __device__ __forceinline__ void force_atom(
     int t, const PairConsts &pc, const AtomRec *__restrict__ xp_, const int32_t *__restrict__ cell_of,
@@ -766,7 +767,8 @@ __device__ __forceinline__ void force_atom(
     const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt,
     const uint8_t *__restrict__ rev, const float4 *__restrict__ pair_grad, const float4 *__restrict__ f_own,
     const int32_t *__restrict__ perm, float *__restrict__ fx, float *__restrict__ fy,
-    float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status)
+    float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status,
+    const double *__restrict__ btab)
 {
     using Rec = typename std::conditional<D48, AtomRec48, AtomRec>::type;
     const Rec *__restrict__ xp = reinterpret_cast<const Rec *>(xp_);
@@ -790,12 +792,10 @@ __device__ __forceinline__ void force_atom(
     auto radial = [&](int32_t e, const Rec &rj, float &r2out) -> bool {
         double ddx, ddy, ddz;
         if constexpr (D48) {
-            const int q = (int)(((uint32_t)e >> pc.jbits) & 31u);
-            const double o0 = q % 3 - 1, o1 = (q / 3) % 3 - 1, o2 = q / 9 - 1;
-            const double *bv = cg->bv;
-            ddx = fma(pc.qs, (double)rj.o[0] - (double)own.o[0], o0 * bv[0] + o1 * bv[3] + o2 * bv[6]);
-            ddy = fma(pc.qs, (double)rj.o[1] - (double)own.o[1], o0 * bv[1] + o1 * bv[4] + o2 * bv[7]);
-            ddz = fma(pc.qs, (double)rj.o[2] - (double)own.o[2], o0 * bv[2] + o1 * bv[5] + o2 * bv[8]);
+            const double *b = btab + 4 * (int)(((uint32_t)e >> pc.jbits) & 31u);
+            ddx = fma(pc.qs, (double)rj.o[0] - (double)own.o[0], b[0]);
+            ddy = fma(pc.qs, (double)rj.o[1] - (double)own.o[1], b[1]);
+            ddz = fma(pc.qs, (double)rj.o[2] - (double)own.o[2], b[2]);
         } else {
             ddx = rj.x - own.x;
             ddy = rj.y - own.y;
@@ -888,20 +888,22 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const int32_t *__restrict__ perm, float *__restrict__ fx, float *__restrict__ fy,
     float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status, int ntiles)
 {
+    __shared__ __align__(16) double btab[D48 ? BIN_TAB : 2];
+    if constexpr (D48) stage_bin_vectors(cells, btab);   // one cell in this mode
     if (lists_blocked(status)) return;
     if (PERSISTENT) {
         for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
             const int t = tile * BS + threadIdx.x;
             if (t < pc.n)
                 force_atom<D48>(t, pc, xp, cell_of, cells, nl_ang, nl_rad, ncnt, rev, pair_grad, f_own, perm, fx,
-                                fy, fz, w_atom, status);
+                                fy, fz, w_atom, status, btab);
         }
     } else {
         const int tile = xcd_block(ntiles);
         const int t = tile * BS + threadIdx.x;
         if (tile < ntiles && t < pc.n)
             force_atom<D48>(t, pc, xp, cell_of, cells, nl_ang, nl_rad, ncnt, rev, pair_grad, f_own, perm, fx, fy,
-                            fz, w_atom, status);
+                            fz, w_atom, status, btab);
     }
 }
 
@@ -1422,7 +1424,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const size_t n = (size_t)pc.n;
     float *fm = F + 3 * m * n;
     force_atom<false>(t, pc, xp + m * n, cell_of, cells, nl_ang, nl_rad, ncnt, rev, pair_grad + (size_t)m * pc.capA * n,
-               f_own + m * n, perm, fm, fm + n, fm + 2 * n, w_atom + 9 * m * n, status);
+               f_own + m * n, perm, fm, fm + n, fm + 2 * n, w_atom + 9 * m * n, status, nullptr);
 }
 
 // grid (n_chunks, n_pop): chunk partials of member blockIdx.y

@@ -69,6 +69,26 @@ __device__ __forceinline__ void add_image(int32_t e, const PairConsts &pc, const
 }
 
 
+// Bin-offset mode: the 27 vectors o0 b0 + o1 b1 + o2 b2 of the neighbour-bin
+// offsets o in {-1, 0, 1}^3 (b_a the bin edge vectors, index
+// q = (o0+1) + 3 (o1+1) + 9 (o2+1)), staged in LDS by every thread of the
+// block, 4 doubles per entry (two aligned LDS reads).  Entry 26 - q is the
+// exact negative of entry q (products and sums negate exactly), so pair
+// vectors formed from the table stay antisymmetric.  Ends with a barrier:
+// call it before any thread of the block can leave.
+constexpr int BIN_TAB = 27 * 4;
+__device__ __forceinline__ void stage_bin_vectors(const CellGeom *__restrict__ cg, double *__restrict__ tab)
+{
+    for (int q = (int)threadIdx.x; q < 27; q += (int)blockDim.x) {
+        const double o0 = q % 3 - 1, o1 = (q / 3) % 3 - 1, o2 = q / 9 - 1;
+        const double *bv = cg->bv;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) tab[4 * q + d] = o0 * bv[d] + o1 * bv[3 + d] + o2 * bv[6 + d];
+        tab[4 * q + 3] = 0.0;
+    }
+    __syncthreads();
+}
+
 // Pair vector in double precision, computed so that the vector seen from the
 // other end of the pair is its exact negative: (x_j - x_i) first, then the
 // image shift n.h (which is exactly negated for -n).

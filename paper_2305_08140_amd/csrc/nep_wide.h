@@ -57,6 +57,16 @@ struct __attribute__((aligned(16))) WAtomRec {
 };
 static_assert(sizeof(WAtomRec) == 96, "WAtomRec must be 96 bytes");
 
+// bin-offset mode (one periodic cell binned along every axis): the position
+// as fixed-point offsets from the corner of the atom's bin, 76 bytes padded
+// to 80, five 16-byte pieces per gather
+struct __attribute__((aligned(16))) WAtomRec80 {
+    int32_t o[3];
+    float a[WKR];
+    float pad;
+};
+static_assert(sizeof(WAtomRec80) == 80, "WAtomRec80 must be 80 bytes");
+
 __global__ void k_w_params64(const float *P, double *C64);
 __global__ void k_w_pop_params(const float *theta, const float *base, float *P, double *C64);
 template <int BS>
@@ -69,15 +79,17 @@ __global__ void k_w_angular(PairConsts pc, const double4 *xq, const int32_t *cel
                             float *Q);
 template <int BS>
 __global__ void k_w_network(int n, const double4 *xq, const float *P, const float *Q, WAtomRec *xw, float *FpA,
-                            double *e_atom);
+                            double *e_atom, const CellGeom *cells, const int32_t *bin_sorted, double qsinv,
+                            int32_t *status);
 template <bool BF16>
 __global__ void k_w_network_mfma(int n_atoms, int ntiles, const double4 *xq, const float *P, const float *Q,
-                                 WAtomRec *xw, float *FpA, double *e_atom);
+                                 WAtomRec *xw, float *FpA, double *e_atom, const CellGeom *cells,
+                                 const int32_t *bin_sorted, double qsinv, int32_t *status);
 template <int BS>
 __global__ void k_w_grad(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
                          const int32_t *nl_ang, const uint32_t *ncnt, const float *P, const double *C64,
                          const float *S, const float *FpA, float4 *pair_grad, float4 *f_own, float *w_atom);
-template <int BS>
+template <int BS, bool D80>
 __global__ void k_w_force(PairConsts pc, const WAtomRec *xw, const int32_t *cell_of, const CellGeom *cells,
                           const int32_t *nl_ang, const int32_t *nl_rad, const uint32_t *ncnt, const uint8_t *rev,
                           const float4 *pair_grad, const float4 *f_own, const int32_t *perm, float *fx, float *fy,

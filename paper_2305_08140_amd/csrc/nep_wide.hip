@@ -4,6 +4,8 @@
 // sums; FP32 l = 4 sums, network, gradient walk and force kernel, whose
 // distance, Chebyshev argument and series stay FP64.  One lane per atom,
 // blocks in XCD-aware order.
+#include <type_traits>
+
 #include "nep_wide.h"
 #include "nep_pairs.h"
 
@@ -47,6 +49,50 @@ __device__ inline int tile_atom(int n)
     const int ntiles = (n + BS - 1) / BS;
     const int tile = xcd_block(ntiles);
     return tile < ntiles ? tile * BS + (int)threadIdx.x : n;
+}
+
+// Bin-offset mode: the record's position as fixed-point offsets (units
+// 1/qsinv) from the corner of the atom's bin at the last list build; an
+// offset beyond the 32-bit range means the atom moved far past the list
+// skin (error -9, as for any list that no longer holds).
+__device__ inline void w_bin_offsets(const CellGeom *cg, int lbin, const double4 &p, double qsinv, int32_t o[3],
+                                     int32_t *status)
+{
+    const int b0 = lbin % cg->nb[0], b1 = (lbin / cg->nb[0]) % cg->nb[1], b2 = lbin / (cg->nb[0] * cg->nb[1]);
+    const double *bv = cg->bv;
+    const double d[3] = {p.x - (b0 * bv[0] + b1 * bv[3] + b2 * bv[6]), p.y - (b0 * bv[1] + b1 * bv[4] + b2 * bv[7]),
+                         p.z - (b0 * bv[2] + b1 * bv[5] + b2 * bv[8])};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double v = rint(d[k] * qsinv);
+        if (!(fabs(v) < 2147483000.0)) latch_error(status, -9);
+        o[k] = (int32_t)fmin(fmax(v, -2147483000.0), 2147483000.0);
+    }
+}
+
+// One atom's force record: FP64 position, or with bin_sorted set (bin-offset
+// mode, a single cell) the 80-byte fixed-point form.
+__device__ inline void w_store_record(WAtomRec *__restrict__ xw, int t, const double4 &p, const float a[WKR],
+                                      const CellGeom *__restrict__ cells, const int32_t *__restrict__ bin_sorted,
+                                      double qsinv, int32_t *__restrict__ status)
+{
+    if (bin_sorted) {
+        WAtomRec80 r;
+        w_bin_offsets(cells, bin_sorted[t], p, qsinv, r.o, status);
+#pragma unroll
+        for (int k = 0; k < WKR; ++k) r.a[k] = a[k];
+        r.pad = 0.0f;
+        reinterpret_cast<WAtomRec80 *>(xw)[t] = r;
+    } else {
+        WAtomRec r;
+        r.x = p.x;
+        r.y = p.y;
+        r.z = p.z;
+#pragma unroll
+        for (int k = 0; k < WKR; ++k) r.a[k] = a[k];
+        r.pad[0] = r.pad[1] = 0.0f;
+        xw[t] = r;
+    }
 }
 
 __global__ void k_w_params64(const float *__restrict__ P, double *__restrict__ C64)
@@ -283,7 +329,9 @@ template <int BS>
 __global__ __launch_bounds__(BS) void k_w_network(int n_atoms, const double4 *__restrict__ xq,
                                                    const float *__restrict__ P, const float *__restrict__ Q,
                                                    WAtomRec *__restrict__ xw, float *__restrict__ FpA,
-                                                   double *__restrict__ e_atom)
+                                                   double *__restrict__ e_atom, const CellGeom *__restrict__ cells,
+                                                   const int32_t *__restrict__ bin_sorted, double qsinv,
+                                                   int32_t *__restrict__ status)
 {
     const int t = tile_atom<BS>(n_atoms);
     if (t >= n_atoms) return;
@@ -311,21 +359,15 @@ __global__ __launch_bounds__(BS) void k_w_network(int n_atoms, const double4 *__
 #pragma unroll
     for (int nu = 0; nu < WDIM; ++nu) Fp[nu] *= P[W_QS + nu];
     e_atom[t] += (double)U;
-    WAtomRec rec;
-    const double4 p = xq[t];
-    rec.x = p.x;
-    rec.y = p.y;
-    rec.z = p.z;
+    float ak[WKR];
 #pragma unroll
     for (int k = 0; k < WKR; ++k) {
         float s = 0.0f;
 #pragma unroll
         for (int m = 0; m < WR; ++m) s = fmaf(Fp[m], P[W_CR + m * WKR + k], s);
-        rec.a[k] = s;
+        ak[k] = s;
     }
-#pragma unroll
-    for (int k = 0; k < 2; ++k) rec.pad[k] = 0.0f;
-    xw[t] = rec;
+    w_store_record(xw, t, xq[t], ak, cells, bin_sorted, qsinv, status);
 #pragma unroll
     for (int nu = WR; nu < WDIM; ++nu) FpA[(nu - WR) * n + t] = Fp[nu];
 }
@@ -360,7 +402,9 @@ typedef __attribute__((ext_vector_type(8))) __bf16 w_bf16x8;
 template <bool BF16>
 __global__ __launch_bounds__(WN_BS) __attribute__((amdgpu_waves_per_eu(3))) void k_w_network_mfma(
     int n_atoms, int ntiles, const double4 *__restrict__ xq, const float *__restrict__ P, const float *__restrict__ Q,
-    WAtomRec *__restrict__ xw, float *__restrict__ FpA, double *__restrict__ e_atom)
+    WAtomRec *__restrict__ xw, float *__restrict__ FpA, double *__restrict__ e_atom,
+    const CellGeom *__restrict__ cells, const int32_t *__restrict__ bin_sorted, double qsinv,
+    int32_t *__restrict__ status)
 {
     __shared__ float w0s[WN_MT * 32 * WN_LD];      // w0[mu][nu] at mu * WN_LD + nu, zero past 100 x 60
     __shared__ float b0s[WN_MT * 32], w1s[WN_MT * 32];
@@ -516,24 +560,18 @@ __global__ __launch_bounds__(WN_BS) __attribute__((amdgpu_waves_per_eu(3))) void
             for (int k = 0; k < WKR; ++k) ak[k] += __shfl_xor(ak[k], 32, 64);
             if (valid && hi == 0) {
                 e_atom[atom] += (double)U;
-                const double4 p = xq[atom];
-                WAtomRec rec;
-                rec.x = p.x;
-                rec.y = p.y;
-                rec.z = p.z;
-#pragma unroll
-                for (int k = 0; k < WKR; ++k) rec.a[k] = ak[k];
-                rec.pad[0] = rec.pad[1] = 0.0f;
-                xw[atom] = rec;
+                w_store_record(xw, atom, xq[atom], ak, cells, bin_sorted, qsinv, status);
             }
         }
     }
 }
 
 template __global__ void k_w_network_mfma<false>(int, int, const double4 *, const float *, const float *, WAtomRec *,
-                                                  float *, double *);
+                                                  float *, double *, const CellGeom *, const int32_t *, double,
+                                                  int32_t *);
 template __global__ void k_w_network_mfma<true>(int, int, const double4 *, const float *, const float *, WAtomRec *,
-                                                 float *, double *);
+                                                  float *, double *, const CellGeom *, const int32_t *, double,
+                                                  int32_t *);
 
 // Contributions of the channels c0 .. c0+NC-1 to dU_i/dr_ij of every angular
 // slot, added into pair_grad (the first group writes), and to the atom's own
@@ -698,26 +736,33 @@ __global__ __launch_bounds__(BS, 2) void k_w_grad(
     for (int k = 0; k < 9; ++k) w[k] = -W[k];
 }
 
-// Forces: the default model's force kernel with 16 radial adjoints.
-template <int BS>
+// Forces: the default model's force kernel with 16 radial adjoints.  D80:
+// bin-offset mode, 80-byte records (WAtomRec80): the pair vector is the sum
+// of the neighbour bin's edge vectors (the list entry's bin offset, from the
+// block's LDS table) and the difference of the two fixed-point offsets,
+// exactly antisymmetric as the FP64 positions' difference.  Both walks load
+// the neighbour's record one entry ahead.
+template <int BS, bool D80>
 __global__ __launch_bounds__(BS) void k_w_force(
-    PairConsts pc, const WAtomRec *__restrict__ xw, const int32_t *__restrict__ cell_of,
+    PairConsts pc, const WAtomRec *__restrict__ xw_, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const int32_t *__restrict__ nl_rad,
     const uint32_t *__restrict__ ncnt, const uint8_t *__restrict__ rev, const float4 *__restrict__ pair_grad,
     const float4 *__restrict__ f_own, const int32_t *__restrict__ perm, float *__restrict__ fx,
     float *__restrict__ fy, float *__restrict__ fz, float *__restrict__ w_atom, int32_t *__restrict__ status)
 {
+    using Rec = typename std::conditional<D80, WAtomRec80, WAtomRec>::type;
+    const Rec *__restrict__ xw = reinterpret_cast<const Rec *>(xw_);
+    __shared__ __align__(16) double btab[D80 ? BIN_TAB : 2];
+    if constexpr (D80) stage_bin_vectors(cells, btab);   // one cell in this mode
     const int t = tile_atom<BS>(pc.n);
     if (t >= pc.n || lists_blocked(status)) return;
-    const double xi = xw[t].x, yi = xw[t].y, zi = xw[t].z;
-    const CellGeom *cg = cells + cell_of[t];
+    const Rec own = xw[t];
+    // bin-offset mode has one cell: its geometry is uniform (scalar loads)
+    const CellGeom *cg = D80 ? cells : cells + cell_of[t];
     const int base = cg->atom_start;
     const uint32_t cnt = ncnt[t];
     const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
     const uint32_t jmask = (1u << pc.jbits) - 1u;
-    float ai[WKR];
-#pragma unroll
-    for (int k = 0; k < WKR; ++k) ai[k] = xw[t].a[k];
     const float4 fo = f_own[t];
     float Fx = fo.x, Fy = fo.y, Fz = fo.z;
     float W[9];
@@ -726,9 +771,19 @@ __global__ __launch_bounds__(BS) void k_w_force(
     bool bad = false;
     const double inv_rR = 1.0 / (double)pc.rc_rad;
 
-    auto radial = [&](int32_t e, const WAtomRec &rj, float &r2out) -> bool {
-        double ddx = rj.x - xi, ddy = rj.y - yi, ddz = rj.z - zi;
-        add_image(e, pc, cg, ddx, ddy, ddz);
+    auto radial = [&](int32_t e, const Rec &rj, float &r2out) -> bool {
+        double ddx, ddy, ddz;
+        if constexpr (D80) {
+            const double *b = btab + 4 * (int)(((uint32_t)e >> pc.jbits) & 31u);
+            ddx = fma(pc.qs, (double)rj.o[0] - (double)own.o[0], b[0]);
+            ddy = fma(pc.qs, (double)rj.o[1] - (double)own.o[1], b[1]);
+            ddz = fma(pc.qs, (double)rj.o[2] - (double)own.o[2], b[2]);
+        } else {
+            ddx = rj.x - own.x;
+            ddy = rj.y - own.y;
+            ddz = rj.z - own.z;
+            add_image(e, pc, cg, ddx, ddy, ddz);
+        }
         const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
         const float r2 = dx * dx + dy * dy + dz * dz;
         r2out = r2;
@@ -742,13 +797,13 @@ __global__ __launch_bounds__(BS) void k_w_force(
         cutoff((float)ttd, pc.inv_rc_rad, fc, dfc);
         const double xd = 2.0 * ttd * ttd - 1.0;
         double Tm2 = 1.0, Tm1 = xd, dTm2 = 0.0, dTm1 = 1.0;
-        const double a0 = (double)ai[0] + (double)rj.a[0], a1 = (double)ai[1] + (double)rj.a[1];
+        const double a0 = (double)own.a[0] + (double)rj.a[0], a1 = (double)own.a[1] + (double)rj.a[1];
         double s0d = fma(a1, xd, a0), s1d = a1, sa = a0 + a1;
 #pragma unroll
         for (int k = 2; k < WKR; ++k) {
             const double Tk = fma(2.0 * xd, Tm1, -Tm2);
             const double dTk = fma(2.0 * xd, dTm1, fma(2.0, Tm1, -dTm2));
-            const double ah = (double)ai[k] + (double)rj.a[k];
+            const double ah = (double)own.a[k] + (double)rj.a[k];
             s0d = fma(ah, Tk, s0d);
             s1d = fma(ah, dTk, s1d);
             sa += ah;
@@ -773,23 +828,54 @@ __global__ __launch_bounds__(BS) void k_w_force(
     };
 
     const int nA = naf + nab;
-    for (ListWalk wa(t, pc.n, naf, nab, pc.capA); wa.s < nA; wa.next()) {
-        const int32_t e = nl_ang[wa.off];
-        const WAtomRec rj = xw[(int)((uint32_t)e & jmask) + base];
-        float r2;
-        if (!radial(e, rj, r2) || r2 >= pc.rc_ang2_read) continue;
-        const int sj = rev[wa.off];
-        if (sj == 255) { bad = true; continue; }
-        const float4 gj = pair_grad[(size_t)sj * pc.n + (int)((uint32_t)e & jmask) + base];
-        Fx -= gj.x; Fy -= gj.y; Fz -= gj.z;
+    {
+        ListWalk wa(t, pc.n, naf, nab, pc.capA);
+        int32_t e_nx = 0;
+        int sj_nx = 255;
+        Rec r_nx;
+        if (nA > 0) {
+            e_nx = nl_ang[wa.off];
+            sj_nx = rev[wa.off];
+            r_nx = xw[(int)((uint32_t)e_nx & jmask) + base];
+        }
+        for (int s = 0; s < nA; ++s) {
+            const int32_t e = e_nx;
+            const int sj = sj_nx;
+            const Rec rj = r_nx;
+            wa.next();
+            if (s + 1 < nA) {
+                e_nx = nl_ang[wa.off];
+                sj_nx = rev[wa.off];
+                r_nx = xw[(int)((uint32_t)e_nx & jmask) + base];
+            }
+            float r2;
+            if (!radial(e, rj, r2) || r2 >= pc.rc_ang2_read) continue;
+            if (sj == 255) { bad = true; continue; }
+            const float4 gj = pair_grad[(size_t)sj * pc.n + (int)((uint32_t)e & jmask) + base];
+            Fx -= gj.x; Fy -= gj.y; Fz -= gj.z;
+        }
     }
     // radial list: only the entries k_w_radial found inside rc_rad
-    MaskWalk mr(pc.rmask, pc.n, t, nrf + nrb);
-    for (int sr = mr.next(); sr >= 0; sr = mr.next()) {
-        const int32_t e = nl_rad[(size_t)list_slot(sr, nrf, nrb, pc.capR) * pc.n + t];
-        const WAtomRec rj = xw[(int)((uint32_t)e & jmask) + base];
-        float r2;
-        radial(e, rj, r2);
+    {
+        MaskWalk mr(pc.rmask, pc.n, t, nrf + nrb);
+        int sr = mr.next();
+        int32_t e_nx = 0;
+        Rec r_nx;
+        if (sr >= 0) {
+            e_nx = nl_rad[(size_t)list_slot(sr, nrf, nrb, pc.capR) * pc.n + t];
+            r_nx = xw[(int)((uint32_t)e_nx & jmask) + base];
+        }
+        while (sr >= 0) {
+            const int32_t e = e_nx;
+            const Rec rj = r_nx;
+            sr = mr.next();
+            if (sr >= 0) {
+                e_nx = nl_rad[(size_t)list_slot(sr, nrf, nrb, pc.capR) * pc.n + t];
+                r_nx = xw[(int)((uint32_t)e_nx & jmask) + base];
+            }
+            float r2;
+            radial(e, rj, r2);
+        }
     }
     if (bad) latch_error(status, -9);
     const int i = perm[t];
@@ -1021,14 +1107,18 @@ __global__ __launch_bounds__(64) void k_w_param_grad(
                                              const int32_t *, const uint32_t *, const double *, int, float *,         \
                                              float *);                                                                \
     template __global__ void k_w_network<BS>(int, const double4 *, const float *, const float *, WAtomRec *, float *, \
-                                             double *);                                                               \
+                                             double *, const CellGeom *, const int32_t *, double, int32_t *);         \
     template __global__ void k_w_grad<BS>(PairConsts, const double4 *, const int32_t *, const CellGeom *,             \
                                           const int32_t *, const uint32_t *, const float *, const double *,           \
                                           const float *, const float *, float4 *, float4 *, float *);                 \
-    template __global__ void k_w_force<BS>(PairConsts, const WAtomRec *, const int32_t *, const CellGeom *,           \
-                                           const int32_t *, const int32_t *, const uint32_t *, const uint8_t *,       \
-                                           const float4 *, const float4 *, const int32_t *, float *, float *,         \
-                                           float *, float *, int32_t *);
+    template __global__ void k_w_force<BS, false>(PairConsts, const WAtomRec *, const int32_t *, const CellGeom *,    \
+                                                  const int32_t *, const int32_t *, const uint32_t *,                 \
+                                                  const uint8_t *, const float4 *, const float4 *, const int32_t *,   \
+                                                  float *, float *, float *, float *, int32_t *);                     \
+    template __global__ void k_w_force<BS, true>(PairConsts, const WAtomRec *, const int32_t *, const CellGeom *,     \
+                                                 const int32_t *, const int32_t *, const uint32_t *,                  \
+                                                 const uint8_t *, const float4 *, const float4 *, const int32_t *,    \
+                                                 float *, float *, float *, float *, int32_t *);
 NEP_W_INST(64)
 NEP_W_INST(128)
 NEP_W_INST(256)
