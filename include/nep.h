@@ -48,7 +48,8 @@ extern "C" {
 #define NEP_E_DT_UNDERFLOW    -6  /* adaptive time step fell below nep_md.dt_min */
 #define NEP_E_STATE           -7  /* call order: nep_compute_efv before nep_build_neighbors on this system */
 #define NEP_E_UNSUPPORTED     -8  /* hyperparameters for which no kernel is compiled */
-#define NEP_E_INTERNAL        -9  /* internal consistency check failed (neighbour lists not symmetric) */
+#define NEP_E_INTERNAL        -9  /* internal consistency check failed (neighbour lists not symmetric),
+                                     or an atom far outside its bin of the last build (bin-offset mode) */
 #define NEP_E_CAPACITY       -10  /* more defect sites than the caller's arrays hold */
 
 typedef struct nep_ctx nep_ctx;
@@ -189,6 +190,15 @@ int nep_set_weights(nep_ctx *ctx, const nep_weights *w, int32_t weights_on_devic
  * are returned by nep_required_neighbors) and non-finite positions latch
  * NEP_E_NONFINITE; after such a build the lists stay unusable, and evaluations
  * on them latch NEP_E_STATE until a build succeeds.
+ * Bin-offset mode: a system of one cell, periodic along all three axes, at
+ * least three bins of rc_rad + skin wide along each, and at most 2^23 atoms,
+ * stores in each list entry the offset of the neighbour's bin from the
+ * atom's own instead of the periodic image, and the force evaluation reads
+ * positions as fixed-point offsets (units 2^-k A, k as large as the bin size
+ * allows) from the corner of the atom's bin of this build.  The results are
+ * those of the general layout up to that rounding (~4e-9 A); an atom that
+ * has left its bin by more than skin + 1 A before the next build latches
+ * NEP_E_INTERNAL at the next evaluation.
  * Returns NEP_OK, NEP_E_ARG or NEP_E_HIP. */
 int nep_build_neighbors(nep_ctx *ctx, const nep_system *sys, void *stream);
 

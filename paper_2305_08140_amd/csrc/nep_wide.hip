@@ -131,8 +131,10 @@ __global__ __launch_bounds__(256) void k_w_pop_params(const float *__restrict__ 
 // q_n = sum_k c_nk F_k -> Q[n][t]; ZBL half energies -> e_atom[t].  The
 // radial list is walked in full when *cflag is set, else over the candidates
 // of the last full walk (see the default model's descriptor_sums).
+// (three waves per SIMD: 168 registers, a few spilled, measured faster than
+// two waves without spills)
 template <int BS>
-__global__ __launch_bounds__(BS) void k_w_radial(
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_w_radial(
     PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const int32_t *__restrict__ nl_rad,
     const uint32_t *__restrict__ ncnt, const float *__restrict__ P, float *__restrict__ Q,
