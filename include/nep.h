@@ -196,9 +196,10 @@ int nep_set_weights(nep_ctx *ctx, const nep_weights *w, int32_t weights_on_devic
  * atom's own instead of the periodic image, and the force evaluation reads
  * positions as fixed-point offsets (units 2^-k A, k as large as the bin size
  * allows) from the corner of the atom's bin of this build.  The results are
- * those of the general layout up to that rounding (~4e-9 A); an atom that
- * has left its bin by more than skin + 1 A before the next build latches
- * NEP_E_INTERNAL at the next evaluation.
+ * those of the general layout up to that rounding (~4e-9 A).  The range of
+ * the offsets covers the bin plus at least skin + 1 A on every side; an atom
+ * beyond it (possible only on lists used long after they went stale)
+ * latches NEP_E_INTERNAL at the next evaluation.
  * Returns NEP_OK, NEP_E_ARG or NEP_E_HIP. */
 int nep_build_neighbors(nep_ctx *ctx, const nep_system *sys, void *stream);
 

@@ -1,0 +1,97 @@
+"""Bin-offset mode of the neighbour lists and force records, through the C ABI.
+
+A single periodic cell binned along every axis (at most 2^23 atoms) takes
+this mode: list entries carry the offset of the neighbour's bin from the
+atom's own, and the force kernels read positions as fixed-point offsets from
+the corner of the atom's bin (48-byte records for the default model, 80-byte
+for the paper-size one).  The same cell as both members of a two-cell batch
+takes the image mode with FP64 record positions.  The descriptor side does
+the same arithmetic in both (the image shift is n.h either way), so site
+energies agree to the FP32 rounding of the network at most; forces and
+virials differ only by the fixed-point rounding (at most half a unit, ~4e-9
+A, per coordinate) and the FP32 rounding of the force sums.  An atom carried
+beyond the fixed-point range (the bin plus at least skin + 1 A on every
+side) before the next build makes the evaluation report NEP_E_INTERNAL
+instead of returning numbers."""
+import numpy as np
+import pytest
+
+import nep_synth
+from gpu_common import gpu_available, model
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _cell(shear, seed=11, n=12, sigma=0.1):
+    rng = np.random.default_rng(seed)
+    pos, h = nep_synth.bcc_lattice(n, n, n)
+    frac = pos / np.diag(h)
+    h = h.copy()
+    h[1, 0] = shear * h[1, 1]            # second lattice vector tilted along x
+    h[2, 1] = 0.5 * shear * h[2, 2]
+    pos = frac @ h + rng.normal(0.0, sigma, size=pos.shape)
+    return pos, h
+
+
+def _run(m, pos_list, h):
+    import torch
+    import paper_2305_08140_amd as nep
+    pos = np.concatenate(pos_list)
+    starts = np.concatenate([[0], np.cumsum([p.shape[0] for p in pos_list])]).astype(np.int64)
+    s = nep_synth.System(pos=pos, vel=np.zeros_like(pos), cell_start=starts,
+                         h=np.stack([h] * len(pos_list)))
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(m, s.n_atoms, s.n_cells)
+    out = nep.EFV(s.n_atoms, s.n_cells)
+    ctx.nep_build_neighbors(sysd)
+    ctx.nep_compute_efv(sysd, out)
+    torch.cuda.synchronize()
+    return (out.energy.cpu().numpy(), out.forces().cpu().numpy().astype(np.float64),
+            out.virial.cpu().numpy().reshape(-1, 3, 3), out.energy_atom.cpu().numpy())
+
+
+@pytest.mark.parametrize("size,shear", [("small", 0.0), ("small", 0.15), ("paper", 0.0)])
+def test_bin_offset_mode_matches_image_mode(size, shear):
+    m = nep_synth.random_model(size=size) if size == "paper" else model()
+    pos, h = _cell(shear)
+    n = pos.shape[0]
+    print(f"[bin-offset] {size} model, shear {shear}, {n} atoms", flush=True)
+    e1, f1, w1, ea1 = _run(m, [pos], h)       # one cell: bin-offset mode
+    e2, f2, w2, ea2 = _run(m, [pos, pos], h)  # two-cell batch: image mode
+    for c in range(2):
+        assert abs(e2[c] - e1[0]) <= 1e-7 * n, (c, e1[0], e2[c])
+        fb = f2[c * n:(c + 1) * n]
+        rel = np.linalg.norm(fb - f1) / np.linalg.norm(f1)
+        worst = np.max(np.linalg.norm(fb - f1, axis=1)) / np.sqrt(np.mean(np.sum(f1 * f1, axis=1)))
+        print(f"[bin-offset] cell {c}: force rel diff {rel:.2e}, worst atom {worst:.2e} of the RMS force",
+              flush=True)
+        assert rel <= 1e-6, rel
+        assert worst <= 1e-5, worst
+        assert np.max(np.abs(w2[c] - w1[0])) <= 1e-6 * np.max(np.abs(w1[0])), (w1[0], w2[c])
+        assert np.max(np.abs(ea2[c * n:(c + 1) * n] - ea1)) <= 1e-6
+
+
+def test_atom_far_beyond_its_bin_is_reported():
+    import torch
+    import paper_2305_08140_amd as nep
+    m = model()
+    pos, h = _cell(0.0, sigma=0.02)
+    s = nep_synth._single(pos, h)
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(m, s.n_atoms, 1, skin=1.0)
+    out = nep.EFV(s.n_atoms, 1)
+    ctx.nep_build_neighbors(sysd)
+    ctx.nep_compute_efv(sysd, out)
+    # one atom carried 45 A along x without a rebuild: beyond the
+    # fixed-point range, which covers the bin plus skin + 1 A on every side
+    # rounded up to a power of two of the unit (less than 2 x 9.6 A here:
+    # 7.6 A bins, 1 A skin)
+    sysd.x[5] += 45.0
+    with pytest.raises(nep.NepError) as e:
+        ctx.nep_compute_efv(sysd, out)
+    assert e.value.code == nep.NEP_E_INTERNAL
+    # a rebuild at the new positions takes it back
+    ctx.nep_build_neighbors(sysd)
+    ctx.nep_compute_efv(sysd, out)
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(out.forces().cpu().numpy()))
