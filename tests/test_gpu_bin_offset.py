@@ -95,3 +95,46 @@ def test_atom_far_beyond_its_bin_is_reported():
     ctx.nep_compute_efv(sysd, out)
     torch.cuda.synchronize()
     assert np.all(np.isfinite(out.forces().cpu().numpy()))
+
+
+@pytest.mark.parametrize("size", ["small", "paper"])
+def test_population_on_one_periodic_cell(size):
+    # population members on one periodic cell (bin-offset lists): the default
+    # model's members run on the general 64-byte records, so they equal the
+    # single-model path up to the fixed-point rounding (energies, which do
+    # not depend on the records, bit for bit); the paper-size model's run
+    # through the same staged phases as a single evaluation, bit for bit
+    import torch
+    import paper_2305_08140_amd as nep
+    m = nep_synth.random_model(size=size) if size == "paper" else model()
+    pos, h = _cell(0.0, seed=5)
+    s = nep_synth._single(pos, h)
+    rng = np.random.default_rng(3)
+    th0 = m.param_vector()
+    th = th0[None, :] + 0.05 * rng.standard_normal((3, th0.size)) * np.maximum(np.abs(th0), 0.1)[None, :]
+    th[0] = th0
+    th = th.astype(np.float32)
+    print(f"[bin-offset] population of 3, {size} model, {s.n_atoms} atoms", flush=True)
+    sysd = nep.DeviceSystem.from_synth(s)
+    ctx = nep.Context(m, s.n_atoms, 1)
+    ctx.nep_build_neighbors(sysd)
+    ctx.nep_population_reserve(3)
+    res = ctx.nep_population_efv(sysd, torch.tensor(th, device="cuda"))
+    single = nep.Context(m, s.n_atoms, 1)
+    out = nep.EFV(s.n_atoms, 1)
+    single.nep_build_neighbors(sysd)
+    for k in range(3):
+        single.nep_set_weights(m.with_param_vector(th[k].astype(np.float64)))
+        single.nep_compute_efv(sysd, out)
+        torch.cuda.synchronize()
+        assert torch.equal(res["energy"][k], out.energy), k
+        f_pop = res["forces"][k].cpu().numpy().astype(np.float64)
+        f_one = np.stack([out.fx.cpu().numpy(), out.fy.cpu().numpy(), out.fz.cpu().numpy()]).astype(np.float64)
+        w_pop, w_one = res["virial"][k].cpu().numpy(), out.virial.reshape(-1, 9).cpu().numpy()
+        if size == "paper":
+            assert np.array_equal(f_pop, f_one) and np.array_equal(w_pop, w_one), k
+        else:
+            rel = np.linalg.norm(f_pop - f_one) / np.linalg.norm(f_one)
+            print(f"[bin-offset] member {k}: force rel diff {rel:.2e}", flush=True)
+            assert rel <= 1e-6, (k, rel)
+            assert np.max(np.abs(w_pop - w_one)) <= 1e-6 * np.max(np.abs(w_one)), k
