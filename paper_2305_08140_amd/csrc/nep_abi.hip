@@ -140,6 +140,7 @@ struct nep_ctx {
     bool wide = false;
     float *w_S = nullptr, *w_Q = nullptr, *w_FpA = nullptr;
     WAtomRec *xw = nullptr;
+    int4 *xf = nullptr;          // bin-offset mode: fixed-point positions for the radial phase
     double *xref = nullptr;      // [3][N] caller-order positions at the last build
     int32_t *perm = nullptr, *bin_of = nullptr, *wrap = nullptr, *cell_of = nullptr, *tmp = nullptr,
             *bin_sorted = nullptr;
@@ -319,7 +320,7 @@ void nep_destroy(nep_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     free_population(c);
-    void *bufs[] = {c->params, c->c64, c->w_S, c->w_Q, c->w_FpA, c->xw, c->xp, c->xq, c->xref, c->bin_rank, c->bin_lin, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
+    void *bufs[] = {c->params, c->c64, c->w_S, c->w_Q, c->w_FpA, c->xw, c->xf, c->xp, c->xq, c->xref, c->bin_rank, c->bin_lin, c->perm, c->bin_of, c->wrap, c->cell_of, c->tmp,
                     c->bin_sorted, c->ncnt, c->nl_ang, c->nl_rad, c->pair_grad, c->f_own, c->rev,
                     c->w_atom,
                     c->e_atom, c->cells, c->cell_start_d, c->chunk_begin, c->chunk_end, c->cell_chunk,
@@ -375,6 +376,7 @@ int nep_create(const nep_hparams *hp, const nep_config *cfg, nep_ctx **out)
     A((void **)&c->c64, (wide ? W_C64 : NA * KB + NA) * sizeof(double));
     if (wide) {
         A((void **)&c->xw, N * sizeof(WAtomRec));
+        A((void **)&c->xf, N * sizeof(int4));
         A((void **)&c->w_S, N * WA * NLM * sizeof(float));
         A((void **)&c->w_Q, N * WDIM * sizeof(float));
         A((void **)&c->w_FpA, N * WA * LMAX * sizeof(float));
@@ -892,8 +894,18 @@ template <int BS>
 static void launch_wide_sums_t(nep_ctx *c, hipStream_t st)
 {
     const int n = c->pc.n, grid = xcd_grid((n + BS - 1) / BS);
-    k_w_radial<BS><<<grid, BS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->nl_rad, c->ncnt,
-                                        c->params, c->w_Q, c->e_atom, c->status, c->cflag);
+    if (c->pc.delta) {
+        // bin-offset mode: the radial phase gathers 16-byte fixed-point positions
+        k_w_fixed_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->xq, c->bin_sorted, c->cells, c->pc.qsinv,
+                                                              c->xf, c->status);
+        k_w_radial<BS, true><<<grid, BS, 0, st>>>(c->pc, c->xq, c->xf, c->cell_of, c->cells, c->nl_ang,
+                                                  c->nl_rad, c->ncnt, c->params, c->w_Q, c->e_atom, c->status,
+                                                  c->cflag);
+    } else {
+        k_w_radial<BS, false><<<grid, BS, 0, st>>>(c->pc, c->xq, c->xf, c->cell_of, c->cells, c->nl_ang,
+                                                   c->nl_rad, c->ncnt, c->params, c->w_Q, c->e_atom, c->status,
+                                                   c->cflag);
+    }
     for (int g = 0; g < WNGA; ++g)
         k_w_angular<BS><<<grid, BS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->c64, g,
                                              c->w_S, c->w_Q);

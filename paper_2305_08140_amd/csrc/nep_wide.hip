@@ -127,24 +127,132 @@ __global__ __launch_bounds__(256) void k_w_pop_params(const float *__restrict__ 
     }
 }
 
+// Bin-offset mode: every atom's position as fixed-point offsets from the
+// corner of its bin of the last build (the radial phase's 16-byte gathers).
+__global__ __launch_bounds__(256) void k_w_fixed_positions(int n, const double4 *__restrict__ xq,
+                                                           const int32_t *__restrict__ bin_sorted,
+                                                           const CellGeom *__restrict__ cells, double qsinv,
+                                                           int4 *__restrict__ xf, int32_t *__restrict__ status)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int32_t o[3];
+    w_bin_offsets(cells, bin_sorted[t], xq[t], qsinv, o, status);
+    xf[t] = make_int4(o[0], o[1], o[2], 0);
+}
+
+// The software pipelines of NeighbourPipe (every entry) and MaskPipe (the
+// entries of a bitmask) over the 16-byte fixed-point positions: entries two
+// neighbours ahead, the neighbour's position one ahead.
+struct FixedNeighbourPipe {
+    ListWalk w;
+    int count, s;
+    int32_t e_cur, e_nx;
+    int4 p_cur;
+    __device__ FixedNeighbourPipe(const int32_t *__restrict__ nl, const int4 *__restrict__ xf, int base,
+                                  uint32_t jmask, int t, int n, int nf, int nb, int cap)
+        : w(t, n, nf, nb, cap), count(nf + nb), s(0), e_cur(0), e_nx(0), p_cur(make_int4(0, 0, 0, 0))
+    {
+        if (count > 0) {
+            e_cur = nl[w.off];
+            p_cur = xf[(int)((uint32_t)e_cur & jmask) + base];
+        }
+        w.next();
+        if (w.s < count) e_nx = nl[w.off];
+    }
+    __device__ void pop(const int32_t *__restrict__ nl, const int4 *__restrict__ xf, int base, uint32_t jmask,
+                        int32_t &e, int4 &p)
+    {
+        e = e_cur;
+        p = p_cur;
+        ++s;
+        if (s < count) {
+            e_cur = e_nx;
+            p_cur = xf[(int)((uint32_t)e_cur & jmask) + base];
+            w.next();
+            if (w.s < count) e_nx = nl[w.off];
+        }
+    }
+};
+
+struct FixedMaskPipe {
+    MaskWalk mw;
+    size_t n;
+    int t, nf, nb, cap;
+    int s_cur, s_nx;
+    int32_t e_cur, e_nx;
+    int4 p_cur;
+    __device__ size_t off(int s) const { return (size_t)list_slot(s, nf, nb, cap) * n + t; }
+    __device__ FixedMaskPipe(const uint32_t *__restrict__ mask, const int32_t *__restrict__ nl,
+                             const int4 *__restrict__ xf, int base, uint32_t jmask, int t_, int n_, int nf_,
+                             int nb_, int cap_)
+        : mw(mask, n_, t_, nf_ + nb_), n((size_t)n_), t(t_), nf(nf_), nb(nb_), cap(cap_), e_cur(0), e_nx(0),
+          p_cur(make_int4(0, 0, 0, 0))
+    {
+        s_cur = mw.next();
+        if (s_cur >= 0) {
+            e_cur = nl[off(s_cur)];
+            p_cur = xf[(int)((uint32_t)e_cur & jmask) + base];
+        }
+        s_nx = mw.next();
+        if (s_nx >= 0) e_nx = nl[off(s_nx)];
+    }
+    __device__ bool valid() const { return s_cur >= 0; }
+    __device__ void pop(const int32_t *__restrict__ nl, const int4 *__restrict__ xf, int base, uint32_t jmask,
+                        int32_t &e, int4 &p, int &s)
+    {
+        e = e_cur;
+        p = p_cur;
+        s = s_cur;
+        s_cur = s_nx;
+        if (s_cur >= 0) {
+            e_cur = e_nx;
+            p_cur = xf[(int)((uint32_t)e_cur & jmask) + base];
+            s_nx = mw.next();
+            if (s_nx >= 0) e_nx = nl[off(s_nx)];
+        }
+    }
+};
+
+// Pair vector of bin-offset mode: the neighbour bin's edge-vector sum from
+// the block's LDS table plus the difference of the fixed-point offsets,
+// exactly antisymmetric in the two ends.
+__device__ __forceinline__ void pair_vector_f(int32_t e, const PairConsts &pc, const int4 &pj, const int4 &pi,
+                                              const double *__restrict__ btab, double &dx, double &dy, double &dz)
+{
+    const double *b = btab + 4 * (int)(((uint32_t)e >> pc.jbits) & 31u);
+    dx = fma(pc.qs, (double)pj.x - (double)pi.x, b[0]);
+    dy = fma(pc.qs, (double)pj.y - (double)pi.y, b[1]);
+    dz = fma(pc.qs, (double)pj.z - (double)pi.z, b[2]);
+}
+
 // Radial sums F_k = sum_j f_k(r_ij) over both lists (FP64), descriptors
 // q_n = sum_k c_nk F_k -> Q[n][t]; ZBL half energies -> e_atom[t].  The
 // radial list is walked in full when *cflag is set, else over the candidates
-// of the last full walk (see the default model's descriptor_sums).
+// of the last full walk (see the default model's descriptor_sums).  D16:
+// bin-offset mode, the neighbours' positions gathered as 16-byte fixed-point
+// offsets (xf) instead of 32-byte FP64 positions, with the pair vectors of
+// the force kernel (this walk is bound by its gathers' tag lookups).
 // (three waves per SIMD: 168 registers, a few spilled, measured faster than
 // two waves without spills)
-template <int BS>
+template <int BS, bool D16>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_w_radial(
-    PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
-    const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const int32_t *__restrict__ nl_rad,
-    const uint32_t *__restrict__ ncnt, const float *__restrict__ P, float *__restrict__ Q,
-    double *__restrict__ e_atom, int32_t *__restrict__ status, const int32_t *__restrict__ cflag)
+    PairConsts pc, const double4 *__restrict__ xq, const int4 *__restrict__ xf,
+    const int32_t *__restrict__ cell_of, const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang,
+    const int32_t *__restrict__ nl_rad, const uint32_t *__restrict__ ncnt, const float *__restrict__ P,
+    float *__restrict__ Q, double *__restrict__ e_atom, int32_t *__restrict__ status,
+    const int32_t *__restrict__ cflag)
 {
+    __shared__ __align__(16) double btab[D16 ? BIN_TAB : 2];
+    if constexpr (D16) stage_bin_vectors(cells, btab);   // one cell in this mode
     const int t = tile_atom<BS>(pc.n);
     if (t >= pc.n || lists_blocked(status)) return;
-    const double4 pi = xq[t];
-    const CellGeom *cg = cells + cell_of[t];
+    const CellGeom *cg = D16 ? cells : cells + cell_of[t];
     const int base = cg->atom_start;
+    double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
+    int4 fi = make_int4(0, 0, 0, 0);
+    if constexpr (D16) fi = xf[t];
+    else pi = xq[t];
     const uint32_t cnt = ncnt[t];
     const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff, nrf = (cnt >> 16) & 0xff, nrb = cnt >> 24;
     const double inv_rR = 1.0 / (double)pc.rc_rad, rcR2 = (double)pc.rc_rad * pc.rc_rad;
@@ -167,21 +275,42 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_
             ezbl += 0.5 * U;
         }
     };
+    // |r_ij|^2 of a popped entry, in either position form
+    auto dist2_p = [&](int32_t e, double px, double py, double pz) {
+        double dx, dy, dz;
+        pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
+        return dx * dx + dy * dy + dz * dz;
+    };
+    auto dist2_f = [&](int32_t e, const int4 &pj) {
+        double dx, dy, dz;
+        pair_vector_f(e, pc, pj, fi, btab, dx, dy, dz);
+        return dx * dx + dy * dy + dz * dz;
+    };
     {
         // angular list: every entry, marking those within the pair-gradient
         // write radius (with a margin) for the angular phases
         const double awr = (double)pc.rc_ang2_write * (1.0 + 0x1p-15);
         MaskWriter mw;
-        for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
-            const int s = q.s;
-            int32_t e;
-            double px, py, pz;
-            q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
-            double dx, dy, dz;
-            pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            mw.add(pc.amask, pc.n, t, s, q.count, r2 < awr);
+        auto entry = [&](int s, int count, double r2) {
+            mw.add(pc.amask, pc.n, t, s, count, r2 < awr);
             if (r2 < rcR2) radial_term(r2);
+        };
+        if constexpr (D16) {
+            for (FixedNeighbourPipe q(nl_ang, xf, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
+                const int s = q.s;
+                int32_t e;
+                int4 pj;
+                q.pop(nl_ang, xf, base, jmask, e, pj);
+                entry(s, q.count, dist2_f(e, pj));
+            }
+        } else {
+            for (NeighbourPipe q(nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.s < q.count;) {
+                const int s = q.s;
+                int32_t e;
+                double px, py, pz;
+                q.pop(nl_ang, xq, base, jmask, e, px, py, pz);
+                entry(s, q.count, dist2_p(e, px, py, pz));
+            }
         }
     }
     // radial list: the entries inside rc_rad marked for the force kernel; in
@@ -189,33 +318,53 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_
     // descriptor) or over the last full walk's candidates
     if (*cflag == 0) {
         SparseMaskWriter mw(pc.rmask, pc.n, t, nrf + nrb);
-        for (MaskPipe q(pc.cmask, nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.valid();) {
-            int32_t e;
-            double px, py, pz;
-            int s;
-            q.pop(nl_rad, xq, base, jmask, e, px, py, pz, s);
-            double dx, dy, dz;
-            pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 >= rcR2) continue;
+        auto entry = [&](int s, double r2) {
+            if (r2 >= rcR2) return;
             mw.set(s);
             radial_term(r2);
+        };
+        if constexpr (D16) {
+            for (FixedMaskPipe q(pc.cmask, nl_rad, xf, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.valid();) {
+                int32_t e;
+                int4 pj;
+                int s;
+                q.pop(nl_rad, xf, base, jmask, e, pj, s);
+                entry(s, dist2_f(e, pj));
+            }
+        } else {
+            for (MaskPipe q(pc.cmask, nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.valid();) {
+                int32_t e;
+                double px, py, pz;
+                int s;
+                q.pop(nl_rad, xq, base, jmask, e, px, py, pz, s);
+                entry(s, dist2_p(e, px, py, pz));
+            }
         }
         mw.finish();
     } else {
         const double rcC2 = (double)pc.rc_cand * pc.rc_cand;
         MaskWriter mw, cw;
-        for (NeighbourPipe q(nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.s < q.count;) {
-            const int s = q.s;
-            int32_t e;
-            double px, py, pz;
-            q.pop(nl_rad, xq, base, jmask, e, px, py, pz);
-            double dx, dy, dz;
-            pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            mw.add(pc.rmask, pc.n, t, s, q.count, r2 < rcR2);
-            cw.add(pc.cmask, pc.n, t, s, q.count, r2 < rcC2);
+        auto entry = [&](int s, int count, double r2) {
+            mw.add(pc.rmask, pc.n, t, s, count, r2 < rcR2);
+            cw.add(pc.cmask, pc.n, t, s, count, r2 < rcC2);
             if (r2 < rcR2) radial_term(r2);
+        };
+        if constexpr (D16) {
+            for (FixedNeighbourPipe q(nl_rad, xf, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.s < q.count;) {
+                const int s = q.s;
+                int32_t e;
+                int4 pj;
+                q.pop(nl_rad, xf, base, jmask, e, pj);
+                entry(s, q.count, dist2_f(e, pj));
+            }
+        } else {
+            for (NeighbourPipe q(nl_rad, xq, base, jmask, t, pc.n, nrf, nrb, pc.capR); q.s < q.count;) {
+                const int s = q.s;
+                int32_t e;
+                double px, py, pz;
+                q.pop(nl_rad, xq, base, jmask, e, px, py, pz);
+                entry(s, q.count, dist2_p(e, px, py, pz));
+            }
         }
     }
     if (overlap) latch_error(status, -4);
@@ -1102,9 +1251,14 @@ __global__ __launch_bounds__(64) void k_w_param_grad(
 
 // launch shapes: 64, 128 and 256 threads per block (chosen by nep_autotune)
 #define NEP_W_INST(BS)                                                                                               \
-    template __global__ void k_w_radial<BS>(PairConsts, const double4 *, const int32_t *, const CellGeom *,            \
-                                            const int32_t *, const int32_t *, const uint32_t *, const float *,        \
-                                            float *, double *, int32_t *, const int32_t *);                           \
+    template __global__ void k_w_radial<BS, false>(PairConsts, const double4 *, const int4 *, const int32_t *,       \
+                                                   const CellGeom *, const int32_t *, const int32_t *,                \
+                                                   const uint32_t *, const float *, float *, double *, int32_t *,     \
+                                                   const int32_t *);                                                  \
+    template __global__ void k_w_radial<BS, true>(PairConsts, const double4 *, const int4 *, const int32_t *,        \
+                                                  const CellGeom *, const int32_t *, const int32_t *,                 \
+                                                  const uint32_t *, const float *, float *, double *, int32_t *,      \
+                                                  const int32_t *);                                                   \
     template __global__ void k_w_angular<BS>(PairConsts, const double4 *, const int32_t *, const CellGeom *,           \
                                              const int32_t *, const uint32_t *, const double *, int, float *,         \
                                              float *);                                                                \
