@@ -906,9 +906,14 @@ static void launch_wide_sums_t(nep_ctx *c, hipStream_t st)
                                                    c->nl_rad, c->ncnt, c->params, c->w_Q, c->e_atom, c->status,
                                                    c->cflag);
     }
-    for (int g = 0; g < WNGA; ++g)
-        k_w_angular<BS><<<grid, BS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->c64, g,
-                                             c->w_S, c->w_Q);
+    for (int g = 0; g < WNGA; ++g) {
+        if (c->pc.delta)
+            k_w_angular<BS, true><<<grid, BS, 0, st>>>(c->pc, c->xq, c->xf, c->cell_of, c->cells, c->nl_ang, c->ncnt,
+                                                       c->c64, g, c->w_S, c->w_Q);
+        else
+            k_w_angular<BS, false><<<grid, BS, 0, st>>>(c->pc, c->xq, c->xf, c->cell_of, c->cells, c->nl_ang,
+                                                        c->ncnt, c->c64, g, c->w_S, c->w_Q);
+    }
     // bin-offset mode: the records carry fixed-point positions (WAtomRec80)
     const int32_t *bs = c->pc.delta ? c->bin_sorted : nullptr;
     if (c->nn_mode != 0) {
@@ -934,8 +939,14 @@ static void launch_wide_desc_t(nep_ctx *c, hipStream_t st)
 {
     const int n = c->pc.n, grid = xcd_grid((n + BS - 1) / BS);
     launch_wide_sums_t<BS>(c, st);
-    k_w_grad<BS><<<grid, BS, 0, st>>>(c->pc, c->xq, c->cell_of, c->cells, c->nl_ang, c->ncnt, c->params, c->c64,
-                                      c->w_S, c->w_FpA, c->pair_grad, c->f_own, c->w_atom);
+    if (c->pc.delta)
+        k_w_grad<BS, true><<<grid, BS, 0, st>>>(c->pc, c->xq, c->xf, c->cell_of, c->cells, c->nl_ang, c->ncnt,
+                                                c->params, c->c64, c->w_S, c->w_FpA, c->pair_grad, c->f_own,
+                                                c->w_atom);
+    else
+        k_w_grad<BS, false><<<grid, BS, 0, st>>>(c->pc, c->xq, c->xf, c->cell_of, c->cells, c->nl_ang, c->ncnt,
+                                                 c->params, c->c64, c->w_S, c->w_FpA, c->pair_grad, c->f_own,
+                                                 c->w_atom);
 }
 
 template <int BS>

@@ -76,10 +76,10 @@ __global__ void k_w_radial(PairConsts pc, const double4 *xq, const int4 *xf, con
                            const CellGeom *cells, const int32_t *nl_ang, const int32_t *nl_rad,
                            const uint32_t *ncnt, const float *P, float *Q, double *e_atom, int32_t *status,
                            const int32_t *cflag);
-template <int BS>
-__global__ void k_w_angular(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
-                            const int32_t *nl_ang, const uint32_t *ncnt, const double *C64, int group, float *S,
-                            float *Q);
+template <int BS, bool D16>
+__global__ void k_w_angular(PairConsts pc, const double4 *xq, const int4 *xf, const int32_t *cell_of,
+                            const CellGeom *cells, const int32_t *nl_ang, const uint32_t *ncnt, const double *C64,
+                            int group, float *S, float *Q);
 template <int BS>
 __global__ void k_w_network(int n, const double4 *xq, const float *P, const float *Q, WAtomRec *xw, float *FpA,
                             double *e_atom, const CellGeom *cells, const int32_t *bin_sorted, double qsinv,
@@ -88,10 +88,11 @@ template <bool BF16>
 __global__ void k_w_network_mfma(int n_atoms, int ntiles, const double4 *xq, const float *P, const float *Q,
                                  WAtomRec *xw, float *FpA, double *e_atom, const CellGeom *cells,
                                  const int32_t *bin_sorted, double qsinv, int32_t *status);
-template <int BS>
-__global__ void k_w_grad(PairConsts pc, const double4 *xq, const int32_t *cell_of, const CellGeom *cells,
-                         const int32_t *nl_ang, const uint32_t *ncnt, const float *P, const double *C64,
-                         const float *S, const float *FpA, float4 *pair_grad, float4 *f_own, float *w_atom);
+template <int BS, bool D16>
+__global__ void k_w_grad(PairConsts pc, const double4 *xq, const int4 *xf, const int32_t *cell_of,
+                         const CellGeom *cells, const int32_t *nl_ang, const uint32_t *ncnt, const float *P,
+                         const double *C64, const float *S, const float *FpA, float4 *pair_grad, float4 *f_own,
+                         float *w_atom);
 template <int BS, bool D80>
 __global__ void k_w_force(PairConsts pc, const WAtomRec *xw, const int32_t *cell_of, const CellGeom *cells,
                           const int32_t *nl_ang, const int32_t *nl_rad, const uint32_t *ncnt, const uint8_t *rev,

@@ -379,19 +379,54 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_
     e_atom[t] = ezbl;
 }
 
+// The angular-list entries within the pair-gradient write radius (amask)
+// with their FP64 pair vectors: from the FP64 positions, or in bin-offset
+// mode (D16) from the 16-byte fixed-point positions and the block's table of
+// bin-offset vectors.  body(e, off, dx, dy, dz), off = the slot's offset.
+template <bool D16, class Body>
+__device__ __forceinline__ void angular_walk(const PairConsts &pc, const double4 *__restrict__ xq,
+                                             const int4 *__restrict__ xf, const double *__restrict__ btab, int t,
+                                             const CellGeom *cg, const int32_t *__restrict__ nl_ang, int naf,
+                                             int nab, Body &&body)
+{
+    const int base = cg->atom_start;
+    const uint32_t jmask = (1u << pc.jbits) - 1u;
+    if constexpr (D16) {
+        const int4 fi = xf[t];
+        for (FixedMaskPipe q(pc.amask, nl_ang, xf, base, jmask, t, pc.n, naf, nab, pc.capA); q.valid();) {
+            int32_t e;
+            int4 pj;
+            int s;
+            q.pop(nl_ang, xf, base, jmask, e, pj, s);
+            double dx, dy, dz;
+            pair_vector_f(e, pc, pj, fi, btab, dx, dy, dz);
+            body(e, q.off(s), dx, dy, dz);
+        }
+    } else {
+        const double4 pi = xq[t];
+        for (MaskPipe q(pc.amask, nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.valid();) {
+            int32_t e;
+            double px, py, pz;
+            int s;
+            q.pop(nl_ang, xq, base, jmask, e, px, py, pz, s);
+            double dx, dy, dz;
+            pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
+            body(e, q.off(s), dx, dy, dz);
+        }
+    }
+}
+
 // Angular sums of the channels c0 .. c0+NC-1 over the angular list:
 // S[(c*24 + lm)][t] (l <= 3 in FP64, l = 4 in FP32, rounded once) and the
 // descriptors q_cl = sum_m S^2 -> Q[WR + WA (l-1) + c][t].
-template <int NC>
-__device__ __forceinline__ void w_angular_group(const PairConsts &pc, const double4 *__restrict__ xq, int t,
+template <int NC, bool D16>
+__device__ __forceinline__ void w_angular_group(const PairConsts &pc, const double4 *__restrict__ xq,
+                                                const int4 *__restrict__ xf, const double *__restrict__ btab, int t,
                                                 const CellGeom *cg, const int32_t *__restrict__ nl_ang, int naf,
                                                 int nab, const double *__restrict__ C64, int c0,
                                                 float *__restrict__ S, float *__restrict__ Q)
 {
-    const double4 pi = xq[t];
-    const int base = cg->atom_start;
     const double inv_rA = 1.0 / (double)pc.rc_ang, rcA2 = (double)pc.rc_ang * pc.rc_ang;
-    const uint32_t jmask = (1u << pc.jbits) - 1u;
     double A[NC][15];
     float A4[NC][9];
 #pragma unroll
@@ -401,15 +436,9 @@ __device__ __forceinline__ void w_angular_group(const PairConsts &pc, const doub
 #pragma unroll
         for (int m = 0; m < 9; ++m) A4[c][m] = 0.0f;
     }
-    for (MaskPipe q(pc.amask, nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.valid();) {
-        int32_t e;
-        double px, py, pz;
-        int s;
-        q.pop(nl_ang, xq, base, jmask, e, px, py, pz, s);
-        double dx, dy, dz;
-        pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, dx, dy, dz);
+    angular_walk<D16>(pc, xq, xf, btab, t, cg, nl_ang, naf, nab, [&](int32_t, size_t, double dx, double dy, double dz) {
         const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 >= rcA2) continue;
+        if (r2 >= rcA2) return;
         const double r = dist_d(r2);
         double rinv = (double)frcp((float)r);
         rinv = rinv * fma(-r, rinv, 2.0);
@@ -440,7 +469,7 @@ __device__ __forceinline__ void w_angular_group(const PairConsts &pc, const doub
 #pragma unroll
             for (int m = 0; m < 9; ++m) A4[c][m] = fmaf(gf, Yf[15 + m], A4[c][m]);
         }
-    }
+    });
     const size_t n = (size_t)pc.n;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -457,20 +486,22 @@ __device__ __forceinline__ void w_angular_group(const PairConsts &pc, const doub
     }
 }
 
-template <int BS>
+template <int BS, bool D16>
 __global__ __launch_bounds__(BS) void k_w_angular(
-    PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
+    PairConsts pc, const double4 *__restrict__ xq, const int4 *__restrict__ xf, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const uint32_t *__restrict__ ncnt,
     const double *__restrict__ C64, int group, float *__restrict__ S, float *__restrict__ Q)
 {
+    __shared__ __align__(16) double btab[D16 ? BIN_TAB : 2];
+    if constexpr (D16) stage_bin_vectors(cells, btab);   // one cell in this mode
     const int t = tile_atom<BS>(pc.n);
     if (t >= pc.n) return;
-    const CellGeom *cg = cells + cell_of[t];
+    const CellGeom *cg = D16 ? cells : cells + cell_of[t];
     const uint32_t cnt = ncnt[t];
     const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff;
     const int c0 = group * WGA;
-    if (WA - c0 >= WGA) w_angular_group<WGA>(pc, xq, t, cg, nl_ang, naf, nab, C64, c0, S, Q);
-    else w_angular_group<WA - (WNGA - 1) * WGA>(pc, xq, t, cg, nl_ang, naf, nab, C64, c0, S, Q);
+    if (WA - c0 >= WGA) w_angular_group<WGA, D16>(pc, xq, xf, btab, t, cg, nl_ang, naf, nab, C64, c0, S, Q);
+    else w_angular_group<WA - (WNGA - 1) * WGA, D16>(pc, xq, xf, btab, t, cg, nl_ang, naf, nab, C64, c0, S, Q);
 }
 
 // Network forward and backward of one atom: U (added to the ZBL half
@@ -727,8 +758,9 @@ template __global__ void k_w_network_mfma<true>(int, int, const double4 *, const
 // Contributions of the channels c0 .. c0+NC-1 to dU_i/dr_ij of every angular
 // slot, added into pair_grad (the first group writes), and to the atom's own
 // force and virial sums.
-template <int NC>
-__device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4 *__restrict__ xq, int t,
+template <int NC, bool D16>
+__device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4 *__restrict__ xq,
+                                             const int4 *__restrict__ xf, const double *__restrict__ btab, int t,
                                              const CellGeom *cg, const int32_t *__restrict__ nl_ang, int naf,
                                              int nab, const float *__restrict__ P, const double *__restrict__ C64,
                                              const float *__restrict__ S,
@@ -736,9 +768,6 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
                                              float &Fx, float &Fy, float &Fz, float W[9])
 {
     const size_t n = (size_t)pc.n;
-    const double4 pi = xq[t];
-    const int base = cg->atom_start;
-    const uint32_t jmask = (1u << pc.jbits) - 1u;
     // B_{c,lm} = 2 (dU/dq_cl) s_{c,lm}, times the harmonic's normalisation
     // (the walk uses the unnormalised polynomials y_lm = Y_lm / sph_norm(lm))
     float B[NC][NLM];
@@ -758,19 +787,13 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
     }
     const bool first = c0 == 0;
     const double inv_rA = 1.0 / (double)pc.rc_ang;
-    for (MaskPipe q(pc.amask, nl_ang, xq, base, jmask, t, pc.n, naf, nab, pc.capA); q.valid();) {
-        int32_t e;
-        double px, py, pz;
-        int s;
-        q.pop(nl_ang, xq, base, jmask, e, px, py, pz, s);
-        const size_t off = q.off(s);
-        double ddx, ddy, ddz;
-        pair_vector_p(e, pc, px, py, pz, pi.x, pi.y, pi.z, cg, ddx, ddy, ddz);
+    angular_walk<D16>(pc, xq, xf, btab, t, cg, nl_ang, naf, nab,
+                      [&](int32_t, size_t off, double ddx, double ddy, double ddz) {
         const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
         const float r2 = dx * dx + dy * dy + dz * dz;
         if (r2 >= pc.rc_ang2) {
             if (first && r2 < pc.rc_ang2_write) pair_grad[off] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            continue;
+            return;
         }
         const float r = fsqrt(r2);
         const float tt = scaled_minus_one(r, pc.inv_rc_ang, pc.inv_rc_ang_lo);
@@ -854,20 +877,22 @@ __device__ __forceinline__ void w_grad_group(const PairConsts &pc, const double4
         W[0] = fmaf(gx, dx, W[0]); W[1] = fmaf(gx, dy, W[1]); W[2] = fmaf(gx, dz, W[2]);
         W[3] = fmaf(gy, dx, W[3]); W[4] = fmaf(gy, dy, W[4]); W[5] = fmaf(gy, dz, W[5]);
         W[6] = fmaf(gz, dx, W[6]); W[7] = fmaf(gz, dy, W[7]); W[8] = fmaf(gz, dz, W[8]);
-    }
+    });
 }
 
-template <int BS>
+template <int BS, bool D16>
 __global__ __launch_bounds__(BS, 2) void k_w_grad(
-    PairConsts pc, const double4 *__restrict__ xq, const int32_t *__restrict__ cell_of,
+    PairConsts pc, const double4 *__restrict__ xq, const int4 *__restrict__ xf, const int32_t *__restrict__ cell_of,
     const CellGeom *__restrict__ cells, const int32_t *__restrict__ nl_ang, const uint32_t *__restrict__ ncnt,
     const float *__restrict__ P, const double *__restrict__ C64, const float *__restrict__ S,
     const float *__restrict__ FpA, float4 *__restrict__ pair_grad, float4 *__restrict__ f_own,
     float *__restrict__ w_atom)
 {
+    __shared__ __align__(16) double btab[D16 ? BIN_TAB : 2];
+    if constexpr (D16) stage_bin_vectors(cells, btab);   // one cell in this mode
     const int t = tile_atom<BS>(pc.n);
     if (t >= pc.n) return;
-    const CellGeom *cg = cells + cell_of[t];
+    const CellGeom *cg = D16 ? cells : cells + cell_of[t];
     const uint32_t cnt = ncnt[t];
     const int naf = cnt & 0xff, nab = (cnt >> 8) & 0xff;
     float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f, W[9];
@@ -876,10 +901,11 @@ __global__ __launch_bounds__(BS, 2) void k_w_grad(
 #pragma unroll 1
     for (int g = 0; g < WNG; ++g) {
         if (WA - g * WG >= WG)
-            w_grad_group<WG>(pc, xq, t, cg, nl_ang, naf, nab, P, C64, S, FpA, g * WG, pair_grad, Fx, Fy, Fz, W);
+            w_grad_group<WG, D16>(pc, xq, xf, btab, t, cg, nl_ang, naf, nab, P, C64, S, FpA, g * WG, pair_grad, Fx,
+                                  Fy, Fz, W);
         else
-            w_grad_group<WA - (WNG - 1) * WG>(pc, xq, t, cg, nl_ang, naf, nab, P, C64, S, FpA, g * WG, pair_grad, Fx,
-                                              Fy, Fz, W);
+            w_grad_group<WA - (WNG - 1) * WG, D16>(pc, xq, xf, btab, t, cg, nl_ang, naf, nab, P, C64, S, FpA, g * WG,
+                                                   pair_grad, Fx, Fy, Fz, W);
     }
     f_own[t] = make_float4(Fx, Fy, Fz, 0.0f);
     float *w = w_atom + (size_t)t * 9;
@@ -1259,14 +1285,22 @@ __global__ __launch_bounds__(64) void k_w_param_grad(
                                                   const CellGeom *, const int32_t *, const int32_t *,                 \
                                                   const uint32_t *, const float *, float *, double *, int32_t *,      \
                                                   const int32_t *);                                                   \
-    template __global__ void k_w_angular<BS>(PairConsts, const double4 *, const int32_t *, const CellGeom *,           \
-                                             const int32_t *, const uint32_t *, const double *, int, float *,         \
-                                             float *);                                                                \
+    template __global__ void k_w_angular<BS, false>(PairConsts, const double4 *, const int4 *, const int32_t *,      \
+                                                    const CellGeom *, const int32_t *, const uint32_t *,              \
+                                                    const double *, int, float *, float *);                           \
+    template __global__ void k_w_angular<BS, true>(PairConsts, const double4 *, const int4 *, const int32_t *,       \
+                                                   const CellGeom *, const int32_t *, const uint32_t *,               \
+                                                   const double *, int, float *, float *);                            \
     template __global__ void k_w_network<BS>(int, const double4 *, const float *, const float *, WAtomRec *, float *, \
                                              double *, const CellGeom *, const int32_t *, double, int32_t *);         \
-    template __global__ void k_w_grad<BS>(PairConsts, const double4 *, const int32_t *, const CellGeom *,             \
-                                          const int32_t *, const uint32_t *, const float *, const double *,           \
-                                          const float *, const float *, float4 *, float4 *, float *);                 \
+    template __global__ void k_w_grad<BS, false>(PairConsts, const double4 *, const int4 *, const int32_t *,         \
+                                                 const CellGeom *, const int32_t *, const uint32_t *, const float *,  \
+                                                 const double *, const float *, const float *, float4 *, float4 *,    \
+                                                 float *);                                                            \
+    template __global__ void k_w_grad<BS, true>(PairConsts, const double4 *, const int4 *, const int32_t *,          \
+                                                const CellGeom *, const int32_t *, const uint32_t *, const float *,   \
+                                                const double *, const float *, const float *, float4 *, float4 *,     \
+                                                float *);                                                             \
     template __global__ void k_w_force<BS, false>(PairConsts, const WAtomRec *, const int32_t *, const CellGeom *,    \
                                                   const int32_t *, const int32_t *, const uint32_t *,                 \
                                                   const uint8_t *, const float4 *, const float4 *, const int32_t *,   \
