@@ -77,7 +77,7 @@ __global__ void k_bin_rank(int, const int32_t *, const int32_t *, const int32_t 
                            const CellGeom *, int32_t *, int32_t *, const int32_t *, const int32_t *);
 __global__ void k_sort_positions(int, const int32_t *, const double *, const double *, const double *,
                                  const int32_t *, const int32_t *, const CellGeom *, double4 *, int32_t *,
-                                 const int32_t *);
+                                 const int32_t *, const int32_t *, double, int4 *);
 __global__ void k_build_lists(PairConsts, double, double, double, double, const double4 *, const int32_t *,
                               const CellGeom *, const int32_t *, const int32_t *, const int32_t *, int32_t *,
                               int32_t *, uint32_t *, int32_t *, const int32_t *, int);
@@ -223,6 +223,9 @@ struct nep_ctx {
 };
 
 static int grid_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+// the fixed-point positions the position refresh writes for the paper-size
+// model's walks in bin-offset mode (none otherwise)
+static int4 *wide_xf(const nep_ctx *c) { return c->wide && c->pc.delta ? c->xf : nullptr; }
 
 
 static int bucket_of(int64_t n)
@@ -753,7 +756,8 @@ static int launch_build(nep_ctx *c, const nep_system *s, hipStream_t st, const i
     // sorted positions for the list build (skipped with the rest of the
     // build when the flag says no rebuild; every evaluation refreshes them)
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                       c->cells, c->xq, c->status, flag);
+                                                       c->cells, c->xq, c->status, flag,
+                                                       c->bin_sorted, c->pc.qsinv, wide_xf(c));
     const double lA = c->hp.rc_ang + c->cfg.skin, lR = c->hp.rc_rad + c->cfg.skin;
     if (c->lb_blocks > 0)
         k_build_lists_blocks<<<xcd_grid(c->lb_blocks), LB_BS, 0, st>>>(
@@ -895,9 +899,8 @@ static void launch_wide_sums_t(nep_ctx *c, hipStream_t st)
 {
     const int n = c->pc.n, grid = xcd_grid((n + BS - 1) / BS);
     if (c->pc.delta) {
-        // bin-offset mode: the radial phase gathers 16-byte fixed-point positions
-        k_w_fixed_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->xq, c->bin_sorted, c->cells, c->pc.qsinv,
-                                                              c->xf, c->status);
+        // bin-offset mode: the walks gather the 16-byte fixed-point positions
+        // the position refresh wrote
         k_w_radial<BS, true><<<grid, BS, 0, st>>>(c->pc, c->xq, c->xf, c->cell_of, c->cells, c->nl_ang,
                                                   c->nl_rad, c->ncnt, c->params, c->w_Q, c->e_atom, c->status,
                                                   c->cflag);
@@ -1014,7 +1017,8 @@ static int launch_efv(nep_ctx *c, const nep_system *s, nep_efv *o, hipStream_t s
     if (!md_step) k_set_flag<<<1, 64, 0, st>>>(c->cflag, 1);
     if (refresh_positions)
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                           c->cells, c->xq, c->status, nullptr);
+                                                           c->cells, c->xq, c->status, nullptr,
+                                                           c->bin_sorted, c->pc.qsinv, wide_xf(c));
     if (ev) HIP_TRY(hipEventRecord(ev[0], st));
     launch_desc_any(c, st);
     if (ev) HIP_TRY(hipEventRecord(ev[1], st));
@@ -1062,7 +1066,8 @@ int nep_time_efv(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, doub
     for (int r = 0; r < reps; ++r) {
         HIP_TRY(hipEventRecord(ev[0], st));
         k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                           c->cells, c->xq, c->status, nullptr);
+                                                           c->cells, c->xq, c->status, nullptr,
+                                                           c->bin_sorted, c->pc.qsinv, wide_xf(c));
         HIP_TRY(hipEventRecord(ev[1], st));
         launch_desc_any(c, st);
         HIP_TRY(hipEventRecord(ev[2], st));
@@ -1122,7 +1127,8 @@ static int backward_launch(nep_ctx *c, const nep_system *s, const nep_efv *o, co
 {
     const int n = (int)s->n_atoms;
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                       c->cells, c->xq, c->status, nullptr);
+                                                       c->cells, c->xq, c->status, nullptr,
+                                                       c->bin_sorted, c->pc.qsinv, wide_xf(c));
     if (c->wide) {
         // the staged sums, descriptors and adjoints of these positions (a
         // full radial walk, as in any evaluation outside the MD loop)
@@ -1190,7 +1196,8 @@ int nep_autotune(nep_ctx *c, const nep_system *s, nep_efv *o, int32_t reps, int3
     HIP_TRY(hipEventCreate(&e1));
     k_set_flag<<<1, 64, 0, st>>>(c->cflag, 1);   // full radial walks
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of,
-                                                       c->cells, c->xq, c->status, nullptr);
+                                                       c->cells, c->xq, c->status, nullptr,
+                                                       c->bin_sorted, c->pc.qsinv, wide_xf(c));
     auto time_it = [&](auto &&launch) -> float {
         launch();   // warm-up
         HIP_TRY(hipEventRecord(e0, st));
@@ -1626,7 +1633,8 @@ int nep_population_efv(nep_ctx *c, const nep_system *s, int32_t n_pop, const flo
         return NEP_OK;
     }
     k_sort_positions<<<grid_for(n, 256), 256, 0, st>>>(n, c->perm, s->x, s->y, s->z, c->wrap, c->cell_of, c->cells,
-                                                       c->xq, c->status, nullptr);
+                                                       c->xq, c->status, nullptr,
+                                                       c->bin_sorted, c->pc.qsinv, wide_xf(c));
     k_pop_params<<<n_pop, 256, 0, st>>>(theta, c->params, c->pop_P, c->pop_c64);
     const int tiles_d = (n + POP_DESC_BS - 1) / POP_DESC_BS;
     const int grid_d = xcd_grid((int)((int64_t)tiles_d * n_pop));

@@ -198,13 +198,18 @@ __global__ void k_bin_rank(int n, const int32_t *__restrict__ bin_of,
 // Wrapped positions in sorted order: xq[t] = x[perm[t]] - w . h, 32-byte
 // records (four atoms per 128-byte line).  Runs at every evaluation (and
 // in a build, when `flag` is non-null and set); non-finite positions latch
-// NEP_E_NONFINITE.
+// NEP_E_NONFINITE.  With xf set (the paper-size model in bin-offset mode,
+// one cell) also the 16-byte fixed-point form its walks gather: offsets
+// from the corner of the atom's bin of the last build in units 1/qsinv (an
+// offset beyond the 32-bit range means the atom left its bin by far more
+// than the skin: error -9).
 __global__ void k_sort_positions(int n, const int32_t *__restrict__ perm,
                                  const double *__restrict__ x, const double *__restrict__ y,
                                  const double *__restrict__ z, const int32_t *__restrict__ wrap,
                                  const int32_t *__restrict__ cell_of,
                                  const CellGeom *__restrict__ cells, double4 *__restrict__ xq,
-                                 int32_t *__restrict__ status, const int32_t *__restrict__ flag)
+                                 int32_t *__restrict__ status, const int32_t *__restrict__ flag,
+                                 const int32_t *__restrict__ bin_sorted, double qsinv, int4 *__restrict__ xf)
 {
     if (flag && *flag == 0) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -219,6 +224,22 @@ __global__ void k_sort_positions(int n, const int32_t *__restrict__ perm,
     const double wy = py - (w0 * h[1] + w1 * h[4] + w2 * h[7]);
     const double wz = pz - (w0 * h[2] + w1 * h[5] + w2 * h[8]);
     xq[t] = make_double4(wx, wy, wz, 0.0);
+    if (xf) {
+        const CellGeom &cg = cells[0];
+        const int lbin = bin_sorted[t];
+        const int b0 = lbin % cg.nb[0], b1 = (lbin / cg.nb[0]) % cg.nb[1], b2 = lbin / (cg.nb[0] * cg.nb[1]);
+        const double *bv = cg.bv;
+        const double d[3] = {wx - (b0 * bv[0] + b1 * bv[3] + b2 * bv[6]), wy - (b0 * bv[1] + b1 * bv[4] + b2 * bv[7]),
+                             wz - (b0 * bv[2] + b1 * bv[5] + b2 * bv[8])};
+        int o[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double v = rint(d[k] * qsinv);
+            if (!(fabs(v) < 2147483000.0)) latch_error(status, -9);
+            o[k] = (int)fmin(fmax(v, -2147483000.0), 2147483000.0);
+        }
+        xf[t] = make_int4(o[0], o[1], o[2], 0);
+    }
 }
 
 // One atom's list build: the candidates of each visited bin are offered in

@@ -69,8 +69,6 @@ static_assert(sizeof(WAtomRec80) == 80, "WAtomRec80 must be 80 bytes");
 
 __global__ void k_w_params64(const float *P, double *C64);
 __global__ void k_w_pop_params(const float *theta, const float *base, float *P, double *C64);
-__global__ void k_w_fixed_positions(int n, const double4 *xq, const int32_t *bin_sorted, const CellGeom *cells,
-                                    double qsinv, int4 *xf, int32_t *status);
 template <int BS, bool D16>
 __global__ void k_w_radial(PairConsts pc, const double4 *xq, const int4 *xf, const int32_t *cell_of,
                            const CellGeom *cells, const int32_t *nl_ang, const int32_t *nl_rad,

@@ -127,20 +127,6 @@ __global__ __launch_bounds__(256) void k_w_pop_params(const float *__restrict__ 
     }
 }
 
-// Bin-offset mode: every atom's position as fixed-point offsets from the
-// corner of its bin of the last build (the radial phase's 16-byte gathers).
-__global__ __launch_bounds__(256) void k_w_fixed_positions(int n, const double4 *__restrict__ xq,
-                                                           const int32_t *__restrict__ bin_sorted,
-                                                           const CellGeom *__restrict__ cells, double qsinv,
-                                                           int4 *__restrict__ xf, int32_t *__restrict__ status)
-{
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    int32_t o[3];
-    w_bin_offsets(cells, bin_sorted[t], xq[t], qsinv, o, status);
-    xf[t] = make_int4(o[0], o[1], o[2], 0);
-}
-
 // The software pipelines of NeighbourPipe (every entry) and MaskPipe (the
 // entries of a bitmask) over the 16-byte fixed-point positions: entries two
 // neighbours ahead, the neighbour's position one ahead.
