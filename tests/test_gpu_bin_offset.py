@@ -4,12 +4,13 @@ A single periodic cell binned along every axis (at most 2^23 atoms) takes
 this mode: list entries carry the offset of the neighbour's bin from the
 atom's own, and the force kernels read positions as fixed-point offsets from
 the corner of the atom's bin (48-byte records for the default model, 80-byte
-for the paper-size one).  The same cell as both members of a two-cell batch
-takes the image mode with FP64 record positions.  The descriptor side does
-the same arithmetic in both (the image shift is n.h either way), so site
-energies agree to the FP32 rounding of the network at most; forces and
-virials differ only by the fixed-point rounding (at most half a unit, ~4e-9
-A, per coordinate) and the FP32 rounding of the force sums.  An atom carried
+for the paper-size one, whose staged walks read 16-byte fixed-point
+positions too).  The same cell as both members of a two-cell batch takes
+the image mode with FP64 positions.  The default model's descriptor does
+the same arithmetic in both (the image shift is n.h either way), so its
+site energies agree to the FP32 rounding of the network at most; the rest
+differs only by the fixed-point rounding (at most half a unit, ~4e-9 A,
+per coordinate) and the FP32 rounding of the sums.  An atom carried
 beyond the fixed-point range (the bin plus at least skin + 1 A on every
 side) before the next build makes the evaluation report NEP_E_INTERNAL
 instead of returning numbers."""
