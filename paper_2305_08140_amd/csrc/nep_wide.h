@@ -8,7 +8,8 @@
 //   k_w_angular   angular sums of one group of WGA channels per launch
 //                 (l <= 3 in FP64, l = 4 in FP32, as in the default model)
 //   k_w_network   network forward and backward per atom, site energy, the
-//                 atom's record (position + 16 radial adjoints, 96 bytes)
+//                 atom's record (position + 16 radial adjoints, 96 bytes;
+//                 80 with a fixed-point position in bin-offset mode)
 //   k_w_grad      dU_i/dr_ij of every angular slot, channel group by group
 //   k_w_force     radial + ZBL pair forces, angular assembly, virial
 // and, for the parameter gradient, k_w_param_grad after the first three.

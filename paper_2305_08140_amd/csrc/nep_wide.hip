@@ -2,7 +2,9 @@
 // arithmetic follows the default model's kernels (nep_kernels.hip) term by
 // term: FP64 pair geometry, Chebyshev basis, radial sums and l <= 3 angular
 // sums; FP32 l = 4 sums, network, gradient walk and force kernel, whose
-// distance, Chebyshev argument and series stay FP64.  One lane per atom,
+// distance, Chebyshev argument and series stay FP64.  In bin-offset mode (one
+// periodic cell) the walks gather 16-byte fixed-point positions and form the
+// FP64 pair vectors from them as the force kernels do.  One lane per atom,
 // blocks in XCD-aware order.
 #include <type_traits>
 
