@@ -601,8 +601,8 @@ def main():
         summarize_rocprof(*args.summarize_rocprof, n, cmd, os.path.join(ROOT, "profiles"))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU (the NEP-ZBL evaluation is not sharded "
-              "across GPUs here); run with --gpus 1", file=sys.stderr)
+        print("bench.py: the NEP-ZBL evaluation runs on exactly one GPU (it is not sharded "
+              "across GPUs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -193,10 +193,11 @@ int nep_set_weights(nep_ctx *ctx, const nep_weights *w, int32_t weights_on_devic
  * Bin-offset mode: a system of one cell, periodic along all three axes, at
  * least three bins of rc_rad + skin wide along each, and at most 2^23 atoms,
  * stores in each list entry the offset of the neighbour's bin from the
- * atom's own instead of the periodic image, and the force evaluation reads
- * positions as fixed-point offsets (units 2^-k A, k as large as the bin size
- * allows) from the corner of the atom's bin of this build.  The results are
- * those of the general layout up to that rounding (~4e-9 A).  The range of
+ * atom's own instead of the periodic image, and the force evaluation (and
+ * every walk of the paper-size model) reads positions as fixed-point offsets
+ * (units 2^-k A, k as large as the bin size allows) from the corner of the
+ * atom's bin at this list build.  The results are those of the general
+ * layout up to that rounding (~4e-9 A).  The range of
  * the offsets covers the bin plus at least skin + 1 A on every side; an atom
  * beyond it (possible only on lists used long after they went stale)
  * latches NEP_E_INTERNAL at the next evaluation.
