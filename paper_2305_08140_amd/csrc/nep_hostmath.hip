@@ -56,4 +56,10 @@ void nep_test_decode(int32_t e, int jbits, int ibits, int ioff, int *out)
 
 void nep_test_sort32(uint32_t *a) { sort32(a); }
 
+uint32_t nep_test_delta_code(int q, int m0, int m1, int m2)
+{
+    const int m[3] = {m0, m1, m2};
+    return delta_code(q, m);
+}
+
 }  // extern "C"

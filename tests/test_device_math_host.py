@@ -34,6 +34,8 @@ def L():
     lib.nep_test_zbl.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, DP, DP]
     lib.nep_test_decode.argtypes = [C.c_int32, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)]
     lib.nep_test_sort32.argtypes = [C.POINTER(C.c_uint32)]
+    lib.nep_test_delta_code.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+    lib.nep_test_delta_code.restype = C.c_uint32
     return lib
 
 
@@ -206,6 +208,33 @@ def test_neighbour_entry_decoding(L):
             e = np.int32(np.uint32(j | (code << jbits)))
             L.nep_test_decode(int(e), jbits, ibits, ioff, out)
             assert tuple(out) == (j,) + n
+
+
+def test_bin_offset_entry_code(L):
+    # bin-offset lists: an entry's code is q | (crossed faces << 5) with
+    # q = (o0+1) + 3 (o1+1) + 9 (o2+1) the neighbour bin's offset; the image
+    # on a crossed axis is the offset itself (a face is crossed only by a
+    # nonzero offset), zero elsewhere.  The entry of the same pair seen from
+    # the neighbour has offset -o, image -m: code (26 - q) with the same
+    # crossed faces, which is what the reverse-index search looks for.
+    import itertools
+    seen = set()
+    for o in itertools.product((-1, 0, 1), repeat=3):
+        q = (o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1)
+        for cross in itertools.product((0, 1), repeat=3):
+            if any(c and oa == 0 for c, oa in zip(cross, o)):
+                continue
+            m = [oa if c else 0 for oa, c in zip(o, cross)]
+            code = L.nep_test_delta_code(q, *m)
+            assert code & 31 == q and code >> 5 == cross[0] | (cross[1] << 1) | (cross[2] << 2)
+            cr = code >> 5
+            n = [(q % 3 - 1) if cr & 1 else 0, ((q // 3) % 3 - 1) if cr & 2 else 0, (q // 9 - 1) if cr & 4 else 0]
+            assert n == m
+            rcode = L.nep_test_delta_code(26 - q, *[-x for x in m])
+            assert rcode == ((26 - (code & 31)) | (code & ~31))
+            assert code < (1 << 8) and code not in seen   # 8 bits beside 23 index bits, one code per case
+            seen.add(code)
+    assert len(seen) == 125
 
 
 def test_sort32_network(L):
